@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark: registered MPix/s on the 5 MP pair (2592x1944 I420, exposure
+ratio 8, sensor noise sigma 2 DN, 10% mover tiles, search radius 16).
+
+A step is one pass of the whole path on one synthetic pair that is already
+resident in HBM: register_pair (equalisation, pyramid, five matching levels
+with weeding and homography fits, level-0 search, propagation, backward
+warp) followed by the deghosted merge. `value` = W*H / step time.
+
+Besides the JSON line's throughput, the run
+  * times every kernel with HIP events on its launch stream over a second,
+    traced pass of the same K steps (the library's lnr_trace_* calls), and
+    reports the dominant kernel against its roofline;
+  * runs the CPU oracle once on the same pair (single thread): its time is
+    `cpu_baseline`, and its tiles give the % of tiles equal to the oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes x 2.4 GHz, 1 op/lane/clk
+
+
+def algo_bytes(kernel, W, H, n_frames, ch):
+    """Algorithmic HBM bytes of one launch at full resolution."""
+    N = W * H
+    table = {
+        # causal + anti-causal vertical pass: read 3 maps + guide, write 3 maps
+        # (the last pass writes F (2 maps) and N~ instead)
+        "k_dt_v<false>": 25 * N, "k_dt_v<true>": 25 * N,
+        # horizontal pass: same; the first synthesises the sparse maps (reads guide only)
+        "k_dt_h<false>": 25 * N, "k_dt_h<true>": 13 * N,
+        # read F, Y, U, V, Y_eq; write RGB + warped Y_eq
+        "k_bwarp": (8 + 1 + 0.5 + 1 + 4 * ch + 4) * N,
+        # read every frame's planes + SSIM, write the weights
+        "k_weights": (n_frames * 4 * ch + (n_frames - 1) * 4 + n_frames * 4) * N,
+        # read two luma maps, write SSIM
+        "k_ssim": 12 * N,
+    }
+    return table.get(kernel)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the registration path is single-GPU by design "
+              "(a pair is one unit of work; see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1504_01441_amd as lnr
+    import synth
+
+    t_gen = time.time()
+    st = synth.make_config_pair("c2", args.seed)
+    f0, f1 = st.frames
+    W, H = f0.width, f0.height
+    print(f"[bench] generated 2592x1944 pair in {time.time() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    ctx = lnr.Context(0)
+    p = lnr.Params(radius0=st.meta["radius0"])
+    ref = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
+    src = lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)
+    reg = lnr.Registration.alloc(W, H, lnr.LNR_I420, p)
+    hdr = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
+
+    def step():
+        lnr.register_pair(ctx, ref, src, p, out=reg)
+        lnr.merge(ctx, [ref, src], 0, [reg], p, out=hdr)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole-path steps, untraced
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) / args.steps * 1e3
+    mpix = W * H / 1e6
+    value = mpix / (ms_step / 1e3)
+
+    # registration alone
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lnr.register_pair(ctx, ref, src, p, out=reg)
+    torch.cuda.synchronize()
+    ms_reg = (time.perf_counter() - t0) / args.steps * 1e3
+
+    # traced pass: per-kernel HIP-event durations on the launch stream
+    ctx.trace(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    tr = ctx.trace_read()
+    ctx.trace(False)
+    per_step = {k: (c / args.steps, ms / args.steps) for k, (c, ms) in tr.items()}
+    kernels = sorted(per_step.items(), key=lambda kv: -kv[1][1])
+    print("[bench] per-step kernel time (ms): " +
+          ", ".join(f"{k} {v[1]:.3f} ({v[0]:.0f}x)" for k, v in kernels), file=sys.stderr,
+          flush=True)
+    roof = None
+    for name, (cnt, ms) in kernels:
+        b = algo_bytes(name, W, H, 2, 3)
+        if b is None:
+            continue
+        avg_s = ms / cnt / 1e3
+        achieved = b / avg_s / 1e9
+        roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
+                "algo_bytes_per_launch": int(b)}
+        break
+    # level-0 search against the int-VALU peak (pixel-candidate operations)
+    out_reg = reg
+    torch.cuda.synchronize()
+    flags0 = out_reg.flags.cpu().numpy()[: reg.tile_off[1]]
+    ncorner = int((flags0 & 1).sum())
+    search_ops = ncorner * (2 * 16 + 1) ** 2 * 21 * 21
+
+    result = {
+        "metric": "registered MPix/s on 5MP pairs, plain vs learned-proposal; % tiles = oracle",
+        "value": round(value, 2),
+        "unit": "MPix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8+f32",
+        "data": "synthetic",
+        "config": {"workload": "5MP pair 2592x1944 I420, exposure ratio 8, noise sigma 2 DN, "
+                               "10% mover tiles, radius 16, plain method; step = register_pair "
+                               "+ merge",
+                   "width": W, "height": H, "seed": args.seed},
+        "registration_only": {"ms": round(ms_reg, 4), "mpix_s": round(mpix / (ms_reg / 1e3), 2)},
+        "learned_proposal": None,
+        "roofline": roof,
+        "search_level0": {"pixel_candidate_ops": search_ops,
+                          "int_peak_tops": round(INT_PEAK_TOPS, 2)},
+        "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kernels},
+    }
+    if "k_search" in per_step:
+        # all five levels' searches; the level-0 share dominates
+        result["search_level0"]["ms_all_levels"] = round(per_step["k_search"][1], 4)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        op = oracle.params(radius0=st.meta["radius0"])
+        t0 = time.perf_counter()
+        o = oracle.register_pair(f0, f1, op)
+        ref_rgb = oracle.frame_to_rgb(f0.y, f0.u, f0.v)
+        oracle.merge([ref_rgb, o["rgb"]], [o["yeq_ref"] / 255.0, o["yeq_warped"]], 0, op)
+        secs = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(mpix / secs, 4), "unit": "MPix/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": "one full 2592x1944 pair (registration + merge), "
+                                            f"{secs:.1f} s single-threaded"}
+        T = len(o["flags"])
+        g = {"flags": reg.flags.cpu().numpy()[:T], "disp": reg.disp.cpu().numpy()[:T]}
+        same = (g["flags"] == o["flags"]) & (g["disp"][:, 0] == o["dx"]) & \
+               (g["disp"][:, 1] == o["dy"])
+        result["tiles_equal_oracle_pct"] = round(100.0 * same.mean(), 3)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * lnr.h -- C ABI of the MI355X (gfx950) implementation of locally non-rigid
+ * HDR registration and deghosted merging (Gallo, Troccoli, Hu, Pulli, Kautz:
+ * "Locally Non-rigid Registration for Mobile HDR Photography").
+ *
+ * Conventions (all entry points):
+ *  - Every image, table and output pointer is a DEVICE pointer on the
+ *    context's GPU, allocated and owned by the caller. The library owns only
+ *    its context and an internal workspace, which grows on first use of a
+ *    larger shape (hipMalloc) and is freed by lnr_destroy.
+ *  - `stream` is a hipStream_t passed as void* (0 = the null stream). All work
+ *    is enqueued on it asynchronously; no entry point synchronises the device
+ *    except lnr_create / lnr_destroy.
+ *  - Errors return a negative lnr_status before anything is enqueued
+ *    (invalid arguments, unsupported sizes) or after a failed HIP call;
+ *    lnr_last_error() gives a message. No entry point aborts or throws.
+ *  - Images are row-major 8-bit planes with a byte stride per row; I420 frames
+ *    carry full-size Y and half-size U, V (even width and height). Float
+ *    outputs are dense planar [c][H][W].
+ *  - Level l of the matching pyramid has size (W >> l) x (H >> l) (floor
+ *    halving), up to 5 levels, none with a side below min_level_dim
+ *    (paper Sec. 2.6). Per-tile arrays hold every level's full tiles, level
+ *    by level, each level in raster order; lnr_query_sizes gives the offsets.
+ *  - Calls that share one context must not overlap: a context's workspace is
+ *    reused by every call on it.
+ */
+#ifndef LNR_H
+#define LNR_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LNR_OK = 0,
+  LNR_E_ARG = -1,          /* null pointer, bad size, mismatched frames */
+  LNR_E_UNSUPPORTED = -2,  /* parameter outside the supported range     */
+  LNR_E_TOO_SMALL = -3,    /* image smaller than one tile               */
+  LNR_E_HIP = -4,          /* a HIP runtime call failed                  */
+  LNR_E_NOMEM = -5         /* workspace allocation failed               */
+} lnr_status;
+
+typedef enum { LNR_Y8 = 0, LNR_I420 = 1 } lnr_format;
+
+typedef struct {
+  int32_t width, height;
+  int32_t format;            /* lnr_format                                      */
+  int32_t reserved;
+  const uint8_t* plane[3];   /* Y, U, V (device); U, V null for LNR_Y8          */
+  int32_t stride[3];         /* bytes per row of each plane                     */
+  float exposure;            /* relative exposure; the shortest is the reference */
+} lnr_frame;
+
+/* Method parameters. lnr_default_params() fills the paper's constants
+ * (Sec. 2.6: 5 levels, 100 px, 21x21 patches, radius 10, grid 1/16 of the
+ * tile, sigma_s 400) and the documented readings for what the paper leaves
+ * open. Supported ranges are checked by every entry point. */
+typedef struct {
+  int32_t tile;            /* S: tile side, 16..64, multiple of 4              */
+  int32_t patch_r;         /* P: patch (2P+1)^2, 1..11                          */
+  int32_t corner_step;     /* g: candidate spacing                              */
+  int32_t corner_half;     /* K: candidates at centre + g*[-K,K]^2, K <= 3      */
+  int32_t quad_r;          /* r: quadrant side of Eq. 1-2                       */
+  int32_t corner_t;        /* T of Eq. 2 (mean DN; compared on sums as T*r*r)   */
+  int32_t max_levels;      /* 1..5                                              */
+  int32_t min_level_dim;   /* smallest side of a coarse level                   */
+  int32_t radius_coarse;   /* search radius on levels >= 1, <= 32               */
+  int32_t radius0;         /* search radius on level 0, <= 32                   */
+  int32_t weed_iters;      /* weeding iterations (Sec. 2.3), 1..65536           */
+  int32_t weed_delta_min;  /* delta = max(min, ceil(pct * N / 100))  (Eq. 5)    */
+  int32_t weed_delta_pct;
+  int32_t dt_iters;        /* domain-transform iterations, 1..8                 */
+  double weed_eps;         /* inlier radius in level pixels                     */
+  double sigma_s;          /* spatial sigma of the propagation (Sec. 2.6: 400)  */
+  double sigma_r;          /* range sigma on the [0,1] guide                    */
+  double n_min;            /* F = P~/N~ only where N~ > n_min (Sec. 2.4)         */
+  double ssim_sigma;       /* SSIM Gaussian window sigma                         */
+  int32_t ssim_radius;     /* SSIM window radius, 1..8                          */
+  int32_t reserved0;
+  double ssim_c1, ssim_c2; /* SSIM stabilisers                                   */
+  double sigma_e;          /* Mertens well-exposedness sigma                     */
+  uint64_t seed;           /* weeding sampler seed                               */
+} lnr_params;
+
+typedef struct {
+  int32_t levels;          /* matching pyramid levels                          */
+  int32_t tiles_total;     /* per-tile array length (all levels)               */
+  int32_t tile_off[6];     /* level l's tiles are [tile_off[l], tile_off[l+1]) */
+  int32_t level_w[5], level_h[5];
+  int32_t channels;        /* 3 for I420 (RGB output), 1 for Y8 (grey)         */
+  int32_t blend_levels;    /* Laplacian-pyramid levels of the merge            */
+} lnr_sizes;
+
+/* Outputs of one registration (device pointers, caller-owned). Pointers
+ * marked optional may be null. Per-tile flags: 1 corner found, 2 valid
+ * match, 4 kept by the weeding filter (Eq. 5), 8 used for the level fit. */
+typedef struct {
+  int32_t* corner_xy;      /* [tiles_total][2] corner pixel, -1 if none        */
+  int32_t* disp;           /* [tiles_total][2] integer displacement d          */
+  uint32_t* ssd;           /* [tiles_total] SSD at the argmin                  */
+  uint8_t* flags;          /* [tiles_total]                                    */
+  int32_t* counts;         /* [5][4] per level: N valid, fit count,
+                              best-consensus count, best iteration             */
+  double* H;               /* [levels+1][9] normalised-frame homographies:
+                              H[l] for l < levels, H[levels] = initial (I)     */
+  uint8_t* yeq_ref;        /* [H][W] equalised reference Y                     */
+  uint8_t* yeq_src;        /* [H][W] equalised source Y (optional)             */
+  uint8_t* warped0;        /* [H][W] level-0 source warped by H[1] (optional)  */
+  float* flow;             /* [2][H][W] residual flow F (Sec. 2.4)             */
+  float* ntilde;           /* [H][W] filtered N (optional)                     */
+  float* image;            /* [channels][H][W] warped source in [0, 1]         */
+  float* yeq_warped;       /* [H][W] warped source Y_eq / 255                  */
+} lnr_registration;
+
+typedef struct lnr_ctx lnr_ctx;
+
+/* Create a context on HIP device `device`. */
+lnr_status lnr_create(lnr_ctx** ctx, int32_t device);
+void lnr_destroy(lnr_ctx* ctx);
+const char* lnr_last_error(const lnr_ctx* ctx);
+void lnr_default_params(lnr_params* p);
+/* Sizes of every output for a width x height frame of `format`. */
+lnr_status lnr_query_sizes(int32_t width, int32_t height, int32_t format,
+                           const lnr_params* p, lnr_sizes* out);
+
+/* Register `src` to `ref` (paper Sec. 2.2 - 2.4): equalise both, estimate the
+ * pyramid homographies (matcher + weeding per level), search level 0, weed,
+ * propagate the kept matches to a dense residual flow, and warp the source
+ * backwards. Both frames must share size and format. */
+lnr_status lnr_register_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                             const lnr_params* p, lnr_registration* out, void* stream);
+
+/* Register an n-frame stack (paper Sec. 2: n - 1 registrations): the
+ * reference is the frame with the smallest exposure (lowest index on ties),
+ * written to *ref_index; outs[k] receives the registration of the k-th
+ * non-reference frame, in frame order. */
+lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
+                              const lnr_params* p, lnr_registration* outs,
+                              int32_t* ref_index, void* stream);
+
+/* Error-tolerant exposure fusion (paper Sec. 2.5): Mertens et al.'s contrast,
+ * saturation and well-exposedness weights times the SSIM between the
+ * equalised reference and each warped frame, blended with Laplacian
+ * pyramids. regs[k] is the registration of the k-th non-reference frame (as
+ * produced by lnr_register_stack); out is [channels][H][W] float. */
+lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t ref_index,
+                     const lnr_registration* regs, const lnr_params* p, float* out,
+                     void* stream);
+
+/* ---- stage entry points: one stage on caller-given inputs (used to check
+ * each kernel on exactly the inputs the oracle sees). -------------------- */
+
+/* Histogram equalisation (Sec. 3 opening) of one 8-bit plane: lut[256] and
+ * out[h][w] (dense). */
+lnr_status lnr_stage_equalize(lnr_ctx* ctx, const uint8_t* img, int32_t w, int32_t h,
+                              int32_t stride, uint8_t* lut, uint8_t* out, void* stream);
+/* Q8 bilinear warp of a level image through the normalised homography
+ * H[9] (device, double), Eq. 3 frame (Sec. 2.2). */
+lnr_status lnr_stage_warp_q8(lnr_ctx* ctx, const uint8_t* src, int32_t w, int32_t h,
+                             const double* H, uint8_t* out, void* stream);
+/* Corners (Eq. 1-2) on `ref` and SSD search (Sec. 2.2) in `warped` with
+ * radius R, for every full tile: corner_xy, disp, ssd, flags (bits 1, 2). */
+lnr_status lnr_stage_search(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,
+                            int32_t w, int32_t h, int32_t R, const lnr_params* p,
+                            int32_t* corner_xy, int32_t* disp, uint32_t* ssd,
+                            uint8_t* flags, void* stream);
+/* Weeding (Sec. 2.3, Eq. 5) and level homography (Sec. 2.2) over the tiles of
+ * one level (flags bit 2 = valid match): sets flags bits 4 and 8, writes
+ * counts[4] and H_out[9] = H_prev o G. */
+lnr_status lnr_stage_weed_fit(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t* disp,
+                              uint8_t* flags, int32_t ntiles, int32_t w, int32_t h,
+                              int32_t level, const lnr_params* p, const double* H_prev,
+                              double* H_out, int32_t* counts, void* stream);
+/* Sparse-to-dense flow (Sec. 2.4, Eq. 6-7) from the level-0 tiles with flags
+ * bit 4, guided by `guide` (dense [h][w]): flow [2][h][w], ntilde (optional). */
+lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t* disp,
+                          const uint8_t* flags, int32_t ntiles, const uint8_t* guide,
+                          int32_t w, int32_t h, const lnr_params* p, float* flow,
+                          float* ntilde, void* stream);
+/* Backward warp of `src` through H[9] (device, normalised, level 0) and the
+ * flow: image [channels][h][w] in [0, 1] and the warped yeq / 255. */
+lnr_status lnr_stage_backward_warp(lnr_ctx* ctx, const lnr_frame* src, const uint8_t* yeq,
+                                   const double* H, const float* flow, float* image,
+                                   float* yeq_warped, void* stream);
+/* Deghosted merge (Sec. 2.5) of n float images [ch][h][w] in [0, 1] with
+ * their equalised luma maps yeqs[k] ([h][w], in [0, 1]); frame ref_index
+ * gets no SSIM weight. imgs and yeqs are device pointers held in host arrays. */
+lnr_status lnr_stage_merge(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32_t h,
+                           const float* const* imgs, const float* const* yeqs,
+                           int32_t ref_index, const lnr_params* p, float* out, void* stream);
+
+/* ---- timing: optional per-kernel GPU timing with HIP events recorded on the
+ * call's stream around every kernel launch of the calls that follow (off by
+ * default; adds one event pair per launch). -------------------------------- */
+typedef struct {
+  char name[32];      /* kernel name, e.g. "k_search"                        */
+  int32_t count;      /* launches timed since the last reset                 */
+  int32_t reserved;
+  double ms_total;    /* summed event-to-event time of those launches        */
+} lnr_trace_entry;
+
+/* Enable (on != 0) or disable timing, and discard what was recorded. */
+lnr_status lnr_trace_enable(lnr_ctx* ctx, int32_t on);
+/* Wait for the recorded events, write up to `max` entries (one per kernel
+ * name, in first-launch order) and return how many there are (or < 0). */
+int32_t lnr_trace_read(lnr_ctx* ctx, lnr_trace_entry* out, int32_t max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,399 @@
+"""Python binding of liblnr (include/lnr.h): locally non-rigid HDR registration
+and deghosted merging on MI355X.
+
+This module only marshals arguments: torch provides device memory and the
+current HIP stream, and every step of the method runs in the library's HIP
+kernels. Importing it without the built library raises (there is no CPU
+fallback); build it with `python -m paper_1504_01441_amd.build`.
+
+Typical use::
+
+    import paper_1504_01441_amd as lnr
+    ctx = lnr.Context()
+    ref = lnr.Frame.from_numpy(y0, u0, v0, exposure=1.0)   # copies to the GPU
+    src = lnr.Frame.from_numpy(y1, u1, v1, exposure=8.0)
+    reg = lnr.register_pair(ctx, ref, src)
+    hdr = lnr.merge(ctx, [ref, src], 0, [reg])              # [3][H][W] float32
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblnr.so")
+
+LNR_Y8, LNR_I420 = 0, 1
+_STATUS = {0: "LNR_OK", -1: "LNR_E_ARG", -2: "LNR_E_UNSUPPORTED", -3: "LNR_E_TOO_SMALL",
+           -4: "LNR_E_HIP", -5: "LNR_E_NOMEM"}
+
+
+class LnrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("tile", C.c_int32), ("patch_r", C.c_int32), ("corner_step", C.c_int32),
+        ("corner_half", C.c_int32), ("quad_r", C.c_int32), ("corner_t", C.c_int32),
+        ("max_levels", C.c_int32), ("min_level_dim", C.c_int32),
+        ("radius_coarse", C.c_int32), ("radius0", C.c_int32), ("weed_iters", C.c_int32),
+        ("weed_delta_min", C.c_int32), ("weed_delta_pct", C.c_int32), ("dt_iters", C.c_int32),
+        ("weed_eps", C.c_double), ("sigma_s", C.c_double), ("sigma_r", C.c_double),
+        ("n_min", C.c_double), ("ssim_sigma", C.c_double), ("ssim_radius", C.c_int32),
+        ("reserved0", C.c_int32), ("ssim_c1", C.c_double), ("ssim_c2", C.c_double),
+        ("sigma_e", C.c_double), ("seed", C.c_uint64),
+    ]
+
+    def __init__(self, **overrides):
+        super().__init__()
+        lib().lnr_default_params(C.byref(self))
+        for k, v in overrides.items():
+            if not any(k == f[0] for f in self._fields_):
+                raise KeyError(k)
+            setattr(self, k, v)
+
+
+class _Frame(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("format", C.c_int32),
+                ("reserved", C.c_int32), ("plane", C.c_void_p * 3), ("stride", C.c_int32 * 3),
+                ("exposure", C.c_float)]
+
+
+class _Sizes(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("tiles_total", C.c_int32), ("tile_off", C.c_int32 * 6),
+                ("level_w", C.c_int32 * 5), ("level_h", C.c_int32 * 5),
+                ("channels", C.c_int32), ("blend_levels", C.c_int32)]
+
+
+class _TraceEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("count", C.c_int32), ("reserved", C.c_int32),
+                ("ms_total", C.c_double)]
+
+
+class _Registration(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("corner_xy", "disp", "ssd", "flags", "counts", "H",
+                                           "yeq_ref", "yeq_src", "warped0", "flow", "ntilde",
+                                           "image", "yeq_warped")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liblnr.so; raises if it was not built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1504_01441_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.lnr_create.argtypes = [C.POINTER(vp), i32]
+        L.lnr_destroy.argtypes = [vp]
+        L.lnr_last_error.argtypes = [vp]
+        L.lnr_last_error.restype = C.c_char_p
+        L.lnr_default_params.argtypes = [C.POINTER(Params)]
+        L.lnr_query_sizes.argtypes = [i32, i32, i32, C.POINTER(Params), C.POINTER(_Sizes)]
+        L.lnr_register_pair.argtypes = [vp, C.POINTER(_Frame), C.POINTER(_Frame),
+                                        C.POINTER(Params), C.POINTER(_Registration), vp]
+        L.lnr_register_stack.argtypes = [vp, C.POINTER(_Frame), i32, C.POINTER(Params),
+                                         C.POINTER(_Registration), C.POINTER(i32), vp]
+        L.lnr_merge.argtypes = [vp, C.POINTER(_Frame), i32, i32, C.POINTER(_Registration),
+                                C.POINTER(Params), vp, vp]
+        L.lnr_stage_equalize.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
+        L.lnr_stage_warp_q8.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+        L.lnr_stage_search.argtypes = [vp, vp, vp, i32, i32, i32, C.POINTER(Params), vp, vp, vp,
+                                       vp, vp]
+        L.lnr_stage_weed_fit.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, C.POINTER(Params),
+                                         vp, vp, vp, vp]
+        L.lnr_stage_flow.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, C.POINTER(Params), vp,
+                                     vp, vp]
+        L.lnr_stage_backward_warp.argtypes = [vp, C.POINTER(_Frame), vp, vp, vp, vp, vp, vp]
+        L.lnr_stage_merge.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, C.POINTER(Params),
+                                      vp, vp]
+        L.lnr_trace_enable.argtypes = [vp, i32]
+        L.lnr_trace_read.argtypes = [vp, C.POINTER(_TraceEntry), i32]
+        for name in ("lnr_trace_enable", "lnr_trace_read", "lnr_create", "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack",
+                     "lnr_merge", "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
+                     "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
+                     "lnr_stage_merge"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
+            "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack", "lnr_merge",
+            "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
+            "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
+            "lnr_stage_merge", "lnr_trace_enable", "lnr_trace_read")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context on one GPU (owns the workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        self.device = device
+        rc = lib().lnr_create(C.byref(self._h), device)
+        if rc:
+            raise LnrError(rc, f"lnr_create(device={device}) failed")
+
+    def check(self, rc):
+        if rc:
+            raise LnrError(rc, lib().lnr_last_error(self._h).decode())
+
+    def trace(self, on: bool = True):
+        """Start (or stop) per-kernel HIP-event timing; clears what was recorded."""
+        self.check(lib().lnr_trace_enable(self._h, 1 if on else 0))
+
+    def trace_read(self) -> dict:
+        """{kernel name: (launches, total ms)} since trace(True); waits for the events."""
+        buf = (_TraceEntry * 64)()
+        n = lib().lnr_trace_read(self._h, buf, 64)
+        if n < 0:
+            self.check(n)
+        return {buf[i].name.decode(): (buf[i].count, buf[i].ms_total) for i in range(min(n, 64))}
+
+    def close(self):
+        if self._h:
+            lib().lnr_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Frame:
+    """An 8-bit Y8 or I420 frame whose planes are uint8 tensors on the GPU."""
+    y: torch.Tensor
+    u: torch.Tensor | None = None
+    v: torch.Tensor | None = None
+    exposure: float = 1.0
+
+    @staticmethod
+    def from_numpy(y, u=None, v=None, exposure=1.0, device="cuda"):
+        t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return Frame(t(y), t(u), t(v), float(exposure))
+
+    @property
+    def fmt(self):
+        return LNR_Y8 if self.u is None else LNR_I420
+
+    @property
+    def width(self):
+        return int(self.y.shape[1])
+
+    @property
+    def height(self):
+        return int(self.y.shape[0])
+
+    def _c(self) -> _Frame:
+        f = _Frame()
+        f.width, f.height, f.format = self.width, self.height, self.fmt
+        planes = [self.y, self.u, self.v]
+        for i, pl in enumerate(planes):
+            if pl is None:
+                f.plane[i] = None
+                f.stride[i] = 0
+            else:
+                if pl.dtype != torch.uint8 or not pl.is_cuda or pl.stride(1) != 1:
+                    raise ValueError("planes must be uint8 CUDA tensors with unit column stride")
+                f.plane[i] = pl.data_ptr()
+                f.stride[i] = pl.stride(0)
+        f.exposure = self.exposure
+        return f
+
+
+def query_sizes(width, height, fmt=LNR_Y8, params=None):
+    p = params or Params()
+    s = _Sizes()
+    rc = lib().lnr_query_sizes(width, height, fmt, C.byref(p), C.byref(s))
+    if rc:
+        raise LnrError(rc, "lnr_query_sizes")
+    return s
+
+
+@dataclass
+class Registration:
+    """Device outputs of one registration (see lnr_registration in lnr.h)."""
+    corner_xy: torch.Tensor
+    disp: torch.Tensor
+    ssd: torch.Tensor
+    flags: torch.Tensor
+    counts: torch.Tensor
+    H: torch.Tensor
+    yeq_ref: torch.Tensor
+    yeq_src: torch.Tensor
+    warped0: torch.Tensor
+    flow: torch.Tensor
+    ntilde: torch.Tensor
+    image: torch.Tensor
+    yeq_warped: torch.Tensor
+    levels: int = 1
+    tile_off: list = field(default_factory=list)
+
+    @staticmethod
+    def alloc(width, height, fmt, params, device="cuda"):
+        s = query_sizes(width, height, fmt, params)
+        T, L, ch = max(s.tiles_total, 1), s.levels, s.channels
+        e = lambda *shape, dt: torch.empty(*shape, dtype=dt, device=device)
+        return Registration(
+            corner_xy=e(T, 2, dt=torch.int32), disp=e(T, 2, dt=torch.int32),
+            ssd=e(T, dt=torch.int32), flags=e(T, dt=torch.uint8),
+            counts=torch.zeros(5, 4, dtype=torch.int32, device=device),
+            H=e(L + 1, 9, dt=torch.float64), yeq_ref=e(height, width, dt=torch.uint8),
+            yeq_src=e(height, width, dt=torch.uint8), warped0=e(height, width, dt=torch.uint8),
+            flow=e(2, height, width, dt=torch.float32), ntilde=e(height, width, dt=torch.float32),
+            image=e(ch, height, width, dt=torch.float32),
+            yeq_warped=e(height, width, dt=torch.float32), levels=L,
+            tile_off=list(s.tile_off)[:L + 1])
+
+    def _c(self) -> _Registration:
+        r = _Registration()
+        for name, _ in _Registration._fields_:
+            setattr(r, name, getattr(self, name).data_ptr())
+        return r
+
+
+def register_pair(ctx: Context, ref: Frame, src: Frame, params: Params | None = None,
+                  out: Registration | None = None) -> Registration:
+    """Register src to ref (paper Sec. 2.2 - 2.4); asynchronous on the current stream."""
+    p = params or Params()
+    out = out or Registration.alloc(ref.width, ref.height, ref.fmt, p, ref.y.device)
+    rf, sf, rr = ref._c(), src._c(), out._c()
+    ctx.check(lib().lnr_register_pair(ctx._h, C.byref(rf), C.byref(sf), C.byref(p),
+                                      C.byref(rr), _stream()))
+    return out
+
+
+def register_stack(ctx: Context, frames, params: Params | None = None):
+    """Register every frame to the shortest exposure; returns (registrations, ref_index)."""
+    p = params or Params()
+    n = len(frames)
+    f0 = frames[0]
+    regs = [Registration.alloc(f0.width, f0.height, f0.fmt, p, f0.y.device) for _ in range(n - 1)]
+    FA = (_Frame * n)(*[f._c() for f in frames])
+    RA = (_Registration * max(n - 1, 1))(*[r._c() for r in regs])
+    ref_index = C.c_int32(-1)
+    ctx.check(lib().lnr_register_stack(ctx._h, FA, n, C.byref(p), RA, C.byref(ref_index),
+                                       _stream()))
+    return regs, ref_index.value
+
+
+def merge(ctx: Context, frames, ref_index: int, regs, params: Params | None = None,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """Error-tolerant exposure fusion (paper Sec. 2.5); returns [ch][H][W] float32."""
+    p = params or Params()
+    n = len(frames)
+    f0 = frames[ref_index]
+    ch = 3 if f0.fmt == LNR_I420 else 1
+    out = out if out is not None else torch.empty(ch, f0.height, f0.width, dtype=torch.float32,
+                                                  device=f0.y.device)
+    FA = (_Frame * n)(*[f._c() for f in frames])
+    RA = (_Registration * max(n - 1, 1))(*[r._c() for r in regs])
+    ctx.check(lib().lnr_merge(ctx._h, FA, n, ref_index, RA, C.byref(p), _ptr(out), _stream()))
+    return out
+
+
+# ----------------------------------------------------------------- stage entry points
+
+def stage_equalize(ctx, img: torch.Tensor):
+    h, w = img.shape
+    lut = torch.empty(256, dtype=torch.uint8, device=img.device)
+    out = torch.empty(h, w, dtype=torch.uint8, device=img.device)
+    ctx.check(lib().lnr_stage_equalize(ctx._h, _ptr(img), w, h, img.stride(0), _ptr(lut),
+                                       _ptr(out), _stream()))
+    return lut, out
+
+
+def stage_warp_q8(ctx, src: torch.Tensor, H: torch.Tensor):
+    h, w = src.shape
+    out = torch.empty_like(src)
+    Hd = H.to(device=src.device, dtype=torch.float64).contiguous()
+    ctx.check(lib().lnr_stage_warp_q8(ctx._h, _ptr(src), w, h, _ptr(Hd), _ptr(out), _stream()))
+    return out
+
+
+def stage_search(ctx, ref: torch.Tensor, warped: torch.Tensor, R: int, params=None):
+    p = params or Params()
+    h, w = ref.shape
+    nt = max((w // p.tile) * (h // p.tile), 1)
+    dev = ref.device
+    cxy = torch.empty(nt, 2, dtype=torch.int32, device=dev)
+    disp = torch.empty(nt, 2, dtype=torch.int32, device=dev)
+    ssd = torch.empty(nt, dtype=torch.int32, device=dev)
+    flags = torch.empty(nt, dtype=torch.uint8, device=dev)
+    ctx.check(lib().lnr_stage_search(ctx._h, _ptr(ref), _ptr(warped), w, h, R, C.byref(p),
+                                     _ptr(cxy), _ptr(disp), _ptr(ssd), _ptr(flags), _stream()))
+    return cxy, disp, ssd, flags
+
+
+def stage_weed_fit(ctx, corner_xy, disp, flags, w, h, level, H_prev, params=None):
+    p = params or Params()
+    dev = corner_xy.device
+    flags = flags.clone()
+    Hp = H_prev.to(device=dev, dtype=torch.float64).contiguous()
+    Ho = torch.empty(9, dtype=torch.float64, device=dev)
+    counts = torch.empty(4, dtype=torch.int32, device=dev)
+    ctx.check(lib().lnr_stage_weed_fit(ctx._h, _ptr(corner_xy), _ptr(disp), _ptr(flags),
+                                       flags.numel(), w, h, level, C.byref(p), _ptr(Hp), _ptr(Ho),
+                                       _ptr(counts), _stream()))
+    return flags, Ho, counts
+
+
+def stage_flow(ctx, corner_xy, disp, flags, guide: torch.Tensor, params=None):
+    p = params or Params()
+    h, w = guide.shape
+    flow = torch.empty(2, h, w, dtype=torch.float32, device=guide.device)
+    ntilde = torch.empty(h, w, dtype=torch.float32, device=guide.device)
+    nt = (w // p.tile) * (h // p.tile)
+    ctx.check(lib().lnr_stage_flow(ctx._h, _ptr(corner_xy), _ptr(disp), _ptr(flags), nt,
+                                   _ptr(guide), w, h, C.byref(p), _ptr(flow), _ptr(ntilde),
+                                   _stream()))
+    return flow, ntilde
+
+
+def stage_backward_warp(ctx, src: Frame, yeq: torch.Tensor, H: torch.Tensor,
+                        flow: torch.Tensor):
+    ch = 3 if src.fmt == LNR_I420 else 1
+    dev = src.y.device
+    img = torch.empty(ch, src.height, src.width, dtype=torch.float32, device=dev)
+    yw = torch.empty(src.height, src.width, dtype=torch.float32, device=dev)
+    Hd = H.to(device=dev, dtype=torch.float64).contiguous()
+    sf = src._c()
+    ctx.check(lib().lnr_stage_backward_warp(ctx._h, C.byref(sf), _ptr(yeq), _ptr(Hd),
+                                            _ptr(flow.contiguous()), _ptr(img), _ptr(yw),
+                                            _stream()))
+    return img, yw
+
+
+def stage_merge(ctx, imgs, yeqs, ref_index, params=None):
+    p = params or Params()
+    n = len(imgs)
+    ch, h, w = imgs[0].shape
+    out = torch.empty(ch, h, w, dtype=torch.float32, device=imgs[0].device)
+    IA = (C.c_void_p * n)(*[i.data_ptr() for i in imgs])
+    YA = (C.c_void_p * n)(*[y.data_ptr() for y in yeqs])
+    ctx.check(lib().lnr_stage_merge(ctx._h, n, ch, w, h, IA, YA, ref_index, C.byref(p),
+                                    _ptr(out), _stream()))
+    return out

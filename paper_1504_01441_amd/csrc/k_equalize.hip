@@ -1,0 +1,154 @@
+// k_equalize.hip -- exposure normalisation (histogram equalisation, applied to
+// every input before matching: paper Sec. 3 opening) and the matching pyramid
+// (Sec. 2.2 / 2.6: up to 5 levels, 2x2 box mean rounded half up).
+//
+// k_hist: per-wave LDS histograms, one global atomic add per bin per block.
+// k_lut_pyr: each block rebuilds the 256-entry LUT from the histogram (prefix
+// sum in LDS), equalises a 64x64 block of Y and writes pyramid levels 1..L-1
+// of that block from LDS, so the pyramid costs no extra pass over HBM.
+#include "lnr_internal.h"
+
+namespace lnr {
+namespace {
+
+constexpr int kHistBlocks = 192;
+
+__global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ y0, int s0,
+                                              const uint8_t* __restrict__ y1, int s1, int W,
+                                              int H, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t bins[4][256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int i = tid; i < 4 * 256; i += 256) (&bins[0][0])[i] = 0;
+  __syncthreads();
+  const uint8_t* img = blockIdx.y ? y1 : y0;
+  const int stride = blockIdx.y ? s1 : s0;
+  for (int row = blockIdx.x; row < H; row += gridDim.x) {
+    const uint8_t* p = img + (size_t)row * stride;
+    for (int x = tid; x < W; x += 256) atomicAdd(&bins[wave][p[x]], 1u);
+  }
+  __syncthreads();
+  uint32_t s = bins[0][tid] + bins[1][tid] + bins[2][tid] + bins[3][tid];
+  if (s) atomicAdd(&hist[blockIdx.y * 256 + tid], s);
+}
+
+// LUT[v] = round-half-up(255 (cdf[v] - cdf_min) / (n - cdf_min)), cdf_min the
+// cdf at the first occupied bin; identity when the image has one value.
+__device__ void build_lut(const uint32_t* __restrict__ hist, uint8_t* lut, uint32_t* scan) {
+  const int v = threadIdx.x;
+  scan[v] = hist[v];
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t add = v >= off ? scan[v - off] : 0u;
+    __syncthreads();
+    scan[v] += add;
+    __syncthreads();
+  }
+  __shared__ uint32_t c0s;
+  const uint32_t cdf = scan[v];
+  const uint32_t prev = v ? scan[v - 1] : 0u;
+  if (cdf != 0u && prev == 0u) c0s = cdf;  // exactly one bin is the first occupied
+  __syncthreads();
+  const int64_t n = scan[255], c0 = c0s;
+  int64_t num = (int64_t)cdf - c0;
+  if (num < 0) num = 0;
+  const int64_t den = n - c0;
+  lut[v] = den == 0 ? (uint8_t)v : (uint8_t)((2 * 255 * num + den) / (2 * den));
+  __syncthreads();
+}
+
+struct LevelGeom {
+  int w[kMaxLevels], h[kMaxLevels];
+  long long off[kMaxLevels];
+  int levels;
+};
+
+__global__ __launch_bounds__(256) void k_lut_pyr(const uint8_t* __restrict__ y0, int s0,
+                                                 const uint8_t* __restrict__ y1, int s1,
+                                                 const uint32_t* __restrict__ hist,
+                                                 LevelGeom g, uint8_t* __restrict__ pyr0,
+                                                 uint8_t* __restrict__ pyr1,
+                                                 uint8_t* __restrict__ lut_out) {
+  __shared__ uint32_t scan[256];
+  __shared__ uint8_t lut[256];
+  __shared__ uint8_t tileA[64 * 64];
+  __shared__ uint8_t tileB[32 * 32];
+  const int f = blockIdx.z, tid = threadIdx.x;
+  build_lut(hist + f * 256, lut, scan);
+  if (lut_out && blockIdx.x == 0 && blockIdx.y == 0) lut_out[f * 256 + tid] = lut[tid];
+  const uint8_t* img = f ? y1 : y0;
+  const int stride = f ? s1 : s0;
+  uint8_t* pyr = f ? pyr1 : pyr0;
+  const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
+  const int W = g.w[0], H = g.h[0];
+  // level 0: 64 x 64 block, 16 pixels per thread (4 bytes x 4 rows)
+  for (int i = tid; i < 64 * 16; i += 256) {
+    const int r = i >> 4, c4 = (i & 15) * 4;
+    const int y = by + r;
+    uint32_t packed = 0;
+    if (y < H) {
+      const uint8_t* src = img + (size_t)y * stride;
+      uint8_t* dst = pyr + g.off[0] + (size_t)y * W;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = bx + c4 + k;
+        if (x < W) {
+          const uint8_t e = lut[src[x]];
+          dst[x] = e;
+          packed |= (uint32_t)e << (8 * k);
+        }
+      }
+    }
+    *reinterpret_cast<uint32_t*>(&tileA[r * 64 + c4]) = packed;
+  }
+  __syncthreads();
+  // levels 1.. from the block in LDS; level l of this block covers
+  // [bx >> l, (bx >> l) + (64 >> l)) and only pixels inside the level are kept.
+  uint8_t* cur = tileA;
+  uint8_t* nxt = tileB;
+  int side = 64;
+  for (int l = 1; l < g.levels; ++l) {
+    const int ns = side >> 1;
+    const int ox = bx >> l, oy = by >> l;
+    for (int i = tid; i < ns * ns; i += 256) {
+      const int r = i / ns, c = i % ns;
+      const int s = cur[(2 * r) * side + 2 * c] + cur[(2 * r) * side + 2 * c + 1] +
+                    cur[(2 * r + 1) * side + 2 * c] + cur[(2 * r + 1) * side + 2 * c + 1];
+      const uint8_t val = (uint8_t)((s + 2) >> 2);
+      nxt[r * ns + c] = val;
+      const int x = ox + c, y = oy + r;
+      if (x < g.w[l] && y < g.h[l]) pyr[g.off[l] + (size_t)y * g.w[l] + x] = val;
+    }
+    __syncthreads();
+    uint8_t* t = cur;  // both buffers hold any level from 32 x 32 down
+    cur = nxt;
+    nxt = t;
+    side = ns;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int W, int H,
+                       uint32_t* hist, int nframes, hipStream_t st) {
+  dim3 grid(kHistBlocks < H ? kHistBlocks : H, nframes);
+  LNR_LAUNCH(k_hist, grid, dim3(256), 0, st, y0, s0, y1, s1, W, H, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
+                          const uint32_t* hist, const Geometry& geo, uint8_t* pyr0,
+                          uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st) {
+  LevelGeom g;
+  g.levels = geo.levels;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    g.w[l] = l < geo.levels ? geo.lv[l].w : 0;
+    g.h[l] = l < geo.levels ? geo.lv[l].h : 0;
+    g.off[l] = l < geo.levels ? (long long)geo.lv[l].pix_off : 0;
+  }
+  dim3 grid((geo.W + 63) / 64, (geo.H + 63) / 64, nframes);
+  LNR_LAUNCH(k_lut_pyr, grid, dim3(256), 0, st, y0, s0, y1, s1, hist, g, pyr0, pyr1,
+                     lut_out);
+  return hipGetLastError();
+}
+
+}  // namespace lnr

@@ -1,0 +1,305 @@
+// k_merge.hip -- error-tolerant exposure fusion (paper Sec. 2.5): Mertens et
+// al.'s contrast, saturation and well-exposedness weights, times the SSIM
+// between the equalised reference and each warped frame (Wang et al.:
+// Gaussian window, five filterings), blended with Laplacian pyramids.
+//
+//  k_ssim:    64x16 output tile; the two luma maps (+ halo) are staged in LDS,
+//             the five horizontal Gaussian sums are kept in LDS, then the
+//             vertical sums give SSIM.
+//  k_weights: per pixel, every frame's C * S * E (* max(SSIM, 0)) + 1e-12,
+//             normalised over the frames.
+//  k_reduce:  REDUCE ([1 4 6 4 1]/16 separable, clamped, even samples) of
+//             every weight and image plane of one level, through LDS.
+//  k_blend:   from the top level down, R_l = sum_k W_k,l (G_k,l - E(G_k,l+1))
+//             + E(R_l+1), E the EXPAND rule; level 0 goes to the output.
+#include "lnr_internal.h"
+
+namespace lnr {
+namespace {
+
+constexpr int kMaxMaps = 64;
+constexpr int kSsimTW = 64, kSsimTH = 16, kSsimMaxR = 8;
+
+__global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
+                                              const float* __restrict__ b, int W, int H, int r,
+                                              double sigma, float c1, float c2,
+                                              float* __restrict__ out) {
+  __shared__ float sa[kSsimTH + 2 * kSsimMaxR][kSsimTW + 2 * kSsimMaxR];
+  __shared__ float sb[kSsimTH + 2 * kSsimMaxR][kSsimTW + 2 * kSsimMaxR];
+  __shared__ float hs[5][kSsimTH + 2 * kSsimMaxR][kSsimTW];
+  __shared__ float gw[2 * kSsimMaxR + 1];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double g[2 * kSsimMaxR + 1], s = 0;
+    for (int k = -r; k <= r; ++k) {
+      g[k + r] = exp(-(double)(k * k) / (2.0 * sigma * sigma));
+      s += g[k + r];
+    }
+    for (int k = 0; k <= 2 * r; ++k) gw[k] = (float)(g[k] / s);
+  }
+  const int ox = blockIdx.x * kSsimTW, oy = blockIdx.y * kSsimTH;
+  const int rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
+  for (int i = tid; i < rows * cols; i += 256) {
+    const int yy = i / cols, xx = i % cols;
+    const int gy = min(max(oy + yy - r, 0), H - 1), gx = min(max(ox + xx - r, 0), W - 1);
+    sa[yy][xx] = a[(size_t)gy * W + gx];
+    sb[yy][xx] = b[(size_t)gy * W + gx];
+  }
+  __syncthreads();
+  for (int i = tid; i < rows * kSsimTW; i += 256) {
+    const int yy = i / kSsimTW, xx = i % kSsimTW;
+    float m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
+    for (int k = 0; k <= 2 * r; ++k) {
+      const float p = sa[yy][xx + k], q = sb[yy][xx + k], wk = gw[k];
+      m1 += wk * p;
+      m2 += wk * q;
+      s11 += wk * (p * p);
+      s22 += wk * (q * q);
+      s12 += wk * (p * q);
+    }
+    hs[0][yy][xx] = m1; hs[1][yy][xx] = m2; hs[2][yy][xx] = s11;
+    hs[3][yy][xx] = s22; hs[4][yy][xx] = s12;
+  }
+  __syncthreads();
+  for (int i = tid; i < kSsimTH * kSsimTW; i += 256) {
+    const int yy = i / kSsimTW, xx = i % kSsimTW;
+    const int gy = oy + yy, gx = ox + xx;
+    if (gy >= H || gx >= W) continue;
+    float m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
+    for (int k = 0; k <= 2 * r; ++k) {
+      const float wk = gw[k];
+      m1 += wk * hs[0][yy + k][xx];
+      m2 += wk * hs[1][yy + k][xx];
+      s11 += wk * hs[2][yy + k][xx];
+      s22 += wk * hs[3][yy + k][xx];
+      s12 += wk * hs[4][yy + k][xx];
+    }
+    const float vx = s11 - m1 * m1, vy = s22 - m2 * m2, cxy = s12 - m1 * m2;
+    out[(size_t)gy * W + gx] = ((2.f * m1 * m2 + c1) * (2.f * cxy + c2)) /
+                               ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2));
+  }
+}
+
+struct FramePtrs {
+  const float* img[16];
+  const float* ssim[16];
+  float* wout[16];
+};
+
+__device__ inline float grey_at(const float* I, int ch, size_t plane, size_t o) {
+  return ch == 3 ? 0.299f * I[o] + 0.587f * I[plane + o] + 0.114f * I[2 * plane + o] : I[o];
+}
+
+__global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int W, int H,
+                                                 int ref, float two_se2) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W) return;
+  const size_t plane = (size_t)W * H, o = (size_t)y * W + x;
+  const size_t oU = (size_t)max(y - 1, 0) * W + x, oD = (size_t)min(y + 1, H - 1) * W + x;
+  const size_t oL = (size_t)y * W + max(x - 1, 0), oR = (size_t)y * W + min(x + 1, W - 1);
+  float sum = 0.f;
+  for (int k = 0; k < n; ++k) {
+    const float* I = f.img[k];
+    const float lap = grey_at(I, ch, plane, oU) + grey_at(I, ch, plane, oL) +
+                      grey_at(I, ch, plane, oR) + grey_at(I, ch, plane, oD) -
+                      4.f * grey_at(I, ch, plane, o);
+    const float C = fabsf(lap);
+    float S = 1.f, E;
+    if (ch == 3) {
+      const float R = I[o], G = I[plane + o], B = I[2 * plane + o];
+      const float mu = (R + G + B) / 3.f;
+      S = sqrtf(((R - mu) * (R - mu) + (G - mu) * (G - mu) + (B - mu) * (B - mu)) / 3.f);
+      const float e = (R - 0.5f) * (R - 0.5f) + (G - 0.5f) * (G - 0.5f) + (B - 0.5f) * (B - 0.5f);
+      E = expf(-e / two_se2);
+    } else {
+      const float e = (I[o] - 0.5f) * (I[o] - 0.5f);
+      E = expf(-e / two_se2);
+    }
+    float wt = C * S * E;
+    if (k != ref) wt *= fmaxf(f.ssim[k][o], 0.f);
+    wt += 1e-12f;
+    f.wout[k][o] = wt;
+    sum += wt;
+  }
+  for (int k = 0; k < n; ++k) f.wout[k][o] = f.wout[k][o] / sum;
+}
+
+struct MapPtrs {
+  const float* in[kMaxMaps];
+  float* out[kMaxMaps];
+};
+
+constexpr int kRedTW = 64, kRedTH = 8;
+
+__global__ __launch_bounds__(256) void k_reduce(MapPtrs m, int w, int h, int w2, int h2) {
+  __shared__ float src[2 * kRedTH + 3][2 * kRedTW + 3];
+  __shared__ float hb[2 * kRedTH + 3][kRedTW];
+  const float kf[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+  const float* in = m.in[blockIdx.z];
+  float* out = m.out[blockIdx.z];
+  const int ox = blockIdx.x * kRedTW, oy = blockIdx.y * kRedTH;
+  const int rows = 2 * kRedTH + 3, cols = 2 * kRedTW + 3;
+  for (int i = threadIdx.x; i < rows * cols; i += 256) {
+    const int yy = i / cols, xx = i % cols;
+    const int gy = min(max(2 * oy - 2 + yy, 0), h - 1), gx = min(max(2 * ox - 2 + xx, 0), w - 1);
+    src[yy][xx] = in[(size_t)gy * w + gx];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < rows * kRedTW; i += 256) {
+    const int yy = i / kRedTW, xx = i % kRedTW;
+    float s = 0.f;
+    for (int k = 0; k < 5; ++k) s += kf[k] * src[yy][2 * xx + k];
+    hb[yy][xx] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRedTH * kRedTW; i += 256) {
+    const int yy = i / kRedTW, xx = i % kRedTW;
+    const int gy = oy + yy, gx = ox + xx;
+    if (gy >= h2 || gx >= w2) continue;
+    float s = 0.f;
+    for (int k = 0; k < 5; ++k) s += kf[k] * hb[2 * yy + k][xx];
+    out[(size_t)gy * w2 + gx] = s;
+  }
+}
+
+// EXPAND of a coarse plane c (cw x chh) at fine pixel (x, y): rows first
+// (even 2i: (c[i-1] + 6 c[i] + c[i+1]) / 8, odd 2i+1: (c[i] + c[i+1]) / 2,
+// clamped coarse indices), then columns with the same rule.
+__device__ inline float expand_at(const float* __restrict__ c, int cw, int chh, int x, int y) {
+  const int i = x >> 1, j = y >> 1;
+  const int xm = max(i - 1, 0), x0 = min(i, cw - 1), xp = min(i + 1, cw - 1);
+  float rowv[3];
+  int nr;
+  int rj[3];
+  if ((y & 1) == 0) {
+    rj[0] = max(j - 1, 0); rj[1] = min(j, chh - 1); rj[2] = min(j + 1, chh - 1); nr = 3;
+  } else {
+    rj[0] = min(j, chh - 1); rj[1] = min(j + 1, chh - 1); nr = 2;
+  }
+  for (int q = 0; q < nr; ++q) {
+    const float* row = c + (size_t)rj[q] * cw;
+    rowv[q] = (x & 1) == 0 ? (row[xm] + 6.f * row[x0] + row[xp]) / 8.f : (row[x0] + row[xp]) / 2.f;
+  }
+  return nr == 3 ? (rowv[0] + 6.f * rowv[1] + rowv[2]) / 8.f : (rowv[0] + rowv[1]) / 2.f;
+}
+
+struct BlendPtrs {
+  const float* w[16];        // weights at level l
+  const float* wc[16];       // unused (kept for symmetry)
+  const float* g[16][3];     // image planes at level l
+  const float* gc[16][3];    // image planes at level l + 1
+  const float* rc[3];        // collapsed result at level l + 1
+  float* out[3];             // result at level l
+};
+
+__global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int ch, int w, int h, int cw,
+                                               int chh, int top) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= w) return;
+  const size_t o = (size_t)y * w + x;
+  for (int c = 0; c < ch; ++c) {
+    float acc = 0.f;
+    for (int k = 0; k < n; ++k) {
+      const float gi = b.g[k][c][o];
+      const float e = top ? 0.f : expand_at(b.gc[k][c], cw, chh, x, y);
+      acc += b.w[k][o] * (gi - e);
+    }
+    if (!top) acc += expand_at(b.rc[c], cw, chh, x, y);
+    b.out[c][o] = acc;
+  }
+}
+
+}  // namespace
+
+int merge_levels(int W, int H) {
+  const int m = W < H ? W : H;
+  int k = 0;
+  while ((8ll << (k + 1)) <= m) ++k;
+  return 1 + k;
+}
+
+// elements of one plane's pyramid levels 1..L-1
+size_t merge_pyr_elems(int W, int H, int levels) {
+  size_t tot = 0;
+  int w = W, h = H;
+  for (int l = 1; l < levels; ++l) {
+    w = (w + 1) / 2;
+    h = (h + 1) / 2;
+    tot += (size_t)w * h;
+  }
+  return tot;
+}
+
+hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
+                        const float* const* yeqs, int ref_index, const lnr_params& p,
+                        const MergeBufs& bufs, float* out, hipStream_t st) {
+  const int L = merge_levels(W, H);
+  const size_t N = (size_t)W * H;
+  const size_t tot = merge_pyr_elems(W, H, L);
+  int lw[32], lh[32];
+  size_t loff[33];
+  lw[0] = W; lh[0] = H; loff[0] = 0; loff[1] = 0;
+  for (int l = 1; l < L; ++l) {
+    lw[l] = (lw[l - 1] + 1) / 2;
+    lh[l] = (lh[l - 1] + 1) / 2;
+    loff[l + 1] = loff[l] + (size_t)lw[l] * lh[l];
+  }
+  hipError_t e;
+  // SSIM of every warped frame against the reference
+  FramePtrs fp;
+  for (int k = 0; k < n; ++k) {
+    fp.img[k] = imgs[k];
+    fp.ssim[k] = bufs.ssim + (size_t)k * N;
+    fp.wout[k] = bufs.w0 + (size_t)k * N;
+    if (k == ref_index) continue;
+    dim3 g((W + kSsimTW - 1) / kSsimTW, (H + kSsimTH - 1) / kSsimTH);
+    LNR_LAUNCH(k_ssim, g, dim3(256), 0, st, yeqs[ref_index], yeqs[k], W, H,
+                       p.ssim_radius, p.ssim_sigma, (float)p.ssim_c1, (float)p.ssim_c2,
+                       bufs.ssim + (size_t)k * N);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  LNR_LAUNCH(k_weights, dim3((W + 255) / 256, H), dim3(256), 0, st, fp, n, ch, W, H,
+                     ref_index, (float)(2.0 * p.sigma_e * p.sigma_e));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // Gaussian pyramids of every weight and image plane
+  const int maps = n * (ch + 1);
+  auto plane_ptr = [&](int z, int l) -> float* {
+    const int k = z / (ch + 1), q = z % (ch + 1);
+    if (l == 0)
+      return q == 0 ? bufs.w0 + (size_t)k * N : const_cast<float*>(imgs[k]) + (size_t)(q - 1) * N;
+    return bufs.pyr + (size_t)z * tot + loff[l];
+  };
+  for (int l = 1; l < L; ++l) {
+    MapPtrs mp;
+    for (int z = 0; z < maps; ++z) {
+      mp.in[z] = plane_ptr(z, l - 1);
+      mp.out[z] = plane_ptr(z, l);
+    }
+    dim3 g((lw[l] + kRedTW - 1) / kRedTW, (lh[l] + kRedTH - 1) / kRedTH, maps);
+    LNR_LAUNCH(k_reduce, g, dim3(256), 0, st, mp, lw[l - 1], lh[l - 1], lw[l], lh[l]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // blend + collapse, top level first
+  for (int l = L - 1; l >= 0; --l) {
+    BlendPtrs bp;
+    for (int k = 0; k < n; ++k) {
+      bp.w[k] = plane_ptr(k * (ch + 1), l);
+      bp.wc[k] = nullptr;
+      for (int c = 0; c < ch; ++c) {
+        bp.g[k][c] = plane_ptr(k * (ch + 1) + 1 + c, l);
+        bp.gc[k][c] = l + 1 < L ? plane_ptr(k * (ch + 1) + 1 + c, l + 1) : nullptr;
+      }
+    }
+    for (int c = 0; c < ch; ++c) {
+      bp.rc[c] = l + 1 < L ? bufs.acc + (size_t)c * tot + loff[l + 1] : nullptr;
+      bp.out[c] = l == 0 ? out + (size_t)c * N : bufs.acc + (size_t)c * tot + loff[l];
+    }
+    const int cw = l + 1 < L ? lw[l + 1] : 1, chh = l + 1 < L ? lh[l + 1] : 1;
+    LNR_LAUNCH(k_blend, dim3((lw[l] + 255) / 256, lh[l]), dim3(256), 0, st, bp, n, ch,
+                       lw[l], lh[l], cw, chh, l + 1 == L ? 1 : 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace lnr

@@ -1,0 +1,297 @@
+// k_search.hip -- the matcher of paper Sec. 2.2 on one pyramid level.
+//
+// k_warp_q8: the source level warped by the previous level's homography
+// (Eq. 3, evaluated as a resampling). Sample positions are computed in double
+// precision in a fixed operation order, rounded half up to 1/256 px, and
+// blended with integer Q16 weights, so the result is exact integers.
+//
+// k_search: one workgroup per full tile.
+//  1. The tile's reference region (every candidate's quadrants and patch) is
+//     staged in LDS; 4 threads per candidate sum its quadrants (Eq. 1), Eq. 2
+//     gates, and an LDS atomicMax on (C << 8 | 255 - index) picks the first
+//     largest cornerness.
+//  2. The warped source window around the corner (patch + 2R) is staged in
+//     LDS, 0 outside the image.
+//  3. Thread (dy, strip) scores KX consecutive dx. The SSD is computed exactly
+//     as  sum r^2 + sum w^2 - 2 sum r w : the cross term uses v_dot4_u32_u8 on
+//     the packed patch rows against window dwords realigned with
+//     v_alignbyte_b32 (about 0.5 VALU instructions per pixel-candidate); the
+//     window energies come from LDS row sums shared by all candidates.
+//  4. The argmin key (ssd << 32 | (|dx|+|dy|) << 16 | (dy+R) << 8 | (dx+R)) is
+//     reduced with wave shuffles and LDS; equal keys cannot occur, so the
+//     result does not depend on the reduction order.
+#include "lnr_device.h"
+#include "lnr_internal.h"
+
+namespace lnr {
+namespace {
+
+constexpr int KX = 8;        // candidates per thread (consecutive dx)
+constexpr int NW = 6;        // patch row dwords (2P+1 <= 24)
+constexpr int kRegion = 64;  // max staged reference region side
+
+__device__ inline long long q8(double s) {
+  double q = floor(s * 256.0 + 0.5);
+  if (!(q > -1073741824.0)) q = -1073741824.0;
+  if (q > 1073741824.0) q = 1073741824.0;
+  return (long long)q;
+}
+
+__global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src, int w, int h,
+                                                 const double* __restrict__ Hn,
+                                                 uint8_t* __restrict__ out) {
+  __shared__ double hp[9];
+  if (threadIdx.x == 0) pixel_homography(Hn, w, h, hp);
+  __syncthreads();
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= w) return;
+  const double X = (double)x, Y = (double)y;
+  const double den = (hp[6] * X + hp[7] * Y) + hp[8];
+  const double sx = ((hp[0] * X + hp[1] * Y) + hp[2]) / den;
+  const double sy = ((hp[3] * X + hp[4] * Y) + hp[5]) / den;
+  const long long QX = q8(sx), QY = q8(sy);
+  const long long ix = QX >> 8, iy = QY >> 8;
+  const uint32_t fx = (uint32_t)(QX & 255), fy = (uint32_t)(QY & 255);
+  const int x0 = (int)(ix < 0 ? 0 : (ix > w - 1 ? w - 1 : ix));
+  const int x1 = (int)(ix + 1 < 0 ? 0 : (ix + 1 > w - 1 ? w - 1 : ix + 1));
+  const int y0 = (int)(iy < 0 ? 0 : (iy > h - 1 ? h - 1 : iy));
+  const int y1 = (int)(iy + 1 < 0 ? 0 : (iy + 1 > h - 1 ? h - 1 : iy + 1));
+  const uint32_t p00 = src[(size_t)y0 * w + x0], p10 = src[(size_t)y0 * w + x1];
+  const uint32_t p01 = src[(size_t)y1 * w + x0], p11 = src[(size_t)y1 * w + x1];
+  const uint32_t acc = (256 - fx) * (256 - fy) * p00 + fx * (256 - fy) * p10 +
+                       (256 - fx) * fy * p01 + fx * fy * p11;
+  out[(size_t)y * w + x] = (uint8_t)((acc + 32768u) >> 16);
+}
+
+struct SearchShape {
+  int R, nstrips, nthreads;
+  int NR;        // window rows = 2P + 2R + 1
+  int wrow;      // window row stride in bytes (multiple of 16)
+  int ncand;     // 2R + 1
+};
+
+__device__ inline unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long u = __shfl_xor(v, o);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref,
+                                                 const uint8_t* __restrict__ wimg, int w, int h,
+                                                 SearchCfg c, SearchShape sh, int ntx,
+                                                 int32_t* __restrict__ corner_xy,
+                                                 int32_t* __restrict__ disp,
+                                                 uint32_t* __restrict__ ssd_out,
+                                                 uint8_t* __restrict__ flags) {
+  extern __shared__ __align__(16) uint8_t dyn[];
+  __shared__ uint8_t reg[kRegion * kRegion];
+  __shared__ uint32_t qsum[4 * 49];
+  __shared__ uint32_t best_key;
+  __shared__ uint32_t refp[(2 * kMaxPatchR + 1) * NW];
+  __shared__ uint32_t er_sum;
+  __shared__ unsigned long long wmin[16];
+
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tile = blockIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
+  const int side = 2 * ext + 1;
+  const int cx0 = tx * c.S + c.S / 2, cy0 = ty * c.S + c.S / 2;
+  const int rx0 = cx0 - ext, ry0 = cy0 - ext;
+
+  // 1. corners (Eq. 1-2) ----------------------------------------------------
+  for (int i = tid; i < side * side; i += nt) {
+    const int yy = i / side, xx = i % side;
+    reg[yy * kRegion + xx] = ref[(size_t)(ry0 + yy) * w + rx0 + xx];
+  }
+  if (tid == 0) { best_key = 0u; er_sum = 0u; }
+  __syncthreads();
+  const int nc1 = 2 * c.K + 1, ncand = nc1 * nc1;
+  for (int i = tid; i < 4 * ncand; i += nt) {
+    const int ci = i >> 2, q = i & 3;
+    const int a = ci % nc1 - c.K, b = ci / nc1 - c.K;
+    const int px = ext + c.g * a, py = ext + c.g * b;
+    // quadrants in cyclic order TL, TR, BR, BL
+    const int qx = (q == 0 || q == 3) ? px - c.r : px;
+    const int qy = (q <= 1) ? py - c.r : py;
+    uint32_t s = 0;
+    for (int yy = 0; yy < c.r; ++yy)
+      for (int xx = 0; xx < c.r; ++xx) s += reg[(qy + yy) * kRegion + qx + xx];
+    qsum[i] = s;
+  }
+  __syncthreads();
+  for (int ci = tid; ci < ncand; ci += nt) {
+    uint32_t C = 0, mn = 0xffffffffu;
+    for (int j = 0; j < 4; ++j) {
+      const int d = (int)qsum[4 * ci + ((j + 1) & 3)] - (int)qsum[4 * ci + j];
+      const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
+      C += ad;
+      mn = ad < mn ? ad : mn;
+    }
+    if (mn > (uint32_t)c.thr) atomicMax(&best_key, (C << 8) | (uint32_t)(255 - ci));
+  }
+  __syncthreads();
+  const uint32_t bk = best_key;
+  if (bk == 0u) {
+    if (tid == 0) {
+      corner_xy[2 * tile] = -1;
+      corner_xy[2 * tile + 1] = -1;
+      disp[2 * tile] = 0;
+      disp[2 * tile + 1] = 0;
+      ssd_out[tile] = 0;
+      flags[tile] = 0;
+    }
+    return;
+  }
+  const int bci = 255 - (int)(bk & 255u);
+  const int ba = bci % nc1 - c.K, bb = bci / nc1 - c.K;
+  const int px = cx0 + c.g * ba, py = cy0 + c.g * bb;  // corner, level coordinates
+  const int prx = ext + c.g * ba, pry = ext + c.g * bb;  // corner, region coordinates
+
+  // 2. packed reference patch and the warped window ------------------------
+  const int P = c.P, PW = 2 * P + 1, R = sh.R;
+  for (int i = tid; i < PW * NW; i += nt) {
+    const int row = i / NW, dw = i % NW;
+    uint32_t v = 0;
+    for (int k = 0; k < 4; ++k) {
+      const int col = dw * 4 + k;
+      if (col < PW) v |= (uint32_t)reg[(pry - P + row) * kRegion + prx - P + col] << (8 * k);
+    }
+    refp[i] = v;
+  }
+  uint8_t* win = dyn;
+  uint32_t* rowsq = reinterpret_cast<uint32_t*>(dyn + sh.NR * sh.wrow);
+  const int wx0 = px - P - R, wy0 = py - P - R;
+  for (int i = tid; i < sh.NR * sh.wrow; i += nt) {
+    const int yy = i / sh.wrow, xx = i % sh.wrow;
+    const int gx = wx0 + xx, gy = wy0 + yy;
+    win[i] = (gx >= 0 && gx < w && gy >= 0 && gy < h) ? wimg[(size_t)gy * w + gx] : (uint8_t)0;
+  }
+  __syncthreads();
+  // patch energy and window row energies: rowsq[y][k] = sum_c win[y][k + c]^2
+  {
+    uint32_t part = 0;
+    for (int i = tid; i < PW * PW; i += nt) {
+      const uint32_t v = reg[(pry - P + i / PW) * kRegion + prx - P + i % PW];
+      part += v * v;
+    }
+    if (part) atomicAdd(&er_sum, part);
+  }
+  for (int i = tid; i < sh.NR * sh.ncand; i += nt) {
+    const int yy = i / sh.ncand, k = i % sh.ncand;
+    const uint8_t* rowp = win + yy * sh.wrow + k;
+    uint32_t s = 0;
+    for (int cc = 0; cc < PW; ++cc) s += (uint32_t)rowp[cc] * rowp[cc];
+    rowsq[i] = s;
+  }
+  __syncthreads();
+
+  // 3. SSD of KX candidates per thread ---------------------------------------
+  unsigned long long key = ~0ull;
+  if (tid < sh.nthreads) {
+    const int j = tid / sh.nstrips, s = tid % sh.nstrips;  // dy index, strip
+    uint32_t acc[KX];
+#pragma unroll
+    for (int k = 0; k < KX; ++k) acc[k] = 0;
+    const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
+    const int rowdw = sh.wrow >> 2;
+    for (int i = 0; i < PW; ++i) {
+      const uint32_t* wr = wdw + (j + i) * rowdw + s * (KX / 4);
+      uint32_t wv[KX / 4 + NW + 1];
+#pragma unroll
+      for (int m = 0; m < KX / 4 + NW + 1; ++m) wv[m] = wr[m];
+      uint32_t rr[NW];
+#pragma unroll
+      for (int m = 0; m < NW; ++m) rr[m] = refp[i * NW + m];
+      uint32_t sft[4][KX / 4 + NW];
+#pragma unroll
+      for (int m = 0; m < KX / 4 + NW; ++m) {
+        sft[0][m] = wv[m];
+        sft[1][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 1);
+        sft[2][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 2);
+        sft[3][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 3);
+      }
+#pragma unroll
+      for (int k = 0; k < KX; ++k) {
+        const int q = k >> 2, rsh = k & 3;
+#pragma unroll
+        for (int m = 0; m < NW; ++m)
+          acc[k] = __builtin_amdgcn_udot4(sft[rsh][q + m], rr[m], acc[k], false);
+      }
+    }
+    const uint32_t er = er_sum;
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+      const int dxi = s * KX + k;
+      if (dxi >= sh.ncand) continue;
+      const int dx = dxi - R, dy = j - R;
+      if (px + dx - P < 0 || px + dx + P > w - 1 || py + dy - P < 0 || py + dy + P > h - 1)
+        continue;
+      uint32_t ew = 0;
+      for (int i = 0; i < PW; ++i) ew += rowsq[(j + i) * sh.ncand + dxi];
+      const uint32_t ssd = er + ew - 2u * acc[k];
+      const uint32_t l1 = (uint32_t)((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy));
+      const unsigned long long kk = ((unsigned long long)ssd << 32) |
+                                    ((unsigned long long)l1 << 16) |
+                                    ((unsigned long long)(dy + R) << 8) |
+                                    (unsigned long long)(dx + R);
+      key = kk < key ? kk : key;
+    }
+  }
+  // 4. argmin ---------------------------------------------------------------
+  key = wave_min_u64(key);
+  if ((tid & 63) == 0) wmin[tid >> 6] = key;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long b = ~0ull;
+    for (int i = 0; i < (nt + 63) / 64; ++i) b = wmin[i] < b ? wmin[i] : b;
+    corner_xy[2 * tile] = px;
+    corner_xy[2 * tile + 1] = py;
+    if (b == ~0ull) {
+      disp[2 * tile] = 0;
+      disp[2 * tile + 1] = 0;
+      ssd_out[tile] = 0;
+      flags[tile] = 1;
+    } else {
+      disp[2 * tile] = (int)(b & 255ull) - R;
+      disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - R;
+      ssd_out[tile] = (uint32_t)(b >> 32);
+      flags[tile] = 3;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
+                          hipStream_t st) {
+  dim3 grid((w + 255) / 256, h);
+  LNR_LAUNCH(k_warp_q8, grid, dim3(256), 0, st, src, w, h, Hn, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
+                         const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
+                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st) {
+  if (ntx * nty == 0) return hipSuccess;
+  SearchShape sh;
+  sh.R = R;
+  sh.ncand = 2 * R + 1;
+  sh.nstrips = (sh.ncand + KX - 1) / KX;
+  sh.nthreads = sh.ncand * sh.nstrips;
+  sh.NR = 2 * c.P + 2 * R + 1;
+  // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
+  const int need = (sh.nstrips * KX) + 4 * (NW + 1);
+  sh.wrow = (need + 15) / 16 * 16;
+  int block = (sh.nthreads + 63) / 64 * 64;
+  if (block < 64) block = 64;
+  const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4;
+  LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
+                     ntx, corner_xy, disp, ssd, flags);
+  return hipGetLastError();
+}
+
+}  // namespace lnr

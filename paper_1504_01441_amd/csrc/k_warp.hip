@@ -1,0 +1,126 @@
+// k_warp.hip -- backward warp of the source to the reference (paper Sec. 2.1:
+// the goal is to warp the source to the reference; Sec. 2.4: the dense flow).
+// The sample position m(x) = Hp1(x + F(x)) is computed in double precision (a
+// 5 MP frame needs position errors well below 1e-4 px), the samples are FP32
+// bilinear with clamp to edge. I420 chroma is upsampled by pixel repetition
+// and converted with BT.601 full-range coefficients; outputs are planar FP32
+// in [0, 1] plus the warped equalised luma (for the SSIM weight of Sec. 2.5).
+#include "lnr_device.h"
+#include "lnr_internal.h"
+
+namespace lnr {
+namespace {
+
+__device__ inline float bil(float p00, float p10, float p01, float p11, float ax, float ay) {
+  return (1.f - ay) * ((1.f - ax) * p00 + ax * p10) + ay * ((1.f - ax) * p01 + ax * p11);
+}
+
+__device__ inline void yuv_rgb(float Y, float U, float V, float& r, float& g, float& b) {
+  const float up = U - 128.f, vp = V - 128.f;
+  r = (Y + 1.402f * vp) / 255.f;
+  g = (Y - 0.344136f * up - 0.714136f * vp) / 255.f;
+  b = (Y + 1.772f * up) / 255.f;
+}
+
+__global__ __launch_bounds__(256) void k_bwarp(const uint8_t* __restrict__ y, int sy,
+                                               const uint8_t* __restrict__ u, int su,
+                                               const uint8_t* __restrict__ v, int sv,
+                                               const uint8_t* __restrict__ yeq, int W, int H,
+                                               const double* __restrict__ Hn,
+                                               const float* __restrict__ flow,
+                                               float* __restrict__ img, float* __restrict__ yw) {
+  __shared__ double hp[9];
+  if (threadIdx.x == 0) pixel_homography(Hn, W, H, hp);
+  __syncthreads();
+  const int px = blockIdx.x * blockDim.x + threadIdx.x, py = blockIdx.y;
+  if (px >= W) return;
+  const size_t plane = (size_t)W * H, o = (size_t)py * W + px;
+  const double X = (double)px + (double)flow[o];
+  const double Y = (double)py + (double)flow[plane + o];
+  const double den = (hp[6] * X + hp[7] * Y) + hp[8];
+  double sx = ((hp[0] * X + hp[1] * Y) + hp[2]) / den;
+  double sy2 = ((hp[3] * X + hp[4] * Y) + hp[5]) / den;
+  if (!(sx >= -1.0)) sx = -1.0;
+  if (sx > (double)W) sx = (double)W;
+  if (!(sy2 >= -1.0)) sy2 = -1.0;
+  if (sy2 > (double)H) sy2 = (double)H;
+  const double fx0 = floor(sx), fy0 = floor(sy2);
+  const float ax = (float)(sx - fx0), ay = (float)(sy2 - fy0);
+  const int ix = (int)fx0, iy = (int)fy0;
+  const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
+  const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
+  const float Yv = bil(y[(size_t)y0 * sy + x0], y[(size_t)y0 * sy + x1], y[(size_t)y1 * sy + x0],
+                       y[(size_t)y1 * sy + x1], ax, ay);
+  const size_t e00 = (size_t)y0 * W + x0, e10 = (size_t)y0 * W + x1;
+  const size_t e01 = (size_t)y1 * W + x0, e11 = (size_t)y1 * W + x1;
+  yw[o] = bil(yeq[e00], yeq[e10], yeq[e01], yeq[e11], ax, ay) / 255.f;
+  if (!u) {
+    img[o] = Yv / 255.f;
+    return;
+  }
+  const size_t c00u = (size_t)(y0 >> 1) * su + (x0 >> 1), c10u = (size_t)(y0 >> 1) * su + (x1 >> 1);
+  const size_t c01u = (size_t)(y1 >> 1) * su + (x0 >> 1), c11u = (size_t)(y1 >> 1) * su + (x1 >> 1);
+  const size_t c00v = (size_t)(y0 >> 1) * sv + (x0 >> 1), c10v = (size_t)(y0 >> 1) * sv + (x1 >> 1);
+  const size_t c01v = (size_t)(y1 >> 1) * sv + (x0 >> 1), c11v = (size_t)(y1 >> 1) * sv + (x1 >> 1);
+  const float Uv = bil(u[c00u], u[c10u], u[c01u], u[c11u], ax, ay);
+  const float Vv = bil(v[c00v], v[c10v], v[c01v], v[c11v], ax, ay);
+  float r, g, b;
+  yuv_rgb(Yv, Uv, Vv, r, g, b);
+  img[o] = r;
+  img[plane + o] = g;
+  img[2 * plane + o] = b;
+}
+
+__global__ __launch_bounds__(256) void k_frame_rgb(const uint8_t* __restrict__ y, int sy,
+                                                   const uint8_t* __restrict__ u, int su,
+                                                   const uint8_t* __restrict__ v, int sv, int W,
+                                                   int H, float* __restrict__ img) {
+  const int px = blockIdx.x * blockDim.x + threadIdx.x, py = blockIdx.y;
+  if (px >= W) return;
+  const size_t plane = (size_t)W * H, o = (size_t)py * W + px;
+  const float Yv = y[(size_t)py * sy + px];
+  if (!u) {
+    img[o] = Yv / 255.f;
+    return;
+  }
+  float r, g, b;
+  yuv_rgb(Yv, u[(size_t)(py >> 1) * su + (px >> 1)], v[(size_t)(py >> 1) * sv + (px >> 1)], r, g,
+          b);
+  img[o] = r;
+  img[plane + o] = g;
+  img[2 * plane + o] = b;
+}
+
+__global__ __launch_bounds__(256) void k_u8_unit(const uint8_t* __restrict__ in, size_t n,
+                                                 float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] / 255.f;
+}
+
+}  // namespace
+
+hipError_t launch_backward_warp(const uint8_t* y, int sy, const uint8_t* u, int su,
+                                const uint8_t* v, int sv, const uint8_t* yeq, int W, int H,
+                                const double* Hn, const float* flow, float* image, float* yeq_w,
+                                hipStream_t st) {
+  dim3 grid((W + 255) / 256, H);
+  LNR_LAUNCH(k_bwarp, grid, dim3(256), 0, st, y, sy, u, su, v, sv, yeq, W, H, Hn, flow,
+                     image, yeq_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_frame_rgb(const uint8_t* y, int sy, const uint8_t* u, int su,
+                            const uint8_t* v, int sv, int W, int H, float* image,
+                            hipStream_t st) {
+  dim3 grid((W + 255) / 256, H);
+  LNR_LAUNCH(k_frame_rgb, grid, dim3(256), 0, st, y, sy, u, su, v, sv, W, H, image);
+  return hipGetLastError();
+}
+
+hipError_t launch_u8_to_unit(const uint8_t* in, int W, int H, float* out, hipStream_t st) {
+  const size_t n = (size_t)W * H;
+  LNR_LAUNCH(k_u8_unit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace lnr

@@ -1,0 +1,675 @@
+// lnr_api.hip -- the C ABI of include/lnr.h: argument checks, the context's
+// workspace, and the order in which the kernels of one registration or merge
+// are enqueued on the caller's stream. No entry point synchronises the device
+// (the homographies and match counts stay in device memory between levels).
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lnr_internal.h"
+
+namespace lnr {
+// Event pairs recorded around kernel launches while tracing is on.
+struct Tracer {
+  struct Rec {
+    int slot;
+    hipEvent_t a, b;
+  };
+  std::vector<std::string> names;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+
+  int slot_of(const char* n) {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == n) return (int)i;
+    names.emplace_back(n);
+    return (int)names.size() - 1;
+  }
+  hipEvent_t take() {
+    if (pool_used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[pool_used++];
+  }
+  void reset() {
+    names.clear();
+    recs.clear();
+    pool_used = 0;
+  }
+  ~Tracer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+thread_local Tracer* g_tracer = nullptr;
+
+TraceScope::TraceScope(const char* name, hipStream_t st) {
+  if (!g_tracer) return;
+  Tracer& t = *g_tracer;
+  hipEvent_t a = t.take(), b = t.take();
+  if (!a || !b) return;
+  slot = (int)t.recs.size();
+  t.recs.push_back(Tracer::Rec{t.slot_of(name), a, b});
+  stream = st;
+  if (hipEventRecord(a, st) != hipSuccess) slot = -1;
+}
+
+TraceScope::~TraceScope() {
+  if (slot < 0 || !g_tracer) return;
+  (void)hipEventRecord(g_tracer->recs[slot].b, stream);
+}
+}  // namespace lnr
+
+struct lnr_ctx {
+  int device = 0;
+  std::string err;
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  bool tracing = false;
+  lnr::Tracer tracer;
+};
+
+namespace lnr {
+namespace {
+
+// Sets the thread's tracer for the duration of one API call.
+struct TraceGuard {
+  explicit TraceGuard(lnr_ctx* c) { g_tracer = (c && c->tracing) ? &c->tracer : nullptr; }
+  ~TraceGuard() { g_tracer = nullptr; }
+};
+
+__global__ void k_set_identity(double* H) {
+  if (threadIdx.x < 9) H[threadIdx.x] = (threadIdx.x % 4 == 0) ? 1.0 : 0.0;
+}
+
+lnr_status fail(lnr_ctx* ctx, lnr_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+lnr_status hip_fail(lnr_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, LNR_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define LNR_HIP(call)                                         \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);    \
+  } while (0)
+
+lnr_status check_params(lnr_ctx* ctx, const lnr_params* p) {
+  if (!p) return fail(ctx, LNR_E_ARG, "params is null");
+  const int ext = p->corner_half * p->corner_step + (p->quad_r > p->patch_r ? p->quad_r : p->patch_r);
+  if (p->tile < 16 || p->tile > 64) return fail(ctx, LNR_E_UNSUPPORTED, "tile must be in [16, 64]");
+  if (p->patch_r < 1 || p->patch_r > kMaxPatchR) return fail(ctx, LNR_E_UNSUPPORTED, "patch_r must be in [1, 11]");
+  if (p->corner_half < 0 || p->corner_half > 3 || p->corner_step < 1 || p->quad_r < 1)
+    return fail(ctx, LNR_E_UNSUPPORTED, "corner candidate grid out of range");
+  if (ext > p->tile / 2 - 1)
+    return fail(ctx, LNR_E_UNSUPPORTED, "corner candidates and patches must stay inside the tile");
+  if (p->corner_t < 0) return fail(ctx, LNR_E_UNSUPPORTED, "corner_t must be >= 0");
+  if (p->max_levels < 1 || p->max_levels > kMaxLevels) return fail(ctx, LNR_E_UNSUPPORTED, "max_levels must be in [1, 5]");
+  if (p->min_level_dim < p->tile) return fail(ctx, LNR_E_UNSUPPORTED, "min_level_dim must be >= tile");
+  if (p->radius0 < 0 || p->radius0 > kMaxRadius || p->radius_coarse < 0 || p->radius_coarse > kMaxRadius)
+    return fail(ctx, LNR_E_UNSUPPORTED, "search radii must be in [0, 32]");
+  if (p->weed_iters < 1 || p->weed_iters > 65536) return fail(ctx, LNR_E_UNSUPPORTED, "weed_iters must be in [1, 65536]");
+  if (p->weed_delta_min < 0 || p->weed_delta_pct < 0 || p->weed_delta_pct > 100)
+    return fail(ctx, LNR_E_UNSUPPORTED, "weeding delta out of range");
+  if (!(p->weed_eps > 0)) return fail(ctx, LNR_E_UNSUPPORTED, "weed_eps must be > 0");
+  if (p->dt_iters < 1 || p->dt_iters > 8) return fail(ctx, LNR_E_UNSUPPORTED, "dt_iters must be in [1, 8]");
+  if (!(p->sigma_s > 0) || !(p->sigma_r > 0)) return fail(ctx, LNR_E_UNSUPPORTED, "sigmas must be > 0");
+  if (p->ssim_radius < 1 || p->ssim_radius > 8 || !(p->ssim_sigma > 0))
+    return fail(ctx, LNR_E_UNSUPPORTED, "SSIM window out of range");
+  if (!(p->sigma_e > 0)) return fail(ctx, LNR_E_UNSUPPORTED, "sigma_e must be > 0");
+  return LNR_OK;
+}
+
+constexpr int kMaxSide = 6144;  // int64 normal equations and row LDS stay in range
+
+lnr_status check_frame(lnr_ctx* ctx, const lnr_frame* f, const char* name) {
+  if (!f) return fail(ctx, LNR_E_ARG, std::string(name) + " is null");
+  if (f->format != LNR_Y8 && f->format != LNR_I420)
+    return fail(ctx, LNR_E_UNSUPPORTED, std::string(name) + ": unknown format");
+  if (f->width < 1 || f->height < 1 || f->width > kMaxSide || f->height > kMaxSide)
+    return fail(ctx, LNR_E_UNSUPPORTED, std::string(name) + ": width/height must be in [1, 6144]");
+  if (!f->plane[0] || f->stride[0] < f->width)
+    return fail(ctx, LNR_E_ARG, std::string(name) + ": bad Y plane");
+  if (f->format == LNR_I420) {
+    if (f->width % 2 || f->height % 2)
+      return fail(ctx, LNR_E_ARG, std::string(name) + ": I420 needs even width and height");
+    if (!f->plane[1] || !f->plane[2] || f->stride[1] < f->width / 2 || f->stride[2] < f->width / 2)
+      return fail(ctx, LNR_E_ARG, std::string(name) + ": bad chroma planes");
+  }
+  return LNR_OK;
+}
+
+Geometry make_geometry(int W, int H, const lnr_params& p) {
+  Geometry g;
+  g.W = W;
+  g.H = H;
+  int levels = 1, w = W, h = H;
+  while (levels < p.max_levels) {
+    const int w2 = w / 2, h2 = h / 2;
+    if ((w2 < h2 ? w2 : h2) < p.min_level_dim) break;
+    w = w2;
+    h = h2;
+    ++levels;
+  }
+  g.levels = levels;
+  size_t off = 0;
+  int toff = 0;
+  w = W;
+  h = H;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    Level& L = g.lv[l];
+    if (l >= levels) {
+      L = Level{0, 0, 0, 0, toff, off};
+      continue;
+    }
+    if (l) { w /= 2; h /= 2; }
+    L.w = w; L.h = h;
+    L.ntx = w / p.tile; L.nty = h / p.tile;
+    L.tile_off = toff;
+    L.pix_off = off;
+    toff += L.ntx * L.nty;
+    off += (size_t)w * h;
+  }
+  g.tiles_total = toff;
+  g.pyr_bytes = off;
+  return g;
+}
+
+SearchCfg search_cfg(const lnr_params& p) {
+  SearchCfg c;
+  c.S = p.tile; c.P = p.patch_r; c.g = p.corner_step; c.K = p.corner_half; c.r = p.quad_r;
+  c.thr = p.corner_t * p.quad_r * p.quad_r;
+  return c;
+}
+
+struct Plan {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_size) return LNR_OK;
+  if (ctx->ws) {
+    hipError_t e = hipFree(ctx->ws);  // waits for work that may still use it
+    ctx->ws = nullptr;
+    ctx->ws_size = 0;
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipFree(workspace)");
+  }
+  const size_t want = bytes + bytes / 8;
+  hipError_t e = hipMalloc(&ctx->ws, want);
+  if (e != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(ctx, LNR_E_NOMEM, std::string("workspace hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  ctx->ws_size = want;
+  return LNR_OK;
+}
+
+struct WeedPlan {
+  size_t matches, tile_of, nmatch, mbits, best, G, cnt;
+};
+
+WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
+  WeedPlan w;
+  const int nt = ntiles > 0 ? ntiles : 1;
+  w.matches = pl.take(sizeof(int4) * (size_t)nt);
+  w.tile_of = pl.take(sizeof(int32_t) * (size_t)nt);
+  w.nmatch = pl.take(sizeof(int32_t));
+  w.mbits = pl.take(sizeof(unsigned long long) * (size_t)((nt + 63) / 64));
+  w.best = pl.take(sizeof(unsigned long long));
+  w.G = pl.take(sizeof(double) * 8 * (size_t)iters);
+  w.cnt = pl.take(sizeof(int32_t) * (size_t)iters);
+  return w;
+}
+
+WeedBufs weed_bufs(char* base, const WeedPlan& w) {
+  WeedBufs b;
+  b.matches = reinterpret_cast<int4*>(base + w.matches);
+  b.tile_of = reinterpret_cast<int32_t*>(base + w.tile_of);
+  b.nmatch = reinterpret_cast<int32_t*>(base + w.nmatch);
+  b.mbits = reinterpret_cast<unsigned long long*>(base + w.mbits);
+  b.best = reinterpret_cast<unsigned long long*>(base + w.best);
+  b.G = reinterpret_cast<double*>(base + w.G);
+  b.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
+  return b;
+}
+
+lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                              const lnr_params* p, lnr_registration* out, hipStream_t st) {
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if ((s = check_frame(ctx, ref, "ref")) != LNR_OK) return s;
+  if ((s = check_frame(ctx, src, "src")) != LNR_OK) return s;
+  if (!out) return fail(ctx, LNR_E_ARG, "out is null");
+  if (ref->width != src->width || ref->height != src->height || ref->format != src->format)
+    return fail(ctx, LNR_E_ARG, "ref and src differ in size or format");
+  const int W = ref->width, H = ref->height;
+  if (W < p->tile || H < p->tile) return fail(ctx, LNR_E_TOO_SMALL, "image smaller than one tile");
+  if (!out->corner_xy || !out->disp || !out->ssd || !out->flags || !out->counts || !out->H ||
+      !out->yeq_ref || !out->flow || !out->image || !out->yeq_warped)
+    return fail(ctx, LNR_E_ARG, "a required output pointer is null");
+  const Geometry g = make_geometry(W, H, *p);
+  const size_t N = (size_t)W * H;
+  Plan pl;
+  const size_t o_hist = pl.take(2 * 256 * sizeof(uint32_t));
+  const size_t o_pref = pl.take(g.pyr_bytes);
+  const size_t o_psrc = pl.take(g.pyr_bytes);
+  const size_t o_warp = pl.take(N);
+  const WeedPlan wp = plan_weed(pl, g.lv[0].ntx * g.lv[0].nty, p->weed_iters);
+  const size_t o_maps = pl.take(3 * N * sizeof(float));
+  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(float));
+  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  char* base = static_cast<char*>(ctx->ws);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + o_hist);
+  uint8_t* pref = reinterpret_cast<uint8_t*>(base + o_pref);
+  uint8_t* psrc = reinterpret_cast<uint8_t*>(base + o_psrc);
+  uint8_t* warped = reinterpret_cast<uint8_t*>(base + o_warp);
+  const WeedBufs wb = weed_bufs(base, wp);
+  float* maps = reinterpret_cast<float*>(base + o_maps);
+  float* coef = reinterpret_cast<float*>(base + o_coef);
+
+  LNR_HIP(hipMemsetAsync(hist, 0, 2 * 256 * sizeof(uint32_t), st));
+  LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
+  LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
+                         pref, psrc, nullptr, 2, st));
+  LNR_HIP(hipMemcpyAsync(out->yeq_ref, pref, N, hipMemcpyDeviceToDevice, st));
+  if (out->yeq_src) LNR_HIP(hipMemcpyAsync(out->yeq_src, psrc, N, hipMemcpyDeviceToDevice, st));
+  LNR_LAUNCH(k_set_identity, dim3(1), dim3(64), 0, st, out->H + 9 * g.levels);
+  LNR_HIP(hipGetLastError());
+  const SearchCfg cfg = search_cfg(*p);
+  for (int l = g.levels - 1; l >= 0; --l) {
+    const Level& L = g.lv[l];
+    const int R = l == 0 ? p->radius0 : p->radius_coarse;
+    const int nt = L.ntx * L.nty;
+    LNR_HIP(launch_warp_q8(psrc + L.pix_off, L.w, L.h, out->H + 9 * (l + 1), warped, st));
+    LNR_HIP(launch_search(pref + L.pix_off, warped, L.w, L.h, R, cfg, L.ntx, L.nty,
+                          out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
+                          out->ssd + L.tile_off, out->flags + L.tile_off, st));
+    LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
+                            out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
+                            out->H + 9 * l, out->counts + 4 * l, wb, st));
+    if (l == 0 && out->warped0)
+      LNR_HIP(hipMemcpyAsync(out->warped0, warped, N, hipMemcpyDeviceToDevice, st));
+  }
+  LNR_HIP(launch_flow(out->corner_xy, out->disp, out->flags, g.lv[0].ntx, g.lv[0].nty, p->tile,
+                      pref, W, H, *p, maps, coef, out->flow, out->ntilde, st));
+  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], src->format == LNR_I420 ? src->plane[1] : nullptr,
+                               src->stride[1], src->format == LNR_I420 ? src->plane[2] : nullptr,
+                               src->stride[2], psrc, W, H, out->H + 9, out->flow, out->image,
+                               out->yeq_warped, st));
+  return LNR_OK;
+}
+
+lnr_status merge_impl(lnr_ctx* ctx, int n, int ch, int W, int H, const float* const* imgs,
+                      const float* const* yeqs, int ref_index, const lnr_params* p, float* out,
+                      hipStream_t st, size_t extra_bytes, size_t* extra_off) {
+  const int L = merge_levels(W, H);
+  const size_t N = (size_t)W * H, tot = merge_pyr_elems(W, H, L);
+  Plan pl;
+  if (extra_off) *extra_off = pl.take(extra_bytes);
+  const size_t o_ssim = pl.take((size_t)n * N * sizeof(float));
+  const size_t o_w0 = pl.take((size_t)n * N * sizeof(float));
+  const size_t o_pyr = pl.take((size_t)n * (ch + 1) * (tot ? tot : 1) * sizeof(float));
+  const size_t o_acc = pl.take((size_t)ch * (tot ? tot : 1) * sizeof(float));
+  lnr_status s;
+  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  char* base = static_cast<char*>(ctx->ws);
+  MergeBufs b;
+  b.ssim = reinterpret_cast<float*>(base + o_ssim);
+  b.w0 = reinterpret_cast<float*>(base + o_w0);
+  b.pyr = reinterpret_cast<float*>(base + o_pyr);
+  b.acc = reinterpret_cast<float*>(base + o_acc);
+  (void)extra_off;
+  LNR_HIP(launch_merge(n, ch, W, H, imgs, yeqs, ref_index, *p, b, out, st));
+  return LNR_OK;
+}
+
+}  // namespace
+}  // namespace lnr
+
+using namespace lnr;
+
+extern "C" {
+
+lnr_status lnr_create(lnr_ctx** ctx, int32_t device) {
+  if (!ctx) return LNR_E_ARG;
+  *ctx = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return LNR_E_ARG;
+  lnr_ctx* c = new (std::nothrow) lnr_ctx();
+  if (!c) return LNR_E_NOMEM;
+  c->device = device;
+  *ctx = c;
+  return LNR_OK;
+}
+
+void lnr_destroy(lnr_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->ws) {
+    int prev = 0;
+    const bool have_prev = hipGetDevice(&prev) == hipSuccess;
+    if (hipSetDevice(ctx->device) == hipSuccess && hipFree(ctx->ws) != hipSuccess)
+      ctx->err = "hipFree(workspace) failed";
+    if (have_prev && hipSetDevice(prev) != hipSuccess) ctx->err = "hipSetDevice(restore) failed";
+  }
+  delete ctx;
+}
+
+const char* lnr_last_error(const lnr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void lnr_default_params(lnr_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->tile = 32;
+  p->patch_r = 10;         // 21 x 21 patches (Sec. 2.6)
+  p->corner_step = 2;      // grid of 1/16 of the tile (Sec. 2.6)
+  p->corner_half = 2;
+  p->quad_r = 10;
+  p->corner_t = 2;
+  p->max_levels = 5;       // Sec. 2.6
+  p->min_level_dim = 100;  // Sec. 2.6
+  p->radius_coarse = 10;   // Sec. 2.6
+  p->radius0 = 16;
+  p->weed_iters = 1024;
+  p->weed_delta_min = 8;
+  p->weed_delta_pct = 2;
+  p->dt_iters = 3;
+  p->weed_eps = 2.0;
+  p->sigma_s = 400.0;      // Sec. 2.6
+  p->sigma_r = 1.0;
+  p->n_min = 1e-30;
+  p->ssim_sigma = 1.5;
+  p->ssim_radius = 5;
+  p->ssim_c1 = 0.01 * 0.01;
+  p->ssim_c2 = 0.03 * 0.03;
+  p->sigma_e = 0.2;
+  p->seed = 0x1504014410ull;
+}
+
+lnr_status lnr_query_sizes(int32_t width, int32_t height, int32_t format, const lnr_params* p,
+                           lnr_sizes* out) {
+  if (!p || !out || width < 1 || height < 1) return LNR_E_ARG;
+  if (check_params(nullptr, p) != LNR_OK) return LNR_E_UNSUPPORTED;
+  const Geometry g = make_geometry(width, height, *p);
+  memset(out, 0, sizeof(*out));
+  out->levels = g.levels;
+  out->tiles_total = g.tiles_total;
+  for (int l = 0; l <= kMaxLevels; ++l) out->tile_off[l] = l < kMaxLevels ? g.lv[l].tile_off : g.tiles_total;
+  for (int l = 0; l < g.levels; ++l) {
+    out->tile_off[l + 1] = g.lv[l].tile_off + g.lv[l].ntx * g.lv[l].nty;
+    out->level_w[l] = g.lv[l].w;
+    out->level_h[l] = g.lv[l].h;
+  }
+  out->channels = format == LNR_I420 ? 3 : 1;
+  out->blend_levels = merge_levels(width, height);
+  return LNR_OK;
+}
+
+lnr_status lnr_register_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                             const lnr_params* p, lnr_registration* out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  return register_pair_impl(ctx, ref, src, p, out, (hipStream_t)stream);
+}
+
+lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
+                              const lnr_params* p, lnr_registration* outs, int32_t* ref_index,
+                              void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!frames || n < 2 || n > 16 || !outs || !ref_index)
+    return fail(ctx, LNR_E_ARG, "register_stack needs 2..16 frames, outputs and ref_index");
+  // Sec. 2.1: the shortest exposure is the reference (lowest index on ties)
+  int r = 0;
+  for (int k = 1; k < n; ++k)
+    if (frames[k].exposure < frames[r].exposure) r = k;
+  *ref_index = r;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  int j = 0;
+  for (int k = 0; k < n; ++k) {
+    if (k == r) continue;
+    lnr_status s = register_pair_impl(ctx, &frames[r], &frames[k], p, &outs[j], (hipStream_t)stream);
+    if (s != LNR_OK) return s;
+    ++j;
+  }
+  return LNR_OK;
+}
+
+lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t ref_index,
+                     const lnr_registration* regs, const lnr_params* p, float* out,
+                     void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (!frames || n < 1 || n > 16 || ref_index < 0 || ref_index >= n || !out || (n > 1 && !regs))
+    return fail(ctx, LNR_E_ARG, "merge needs 1..16 frames, a valid ref_index and outputs");
+  for (int k = 0; k < n; ++k)
+    if ((s = check_frame(ctx, &frames[k], "frame")) != LNR_OK) return s;
+  const lnr_frame& rf = frames[ref_index];
+  const int W = rf.width, H = rf.height, ch = rf.format == LNR_I420 ? 3 : 1;
+  for (int k = 0; k < n; ++k)
+    if (frames[k].width != W || frames[k].height != H || frames[k].format != rf.format)
+      return fail(ctx, LNR_E_ARG, "frames differ in size or format");
+  for (int k = 0; k + 1 < n; ++k)
+    if (!regs[k].image || !regs[k].yeq_warped || !regs[k].yeq_ref)
+      return fail(ctx, LNR_E_ARG, "registration outputs missing");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t N = (size_t)W * H;
+  // the reference image and its equalised luma live at the head of the
+  // workspace; size the whole workspace before anything is enqueued, so the
+  // merge below never reallocates it
+  const size_t ref_bytes = ((ch * N * sizeof(float) + 255) & ~(size_t)255) + N * sizeof(float);
+  {
+    const int L = merge_levels(W, H);
+    const size_t tot = merge_pyr_elems(W, H, L);
+    Plan pl;
+    pl.take(ref_bytes);
+    pl.take((size_t)n * N * 4);
+    pl.take((size_t)n * N * 4);
+    pl.take((size_t)n * (ch + 1) * (tot ? tot : 1) * 4);
+    pl.take((size_t)ch * (tot ? tot : 1) * 4);
+    if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  }
+  char* base = static_cast<char*>(ctx->ws);
+  float* ref_img = reinterpret_cast<float*>(base);
+  float* ref_yeq = reinterpret_cast<float*>(base + ((ch * N * sizeof(float) + 255) & ~(size_t)255));
+  LNR_HIP(launch_frame_rgb(rf.plane[0], rf.stride[0], ch == 3 ? rf.plane[1] : nullptr, rf.stride[1],
+                           ch == 3 ? rf.plane[2] : nullptr, rf.stride[2], W, H, ref_img, st));
+  const float* imgs[16];
+  const float* yeqs[16];
+  if (n > 1) {
+    LNR_HIP(launch_u8_to_unit(regs[0].yeq_ref, W, H, ref_yeq, st));
+  } else {
+    LNR_HIP(hipMemsetAsync(ref_yeq, 0, N * sizeof(float), st));
+  }
+  int j = 0;
+  for (int k = 0; k < n; ++k) {
+    if (k == ref_index) {
+      imgs[k] = ref_img;
+      yeqs[k] = ref_yeq;
+    } else {
+      imgs[k] = regs[j].image;
+      yeqs[k] = regs[j].yeq_warped;
+      ++j;
+    }
+  }
+  size_t extra_off = 0;
+  return merge_impl(ctx, n, ch, W, H, imgs, yeqs, ref_index, p, out, st, ref_bytes, &extra_off);
+}
+
+lnr_status lnr_stage_equalize(lnr_ctx* ctx, const uint8_t* img, int32_t w, int32_t h,
+                              int32_t stride, uint8_t* lut, uint8_t* out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!img || !out || w < 1 || h < 1 || stride < w || w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad equalize arguments");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  lnr_status s;
+  if ((s = ensure_ws(ctx, 256 * sizeof(uint32_t))) != LNR_OK) return s;
+  uint32_t* hist = static_cast<uint32_t*>(ctx->ws);
+  Geometry g;
+  memset(&g, 0, sizeof(g));
+  g.W = w; g.H = h; g.levels = 1;
+  g.lv[0].w = w; g.lv[0].h = h; g.lv[0].pix_off = 0;
+  LNR_HIP(hipMemsetAsync(hist, 0, 256 * sizeof(uint32_t), st));
+  LNR_HIP(launch_hist(img, stride, img, stride, w, h, hist, 1, st));
+  LNR_HIP(launch_lut_pyr(img, stride, img, stride, hist, g, out, out, lut, 1, st));
+  return LNR_OK;
+}
+
+lnr_status lnr_stage_warp_q8(lnr_ctx* ctx, const uint8_t* src, int32_t w, int32_t h,
+                             const double* H, uint8_t* out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!src || !H || !out || w < 1 || h < 1 || w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad warp arguments");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  LNR_HIP(launch_warp_q8(src, w, h, H, out, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_stage_search(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped, int32_t w,
+                            int32_t h, int32_t R, const lnr_params* p, int32_t* corner_xy,
+                            int32_t* disp, uint32_t* ssd, uint8_t* flags, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (!ref || !warped || !corner_xy || !disp || !ssd || !flags || w < 1 || h < 1 ||
+      w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad search arguments");
+  if (R < 0 || R > kMaxRadius) return fail(ctx, LNR_E_UNSUPPORTED, "radius must be in [0, 32]");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  LNR_HIP(launch_search(ref, warped, w, h, R, search_cfg(*p), w / p->tile, h / p->tile,
+                        corner_xy, disp, ssd, flags, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_stage_weed_fit(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t* disp,
+                              uint8_t* flags, int32_t ntiles, int32_t w, int32_t h,
+                              int32_t level, const lnr_params* p, const double* H_prev,
+                              double* H_out, int32_t* counts, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (ntiles < 0 || (ntiles > 0 && (!corner_xy || !disp || !flags)) || !H_prev || !H_out ||
+      !counts || w < 1 || h < 1 || w > kMaxSide || h > kMaxSide || level < 0 || level > 255)
+    return fail(ctx, LNR_E_ARG, "bad weed/fit arguments");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  Plan pl;
+  const WeedPlan wp = plan_weed(pl, ntiles, p->weed_iters);
+  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  const WeedBufs wb = weed_bufs(static_cast<char*>(ctx->ws), wp);
+  LNR_HIP(launch_weed_fit(corner_xy, disp, flags, ntiles, w, h, level, *p, H_prev, H_out, counts,
+                          wb, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t* disp,
+                          const uint8_t* flags, int32_t ntiles, const uint8_t* guide, int32_t w,
+                          int32_t h, const lnr_params* p, float* flow, float* ntilde,
+                          void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (!guide || !flow || w < 1 || h < 1 || w > kMaxSide || h > kMaxSide ||
+      ntiles != (w / p->tile) * (h / p->tile) || (ntiles > 0 && (!corner_xy || !disp || !flags)))
+    return fail(ctx, LNR_E_ARG, "bad flow arguments (ntiles must be the level-0 tile count)");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const size_t N = (size_t)w * h;
+  Plan pl;
+  const size_t o_maps = pl.take(3 * N * sizeof(float));
+  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(float));
+  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  char* base = static_cast<char*>(ctx->ws);
+  LNR_HIP(launch_flow(corner_xy, disp, flags, w / p->tile, h / p->tile, p->tile, guide, w, h, *p,
+                      reinterpret_cast<float*>(base + o_maps), reinterpret_cast<float*>(base + o_coef),
+                      flow, ntilde, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_stage_backward_warp(lnr_ctx* ctx, const lnr_frame* src, const uint8_t* yeq,
+                                   const double* H, const float* flow, float* image,
+                                   float* yeq_warped, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_frame(ctx, src, "src")) != LNR_OK) return s;
+  if (!yeq || !H || !flow || !image || !yeq_warped) return fail(ctx, LNR_E_ARG, "bad warp arguments");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const bool c = src->format == LNR_I420;
+  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], c ? src->plane[1] : nullptr,
+                               src->stride[1], c ? src->plane[2] : nullptr, src->stride[2], yeq,
+                               src->width, src->height, H, flow, image, yeq_warped,
+                               (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_stage_merge(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32_t h,
+                           const float* const* imgs, const float* const* yeqs, int32_t ref_index,
+                           const lnr_params* p, float* out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (n < 1 || n > 16 || (ch != 1 && ch != 3) || w < 1 || h < 1 || w > kMaxSide ||
+      h > kMaxSide || !imgs || !yeqs || !out || ref_index < 0 || ref_index >= n)
+    return fail(ctx, LNR_E_ARG, "bad merge arguments");
+  for (int k = 0; k < n; ++k)
+    if (!imgs[k] || !yeqs[k]) return fail(ctx, LNR_E_ARG, "null image or luma pointer");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  return merge_impl(ctx, n, ch, w, h, imgs, yeqs, ref_index, p, out, (hipStream_t)stream, 0,
+                    nullptr);
+}
+
+lnr_status lnr_trace_enable(lnr_ctx* ctx, int32_t on) {
+  if (!ctx) return LNR_E_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  for (auto& r : ctx->tracer.recs) (void)hipEventSynchronize(r.b);
+  ctx->tracer.reset();
+  ctx->tracing = on != 0;
+  return LNR_OK;
+}
+
+int32_t lnr_trace_read(lnr_ctx* ctx, lnr_trace_entry* out, int32_t max) {
+  if (!ctx) return LNR_E_ARG;
+  Tracer& t = ctx->tracer;
+  std::vector<double> ms(t.names.size(), 0.0);
+  std::vector<int> cnt(t.names.size(), 0);
+  for (auto& r : t.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipEventSynchronize");
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess)
+      return fail(ctx, LNR_E_HIP, "hipEventElapsedTime");
+    ms[r.slot] += e;
+    cnt[r.slot] += 1;
+  }
+  const int n = (int)t.names.size();
+  for (int i = 0; i < n && i < max && out; ++i) {
+    memset(&out[i], 0, sizeof(out[i]));
+    strncpy(out[i].name, t.names[i].c_str(), sizeof(out[i].name) - 1);
+    out[i].count = cnt[i];
+    out[i].ms_total = ms[i];
+  }
+  return n;
+}
+
+}  // extern "C"

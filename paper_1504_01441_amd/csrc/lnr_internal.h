@@ -1,0 +1,110 @@
+// lnr_internal.h -- declarations shared by the HIP sources of liblnr (GPU path
+// only). Kernels are launched through the host functions declared here; each
+// returns hipSuccess or the launch error.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lnr.h"
+
+namespace lnr {
+
+// Optional per-kernel timing: while a traced API call runs on this thread,
+// every kernel launch is bracketed by a TraceScope that records a HIP event
+// pair on the launch stream. Without tracing it does nothing.
+struct TraceScope {
+  TraceScope(const char* name, hipStream_t st);
+  ~TraceScope();
+  int slot = -1;
+  hipStream_t stream = nullptr;
+};
+
+#define LNR_LAUNCH(kernel, grid, block, lds, st, ...)                    \
+  do {                                                                    \
+    ::lnr::TraceScope lnr_ts_(#kernel, st);                               \
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);        \
+  } while (0)
+
+constexpr int kMaxLevels = 5;
+constexpr int kMaxRadius = 32;
+constexpr int kMaxPatchR = 11;   // patch rows fit in 6 dwords
+constexpr int kWeedWave = 64;
+
+struct Level {
+  int w, h;          // level size
+  int ntx, nty;      // full tiles
+  int tile_off;      // first tile of this level in the per-tile arrays
+  size_t pix_off;    // offset of this level in a pyramid buffer
+};
+
+struct Geometry {
+  int W, H, levels, tiles_total;
+  Level lv[kMaxLevels];
+  size_t pyr_bytes;  // bytes of one 8-bit pyramid (all levels)
+};
+
+// search-kernel constants derived from lnr_params
+struct SearchCfg {
+  int S, P, g, K, r;
+  int thr;           // corner_t * r * r
+};
+
+// ---- equalisation + pyramid (k_equalize.hip)
+hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int W, int H,
+                       uint32_t* hist /*[nframes][256]*/, int nframes, hipStream_t st);
+hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
+                          const uint32_t* hist, const Geometry& g, uint8_t* pyr0,
+                          uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st);
+
+// ---- warp + search (k_search.hip)
+hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
+                          hipStream_t st);
+hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
+                         const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
+                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st);
+
+// ---- weeding + level homography (k_weed.hip)
+struct WeedBufs {
+  int4* matches;         // [ntiles] (sx, sy, tx, ty) centred level coordinates
+  int32_t* tile_of;      // [ntiles] match index -> tile
+  int32_t* nmatch;       // [1]
+  unsigned long long* mbits;  // [ceil(ntiles/64)] union bitmask M
+  unsigned long long* best;   // [1] (count << 32) | (~iter)
+  double* G;             // [iters][8] hypothesis homographies
+  int32_t* cnt;          // [iters] inlier counts (-1: skipped)
+};
+hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
+                           int ntiles, int w, int h, int level, const lnr_params& p,
+                           const double* H_prev, double* H_out, int32_t* counts,
+                           const WeedBufs& b, hipStream_t st);
+
+// ---- domain-transform propagation (k_dt.hip)
+hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
+                       int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
+                       const lnr_params& p, float* maps /*[3][H][W]*/, float* coef /*[iters][256]*/,
+                       float* flow, float* ntilde, hipStream_t st);
+
+// ---- backward warp (k_warp.hip)
+hipError_t launch_backward_warp(const uint8_t* y, int sy, const uint8_t* u, int su,
+                                const uint8_t* v, int sv, const uint8_t* yeq, int W, int H,
+                                const double* Hn, const float* flow, float* image,
+                                float* yeq_w, hipStream_t st);
+hipError_t launch_frame_rgb(const uint8_t* y, int sy, const uint8_t* u, int su,
+                            const uint8_t* v, int sv, int W, int H, float* image,
+                            hipStream_t st);
+hipError_t launch_u8_to_unit(const uint8_t* in, int W, int H, float* out, hipStream_t st);
+
+// ---- merge (k_merge.hip)
+struct MergeBufs {
+  float* ssim;     // [n][H][W] SSIM maps (reference slot unused)
+  float* w0;       // [n][H][W] normalised weights (pyramid level 0)
+  float* pyr;      // [n (ch + 1)][levels 1..L-1] weight and image pyramids
+  float* acc;      // [ch][levels 1..L-1] collapsed result
+};
+size_t merge_pyr_elems(int W, int H, int levels);
+int merge_levels(int W, int H);
+hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
+                        const float* const* yeqs, int ref_index, const lnr_params& p,
+                        const MergeBufs& b, float* out, hipStream_t st);
+
+}  // namespace lnr
