@@ -17,6 +17,12 @@
 namespace lnr {
 namespace {
 
+struct FramePtrs {
+  const float* img[16];
+  const float* ssim[16];
+  float* wout[16];
+};
+
 constexpr int kMaxMaps = 64;
 constexpr int kSsimTW = 64, kSsimTH = 16, kSsimMaxR = 8;
 
@@ -39,11 +45,17 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
   }
   const int ox = blockIdx.x * kSsimTW, oy = blockIdx.y * kSsimTH;
   const int rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
+  // The variances are taken about a per-tile shift (the tile's first pixel):
+  // Var(x) = E[(x-c)^2] - E[x-c]^2 is exact for any c and, with c close to the
+  // local values, avoids the float cancellation of E[x^2] - E[x]^2 in flat
+  // regions, where the fusion weights are most sensitive.
+  const float ca = a[(size_t)min(oy, H - 1) * W + min(ox, W - 1)];
+  const float cb = b[(size_t)min(oy, H - 1) * W + min(ox, W - 1)];
   for (int i = tid; i < rows * cols; i += 256) {
     const int yy = i / cols, xx = i % cols;
     const int gy = min(max(oy + yy - r, 0), H - 1), gx = min(max(ox + xx - r, 0), W - 1);
-    sa[yy][xx] = a[(size_t)gy * W + gx];
-    sb[yy][xx] = b[(size_t)gy * W + gx];
+    sa[yy][xx] = a[(size_t)gy * W + gx] - ca;
+    sb[yy][xx] = b[(size_t)gy * W + gx] - cb;
   }
   __syncthreads();
   for (int i = tid; i < rows * kSsimTW; i += 256) {
@@ -65,29 +77,52 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     const int yy = i / kSsimTW, xx = i % kSsimTW;
     const int gy = oy + yy, gx = ox + xx;
     if (gy >= H || gx >= W) continue;
-    float m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
+    float d1 = 0, d2 = 0, s11 = 0, s22 = 0, s12 = 0;
     for (int k = 0; k <= 2 * r; ++k) {
       const float wk = gw[k];
-      m1 += wk * hs[0][yy + k][xx];
-      m2 += wk * hs[1][yy + k][xx];
+      d1 += wk * hs[0][yy + k][xx];
+      d2 += wk * hs[1][yy + k][xx];
       s11 += wk * hs[2][yy + k][xx];
       s22 += wk * hs[3][yy + k][xx];
       s12 += wk * hs[4][yy + k][xx];
     }
-    const float vx = s11 - m1 * m1, vy = s22 - m2 * m2, cxy = s12 - m1 * m2;
+    const float vx = s11 - d1 * d1, vy = s22 - d2 * d2, cxy = s12 - d1 * d2;
+    const float m1 = d1 + ca, m2 = d2 + cb;
     out[(size_t)gy * W + gx] = ((2.f * m1 * m2 + c1) * (2.f * cxy + c2)) /
                                ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2));
   }
 }
 
-struct FramePtrs {
-  const float* img[16];
-  const float* ssim[16];
-  float* wout[16];
-};
+__device__ inline double grey_at(const float* I, int ch, size_t plane, size_t o) {
+  return ch == 3 ? (0.299 * (double)I[o] + 0.587 * (double)I[plane + o]) + 0.114 * (double)I[2 * plane + o]
+                 : (double)I[o];
+}
 
-__device__ inline float grey_at(const float* I, int ch, size_t plane, size_t o) {
-  return ch == 3 ? 0.299f * I[o] + 0.587f * I[plane + o] + 0.114f * I[2 * plane + o] : I[o];
+// C * S * E (* max(SSIM, 0)) of frame k at one pixel. Contrast and saturation
+// are differences of nearly equal values in flat regions, and the normalised
+// weights divide by their sum, which can be ~1e-12 there: they are evaluated
+// in double precision.
+__device__ inline double raw_weight(const FramePtrs& f, int k, int ch, int ref, size_t plane,
+                                    size_t o, size_t oU, size_t oL, size_t oR, size_t oD,
+                                    float two_se2) {
+  const float* I = f.img[k];
+  const double lap = grey_at(I, ch, plane, oU) + grey_at(I, ch, plane, oL) +
+                     grey_at(I, ch, plane, oR) + grey_at(I, ch, plane, oD) -
+                     4.0 * grey_at(I, ch, plane, o);
+  const double C = fabs(lap);
+  double S = 1.0;
+  float e;
+  if (ch == 3) {
+    const double R = I[o], G = I[plane + o], B = I[2 * plane + o];
+    const double mu = (R + G + B) / 3.0;
+    S = sqrt(((R - mu) * (R - mu) + (G - mu) * (G - mu) + (B - mu) * (B - mu)) / 3.0);
+    e = (float)((R - 0.5) * (R - 0.5) + (G - 0.5) * (G - 0.5) + (B - 0.5) * (B - 0.5));
+  } else {
+    e = (float)((I[o] - 0.5) * (I[o] - 0.5));
+  }
+  double wt = C * S * (double)expf(-e / two_se2);
+  if (k != ref) wt *= fmax((double)f.ssim[k][o], 0.0);
+  return wt + 1e-12;
 }
 
 __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int W, int H,
@@ -97,31 +132,10 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
   const size_t plane = (size_t)W * H, o = (size_t)y * W + x;
   const size_t oU = (size_t)max(y - 1, 0) * W + x, oD = (size_t)min(y + 1, H - 1) * W + x;
   const size_t oL = (size_t)y * W + max(x - 1, 0), oR = (size_t)y * W + min(x + 1, W - 1);
-  float sum = 0.f;
-  for (int k = 0; k < n; ++k) {
-    const float* I = f.img[k];
-    const float lap = grey_at(I, ch, plane, oU) + grey_at(I, ch, plane, oL) +
-                      grey_at(I, ch, plane, oR) + grey_at(I, ch, plane, oD) -
-                      4.f * grey_at(I, ch, plane, o);
-    const float C = fabsf(lap);
-    float S = 1.f, E;
-    if (ch == 3) {
-      const float R = I[o], G = I[plane + o], B = I[2 * plane + o];
-      const float mu = (R + G + B) / 3.f;
-      S = sqrtf(((R - mu) * (R - mu) + (G - mu) * (G - mu) + (B - mu) * (B - mu)) / 3.f);
-      const float e = (R - 0.5f) * (R - 0.5f) + (G - 0.5f) * (G - 0.5f) + (B - 0.5f) * (B - 0.5f);
-      E = expf(-e / two_se2);
-    } else {
-      const float e = (I[o] - 0.5f) * (I[o] - 0.5f);
-      E = expf(-e / two_se2);
-    }
-    float wt = C * S * E;
-    if (k != ref) wt *= fmaxf(f.ssim[k][o], 0.f);
-    wt += 1e-12f;
-    f.wout[k][o] = wt;
-    sum += wt;
-  }
-  for (int k = 0; k < n; ++k) f.wout[k][o] = f.wout[k][o] / sum;
+  double sum = 0.0;
+  for (int k = 0; k < n; ++k) sum += raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2);
+  for (int k = 0; k < n; ++k)
+    f.wout[k][o] = (float)(raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2) / sum);
 }
 
 struct MapPtrs {
