@@ -5,7 +5,9 @@
 //
 //  k_ssim:    64x16 output tile; the two luma maps (+ halo) are staged in LDS,
 //             the five horizontal Gaussian sums are kept in LDS, then the
-//             vertical sums give SSIM.
+//             vertical sums give SSIM. The sums are double precision: SSIM
+//             divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat
+//             regions) and the fusion weights amplify them again.
 //  k_weights: per pixel, every frame's C * S * E (* max(SSIM, 0)) + 1e-12,
 //             normalised over the frames.
 //  k_reduce:  REDUCE ([1 4 6 4 1]/16 separable, clamped, even samples) of
@@ -28,12 +30,12 @@ constexpr int kSsimTW = 64, kSsimTH = 16, kSsimMaxR = 8;
 
 __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
                                               const float* __restrict__ b, int W, int H, int r,
-                                              double sigma, float c1, float c2,
+                                              double sigma, double c1, double c2,
                                               float* __restrict__ out) {
   __shared__ float sa[kSsimTH + 2 * kSsimMaxR][kSsimTW + 2 * kSsimMaxR];
   __shared__ float sb[kSsimTH + 2 * kSsimMaxR][kSsimTW + 2 * kSsimMaxR];
-  __shared__ float hs[5][kSsimTH + 2 * kSsimMaxR][kSsimTW];
-  __shared__ float gw[2 * kSsimMaxR + 1];
+  __shared__ double hs[5][kSsimTH + 2 * kSsimMaxR][kSsimTW];
+  __shared__ double gw[2 * kSsimMaxR + 1];
   const int tid = threadIdx.x;
   if (tid == 0) {
     double g[2 * kSsimMaxR + 1], s = 0;
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
       g[k + r] = exp(-(double)(k * k) / (2.0 * sigma * sigma));
       s += g[k + r];
     }
-    for (int k = 0; k <= 2 * r; ++k) gw[k] = (float)(g[k] / s);
+    for (int k = 0; k <= 2 * r; ++k) gw[k] = g[k] / s;
   }
   const int ox = blockIdx.x * kSsimTW, oy = blockIdx.y * kSsimTH;
   const int rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
@@ -60,9 +62,9 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
   __syncthreads();
   for (int i = tid; i < rows * kSsimTW; i += 256) {
     const int yy = i / kSsimTW, xx = i % kSsimTW;
-    float m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
+    double m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
     for (int k = 0; k <= 2 * r; ++k) {
-      const float p = sa[yy][xx + k], q = sb[yy][xx + k], wk = gw[k];
+      const double p = sa[yy][xx + k], q = sb[yy][xx + k], wk = gw[k];
       m1 += wk * p;
       m2 += wk * q;
       s11 += wk * (p * p);
@@ -77,19 +79,19 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     const int yy = i / kSsimTW, xx = i % kSsimTW;
     const int gy = oy + yy, gx = ox + xx;
     if (gy >= H || gx >= W) continue;
-    float d1 = 0, d2 = 0, s11 = 0, s22 = 0, s12 = 0;
+    double d1 = 0, d2 = 0, s11 = 0, s22 = 0, s12 = 0;
     for (int k = 0; k <= 2 * r; ++k) {
-      const float wk = gw[k];
+      const double wk = gw[k];
       d1 += wk * hs[0][yy + k][xx];
       d2 += wk * hs[1][yy + k][xx];
       s11 += wk * hs[2][yy + k][xx];
       s22 += wk * hs[3][yy + k][xx];
       s12 += wk * hs[4][yy + k][xx];
     }
-    const float vx = s11 - d1 * d1, vy = s22 - d2 * d2, cxy = s12 - d1 * d2;
-    const float m1 = d1 + ca, m2 = d2 + cb;
-    out[(size_t)gy * W + gx] = ((2.f * m1 * m2 + c1) * (2.f * cxy + c2)) /
-                               ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2));
+    const double vx = s11 - d1 * d1, vy = s22 - d2 * d2, cxy = s12 - d1 * d2;
+    const double m1 = d1 + ca, m2 = d2 + cb;
+    out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
+                                       ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
   }
 }
 
@@ -268,7 +270,7 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     if (k == ref_index) continue;
     dim3 g((W + kSsimTW - 1) / kSsimTW, (H + kSsimTH - 1) / kSsimTH);
     LNR_LAUNCH(k_ssim, g, dim3(256), 0, st, yeqs[ref_index], yeqs[k], W, H,
-                       p.ssim_radius, p.ssim_sigma, (float)p.ssim_c1, (float)p.ssim_c2,
+                       p.ssim_radius, p.ssim_sigma, p.ssim_c1, p.ssim_c2,
                        bufs.ssim + (size_t)k * N);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
