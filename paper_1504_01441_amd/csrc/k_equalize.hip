@@ -2,7 +2,7 @@
 // every input before matching: paper Sec. 3 opening) and the matching pyramid
 // (Sec. 2.2 / 2.6: up to 5 levels, 2x2 box mean rounded half up).
 //
-// k_hist: per-wave LDS histograms, one global atomic add per bin per block.
+// k_hist: LDS histograms (16 copies), one global atomic add per bin per block.
 // k_lut_pyr: each block rebuilds the 256-entry LUT from the histogram (prefix
 // sum in LDS), equalises a 64x64 block of Y and writes pyramid levels 1..L-1
 // of that block from LDS, so the pyramid costs no extra pass over HBM.
@@ -13,21 +13,27 @@ namespace {
 
 constexpr int kHistBlocks = 192;
 
+constexpr int kCopies = 16, kCopyStride = 257;  // odd stride: copies hit different banks
+
 __global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ y0, int s0,
                                               const uint8_t* __restrict__ y1, int s1, int W,
                                               int H, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t bins[4][256];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  for (int i = tid; i < 4 * 256; i += 256) (&bins[0][0])[i] = 0;
+  // neighbouring pixels share values, so lanes spread their LDS atomics over
+  // 16 copies of the bins
+  __shared__ uint32_t bins[kCopies * kCopyStride];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kCopies * kCopyStride; i += 256) bins[i] = 0;
   __syncthreads();
   const uint8_t* img = blockIdx.y ? y1 : y0;
   const int stride = blockIdx.y ? s1 : s0;
+  uint32_t* mine = bins + (tid & (kCopies - 1)) * kCopyStride;
   for (int row = blockIdx.x; row < H; row += gridDim.x) {
     const uint8_t* p = img + (size_t)row * stride;
-    for (int x = tid; x < W; x += 256) atomicAdd(&bins[wave][p[x]], 1u);
+    for (int x = tid; x < W; x += 256) atomicAdd(&mine[p[x]], 1u);
   }
   __syncthreads();
-  uint32_t s = bins[0][tid] + bins[1][tid] + bins[2][tid] + bins[3][tid];
+  uint32_t s = 0;
+  for (int c = 0; c < kCopies; ++c) s += bins[c * kCopyStride + tid];
   if (s) atomicAdd(&hist[blockIdx.y * 256 + tid], s);
 }
 

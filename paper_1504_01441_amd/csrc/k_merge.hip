@@ -13,7 +13,9 @@
 //  k_reduce:  REDUCE ([1 4 6 4 1]/16 separable, clamped, even samples) of
 //             every weight and image plane of one level, through LDS.
 //  k_blend:   from the top level down, R_l = sum_k W_k,l (G_k,l - E(G_k,l+1))
-//             + E(R_l+1), E the EXPAND rule; level 0 goes to the output.
+//             + E(R_l+1), E the EXPAND rule, on 64x16 tiles whose coarse
+//             neighbourhoods are staged (and row-expanded) in LDS; level 0
+//             goes to the output.
 #include "lnr_internal.h"
 
 namespace lnr {
@@ -26,17 +28,26 @@ struct FramePtrs {
 };
 
 constexpr int kMaxMaps = 64;
-constexpr int kSsimTW = 64, kSsimTH = 16, kSsimMaxR = 8;
+constexpr int kSsimTW = 64, kSsimTH = 8, kSsimMaxR = 8;
 
+// The five Gaussian sums are accumulated in double precision: SSIM divides
+// covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat regions) and the fusion
+// weights amplify them again near SSIM = 0. Inputs are shifted by a
+// per-column value (the tile's middle row), which keeps the moments small
+// without breaking separability (every output column uses one shift).
 __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
                                               const float* __restrict__ b, int W, int H, int r,
                                               double sigma, double c1, double c2,
                                               float* __restrict__ out) {
-  __shared__ float sa[kSsimTH + 2 * kSsimMaxR][kSsimTW + 2 * kSsimMaxR];
-  __shared__ float sb[kSsimTH + 2 * kSsimMaxR][kSsimTW + 2 * kSsimMaxR];
-  __shared__ double hs[5][kSsimTH + 2 * kSsimMaxR][kSsimTW];
-  __shared__ double gw[2 * kSsimMaxR + 1];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
+  const int rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
+  double* hv = reinterpret_cast<double*>(smem);                 // [5][rows][TW]
+  float* sa = reinterpret_cast<float*>(hv + 5 * rows * kSsimTW);  // [rows][cols]
+  float* sb = sa + rows * cols;
+  float* ca = sb + rows * cols;                                 // [cols] shifts
+  float* cb = ca + cols;
+  __shared__ double gw[2 * kSsimMaxR + 1];
   if (tid == 0) {
     double g[2 * kSsimMaxR + 1], s = 0;
     for (int k = -r; k <= r; ++k) {
@@ -46,52 +57,59 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     for (int k = 0; k <= 2 * r; ++k) gw[k] = g[k] / s;
   }
   const int ox = blockIdx.x * kSsimTW, oy = blockIdx.y * kSsimTH;
-  const int rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
-  // The variances are taken about a per-tile shift (the tile's first pixel):
-  // Var(x) = E[(x-c)^2] - E[x-c]^2 is exact for any c and, with c close to the
-  // local values, avoids the float cancellation of E[x^2] - E[x]^2 in flat
-  // regions, where the fusion weights are most sensitive.
-  const float ca = a[(size_t)min(oy, H - 1) * W + min(ox, W - 1)];
-  const float cb = b[(size_t)min(oy, H - 1) * W + min(ox, W - 1)];
+  const int midy = min(oy + kSsimTH / 2, H - 1);
+  for (int i = tid; i < cols; i += 256) {
+    const int gx = min(max(ox + i - r, 0), W - 1);
+    ca[i] = a[(size_t)midy * W + gx];
+    cb[i] = b[(size_t)midy * W + gx];
+  }
+  __syncthreads();
   for (int i = tid; i < rows * cols; i += 256) {
     const int yy = i / cols, xx = i % cols;
     const int gy = min(max(oy + yy - r, 0), H - 1), gx = min(max(ox + xx - r, 0), W - 1);
-    sa[yy][xx] = a[(size_t)gy * W + gx] - ca;
-    sb[yy][xx] = b[(size_t)gy * W + gx] - cb;
+    sa[i] = a[(size_t)gy * W + gx];
+    sb[i] = b[(size_t)gy * W + gx];
   }
   __syncthreads();
   for (int i = tid; i < rows * kSsimTW; i += 256) {
     const int yy = i / kSsimTW, xx = i % kSsimTW;
+    const double sfa = ca[xx + r], sfb = cb[xx + r];   // shift of output column xx
     double m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
+    const float* ra = sa + yy * cols + xx;
+    const float* rb = sb + yy * cols + xx;
     for (int k = 0; k <= 2 * r; ++k) {
-      const double p = sa[yy][xx + k], q = sb[yy][xx + k], wk = gw[k];
-      m1 += wk * p;
-      m2 += wk * q;
-      s11 += wk * (p * p);
-      s22 += wk * (q * q);
-      s12 += wk * (p * q);
+      const double dp = (double)ra[k] - sfa, dq = (double)rb[k] - sfb, wd = gw[k];
+      m1 += wd * dp;
+      m2 += wd * dq;
+      s11 += wd * (dp * dp);
+      s22 += wd * (dq * dq);
+      s12 += wd * (dp * dq);
     }
-    hs[0][yy][xx] = m1; hs[1][yy][xx] = m2; hs[2][yy][xx] = s11;
-    hs[3][yy][xx] = s22; hs[4][yy][xx] = s12;
+    const int n5 = rows * kSsimTW;
+    hv[i] = m1; hv[n5 + i] = m2; hv[2 * n5 + i] = s11; hv[3 * n5 + i] = s22; hv[4 * n5 + i] = s12;
   }
   __syncthreads();
   for (int i = tid; i < kSsimTH * kSsimTW; i += 256) {
     const int yy = i / kSsimTW, xx = i % kSsimTW;
     const int gy = oy + yy, gx = ox + xx;
     if (gy >= H || gx >= W) continue;
-    double d1 = 0, d2 = 0, s11 = 0, s22 = 0, s12 = 0;
+    const int n5 = rows * kSsimTW;
+    double da = 0, db = 0, s11 = 0, s22 = 0, s12 = 0;
     for (int k = 0; k <= 2 * r; ++k) {
-      const double wk = gw[k];
-      d1 += wk * hs[0][yy + k][xx];
-      d2 += wk * hs[1][yy + k][xx];
-      s11 += wk * hs[2][yy + k][xx];
-      s22 += wk * hs[3][yy + k][xx];
-      s12 += wk * hs[4][yy + k][xx];
+      const int j = (yy + k) * kSsimTW + xx;
+      const double wd = gw[k];
+      da += wd * hv[j];
+      db += wd * hv[n5 + j];
+      s11 += wd * hv[2 * n5 + j];
+      s22 += wd * hv[3 * n5 + j];
+      s12 += wd * hv[4 * n5 + j];
     }
-    const double vx = s11 - d1 * d1, vy = s22 - d2 * d2, cxy = s12 - d1 * d2;
-    const double m1 = d1 + ca, m2 = d2 + cb;
-    out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
-                                       ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
+    // central moments from moments about the shift c: with d = mean - c,
+    // Var = E[(x-c)^2] - d^2, Cov = E[(x-c)(y-c')] - d d'
+    const double vx = s11 - da * da, vy = s22 - db * db, cxy = s12 - da * db;
+    const double mu1 = da + (double)ca[xx + r], mu2 = db + (double)cb[xx + r];
+    out[(size_t)gy * W + gx] = (float)(((2.0 * mu1 * mu2 + c1) * (2.0 * cxy + c2)) /
+                                       ((mu1 * mu1 + mu2 * mu2 + c1) * (vx + vy + c2)));
   }
 }
 
@@ -134,10 +152,15 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
   const size_t plane = (size_t)W * H, o = (size_t)y * W + x;
   const size_t oU = (size_t)max(y - 1, 0) * W + x, oD = (size_t)min(y + 1, H - 1) * W + x;
   const size_t oL = (size_t)y * W + max(x - 1, 0), oR = (size_t)y * W + min(x + 1, W - 1);
+  // the raw weights keep 24-bit relative precision as floats once the
+  // cancelling differences inside them were taken in double precision
   double sum = 0.0;
-  for (int k = 0; k < n; ++k) sum += raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2);
-  for (int k = 0; k < n; ++k)
-    f.wout[k][o] = (float)(raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2) / sum);
+  for (int k = 0; k < n; ++k) {
+    const float wk = (float)raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2);
+    f.wout[k][o] = wk;
+    sum += (double)wk;
+  }
+  for (int k = 0; k < n; ++k) f.wout[k][o] = (float)((double)f.wout[k][o] / sum);
 }
 
 struct MapPtrs {
@@ -178,50 +201,73 @@ __global__ __launch_bounds__(256) void k_reduce(MapPtrs m, int w, int h, int w2,
   }
 }
 
-// EXPAND of a coarse plane c (cw x chh) at fine pixel (x, y): rows first
-// (even 2i: (c[i-1] + 6 c[i] + c[i+1]) / 8, odd 2i+1: (c[i] + c[i+1]) / 2,
-// clamped coarse indices), then columns with the same rule.
-__device__ inline float expand_at(const float* __restrict__ c, int cw, int chh, int x, int y) {
-  const int i = x >> 1, j = y >> 1;
-  const int xm = max(i - 1, 0), x0 = min(i, cw - 1), xp = min(i + 1, cw - 1);
-  float rowv[3];
-  int nr;
-  int rj[3];
-  if ((y & 1) == 0) {
-    rj[0] = max(j - 1, 0); rj[1] = min(j, chh - 1); rj[2] = min(j + 1, chh - 1); nr = 3;
-  } else {
-    rj[0] = min(j, chh - 1); rj[1] = min(j + 1, chh - 1); nr = 2;
-  }
-  for (int q = 0; q < nr; ++q) {
-    const float* row = c + (size_t)rj[q] * cw;
-    rowv[q] = (x & 1) == 0 ? (row[xm] + 6.f * row[x0] + row[xp]) / 8.f : (row[x0] + row[xp]) / 2.f;
-  }
-  return nr == 3 ? (rowv[0] + 6.f * rowv[1] + rowv[2]) / 8.f : (rowv[0] + rowv[1]) / 2.f;
-}
-
 struct BlendPtrs {
-  const float* w[16];        // weights at level l
-  const float* wc[16];       // unused (kept for symmetry)
+  const float* w[16];        // normalised weights at level l
   const float* g[16][3];     // image planes at level l
   const float* gc[16][3];    // image planes at level l + 1
   const float* rc[3];        // collapsed result at level l + 1
-  float* out[3];             // result at level l
+  float* out[3];             // collapsed result at level l
 };
 
+constexpr int kBW = 64, kBH = 16;                 // fine output tile
+constexpr int kCW = kBW / 2 + 2, kCH = kBH / 2 + 2;  // coarse tile with its EXPAND halo
+
+// One 64 x 16 tile of level l: R_l = sum_k W_k (G_k - E(G_k,l+1)) + E(R_l+1).
+// EXPAND (even 2i: (c[i-1] + 6 c[i] + c[i+1]) / 8, odd 2i+1: (c[i] + c[i+1]) / 2,
+// clamped coarse indices; rows first, then columns) reads the n + 1 coarse
+// planes of one channel from LDS tiles loaded once per block.
 __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int ch, int w, int h, int cw,
                                                int chh, int top) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= w) return;
-  const size_t o = (size_t)y * w + x;
+  extern __shared__ float sm[];
+  const int tid = threadIdx.x;
+  const int ox = blockIdx.x * kBW, oy = blockIdx.y * kBH;
+  const int cx0 = (ox >> 1) - 1, cy0 = (oy >> 1) - 1;
+  const int nm = top ? 0 : n + 1;
+  float* ct = sm;                       // [nm][kCH][kCW] coarse tiles
+  float* rx = sm + nm * kCH * kCW;      // [nm][kCH][kBW] expanded along x
   for (int c = 0; c < ch; ++c) {
-    float acc = 0.f;
-    for (int k = 0; k < n; ++k) {
-      const float gi = b.g[k][c][o];
-      const float e = top ? 0.f : expand_at(b.gc[k][c], cw, chh, x, y);
-      acc += b.w[k][o] * (gi - e);
+    if (!top) {
+      for (int i = tid; i < nm * kCH * kCW; i += 256) {
+        const int m = i / (kCH * kCW), r = (i / kCW) % kCH, q = i % kCW;
+        const float* src = m < n ? b.gc[m][c] : b.rc[c];
+        const int gy = min(max(cy0 + r, 0), chh - 1), gx = min(max(cx0 + q, 0), cw - 1);
+        ct[i] = src[(size_t)gy * cw + gx];
+      }
+      __syncthreads();
+      for (int i = tid; i < nm * kCH * kBW; i += 256) {
+        const int m = i / (kCH * kBW), r = (i / kBW) % kCH, fx = i % kBW;
+        const float* row = ct + (m * kCH + r) * kCW;
+        const int li = ((ox + fx) >> 1) - cx0;  // local index of coarse i
+        rx[i] = ((ox + fx) & 1) == 0 ? (row[li - 1] + 6.f * row[li] + row[li + 1]) / 8.f
+                                      : (row[li] + row[li + 1]) / 2.f;
+      }
+      __syncthreads();
     }
-    if (!top) acc += expand_at(b.rc[c], cw, chh, x, y);
-    b.out[c][o] = acc;
+    for (int i = tid; i < kBW * kBH; i += 256) {
+      const int fy = i / kBW, fx = i % kBW;
+      const int x = ox + fx, y = oy + fy;
+      if (x >= w || y >= h) continue;
+      const size_t o = (size_t)y * w + x;
+      const int lj = (y >> 1) - cy0;
+      const bool even = (y & 1) == 0;
+      float acc = 0.f;
+      for (int k = 0; k < n; ++k) {
+        float e = 0.f;
+        if (!top) {
+          const float* col = rx + k * kCH * kBW + fx;
+          e = even ? (col[(lj - 1) * kBW] + 6.f * col[lj * kBW] + col[(lj + 1) * kBW]) / 8.f
+                   : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
+        }
+        acc += b.w[k][o] * (b.g[k][c][o] - e);
+      }
+      if (!top) {
+        const float* col = rx + n * kCH * kBW + fx;
+        acc += even ? (col[(lj - 1) * kBW] + 6.f * col[lj * kBW] + col[(lj + 1) * kBW]) / 8.f
+                    : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
+      }
+      b.out[c][o] = acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -269,7 +315,10 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     fp.wout[k] = bufs.w0 + (size_t)k * N;
     if (k == ref_index) continue;
     dim3 g((W + kSsimTW - 1) / kSsimTW, (H + kSsimTH - 1) / kSsimTH);
-    LNR_LAUNCH(k_ssim, g, dim3(256), 0, st, yeqs[ref_index], yeqs[k], W, H,
+    const int r = p.ssim_radius, rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
+    const size_t lds = (size_t)rows * kSsimTW * 5 * 8 + (size_t)rows * cols * 8 +
+                       (size_t)cols * 8;
+    LNR_LAUNCH(k_ssim, g, dim3(256), lds, st, yeqs[ref_index], yeqs[k], W, H,
                        p.ssim_radius, p.ssim_sigma, p.ssim_c1, p.ssim_c2,
                        bufs.ssim + (size_t)k * N);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -300,7 +349,6 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     BlendPtrs bp;
     for (int k = 0; k < n; ++k) {
       bp.w[k] = plane_ptr(k * (ch + 1), l);
-      bp.wc[k] = nullptr;
       for (int c = 0; c < ch; ++c) {
         bp.g[k][c] = plane_ptr(k * (ch + 1) + 1 + c, l);
         bp.gc[k][c] = l + 1 < L ? plane_ptr(k * (ch + 1) + 1 + c, l + 1) : nullptr;
@@ -311,8 +359,10 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
       bp.out[c] = l == 0 ? out + (size_t)c * N : bufs.acc + (size_t)c * tot + loff[l];
     }
     const int cw = l + 1 < L ? lw[l + 1] : 1, chh = l + 1 < L ? lh[l + 1] : 1;
-    LNR_LAUNCH(k_blend, dim3((lw[l] + 255) / 256, lh[l]), dim3(256), 0, st, bp, n, ch,
-                       lw[l], lh[l], cw, chh, l + 1 == L ? 1 : 0);
+    const int top = l + 1 == L ? 1 : 0;
+    const size_t lds = top ? 0 : (size_t)(n + 1) * kCH * (kCW + kBW) * sizeof(float);
+    LNR_LAUNCH(k_blend, dim3((lw[l] + kBW - 1) / kBW, (lh[l] + kBH - 1) / kBH), dim3(256), lds,
+               st, bp, n, ch, lw[l], lh[l], cw, chh, top);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -3,18 +3,19 @@
 //
 // k_compact: one workgroup lists the valid matches of the level in tile order
 //   (centred level coordinates: source side p + d - c, reference side p - c).
-// k_weed: one wavefront per iteration. Every lane draws the same four indices
-//   from the counter-based SplitMix64 stream, solves the same 8x8 system in
-//   double precision (partial pivoting, fixed operation order), then the lanes
-//   test 64 matches at a time; ballots give the inlier bitmask and count. An
-//   accepted hypothesis (count > delta) ORs its bitmask into M with 64-bit
-//   atomics, so M is the same for any execution order (the paper's note that
-//   the iterations can be split freely). The best consensus is kept with a
+// k_hyp:   one thread per iteration draws four distinct indices from the
+//   counter-based SplitMix64 stream and solves the 8x8 system in double
+//   precision (partial pivoting, fixed operation order).
+// k_count: a (256 matches x 8 iterations) block tests inliers; wave ballots
+//   form each iteration's inlier bitmask row, and the counts are summed.
+// k_union: every accepted iteration (count > delta) ORs its row into M with
+//   64-bit atomics, so M is the same for any execution order (the paper's
+//   note that the iterations can be split freely); the best consensus is a
 //   64-bit atomicMax on (count << 32 | ~iteration).
-// k_fit: one wavefront re-tests the best hypothesis, sums the least-squares
+// k_fit: 512 threads re-test the best hypothesis, sum the least-squares
 //   normal equations of G: p -> p + d over its inliers exactly in int64 (so
-//   the sum is order-free), reduces them with shuffles, and lane 0 solves and
-//   composes H_l = H_{l+1} o G in double precision.
+//   the sum is order-free), reduce them, and one thread solves and composes
+//   H_l = H_{l+1} o G in double precision.
 #include "lnr_device.h"
 #include "lnr_internal.h"
 
@@ -144,46 +145,81 @@ __device__ bool hypothesis(const int4* __restrict__ matches, int N, int it, cons
   return solve8(A, g);
 }
 
-__global__ __launch_bounds__(256) void k_weed(const int4* __restrict__ matches,
-                                              const int32_t* __restrict__ nmatch, WeedArgs a,
-                                              unsigned long long* __restrict__ mbits,
-                                              unsigned long long* __restrict__ best,
-                                              double* __restrict__ Gout,
-                                              int32_t* __restrict__ cnt_out) {
-  extern __shared__ unsigned long long bal[];  // [4][nwords]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int it = blockIdx.x * 4 + wave;
-  const int N = *nmatch;
+// One thread per iteration: draw + 4-point fit (flag -1 when degenerate).
+__global__ __launch_bounds__(64) void k_hyp(const int4* __restrict__ matches,
+                                            const int32_t* __restrict__ nmatch, WeedArgs a,
+                                            double* __restrict__ Gout,
+                                            int32_t* __restrict__ cnt) {
+  const int it = blockIdx.x * 64 + threadIdx.x;
   if (it >= a.iters) return;
+  const int N = *nmatch;
   double g[8];
   if (N < 4 || !hypothesis(matches, N, it, a, g)) {
-    if (lane == 0) cnt_out[it] = -1;
+    cnt[it] = -1;
     return;
   }
-  const int nwords = (N + 63) / 64;
-  unsigned long long* mine = bal + (size_t)wave * nwords;
-  int count = 0;
-  for (int wi = 0; wi < nwords; ++wi) {
-    const int k = wi * 64 + lane;
-    const bool in = k < N && is_inlier(g, matches[k], a.eps2);
+  for (int i = 0; i < 8; ++i) Gout[(size_t)it * 8 + i] = g[i];
+  cnt[it] = 0;
+}
+
+constexpr int kItPerBlock = 8;
+
+// Block (match chunk of 256, 8 iterations): inlier tests, ballots to the
+// per-iteration bitmask rows, counts added per iteration.
+__global__ __launch_bounds__(256) void k_count(const int4* __restrict__ matches,
+                                               const int32_t* __restrict__ nmatch, WeedArgs a,
+                                               const double* __restrict__ G,
+                                               int32_t* __restrict__ cnt,
+                                               unsigned long long* __restrict__ bal, int wstride) {
+  __shared__ double gs[kItPerBlock][8];
+  __shared__ int ok[kItPerBlock];
+  __shared__ int wc[kItPerBlock][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int it0 = blockIdx.y * kItPerBlock;
+  const int N = *nmatch;
+  if (tid < kItPerBlock) ok[tid] = (it0 + tid < a.iters) && cnt[it0 + tid] >= 0;
+  if (tid < kItPerBlock * 8) {
+    const int q = tid / 8, i = tid % 8;
+    gs[q][i] = (it0 + q < a.iters) ? G[(size_t)(it0 + q) * 8 + i] : 0.0;
+  }
+  __syncthreads();
+  const int k = blockIdx.x * 256 + tid;
+  const int word = k >> 6;
+  if (N < 4 || blockIdx.x * 256 >= N) return;  // uniform per block
+  const int4 m = k < N ? matches[k] : make_int4(0, 0, 0, 0);
+  for (int q = 0; q < kItPerBlock; ++q) {
+    if (!ok[q]) continue;
+    const bool in = k < N && is_inlier(gs[q], m, a.eps2);
     const unsigned long long b = __ballot(in);
-    count += __popcll(b);
-    if (lane == 0) mine[wi] = b;
-  }
-  if (lane == 0) {
-    cnt_out[it] = count;
-    for (int i = 0; i < 8; ++i) Gout[(size_t)it * 8 + i] = g[i];
-    atomicMax(best, ((unsigned long long)(uint32_t)count << 32) | (unsigned long long)(~(uint32_t)it));
-  }
-  if (count > weed_delta(N, a)) {
-    // lane 0 wrote the ballots; LDS operations of one wavefront complete in
-    // order, the fence keeps the compiler from moving the reads above them
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    for (int wi = lane; wi < nwords; wi += 64) {
-      const unsigned long long b = mine[wi];
-      if (b) atomicOr(&mbits[wi], b);
+    if (lane == 0) {
+      if (word * 64 < N) bal[(size_t)(it0 + q) * wstride + word] = b;
+      wc[q][wave] = __popcll(b);
     }
+  }
+  __syncthreads();
+  if (tid < kItPerBlock && ok[tid]) {
+    const int s = wc[tid][0] + wc[tid][1] + wc[tid][2] + wc[tid][3];
+    if (s) atomicAdd(&cnt[it0 + tid], s);
+  }
+}
+
+// Accepted iterations (count > delta) OR their inlier rows into M; the best
+// consensus is the largest (count << 32 | ~iteration).
+__global__ __launch_bounds__(64) void k_union(const int32_t* __restrict__ nmatch, WeedArgs a,
+                                              const int32_t* __restrict__ cnt,
+                                              const unsigned long long* __restrict__ bal,
+                                              int wstride, unsigned long long* __restrict__ mbits,
+                                              unsigned long long* __restrict__ best) {
+  const int it = blockIdx.y;
+  const int wi = blockIdx.x * 64 + threadIdx.x;
+  const int N = *nmatch;
+  const int c = cnt[it];
+  if (N < 4 || c < 0) return;
+  if (wi == 0)
+    atomicMax(best, ((unsigned long long)(uint32_t)c << 32) | (unsigned long long)(~(uint32_t)it));
+  if (c > weed_delta(N, a) && wi * 64 < N) {
+    const unsigned long long b = bal[(size_t)it * wstride + wi];
+    if (b) atomicOr(&mbits[wi], b);
   }
 }
 
@@ -196,30 +232,33 @@ __device__ inline long long wave_sum_i64(long long v) {
 // index of the upper-triangle entry (i <= j) of the 8x8 normal matrix
 __device__ inline int tri(int i, int j) { return i * 8 - (i * (i - 1)) / 2 + (j - i); }
 
-__global__ __launch_bounds__(64) void k_fit(const int4* __restrict__ matches,
-                                            const int32_t* __restrict__ tile_of,
-                                            const int32_t* __restrict__ nmatch, WeedArgs a,
-                                            const unsigned long long* __restrict__ mbits,
-                                            const unsigned long long* __restrict__ best,
-                                            const double* __restrict__ Gall,
-                                            uint8_t* __restrict__ flags, int w, int h,
-                                            const double* __restrict__ Hprev,
-                                            double* __restrict__ Hout,
-                                            int32_t* __restrict__ counts) {
-  const int lane = threadIdx.x;
+constexpr int kFitThreads = 512;
+
+__global__ __launch_bounds__(kFitThreads) void k_fit(const int4* __restrict__ matches,
+                                                     const int32_t* __restrict__ tile_of,
+                                                     const int32_t* __restrict__ nmatch, WeedArgs a,
+                                                     const unsigned long long* __restrict__ mbits,
+                                                     const unsigned long long* __restrict__ best,
+                                                     const double* __restrict__ Gall,
+                                                     uint8_t* __restrict__ flags, int w, int h,
+                                                     const double* __restrict__ Hprev,
+                                                     double* __restrict__ Hout,
+                                                     int32_t* __restrict__ counts) {
+  __shared__ long long part[kFitThreads / 64][45];
+  __shared__ long long tot[45];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = *nmatch;
   const unsigned long long bkey = *best;
   const int bc = N >= 4 && bkey ? (int)(bkey >> 32) : -1;
   const int bi = N >= 4 && bkey ? (int)(~(uint32_t)(bkey & 0xffffffffull)) : -1;
   const bool fit = bc > weed_delta(N, a);
   double g[8];
-  if (fit)
-    for (int i = 0; i < 8; ++i) g[i] = Gall[(size_t)bi * 8 + i];
+  for (int i = 0; i < 8; ++i) g[i] = fit ? Gall[(size_t)bi * 8 + i] : 0.0;
   long long ata[36], atb[8];
   for (int i = 0; i < 36; ++i) ata[i] = 0;
   for (int i = 0; i < 8; ++i) atb[i] = 0;
-  int m = 0;
-  for (int k = lane; k < N; k += 64) {
+  long long m = 0;
+  for (int k = tid; k < N; k += kFitThreads) {
     const int4 mt = matches[k];
     const bool inM = (mbits[k >> 6] >> (k & 63)) & 1ull;
     const bool sel = fit && is_inlier(g, mt, a.eps2);
@@ -235,16 +274,30 @@ __global__ __launch_bounds__(64) void k_fit(const int4* __restrict__ matches,
       atb[i] += r1[i] * u + r2[i] * v;
     }
   }
+  // exact (order-free) int64 reduction: wave shuffles, then across waves
   for (int i = 0; i < 36; ++i) ata[i] = wave_sum_i64(ata[i]);
   for (int i = 0; i < 8; ++i) atb[i] = wave_sum_i64(atb[i]);
-  for (int o = 32; o > 0; o >>= 1) m += __shfl_xor(m, o);
-  if (lane != 0) return;
+  m = wave_sum_i64(m);
+  if (lane == 0) {
+    for (int i = 0; i < 36; ++i) part[wave][i] = ata[i];
+    for (int i = 0; i < 8; ++i) part[wave][36 + i] = atb[i];
+    part[wave][44] = m;
+  }
+  __syncthreads();
+  if (tid < 45) {
+    long long s = 0;
+    for (int q = 0; q < kFitThreads / 64; ++q) s += part[q][tid];
+    tot[tid] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  const int msel = (int)tot[44];
   counts[0] = N;
-  counts[1] = m;
+  counts[1] = msel;
   counts[2] = bc;
   counts[3] = bi;
   for (int i = 0; i < 9; ++i) Hout[i] = Hprev[i];
-  if (m < 4) return;
+  if (msel < 4) return;
   const int ox = w / 2, oy = h / 2;
   int k = 0;
   const int mx = ox > oy ? (ox > 1 ? ox : 1) : (oy > 1 ? oy : 1);
@@ -253,10 +306,10 @@ __global__ __launch_bounds__(64) void k_fit(const int4* __restrict__ matches,
   double A[8 * 9], hs[8];
   for (int i = 0; i < 8; ++i) {
     for (int j = 0; j < 8; ++j) {
-      const long long v = i <= j ? ata[tri(i, j)] : ata[tri(j, i)];
+      const long long v = i <= j ? tot[tri(i, j)] : tot[tri(j, i)];
       A[i * 9 + j] = ldexp((double)v, -k * (deg[i] + deg[j]));
     }
-    A[i * 9 + 8] = ldexp((double)atb[i], -k * (deg[i] + 1));
+    A[i * 9 + 8] = ldexp((double)tot[36 + i], -k * (deg[i] + 1));
   }
   if (!solve8(A, hs)) return;
   double Gc[9];
@@ -293,22 +346,26 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
   a.delta_pct = p.weed_delta_pct;
   a.eps2 = p.weed_eps * p.weed_eps;
   a.seed = p.seed;
+  hipError_t e;
   if (ntiles > 0) {
-    LNR_LAUNCH(k_compact, dim3(1), dim3(1024), 0, st, corner_xy, disp, flags, ntiles, w,
-                       h, b.matches, b.tile_of, b.nmatch, b.mbits, b.best);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t lds = (size_t)4 * ((ntiles + 63) / 64) * sizeof(unsigned long long);
-    LNR_LAUNCH(k_weed, dim3((a.iters + 3) / 4), dim3(256), lds, st, b.matches, b.nmatch,
-                       a, b.mbits, b.best, b.G, b.cnt);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int words = (ntiles + 63) / 64;
+    LNR_LAUNCH(k_compact, dim3(1), dim3(1024), 0, st, corner_xy, disp, flags, ntiles, w, h,
+               b.matches, b.tile_of, b.nmatch, b.mbits, b.best);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    LNR_LAUNCH(k_hyp, dim3((a.iters + 63) / 64), dim3(64), 0, st, b.matches, b.nmatch, a, b.G,
+               b.cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    LNR_LAUNCH(k_count, dim3((ntiles + 255) / 256, (a.iters + kItPerBlock - 1) / kItPerBlock),
+               dim3(256), 0, st, b.matches, b.nmatch, a, b.G, b.cnt, b.bal, words);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    LNR_LAUNCH(k_union, dim3((words + 63) / 64, a.iters), dim3(64), 0, st, b.nmatch, a, b.cnt,
+               b.bal, words, b.mbits, b.best);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   } else {
-    hipError_t e = hipMemsetAsync(b.nmatch, 0, sizeof(int32_t), st);
-    if (e != hipSuccess) return e;
+    if ((e = hipMemsetAsync(b.nmatch, 0, sizeof(int32_t), st)) != hipSuccess) return e;
   }
-  LNR_LAUNCH(k_fit, dim3(1), dim3(64), 0, st, b.matches, b.tile_of, b.nmatch, a, b.mbits,
-                     b.best, b.G, flags, w, h, H_prev, H_out, counts);
+  LNR_LAUNCH(k_fit, dim3(1), dim3(kFitThreads), 0, st, b.matches, b.tile_of, b.nmatch, a,
+             b.mbits, b.best, b.G, flags, w, h, H_prev, H_out, counts);
   return hipGetLastError();
 }
 

@@ -218,7 +218,7 @@ lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes) {
 }
 
 struct WeedPlan {
-  size_t matches, tile_of, nmatch, mbits, best, G, cnt;
+  size_t matches, tile_of, nmatch, mbits, best, G, cnt, bal;
 };
 
 WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
@@ -231,6 +231,7 @@ WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
   w.best = pl.take(sizeof(unsigned long long));
   w.G = pl.take(sizeof(double) * 8 * (size_t)iters);
   w.cnt = pl.take(sizeof(int32_t) * (size_t)iters);
+  w.bal = pl.take(sizeof(unsigned long long) * (size_t)iters * ((nt + 63) / 64));
   return w;
 }
 
@@ -243,6 +244,7 @@ WeedBufs weed_bufs(char* base, const WeedPlan& w) {
   b.best = reinterpret_cast<unsigned long long*>(base + w.best);
   b.G = reinterpret_cast<double*>(base + w.G);
   b.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
+  b.bal = reinterpret_cast<unsigned long long*>(base + w.bal);
   return b;
 }
 

@@ -72,6 +72,7 @@ struct WeedBufs {
   unsigned long long* best;   // [1] (count << 32) | (~iter)
   double* G;             // [iters][8] hypothesis homographies
   int32_t* cnt;          // [iters] inlier counts (-1: skipped)
+  unsigned long long* bal;  // [iters][ceil(ntiles/64)] inlier bitmask rows
 };
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
