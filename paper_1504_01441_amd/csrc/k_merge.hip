@@ -3,7 +3,7 @@
 // between the equalised reference and each warped frame (Wang et al.:
 // Gaussian window, five filterings), blended with Laplacian pyramids.
 //
-//  k_ssim:    64x16 output tile; the two luma maps (+ halo) are staged in LDS,
+//  k_ssim:    32x16 output tile; the two luma maps (+ halo) are staged in LDS,
 //             the five horizontal Gaussian sums are kept in LDS, then the
 //             vertical sums give SSIM. The sums are double precision: SSIM
 //             divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat
@@ -28,13 +28,12 @@ struct FramePtrs {
 };
 
 constexpr int kMaxMaps = 64;
-constexpr int kSsimTW = 64, kSsimTH = 8, kSsimMaxR = 8;
+constexpr int kSsimTW = 32, kSsimTH = 16, kSsimMaxR = 8;
 
-// The five Gaussian sums are accumulated in double precision: SSIM divides
-// covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat regions) and the fusion
-// weights amplify them again near SSIM = 0. Inputs are shifted by a
-// per-column value (the tile's middle row), which keeps the moments small
-// without breaking separability (every output column uses one shift).
+// The five Gaussian sums (x, y, x^2, y^2, xy) are accumulated in double
+// precision: SSIM divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat
+// regions) and the fusion weights amplify them again near SSIM = 0, so float
+// sums of E[x^2] - E[x]^2 are not accurate enough there.
 __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
                                               const float* __restrict__ b, int W, int H, int r,
                                               double sigma, double c1, double c2,
@@ -42,11 +41,10 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
-  double* hv = reinterpret_cast<double*>(smem);                 // [5][rows][TW]
-  float* sa = reinterpret_cast<float*>(hv + 5 * rows * kSsimTW);  // [rows][cols]
+  const int n5 = rows * kSsimTW;
+  double* hv = reinterpret_cast<double*>(smem);                  // [5][rows][TW]
+  float* sa = reinterpret_cast<float*>(hv + 5 * n5);            // [rows][cols]
   float* sb = sa + rows * cols;
-  float* ca = sb + rows * cols;                                 // [cols] shifts
-  float* cb = ca + cols;
   __shared__ double gw[2 * kSsimMaxR + 1];
   if (tid == 0) {
     double g[2 * kSsimMaxR + 1], s = 0;
@@ -57,13 +55,7 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     for (int k = 0; k <= 2 * r; ++k) gw[k] = g[k] / s;
   }
   const int ox = blockIdx.x * kSsimTW, oy = blockIdx.y * kSsimTH;
-  const int midy = min(oy + kSsimTH / 2, H - 1);
-  for (int i = tid; i < cols; i += 256) {
-    const int gx = min(max(ox + i - r, 0), W - 1);
-    ca[i] = a[(size_t)midy * W + gx];
-    cb[i] = b[(size_t)midy * W + gx];
-  }
-  __syncthreads();
+#pragma unroll 4
   for (int i = tid; i < rows * cols; i += 256) {
     const int yy = i / cols, xx = i % cols;
     const int gy = min(max(oy + yy - r, 0), H - 1), gx = min(max(ox + xx - r, 0), W - 1);
@@ -71,21 +63,19 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     sb[i] = b[(size_t)gy * W + gx];
   }
   __syncthreads();
-  for (int i = tid; i < rows * kSsimTW; i += 256) {
+  for (int i = tid; i < n5; i += 256) {
     const int yy = i / kSsimTW, xx = i % kSsimTW;
-    const double sfa = ca[xx + r], sfb = cb[xx + r];   // shift of output column xx
     double m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
     const float* ra = sa + yy * cols + xx;
     const float* rb = sb + yy * cols + xx;
     for (int k = 0; k <= 2 * r; ++k) {
-      const double dp = (double)ra[k] - sfa, dq = (double)rb[k] - sfb, wd = gw[k];
-      m1 += wd * dp;
-      m2 += wd * dq;
-      s11 += wd * (dp * dp);
-      s22 += wd * (dq * dq);
-      s12 += wd * (dp * dq);
+      const double p = ra[k], q = rb[k], wd = gw[k];
+      m1 += wd * p;
+      m2 += wd * q;
+      s11 += wd * (p * p);
+      s22 += wd * (q * q);
+      s12 += wd * (p * q);
     }
-    const int n5 = rows * kSsimTW;
     hv[i] = m1; hv[n5 + i] = m2; hv[2 * n5 + i] = s11; hv[3 * n5 + i] = s22; hv[4 * n5 + i] = s12;
   }
   __syncthreads();
@@ -93,23 +83,19 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     const int yy = i / kSsimTW, xx = i % kSsimTW;
     const int gy = oy + yy, gx = ox + xx;
     if (gy >= H || gx >= W) continue;
-    const int n5 = rows * kSsimTW;
-    double da = 0, db = 0, s11 = 0, s22 = 0, s12 = 0;
+    double m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
     for (int k = 0; k <= 2 * r; ++k) {
       const int j = (yy + k) * kSsimTW + xx;
       const double wd = gw[k];
-      da += wd * hv[j];
-      db += wd * hv[n5 + j];
+      m1 += wd * hv[j];
+      m2 += wd * hv[n5 + j];
       s11 += wd * hv[2 * n5 + j];
       s22 += wd * hv[3 * n5 + j];
       s12 += wd * hv[4 * n5 + j];
     }
-    // central moments from moments about the shift c: with d = mean - c,
-    // Var = E[(x-c)^2] - d^2, Cov = E[(x-c)(y-c')] - d d'
-    const double vx = s11 - da * da, vy = s22 - db * db, cxy = s12 - da * db;
-    const double mu1 = da + (double)ca[xx + r], mu2 = db + (double)cb[xx + r];
-    out[(size_t)gy * W + gx] = (float)(((2.0 * mu1 * mu2 + c1) * (2.0 * cxy + c2)) /
-                                       ((mu1 * mu1 + mu2 * mu2 + c1) * (vx + vy + c2)));
+    const double vx = s11 - m1 * m1, vy = s22 - m2 * m2, cxy = s12 - m1 * m2;
+    out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
+                                       ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
   }
 }
 
@@ -212,62 +198,73 @@ struct BlendPtrs {
 constexpr int kBW = 64, kBH = 16;                 // fine output tile
 constexpr int kCW = kBW / 2 + 2, kCH = kBH / 2 + 2;  // coarse tile with its EXPAND halo
 
-// One 64 x 16 tile of level l: R_l = sum_k W_k (G_k - E(G_k,l+1)) + E(R_l+1).
+// One 64 x 16 tile of level l, channels [c0, c0 + cg):
+//   R_l = sum_k W_k (G_k - E(G_k,l+1)) + E(R_l+1).
 // EXPAND (even 2i: (c[i-1] + 6 c[i] + c[i+1]) / 8, odd 2i+1: (c[i] + c[i+1]) / 2,
-// clamped coarse indices; rows first, then columns) reads the n + 1 coarse
-// planes of one channel from LDS tiles loaded once per block.
-__global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int ch, int w, int h, int cw,
-                                               int chh, int top) {
+// clamped coarse indices; rows first, then columns) reads the coarse planes
+// from LDS tiles loaded once per block and expanded along x in LDS. Each
+// thread owns 4 consecutive pixels of one row and reads each weight once.
+__device__ inline float expand_col(const float* col, int lj, bool even) {
+  return even ? (col[(lj - 1) * kBW] + 6.f * col[lj * kBW] + col[(lj + 1) * kBW]) / 8.f
+              : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
+}
+
+__global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int cg, int w, int h,
+                                               int cw, int chh, int top) {
   extern __shared__ float sm[];
   const int tid = threadIdx.x;
   const int ox = blockIdx.x * kBW, oy = blockIdx.y * kBH;
   const int cx0 = (ox >> 1) - 1, cy0 = (oy >> 1) - 1;
-  const int nm = top ? 0 : n + 1;
-  float* ct = sm;                       // [nm][kCH][kCW] coarse tiles
-  float* rx = sm + nm * kCH * kCW;      // [nm][kCH][kBW] expanded along x
-  for (int c = 0; c < ch; ++c) {
-    if (!top) {
-      for (int i = tid; i < nm * kCH * kCW; i += 256) {
-        const int m = i / (kCH * kCW), r = (i / kCW) % kCH, q = i % kCW;
-        const float* src = m < n ? b.gc[m][c] : b.rc[c];
-        const int gy = min(max(cy0 + r, 0), chh - 1), gx = min(max(cx0 + q, 0), cw - 1);
-        ct[i] = src[(size_t)gy * cw + gx];
-      }
-      __syncthreads();
-      for (int i = tid; i < nm * kCH * kBW; i += 256) {
-        const int m = i / (kCH * kBW), r = (i / kBW) % kCH, fx = i % kBW;
-        const float* row = ct + (m * kCH + r) * kCW;
-        const int li = ((ox + fx) >> 1) - cx0;  // local index of coarse i
-        rx[i] = ((ox + fx) & 1) == 0 ? (row[li - 1] + 6.f * row[li] + row[li + 1]) / 8.f
-                                      : (row[li] + row[li + 1]) / 2.f;
-      }
-      __syncthreads();
-    }
-    for (int i = tid; i < kBW * kBH; i += 256) {
-      const int fy = i / kBW, fx = i % kBW;
-      const int x = ox + fx, y = oy + fy;
-      if (x >= w || y >= h) continue;
-      const size_t o = (size_t)y * w + x;
-      const int lj = (y >> 1) - cy0;
-      const bool even = (y & 1) == 0;
-      float acc = 0.f;
-      for (int k = 0; k < n; ++k) {
-        float e = 0.f;
-        if (!top) {
-          const float* col = rx + k * kCH * kBW + fx;
-          e = even ? (col[(lj - 1) * kBW] + 6.f * col[lj * kBW] + col[(lj + 1) * kBW]) / 8.f
-                   : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
-        }
-        acc += b.w[k][o] * (b.g[k][c][o] - e);
-      }
-      if (!top) {
-        const float* col = rx + n * kCH * kBW + fx;
-        acc += even ? (col[(lj - 1) * kBW] + 6.f * col[lj * kBW] + col[(lj + 1) * kBW]) / 8.f
-                    : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
-      }
-      b.out[c][o] = acc;
+  const int nm = top ? 0 : (n + 1) * cg;  // plane m = cc (n + 1) + k, k = n: R
+  float* ct = sm;                         // [nm][kCH][kCW] coarse tiles
+  float* rx = sm + nm * kCH * kCW;        // [nm][kCH][kBW] expanded along x
+  if (!top) {
+    for (int i = tid; i < nm * kCH * kCW; i += 256) {
+      const int m = i / (kCH * kCW), r = (i / kCW) % kCH, q = i % kCW;
+      const int cc = m / (n + 1), k = m % (n + 1);
+      const float* src = k < n ? b.gc[k][c0 + cc] : b.rc[c0 + cc];
+      const int gy = min(max(cy0 + r, 0), chh - 1), gx = min(max(cx0 + q, 0), cw - 1);
+      ct[i] = src[(size_t)gy * cw + gx];
     }
     __syncthreads();
+    for (int i = tid; i < nm * kCH * kBW; i += 256) {
+      const int m = i / (kCH * kBW), r = (i / kBW) % kCH, fx = i % kBW;
+      const float* row = ct + (m * kCH + r) * kCW;
+      const int li = ((ox + fx) >> 1) - cx0;  // local index of coarse i
+      rx[i] = ((ox + fx) & 1) == 0 ? (row[li - 1] + 6.f * row[li] + row[li + 1]) / 8.f
+                                    : (row[li] + row[li + 1]) / 2.f;
+    }
+    __syncthreads();
+  }
+  const int fy = tid >> 4, fx0 = (tid & 15) * 4;
+  const int y = oy + fy, x0 = ox + fx0;
+  if (y >= h || x0 >= w) return;
+  const int nx = min(4, w - x0);
+  const size_t o = (size_t)y * w + x0;
+  const int lj = (y >> 1) - cy0;
+  const bool even = (y & 1) == 0;
+  float acc[3][4];
+  for (int cc = 0; cc < cg; ++cc)
+    for (int q = 0; q < 4; ++q) acc[cc][q] = 0.f;
+  for (int k = 0; k < n; ++k) {
+    float wv[4];
+    for (int q = 0; q < 4; ++q) wv[q] = q < nx ? b.w[k][o + q] : 0.f;
+    for (int cc = 0; cc < cg; ++cc) {
+      const float* g = b.g[k][c0 + cc];
+      const float* col = rx + (cc * (n + 1) + k) * kCH * kBW + fx0;
+      for (int q = 0; q < 4; ++q) {
+        if (q >= nx) break;
+        const float e = top ? 0.f : expand_col(col + q, lj, even);
+        acc[cc][q] += wv[q] * (g[o + q] - e);
+      }
+    }
+  }
+  for (int cc = 0; cc < cg; ++cc) {
+    const float* col = rx + (cc * (n + 1) + n) * kCH * kBW + fx0;
+    for (int q = 0; q < nx; ++q) {
+      const float v = top ? acc[cc][q] : acc[cc][q] + expand_col(col + q, lj, even);
+      b.out[c0 + cc][o + q] = v;
+    }
   }
 }
 
@@ -316,8 +313,7 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     if (k == ref_index) continue;
     dim3 g((W + kSsimTW - 1) / kSsimTW, (H + kSsimTH - 1) / kSsimTH);
     const int r = p.ssim_radius, rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
-    const size_t lds = (size_t)rows * kSsimTW * 5 * 8 + (size_t)rows * cols * 8 +
-                       (size_t)cols * 8;
+    const size_t lds = (size_t)rows * kSsimTW * 5 * 8 + (size_t)rows * cols * 8;
     LNR_LAUNCH(k_ssim, g, dim3(256), lds, st, yeqs[ref_index], yeqs[k], W, H,
                        p.ssim_radius, p.ssim_sigma, p.ssim_c1, p.ssim_c2,
                        bufs.ssim + (size_t)k * N);
@@ -360,10 +356,22 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     }
     const int cw = l + 1 < L ? lw[l + 1] : 1, chh = l + 1 < L ? lh[l + 1] : 1;
     const int top = l + 1 == L ? 1 : 0;
-    const size_t lds = top ? 0 : (size_t)(n + 1) * kCH * (kCW + kBW) * sizeof(float);
-    LNR_LAUNCH(k_blend, dim3((lw[l] + kBW - 1) / kBW, (lh[l] + kBH - 1) / kBH), dim3(256), lds,
-               st, bp, n, ch, lw[l], lh[l], cw, chh, top);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t per_plane = (size_t)kCH * (kCW + kBW) * sizeof(float);
+    int cg = ch;  // channels per launch, so that the coarse tiles fit in 64 KB of LDS
+    while (cg > 1 && (size_t)(n + 1) * cg * per_plane > 64 * 1024) --cg;
+    if ((size_t)(n + 1) * per_plane > 64 * 1024) {  // stacks of more than 15 frames
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blend),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)((n + 1) * per_plane));
+      if (e != hipSuccess) return e;
+    }
+    for (int c0 = 0; c0 < ch; c0 += cg) {
+      const int g = min(cg, ch - c0);
+      const size_t lds = top ? 0 : (size_t)(n + 1) * g * per_plane;
+      LNR_LAUNCH(k_blend, dim3((lw[l] + kBW - 1) / kBW, (lh[l] + kBH - 1) / kBH), dim3(256),
+                 lds, st, bp, n, c0, g, lw[l], lh[l], cw, chh, top);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

@@ -16,7 +16,10 @@
 //     as  sum r^2 + sum w^2 - 2 sum r w : the cross term uses v_dot4_u32_u8 on
 //     the packed patch rows against window dwords realigned with
 //     v_alignbyte_b32 (about 0.5 VALU instructions per pixel-candidate); the
-//     window energies come from LDS row sums shared by all candidates.
+//     window energies are column sums of LDS row energies (also v_dot4).
+//  Staging reads aligned dwords (realigned in registers), several in flight
+//  per thread: the kernel's latency, not its arithmetic, bounds the coarse
+//  levels, which have few tiles.
 //  4. The argmin key (ssd << 32 | (|dx|+|dy|) << 16 | (dy+R) << 8 | (dx+R)) is
 //     reduced with wave shuffles and LDS; equal keys cannot occur, so the
 //     result does not depend on the reduction order.
@@ -63,6 +66,38 @@ __global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src
   out[(size_t)y * w + x] = (uint8_t)((acc + 32768u) >> 16);
 }
 
+// Copy rows [y0, y0 + nrows) x bytes [x0, x0 + 4 * ndw) of an 8-bit image
+// into LDS (row stride `ldst`), 0 outside the image. Interior dwords are read
+// as two aligned dwords realigned with v_alignbyte_b32, unrolled so that
+// several loads are in flight per thread.
+__device__ inline void stage_rows(const uint8_t* __restrict__ img, int w, int h, int x0, int y0,
+                                  int nrows, int ndw, uint8_t* dst, int ldst, int tid, int nt) {
+  const int total = nrows * ndw;
+#pragma unroll 4
+  for (int i = tid; i < total; i += nt) {
+    const int r = i / ndw, j = i % ndw;
+    const int gy = y0 + r, gx = x0 + 4 * j;
+    uint32_t v = 0;
+    if (gy >= 0 && gy < h) {
+      const uint8_t* row = img + (size_t)gy * w;
+      const uintptr_t addr = reinterpret_cast<uintptr_t>(row + gx);
+      const int off = (int)(addr & 3u);
+      const uint8_t* base = row + gx - off;  // aligned
+      if (gx >= 0 && (gx - off) + 8 <= w) {
+        const uint32_t lo = *reinterpret_cast<const uint32_t*>(base);
+        const uint32_t hi = *reinterpret_cast<const uint32_t*>(base + 4);
+        v = __builtin_amdgcn_alignbyte(hi, lo, off);
+      } else {
+        for (int b = 0; b < 4; ++b) {
+          const int xx = gx + b;
+          if (xx >= 0 && xx < w) v |= (uint32_t)row[xx] << (8 * b);
+        }
+      }
+    }
+    *reinterpret_cast<uint32_t*>(dst + r * ldst + 4 * j) = v;
+  }
+}
+
 struct SearchShape {
   int R, nstrips, nthreads;
   int NR;        // window rows = 2P + 2R + 1
@@ -103,10 +138,8 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   const int rx0 = cx0 - ext, ry0 = cy0 - ext;
 
   // 1. corners (Eq. 1-2) ----------------------------------------------------
-  for (int i = tid; i < side * side; i += nt) {
-    const int yy = i / side, xx = i % side;
-    reg[yy * kRegion + xx] = ref[(size_t)(ry0 + yy) * w + rx0 + xx];
-  }
+  // the region lies inside the tile; dword-aligned loads realigned in registers
+  stage_rows(ref, w, h, rx0, ry0, side, (side + 3) / 4, reg, kRegion, tid, nt);
   if (tid == 0) { best_key = 0u; er_sum = 0u; }
   __syncthreads();
   const int nc1 = 2 * c.K + 1, ncand = nc1 * nc1;
@@ -165,27 +198,32 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   uint8_t* win = dyn;
   uint32_t* rowsq = reinterpret_cast<uint32_t*>(dyn + sh.NR * sh.wrow);
   const int wx0 = px - P - R, wy0 = py - P - R;
-  for (int i = tid; i < sh.NR * sh.wrow; i += nt) {
-    const int yy = i / sh.wrow, xx = i % sh.wrow;
-    const int gx = wx0 + xx, gy = wy0 + yy;
-    win[i] = (gx >= 0 && gx < w && gy >= 0 && gy < h) ? wimg[(size_t)gy * w + gx] : (uint8_t)0;
-  }
+  stage_rows(wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
   __syncthreads();
-  // patch energy and window row energies: rowsq[y][k] = sum_c win[y][k + c]^2
+  // patch energy and window row energies rowsq[y][k] = sum_c win[y][k + c]^2,
+  // from realigned dwords with v_dot4 (bytes past the patch width masked off)
   {
     uint32_t part = 0;
-    for (int i = tid; i < PW * PW; i += nt) {
-      const uint32_t v = reg[(pry - P + i / PW) * kRegion + prx - P + i % PW];
-      part += v * v;
-    }
+    for (int i = tid; i < PW * NW; i += nt) part = __builtin_amdgcn_udot4(refp[i], refp[i], part, false);
     if (part) atomicAdd(&er_sum, part);
   }
-  for (int i = tid; i < sh.NR * sh.ncand; i += nt) {
-    const int yy = i / sh.ncand, k = i % sh.ncand;
-    const uint8_t* rowp = win + yy * sh.wrow + k;
-    uint32_t s = 0;
-    for (int cc = 0; cc < PW; ++cc) s += (uint32_t)rowp[cc] * rowp[cc];
-    rowsq[i] = s;
+  {
+    const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
+    const int rowdw = sh.wrow >> 2;
+    for (int i = tid; i < sh.NR * sh.ncand; i += nt) {
+      const int yy = i / sh.ncand, k = i % sh.ncand;
+      const uint32_t* rp = wdw + yy * rowdw + (k >> 2);
+      const int rsh = k & 3;
+      uint32_t s2 = 0;
+#pragma unroll
+      for (int m = 0; m < NW; ++m) {
+        const int nb = PW - 4 * m;
+        const uint32_t mask = nb >= 4 ? 0xffffffffu : (nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u));
+        const uint32_t d = __builtin_amdgcn_alignbyte(rp[m + 1], rp[m], rsh) & mask;
+        s2 = __builtin_amdgcn_udot4(d, d, s2, false);
+      }
+      rowsq[i] = s2;
+    }
   }
   __syncthreads();
 
@@ -193,9 +231,9 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   unsigned long long key = ~0ull;
   if (tid < sh.nthreads) {
     const int j = tid / sh.nstrips, s = tid % sh.nstrips;  // dy index, strip
-    uint32_t acc[KX];
+    uint32_t acc[KX], ew[KX];
 #pragma unroll
-    for (int k = 0; k < KX; ++k) acc[k] = 0;
+    for (int k = 0; k < KX; ++k) { acc[k] = 0; ew[k] = 0; }
     const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
     const int rowdw = sh.wrow >> 2;
     for (int i = 0; i < PW; ++i) {
@@ -221,6 +259,10 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
         for (int m = 0; m < NW; ++m)
           acc[k] = __builtin_amdgcn_udot4(sft[rsh][q + m], rr[m], acc[k], false);
       }
+      // window energy of the KX candidates: column sums of the row energies
+      const uint32_t* rq = rowsq + (j + i) * sh.ncand + s * KX;
+#pragma unroll
+      for (int k = 0; k < KX; ++k) ew[k] += (s * KX + k < sh.ncand) ? rq[k] : 0u;
     }
     const uint32_t er = er_sum;
 #pragma unroll
@@ -230,9 +272,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       const int dx = dxi - R, dy = j - R;
       if (px + dx - P < 0 || px + dx + P > w - 1 || py + dy - P < 0 || py + dy + P > h - 1)
         continue;
-      uint32_t ew = 0;
-      for (int i = 0; i < PW; ++i) ew += rowsq[(j + i) * sh.ncand + dxi];
-      const uint32_t ssd = er + ew - 2u * acc[k];
+      const uint32_t ssd = er + ew[k] - 2u * acc[k];
       const uint32_t l1 = (uint32_t)((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy));
       const unsigned long long kk = ((unsigned long long)ssd << 32) |
                                     ((unsigned long long)l1 << 16) |
@@ -288,7 +328,8 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
   sh.wrow = (need + 15) / 16 * 16;
   int block = (sh.nthreads + 63) / 64 * 64;
   if (block < 64) block = 64;
-  const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4;
+  // (+ KX words: the last strip's padded candidates read past the last row)
+  const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4;
   LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
                      ntx, corner_xy, disp, ssd, flags);
   return hipGetLastError();
