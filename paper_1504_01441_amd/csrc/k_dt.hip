@@ -9,14 +9,13 @@
 // The step coefficient c = a_i^(1 + sigma_s/sigma_r |dI|) depends only on the
 // 8-bit guide difference, so each iteration uses a 256-entry table.
 //
-//  k_dt_h: one workgroup per row (the row's three maps and guide live in LDS;
-//          256 segments, wave shuffles + LDS for the scan). The first pass
-//          writes the sparse maps itself from the tile list (no zero-fill pass).
-//  k_dt_v: one workgroup per 16-column strip over the full height: 64 row
-//          segments x 16 columns, a 6-step scan over segments in LDS; the
-//          anti-causal transfer is accumulated during the causal sweep, so a
-//          vertical pass reads the maps three times (L2 / MALL resident) and
-//          writes them twice. The last pass writes F (and N~) instead.
+//  k_dt_row: one workgroup per row; the row is staged in LDS with coalesced
+//          loads, each of the 256 threads keeps a segment in registers, and
+//          wave shuffles + LDS combine the segment maps. The first pass writes
+//          the sparse maps itself from the tile list (no zero-fill pass).
+//  k_dt_col: one workgroup per strip of 2-8 columns over the full height, as
+//          128 segments per column held in registers; the maps are read and
+//          written once per pass. The last pass writes F (and N~) instead.
 #include "lnr_internal.h"
 
 namespace lnr {
@@ -106,14 +105,23 @@ __device__ void block_carry(Aff v, Aff* wtot, float& c0, float& c1, float& c2) {
   __syncthreads();
 }
 
-template <bool FIRST>
-__global__ __launch_bounds__(256) void k_dt_h(float* __restrict__ maps,
-                                              const uint8_t* __restrict__ guide, int W, int H,
-                                              const float* __restrict__ coef,
-                                              const int32_t* __restrict__ cxy,
-                                              const int32_t* __restrict__ disp,
-                                              const uint8_t* __restrict__ flags, int ntx,
-                                              int nty, int tile) {
+// Coefficient between positions i-1 and i of a line: 0 where i - 1 or i is
+// outside [0, n) (the recursion starts fresh at both ends).
+__device__ inline float coef_at(const float* cf, int gprev, int gcur) {
+  return cf[abs(gcur - gprev)];
+}
+
+// ---------------------------------------------------------------------------
+// Horizontal pass: one block per row; the row is staged in LDS (coalesced),
+// each thread keeps a segment of SEG consecutive pixels in registers.
+template <int SEG, bool FIRST>
+__global__ __launch_bounds__(256) void k_dt_row(float* __restrict__ maps,
+                                                const uint8_t* __restrict__ guide, int W, int H,
+                                                const float* __restrict__ coef,
+                                                const int32_t* __restrict__ cxy,
+                                                const int32_t* __restrict__ disp,
+                                                const uint8_t* __restrict__ flags, int ntx,
+                                                int nty, int tile) {
   extern __shared__ float sm[];
   __shared__ float cf[256];
   __shared__ Aff wtot[4];
@@ -147,46 +155,71 @@ __global__ __launch_bounds__(256) void k_dt_h(float* __restrict__ maps,
       }
   }
   __syncthreads();
-  const int seg = (W + 255) / 256;
-  const int xb = min(W, tid * seg), xe = min(W, xb + seg);
-  // causal: J[x] = J[x] + c (J[x-1] - J[x]), c between x-1 and x (0 at x = 0)
+  const int xb = tid * SEG;
+  float a0[SEG], a1[SEG], a2[SEG], cc[SEG + 1];  // cc[j]: between xb+j-1 and xb+j
+  int gp = xb > 0 && xb - 1 < W ? g[xb - 1] : 0;
+#pragma unroll
+  for (int j = 0; j <= SEG; ++j) {
+    const int x = xb + j;
+    const int gc = x < W ? g[x] : 0;
+    cc[j] = (x > 0 && x < W) ? coef_at(cf, gp, gc) : 0.f;
+    gp = gc;
+    if (j < SEG) {
+      a0[j] = x < W ? v0[x] : 0.f;
+      a1[j] = x < W ? v1[x] : 0.f;
+      a2[j] = x < W ? v2[x] : 0.f;
+    }
+  }
+  // causal: J[x] = J[x] + c (J[x-1] - J[x])
   {
     Aff t{1.f, 0.f, 0.f, 0.f};
-    for (int x = xb; x < xe; ++x) {
-      const float c = x ? cf[abs((int)g[x] - (int)g[x - 1])] : 0.f;
-      t.B0 = v0[x] + c * (t.B0 - v0[x]);
-      t.B1 = v1[x] + c * (t.B1 - v1[x]);
-      t.B2 = v2[x] + c * (t.B2 - v2[x]);
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      if (xb + j >= W) break;
+      const float c = cc[j];
+      t.B0 = a0[j] + c * (t.B0 - a0[j]);
+      t.B1 = a1[j] + c * (t.B1 - a1[j]);
+      t.B2 = a2[j] + c * (t.B2 - a2[j]);
       t.A *= c;
     }
     float p0, p1, p2;
     block_carry<true>(t, wtot, p0, p1, p2);
-    for (int x = xb; x < xe; ++x) {
-      const float c = x ? cf[abs((int)g[x] - (int)g[x - 1])] : 0.f;
-      p0 = v0[x] + c * (p0 - v0[x]); v0[x] = p0;
-      p1 = v1[x] + c * (p1 - v1[x]); v1[x] = p1;
-      p2 = v2[x] + c * (p2 - v2[x]); v2[x] = p2;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      if (xb + j >= W) break;
+      const float c = cc[j];
+      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
+      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
+      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
     }
   }
-  __syncthreads();
   // anti-causal: J[x] = J[x] + c (J[x+1] - J[x]), c between x and x+1
   {
     Aff t{1.f, 0.f, 0.f, 0.f};
-    for (int x = xe - 1; x >= xb; --x) {
-      const float c = x + 1 < W ? cf[abs((int)g[x + 1] - (int)g[x])] : 0.f;
-      t.B0 = v0[x] + c * (t.B0 - v0[x]);
-      t.B1 = v1[x] + c * (t.B1 - v1[x]);
-      t.B2 = v2[x] + c * (t.B2 - v2[x]);
+#pragma unroll
+    for (int j = SEG - 1; j >= 0; --j) {
+      if (xb + j >= W) continue;
+      const float c = cc[j + 1];
+      t.B0 = a0[j] + c * (t.B0 - a0[j]);
+      t.B1 = a1[j] + c * (t.B1 - a1[j]);
+      t.B2 = a2[j] + c * (t.B2 - a2[j]);
       t.A *= c;
     }
     float p0, p1, p2;
     block_carry<false>(t, wtot, p0, p1, p2);
-    for (int x = xe - 1; x >= xb; --x) {
-      const float c = x + 1 < W ? cf[abs((int)g[x + 1] - (int)g[x])] : 0.f;
-      p0 = v0[x] + c * (p0 - v0[x]); v0[x] = p0;
-      p1 = v1[x] + c * (p1 - v1[x]); v1[x] = p1;
-      p2 = v2[x] + c * (p2 - v2[x]); v2[x] = p2;
+#pragma unroll
+    for (int j = SEG - 1; j >= 0; --j) {
+      if (xb + j >= W) continue;
+      const float c = cc[j + 1];
+      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
+      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
+      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
     }
+  }
+#pragma unroll
+  for (int j = 0; j < SEG; ++j) {
+    const int x = xb + j;
+    if (x < W) { v0[x] = a0[j]; v1[x] = a1[j]; v2[x] = a2[j]; }
   }
   __syncthreads();
   for (int x = tid; x < W; x += 256) {
@@ -194,114 +227,186 @@ __global__ __launch_bounds__(256) void k_dt_h(float* __restrict__ maps,
   }
 }
 
-constexpr int kStrip = 16, kSegs = 64;
+// ---------------------------------------------------------------------------
+// Vertical pass: a block covers NCOL adjacent columns over the full height as
+// NSEG = 1024 / NCOL (or 512 / NCOL) segments of L rows; each thread keeps its
+// segment of one column in registers, so the maps are read and written once.
+// Segment carries are combined with wave shuffles (segments of a column sit
+// NCOL lanes apart) and per-wave totals in LDS.
+template <int NCOL, int NSEG>
+__device__ void seg_carry(Aff v, bool fwd, Aff* wt /*[NSEG*NCOL/64][NCOL]*/, float& c0,
+                          float& c1, float& c2) {
+  constexpr int PER = 64 / NCOL;  // segments of one column per wave
+  constexpr int NW = NSEG / PER;  // waves
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = tid % NCOL;
+  const int sl = lane / NCOL;  // segment index within the wave
+  Aff inc = v;
+#pragma unroll
+  for (int off = 1; off < PER; off <<= 1) {
+    const Aff o = fwd ? shfl_up_aff(inc, off * NCOL) : shfl_down_aff(inc, off * NCOL);
+    const bool ok = fwd ? sl >= off : sl + off < PER;
+    if (ok) inc = compose(inc, o);
+  }
+  if (fwd ? sl == PER - 1 : sl == 0) wt[wave * NCOL + cl] = inc;
+  __syncthreads();
+  float z0 = 0.f, z1 = 0.f, z2 = 0.f;
+  if (fwd) {
+    for (int w = 0; w < wave; ++w) {
+      const Aff t = wt[w * NCOL + cl];
+      z0 = t.A * z0 + t.B0; z1 = t.A * z1 + t.B1; z2 = t.A * z2 + t.B2;
+    }
+  } else {
+    for (int w = NW - 1; w > wave; --w) {
+      const Aff t = wt[w * NCOL + cl];
+      z0 = t.A * z0 + t.B0; z1 = t.A * z1 + t.B1; z2 = t.A * z2 + t.B2;
+    }
+  }
+  const Aff prev = fwd ? shfl_up_aff(inc, NCOL) : shfl_down_aff(inc, NCOL);
+  const bool edge = fwd ? sl == 0 : sl == PER - 1;
+  if (edge) { c0 = z0; c1 = z1; c2 = z2; }
+  else {
+    c0 = prev.A * z0 + prev.B0;
+    c1 = prev.A * z1 + prev.B1;
+    c2 = prev.A * z2 + prev.B2;
+  }
+  __syncthreads();
+}
 
-template <bool LAST>
-__global__ __launch_bounds__(1024) void k_dt_v(float* __restrict__ maps,
-                                               const uint8_t* __restrict__ guide, int W, int H,
-                                               const float* __restrict__ coef,
-                                               float* __restrict__ flow,
-                                               float* __restrict__ ntilde, float nmin) {
+template <int L, int NCOL, int NSEG, bool LAST>
+__global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps,
+                                                        const uint8_t* __restrict__ guide, int W,
+                                                        int H, const float* __restrict__ coef,
+                                                        float* __restrict__ flow,
+                                                        float* __restrict__ ntilde, float nmin) {
   __shared__ float cf[256];
-  __shared__ Aff T[kSegs][kStrip];
-  const int tid = threadIdx.x, cl = tid % kStrip, sg = tid / kStrip;
-  const int col = blockIdx.x * kStrip + cl;
+  __shared__ Aff wt[NSEG * NCOL / 64 * NCOL];
+  const int tid = threadIdx.x, cl = tid % NCOL, sg = tid / NCOL;
+  // XCD-aware strip order: consecutive blocks run on different XCDs, so
+  // neighbouring strips (which share cache lines) are given to one XCD
+  const int nb = gridDim.x, b = blockIdx.x, full = nb / 8 * 8;
+  const int strip = b < full ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int col = strip * NCOL + cl;
   const bool act = col < W;
-  const int len = (H + kSegs - 1) / kSegs;
-  const int r0 = min(H, sg * len), r1 = min(H, r0 + len);
+  const int r0 = sg * L;
   const size_t plane = (size_t)W * H;
-  if (tid < 256) cf[tid] = coef[tid];
+  for (int i = tid; i < 256; i += NCOL * NSEG) cf[i] = coef[i];
   __syncthreads();
-  // phase 1: causal transfer of this segment
-  Aff t{1.f, 0.f, 0.f, 0.f};
-  if (act) {
-    int gp = r0 > 0 ? guide[(size_t)(r0 - 1) * W + col] : 0;
-    for (int y = r0; y < r1; ++y) {
-      const size_t o = (size_t)y * W + col;
-      const int gy = guide[o];
-      const float c = y ? cf[abs(gy - gp)] : 0.f;
-      const float a0 = maps[o], a1 = maps[plane + o], a2 = maps[2 * plane + o];
-      t.B0 = a0 + c * (t.B0 - a0);
-      t.B1 = a1 + c * (t.B1 - a1);
-      t.B2 = a2 + c * (t.B2 - a2);
+  // guide bytes of rows r0-1 .. r0+L, four per register; the coefficient
+  // between rows r0+j-1 and r0+j is looked up when needed (0 at the ends)
+  constexpr int NG = (L + 2 + 3) / 4;
+  uint32_t gpk[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) gpk[q] = 0u;
+  float a0[L], a1[L], a2[L];
+#pragma unroll
+  for (int j = -1; j <= L; ++j) {
+    const int y = r0 + j;
+    const bool in = act && y >= 0 && y < H;
+    const size_t o = (size_t)y * W + col;
+    const uint32_t gv = in ? guide[o] : 0u;
+    gpk[(j + 1) >> 2] |= gv << (8 * ((j + 1) & 3));
+    if (j >= 0 && j < L) {
+      a0[j] = in ? maps[o] : 0.f;
+      a1[j] = in ? maps[plane + o] : 0.f;
+      a2[j] = in ? maps[2 * plane + o] : 0.f;
+    }
+  }
+#define GB(j) ((int)((gpk[((j) + 1) >> 2] >> (8 * (((j) + 1) & 3))) & 255u))
+#define CC(j) ((r0 + (j) > 0 && r0 + (j) < H) ? cf[abs(GB(j) - GB((j) - 1))] : 0.f)
+  {
+    Aff t{1.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      if (r0 + j >= H) break;
+      const float c = CC(j);
+      t.B0 = a0[j] + c * (t.B0 - a0[j]);
+      t.B1 = a1[j] + c * (t.B1 - a1[j]);
+      t.B2 = a2[j] + c * (t.B2 - a2[j]);
       t.A *= c;
-      gp = gy;
+    }
+    float p0, p1, p2;
+    seg_carry<NCOL, NSEG>(t, true, wt, p0, p1, p2);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      if (r0 + j >= H) break;
+      const float c = CC(j);
+      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
+      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
+      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
     }
   }
-  T[sg][cl] = t;
-  __syncthreads();
-  for (int off = 1; off < kSegs; off <<= 1) {  // inclusive scan over segments
-    Aff o{1.f, 0.f, 0.f, 0.f};
-    if (sg >= off) o = T[sg - off][cl];
-    __syncthreads();
-    if (sg >= off) t = compose(t, o);
-    T[sg][cl] = t;
-    __syncthreads();
-  }
-  float p0 = 0.f, p1 = 0.f, p2 = 0.f;
-  if (sg > 0) {  // prefix applied to 0 (segment 0 starts with c = 0)
-    const Aff pr = T[sg - 1][cl];
-    p0 = pr.B0; p1 = pr.B1; p2 = pr.B2;
-  }
-  __syncthreads();
-  // phase 3: causal sweep with the carry; accumulate the anti-causal transfer
-  // K[top] = sum_n (prod_{m=top+1..n} c_m)(1 - c_{n+1}) J[n] + (prod c) e_in
-  Aff u{1.f, 0.f, 0.f, 0.f};
-  if (act) {
-    int gp = r0 > 0 ? guide[(size_t)(r0 - 1) * W + col] : 0;
-    for (int y = r0; y < r1; ++y) {
-      const size_t o = (size_t)y * W + col;
-      const int gy = guide[o];
-      const float c = y ? cf[abs(gy - gp)] : 0.f;
-      const float a0 = maps[o], a1 = maps[plane + o], a2 = maps[2 * plane + o];
-      p0 = a0 + c * (p0 - a0);
-      p1 = a1 + c * (p1 - a1);
-      p2 = a2 + c * (p2 - a2);
-      maps[o] = p0; maps[plane + o] = p1; maps[2 * plane + o] = p2;
-      const float cn = y + 1 < H ? cf[abs((int)guide[o + W] - gy)] : 0.f;
-      const float wgt = u.A * (1.f - cn);
-      u.B0 += wgt * p0; u.B1 += wgt * p1; u.B2 += wgt * p2;
-      u.A *= cn;
-      gp = gy;
+  {
+    Aff t{1.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = L - 1; j >= 0; --j) {
+      if (r0 + j >= H) continue;
+      const float c = CC(j + 1);
+      t.B0 = a0[j] + c * (t.B0 - a0[j]);
+      t.B1 = a1[j] + c * (t.B1 - a1[j]);
+      t.B2 = a2[j] + c * (t.B2 - a2[j]);
+      t.A *= c;
+    }
+    float p0, p1, p2;
+    seg_carry<NCOL, NSEG>(t, false, wt, p0, p1, p2);
+#pragma unroll
+    for (int j = L - 1; j >= 0; --j) {
+      if (r0 + j >= H) continue;
+      const float c = CC(j + 1);
+      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
+      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
+      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
     }
   }
-  T[sg][cl] = u;
-  __syncthreads();
-  for (int off = 1; off < kSegs; off <<= 1) {  // inclusive suffix scan
-    Aff o{1.f, 0.f, 0.f, 0.f};
-    if (sg + off < kSegs) o = T[sg + off][cl];
-    __syncthreads();
-    if (sg + off < kSegs) u = compose(u, o);
-    T[sg][cl] = u;
-    __syncthreads();
-  }
-  float e0 = 0.f, e1 = 0.f, e2 = 0.f;
-  if (sg + 1 < kSegs) {
-    const Aff nx = T[sg + 1][cl];
-    e0 = nx.B0; e1 = nx.B1; e2 = nx.B2;
-  }
-  // phase 5: anti-causal sweep upwards
-  if (act) {
-    int gb = r1 < H ? guide[(size_t)r1 * W + col] : 0;
-    for (int y = r1 - 1; y >= r0; --y) {
-      const size_t o = (size_t)y * W + col;
-      const int gy = guide[o];
-      const float cn = y + 1 < H ? cf[abs(gb - gy)] : 0.f;
-      const float a0 = maps[o], a1 = maps[plane + o], a2 = maps[2 * plane + o];
-      e0 = a0 + cn * (e0 - a0);
-      e1 = a1 + cn * (e1 - a1);
-      e2 = a2 + cn * (e2 - a2);
-      if (LAST) {
-        const bool ok = e2 > nmin;
-        flow[o] = ok ? e0 / e2 : 0.f;
-        flow[plane + o] = ok ? e1 / e2 : 0.f;
-        if (ntilde) ntilde[o] = e2;
-      } else {
-        maps[o] = e0; maps[plane + o] = e1; maps[2 * plane + o] = e2;
-      }
-      gb = gy;
+#undef CC
+#undef GB
+  if (!act) return;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const int y = r0 + j;
+    if (y >= H) break;
+    const size_t o = (size_t)y * W + col;
+    if (LAST) {
+      const bool ok = a2[j] > nmin;
+      flow[o] = ok ? a0[j] / a2[j] : 0.f;
+      flow[plane + o] = ok ? a1[j] / a2[j] : 0.f;
+      if (ntilde) ntilde[o] = a2[j];
+    } else {
+      maps[o] = a0[j]; maps[plane + o] = a1[j]; maps[2 * plane + o] = a2[j];
     }
   }
+}
+
+template <int SEG>
+hipError_t launch_row(bool first, float* maps, const uint8_t* guide, int W, int H,
+                      const float* cf, const int32_t* cxy, const int32_t* disp,
+                      const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
+  const size_t lds = (size_t)W * 3 * sizeof(float) + (size_t)W + 16;
+  if (lds > 64 * 1024) {  // rows wider than ~5000 px need more than the default LDS
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(first ? &k_dt_row<SEG, true> : &k_dt_row<SEG, false>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (first)
+    LNR_LAUNCH((k_dt_row<SEG, true>), dim3(H), dim3(256), lds, st, maps, guide, W, H, cf, cxy,
+               disp, flags, ntx, nty, tile);
+  else
+    LNR_LAUNCH((k_dt_row<SEG, false>), dim3(H), dim3(256), lds, st, maps, guide, W, H, cf, cxy,
+               disp, flags, ntx, nty, tile);
+  return hipGetLastError();
+}
+
+template <int L, int NCOL, int NSEG>
+hipError_t launch_col(bool last, float* maps, const uint8_t* guide, int W, int H,
+                      const float* cf, float* flow, float* ntilde, float nmin, hipStream_t st) {
+  const dim3 grid((W + NCOL - 1) / NCOL);
+  if (last)
+    LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, true>), grid, dim3(NCOL * NSEG), 0, st, maps, guide, W, H,
+               cf, flow, ntilde, nmin);
+  else
+    LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, false>), grid, dim3(NCOL * NSEG), 0, st, maps, guide, W,
+               H, cf, flow, ntilde, nmin);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -317,34 +422,24 @@ hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint
   LNR_LAUNCH(k_dt_coef, dim3(a.iters), dim3(256), 0, st, a, coef);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)W * 3 * sizeof(float) + (size_t)W + 16;
-  if (lds > 64 * 1024) {  // rows wider than ~5000 px need more than the default LDS
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dt_h<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dt_h<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
   const float nmin = (float)p.n_min;
+  const int seg = (W + 255) / 256;  // row segment per thread (W <= 6144)
   for (int i = 0; i < a.iters; ++i) {
     const float* cf = coef + 256 * i;
-    if (i == 0)
-      LNR_LAUNCH(k_dt_h<true>, dim3(H), dim3(256), lds, st, maps, guide, W, H, cf,
-                         corner_xy, disp, flags, ntx, nty, tile);
-    else
-      LNR_LAUNCH(k_dt_h<false>, dim3(H), dim3(256), lds, st, maps, guide, W, H, cf,
-                         corner_xy, disp, flags, ntx, nty, tile);
-    e = hipGetLastError();
+    const bool first = i == 0, last = i + 1 == a.iters;
+    if (seg <= 4) e = launch_row<4>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else if (seg <= 8) e = launch_row<8>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else if (seg <= 12) e = launch_row<12>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else if (seg <= 16) e = launch_row<16>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else e = launch_row<24>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
     if (e != hipSuccess) return e;
-    const dim3 grid((W + kStrip - 1) / kStrip);
-    if (i + 1 == a.iters)
-      LNR_LAUNCH(k_dt_v<true>, grid, dim3(1024), 0, st, maps, guide, W, H, cf, flow,
-                         ntilde, nmin);
-    else
-      LNR_LAUNCH(k_dt_v<false>, grid, dim3(1024), 0, st, maps, guide, W, H, cf, flow,
-                         ntilde, nmin);
-    e = hipGetLastError();
+    // column segments: 128 per column, L rows each (H <= 6144)
+    if (H <= 1024) e = launch_col<8, 8, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    else if (H <= 2048) e = launch_col<16, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    else if (H <= 3072) e = launch_col<24, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    else if (H <= 4096) e = launch_col<32, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    else e = launch_col<48, 2, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    // (register budget: 128 VGPRs at 1024 threads, 256 at 512, 512 at 256)
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -203,7 +203,7 @@ constexpr int kCW = kBW / 2 + 2, kCH = kBH / 2 + 2;  // coarse tile with its EXP
 // EXPAND (even 2i: (c[i-1] + 6 c[i] + c[i+1]) / 8, odd 2i+1: (c[i] + c[i+1]) / 2,
 // clamped coarse indices; rows first, then columns) reads the coarse planes
 // from LDS tiles loaded once per block and expanded along x in LDS. Each
-// thread owns 4 consecutive pixels of one row and reads each weight once.
+// thread owns one column of the tile (4 rows) and reads each weight once.
 __device__ inline float expand_col(const float* col, int lj, bool even) {
   return even ? (col[(lj - 1) * kBW] + 6.f * col[lj * kBW] + col[(lj + 1) * kBW]) / 8.f
               : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
@@ -236,34 +236,40 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
     }
     __syncthreads();
   }
-  const int fy = tid >> 4, fx0 = (tid & 15) * 4;
-  const int y = oy + fy, x0 = ox + fx0;
-  if (y >= h || x0 >= w) return;
-  const int nx = min(4, w - x0);
-  const size_t o = (size_t)y * w + x0;
-  const int lj = (y >> 1) - cy0;
-  const bool even = (y & 1) == 0;
+  // thread = one column of the tile (lanes are consecutive pixels), 4 rows
+  const int fx = tid & 63, fy0 = tid >> 6;
+  const int x = ox + fx;
+  if (x >= w) return;
   float acc[3][4];
   for (int cc = 0; cc < cg; ++cc)
     for (int q = 0; q < 4; ++q) acc[cc][q] = 0.f;
   for (int k = 0; k < n; ++k) {
     float wv[4];
-    for (int q = 0; q < 4; ++q) wv[q] = q < nx ? b.w[k][o + q] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int y = oy + fy0 + 4 * q;
+      wv[q] = y < h ? b.w[k][(size_t)y * w + x] : 0.f;
+    }
     for (int cc = 0; cc < cg; ++cc) {
       const float* g = b.g[k][c0 + cc];
-      const float* col = rx + (cc * (n + 1) + k) * kCH * kBW + fx0;
+      const float* col = rx + (cc * (n + 1) + k) * kCH * kBW + fx;
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (q >= nx) break;
-        const float e = top ? 0.f : expand_col(col + q, lj, even);
-        acc[cc][q] += wv[q] * (g[o + q] - e);
+        const int y = oy + fy0 + 4 * q;
+        if (y >= h) break;
+        const float e = top ? 0.f : expand_col(col, (y >> 1) - cy0, (y & 1) == 0);
+        acc[cc][q] += wv[q] * (g[(size_t)y * w + x] - e);
       }
     }
   }
   for (int cc = 0; cc < cg; ++cc) {
-    const float* col = rx + (cc * (n + 1) + n) * kCH * kBW + fx0;
-    for (int q = 0; q < nx; ++q) {
-      const float v = top ? acc[cc][q] : acc[cc][q] + expand_col(col + q, lj, even);
-      b.out[c0 + cc][o + q] = v;
+    const float* col = rx + (cc * (n + 1) + n) * kCH * kBW + fx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int y = oy + fy0 + 4 * q;
+      if (y >= h) break;
+      const float v = top ? acc[cc][q] : acc[cc][q] + expand_col(col, (y >> 1) - cy0, (y & 1) == 0);
+      b.out[c0 + cc][(size_t)y * w + x] = v;
     }
   }
 }
