@@ -3,19 +3,18 @@
 //
 // k_compact: one workgroup lists the valid matches of the level in tile order
 //   (centred level coordinates: source side p + d - c, reference side p - c).
-// k_hyp:   one thread per iteration draws four distinct indices from the
-//   counter-based SplitMix64 stream and solves the 8x8 system in double
-//   precision (partial pivoting, fixed operation order).
-// k_count: a (256 matches x 8 iterations) block tests inliers; wave ballots
-//   form each iteration's inlier bitmask row, and the counts are summed.
-// k_union: every accepted iteration (count > delta) ORs its row into M with
-//   64-bit atomics, so M is the same for any execution order (the paper's
-//   note that the iterations can be split freely); the best consensus is a
-//   64-bit atomicMax on (count << 32 | ~iteration).
-// k_fit: 512 threads re-test the best hypothesis, sum the least-squares
-//   normal equations of G: p -> p + d over its inliers exactly in int64 (so
-//   the sum is order-free), reduce them, and one thread solves and composes
-//   H_l = H_{l+1} o G in double precision.
+// k_weedfit: a (256 matches x 8 iterations) block draws four distinct
+//   indices per iteration from the counter-based SplitMix64 stream, solves
+//   the 8x8 system in double precision (partial pivoting, fixed operation
+//   order), and tests its matches; wave ballots form each iteration's inlier
+//   bitmask row and the counts are summed with atomics. The last block of an
+//   iteration group ORs the accepted rows (count > delta) into M with 64-bit
+//   atomics, so M is the same for any execution order (the paper's note that
+//   the iterations can be split freely), and keeps the best consensus as a
+//   64-bit atomicMax on (count << 32 | ~iteration). The last block overall
+//   re-tests the best hypothesis, sums the least-squares normal equations of
+//   G: p -> p + d over its inliers exactly in int64 (order-free), and solves
+//   and composes H_l = H_{l+1} o G in double precision.
 #include "lnr_device.h"
 #include "lnr_internal.h"
 
@@ -77,7 +76,9 @@ __global__ __launch_bounds__(1024) void k_compact(const int32_t* __restrict__ cx
                                                   int32_t* __restrict__ tile_of,
                                                   int32_t* __restrict__ nmatch,
                                                   unsigned long long* __restrict__ mbits,
-                                                  unsigned long long* __restrict__ best) {
+                                                  unsigned long long* __restrict__ best,
+                                                  int32_t* __restrict__ counts, int iters,
+                                                  uint32_t* __restrict__ done, int ndone) {
   __shared__ int part[1024];
   const int tid = threadIdx.x;
   const int chunk = (ntiles + 1023) / 1024;
@@ -103,6 +104,8 @@ __global__ __launch_bounds__(1024) void k_compact(const int32_t* __restrict__ cx
     }
   if (tid == 1023) *nmatch = part[1023];
   for (int i = tid; i < (ntiles + 63) / 64; i += 1024) mbits[i] = 0ull;
+  for (int i = tid; i < iters; i += 1024) counts[i] = 0;
+  for (int i = tid; i < ndone; i += 1024) done[i] = 0u;
   if (tid == 0) *best = 0ull;
 }
 
@@ -145,84 +148,6 @@ __device__ bool hypothesis(const int4* __restrict__ matches, int N, int it, cons
   return solve8(A, g);
 }
 
-// One thread per iteration: draw + 4-point fit (flag -1 when degenerate).
-__global__ __launch_bounds__(64) void k_hyp(const int4* __restrict__ matches,
-                                            const int32_t* __restrict__ nmatch, WeedArgs a,
-                                            double* __restrict__ Gout,
-                                            int32_t* __restrict__ cnt) {
-  const int it = blockIdx.x * 64 + threadIdx.x;
-  if (it >= a.iters) return;
-  const int N = *nmatch;
-  double g[8];
-  if (N < 4 || !hypothesis(matches, N, it, a, g)) {
-    cnt[it] = -1;
-    return;
-  }
-  for (int i = 0; i < 8; ++i) Gout[(size_t)it * 8 + i] = g[i];
-  cnt[it] = 0;
-}
-
-constexpr int kItPerBlock = 8;
-
-// Block (match chunk of 256, 8 iterations): inlier tests, ballots to the
-// per-iteration bitmask rows, counts added per iteration.
-__global__ __launch_bounds__(256) void k_count(const int4* __restrict__ matches,
-                                               const int32_t* __restrict__ nmatch, WeedArgs a,
-                                               const double* __restrict__ G,
-                                               int32_t* __restrict__ cnt,
-                                               unsigned long long* __restrict__ bal, int wstride) {
-  __shared__ double gs[kItPerBlock][8];
-  __shared__ int ok[kItPerBlock];
-  __shared__ int wc[kItPerBlock][4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int it0 = blockIdx.y * kItPerBlock;
-  const int N = *nmatch;
-  if (tid < kItPerBlock) ok[tid] = (it0 + tid < a.iters) && cnt[it0 + tid] >= 0;
-  if (tid < kItPerBlock * 8) {
-    const int q = tid / 8, i = tid % 8;
-    gs[q][i] = (it0 + q < a.iters) ? G[(size_t)(it0 + q) * 8 + i] : 0.0;
-  }
-  __syncthreads();
-  const int k = blockIdx.x * 256 + tid;
-  const int word = k >> 6;
-  if (N < 4 || blockIdx.x * 256 >= N) return;  // uniform per block
-  const int4 m = k < N ? matches[k] : make_int4(0, 0, 0, 0);
-  for (int q = 0; q < kItPerBlock; ++q) {
-    if (!ok[q]) continue;
-    const bool in = k < N && is_inlier(gs[q], m, a.eps2);
-    const unsigned long long b = __ballot(in);
-    if (lane == 0) {
-      if (word * 64 < N) bal[(size_t)(it0 + q) * wstride + word] = b;
-      wc[q][wave] = __popcll(b);
-    }
-  }
-  __syncthreads();
-  if (tid < kItPerBlock && ok[tid]) {
-    const int s = wc[tid][0] + wc[tid][1] + wc[tid][2] + wc[tid][3];
-    if (s) atomicAdd(&cnt[it0 + tid], s);
-  }
-}
-
-// Accepted iterations (count > delta) OR their inlier rows into M; the best
-// consensus is the largest (count << 32 | ~iteration).
-__global__ __launch_bounds__(64) void k_union(const int32_t* __restrict__ nmatch, WeedArgs a,
-                                              const int32_t* __restrict__ cnt,
-                                              const unsigned long long* __restrict__ bal,
-                                              int wstride, unsigned long long* __restrict__ mbits,
-                                              unsigned long long* __restrict__ best) {
-  const int it = blockIdx.y;
-  const int wi = blockIdx.x * 64 + threadIdx.x;
-  const int N = *nmatch;
-  const int c = cnt[it];
-  if (N < 4 || c < 0) return;
-  if (wi == 0)
-    atomicMax(best, ((unsigned long long)(uint32_t)c << 32) | (unsigned long long)(~(uint32_t)it));
-  if (c > weed_delta(N, a) && wi * 64 < N) {
-    const unsigned long long b = bal[(size_t)it * wstride + wi];
-    if (b) atomicOr(&mbits[wi], b);
-  }
-}
-
 __device__ inline long long wave_sum_i64(long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -232,23 +157,32 @@ __device__ inline long long wave_sum_i64(long long v) {
 // index of the upper-triangle entry (i <= j) of the 8x8 normal matrix
 __device__ inline int tri(int i, int j) { return i * 8 - (i * (i - 1)) / 2 + (j - i); }
 
-constexpr int kFitThreads = 512;
+constexpr int kItPerBlock = 8;
+constexpr int kWeedThreads = 256;
 
-__global__ __launch_bounds__(kFitThreads) void k_fit(const int4* __restrict__ matches,
-                                                     const int32_t* __restrict__ tile_of,
-                                                     const int32_t* __restrict__ nmatch, WeedArgs a,
-                                                     const unsigned long long* __restrict__ mbits,
-                                                     const unsigned long long* __restrict__ best,
-                                                     const double* __restrict__ Gall,
-                                                     uint8_t* __restrict__ flags, int w, int h,
-                                                     const double* __restrict__ Hprev,
-                                                     double* __restrict__ Hout,
-                                                     int32_t* __restrict__ counts) {
-  __shared__ long long part[kFitThreads / 64][45];
+// Signal that this block is done with its share; returns true in the one
+// block that finishes last. Writes before the call are visible to that block.
+__device__ inline bool last_to_finish(uint32_t* counter, uint32_t total, int* flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = atomicAdd(counter, 1u) == total - 1;
+  __syncthreads();
+  const bool last = *flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Least-squares level homography over the inliers of the best-consensus
+// hypothesis (one block), plus the per-tile flags 4 (in M) and 8 (in the fit).
+__device__ void fit_level(const int4* __restrict__ matches, const int32_t* __restrict__ tile_of,
+                          int N, const WeedArgs& a, const unsigned long long* mbits,
+                          unsigned long long bkey, const double* __restrict__ Gall,
+                          uint8_t* __restrict__ flags, int w, int h,
+                          const double* __restrict__ Hprev, double* __restrict__ Hout,
+                          int32_t* __restrict__ counts) {
+  __shared__ long long part[kWeedThreads / 64][45];
   __shared__ long long tot[45];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int N = *nmatch;
-  const unsigned long long bkey = *best;
   const int bc = N >= 4 && bkey ? (int)(bkey >> 32) : -1;
   const int bi = N >= 4 && bkey ? (int)(~(uint32_t)(bkey & 0xffffffffull)) : -1;
   const bool fit = bc > weed_delta(N, a);
@@ -258,7 +192,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(const int4* __restrict__ ma
   for (int i = 0; i < 36; ++i) ata[i] = 0;
   for (int i = 0; i < 8; ++i) atb[i] = 0;
   long long m = 0;
-  for (int k = tid; k < N; k += kFitThreads) {
+  for (int k = tid; k < N; k += kWeedThreads) {
     const int4 mt = matches[k];
     const bool inM = (mbits[k >> 6] >> (k & 63)) & 1ull;
     const bool sel = fit && is_inlier(g, mt, a.eps2);
@@ -286,7 +220,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(const int4* __restrict__ ma
   __syncthreads();
   if (tid < 45) {
     long long s = 0;
-    for (int q = 0; q < kFitThreads / 64; ++q) s += part[q][tid];
+    for (int q = 0; q < kWeedThreads / 64; ++q) s += part[q][tid];
     tot[tid] = s;
   }
   __syncthreads();
@@ -333,6 +267,97 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(const int4* __restrict__ ma
   for (int i = 0; i < 9; ++i) Hout[i] = Hn[i];
 }
 
+// Block (256 matches, 8 iterations). Every block draws and fits its 8
+// hypotheses (8 threads), tests its matches against them (wave ballots form
+// the inlier bitmask rows) and adds the counts. The last block of an
+// iteration group ORs the accepted rows (count > delta) into M and updates
+// the best consensus (count << 32 | ~iteration); the last block overall fits
+// the level homography. No block waits for another.
+__global__ __launch_bounds__(kWeedThreads) void k_weedfit(
+    const int4* __restrict__ matches, const int32_t* __restrict__ tile_of,
+    const int32_t* __restrict__ nmatch, WeedArgs a, double* __restrict__ G,
+    int32_t* __restrict__ cnt, unsigned long long* __restrict__ bal, int wstride,
+    unsigned long long* __restrict__ mbits, unsigned long long* __restrict__ best,
+    uint32_t* __restrict__ done, uint8_t* __restrict__ flags, int w, int h,
+    const double* __restrict__ Hprev, double* __restrict__ Hout, int32_t* __restrict__ counts) {
+  __shared__ double gs[kItPerBlock][8];
+  __shared__ int ok[kItPerBlock];
+  __shared__ int wc[kItPerBlock][kWeedThreads / 64];
+  __shared__ int lastflag;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int it0 = blockIdx.y * kItPerBlock;
+  const int N = *nmatch;
+  const int k = blockIdx.x * kWeedThreads + tid;
+  const bool work = N >= 4 && blockIdx.x * kWeedThreads < N;
+  if (work && tid < kItPerBlock) {
+    const int it = it0 + tid;
+    double g[8];
+    const bool good = it < a.iters && hypothesis(matches, N, it, a, g);
+    ok[tid] = good;
+    for (int i = 0; i < 8; ++i) gs[tid][i] = good ? g[i] : 0.0;
+    if (blockIdx.x == 0 && it < a.iters) {  // block 0 of the group publishes G
+      if (good)
+        for (int i = 0; i < 8; ++i) G[(size_t)it * 8 + i] = g[i];
+      else
+        cnt[it] = -1;  // degenerate: no block adds to it
+    }
+  }
+  __syncthreads();
+  if (work) {
+    const int4 m = k < N ? matches[k] : make_int4(0, 0, 0, 0);
+    const int word = k >> 6;
+    for (int q = 0; q < kItPerBlock; ++q) {
+      if (!ok[q]) continue;
+      const bool in = k < N && is_inlier(gs[q], m, a.eps2);
+      const unsigned long long b = __ballot(in);
+      if (lane == 0) {
+        if (word * 64 < N) bal[(size_t)(it0 + q) * wstride + word] = b;
+        wc[q][wave] = __popcll(b);
+      }
+    }
+    __syncthreads();
+    if (tid < kItPerBlock && ok[tid]) {
+      int s = 0;
+      for (int q = 0; q < kWeedThreads / 64; ++q) s += wc[tid][q];
+      if (s) atomicAdd(&cnt[it0 + tid], s);
+    }
+  }
+  // the last block of this iteration group: union of accepted rows into M
+  if (last_to_finish(&done[1 + blockIdx.y], gridDim.x, &lastflag) && N >= 4) {
+    const int delta = weed_delta(N, a);
+    const int nwords = (N + 63) / 64;
+    __shared__ int acc[kItPerBlock];
+    __shared__ int cval[kItPerBlock];
+    if (tid < kItPerBlock) {
+      const int it = it0 + tid;
+      cval[tid] = it < a.iters ? __atomic_load_n(&cnt[it], __ATOMIC_RELAXED) : -1;
+      acc[tid] = cval[tid] > delta;  // -1 marks a degenerate iteration
+    }
+    __syncthreads();
+    for (int wi = tid; wi < nwords; wi += kWeedThreads) {
+      unsigned long long v = 0ull;
+      for (int q = 0; q < kItPerBlock; ++q)
+        if (acc[q]) v |= bal[(size_t)(it0 + q) * wstride + wi];
+      if (v) atomicOr(&mbits[wi], v);
+    }
+    if (tid == 0) {
+      unsigned long long bk = 0ull;
+      for (int q = 0; q < kItPerBlock; ++q)
+        if (cval[q] >= 0) {
+          const unsigned long long key = ((unsigned long long)(uint32_t)cval[q] << 32) |
+                                         (unsigned long long)(~(uint32_t)(it0 + q));
+          bk = key > bk ? key : bk;
+        }
+      if (bk) atomicMax(best, bk);
+    }
+  }
+  // the last block overall: level homography
+  if (last_to_finish(&done[0], gridDim.x * gridDim.y, &lastflag)) {
+    const unsigned long long bkey = __atomic_load_n(best, __ATOMIC_RELAXED);
+    fit_level(matches, tile_of, N, a, mbits, bkey, G, flags, w, h, Hprev, Hout, counts);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
@@ -346,26 +371,16 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
   a.delta_pct = p.weed_delta_pct;
   a.eps2 = p.weed_eps * p.weed_eps;
   a.seed = p.seed;
-  hipError_t e;
-  if (ntiles > 0) {
-    const int words = (ntiles + 63) / 64;
-    LNR_LAUNCH(k_compact, dim3(1), dim3(1024), 0, st, corner_xy, disp, flags, ntiles, w, h,
-               b.matches, b.tile_of, b.nmatch, b.mbits, b.best);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    LNR_LAUNCH(k_hyp, dim3((a.iters + 63) / 64), dim3(64), 0, st, b.matches, b.nmatch, a, b.G,
-               b.cnt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    LNR_LAUNCH(k_count, dim3((ntiles + 255) / 256, (a.iters + kItPerBlock - 1) / kItPerBlock),
-               dim3(256), 0, st, b.matches, b.nmatch, a, b.G, b.cnt, b.bal, words);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    LNR_LAUNCH(k_union, dim3((words + 63) / 64, a.iters), dim3(64), 0, st, b.nmatch, a, b.cnt,
-               b.bal, words, b.mbits, b.best);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  } else {
-    if ((e = hipMemsetAsync(b.nmatch, 0, sizeof(int32_t), st)) != hipSuccess) return e;
-  }
-  LNR_LAUNCH(k_fit, dim3(1), dim3(kFitThreads), 0, st, b.matches, b.tile_of, b.nmatch, a,
-             b.mbits, b.best, b.G, flags, w, h, H_prev, H_out, counts);
+  const int words = ntiles > 0 ? (ntiles + 63) / 64 : 1;
+  const int chunks = ntiles > 0 ? (ntiles + kWeedThreads - 1) / kWeedThreads : 1;
+  const int groups = (a.iters + kItPerBlock - 1) / kItPerBlock;
+  LNR_LAUNCH(k_compact, dim3(1), dim3(1024), 0, st, corner_xy, disp, flags, ntiles, w, h,
+             b.matches, b.tile_of, b.nmatch, b.mbits, b.best, b.cnt, a.iters, b.done, 1 + groups);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  LNR_LAUNCH(k_weedfit, dim3(chunks, groups), dim3(kWeedThreads), 0, st, b.matches, b.tile_of,
+             b.nmatch, a, b.G, b.cnt, b.bal, words, b.mbits, b.best, b.done, flags, w, h, H_prev,
+             H_out, counts);
   return hipGetLastError();
 }
 

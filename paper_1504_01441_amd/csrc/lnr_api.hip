@@ -218,7 +218,7 @@ lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes) {
 }
 
 struct WeedPlan {
-  size_t matches, tile_of, nmatch, mbits, best, G, cnt, bal;
+  size_t matches, tile_of, nmatch, mbits, best, G, cnt, bal, done;
 };
 
 WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
@@ -232,6 +232,7 @@ WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
   w.G = pl.take(sizeof(double) * 8 * (size_t)iters);
   w.cnt = pl.take(sizeof(int32_t) * (size_t)iters);
   w.bal = pl.take(sizeof(unsigned long long) * (size_t)iters * ((nt + 63) / 64));
+  w.done = pl.take(sizeof(uint32_t) * (size_t)(1 + (iters + 7) / 8));
   return w;
 }
 
@@ -245,6 +246,7 @@ WeedBufs weed_bufs(char* base, const WeedPlan& w) {
   b.G = reinterpret_cast<double*>(base + w.G);
   b.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
   b.bal = reinterpret_cast<unsigned long long*>(base + w.bal);
+  b.done = reinterpret_cast<uint32_t*>(base + w.done);
   return b;
 }
 

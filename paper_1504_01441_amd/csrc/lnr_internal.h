@@ -73,6 +73,7 @@ struct WeedBufs {
   double* G;             // [iters][8] hypothesis homographies
   int32_t* cnt;          // [iters] inlier counts (-1: skipped)
   unsigned long long* bal;  // [iters][ceil(ntiles/64)] inlier bitmask rows
+  uint32_t* done;           // [1 + iteration groups] completion counters
 };
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
