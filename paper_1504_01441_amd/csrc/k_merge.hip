@@ -120,8 +120,9 @@ __device__ inline double raw_weight(const FramePtrs& f, int k, int ch, int ref, 
   float e;
   if (ch == 3) {
     const double R = I[o], G = I[plane + o], B = I[2 * plane + o];
-    const double mu = (R + G + B) / 3.0;
-    S = sqrt(((R - mu) * (R - mu) + (G - mu) * (G - mu) + (B - mu) * (B - mu)) / 3.0);
+    const double mu = (R + G + B) * (1.0 / 3.0);
+    const double var = ((R - mu) * (R - mu) + (G - mu) * (G - mu) + (B - mu) * (B - mu)) * (1.0 / 3.0);
+    S = (double)sqrtf((float)var);  // the cancelling differences are in double
     e = (float)((R - 0.5) * (R - 0.5) + (G - 0.5) * (G - 0.5) + (B - 0.5) * (B - 0.5));
   } else {
     e = (float)((I[o] - 0.5) * (I[o] - 0.5));
@@ -163,11 +164,20 @@ __global__ __launch_bounds__(256) void k_reduce(MapPtrs m, int w, int h, int w2,
   const float* in = m.in[blockIdx.z];
   float* out = m.out[blockIdx.z];
   const int ox = blockIdx.x * kRedTW, oy = blockIdx.y * kRedTH;
-  const int rows = 2 * kRedTH + 3, cols = 2 * kRedTW + 3;
-  for (int i = threadIdx.x; i < rows * cols; i += 256) {
+  constexpr int rows = 2 * kRedTH + 3, cols = 2 * kRedTW + 3;
+  constexpr int per = (rows * cols + 255) / 256;
+  float v[per];
+#pragma unroll
+  for (int q = 0; q < per; ++q) {  // all loads in flight before the LDS stores
+    const int i = threadIdx.x + 256 * q;
     const int yy = i / cols, xx = i % cols;
     const int gy = min(max(2 * oy - 2 + yy, 0), h - 1), gx = min(max(2 * ox - 2 + xx, 0), w - 1);
-    src[yy][xx] = in[(size_t)gy * w + gx];
+    v[q] = i < rows * cols ? in[(size_t)gy * w + gx] : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const int i = threadIdx.x + 256 * q;
+    if (i < rows * cols) src[i / cols][i % cols] = v[q];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < rows * kRedTW; i += 256) {

@@ -40,14 +40,8 @@ __device__ inline long long q8(double s) {
   return (long long)q;
 }
 
-__global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src, int w, int h,
-                                                 const double* __restrict__ Hn,
-                                                 uint8_t* __restrict__ out) {
-  __shared__ double hp[9];
-  if (threadIdx.x == 0) pixel_homography(Hn, w, h, hp);
-  __syncthreads();
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= w) return;
+__device__ inline uint32_t warp_px(const uint8_t* __restrict__ src, int w, int h,
+                                   const double* hp, int x, int y) {
   const double X = (double)x, Y = (double)y;
   const double den = (hp[6] * X + hp[7] * Y) + hp[8];
   const double sx = ((hp[0] * X + hp[1] * Y) + hp[2]) / den;
@@ -63,7 +57,27 @@ __global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src
   const uint32_t p01 = src[(size_t)y1 * w + x0], p11 = src[(size_t)y1 * w + x1];
   const uint32_t acc = (256 - fx) * (256 - fy) * p00 + fx * (256 - fy) * p10 +
                        (256 - fx) * fy * p01 + fx * fy * p11;
-  out[(size_t)y * w + x] = (uint8_t)((acc + 32768u) >> 16);
+  return (acc + 32768u) >> 16;
+}
+
+// Four consecutive pixels per thread, one 32-bit store when the row allows it.
+__global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src, int w, int h,
+                                                 const double* __restrict__ Hn,
+                                                 uint8_t* __restrict__ out) {
+  __shared__ double hp[9];
+  if (threadIdx.x == 0) pixel_homography(Hn, w, h, hp);
+  __syncthreads();
+  const int x = 4 * (blockIdx.x * blockDim.x + threadIdx.x), y = blockIdx.y;
+  if (x >= w) return;
+  uint8_t* row = out + (size_t)y * w;
+  if (x + 4 <= w && ((reinterpret_cast<uintptr_t>(row + x) & 3u) == 0)) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v |= warp_px(src, w, h, hp, x + k, y) << (8 * k);
+    *reinterpret_cast<uint32_t*>(row + x) = v;
+  } else {
+    for (int k = 0; k < 4 && x + k < w; ++k) row[x + k] = (uint8_t)warp_px(src, w, h, hp, x + k, y);
+  }
 }
 
 // Copy rows [y0, y0 + nrows) x bytes [x0, x0 + 4 * ndw) of an 8-bit image
@@ -124,6 +138,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   extern __shared__ __align__(16) uint8_t dyn[];
   __shared__ uint8_t reg[kRegion * kRegion];
   __shared__ uint32_t qsum[4 * 49];
+  __shared__ uint32_t hsum[64 * 14];
   __shared__ uint32_t best_key;
   __shared__ uint32_t refp[(2 * kMaxPatchR + 1) * NW];
   __shared__ uint32_t er_sum;
@@ -143,17 +158,41 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   if (tid == 0) { best_key = 0u; er_sum = 0u; }
   __syncthreads();
   const int nc1 = 2 * c.K + 1, ncand = nc1 * nc1;
-  for (int i = tid; i < 4 * ncand; i += nt) {
-    const int ci = i >> 2, q = i & 3;
-    const int a = ci % nc1 - c.K, b = ci / nc1 - c.K;
-    const int px = ext + c.g * a, py = ext + c.g * b;
-    // quadrants in cyclic order TL, TR, BR, BL
-    const int qx = (q == 0 || q == 3) ? px - c.r : px;
-    const int qy = (q <= 1) ? py - c.r : py;
-    uint32_t s = 0;
-    for (int yy = 0; yy < c.r; ++yy)
-      for (int xx = 0; xx < c.r; ++xx) s += reg[(qy + yy) * kRegion + qx + xx];
-    qsum[i] = s;
+  // Quadrant sums as separable box sums: horizontal r-pixel sums for every
+  // region row and every quadrant x-origin (left origin px - r and right
+  // origin px of each candidate column a), then r-row vertical sums.
+  {
+    const uint32_t* rdw = reinterpret_cast<const uint32_t*>(reg);
+    const int nrow = 2 * (c.K * c.g + c.r);       // rows spanned by the quadrants
+    const int yo = ext - c.K * c.g - c.r;          // first such region row
+    const int nxo = 2 * nc1;
+    const int nd = (c.r + 3) >> 2;
+    for (int i = tid; i < nrow * nxo; i += nt) {
+      const int row = i / nxo, xo = i % nxo;
+      const int a = xo >> 1;
+      const int X0 = ext + c.g * (a - c.K) - ((xo & 1) ? 0 : c.r);
+      const uint32_t* rp = rdw + (yo + row) * (kRegion / 4) + (X0 >> 2);
+      const int rsh = X0 & 3;
+      uint32_t s = 0;
+      for (int m = 0; m < nd; ++m) {
+        const int nb = c.r - 4 * m;
+        const uint32_t mask = nb >= 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1u);
+        const uint32_t d = __builtin_amdgcn_alignbyte(rp[m + 1], rp[m], rsh) & mask;
+        s = __builtin_amdgcn_udot4(d, 0x01010101u, s, false);
+      }
+      hsum[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < 4 * ncand; i += nt) {
+      const int ci = i >> 2, q = i & 3;
+      const int a = ci % nc1, b = ci / nc1;
+      // quadrants in cyclic order TL, TR, BR, BL
+      const int xo = 2 * a + ((q == 0 || q == 3) ? 0 : 1);
+      const int r0 = c.g * b + ((q <= 1) ? 0 : c.r);   // first row, relative to yo
+      uint32_t s = 0;
+      for (int yy = 0; yy < c.r; ++yy) s += hsum[(r0 + yy) * nxo + xo];
+      qsum[i] = s;
+    }
   }
   __syncthreads();
   for (int ci = tid; ci < ncand; ci += nt) {
@@ -308,7 +347,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
 
 hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
                           hipStream_t st) {
-  dim3 grid((w + 255) / 256, h);
+  dim3 grid((w + 1023) / 1024, h);
   LNR_LAUNCH(k_warp_q8, grid, dim3(256), 0, st, src, w, h, Hn, out);
   return hipGetLastError();
 }
