@@ -29,23 +29,65 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes x 2.4 GHz, 1 op/lane/clk
 
 
-def algo_bytes(kernel, W, H, n_frames, ch):
-    """Algorithmic HBM bytes of one launch at full resolution."""
+def kernel_key(name):
+    """Trace names are the launched expressions, e.g. "(k_dt_row<SEG, NT, true>)":
+    return (base name, last template flag)."""
+    n = name.strip("()")
+    return n.split("<")[0], n.endswith("true>")
+
+
+def algo_bytes_per_step(W, H, fmt_i420, n, ch, reg_sizes, blend_levels, launches):
+    """Algorithmic HBM bytes of one whole-path step, per kernel base name: the
+    bytes each launch must move at least (every input read once, every output
+    written once), summed over that kernel's launches in the step.
+
+    launches: {trace name: launches per step}. Only bandwidth-type kernels are
+    modelled; the search is priced in pixel-candidate operations instead.
+    """
     N = W * H
-    table = {
-        # causal + anti-causal vertical pass: read 3 maps + guide, write 3 maps
-        # (the last pass writes F (2 maps) and N~ instead)
-        "k_dt_v<false>": 25 * N, "k_dt_v<true>": 25 * N,
-        # horizontal pass: same; the first synthesises the sparse maps (reads guide only)
-        "k_dt_h<false>": 25 * N, "k_dt_h<true>": 13 * N,
-        # read F, Y, U, V, Y_eq; write RGB + warped Y_eq
-        "k_bwarp": (8 + 1 + 0.5 + 1 + 4 * ch + 4) * N,
-        # read every frame's planes + SSIM, write the weights
-        "k_weights": (n_frames * 4 * ch + (n_frames - 1) * 4 + n_frames * 4) * N,
-        # read two luma maps, write SSIM
-        "k_ssim": 12 * N,
-    }
-    return table.get(kernel)
+    chroma = 0.5 if fmt_i420 else 0.0
+    # registration pyramid levels (equalised luma, u8)
+    reg_px = [reg_sizes.level_w[i] * reg_sizes.level_h[i] for i in range(reg_sizes.levels)]
+    # merge (Burt-Adelson) pyramid levels: sizes halve with rounding up
+    mw, mh, mpx = W, H, []
+    for _ in range(blend_levels):
+        mpx.append(mw * mh)
+        mw, mh = (mw + 1) // 2, (mh + 1) // 2
+    out = {}
+
+    def add(k, v):
+        out[k] = out.get(k, 0) + v
+
+    for name, cnt in launches.items():
+        base, flag = kernel_key(name)
+        if base == "k_hist":            # read both frames' luma
+            add(base, 2 * N)
+        elif base == "k_lut_pyr":       # read luma, write every pyramid level (both frames)
+            add(base, 2 * N + 2 * sum(reg_px))
+        elif base == "k_dt_row":        # first pass: guide in, 3 maps out; else 3 maps in/out
+            add(base, cnt * (13 * N if flag else 25 * N))
+        elif base == "k_dt_col":        # 3 maps + guide in; 3 maps (last: F and N~) out
+            add(base, cnt * 25 * N)
+        elif base == "k_bwarp":         # F, Y, UV, Y_eq in; RGB + warped Y_eq out
+            add(base, cnt * (8 + 1 + chroma + 1 + 4 * ch + 4) * N)
+        elif base == "k_frame_rgb":
+            add(base, cnt * (1 + chroma + 4 * ch) * N)
+        elif base == "k_u8_unit":
+            add(base, cnt * 5 * N)
+        elif base == "k_ssim":          # two luma maps in, SSIM out
+            add(base, cnt * 12 * N)
+        elif base == "k_weights":       # all frames' planes + SSIM in, weights out
+            add(base, cnt * (n * ch * 4 + (n - 1) * 4 + n * 4) * N)
+        elif base == "k_reduce":        # every weight/image plane, level l-1 in, level l out
+            add(base, sum(n * (ch + 1) * 4 * (mpx[l - 1] + mpx[l]) for l in range(1, blend_levels)))
+        elif base == "k_blend":         # weights, images, coarse images, coarse result in; result out
+            tot = 0
+            for l in range(blend_levels):
+                tot += (n * 4 + n * ch * 4 + ch * 4) * mpx[l]
+                if l + 1 < blend_levels:
+                    tot += (n * ch * 4 + ch * 4) * mpx[l + 1]
+            add(base, tot)
+    return out
 
 
 def main():
@@ -120,18 +162,34 @@ def main():
     print("[bench] per-step kernel time (ms): " +
           ", ".join(f"{k} {v[1]:.3f} ({v[0]:.0f}x)" for k, v in kernels), file=sys.stderr,
           flush=True)
+    sizes = lnr.query_sizes(W, H, lnr.LNR_I420, p)
+    launches = {k: v[0] for k, v in per_step.items()}
+    model = algo_bytes_per_step(W, H, True, 2, 3, sizes, sizes.blend_levels, launches)
+    by_base = {}
+    for name, (cnt, ms) in per_step.items():
+        base, _ = kernel_key(name)
+        c, t = by_base.get(base, (0.0, 0.0))
+        by_base[base] = (c + cnt, t + ms)
+    hbm = {}
+    for base, (cnt, ms) in by_base.items():
+        if base in model:
+            gbs = model[base] / (ms / 1e3) / 1e9
+            hbm[base] = {"ms": round(ms, 4), "launches": round(cnt, 2),
+                         "algo_bytes": int(model[base]), "gbs": round(gbs, 1),
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
     roof = None
-    for name, (cnt, ms) in kernels:
-        b = algo_bytes(name, W, H, 2, 3)
-        if b is None:
-            continue
-        avg_s = ms / cnt / 1e3
-        achieved = b / avg_s / 1e9
-        roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
-                "algo_bytes_per_launch": int(b)}
-        break
+    dom = max(by_base.items(), key=lambda kv: kv[1][1])[0] if by_base else None
+    # the dominant kernel with a bandwidth model (the search is reported apart)
+    cands = sorted(hbm.items(), key=lambda kv: -kv[1]["ms"])
+    if cands:
+        base, h = cands[0]
+        avg_s = by_base[base][1] / by_base[base][0] / 1e3
+        per_launch = h["algo_bytes"] / by_base[base][0]
+        roof = {"kernel": base, "bound": "hbm", "achieved": h["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": h["frac"], "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2),
+                "algo_bytes_per_launch": int(per_launch),
+                "dominant_overall": dom}
     # level-0 search against the int-VALU peak (pixel-candidate operations)
     out_reg = reg
     torch.cuda.synchronize()
@@ -162,6 +220,7 @@ def main():
         "search_level0": {"pixel_candidate_ops": search_ops,
                           "int_peak_tops": round(INT_PEAK_TOPS, 2)},
         "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kernels},
+        "hbm_kernels": hbm,
     }
     if "k_search" in per_step:
         # all five levels' searches; the level-0 share dominates

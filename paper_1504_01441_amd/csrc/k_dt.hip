@@ -8,13 +8,16 @@
 // maps are combined with a parallel scan, then re-run with the exact carry.
 // The step coefficient c = a_i^(1 + sigma_s/sigma_r |dI|) depends only on the
 // 8-bit guide difference, so each iteration uses a 256-entry table.
+// The recursions run in double precision (the maps are stored as float between
+// passes): with c close to 1 (sigma_s = 400) a float recursion amplifies
+// rounding by ~1/(1 - c), which would move the flow by ~1e-4 px.
 //
 //  k_dt_row: one workgroup per row; the row is staged in LDS with coalesced
-//          loads, each of the 256 threads keeps a segment in registers, and
+//          loads, each of the 256 or 512 threads keeps a segment in registers, and
 //          wave shuffles + LDS combine the segment maps. The first pass writes
 //          the sparse maps itself from the tile list (no zero-fill pass).
 //  k_dt_col: one workgroup per strip of 2-8 columns over the full height, as
-//          128 segments per column held in registers; the maps are read and
+//          128 or 256 segments per column held in registers; the maps are read and
 //          written once per pass. The last pass writes F (and N~) instead.
 #include "lnr_internal.h"
 
@@ -28,16 +31,16 @@ struct DtArgs {
 
 // c_i[k] = a_i ^ (1 + ratio * k / 255),  a_i = exp(-sqrt(2) / sigma_i),
 // sigma_i = sigma_s sqrt(3) 2^(n - i) / sqrt(4^n - 1)  (i = 1..n)
-__global__ void k_dt_coef(DtArgs a, float* __restrict__ coef) {
+__global__ void k_dt_coef(DtArgs a, double* __restrict__ coef) {
   const int i = blockIdx.x + 1, k = threadIdx.x;
   const double sig = a.sigma_s * sqrt(3.0) * pow(2.0, (double)(a.iters - i)) /
                      sqrt(pow(4.0, (double)a.iters) - 1.0);
   const double ai = exp(-sqrt(2.0) / sig);
-  coef[blockIdx.x * 256 + k] = (float)pow(ai, 1.0 + a.ratio * ((double)k / 255.0));
+  coef[blockIdx.x * 256 + k] = pow(ai, 1.0 + a.ratio * ((double)k / 255.0));
 }
 
 struct Aff {  // z -> A z + B (three channels share A)
-  float A, B0, B1, B2;
+  double A, B0, B1, B2;
 };
 
 // later o earlier
@@ -68,10 +71,10 @@ __device__ inline Aff shfl_down_aff(const Aff& v, int off) {
   return r;
 }
 
-// Carry into each thread of a 256-thread block: the composition of every
+// Carry into each thread of an NT-thread block: the composition of every
 // earlier thread's map (forward: lower tid; backward: higher tid) applied to 0.
-template <bool FWD>
-__device__ void block_carry(Aff v, Aff* wtot, float& c0, float& c1, float& c2) {
+template <int NT, bool FWD>
+__device__ void block_carry(Aff v, Aff* wtot, double& c0, double& c1, double& c2) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   Aff inc = v;
 #pragma unroll
@@ -82,14 +85,14 @@ __device__ void block_carry(Aff v, Aff* wtot, float& c0, float& c1, float& c2) {
   }
   if (FWD ? lane == 63 : lane == 0) wtot[wave] = inc;
   __syncthreads();
-  float z0 = 0.f, z1 = 0.f, z2 = 0.f;  // carry into this wave
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;  // carry into this wave
   if (FWD) {
     for (int w = 0; w < wave; ++w) {
       const Aff t = wtot[w];
       z0 = t.A * z0 + t.B0; z1 = t.A * z1 + t.B1; z2 = t.A * z2 + t.B2;
     }
   } else {
-    for (int w = 3; w > wave; --w) {
+    for (int w = NT / 64 - 1; w > wave; --w) {
       const Aff t = wtot[w];
       z0 = t.A * z0 + t.B0; z1 = t.A * z1 + t.B1; z2 = t.A * z2 + t.B2;
     }
@@ -107,32 +110,32 @@ __device__ void block_carry(Aff v, Aff* wtot, float& c0, float& c1, float& c2) {
 
 // Coefficient between positions i-1 and i of a line: 0 where i - 1 or i is
 // outside [0, n) (the recursion starts fresh at both ends).
-__device__ inline float coef_at(const float* cf, int gprev, int gcur) {
+__device__ inline double coef_at(const double* cf, int gprev, int gcur) {
   return cf[abs(gcur - gprev)];
 }
 
 // ---------------------------------------------------------------------------
 // Horizontal pass: one block per row; the row is staged in LDS (coalesced),
 // each thread keeps a segment of SEG consecutive pixels in registers.
-template <int SEG, bool FIRST>
-__global__ __launch_bounds__(256) void k_dt_row(float* __restrict__ maps,
+template <int SEG, int NT, bool FIRST>
+__global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
                                                 const uint8_t* __restrict__ guide, int W, int H,
-                                                const float* __restrict__ coef,
+                                                const double* __restrict__ coef,
                                                 const int32_t* __restrict__ cxy,
                                                 const int32_t* __restrict__ disp,
                                                 const uint8_t* __restrict__ flags, int ntx,
                                                 int nty, int tile) {
   extern __shared__ float sm[];
-  __shared__ float cf[256];
-  __shared__ Aff wtot[4];
+  __shared__ double cf[256];
+  __shared__ Aff wtot[NT / 64];
   float* v0 = sm;
   float* v1 = sm + W;
   float* v2 = sm + 2 * W;
   uint8_t* g = reinterpret_cast<uint8_t*>(sm + 3 * W);
   const int y = blockIdx.x, tid = threadIdx.x;
   const size_t plane = (size_t)W * H, ro = (size_t)y * W;
-  cf[tid] = coef[tid];
-  for (int x = tid; x < W; x += 256) {
+  if (tid < 256) cf[tid] = coef[tid];
+  for (int x = tid; x < W; x += NT) {
     g[x] = guide[ro + x];
     if (FIRST) {
       v0[x] = 0.f; v1[x] = 0.f; v2[x] = 0.f;
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(256) void k_dt_row(float* __restrict__ maps,
     __syncthreads();
     const int ty = y / tile;
     if (ty < nty)
-      for (int tx = tid; tx < ntx; tx += 256) {
+      for (int tx = tid; tx < ntx; tx += NT) {
         const int t = ty * ntx + tx;
         if ((flags[t] & 4) && cxy[2 * t + 1] == y) {
           const int x = cxy[2 * t];
@@ -156,38 +159,38 @@ __global__ __launch_bounds__(256) void k_dt_row(float* __restrict__ maps,
   }
   __syncthreads();
   const int xb = tid * SEG;
-  float a0[SEG], a1[SEG], a2[SEG], cc[SEG + 1];  // cc[j]: between xb+j-1 and xb+j
+  double a0[SEG], a1[SEG], a2[SEG], cc[SEG + 1];  // cc[j]: between xb+j-1 and xb+j
   int gp = xb > 0 && xb - 1 < W ? g[xb - 1] : 0;
 #pragma unroll
   for (int j = 0; j <= SEG; ++j) {
     const int x = xb + j;
     const int gc = x < W ? g[x] : 0;
-    cc[j] = (x > 0 && x < W) ? coef_at(cf, gp, gc) : 0.f;
+    cc[j] = (x > 0 && x < W) ? coef_at(cf, gp, gc) : 0.0;
     gp = gc;
     if (j < SEG) {
-      a0[j] = x < W ? v0[x] : 0.f;
-      a1[j] = x < W ? v1[x] : 0.f;
-      a2[j] = x < W ? v2[x] : 0.f;
+      a0[j] = x < W ? (double)v0[x] : 0.0;
+      a1[j] = x < W ? (double)v1[x] : 0.0;
+      a2[j] = x < W ? (double)v2[x] : 0.0;
     }
   }
   // causal: J[x] = J[x] + c (J[x-1] - J[x])
   {
-    Aff t{1.f, 0.f, 0.f, 0.f};
+    Aff t{1.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
-      if (xb + j >= W) break;
-      const float c = cc[j];
+      if (xb + j >= W) continue;
+      const double c = cc[j];
       t.B0 = a0[j] + c * (t.B0 - a0[j]);
       t.B1 = a1[j] + c * (t.B1 - a1[j]);
       t.B2 = a2[j] + c * (t.B2 - a2[j]);
       t.A *= c;
     }
-    float p0, p1, p2;
-    block_carry<true>(t, wtot, p0, p1, p2);
+    double p0, p1, p2;
+    block_carry<NT, true>(t, wtot, p0, p1, p2);
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
-      if (xb + j >= W) break;
-      const float c = cc[j];
+      if (xb + j >= W) continue;
+      const double c = cc[j];
       p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
       p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
       p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
@@ -195,22 +198,22 @@ __global__ __launch_bounds__(256) void k_dt_row(float* __restrict__ maps,
   }
   // anti-causal: J[x] = J[x] + c (J[x+1] - J[x]), c between x and x+1
   {
-    Aff t{1.f, 0.f, 0.f, 0.f};
+    Aff t{1.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = SEG - 1; j >= 0; --j) {
       if (xb + j >= W) continue;
-      const float c = cc[j + 1];
+      const double c = cc[j + 1];
       t.B0 = a0[j] + c * (t.B0 - a0[j]);
       t.B1 = a1[j] + c * (t.B1 - a1[j]);
       t.B2 = a2[j] + c * (t.B2 - a2[j]);
       t.A *= c;
     }
-    float p0, p1, p2;
-    block_carry<false>(t, wtot, p0, p1, p2);
+    double p0, p1, p2;
+    block_carry<NT, false>(t, wtot, p0, p1, p2);
 #pragma unroll
     for (int j = SEG - 1; j >= 0; --j) {
       if (xb + j >= W) continue;
-      const float c = cc[j + 1];
+      const double c = cc[j + 1];
       p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
       p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
       p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
@@ -219,23 +222,23 @@ __global__ __launch_bounds__(256) void k_dt_row(float* __restrict__ maps,
 #pragma unroll
   for (int j = 0; j < SEG; ++j) {
     const int x = xb + j;
-    if (x < W) { v0[x] = a0[j]; v1[x] = a1[j]; v2[x] = a2[j]; }
+    if (x < W) { v0[x] = (float)a0[j]; v1[x] = (float)a1[j]; v2[x] = (float)a2[j]; }
   }
   __syncthreads();
-  for (int x = tid; x < W; x += 256) {
+  for (int x = tid; x < W; x += NT) {
     maps[ro + x] = v0[x]; maps[plane + ro + x] = v1[x]; maps[2 * plane + ro + x] = v2[x];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Vertical pass: a block covers NCOL adjacent columns over the full height as
-// NSEG = 1024 / NCOL (or 512 / NCOL) segments of L rows; each thread keeps its
+// NSEG segments of L rows (NCOL * NSEG = 512 threads); each thread keeps its
 // segment of one column in registers, so the maps are read and written once.
 // Segment carries are combined with wave shuffles (segments of a column sit
 // NCOL lanes apart) and per-wave totals in LDS.
 template <int NCOL, int NSEG>
-__device__ void seg_carry(Aff v, bool fwd, Aff* wt /*[NSEG*NCOL/64][NCOL]*/, float& c0,
-                          float& c1, float& c2) {
+__device__ void seg_carry(Aff v, bool fwd, Aff* wt /*[NSEG*NCOL/64][NCOL]*/, double& c0,
+                          double& c1, double& c2) {
   constexpr int PER = 64 / NCOL;  // segments of one column per wave
   constexpr int NW = NSEG / PER;  // waves
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = tid % NCOL;
@@ -249,7 +252,7 @@ __device__ void seg_carry(Aff v, bool fwd, Aff* wt /*[NSEG*NCOL/64][NCOL]*/, flo
   }
   if (fwd ? sl == PER - 1 : sl == 0) wt[wave * NCOL + cl] = inc;
   __syncthreads();
-  float z0 = 0.f, z1 = 0.f, z2 = 0.f;
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
   if (fwd) {
     for (int w = 0; w < wave; ++w) {
       const Aff t = wt[w * NCOL + cl];
@@ -275,10 +278,10 @@ __device__ void seg_carry(Aff v, bool fwd, Aff* wt /*[NSEG*NCOL/64][NCOL]*/, flo
 template <int L, int NCOL, int NSEG, bool LAST>
 __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps,
                                                         const uint8_t* __restrict__ guide, int W,
-                                                        int H, const float* __restrict__ coef,
+                                                        int H, const double* __restrict__ coef,
                                                         float* __restrict__ flow,
-                                                        float* __restrict__ ntilde, float nmin) {
-  __shared__ float cf[256];
+                                                        float* __restrict__ ntilde, double nmin) {
+  __shared__ double cf[256];
   __shared__ Aff wt[NSEG * NCOL / 64 * NCOL];
   const int tid = threadIdx.x, cl = tid % NCOL, sg = tid / NCOL;
   // XCD-aware strip order: consecutive blocks run on different XCDs, so
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
   uint32_t gpk[NG];
 #pragma unroll
   for (int q = 0; q < NG; ++q) gpk[q] = 0u;
-  float a0[L], a1[L], a2[L];
+  double a0[L], a1[L], a2[L];
 #pragma unroll
   for (int j = -1; j <= L; ++j) {
     const int y = r0 + j;
@@ -306,52 +309,52 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     const uint32_t gv = in ? guide[o] : 0u;
     gpk[(j + 1) >> 2] |= gv << (8 * ((j + 1) & 3));
     if (j >= 0 && j < L) {
-      a0[j] = in ? maps[o] : 0.f;
-      a1[j] = in ? maps[plane + o] : 0.f;
-      a2[j] = in ? maps[2 * plane + o] : 0.f;
+      a0[j] = in ? (double)maps[o] : 0.0;
+      a1[j] = in ? (double)maps[plane + o] : 0.0;
+      a2[j] = in ? (double)maps[2 * plane + o] : 0.0;
     }
   }
 #define GB(j) ((int)((gpk[((j) + 1) >> 2] >> (8 * (((j) + 1) & 3))) & 255u))
-#define CC(j) ((r0 + (j) > 0 && r0 + (j) < H) ? cf[abs(GB(j) - GB((j) - 1))] : 0.f)
+#define CC(j) ((r0 + (j) > 0 && r0 + (j) < H) ? cf[abs(GB(j) - GB((j) - 1))] : 0.0)
   {
-    Aff t{1.f, 0.f, 0.f, 0.f};
+    Aff t{1.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < L; ++j) {
       if (r0 + j >= H) break;
-      const float c = CC(j);
+      const double c = CC(j);
       t.B0 = a0[j] + c * (t.B0 - a0[j]);
       t.B1 = a1[j] + c * (t.B1 - a1[j]);
       t.B2 = a2[j] + c * (t.B2 - a2[j]);
       t.A *= c;
     }
-    float p0, p1, p2;
+    double p0, p1, p2;
     seg_carry<NCOL, NSEG>(t, true, wt, p0, p1, p2);
 #pragma unroll
     for (int j = 0; j < L; ++j) {
       if (r0 + j >= H) break;
-      const float c = CC(j);
+      const double c = CC(j);
       p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
       p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
       p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
     }
   }
   {
-    Aff t{1.f, 0.f, 0.f, 0.f};
+    Aff t{1.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
       if (r0 + j >= H) continue;
-      const float c = CC(j + 1);
+      const double c = CC(j + 1);
       t.B0 = a0[j] + c * (t.B0 - a0[j]);
       t.B1 = a1[j] + c * (t.B1 - a1[j]);
       t.B2 = a2[j] + c * (t.B2 - a2[j]);
       t.A *= c;
     }
-    float p0, p1, p2;
+    double p0, p1, p2;
     seg_carry<NCOL, NSEG>(t, false, wt, p0, p1, p2);
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
       if (r0 + j >= H) continue;
-      const float c = CC(j + 1);
+      const double c = CC(j + 1);
       p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
       p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
       p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
@@ -367,38 +370,38 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     const size_t o = (size_t)y * W + col;
     if (LAST) {
       const bool ok = a2[j] > nmin;
-      flow[o] = ok ? a0[j] / a2[j] : 0.f;
-      flow[plane + o] = ok ? a1[j] / a2[j] : 0.f;
-      if (ntilde) ntilde[o] = a2[j];
+      flow[o] = ok ? (float)(a0[j] / a2[j]) : 0.f;
+      flow[plane + o] = ok ? (float)(a1[j] / a2[j]) : 0.f;
+      if (ntilde) ntilde[o] = (float)a2[j];
     } else {
-      maps[o] = a0[j]; maps[plane + o] = a1[j]; maps[2 * plane + o] = a2[j];
+      maps[o] = (float)a0[j]; maps[plane + o] = (float)a1[j]; maps[2 * plane + o] = (float)a2[j];
     }
   }
 }
 
-template <int SEG>
+template <int SEG, int NT>
 hipError_t launch_row(bool first, float* maps, const uint8_t* guide, int W, int H,
-                      const float* cf, const int32_t* cxy, const int32_t* disp,
+                      const double* cf, const int32_t* cxy, const int32_t* disp,
                       const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
   const size_t lds = (size_t)W * 3 * sizeof(float) + (size_t)W + 16;
   if (lds > 64 * 1024) {  // rows wider than ~5000 px need more than the default LDS
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(first ? &k_dt_row<SEG, true> : &k_dt_row<SEG, false>),
+        reinterpret_cast<const void*>(first ? &k_dt_row<SEG, NT, true> : &k_dt_row<SEG, NT, false>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   if (first)
-    LNR_LAUNCH((k_dt_row<SEG, true>), dim3(H), dim3(256), lds, st, maps, guide, W, H, cf, cxy,
+    LNR_LAUNCH((k_dt_row<SEG, NT, true>), dim3(H), dim3(NT), lds, st, maps, guide, W, H, cf, cxy,
                disp, flags, ntx, nty, tile);
   else
-    LNR_LAUNCH((k_dt_row<SEG, false>), dim3(H), dim3(256), lds, st, maps, guide, W, H, cf, cxy,
+    LNR_LAUNCH((k_dt_row<SEG, NT, false>), dim3(H), dim3(NT), lds, st, maps, guide, W, H, cf, cxy,
                disp, flags, ntx, nty, tile);
   return hipGetLastError();
 }
 
 template <int L, int NCOL, int NSEG>
 hipError_t launch_col(bool last, float* maps, const uint8_t* guide, int W, int H,
-                      const float* cf, float* flow, float* ntilde, float nmin, hipStream_t st) {
+                      const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
   const dim3 grid((W + NCOL - 1) / NCOL);
   if (last)
     LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, true>), grid, dim3(NCOL * NSEG), 0, st, maps, guide, W, H,
@@ -413,7 +416,7 @@ hipError_t launch_col(bool last, float* maps, const uint8_t* guide, int W, int H
 
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
                        int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
-                       const lnr_params& p, float* maps, float* coef, float* flow,
+                       const lnr_params& p, float* maps, double* coef, float* flow,
                        float* ntilde, hipStream_t st) {
   DtArgs a;
   a.iters = p.dt_iters;
@@ -422,24 +425,24 @@ hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint
   LNR_LAUNCH(k_dt_coef, dim3(a.iters), dim3(256), 0, st, a, coef);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const float nmin = (float)p.n_min;
-  const int seg = (W + 255) / 256;  // row segment per thread (W <= 6144)
+  const double nmin = p.n_min;
   for (int i = 0; i < a.iters; ++i) {
-    const float* cf = coef + 256 * i;
+    const double* cf = coef + 256 * i;
     const bool first = i == 0, last = i + 1 == a.iters;
-    if (seg <= 4) e = launch_row<4>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else if (seg <= 8) e = launch_row<8>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else if (seg <= 12) e = launch_row<12>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else if (seg <= 16) e = launch_row<16>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else e = launch_row<24>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    // row segments of SEG pixels per thread (W <= 6144); the double-precision
+    // segments stay within 256 VGPRs per thread
+    if (W <= 1024) e = launch_row<4, 256>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else if (W <= 2048) e = launch_row<8, 256>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else if (W <= 3072) e = launch_row<12, 256>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else if (W <= 4096) e = launch_row<8, 512>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    else e = launch_row<12, 512>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
     if (e != hipSuccess) return e;
-    // column segments: 128 per column, L rows each (H <= 6144)
+    // column segments of L rows, NSEG per column (H <= 6144)
     if (H <= 1024) e = launch_col<8, 8, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
     else if (H <= 2048) e = launch_col<16, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
     else if (H <= 3072) e = launch_col<24, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
-    else if (H <= 4096) e = launch_col<32, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
-    else e = launch_col<48, 2, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
-    // (register budget: 128 VGPRs at 1024 threads, 256 at 512, 512 at 256)
+    else if (H <= 4096) e = launch_col<16, 2, 256>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    else e = launch_col<24, 2, 256>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

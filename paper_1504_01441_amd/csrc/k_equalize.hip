@@ -2,7 +2,8 @@
 // every input before matching: paper Sec. 3 opening) and the matching pyramid
 // (Sec. 2.2 / 2.6: up to 5 levels, 2x2 box mean rounded half up).
 //
-// k_hist: LDS histograms (16 copies), one global atomic add per bin per block.
+// k_hist: LDS histograms (16 copies; a wave per row, 32-bit loads), one global
+// atomic add per bin per block.
 // k_lut_pyr: each block rebuilds the 256-entry LUT from the histogram (prefix
 // sum in LDS), equalises a 64x64 block of Y and writes pyramid levels 1..L-1
 // of that block from LDS, so the pyramid costs no extra pass over HBM.
@@ -11,7 +12,7 @@
 namespace lnr {
 namespace {
 
-constexpr int kHistBlocks = 192;
+constexpr int kHistRows = 4;  // rows per block, one wave per row
 
 constexpr int kCopies = 16, kCopyStride = 257;  // odd stride: copies hit different banks
 
@@ -21,15 +22,35 @@ __global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ y0, in
   // neighbouring pixels share values, so lanes spread their LDS atomics over
   // 16 copies of the bins
   __shared__ uint32_t bins[kCopies * kCopyStride];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < kCopies * kCopyStride; i += 256) bins[i] = 0;
   __syncthreads();
   const uint8_t* img = blockIdx.y ? y1 : y0;
   const int stride = blockIdx.y ? s1 : s0;
-  uint32_t* mine = bins + (tid & (kCopies - 1)) * kCopyStride;
-  for (int row = blockIdx.x; row < H; row += gridDim.x) {
+  uint32_t* mine = bins + (lane & (kCopies - 1)) * kCopyStride;
+  const int row = blockIdx.x * kHistRows + wave;
+  if (row < H) {
+    // the row as aligned 32-bit words plus unaligned head and tail bytes
     const uint8_t* p = img + (size_t)row * stride;
-    for (int x = tid; x < W; x += 256) atomicAdd(&mine[p[x]], 1u);
+    const int head = min(W, (int)((4 - ((uintptr_t)p & 3)) & 3));
+    const int nw = (W - head) >> 2;
+    const int tail = W - head - 4 * nw;
+    if (lane < head) atomicAdd(&mine[p[lane]], 1u);
+    if (lane < tail) atomicAdd(&mine[p[head + 4 * nw + lane]], 1u);
+    const uint32_t* pw = reinterpret_cast<const uint32_t*>(p + head);
+    for (int i0 = lane; i0 < nw; i0 += 64 * 4) {
+      uint32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = i0 + 64 * u < nw ? pw[i0 + 64 * u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + 64 * u < nw) {
+          atomicAdd(&mine[v[u] & 255u], 1u);
+          atomicAdd(&mine[(v[u] >> 8) & 255u], 1u);
+          atomicAdd(&mine[(v[u] >> 16) & 255u], 1u);
+          atomicAdd(&mine[v[u] >> 24], 1u);
+        }
+    }
   }
   __syncthreads();
   uint32_t s = 0;
@@ -136,7 +157,7 @@ __global__ __launch_bounds__(256) void k_lut_pyr(const uint8_t* __restrict__ y0,
 
 hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int W, int H,
                        uint32_t* hist, int nframes, hipStream_t st) {
-  dim3 grid(kHistBlocks < H ? kHistBlocks : H, nframes);
+  dim3 grid((H + kHistRows - 1) / kHistRows, nframes);
   LNR_LAUNCH(k_hist, grid, dim3(256), 0, st, y0, s0, y1, s1, W, H, hist);
   return hipGetLastError();
 }

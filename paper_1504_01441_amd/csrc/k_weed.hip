@@ -1,20 +1,23 @@
 // k_weed.hip -- match weeding (paper Sec. 2.3, Eq. 5) and the level
-// homography (Sec. 2.2) on the GPU, with no host round trip.
+// homography (Sec. 2.2) on the GPU, with no host round trip. Matches are the
+// valid tiles of the level, indexed in tile order (centred level coordinates:
+// source side p + d - c, reference side p - c).
 //
-// k_compact: one workgroup lists the valid matches of the level in tile order
-//   (centred level coordinates: source side p + d - c, reference side p - c).
-// k_weedfit: a (256 matches x 8 iterations) block draws four distinct
-//   indices per iteration from the counter-based SplitMix64 stream, solves
-//   the 8x8 system in double precision (partial pivoting, fixed operation
-//   order), and tests its matches; wave ballots form each iteration's inlier
-//   bitmask row and the counts are summed with atomics. The last block of an
-//   iteration group ORs the accepted rows (count > delta) into M with 64-bit
-//   atomics, so M is the same for any execution order (the paper's note that
-//   the iterations can be split freely), and keeps the best consensus as a
-//   64-bit atomicMax on (count << 32 | ~iteration). The last block overall
-//   re-tests the best hypothesis, sums the least-squares normal equations of
-//   G: p -> p + d over its inliers exactly in int64 (order-free), and solves
-//   and composes H_l = H_{l+1} o G in double precision.
+// k_hyp:  one lane per iteration. Each wave counts the valid tiles, draws four
+//         distinct match indices from the counter-based SplitMix64 stream,
+//         maps them to tiles with a rank-select over ballot masks, and solves
+//         the 8x8 system in double precision (partial pivoting, fixed
+//         operation order) with the matrix in registers.
+// k_test: a (256 tiles x 8 iterations) block tests its tiles against its
+//         hypotheses; wave ballots form each iteration's inlier bitmask row,
+//         and the block's count per iteration is added atomically.
+// k_fit:  one block sums the counts, takes M as the union of the rows whose
+//         count exceeds delta (any split of the iterations gives the same M,
+//         as the paper notes), finds the best consensus (most inliers, lowest
+//         iteration), sums the least-squares normal equations of G: p -> p + d
+//         over that hypothesis' inliers exactly in int64 (order-free), and
+//         solves and composes H_l = H_{l+1} o G in double precision.
+// The three are ordered by the stream; no block waits for another.
 #include "lnr_device.h"
 #include "lnr_internal.h"
 
@@ -28,30 +31,42 @@ __device__ inline unsigned long long splitmix64(unsigned long long x) {
   return z ^ (z >> 31);
 }
 
-// 8x8 solve of the augmented system a (row-major 8 x 9): Gaussian elimination
-// with partial pivoting (first largest |pivot|); |pivot| < 1e-12 or NaN fails.
-__device__ bool solve8(double* a, double* x) {
+// 8x8 solve of the augmented system a (row-major 8 x 9), kept in registers
+// (every index is a compile-time constant): Gaussian elimination with partial
+// pivoting (first largest |pivot|); |pivot| < 1e-12 or NaN fails. Entries left
+// of the pivot column are never read again, so row swaps move columns c..8.
+__device__ inline bool solve8(double (&a)[72], double (&x)[8]) {
+#pragma unroll
   for (int c = 0; c < 8; ++c) {
     int piv = c;
     double best = fabs(a[c * 9 + c]);
+#pragma unroll
     for (int r = c + 1; r < 8; ++r) {
       const double v = fabs(a[r * 9 + c]);
       if (v > best) { best = v; piv = r; }
     }
     if (!(best >= 1e-12)) return false;
-    if (piv != c)
-      for (int j = 0; j < 9; ++j) {
-        const double t = a[c * 9 + j];
-        a[c * 9 + j] = a[piv * 9 + j];
-        a[piv * 9 + j] = t;
+#pragma unroll
+    for (int r = c + 1; r < 8; ++r)
+      if (piv == r) {
+#pragma unroll
+        for (int j = c; j < 9; ++j) {
+          const double t = a[c * 9 + j];
+          a[c * 9 + j] = a[r * 9 + j];
+          a[r * 9 + j] = t;
+        }
       }
+#pragma unroll
     for (int r = c + 1; r < 8; ++r) {
       const double f = a[r * 9 + c] / a[c * 9 + c];
+#pragma unroll
       for (int j = c; j < 9; ++j) a[r * 9 + j] = a[r * 9 + j] - f * a[c * 9 + j];
     }
   }
+#pragma unroll
   for (int c = 7; c >= 0; --c) {
     double s = a[c * 9 + 8];
+#pragma unroll
     for (int j = c + 1; j < 8; ++j) s = s - a[c * 9 + j] * x[j];
     x[c] = s / a[c * 9 + c];
   }
@@ -69,44 +84,10 @@ __device__ inline bool is_inlier(const double* g, int4 m, double eps2) {
   return e2 < eps2;
 }
 
-__global__ __launch_bounds__(1024) void k_compact(const int32_t* __restrict__ cxy,
-                                                  const int32_t* __restrict__ disp,
-                                                  const uint8_t* __restrict__ flags, int ntiles,
-                                                  int w, int h, int4* __restrict__ matches,
-                                                  int32_t* __restrict__ tile_of,
-                                                  int32_t* __restrict__ nmatch,
-                                                  unsigned long long* __restrict__ mbits,
-                                                  unsigned long long* __restrict__ best,
-                                                  int32_t* __restrict__ counts, int iters,
-                                                  uint32_t* __restrict__ done, int ndone) {
-  __shared__ int part[1024];
-  const int tid = threadIdx.x;
-  const int chunk = (ntiles + 1023) / 1024;
-  const int t0 = tid * chunk, t1 = min(ntiles, t0 + chunk);
-  int cnt = 0;
-  for (int t = t0; t < t1; ++t) cnt += (flags[t] & 2) ? 1 : 0;
-  part[tid] = cnt;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int add = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += add;
-    __syncthreads();
-  }
-  int k = part[tid] - cnt;
-  const int ox = w / 2, oy = h / 2;
-  for (int t = t0; t < t1; ++t)
-    if (flags[t] & 2) {
-      const int px = cxy[2 * t], py = cxy[2 * t + 1];
-      matches[k] = make_int4(px + disp[2 * t] - ox, py + disp[2 * t + 1] - oy, px - ox, py - oy);
-      tile_of[k] = t;
-      ++k;
-    }
-  if (tid == 1023) *nmatch = part[1023];
-  for (int i = tid; i < (ntiles + 63) / 64; i += 1024) mbits[i] = 0ull;
-  for (int i = tid; i < iters; i += 1024) counts[i] = 0;
-  for (int i = tid; i < ndone; i += 1024) done[i] = 0u;
-  if (tid == 0) *best = 0ull;
+__device__ inline int4 tile_match(const int32_t* __restrict__ cxy,
+                                  const int32_t* __restrict__ disp, int t, int ox, int oy) {
+  const int px = cxy[2 * t], py = cxy[2 * t + 1];
+  return make_int4(px + disp[2 * t] - ox, py + disp[2 * t + 1] - oy, px - ox, py - oy);
 }
 
 struct WeedArgs {
@@ -120,32 +101,178 @@ __device__ inline int weed_delta(int N, const WeedArgs& a) {
   return d > a.delta_min ? d : a.delta_min;
 }
 
-// Draw and fit hypothesis `it` (identical in every lane). Returns false when
-// the draw or the fit is degenerate.
-__device__ bool hypothesis(const int4* __restrict__ matches, int N, int it, const WeedArgs& a,
-                           double* g) {
-  const unsigned long long base = a.seed ^ ((unsigned long long)(uint32_t)a.level << 56);
-  int pick[4], np = 0;
-  for (int t = 0; t < 16 && np < 4; ++t) {
-    const unsigned long long u = splitmix64(base + (unsigned long long)it * 16ull + (unsigned long long)t);
-    const int id = (int)(((u >> 32) * (unsigned long long)N) >> 32);
-    bool dup = false;
-    for (int q = 0; q < np; ++q) dup |= pick[q] == id;
-    if (!dup) pick[np++] = id;
+// position of the k-th (0-based) set bit of m (k < popcount(m))
+__device__ inline int select_bit(unsigned long long m, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int half = 32; half >= 1; half >>= 1) {
+    const unsigned long long lo = m & ((1ull << half) - 1ull);
+    const int c = __popcll(lo);
+    if (k >= c) {
+      k -= c;
+      m >>= half;
+      pos += half;
+    } else {
+      m = lo;
+    }
   }
-  if (np < 4) return false;
-  double A[8 * 9];
-  for (int q = 0; q < 4; ++q) {
-    const int4 m = matches[pick[q]];
-    const double sx = (double)m.x, sy = (double)m.y, tx = (double)m.z, ty = (double)m.w;
-    double* r0 = A + (2 * q) * 9;
-    double* r1 = A + (2 * q + 1) * 9;
-    r0[0] = sx; r0[1] = sy; r0[2] = 1; r0[3] = 0; r0[4] = 0; r0[5] = 0;
-    r0[6] = -(sx * tx); r0[7] = -(sy * tx); r0[8] = tx;
-    r1[0] = 0; r1[1] = 0; r1[2] = 0; r1[3] = sx; r1[4] = sy; r1[5] = 1;
-    r1[6] = -(sx * ty); r1[7] = -(sy * ty); r1[8] = ty;
+  return pos;
+}
+
+constexpr int kHypThreads = 256;
+constexpr int kItPerBlock = 8;
+constexpr int kTestThreads = 256;
+constexpr int kFitThreads = 512;  // the final solve needs ~160 VGPRs
+constexpr int kMaxIters = 65536;  // the parameter check's bound on weed_iters
+constexpr int kMaxWords = 2304;   // tile bitmask words: (6144 / 16)^2 tiles
+
+__global__ __launch_bounds__(kHypThreads) void k_hyp(
+    const uint8_t* __restrict__ flags, const int32_t* __restrict__ cxy,
+    const int32_t* __restrict__ disp, int ntiles, int w, int h, WeedArgs a,
+    double* __restrict__ G, int32_t* __restrict__ cnt, int32_t* __restrict__ nmatch) {
+  __shared__ unsigned long long vb[kMaxWords];  // valid-tile bits, tile order
+  __shared__ int wpre[kMaxWords + 1];            // valid tiles before each word
+  __shared__ int wsum[kHypThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = kHypThreads / 64;
+  const int nwords = (ntiles + 63) >> 6;
+  // word wi = ballot of tiles 64 wi .. 64 wi + 63 (one coalesced byte load per lane)
+  for (int w0 = wave; w0 < nwords; w0 += 8 * NW) {
+    uint8_t f[8];  // eight loads in flight, then the ballots
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = (w0 + u * NW) * 64 + lane;
+      f[u] = t < ntiles ? flags[t] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const unsigned long long m = __ballot(f[u] & 2);
+      if (lane == 0 && w0 + u * NW < nwords) vb[w0 + u * NW] = m;
+    }
   }
-  return solve8(A, g);
+  __syncthreads();
+  // exclusive prefix of the words' popcounts: thread owns a run of K words
+  const int K = (nwords + kHypThreads - 1) / kHypThreads;
+  int c = 0;
+  for (int j = 0; j < K; ++j) {
+    const int wi = tid * K + j;
+    if (wi < nwords) c += __popcll(vb[wi]);
+  }
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int before = 0, N = 0;
+  for (int q = 0; q < NW; ++q) {
+    before += q < wave ? wsum[q] : 0;
+    N += wsum[q];
+  }
+  int run = before + incl - c;
+  for (int j = 0; j < K; ++j) {
+    const int wi = tid * K + j;
+    if (wi < nwords) {
+      wpre[wi] = run;
+      run += __popcll(vb[wi]);
+    }
+  }
+  if (tid == 0) wpre[nwords] = N;
+  __syncthreads();
+  if (blockIdx.x == 0 && tid == 0) *nmatch = N;
+  const int it = blockIdx.x * kHypThreads + tid;
+  bool ok = N >= 4 && it < a.iters;
+  int pk[4] = {-1, -1, -1, -1};
+  if (ok) {
+    const unsigned long long base = a.seed ^ ((unsigned long long)(uint32_t)a.level << 56);
+    int np = 0;
+    for (int t = 0; t < 16 && np < 4; ++t) {
+      const unsigned long long u =
+          splitmix64(base + (unsigned long long)it * 16ull + (unsigned long long)t);
+      const int id = (int)(((u >> 32) * (unsigned long long)N) >> 32);
+      if (id == pk[0] || id == pk[1] || id == pk[2]) continue;  // a repeat: draw again
+      if (np == 0) pk[0] = id;
+      else if (np == 1) pk[1] = id;
+      else if (np == 2) pk[2] = id;
+      else pk[3] = id;
+      ++np;
+    }
+    ok = np == 4;
+  }
+  if (ok) {
+    const int ox = w / 2, oy = h / 2;
+    double A[72];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // match index -> tile: last word with wpre <= id, then the bit within it
+      const int id = pk[q];
+      int lo = 0, hi = nwords - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wpre[mid] <= id) lo = mid;
+        else hi = mid - 1;
+      }
+      const int tq = lo * 64 + select_bit(vb[lo], id - wpre[lo]);
+      const int4 m = tile_match(cxy, disp, tq, ox, oy);
+      const double sx = (double)m.x, sy = (double)m.y, tx = (double)m.z, ty = (double)m.w;
+      double* r0 = A + (2 * q) * 9;
+      double* r1 = A + (2 * q + 1) * 9;
+      r0[0] = sx; r0[1] = sy; r0[2] = 1; r0[3] = 0; r0[4] = 0; r0[5] = 0;
+      r0[6] = -(sx * tx); r0[7] = -(sy * tx); r0[8] = tx;
+      r1[0] = 0; r1[1] = 0; r1[2] = 0; r1[3] = sx; r1[4] = sy; r1[5] = 1;
+      r1[6] = -(sx * ty); r1[7] = -(sy * ty); r1[8] = ty;
+    }
+    double g[8];
+    ok = solve8(A, g);
+    if (ok)
+      for (int i = 0; i < 8; ++i) G[(size_t)it * 8 + i] = g[i];
+  }
+  // k_test adds each tile chunk's inliers; -1: too few matches, degenerate draw or fit
+  if (it < a.iters) cnt[it] = ok ? 0 : -1;
+}
+
+// Tile chunk blockIdx.x x iteration group blockIdx.y: adds the chunk's inlier
+// counts to cnt[iter] and stores the inlier bits in bal[word][iter]
+// (word-major, so that the union reads each word's rows contiguously).
+__global__ __launch_bounds__(kTestThreads) void k_test(
+    const int32_t* __restrict__ cxy, const int32_t* __restrict__ disp,
+    const uint8_t* __restrict__ flags, int ntiles, int w, int h, WeedArgs a,
+    const double* __restrict__ G, int32_t* __restrict__ cnt,
+    unsigned long long* __restrict__ bal, int wstride) {
+  __shared__ double gs[kItPerBlock][8];
+  __shared__ int ok[kItPerBlock];
+  __shared__ int wc[kItPerBlock][kTestThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int it0 = blockIdx.y * kItPerBlock;
+  if (tid < kItPerBlock) {
+    const int it = it0 + tid;
+    // usable hypotheses start at 0 and only grow, so the sign is stable
+    const bool good = it < a.iters && __atomic_load_n(&cnt[it], __ATOMIC_RELAXED) >= 0;
+    ok[tid] = good;
+    for (int i = 0; i < 8; ++i) gs[tid][i] = good ? G[(size_t)it * 8 + i] : 0.0;
+  }
+  __syncthreads();
+  const int t = blockIdx.x * kTestThreads + tid;
+  const bool valid = t < ntiles && (flags[t] & 2);
+  const int4 m = valid ? tile_match(cxy, disp, t, w / 2, h / 2) : make_int4(0, 0, 0, 0);
+  const int word = t >> 6;
+  for (int q = 0; q < kItPerBlock; ++q) {
+    if (!ok[q]) continue;
+    const bool in = valid && is_inlier(gs[q], m, a.eps2);
+    const unsigned long long b = __ballot(in);
+    if (lane == 0) {
+      if (word < wstride) bal[(size_t)word * a.iters + it0 + q] = b;
+      wc[q][wave] = __popcll(b);
+    }
+  }
+  __syncthreads();
+  if (tid < kItPerBlock && ok[tid]) {
+    int s = 0;
+    for (int q = 0; q < kTestThreads / 64; ++q) s += wc[tid][q];
+    if (s) atomicAdd(&cnt[it0 + tid], s);
+  }
 }
 
 __device__ inline long long wave_sum_i64(long long v) {
@@ -154,98 +281,281 @@ __device__ inline long long wave_sum_i64(long long v) {
   return v;
 }
 
-// index of the upper-triangle entry (i <= j) of the 8x8 normal matrix
-__device__ inline int tri(int i, int j) { return i * 8 - (i * (i - 1)) / 2 + (j - i); }
-
-constexpr int kItPerBlock = 8;
-constexpr int kWeedThreads = 256;
-
-// Signal that this block is done with its share; returns true in the one
-// block that finishes last. Writes before the call are visible to that block.
-__device__ inline bool last_to_finish(uint32_t* counter, uint32_t total, int* flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) *flag = atomicAdd(counter, 1u) == total - 1;
-  __syncthreads();
-  const bool last = *flag != 0;
-  if (last) __threadfence();
-  return last;
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long u = __shfl_xor(v, o);
+    v = u > v ? u : v;
+  }
+  return v;
 }
 
-// Least-squares level homography over the inliers of the best-consensus
-// hypothesis (one block), plus the per-tile flags 4 (in M) and 8 (in the fit).
-__device__ void fit_level(const int4* __restrict__ matches, const int32_t* __restrict__ tile_of,
-                          int N, const WeedArgs& a, const unsigned long long* mbits,
-                          unsigned long long bkey, const double* __restrict__ Gall,
-                          uint8_t* __restrict__ flags, int w, int h,
-                          const double* __restrict__ Hprev, double* __restrict__ Hout,
-                          int32_t* __restrict__ counts) {
-  __shared__ long long part[kWeedThreads / 64][45];
-  __shared__ long long tot[45];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bc = N >= 4 && bkey ? (int)(bkey >> 32) : -1;
-  const int bi = N >= 4 && bkey ? (int)(~(uint32_t)(bkey & 0xffffffffull)) : -1;
-  const bool fit = bc > weed_delta(N, a);
-  double g[8];
-  for (int i = 0; i < 8; ++i) g[i] = fit ? Gall[(size_t)bi * 8 + i] : 0.0;
-  long long ata[36], atb[8];
-  for (int i = 0; i < 36; ++i) ata[i] = 0;
-  for (int i = 0; i < 8; ++i) atb[i] = 0;
-  long long m = 0;
-  for (int k = tid; k < N; k += kWeedThreads) {
-    const int4 mt = matches[k];
-    const bool inM = (mbits[k >> 6] >> (k & 63)) & 1ull;
-    const bool sel = fit && is_inlier(g, mt, a.eps2);
-    const int t = tile_of[k];
-    flags[t] = (uint8_t)((flags[t] & 3) | (inM ? 4 : 0) | (sel ? 8 : 0));
-    if (!sel) continue;
-    ++m;
-    const long long x = mt.z, y = mt.w, u = mt.x, v = mt.y;  // G: (x, y) -> (u, v)
-    const long long r1[8] = {x, y, 1, 0, 0, 0, -x * u, -y * u};
-    const long long r2[8] = {0, 0, 0, x, y, 1, -x * v, -y * v};
-    for (int i = 0; i < 8; ++i) {
-      for (int j = i; j < 8; ++j) ata[tri(i, j)] += r1[i] * r1[j] + r2[i] * r2[j];
-      atb[i] += r1[i] * u + r2[i] * v;
+// distinct sums of the normal equations (see k_fit)
+constexpr int kSums = 23;
+
+// polynomial degree of unknown i (h11 h12 h13 h21 h22 h23 h31 h32) in the
+// coordinates, for the power-of-two scaling
+__device__ inline int deg_of(int i) { return (i == 2 || i == 5) ? 0 : (i >= 6 ? 2 : 1); }
+
+// Entry (i, j) of A^T A from the 23 sums T (order: 1, x, y, xx, xy, yy, u, v,
+// xu, yu, xv, yv, xxu, xyu, yyu, xxv, xyv, yyv, xq, yq, xxq, xyq, yyq with
+// q = u^2 + v^2).
+__device__ inline long long normal_entry(const long long* T, int i, int j) {
+  if (i > j) { const int t = i; i = j; j = t; }
+  switch (i * 8 + j) {
+    case 0: return T[3];   case 1: return T[4];   case 2: return T[1];
+    case 6: return -T[12]; case 7: return -T[13];
+    case 9: return T[5];   case 10: return T[2];  case 14: return -T[13]; case 15: return -T[14];
+    case 18: return T[0];  case 22: return -T[8]; case 23: return -T[9];
+    case 27: return T[3];  case 28: return T[4];  case 29: return T[1];
+    case 30: return -T[15]; case 31: return -T[16];
+    case 36: return T[5];  case 37: return T[2];  case 38: return -T[16]; case 39: return -T[17];
+    case 45: return T[0];  case 46: return -T[10]; case 47: return -T[11];
+    case 54: return T[20]; case 55: return T[21];
+    case 63: return T[22];
+    default: return 0;
+  }
+}
+
+// Entry i of A^T b
+__device__ inline long long normal_rhs(const long long* T, int i) {
+  switch (i) {
+    case 0: return T[8];  case 1: return T[9];  case 2: return T[6];  case 3: return T[10];
+    case 4: return T[11]; case 5: return T[7];  case 6: return -T[18];
+    default: return -T[19];
+  }
+}
+
+// The 8x8 solve of solve8 with one row per lane (lanes 0-7 of a wave; the
+// other lanes mirror row 7 and are ignored): identical arithmetic per entry,
+// the pivot search as a first-largest reduction. Every lane returns the same.
+__device__ inline bool solve8_wave(double (&row)[9], double (&x)[8]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    // first largest |a[r][c]| over r >= c; a NaN below the pivot row is never
+    // larger, a NaN in the pivot row fails
+    const double ac = fabs(row[c]);
+    double v = (lane >= c && lane < 8) ? ac : -1.0;
+    if (lane != c && !(v >= 0.0)) v = -1.0;
+    int idx = lane < 8 ? lane : 8;
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      const double v2 = __shfl_xor(v, o);
+      const int i2 = __shfl_xor(idx, o);
+      if (v2 > v || (v2 == v && i2 < idx)) { v = v2; idx = i2; }
+    }
+    const double best = __shfl(v, 0);
+    const int piv = __shfl(idx, 0);
+    const double diag = __shfl(ac, c);
+    if (!(diag == diag) || !(best >= 1e-12)) return false;
+    const int src = lane == c ? piv : (lane == piv ? c : lane);
+#pragma unroll
+    for (int j = c; j < 9; ++j) row[j] = __shfl(row[j], src);
+    double pr[9];
+#pragma unroll
+    for (int j = c; j < 9; ++j) pr[j] = __shfl(row[j], c);
+    if (lane > c && lane < 8) {
+      const double f = row[c] / pr[c];
+#pragma unroll
+      for (int j = c; j < 9; ++j) row[j] = row[j] - f * pr[j];
     }
   }
-  // exact (order-free) int64 reduction: wave shuffles, then across waves
-  for (int i = 0; i < 36; ++i) ata[i] = wave_sum_i64(ata[i]);
-  for (int i = 0; i < 8; ++i) atb[i] = wave_sum_i64(atb[i]);
-  m = wave_sum_i64(m);
-  if (lane == 0) {
-    for (int i = 0; i < 36; ++i) part[wave][i] = ata[i];
-    for (int i = 0; i < 8; ++i) part[wave][36 + i] = atb[i];
-    part[wave][44] = m;
+#pragma unroll
+  for (int c = 7; c >= 0; --c) {
+    double s = row[8];
+#pragma unroll
+    for (int j = c + 1; j < 8; ++j) s = s - row[j] * x[j];
+    x[c] = __shfl(s / row[c], c);
+  }
+  return true;
+}
+
+// One block: union M, best consensus, least-squares level homography, and
+// the per-tile flags 4 (in M) and 8 (in the fit).
+__global__ __launch_bounds__(kFitThreads) void k_fit(
+    const int32_t* __restrict__ cxy, const int32_t* __restrict__ disp,
+    uint8_t* __restrict__ flags, int ntiles, int w, int h, WeedArgs a,
+    const int32_t* __restrict__ nmatch, const double* __restrict__ G,
+    const int32_t* __restrict__ cnt, const unsigned long long* __restrict__ bal, int wstride,
+    const double* __restrict__ Hprev, double* __restrict__ Hout, int32_t* __restrict__ counts) {
+  extern __shared__ unsigned long long mw[];  // [wstride] union bitmask M
+  __shared__ unsigned int accw[kMaxIters / 32];  // accepted iterations
+  __shared__ unsigned long long kmax[kFitThreads / 64];
+  __shared__ long long part[kFitThreads / 64][kSums];
+  __shared__ long long tot[kSums];
+  constexpr int NWV = kFitThreads / 64, TPT = 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // The phases below depend on each other (counts -> union and best row ->
+  // fit), so each issues all of its loads before using any; the first batch
+  // of tile data is loaded up front.
+  uint8_t tf[TPT];
+  int tpx[TPT], tpy[TPT], tdx[TPT], tdy[TPT];
+#pragma unroll
+  for (int j = 0; j < TPT; ++j) {
+    const int t = tid + j * kFitThreads;
+    const bool in = t < ntiles;
+    tf[j] = in ? flags[t] : 0;
+    tpx[j] = in ? cxy[2 * t] : 0;
+    tpy[j] = in ? cxy[2 * t + 1] : 0;
+    tdx[j] = in ? disp[2 * t] : 0;
+    tdy[j] = in ? disp[2 * t + 1] : 0;
+  }
+  const int N = *nmatch;
+  const int delta = weed_delta(N, a);
+  // per-iteration counts, acceptance bits, best key
+  unsigned long long kb = 0ull;
+  for (int i0 = 0; i0 < a.iters; i0 += 2 * kFitThreads) {
+    int c[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int i = i0 + r * kFitThreads + tid;
+      c[r] = i < a.iters && N >= 4 ? cnt[i] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int i = i0 + r * kFitThreads + tid;
+      const int ib = i0 + r * kFitThreads + wave * 64;
+      const unsigned long long acc = __ballot(c[r] > delta);
+      if (lane == 0 && ib < a.iters) {
+        accw[ib >> 5] = (unsigned int)acc;
+        accw[(ib >> 5) + 1] = (unsigned int)(acc >> 32);
+      }
+      if (c[r] >= 0) {
+        const unsigned long long key =
+            ((unsigned long long)(uint32_t)c[r] << 32) | (unsigned long long)(~(uint32_t)i);
+        kb = key > kb ? key : kb;
+      }
+    }
+  }
+  kb = wave_max_u64(kb);
+  if (lane == 0) kmax[wave] = kb;
+  __syncthreads();
+  unsigned long long bkey = 0ull;
+  for (int q = 0; q < NWV; ++q) bkey = kmax[q] > bkey ? kmax[q] : bkey;
+  const int bc = N >= 4 && bkey ? (int)(bkey >> 32) : -1;
+  const int bi = N >= 4 && bkey ? (int)(~(uint32_t)(bkey & 0xffffffffull)) : -1;
+  const bool fit = bc > delta;
+  // the best hypothesis' inlier bits for the first tile batch
+  unsigned long long brow[TPT];
+#pragma unroll
+  for (int j = 0; j < TPT; ++j) {
+    const int t = tid + j * kFitThreads;
+    brow[j] = fit && t < ntiles ? bal[(size_t)(t >> 6) * a.iters + bi] : 0ull;
+  }
+  // M: OR of the accepted rows; a wave per word (two at a time), its lanes
+  // over the iterations
+  for (int w0 = wave; w0 < wstride; w0 += 2 * NWV) {
+    const int w1 = w0 + NWV;
+    unsigned long long v0 = 0ull, v1 = 0ull;
+    for (int i0 = 0; i0 < a.iters; i0 += 64 * 16) {
+      unsigned long long r0[16], r1[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u * 64 + lane;
+        r0[u] = i < a.iters ? bal[(size_t)w0 * a.iters + i] : 0ull;
+        r1[u] = i < a.iters && w1 < wstride ? bal[(size_t)w1 * a.iters + i] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u * 64 + lane;
+        if (i < a.iters && ((accw[i >> 5] >> (i & 31)) & 1u)) {
+          v0 |= r0[u];
+          v1 |= r1[u];
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      v0 |= __shfl_xor(v0, o);
+      v1 |= __shfl_xor(v1, o);
+    }
+    if (lane == 0) {
+      mw[w0] = v0;
+      if (w1 < wstride) mw[w1] = v1;
+    }
   }
   __syncthreads();
-  if (tid < 45) {
-    long long s = 0;
-    for (int q = 0; q < kWeedThreads / 64; ++q) s += part[q][tid];
-    tot[tid] = s;
-  }
-  __syncthreads();
-  if (tid != 0) return;
-  const int msel = (int)tot[44];
-  counts[0] = N;
-  counts[1] = msel;
-  counts[2] = bc;
-  counts[3] = bi;
-  for (int i = 0; i < 9; ++i) Hout[i] = Hprev[i];
-  if (msel < 4) return;
+  // normal equations of G: (x, y) -> (u, v), reference side to source side,
+  // over the best hypothesis' inliers; the 8x8 matrix has 23 distinct sums
+  long long s[kSums];
+#pragma unroll
+  for (int i = 0; i < kSums; ++i) s[i] = 0;
   const int ox = w / 2, oy = h / 2;
+  for (int t0 = 0; t0 < ntiles; t0 += TPT * kFitThreads) {
+    if (t0 > 0) {  // later batches (levels with more than 8192 tiles)
+#pragma unroll
+      for (int j = 0; j < TPT; ++j) {
+        const int t = t0 + tid + j * kFitThreads;
+        const bool in = t < ntiles;
+        tf[j] = in ? flags[t] : 0;
+        tpx[j] = in ? cxy[2 * t] : 0;
+        tpy[j] = in ? cxy[2 * t + 1] : 0;
+        tdx[j] = in ? disp[2 * t] : 0;
+        tdy[j] = in ? disp[2 * t + 1] : 0;
+        brow[j] = fit && in ? bal[(size_t)(t >> 6) * a.iters + bi] : 0ull;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < TPT; ++j) {
+      const int t = t0 + tid + j * kFitThreads;
+      if (t >= ntiles || !(tf[j] & 2)) continue;
+      const bool inM = (mw[t >> 6] >> (t & 63)) & 1ull;
+      const bool sel = (brow[j] >> (t & 63)) & 1ull;
+      flags[t] = (uint8_t)((tf[j] & 3) | (inM ? 4 : 0) | (sel ? 8 : 0));
+      if (!sel) continue;
+      const long long x = tpx[j] - ox, y = tpy[j] - oy, u = x + tdx[j], v = y + tdy[j];
+      const long long xx = x * x, xy = x * y, yy = y * y, q = u * u + v * v;
+      s[0] += 1;       s[1] += x;       s[2] += y;
+      s[3] += xx;      s[4] += xy;      s[5] += yy;
+      s[6] += u;       s[7] += v;
+      s[8] += x * u;   s[9] += y * u;   s[10] += x * v;  s[11] += y * v;
+      s[12] += xx * u; s[13] += xy * u; s[14] += yy * u;
+      s[15] += xx * v; s[16] += xy * v; s[17] += yy * v;
+      s[18] += x * q;  s[19] += y * q;
+      s[20] += xx * q; s[21] += xy * q; s[22] += yy * q;
+    }
+  }
+  // exact (order-free) int64 reduction
+#pragma unroll
+  for (int i = 0; i < kSums; ++i) s[i] = wave_sum_i64(s[i]);
+  if (lane == 0)
+    for (int i = 0; i < kSums; ++i) part[wave][i] = s[i];
+  __syncthreads();
+  if (tid < kSums) {
+    long long z = 0;
+    for (int q = 0; q < kFitThreads / 64; ++q) z += part[q][tid];
+    tot[tid] = z;
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  const int msel = (int)tot[0];
+  if (lane == 0) {
+    counts[0] = N;
+    counts[1] = msel;
+    counts[2] = bc;
+    counts[3] = bi;
+    for (int i = 0; i < 9; ++i) Hout[i] = Hprev[i];
+  }
+  if (msel < 4) return;
+  // A^T A and A^T b of the rows (x, y, 1, 0, 0, 0, -xu, -yu | u) and
+  // (0, 0, 0, x, y, 1, -xv, -yv | v), scaled by powers of two; lane r < 8
+  // holds row r
   int k = 0;
   const int mx = ox > oy ? (ox > 1 ? ox : 1) : (oy > 1 ? oy : 1);
   while ((1 << k) < mx) ++k;
   const int deg[8] = {1, 1, 0, 1, 1, 0, 2, 2};
-  double A[8 * 9], hs[8];
-  for (int i = 0; i < 8; ++i) {
-    for (int j = 0; j < 8; ++j) {
-      const long long v = i <= j ? tot[tri(i, j)] : tot[tri(j, i)];
-      A[i * 9 + j] = ldexp((double)v, -k * (deg[i] + deg[j]));
-    }
-    A[i * 9 + 8] = ldexp((double)tot[36 + i], -k * (deg[i] + 1));
+  const int r = lane < 8 ? lane : 7;
+  double row[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const long long v = j < 8 ? normal_entry(tot, r, j) : normal_rhs(tot, r);
+    const int e = j < 8 ? -k * (deg_of(r) + deg[j]) : -k * (deg_of(r) + 1);
+    row[j] = ldexp((double)v, e);
   }
-  if (!solve8(A, hs)) return;
+  double hs[8];
+  if (!solve8_wave(row, hs)) return;
+  if (lane != 0) return;
   double Gc[9];
   for (int i = 0; i < 8; ++i) Gc[i] = ldexp(hs[i], k * (1 - deg[i]));
   Gc[8] = 1.0;
@@ -267,97 +577,6 @@ __device__ void fit_level(const int4* __restrict__ matches, const int32_t* __res
   for (int i = 0; i < 9; ++i) Hout[i] = Hn[i];
 }
 
-// Block (256 matches, 8 iterations). Every block draws and fits its 8
-// hypotheses (8 threads), tests its matches against them (wave ballots form
-// the inlier bitmask rows) and adds the counts. The last block of an
-// iteration group ORs the accepted rows (count > delta) into M and updates
-// the best consensus (count << 32 | ~iteration); the last block overall fits
-// the level homography. No block waits for another.
-__global__ __launch_bounds__(kWeedThreads) void k_weedfit(
-    const int4* __restrict__ matches, const int32_t* __restrict__ tile_of,
-    const int32_t* __restrict__ nmatch, WeedArgs a, double* __restrict__ G,
-    int32_t* __restrict__ cnt, unsigned long long* __restrict__ bal, int wstride,
-    unsigned long long* __restrict__ mbits, unsigned long long* __restrict__ best,
-    uint32_t* __restrict__ done, uint8_t* __restrict__ flags, int w, int h,
-    const double* __restrict__ Hprev, double* __restrict__ Hout, int32_t* __restrict__ counts) {
-  __shared__ double gs[kItPerBlock][8];
-  __shared__ int ok[kItPerBlock];
-  __shared__ int wc[kItPerBlock][kWeedThreads / 64];
-  __shared__ int lastflag;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int it0 = blockIdx.y * kItPerBlock;
-  const int N = *nmatch;
-  const int k = blockIdx.x * kWeedThreads + tid;
-  const bool work = N >= 4 && blockIdx.x * kWeedThreads < N;
-  if (work && tid < kItPerBlock) {
-    const int it = it0 + tid;
-    double g[8];
-    const bool good = it < a.iters && hypothesis(matches, N, it, a, g);
-    ok[tid] = good;
-    for (int i = 0; i < 8; ++i) gs[tid][i] = good ? g[i] : 0.0;
-    if (blockIdx.x == 0 && it < a.iters) {  // block 0 of the group publishes G
-      if (good)
-        for (int i = 0; i < 8; ++i) G[(size_t)it * 8 + i] = g[i];
-      else
-        cnt[it] = -1;  // degenerate: no block adds to it
-    }
-  }
-  __syncthreads();
-  if (work) {
-    const int4 m = k < N ? matches[k] : make_int4(0, 0, 0, 0);
-    const int word = k >> 6;
-    for (int q = 0; q < kItPerBlock; ++q) {
-      if (!ok[q]) continue;
-      const bool in = k < N && is_inlier(gs[q], m, a.eps2);
-      const unsigned long long b = __ballot(in);
-      if (lane == 0) {
-        if (word * 64 < N) bal[(size_t)(it0 + q) * wstride + word] = b;
-        wc[q][wave] = __popcll(b);
-      }
-    }
-    __syncthreads();
-    if (tid < kItPerBlock && ok[tid]) {
-      int s = 0;
-      for (int q = 0; q < kWeedThreads / 64; ++q) s += wc[tid][q];
-      if (s) atomicAdd(&cnt[it0 + tid], s);
-    }
-  }
-  // the last block of this iteration group: union of accepted rows into M
-  if (last_to_finish(&done[1 + blockIdx.y], gridDim.x, &lastflag) && N >= 4) {
-    const int delta = weed_delta(N, a);
-    const int nwords = (N + 63) / 64;
-    __shared__ int acc[kItPerBlock];
-    __shared__ int cval[kItPerBlock];
-    if (tid < kItPerBlock) {
-      const int it = it0 + tid;
-      cval[tid] = it < a.iters ? __atomic_load_n(&cnt[it], __ATOMIC_RELAXED) : -1;
-      acc[tid] = cval[tid] > delta;  // -1 marks a degenerate iteration
-    }
-    __syncthreads();
-    for (int wi = tid; wi < nwords; wi += kWeedThreads) {
-      unsigned long long v = 0ull;
-      for (int q = 0; q < kItPerBlock; ++q)
-        if (acc[q]) v |= bal[(size_t)(it0 + q) * wstride + wi];
-      if (v) atomicOr(&mbits[wi], v);
-    }
-    if (tid == 0) {
-      unsigned long long bk = 0ull;
-      for (int q = 0; q < kItPerBlock; ++q)
-        if (cval[q] >= 0) {
-          const unsigned long long key = ((unsigned long long)(uint32_t)cval[q] << 32) |
-                                         (unsigned long long)(~(uint32_t)(it0 + q));
-          bk = key > bk ? key : bk;
-        }
-      if (bk) atomicMax(best, bk);
-    }
-  }
-  // the last block overall: level homography
-  if (last_to_finish(&done[0], gridDim.x * gridDim.y, &lastflag)) {
-    const unsigned long long bkey = __atomic_load_n(best, __ATOMIC_RELAXED);
-    fit_level(matches, tile_of, N, a, mbits, bkey, G, flags, w, h, Hprev, Hout, counts);
-  }
-}
-
 }  // namespace
 
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
@@ -372,15 +591,20 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
   a.eps2 = p.weed_eps * p.weed_eps;
   a.seed = p.seed;
   const int words = ntiles > 0 ? (ntiles + 63) / 64 : 1;
-  const int chunks = ntiles > 0 ? (ntiles + kWeedThreads - 1) / kWeedThreads : 1;
+  const int chunks = ntiles > 0 ? (ntiles + kTestThreads - 1) / kTestThreads : 1;
   const int groups = (a.iters + kItPerBlock - 1) / kItPerBlock;
-  LNR_LAUNCH(k_compact, dim3(1), dim3(1024), 0, st, corner_xy, disp, flags, ntiles, w, h,
-             b.matches, b.tile_of, b.nmatch, b.mbits, b.best, b.cnt, a.iters, b.done, 1 + groups);
+  if (words > kMaxWords || a.iters > kMaxIters) return hipErrorInvalidValue;
+  LNR_LAUNCH(k_hyp, dim3((a.iters + kHypThreads - 1) / kHypThreads), dim3(kHypThreads), 0, st,
+             flags, corner_xy, disp, ntiles, w, h, a, b.G, b.cnt, b.nmatch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  LNR_LAUNCH(k_weedfit, dim3(chunks, groups), dim3(kWeedThreads), 0, st, b.matches, b.tile_of,
-             b.nmatch, a, b.G, b.cnt, b.bal, words, b.mbits, b.best, b.done, flags, w, h, H_prev,
-             H_out, counts);
+  if (ntiles > 0) {
+    LNR_LAUNCH(k_test, dim3(chunks, groups), dim3(kTestThreads), 0, st, corner_xy, disp, flags,
+               ntiles, w, h, a, b.G, b.cnt, b.bal, words);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  LNR_LAUNCH(k_fit, dim3(1), dim3(kFitThreads), (size_t)words * 8, st, corner_xy, disp, flags,
+             ntiles, w, h, a, b.nmatch, b.G, b.cnt, b.bal, words, H_prev, H_out, counts);
   return hipGetLastError();
 }
 

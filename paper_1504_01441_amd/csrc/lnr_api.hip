@@ -218,35 +218,25 @@ lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes) {
 }
 
 struct WeedPlan {
-  size_t matches, tile_of, nmatch, mbits, best, G, cnt, bal, done;
+  size_t nmatch, G, cnt, bal;
 };
 
 WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
   WeedPlan w;
   const int nt = ntiles > 0 ? ntiles : 1;
-  w.matches = pl.take(sizeof(int4) * (size_t)nt);
-  w.tile_of = pl.take(sizeof(int32_t) * (size_t)nt);
   w.nmatch = pl.take(sizeof(int32_t));
-  w.mbits = pl.take(sizeof(unsigned long long) * (size_t)((nt + 63) / 64));
-  w.best = pl.take(sizeof(unsigned long long));
   w.G = pl.take(sizeof(double) * 8 * (size_t)iters);
   w.cnt = pl.take(sizeof(int32_t) * (size_t)iters);
   w.bal = pl.take(sizeof(unsigned long long) * (size_t)iters * ((nt + 63) / 64));
-  w.done = pl.take(sizeof(uint32_t) * (size_t)(1 + (iters + 7) / 8));
   return w;
 }
 
 WeedBufs weed_bufs(char* base, const WeedPlan& w) {
   WeedBufs b;
-  b.matches = reinterpret_cast<int4*>(base + w.matches);
-  b.tile_of = reinterpret_cast<int32_t*>(base + w.tile_of);
   b.nmatch = reinterpret_cast<int32_t*>(base + w.nmatch);
-  b.mbits = reinterpret_cast<unsigned long long*>(base + w.mbits);
-  b.best = reinterpret_cast<unsigned long long*>(base + w.best);
   b.G = reinterpret_cast<double*>(base + w.G);
   b.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
   b.bal = reinterpret_cast<unsigned long long*>(base + w.bal);
-  b.done = reinterpret_cast<uint32_t*>(base + w.done);
   return b;
 }
 
@@ -273,7 +263,7 @@ lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
   const size_t o_warp = pl.take(N);
   const WeedPlan wp = plan_weed(pl, g.lv[0].ntx * g.lv[0].nty, p->weed_iters);
   const size_t o_maps = pl.take(3 * N * sizeof(float));
-  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(float));
+  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
   char* base = static_cast<char*>(ctx->ws);
   uint32_t* hist = reinterpret_cast<uint32_t*>(base + o_hist);
@@ -282,7 +272,7 @@ lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
   uint8_t* warped = reinterpret_cast<uint8_t*>(base + o_warp);
   const WeedBufs wb = weed_bufs(base, wp);
   float* maps = reinterpret_cast<float*>(base + o_maps);
-  float* coef = reinterpret_cast<float*>(base + o_coef);
+  double* coef = reinterpret_cast<double*>(base + o_coef);
 
   LNR_HIP(hipMemsetAsync(hist, 0, 2 * 256 * sizeof(uint32_t), st));
   LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
@@ -601,11 +591,11 @@ lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t*
   const size_t N = (size_t)w * h;
   Plan pl;
   const size_t o_maps = pl.take(3 * N * sizeof(float));
-  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(float));
+  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
   char* base = static_cast<char*>(ctx->ws);
   LNR_HIP(launch_flow(corner_xy, disp, flags, w / p->tile, h / p->tile, p->tile, guide, w, h, *p,
-                      reinterpret_cast<float*>(base + o_maps), reinterpret_cast<float*>(base + o_coef),
+                      reinterpret_cast<float*>(base + o_maps), reinterpret_cast<double*>(base + o_coef),
                       flow, ntilde, (hipStream_t)stream));
   return LNR_OK;
 }

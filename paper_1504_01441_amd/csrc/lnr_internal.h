@@ -65,15 +65,10 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
 
 // ---- weeding + level homography (k_weed.hip)
 struct WeedBufs {
-  int4* matches;         // [ntiles] (sx, sy, tx, ty) centred level coordinates
-  int32_t* tile_of;      // [ntiles] match index -> tile
-  int32_t* nmatch;       // [1]
-  unsigned long long* mbits;  // [ceil(ntiles/64)] union bitmask M
-  unsigned long long* best;   // [1] (count << 32) | (~iter)
-  double* G;             // [iters][8] hypothesis homographies
-  int32_t* cnt;          // [iters] inlier counts (-1: skipped)
-  unsigned long long* bal;  // [iters][ceil(ntiles/64)] inlier bitmask rows
-  uint32_t* done;           // [1 + iteration groups] completion counters
+  int32_t* nmatch;          // [1] valid matches of the level
+  double* G;                // [iters][8] hypothesis homographies
+  int32_t* cnt;             // [iters] inlier counts (-1: hypothesis unusable)
+  unsigned long long* bal;  // [ceil(ntiles/64)][iters] inlier bitmask rows
 };
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
@@ -83,7 +78,7 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
 // ---- domain-transform propagation (k_dt.hip)
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
                        int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
-                       const lnr_params& p, float* maps /*[3][H][W]*/, float* coef /*[iters][256]*/,
+                       const lnr_params& p, float* maps /*[3][H][W]*/, double* coef /*[iters][256]*/,
                        float* flow, float* ntilde, hipStream_t st);
 
 // ---- backward warp (k_warp.hip)
