@@ -5,7 +5,9 @@ import this package. The product library (paper_1504_01441_amd) never does,
 and this package imports nothing from it: the C sources here share no code
 with the GPU path.
 
-`build()` compiles lnr_oracle.c with gcc into liblnr_oracle.so next to it.
+`build()` compiles lnr_oracle.c (the paper's method) and proposal_oracle.c
+(the learned displacement proposal, an extension) with gcc into
+liblnr_oracle.so next to them.
 """
 from __future__ import annotations
 
@@ -17,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lnr_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "proposal_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liblnr_oracle.so")
 _lib = None
 
@@ -27,7 +30,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
                                "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -62,10 +65,15 @@ class _Registration(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+                os.path.getmtime(f) for f in _SRCS + [os.path.join(_HERE, "lnr_oracle.h")]):
             build(force=True)
         _lib = C.CDLL(_LIB_PATH)
         _lib.lo_default_params.argtypes = [C.POINTER(Params)]
+        _lib.lo_bf16.argtypes = [C.c_double]
+        _lib.lo_bf16.restype = C.c_double
+        _lib.lo_cnn_loss_grad.restype = C.c_double
+        _lib.lo_adamw.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_int] + [C.c_double] * 5
         _lib.lo_num_levels.argtypes = [C.c_int, C.c_int, C.POINTER(Params)]
         _lib.lo_num_levels.restype = C.c_int
         _lib.lo_weed.restype = C.c_int
@@ -369,3 +377,72 @@ def register_pair(ref, src, p=None, H_init=None):
     o["H"] = o["H"].reshape(L + 1, 3, 3)
     o["level_sizes"] = list(zip(lw, lh))
     return o
+
+
+# --------------------------------------------------------------------------- learned proposal
+# (an extension beyond the paper: a CNN proposes each level-0 tile's
+# displacement so that the Sec. 2.2 search scans a small window)
+
+CNN_PARAMS = 29891
+
+
+def bf16(v):
+    """bfloat16 round-to-nearest-even of each value (as a float32 -> bf16 cast)."""
+    a = np.asarray(v, dtype=np.float64)
+    return np.vectorize(lambda t: lib().lo_bf16(float(t)), otypes=[np.float64])(a)
+
+
+def cnn_tile_inputs(ref, warped, tiles, tile=32):
+    """[n, 2, 16, 16] network inputs of the given level-0 tile indices."""
+    ref = _c(ref, np.uint8)
+    warped = _c(warped, np.uint8)
+    h, w = ref.shape
+    ntx = w // tile
+    out = np.zeros((len(tiles), 2, 16, 16), np.float64)
+    for k, t in enumerate(tiles):
+        tx, ty = int(t) % ntx, int(t) // ntx
+        lib().lo_cnn_tile_input(_p(ref), _p(warped), w, tx * tile, ty * tile,
+                                _p(out[k]))
+    return out
+
+
+def cnn_forward(params, x, rnd=True):
+    """[n, 3] network outputs (o0, o1, o2): prediction (8 o0, 8 o1), logit o2."""
+    params = _c(params, np.float64)
+    x = _c(x, np.float64).reshape(-1, 512)
+    out = np.zeros((x.shape[0], 3), np.float64)
+    lib().lo_cnn_forward(_p(params), _p(x), x.shape[0], int(rnd), _p(out))
+    return out
+
+
+def cnn_loss_grad(params, x, labels, rnd=True):
+    """(mean loss, gradient over the flat parameter vector)."""
+    params = _c(params, np.float64)
+    x = _c(x, np.float64).reshape(-1, 512)
+    lab = _c(labels, np.int32).reshape(-1, 2)
+    g = np.zeros(CNN_PARAMS, np.float64)
+    loss = lib().lo_cnn_loss_grad(_p(params), _p(x), _p(lab), x.shape[0], int(rnd), _p(g))
+    return loss, g
+
+
+def adamw(w, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+    """One AdamW step in place on float64 arrays w, m, v."""
+    lib().lo_adamw(_p(w), _p(m), _p(v), _p(_c(g, np.float64)), len(w), int(t), float(lr),
+                   float(b1), float(b2), float(eps), float(wd))
+
+
+def search_window(ref, wimg, R, centre_x, centre_y, cx, cy, has, p=None):
+    """Sec. 2.2 search restricted to centre + [-R, R]^2 per tile."""
+    p = p or params()
+    ref = _c(ref, np.uint8)
+    wimg = _c(wimg, np.uint8)
+    h, w = ref.shape
+    nt = len(cx)
+    dx = np.zeros(nt, np.int32)
+    dy = np.zeros(nt, np.int32)
+    ssd = np.zeros(nt, np.uint32)
+    valid = np.zeros(nt, np.uint8)
+    args = [_c(a, np.int32) for a in (centre_x, centre_y, cx, cy)]
+    lib().lo_search_window(_p(ref), _p(wimg), w, h, C.byref(p), R, *[_p(a) for a in args],
+                           _p(_c(has, np.uint8)), _p(dx), _p(dy), _p(ssd), _p(valid))
+    return dx, dy, ssd, valid

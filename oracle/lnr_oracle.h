@@ -142,6 +142,22 @@ int  lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t*
 int  lo_merge(int n, int ch, int w, int h, const double* const* imgs,
               const double* const* yeqs, int ref_index, const lo_params* p, double* out);
 
+/* ---- learned displacement proposal (proposal_oracle.c; an extension, not
+ * part of the paper: it narrows the search of Sec. 2.2) ---------------------- */
+double lo_bf16(double v);
+int    lo_cnn_param_count(void);
+void   lo_cnn_tile_input(const uint8_t* ref, const uint8_t* warped, int w, int x0, int y0,
+                         double* x);
+void   lo_cnn_forward(const double* params, const double* x, int n, int rnd, double* out);
+double lo_cnn_loss_grad(const double* params, const double* x, const int32_t* label, int n,
+                        int rnd, double* grad);
+void   lo_adamw(double* w, double* m, double* v, const double* g, int n, int t, double lr,
+                double b1, double b2, double eps, double wd);
+void   lo_search_window(const uint8_t* ref, const uint8_t* wimg, int w, int h,
+                        const lo_params* p, int R, const int32_t* ccx, const int32_t* ccy,
+                        const int32_t* cx, const int32_t* cy, const uint8_t* has, int32_t* dx,
+                        int32_t* dy, uint32_t* ssd, uint8_t* valid);
+
 #ifdef __cplusplus
 }
 #endif
