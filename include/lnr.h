@@ -81,6 +81,14 @@ typedef struct {
   double ssim_c1, ssim_c2; /* SSIM stabilisers                                   */
   double sigma_e;          /* Mertens well-exposedness sigma                     */
   uint64_t seed;           /* weeding sampler seed                               */
+  /* learned displacement proposal (an extension beyond the paper): with
+   * learned = 1 the level-0 search of Sec. 2.2 scans only centre + [-window_r,
+   * window_r]^2 per tile, the centre being the context's network prediction,
+   * and falls back to the exhaustive radius0 search where the network's
+   * confidence is below conf_min. Needs lnr_proposal_set() first and tile 32. */
+  int32_t learned;         /* 0: plain method (default), 1: learned proposal    */
+  int32_t window_r;        /* window radius, 0..radius0 (default 2)             */
+  double conf_min;         /* confidence threshold in (0, 1) (default 0.5)      */
 } lnr_params;
 
 typedef struct {
@@ -94,7 +102,8 @@ typedef struct {
 
 /* Outputs of one registration (device pointers, caller-owned). Pointers
  * marked optional may be null. Per-tile flags: 1 corner found, 2 valid
- * match, 4 kept by the weeding filter (Eq. 5), 8 used for the level fit. */
+ * match, 4 kept by the weeding filter (Eq. 5), 8 used for the level fit,
+ * 16 exhaustive fallback taken (learned proposal only). */
 typedef struct {
   int32_t* corner_xy;      /* [tiles_total][2] corner pixel, -1 if none        */
   int32_t* disp;           /* [tiles_total][2] integer displacement d          */
@@ -189,6 +198,70 @@ lnr_status lnr_stage_backward_warp(lnr_ctx* ctx, const lnr_frame* src, const uin
 lnr_status lnr_stage_merge(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32_t h,
                            const float* const* imgs, const float* const* yeqs,
                            int32_t ref_index, const lnr_params* p, float* out, void* stream);
+
+/* ---- batches: several pairs of any sizes in one call (streams, graphs,
+ * autotuning; no new method). -------------------------------------------- */
+#define LNR_BATCH_GRAPH 1     /* capture the batch as one HIP graph, cached per
+                                 (inputs, outputs, parameters), and launch it */
+#define LNR_BATCH_AUTOTUNE 2  /* on the first call of a batch shape, time 1, 2,
+                                 4 and 8 concurrent streams and keep the fastest */
+/* Register n pairs (refs[i], srcs[i]) -> outs[i], each exactly as
+ * lnr_register_pair would. The pairs are spread over concurrent streams
+ * (longest first, each to the least-loaded stream), each with its own
+ * workspace slot; the call's stream waits for all of them. Graph mode needs
+ * the same pointers again to reuse a capture. */
+lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_frame* srcs,
+                              int32_t n, const lnr_params* p, lnr_registration* outs,
+                              int32_t flags, void* stream);
+/* Time every domain-transform kernel shape that covers w x h (Sec. 2.4 pass;
+ * results do not depend on the shape) and use the fastest for that size from
+ * then on. shape_out[5] (optional): rows per thread, row block, rows per
+ * column segment, columns per block, segments per column. Synchronises. */
+lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
+                             int32_t* shape_out, void* stream);
+
+/* ---- learned displacement proposal (an extension beyond the paper; it
+ * narrows the Sec. 2.2 search). The network: per level-0 tile of 32 x 32 the
+ * input x[2][16][16] (reference and warped source, 2 x 2 sums s mapped to
+ * bf16((s - 510) / 512)), four 3x3 convolutions to 32 channels (strides 1, 2,
+ * 1, 2, padding 1, ReLU, activations rounded to bf16), a linear head 512 -> 3.
+ * Outputs o: predicted displacement (8 o[0], 8 o[1]) and confidence logit
+ * o[2]. Parameters: one fp32 vector of LNR_PROPOSAL_PARAMS values, in order
+ * W1[32][2][3][3] b1[32] W2[32][32][3][3] b2 W3 b3 W4 b4 Wh[3][512] bh[3]
+ * (head feature f = (y * 4 + x) * 32 + c). The context owns one network and
+ * its AdamW state; the calls below run on the GPU (bf16 matrix cores, fp32
+ * accumulation). ------------------------------------------------------------ */
+#define LNR_PROPOSAL_PARAMS 29891
+
+/* Load the network parameters params[LNR_PROPOSAL_PARAMS] (device, fp32)
+ * into the context and reset the AdamW moments and step count. */
+lnr_status lnr_proposal_set(lnr_ctx* ctx, const float* params, void* stream);
+/* Copy the context's parameters to params[LNR_PROPOSAL_PARAMS] (device). */
+lnr_status lnr_proposal_get(lnr_ctx* ctx, float* params, void* stream);
+/* Network inputs of every full 32 x 32 tile of two dense [h][w] 8-bit
+ * images (raster tile order): x[ntiles][2][16][16], bf16 bit patterns. */
+lnr_status lnr_proposal_inputs(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,
+                               int32_t w, int32_t h, uint16_t* x, void* stream);
+/* Inference on n inputs (device bf16 [n][2][16][16]): out[n][3] (device). */
+lnr_status lnr_proposal_forward(lnr_ctx* ctx, const uint16_t* x, int32_t n, float* out,
+                                void* stream);
+/* One training step on a batch: forward, loss (Huber on 8 o[0] - label_x and
+ * 8 o[1] - label_y, plus the logistic loss of o[2] against the soft target
+ * q = sigmoid(4 (2.5 - max |pred - label|)) held constant: "the rounded
+ * prediction lies within 2 px"), back-propagation and AdamW
+ * (beta 0.9 / 0.999, eps 1e-8, decoupled decay wd). labels[n][2] (device
+ * int32). Optional outputs: loss[n] per sample, grad[LNR_PROPOSAL_PARAMS]
+ * the batch gradient. lr = 0 and wd = 0 leaves the parameters unchanged. */
+lnr_status lnr_proposal_train_step(lnr_ctx* ctx, const uint16_t* x, const int32_t* labels,
+                                   int32_t n, float lr, float wd, float* loss, float* grad,
+                                   void* stream);
+/* The Sec. 2.2 search of lnr_stage_search restricted, per tile t, to the
+ * displacements centre[t] + [-R, R]^2 (centre [ntiles][2], device int32,
+ * |centre| + R <= 32). */
+lnr_status lnr_stage_search_window(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,
+                                   int32_t w, int32_t h, int32_t R, const int32_t* centre,
+                                   const lnr_params* p, int32_t* corner_xy, int32_t* disp,
+                                   uint32_t* ssd, uint8_t* flags, void* stream);
 
 /* ---- timing: optional per-kernel GPU timing with HIP events recorded on the
  * call's stream around every kernel launch of the calls that follow (off by

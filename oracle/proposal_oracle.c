@@ -28,8 +28,9 @@
  * Loss per sample with label (lx, ly), averaged over the batch:
  *   huber(dx - lx) + huber(dy - ly) + bce(o[2], q),
  *   huber(e) = e^2 / 2 for |e| <= 1, |e| - 1/2 otherwise,
- *   q = exp(-((dx - lx)^2 + (dy - ly)^2) / 4.5)  (a soft "within 1.5 px"
- *   target, held constant in the gradient),
+ *   q = 1 / (1 + exp(-4 (2.5 - max(|dx - lx|, |dy - ly|))))  (a soft "the
+ *   rounded prediction is within 2 px" target, held constant in the
+ *   gradient),
  *   bce(z, q) = max(z, 0) - q z + log(1 + exp(-|z|)).
  */
 #include <math.h>
@@ -189,7 +190,8 @@ double lo_cnn_loss_grad(const double* params, const double* x, const int32_t* la
     const double* xs = x + (size_t)s * 512;
     forward_one(params, &L, Wr, xs, rnd, A);
     const double ex = 8.0 * A->o[0] - label[2 * s], ey = 8.0 * A->o[1] - label[2 * s + 1];
-    const double q = exp(-(ex * ex + ey * ey) / 4.5), z = A->o[2];
+    const double em = fabs(ex) > fabs(ey) ? fabs(ex) : fabs(ey);
+    const double q = 1.0 / (1.0 + exp(-4.0 * (2.5 - em))), z = A->o[2];
     loss += huber(ex) + huber(ey) + (z > 0 ? z : 0.0) - q * z + log(1.0 + exp(-fabs(z)));
     double dO[3];
     dO[0] = 8.0 * huber_grad(ex) / n;

@@ -49,6 +49,7 @@ class Params(C.Structure):
         ("n_min", C.c_double), ("ssim_sigma", C.c_double), ("ssim_radius", C.c_int32),
         ("reserved0", C.c_int32), ("ssim_c1", C.c_double), ("ssim_c2", C.c_double),
         ("sigma_e", C.c_double), ("seed", C.c_uint64),
+        ("learned", C.c_int32), ("window_r", C.c_int32), ("conf_min", C.c_double),
     ]
 
     def __init__(self, **overrides):
@@ -118,12 +119,24 @@ def lib():
         L.lnr_stage_backward_warp.argtypes = [vp, C.POINTER(_Frame), vp, vp, vp, vp, vp, vp]
         L.lnr_stage_merge.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, C.POINTER(Params),
                                       vp, vp]
+        L.lnr_stage_search_window.argtypes = [vp, vp, vp, i32, i32, i32, vp, C.POINTER(Params),
+                                              vp, vp, vp, vp, vp]
+        L.lnr_proposal_set.argtypes = [vp, vp, vp]
+        L.lnr_proposal_get.argtypes = [vp, vp, vp]
+        L.lnr_proposal_inputs.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+        L.lnr_proposal_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.lnr_proposal_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.c_float, vp, vp, vp]
+        L.lnr_register_batch.argtypes = [vp, C.POINTER(_Frame), C.POINTER(_Frame), i32,
+                                         C.POINTER(Params), C.POINTER(_Registration), i32, vp]
+        L.lnr_autotune_flow.argtypes = [vp, i32, i32, C.POINTER(Params), vp, vp]
         L.lnr_trace_enable.argtypes = [vp, i32]
         L.lnr_trace_read.argtypes = [vp, C.POINTER(_TraceEntry), i32]
         for name in ("lnr_trace_enable", "lnr_trace_read", "lnr_create", "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack",
                      "lnr_merge", "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
                      "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
-                     "lnr_stage_merge"):
+                     "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
+                     "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
+                     "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -133,7 +146,14 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack", "lnr_merge",
             "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
             "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
-            "lnr_stage_merge", "lnr_trace_enable", "lnr_trace_read")
+            "lnr_stage_merge", "lnr_trace_enable", "lnr_trace_read",
+            "lnr_stage_search_window", "lnr_proposal_set", "lnr_proposal_get",
+            "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
+            "lnr_register_batch", "lnr_autotune_flow")
+
+BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
+
+PROPOSAL_PARAMS = 29891
 
 
 def _stream():
@@ -397,3 +417,100 @@ def stage_merge(ctx, imgs, yeqs, ref_index, params=None):
     ctx.check(lib().lnr_stage_merge(ctx._h, n, ch, w, h, IA, YA, ref_index, C.byref(p),
                                     _ptr(out), _stream()))
     return out
+
+
+# --------------------------------------------------------------------------- learned proposal
+# (an extension beyond the paper: a CNN proposes each level-0 tile's
+# displacement; the library's kernels run inference and training)
+
+def stage_search_window(ctx, ref: torch.Tensor, warped: torch.Tensor, R: int,
+                        centre: torch.Tensor, params=None):
+    """Search of stage_search restricted to centre[t] + [-R, R]^2 per tile."""
+    p = params or Params()
+    h, w = ref.shape
+    nt = max((w // p.tile) * (h // p.tile), 1)
+    dev = ref.device
+    centre = centre.to(device=dev, dtype=torch.int32).contiguous()
+    cxy = torch.empty(nt, 2, dtype=torch.int32, device=dev)
+    disp = torch.empty(nt, 2, dtype=torch.int32, device=dev)
+    ssd = torch.empty(nt, dtype=torch.int32, device=dev)
+    flags = torch.empty(nt, dtype=torch.uint8, device=dev)
+    ctx.check(lib().lnr_stage_search_window(ctx._h, _ptr(ref), _ptr(warped), w, h, R,
+                                            _ptr(centre), C.byref(p), _ptr(cxy), _ptr(disp),
+                                            _ptr(ssd), _ptr(flags), _stream()))
+    return cxy, disp, ssd, flags
+
+
+def proposal_set(ctx, params: torch.Tensor):
+    """Load network parameters (float32 [29891], device) and reset AdamW."""
+    params = params.to(device="cuda", dtype=torch.float32).contiguous()
+    assert params.numel() == PROPOSAL_PARAMS
+    ctx.check(lib().lnr_proposal_set(ctx._h, _ptr(params), _stream()))
+
+
+def proposal_get(ctx) -> torch.Tensor:
+    out = torch.empty(PROPOSAL_PARAMS, dtype=torch.float32, device="cuda")
+    ctx.check(lib().lnr_proposal_get(ctx._h, _ptr(out), _stream()))
+    return out
+
+
+def proposal_inputs(ctx, ref: torch.Tensor, warped: torch.Tensor) -> torch.Tensor:
+    """Network inputs of every full 32x32 tile: int16 view of bf16 [n, 2, 16, 16]."""
+    h, w = ref.shape
+    n = (w // 32) * (h // 32)
+    x = torch.empty(max(n, 1), 2, 16, 16, dtype=torch.int16, device=ref.device)
+    ctx.check(lib().lnr_proposal_inputs(ctx._h, _ptr(ref.contiguous()), _ptr(warped.contiguous()),
+                                        w, h, _ptr(x), _stream()))
+    return x[:n]
+
+
+def proposal_forward(ctx, x: torch.Tensor) -> torch.Tensor:
+    """[n, 3] outputs for bf16 inputs x (int16 bit patterns or bfloat16)."""
+    x = x.contiguous()
+    n = x.shape[0]
+    out = torch.empty(max(n, 1), 3, dtype=torch.float32, device=x.device)
+    ctx.check(lib().lnr_proposal_forward(ctx._h, _ptr(x), n, _ptr(out), _stream()))
+    return out[:n]
+
+
+def proposal_train_step(ctx, x: torch.Tensor, labels: torch.Tensor, lr: float, wd: float = 0.0,
+                        want_loss: bool = True, want_grad: bool = False):
+    """One AdamW step on a batch; returns (per-sample loss or None, gradient or None)."""
+    x = x.contiguous()
+    n = x.shape[0]
+    labels = labels.to(device=x.device, dtype=torch.int32).contiguous()
+    loss = torch.empty(n, dtype=torch.float32, device=x.device) if want_loss else None
+    grad = torch.empty(PROPOSAL_PARAMS, dtype=torch.float32, device=x.device) if want_grad else None
+    ctx.check(lib().lnr_proposal_train_step(
+        ctx._h, _ptr(x), _ptr(labels), n, float(lr), float(wd),
+        None if loss is None else _ptr(loss), None if grad is None else _ptr(grad), _stream()))
+    return loss, grad
+
+
+# --------------------------------------------------------------------------- batches
+
+def register_batch(ctx: Context, refs, srcs, params: Params | None = None, outs=None,
+                   graph: bool = False, autotune: bool = False):
+    """Register len(refs) pairs of any sizes in one call (concurrent streams;
+    optionally one cached HIP graph). Returns the list of Registrations."""
+    p = params or Params()
+    n = len(refs)
+    assert n == len(srcs) and n > 0
+    if outs is None:
+        outs = [Registration.alloc(r.width, r.height, r.fmt, p) for r in refs]
+    RA = (_Frame * n)(*[r._c() for r in refs])
+    SA = (_Frame * n)(*[s._c() for s in srcs])
+    OA = (_Registration * n)(*[o._c() for o in outs])
+    flags = (BATCH_GRAPH if graph else 0) | (BATCH_AUTOTUNE if autotune else 0)
+    ctx.check(lib().lnr_register_batch(ctx._h, RA, SA, n, C.byref(p), OA, flags, _stream()))
+    return outs
+
+
+def autotune_flow(ctx: Context, w: int, h: int, params: Params | None = None):
+    """Pick the fastest domain-transform kernel shape for w x h; returns it
+    (rows per thread, row block, rows per column segment, columns per block,
+    segments per column)."""
+    p = params or Params()
+    out = (C.c_int32 * 5)()
+    ctx.check(lib().lnr_autotune_flow(ctx._h, w, h, C.byref(p), out, _stream()))
+    return tuple(out)

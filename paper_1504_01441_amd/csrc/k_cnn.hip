@@ -1,0 +1,600 @@
+// k_cnn.hip -- the learned displacement proposal (an extension beyond the
+// paper: a small CNN predicts each level-0 tile's displacement so that the
+// Sec. 2.2 search only scans a window around it). Inference and training run
+// on the matrix cores: every convolution is an implicit GEMM on
+// v_mfma_f32_16x16x16_bf16 (bf16 operands, fp32 accumulation).
+//
+// Network (per tile): x [16][16][2] -> conv3x3 s1 -> 32 ch [16][16] -> conv s2
+// -> [8][8] -> conv s1 -> [8][8] -> conv s2 -> [4][4] -> linear 512 -> 3,
+// ReLU after every convolution, activations rounded to bf16; outputs
+// (dx / 8, dy / 8, confidence logit). On the device, activations are NHWC
+// (32 channels innermost) so that an MFMA operand is one 8-byte load.
+//
+// MFMA 16x16x16 operand layout (lane l, r = l % 16, g = l / 16, j = 0..3):
+//   A[r][4g + j],  B[4g + j][r],  D[4g + j][r].
+//
+//  k_cnn_pack     fp32 master parameters -> bf16 weight layouts for the kernels
+//  k_cnn_input    tile pairs -> network input (2x2 sums, bf16)
+//  k_cnn_fwd      per-wave sample pipeline, weights and activations in LDS;
+//                 inference writes the proposal (window centre, fallback
+//                 flag), training writes the activations and outputs
+//  k_cnn_loss     loss and output gradient per sample
+//  k_cnn_bwd      per-sample back-propagation through the ReLUs and the
+//                 transposed convolutions (activation gradients)
+//  k_cnn_wgrad    weight and bias gradients of one layer, per block of samples
+//  k_cnn_head_grad  head gradients
+//  k_cnn_adamw    sums the per-block gradients and applies AdamW (fp32)
+#include "lnr_internal.h"
+
+namespace lnr {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int CH = 32;
+constexpr int kWave = 64;
+constexpr int kFwdWaves = 4;
+
+// flat parameter vector: W1[32][2][3][3] b1 W2[32][32][3][3] b2 W3 b3 W4 b4
+// Wh[3][512] bh[3]
+constexpr int kOffW[4] = {0, 608, 9856, 19104};
+constexpr int kOffB[4] = {576, 9824, 19072, 28320};
+constexpr int kOffWh = 28352, kOffBh = 29888, kNParam = 29891;
+
+// packed bf16 weights: W1p[32 co][32 k] (k = tap * 2 + ci, zero from 18),
+// Wp[l][32 co][9 tap][32 ci] and the transposes WT[l][32 ci][9 tap][32 co]
+constexpr int kW1p = CH * 32;
+constexpr int kWp = CH * 9 * CH;
+constexpr int kPacked = kW1p + 3 * kWp + 3 * kWp;
+
+// per-sample stored activations (bf16, NHWC): x, a1, a2, a3, a4
+constexpr int kActX = 0, kActA1 = 512, kActA2 = kActA1 + 8192, kActA3 = kActA2 + 2048,
+              kActA4 = kActA3 + 2048, kActN = kActA4 + 512;
+// per-sample activation gradients after the ReLU (bf16, channel-major [c][p])
+constexpr int kDz1 = 0, kDz2 = 8192, kDz3 = kDz2 + 2048, kDz4 = kDz3 + 2048,
+              kDzN = kDz4 + 512;
+
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ inline bf16x4 ld4(const uint16_t* p) { return *reinterpret_cast<const bf16x4*>(p); }
+
+__global__ __launch_bounds__(256) void k_cnn_pack(const float* __restrict__ P,
+                                                  uint16_t* __restrict__ pk) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < kW1p) {
+    const int co = i / 32, k = i % 32;
+    float v = 0.f;
+    if (k < 18) {
+      const int tap = k >> 1, ci = k & 1;
+      v = P[kOffW[0] + (co * 2 + ci) * 9 + tap];
+    }
+    pk[i] = f2bf(v);
+    return;
+  }
+  int j = i - kW1p;
+  if (j >= 6 * kWp) return;
+  const bool tr = j >= 3 * kWp;
+  if (tr) j -= 3 * kWp;
+  const int l = 1 + j / kWp, e = j % kWp;
+  int co, tap, ci;
+  if (!tr) { co = e / (9 * CH); tap = (e / CH) % 9; ci = e % CH; }
+  else { ci = e / (9 * CH); tap = (e / CH) % 9; co = e % CH; }
+  pk[i] = f2bf(P[kOffW[l] + (co * CH + ci) * 9 + tap]);
+}
+
+// One tile pair per thread row: 16x16 values per channel.
+__global__ __launch_bounds__(256) void k_cnn_input(const uint8_t* __restrict__ ref,
+                                                   const uint8_t* __restrict__ wrp, int w, int ntx,
+                                                   int ntiles, uint16_t* __restrict__ x) {
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
+  const int x0 = (t % ntx) * 32, y0 = (t / ntx) * 32;
+  const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+  for (int c = 0; c < 2; ++c) {
+    const uint8_t* img = c ? wrp : ref;
+    const size_t r0 = (size_t)(y0 + 2 * i) * w + (size_t)(x0 + 2 * j);
+    const int s = img[r0] + img[r0 + 1] + img[r0 + w] + img[r0 + w + 1];
+    x[(size_t)t * 512 + (c * 16 + i) * 16 + j] = f2bf((float)(s - 510) * (1.f / 512.f));
+  }
+}
+
+// conv1 (2 -> 32, stride 1): K = 18 (tap, ci) padded to 32
+__device__ void conv1_fwd(const uint16_t* in /*[16][16][2]*/, const uint16_t* W1p,
+                          const float* bias, uint16_t* out /*[16][16][32]*/, int lane) {
+  const int r = lane & 15, g = lane >> 4;
+  for (int mt = 0; mt < 16; ++mt) {
+    const int m = mt * 16 + r, oy = m >> 4, ox = m & 15;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int t0 = half * 8 + g * 2;  // taps t0, t0 + 1 (channels 0, 1 each)
+      uint32_t v[2] = {0u, 0u};
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int tap = t0 + q;
+        const int iy = oy + tap / 3 - 1, ix = ox + tap % 3 - 1;
+        if (tap < 9 && iy >= 0 && iy < 16 && ix >= 0 && ix < 16)
+          v[q] = *reinterpret_cast<const uint32_t*>(in + (iy * 16 + ix) * 2);
+      }
+      bf16x4 a;
+      a[0] = (short)(v[0] & 0xffff); a[1] = (short)(v[0] >> 16);
+      a[2] = (short)(v[1] & 0xffff); a[3] = (short)(v[1] >> 16);
+      const bf16x4 b0 = ld4(W1p + r * 32 + half * 16 + g * 4);
+      const bf16x4 b1 = ld4(W1p + (16 + r) * 32 + half * 16 + g * 4);
+      acc0 = mfma(a, b0, acc0);
+      acc1 = mfma(a, b1, acc1);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = mt * 16 + g * 4 + j;
+      out[p * CH + r] = f2bf(fmaxf(acc0[j] + bias[r], 0.f));
+      out[p * CH + 16 + r] = f2bf(fmaxf(acc1[j] + bias[16 + r], 0.f));
+    }
+  }
+}
+
+// conv 32 -> 32 (3x3, pad 1, stride S), NHWC bf16 in / out, W [co][tap][ci]
+template <int HIN, int HOUT, int S>
+__device__ void conv_fwd(const uint16_t* in, const uint16_t* W, const float* bias, uint16_t* out,
+                         int lane) {
+  const int r = lane & 15, g = lane >> 4;
+  constexpr int MT = HOUT * HOUT / 16;
+  const bf16x4 zero = {0, 0, 0, 0};
+  for (int mt = 0; mt < MT; ++mt) {
+    const int m = mt * 16 + r, oy = m / HOUT, ox = m % HOUT;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+      const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int ci = half * 16 + g * 4;
+        const bf16x4 a = ok ? ld4(in + (iy * HIN + ix) * CH + ci) : zero;
+        const bf16x4 b0 = ld4(W + (r * 9 + tap) * CH + ci);
+        const bf16x4 b1 = ld4(W + ((16 + r) * 9 + tap) * CH + ci);
+        acc0 = mfma(a, b0, acc0);
+        acc1 = mfma(a, b1, acc1);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = mt * 16 + g * 4 + j;
+      out[p * CH + r] = f2bf(fmaxf(acc0[j] + bias[r], 0.f));
+      out[p * CH + 16 + r] = f2bf(fmaxf(acc1[j] + bias[16 + r], 0.f));
+    }
+  }
+}
+
+struct ProposalOut {
+  int32_t* centre;    // [ntiles][2] window centre (null: not wanted)
+  uint8_t* fallback;  // [ntiles] 1: exhaustive search
+  int clampc;         // |centre| <= clampc
+  float conf_logit;   // window search when the logit is >= this
+};
+
+// LDS: packed weights (W1p, W2..W4), biases, head, then per wave a 16 KB and
+// a 4 KB activation buffer (x -> a1 -> a2 -> a3 -> a4 ping-pong).
+constexpr int kFwdLdsWeights = (kW1p + 3 * kWp) * 2 + 4 * CH * 4 + 3 * 512 * 4 + 4 * 4;
+constexpr int kFwdLdsWave = (8192 + 2048) * 2;
+constexpr int kFwdLds = kFwdLdsWeights + kFwdWaves * kFwdLdsWave;
+
+template <bool TRAIN>
+__global__ __launch_bounds__(kFwdWaves * kWave) void k_cnn_fwd(
+    const uint16_t* __restrict__ pk, const float* __restrict__ P, const uint16_t* __restrict__ x,
+    int n, float* __restrict__ out, uint16_t* __restrict__ acts, ProposalOut po) {
+  extern __shared__ __align__(16) uint8_t sm[];
+  uint16_t* sW1 = reinterpret_cast<uint16_t*>(sm);
+  uint16_t* sW = sW1 + kW1p;  // [3][32][9][32]
+  float* sb = reinterpret_cast<float*>(sW + 3 * kWp);  // [4][32]
+  float* sWh = sb + 4 * CH;                            // [3][512]
+  float* sbh = sWh + 3 * 512;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(pk);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(sm);
+    for (int i = tid; i < (kW1p + 3 * kWp) / 2; i += blockDim.x) dst[i] = src[i];
+    for (int i = tid; i < 4 * CH; i += blockDim.x) sb[i] = P[kOffB[i / CH] + i % CH];
+    for (int i = tid; i < 3 * 512; i += blockDim.x) sWh[i] = P[kOffWh + i];
+    if (tid < 3) sbh[tid] = P[kOffBh + tid];
+  }
+  __syncthreads();
+  uint16_t* bufA = reinterpret_cast<uint16_t*>(sm + kFwdLdsWeights + wave * kFwdLdsWave);
+  uint16_t* bufB = bufA + 8192;
+  for (int s = blockIdx.x * kFwdWaves + wave; s < n; s += gridDim.x * kFwdWaves) {
+    // x: NCHW [2][16][16] -> NHWC [16][16][2] in bufB
+    const uint16_t* xs = x + (size_t)s * 512;
+    for (int i = lane; i < 256; i += kWave) {
+      bufB[2 * i] = xs[i];
+      bufB[2 * i + 1] = xs[256 + i];
+    }
+    if (TRAIN)
+      for (int i = lane; i < 512; i += kWave) acts[(size_t)s * kActN + kActX + i] = bufB[i];
+    conv1_fwd(bufB, sW1, sb, bufA, lane);                     // a1 -> bufA
+    conv_fwd<16, 8, 2>(bufA, sW, sb + CH, bufB, lane);         // a2 -> bufB
+    if (TRAIN) {
+      uint16_t* a = acts + (size_t)s * kActN;
+      for (int i = lane; i < 8192; i += kWave) a[kActA1 + i] = bufA[i];
+      for (int i = lane; i < 2048; i += kWave) a[kActA2 + i] = bufB[i];
+    }
+    conv_fwd<8, 8, 1>(bufB, sW + kWp, sb + 2 * CH, bufA, lane);       // a3 -> bufA
+    conv_fwd<8, 4, 2>(bufA, sW + 2 * kWp, sb + 3 * CH, bufB, lane);   // a4 -> bufB
+    if (TRAIN) {
+      uint16_t* a = acts + (size_t)s * kActN;
+      for (int i = lane; i < 2048; i += kWave) a[kActA3 + i] = bufA[i];
+      for (int i = lane; i < 512; i += kWave) a[kActA4 + i] = bufB[i];
+    }
+    // head (fp32): f = p * 32 + c, eight features per lane
+    float o[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int f = lane * 8 + k;
+      const float a = bf2f(bufB[f]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) o[j] += sWh[j * 512 + f] * a;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) o[j] += __shfl_xor(o[j], off);
+    if (lane == 0) {
+      const float o0 = o[0] + sbh[0], o1 = o[1] + sbh[1], o2 = o[2] + sbh[2];
+      if (out) {
+        out[(size_t)s * 3] = o0;
+        out[(size_t)s * 3 + 1] = o1;
+        out[(size_t)s * 3 + 2] = o2;
+      }
+      if (po.centre) {
+        // window centre: prediction rounded half up, kept inside the search range
+        int cx = (int)floorf(8.f * o0 + 0.5f), cy = (int)floorf(8.f * o1 + 0.5f);
+        cx = min(max(cx, -po.clampc), po.clampc);
+        cy = min(max(cy, -po.clampc), po.clampc);
+        po.centre[2 * s] = cx;
+        po.centre[2 * s + 1] = cy;
+        po.fallback[s] = o2 >= po.conf_logit ? 0 : 1;
+      }
+    }
+  }
+}
+
+// loss and output gradient (the soft target is held constant)
+__global__ __launch_bounds__(256) void k_cnn_loss(const float* __restrict__ o,
+                                                  const int32_t* __restrict__ lab, int n,
+                                                  float* __restrict__ dO,
+                                                  float* __restrict__ loss) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  const float ex = 8.f * o[3 * s] - (float)lab[2 * s];
+  const float ey = 8.f * o[3 * s + 1] - (float)lab[2 * s + 1];
+  const float z = o[3 * s + 2];
+  const float q = 1.f / (1.f + expf(-4.f * (2.5f - fmaxf(fabsf(ex), fabsf(ey)))));
+  const float inv = 1.f / (float)n;
+  dO[3 * s] = 8.f * fminf(fmaxf(ex, -1.f), 1.f) * inv;
+  dO[3 * s + 1] = 8.f * fminf(fmaxf(ey, -1.f), 1.f) * inv;
+  dO[3 * s + 2] = (1.f / (1.f + expf(-z)) - q) * inv;
+  if (loss) {
+    auto hub = [](float e) { return fabsf(e) <= 1.f ? 0.5f * e * e : fabsf(e) - 0.5f; };
+    loss[s] = hub(ex) + hub(ey) + fmaxf(z, 0.f) - q * z + log1pf(expf(-fabsf(z)));
+  }
+}
+
+// da_in = transposed conv of dz (NHWC [HOUT^2][32]) with W (WT [ci][tap][co]);
+// dz_in = bf16(da_in where a_in > 0), to LDS (NHWC) and global ([ci][q])
+template <int HIN, int HOUT, int S>
+__device__ void conv_bwd_data(const uint16_t* dz, const uint16_t* WT,
+                              const uint16_t* __restrict__ a_in /*global NHWC*/,
+                              uint16_t* dz_in, uint16_t* __restrict__ dz_in_g, int lane) {
+  const int r = lane & 15, g = lane >> 4;
+  constexpr int MT = HIN * HIN / 16;
+  const bf16x4 zero = {0, 0, 0, 0};
+  for (int mt = 0; mt < MT; ++mt) {
+    const int q = mt * 16 + r, qy = q / HIN, qx = q % HIN;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ty = qy + 1 - tap / 3, tx = qx + 1 - tap % 3;
+      const int oy = ty / S, ox = tx / S;
+      const bool ok = ty >= 0 && tx >= 0 && ty % S == 0 && tx % S == 0 && oy < HOUT && ox < HOUT;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int co = half * 16 + g * 4;
+        const bf16x4 a = ok ? ld4(dz + (oy * HOUT + ox) * CH + co) : zero;
+        const bf16x4 b0 = ld4(WT + (r * 9 + tap) * CH + co);
+        const bf16x4 b1 = ld4(WT + ((16 + r) * 9 + tap) * CH + co);
+        acc0 = mfma(a, b0, acc0);
+        acc1 = mfma(a, b1, acc1);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = mt * 16 + g * 4 + j;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int ci = h * 16 + r;
+        const float d = h ? acc1[j] : acc0[j];
+        const uint16_t v = a_in[p * CH + ci] != 0 && bf2f(a_in[p * CH + ci]) > 0.f ? f2bf(d) : 0;
+        dz_in[p * CH + ci] = v;
+        dz_in_g[ci * HIN * HIN + p] = v;
+      }
+    }
+  }
+}
+
+constexpr int kBwdLdsWeights = 3 * kWp * 2 + 3 * 512 * 4;
+constexpr int kBwdLdsWave = (8192 + 2048 + 2048) * 2;
+constexpr int kBwdWaves = 4;
+constexpr int kBwdLds = kBwdLdsWeights + kBwdWaves * kBwdLdsWave;
+
+__global__ __launch_bounds__(kBwdWaves * kWave) void k_cnn_bwd(
+    const uint16_t* __restrict__ pk, const float* __restrict__ P,
+    const uint16_t* __restrict__ acts, const float* __restrict__ dO, int n,
+    uint16_t* __restrict__ dzs) {
+  extern __shared__ __align__(16) uint8_t sm[];
+  uint16_t* sWT = reinterpret_cast<uint16_t*>(sm);  // [3][32 ci][9][32 co]
+  float* sWh = reinterpret_cast<float*>(sWT + 3 * kWp);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(pk + kW1p + 3 * kWp);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(sm);
+    for (int i = tid; i < 3 * kWp / 2; i += blockDim.x) dst[i] = src[i];
+    for (int i = tid; i < 3 * 512; i += blockDim.x) sWh[i] = P[kOffWh + i];
+  }
+  __syncthreads();
+  uint16_t* bufA = reinterpret_cast<uint16_t*>(sm + kBwdLdsWeights + wave * kBwdLdsWave);
+  uint16_t* bufB = bufA + 8192;
+  uint16_t* bufC = bufB + 2048;
+  for (int s = blockIdx.x * kBwdWaves + wave; s < n; s += gridDim.x * kBwdWaves) {
+    const uint16_t* a = acts + (size_t)s * kActN;
+    uint16_t* dz = dzs + (size_t)s * kDzN;
+    const float d0 = dO[3 * s], d1 = dO[3 * s + 1], d2 = dO[3 * s + 2];
+    // through the head and the last ReLU: dz4 (NHWC in bufB, [c][p] global)
+    for (int f = lane; f < 512; f += kWave) {
+      const float da = sWh[f] * d0 + sWh[512 + f] * d1 + sWh[1024 + f] * d2;
+      const uint16_t av = a[kActA4 + f];
+      const uint16_t v = av != 0 && bf2f(av) > 0.f ? f2bf(da) : 0;
+      bufB[f] = v;
+      dz[kDz4 + (f % CH) * 16 + f / CH] = v;
+    }
+    conv_bwd_data<8, 4, 2>(bufB, sWT + 2 * kWp, a + kActA3, bufC, dz + kDz3, lane);
+    conv_bwd_data<8, 8, 1>(bufC, sWT + kWp, a + kActA2, bufB, dz + kDz2, lane);
+    conv_bwd_data<16, 8, 2>(bufB, sWT, a + kActA1, bufA, dz + kDz1, lane);
+  }
+}
+
+// Weight and bias gradients of layer L (1..4) over the samples of this block:
+// dW[co][tap][ci] = sum_{s,p} dz[s][co][p] a_in[s][in(p, tap)][ci]
+// (M = co, N = (tap, ci), K = (s, p)), written to part[block] in the master
+// layout.
+template <int L>
+__global__ __launch_bounds__(256) void k_cnn_wgrad(const uint16_t* __restrict__ acts,
+                                                   const uint16_t* __restrict__ dzs, int n,
+                                                   int per_block, float* __restrict__ part) {
+  constexpr int CIN = L == 1 ? 2 : CH;
+  constexpr int HIN = L <= 2 ? 16 : 8;
+  constexpr int HOUT = L == 1 ? 16 : (L == 4 ? 4 : 8);
+  constexpr int S = (L == 2 || L == 4) ? 2 : 1;
+  constexpr int NP = HOUT * HOUT;
+  constexpr int NN = 9 * CIN;                 // 18 or 288
+  constexpr int NT = (NN + 15) / 16;          // N tiles
+  constexpr int NTW = (NT + 3) / 4;           // per wave
+  constexpr int AIN = L == 1 ? kActX : (L == 2 ? kActA1 : (L == 3 ? kActA2 : kActA3));
+  constexpr int DZ = L == 1 ? kDz1 : (L == 2 ? kDz2 : (L == 3 ? kDz3 : kDz4));
+  __shared__ float bsum[8][CH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int s0 = blockIdx.x * per_block, s1 = min(n, s0 + per_block);
+  f32x4 acc[2][NTW];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) acc[m][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int s = s0; s < s1; ++s) {
+    const uint16_t* dz = dzs + (size_t)s * kDzN + DZ;
+    const uint16_t* ain = acts + (size_t)s * kActN + AIN;
+    for (int k0 = 0; k0 < NP; k0 += 16) {
+      const int p0 = k0 + g * 4;
+      const bf16x4 a0 = ld4(dz + r * NP + p0);
+      const bf16x4 a1 = ld4(dz + (16 + r) * NP + p0);
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int nt = wave + 4 * t;
+        if (nt >= NT) continue;
+        const int nn = nt * 16 + r;
+        bf16x4 b = {0, 0, 0, 0};
+        if (nn < NN) {
+          const int tap = nn / CIN, ci = nn % CIN;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j, oy = p / HOUT, ox = p % HOUT;
+            const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+            if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN)
+              b[j] = (short)ain[(iy * HIN + ix) * CIN + ci];
+          }
+        }
+        acc[0][t] = mfma(a0, b, acc[0][t]);
+        acc[1][t] = mfma(a1, b, acc[1][t]);
+      }
+    }
+  }
+  float* out = part + (size_t)blockIdx.x * kNParam;
+#pragma unroll
+  for (int t = 0; t < NTW; ++t) {
+    const int nt = wave + 4 * t;
+    const int nn = nt * 16 + r;
+    if (nt >= NT || nn >= NN) continue;
+    const int tap = nn / CIN, ci = nn % CIN;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int co = m * 16 + g * 4 + j;
+        out[kOffW[L - 1] + (co * CIN + ci) * 9 + tap] = acc[m][t][j];
+      }
+  }
+  // bias gradient: 8 position groups per channel
+  {
+    const int co = tid & 31, grp = tid >> 5;
+    float sacc = 0.f;
+    for (int s = s0; s < s1; ++s) {
+      const uint16_t* dz = dzs + (size_t)s * kDzN + DZ + co * NP;
+      for (int p = grp; p < NP; p += 8) sacc += bf2f(dz[p]);
+    }
+    bsum[grp][co] = sacc;
+    __syncthreads();
+    if (tid < CH) {
+      float b = 0.f;
+      for (int q = 0; q < 8; ++q) b += bsum[q][tid];
+      out[kOffB[L - 1] + tid] = b;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cnn_head_grad(const uint16_t* __restrict__ acts,
+                                                       const float* __restrict__ dO, int n,
+                                                       int per_block, float* __restrict__ part) {
+  const int tid = threadIdx.x;
+  const int s0 = blockIdx.x * per_block, s1 = min(n, s0 + per_block);
+  float* out = part + (size_t)blockIdx.x * kNParam;
+  for (int f = tid; f < 512; f += 256) {
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    for (int s = s0; s < s1; ++s) {
+      const float a = bf2f(acts[(size_t)s * kActN + kActA4 + f]);
+      g0 += dO[3 * s] * a;
+      g1 += dO[3 * s + 1] * a;
+      g2 += dO[3 * s + 2] * a;
+    }
+    out[kOffWh + f] = g0;
+    out[kOffWh + 512 + f] = g1;
+    out[kOffWh + 1024 + f] = g2;
+  }
+  if (tid < 3) {
+    float b = 0.f;
+    for (int s = s0; s < s1; ++s) b += dO[3 * s + tid];
+    out[kOffBh + tid] = b;
+  }
+}
+
+struct AdamArgs {
+  float lr, b1, b2, eps, wd, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+__global__ __launch_bounds__(256) void k_cnn_adamw(const float* __restrict__ part, int nblk,
+                                                   float* __restrict__ P, float* __restrict__ m,
+                                                   float* __restrict__ v, AdamArgs a,
+                                                   float* __restrict__ grad_out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= kNParam) return;
+  float g = 0.f;
+  for (int b = 0; b < nblk; ++b) g += part[(size_t)b * kNParam + i];
+  if (grad_out) grad_out[i] = g;
+  if (a.lr == 0.f && a.wd == 0.f) return;  // gradient only
+  const float mi = a.b1 * m[i] + (1.f - a.b1) * g;
+  const float vi = a.b2 * v[i] + (1.f - a.b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / a.c1, vh = vi / a.c2;
+  P[i] = P[i] - a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * P[i]);
+}
+
+}  // namespace
+
+int cnn_param_count() { return kNParam; }
+size_t cnn_packed_elems() { return kPacked; }
+size_t cnn_act_elems() { return kActN; }
+size_t cnn_dz_elems() { return kDzN; }
+
+hipError_t launch_cnn_pack(const float* params, uint16_t* packed, hipStream_t st) {
+  LNR_LAUNCH(k_cnn_pack, dim3((kPacked + 255) / 256), dim3(256), 0, st, params, packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, int ntx, int nty,
+                            uint16_t* x, hipStream_t st) {
+  if (ntx * nty == 0) return hipSuccess;
+  LNR_LAUNCH(k_cnn_input, dim3(ntx * nty), dim3(256), 0, st, ref, warped, w, ntx, ntx * nty, x);
+  return hipGetLastError();
+}
+
+static int fwd_blocks(int n) {
+  int b = (n + kFwdWaves - 1) / kFwdWaves;
+  return b < 1024 ? (b < 1 ? 1 : b) : 1024;
+}
+
+hipError_t launch_cnn_forward(const uint16_t* packed, const float* params, const uint16_t* x,
+                              int n, float* out, uint16_t* acts, int32_t* centre,
+                              uint8_t* fallback, int clampc, float conf_logit, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  ProposalOut po{centre, fallback, clampc, conf_logit};
+  hipError_t e;
+  if (acts) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cnn_fwd<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kFwdLds);
+    if (e != hipSuccess) return e;
+    LNR_LAUNCH(k_cnn_fwd<true>, dim3(fwd_blocks(n)), dim3(kFwdWaves * kWave), kFwdLds, st,
+               packed, params, x, n, out, acts, po);
+  } else {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cnn_fwd<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kFwdLds);
+    if (e != hipSuccess) return e;
+    LNR_LAUNCH(k_cnn_fwd<false>, dim3(fwd_blocks(n)), dim3(kFwdWaves * kWave), kFwdLds, st,
+               packed, params, x, n, out, acts, po);
+  }
+  return hipGetLastError();
+}
+
+int cnn_grad_blocks(int n, int* per_block) {
+  const int pb = 64;
+  *per_block = pb;
+  return (n + pb - 1) / pb;
+}
+
+hipError_t launch_cnn_backward(const uint16_t* packed, const float* params,
+                               const uint16_t* acts, const float* out, const int32_t* labels,
+                               int n, float* dO, float* loss, uint16_t* dzs, float* part,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  LNR_LAUNCH(k_cnn_loss, dim3((n + 255) / 256), dim3(256), 0, st, out, labels, n, dO, loss);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cnn_bwd),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, kBwdLds);
+  if (e != hipSuccess) return e;
+  LNR_LAUNCH(k_cnn_bwd, dim3(fwd_blocks(n)), dim3(kBwdWaves * kWave), kBwdLds, st, packed, params,
+             acts, dO, n, dzs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int pb = 0;
+  const int nb = cnn_grad_blocks(n, &pb);
+  LNR_LAUNCH(k_cnn_wgrad<1>, dim3(nb), dim3(256), 0, st, acts, dzs, n, pb, part);
+  LNR_LAUNCH(k_cnn_wgrad<2>, dim3(nb), dim3(256), 0, st, acts, dzs, n, pb, part);
+  LNR_LAUNCH(k_cnn_wgrad<3>, dim3(nb), dim3(256), 0, st, acts, dzs, n, pb, part);
+  LNR_LAUNCH(k_cnn_wgrad<4>, dim3(nb), dim3(256), 0, st, acts, dzs, n, pb, part);
+  LNR_LAUNCH(k_cnn_head_grad, dim3(nb), dim3(256), 0, st, acts, dO, n, pb, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_cnn_adamw(const float* part, int nblk, float* params, float* m, float* v,
+                            float lr, float wd, int step, float* grad_out, hipStream_t st) {
+  AdamArgs a;
+  a.lr = lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.wd = wd;
+  a.c1 = (float)(1.0 - pow(0.9, step));
+  a.c2 = (float)(1.0 - pow(0.999, step));
+  LNR_LAUNCH(k_cnn_adamw, dim3((kNParam + 255) / 256), dim3(256), 0, st, part, nblk, params, m,
+             v, a, grad_out);
+  return hipGetLastError();
+}
+
+}  // namespace lnr

@@ -414,14 +414,80 @@ hipError_t launch_col(bool last, float* maps, const uint8_t* guide, int W, int H
 
 }  // namespace
 
+namespace {
+const DtShape kRowShapes[] = {{4, 256, 0, 0, 0}, {8, 256, 0, 0, 0}, {12, 256, 0, 0, 0},
+                              {4, 512, 0, 0, 0}, {8, 512, 0, 0, 0}, {12, 512, 0, 0, 0}};
+const DtShape kColShapes[] = {{0, 0, 8, 8, 128},  {0, 0, 8, 4, 128},  {0, 0, 16, 4, 128},
+                              {0, 0, 8, 2, 256},  {0, 0, 24, 4, 128}, {0, 0, 16, 2, 256},
+                              {0, 0, 24, 2, 256}};
+
+hipError_t row_pass(const DtShape& s, bool first, float* maps, const uint8_t* guide, int W, int H,
+                    const double* cf, const int32_t* cxy, const int32_t* disp,
+                    const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
+#define ROW(SEG, NT)                                                                           \
+  if (s.seg == SEG && s.nt == NT)                                                              \
+    return launch_row<SEG, NT>(first, maps, guide, W, H, cf, cxy, disp, flags, ntx, nty, tile, st);
+  ROW(4, 256) ROW(8, 256) ROW(12, 256) ROW(4, 512) ROW(8, 512) ROW(12, 512)
+#undef ROW
+  return hipErrorInvalidValue;
+}
+
+hipError_t col_pass(const DtShape& s, bool last, float* maps, const uint8_t* guide, int W, int H,
+                    const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
+#define COL(L, NC, NS)                                                              \
+  if (s.l == L && s.ncol == NC && s.nseg == NS)                                      \
+    return launch_col<L, NC, NS>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+  COL(8, 8, 128) COL(8, 4, 128) COL(16, 4, 128) COL(8, 2, 256) COL(24, 4, 128)
+  COL(16, 2, 256) COL(24, 2, 256)
+#undef COL
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+bool dt_shape_valid(const DtShape& s, int W, int H) {
+  bool row = false, col = false;
+  for (const DtShape& r : kRowShapes) row |= r.seg == s.seg && r.nt == s.nt;
+  for (const DtShape& c : kColShapes) col |= c.l == s.l && c.ncol == s.ncol && c.nseg == s.nseg;
+  return row && col && W <= s.seg * s.nt && H <= s.l * s.nseg;
+}
+
+// Every instantiated (row, column) pair that covers W x H.
+int dt_shape_candidates(int W, int H, DtShape* out, int max) {
+  int n = 0;
+  for (const DtShape& r : kRowShapes)
+    for (const DtShape& c : kColShapes) {
+      const DtShape s{r.seg, r.nt, c.l, c.ncol, c.nseg};
+      if (dt_shape_valid(s, W, H) && n < max) out[n++] = s;
+    }
+  return n;
+}
+
+// The default table: the fewest rows / segments per thread that cover the
+// image (double-precision segments stay within 256 VGPRs).
+DtShape dt_default_shape(int W, int H) {
+  DtShape s;
+  if (W <= 1024) { s.seg = 4; s.nt = 256; }
+  else if (W <= 2048) { s.seg = 8; s.nt = 256; }
+  else if (W <= 3072) { s.seg = 12; s.nt = 256; }
+  else if (W <= 4096) { s.seg = 8; s.nt = 512; }
+  else { s.seg = 12; s.nt = 512; }
+  if (H <= 1024) { s.l = 8; s.ncol = 8; s.nseg = 128; }
+  else if (H <= 2048) { s.l = 16; s.ncol = 4; s.nseg = 128; }
+  else if (H <= 3072) { s.l = 24; s.ncol = 4; s.nseg = 128; }
+  else if (H <= 4096) { s.l = 16; s.ncol = 2; s.nseg = 256; }
+  else { s.l = 24; s.ncol = 2; s.nseg = 256; }
+  return s;
+}
+
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
                        int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
                        const lnr_params& p, float* maps, double* coef, float* flow,
-                       float* ntilde, hipStream_t st) {
+                       float* ntilde, hipStream_t st, const DtShape* shape) {
   DtArgs a;
   a.iters = p.dt_iters;
   a.sigma_s = p.sigma_s;
   a.ratio = p.sigma_s / p.sigma_r;
+  const DtShape sh = shape && dt_shape_valid(*shape, W, H) ? *shape : dt_default_shape(W, H);
   LNR_LAUNCH(k_dt_coef, dim3(a.iters), dim3(256), 0, st, a, coef);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -429,20 +495,9 @@ hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint
   for (int i = 0; i < a.iters; ++i) {
     const double* cf = coef + 256 * i;
     const bool first = i == 0, last = i + 1 == a.iters;
-    // row segments of SEG pixels per thread (W <= 6144); the double-precision
-    // segments stay within 256 VGPRs per thread
-    if (W <= 1024) e = launch_row<4, 256>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else if (W <= 2048) e = launch_row<8, 256>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else if (W <= 3072) e = launch_row<12, 256>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else if (W <= 4096) e = launch_row<8, 512>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
-    else e = launch_row<12, 512>(first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    e = row_pass(sh, first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
     if (e != hipSuccess) return e;
-    // column segments of L rows, NSEG per column (H <= 6144)
-    if (H <= 1024) e = launch_col<8, 8, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
-    else if (H <= 2048) e = launch_col<16, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
-    else if (H <= 3072) e = launch_col<24, 4, 128>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
-    else if (H <= 4096) e = launch_col<16, 2, 256>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
-    else e = launch_col<24, 2, 256>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    e = col_pass(sh, last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -134,7 +134,9 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
                                                  int32_t* __restrict__ corner_xy,
                                                  int32_t* __restrict__ disp,
                                                  uint32_t* __restrict__ ssd_out,
-                                                 uint8_t* __restrict__ flags) {
+                                                 uint8_t* __restrict__ flags,
+                                                 const int32_t* __restrict__ centre,
+                                                 const uint8_t* __restrict__ mode, int want) {
   extern __shared__ __align__(16) uint8_t dyn[];
   __shared__ uint8_t reg[kRegion * kRegion];
   __shared__ uint32_t qsum[4 * 49];
@@ -146,6 +148,9 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
 
   const int tid = threadIdx.x, nt = blockDim.x;
   const int tile = blockIdx.x;
+  // with a proposal, each tile is searched by the launch of its mode only
+  if (mode && mode[tile] != want) return;
+  const int cdx = centre ? centre[2 * tile] : 0, cdy = centre ? centre[2 * tile + 1] : 0;
   const int tx = tile % ntx, ty = tile / ntx;
   const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
   const int side = 2 * ext + 1;
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   }
   uint8_t* win = dyn;
   uint32_t* rowsq = reinterpret_cast<uint32_t*>(dyn + sh.NR * sh.wrow);
-  const int wx0 = px - P - R, wy0 = py - P - R;
+  const int wx0 = px + cdx - P - R, wy0 = py + cdy - P - R;
   stage_rows(wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
   __syncthreads();
   // patch energy and window row energies rowsq[y][k] = sum_c win[y][k + c]^2,
@@ -308,15 +313,16 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
     for (int k = 0; k < KX; ++k) {
       const int dxi = s * KX + k;
       if (dxi >= sh.ncand) continue;
-      const int dx = dxi - R, dy = j - R;
+      const int dx = dxi - R + cdx, dy = j - R + cdy;
       if (px + dx - P < 0 || px + dx + P > w - 1 || py + dy - P < 0 || py + dy + P > h - 1)
         continue;
       const uint32_t ssd = er + ew[k] - 2u * acc[k];
       const uint32_t l1 = (uint32_t)((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy));
+      // (ssd, |dx| + |dy|, dy, dx), displacements biased by 64 (|d| <= 64)
       const unsigned long long kk = ((unsigned long long)ssd << 32) |
                                     ((unsigned long long)l1 << 16) |
-                                    ((unsigned long long)(dy + R) << 8) |
-                                    (unsigned long long)(dx + R);
+                                    ((unsigned long long)(dy + 64) << 8) |
+                                    (unsigned long long)(dx + 64);
       key = kk < key ? kk : key;
     }
   }
@@ -333,12 +339,12 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       disp[2 * tile] = 0;
       disp[2 * tile + 1] = 0;
       ssd_out[tile] = 0;
-      flags[tile] = 1;
+      flags[tile] = (uint8_t)(1 | (mode && want ? 16 : 0));
     } else {
-      disp[2 * tile] = (int)(b & 255ull) - R;
-      disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - R;
+      disp[2 * tile] = (int)(b & 255ull) - 64;
+      disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - 64;
       ssd_out[tile] = (uint32_t)(b >> 32);
-      flags[tile] = 3;
+      flags[tile] = (uint8_t)(3 | (mode && want ? 16 : 0));
     }
   }
 }
@@ -354,7 +360,8 @@ hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, ui
 
 hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
-                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st) {
+                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st,
+                         const int32_t* centre, const uint8_t* mode, int want) {
   if (ntx * nty == 0) return hipSuccess;
   SearchShape sh;
   sh.R = R;
@@ -370,7 +377,7 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
   // (+ KX words: the last strip's padded candidates read past the last row)
   const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4;
   LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
-                     ntx, corner_xy, disp, ssd, flags);
+                     ntx, corner_xy, disp, ssd, flags, centre, mode, want);
   return hipGetLastError();
 }
 

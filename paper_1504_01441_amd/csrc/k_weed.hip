@@ -502,7 +502,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(
       if (t >= ntiles || !(tf[j] & 2)) continue;
       const bool inM = (mw[t >> 6] >> (t & 63)) & 1ull;
       const bool sel = (brow[j] >> (t & 63)) & 1ull;
-      flags[t] = (uint8_t)((tf[j] & 3) | (inM ? 4 : 0) | (sel ? 8 : 0));
+      flags[t] = (uint8_t)((tf[j] & 0x13) | (inM ? 4 : 0) | (sel ? 8 : 0));
       if (!sel) continue;
       const long long x = tpx[j] - ox, y = tpy[j] - oy, u = x + tdx[j], v = y + tdy[j];
       const long long xx = x * x, xy = x * y, yy = y * y, q = u * u + v * v;

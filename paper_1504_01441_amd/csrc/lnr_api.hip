@@ -5,6 +5,9 @@
 #include <string.h>
 
 #include <new>
+#include <algorithm>
+#include <cmath>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -72,6 +75,22 @@ struct lnr_ctx {
   size_t ws_size = 0;
   bool tracing = false;
   lnr::Tracer tracer;
+  // learned proposal: fp32 parameters, AdamW moments, packed bf16 weights
+  float* cnn = nullptr;        // [3][nparam]: params, m, v
+  uint16_t* cnn_packed = nullptr;
+  int cnn_step = 0;
+  // domain-transform kernel shapes picked by the autotuner, per (W, H)
+  std::map<std::pair<int, int>, lnr::DtShape> dt_shapes;
+  // batches: worker streams, fork / join events, cached executable graphs
+  std::vector<hipStream_t> workers;
+  std::vector<hipEvent_t> events;
+  hipStream_t capture = nullptr;
+  struct Cached {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Cached> graphs;
+  std::map<std::vector<uint64_t>, int> batch_k;  // autotuned concurrency per batch
 };
 
 namespace lnr {
@@ -125,6 +144,14 @@ lnr_status check_params(lnr_ctx* ctx, const lnr_params* p) {
   if (p->ssim_radius < 1 || p->ssim_radius > 8 || !(p->ssim_sigma > 0))
     return fail(ctx, LNR_E_UNSUPPORTED, "SSIM window out of range");
   if (!(p->sigma_e > 0)) return fail(ctx, LNR_E_UNSUPPORTED, "sigma_e must be > 0");
+  if (p->learned != 0 && p->learned != 1) return fail(ctx, LNR_E_UNSUPPORTED, "learned must be 0 or 1");
+  if (p->learned) {
+    if (p->tile != 32) return fail(ctx, LNR_E_UNSUPPORTED, "the learned proposal needs tile 32");
+    if (p->window_r < 0 || p->window_r > p->radius0)
+      return fail(ctx, LNR_E_UNSUPPORTED, "window_r must be in [0, radius0]");
+    if (!(p->conf_min > 0.0 && p->conf_min < 1.0))
+      return fail(ctx, LNR_E_UNSUPPORTED, "conf_min must be in (0, 1)");
+  }
   return LNR_OK;
 }
 
@@ -240,8 +267,15 @@ WeedBufs weed_bufs(char* base, const WeedPlan& w) {
   return b;
 }
 
-lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
-                              const lnr_params* p, lnr_registration* out, hipStream_t st) {
+// Workspace layout of one registration (offsets from the pair's base).
+struct PairPlan {
+  Geometry g;
+  size_t bytes, o_hist, o_pref, o_psrc, o_warp, o_maps, o_coef, o_cx, o_cc, o_cm;
+  WeedPlan wp;
+};
+
+lnr_status check_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                      const lnr_params* p, const lnr_registration* out) {
   lnr_status s;
   if ((s = check_params(ctx, p)) != LNR_OK) return s;
   if ((s = check_frame(ctx, ref, "ref")) != LNR_OK) return s;
@@ -249,32 +283,59 @@ lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
   if (!out) return fail(ctx, LNR_E_ARG, "out is null");
   if (ref->width != src->width || ref->height != src->height || ref->format != src->format)
     return fail(ctx, LNR_E_ARG, "ref and src differ in size or format");
-  const int W = ref->width, H = ref->height;
-  if (W < p->tile || H < p->tile) return fail(ctx, LNR_E_TOO_SMALL, "image smaller than one tile");
+  if (ref->width < p->tile || ref->height < p->tile)
+    return fail(ctx, LNR_E_TOO_SMALL, "image smaller than one tile");
   if (!out->corner_xy || !out->disp || !out->ssd || !out->flags || !out->counts || !out->H ||
       !out->yeq_ref || !out->flow || !out->image || !out->yeq_warped)
     return fail(ctx, LNR_E_ARG, "a required output pointer is null");
-  const Geometry g = make_geometry(W, H, *p);
+  if (p->learned && !ctx->cnn)
+    return fail(ctx, LNR_E_ARG, "learned proposal requested but no network set (lnr_proposal_set)");
+  return LNR_OK;
+}
+
+PairPlan plan_pair(int W, int H, const lnr_params* p) {
+  PairPlan q;
+  q.g = make_geometry(W, H, *p);
   const size_t N = (size_t)W * H;
   Plan pl;
-  const size_t o_hist = pl.take(2 * 256 * sizeof(uint32_t));
-  const size_t o_pref = pl.take(g.pyr_bytes);
-  const size_t o_psrc = pl.take(g.pyr_bytes);
-  const size_t o_warp = pl.take(N);
-  const WeedPlan wp = plan_weed(pl, g.lv[0].ntx * g.lv[0].nty, p->weed_iters);
-  const size_t o_maps = pl.take(3 * N * sizeof(float));
-  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
-  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
-  char* base = static_cast<char*>(ctx->ws);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(base + o_hist);
-  uint8_t* pref = reinterpret_cast<uint8_t*>(base + o_pref);
-  uint8_t* psrc = reinterpret_cast<uint8_t*>(base + o_psrc);
-  uint8_t* warped = reinterpret_cast<uint8_t*>(base + o_warp);
-  const WeedBufs wb = weed_bufs(base, wp);
-  float* maps = reinterpret_cast<float*>(base + o_maps);
-  double* coef = reinterpret_cast<double*>(base + o_coef);
+  q.o_hist = pl.take(2 * 256 * sizeof(uint32_t));
+  q.o_pref = pl.take(q.g.pyr_bytes);
+  q.o_psrc = pl.take(q.g.pyr_bytes);
+  q.o_warp = pl.take(N);
+  q.wp = plan_weed(pl, q.g.lv[0].ntx * q.g.lv[0].nty, p->weed_iters);
+  q.o_maps = pl.take(3 * N * sizeof(float));
+  q.o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
+  const size_t nt0 = (size_t)q.g.lv[0].ntx * q.g.lv[0].nty;
+  q.o_cx = p->learned ? pl.take(nt0 * 512 * sizeof(uint16_t)) : 0;
+  q.o_cc = p->learned ? pl.take(nt0 * 2 * sizeof(int32_t)) : 0;
+  q.o_cm = p->learned ? pl.take(nt0) : 0;
+  q.bytes = pl.off;
+  return q;
+}
 
-  LNR_HIP(hipMemsetAsync(hist, 0, 2 * 256 * sizeof(uint32_t), st));
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Enqueue one registration on `st` using the workspace at `base` (checked and
+// sized by the caller). Launches only: safe under stream capture.
+lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                        const lnr_params* p, lnr_registration* out, const PairPlan& q,
+                        char* base, hipStream_t st) {
+  const Geometry& g = q.g;
+  const int W = ref->width, H = ref->height;
+  const size_t N = (size_t)W * H;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + q.o_hist);
+  uint8_t* pref = reinterpret_cast<uint8_t*>(base + q.o_pref);
+  uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
+  uint8_t* warped = reinterpret_cast<uint8_t*>(base + q.o_warp);
+  const WeedBufs wb = weed_bufs(base, q.wp);
+  float* maps = reinterpret_cast<float*>(base + q.o_maps);
+  double* coef = reinterpret_cast<double*>(base + q.o_coef);
+
+  LNR_LAUNCH(k_zero_u32, dim3(2), dim3(256), 0, st, hist, 512);
+  LNR_HIP(hipGetLastError());
   LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
   LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
                          pref, psrc, nullptr, 2, st));
@@ -288,22 +349,50 @@ lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
     const int R = l == 0 ? p->radius0 : p->radius_coarse;
     const int nt = L.ntx * L.nty;
     LNR_HIP(launch_warp_q8(psrc + L.pix_off, L.w, L.h, out->H + 9 * (l + 1), warped, st));
-    LNR_HIP(launch_search(pref + L.pix_off, warped, L.w, L.h, R, cfg, L.ntx, L.nty,
-                          out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
-                          out->ssd + L.tile_off, out->flags + L.tile_off, st));
+    if (l == 0 && p->learned) {
+      // the network proposes a window per tile; confident tiles scan it,
+      // the others fall back to the exhaustive search (flag 16)
+      uint16_t* x = reinterpret_cast<uint16_t*>(base + q.o_cx);
+      int32_t* centre = reinterpret_cast<int32_t*>(base + q.o_cc);
+      uint8_t* mode = reinterpret_cast<uint8_t*>(base + q.o_cm);
+      const float logit = (float)std::log(p->conf_min / (1.0 - p->conf_min));
+      LNR_HIP(launch_cnn_input(pref, warped, W, L.ntx, L.nty, x, st));
+      LNR_HIP(launch_cnn_forward(ctx->cnn_packed, ctx->cnn, x, nt, nullptr, nullptr, centre, mode,
+                                 p->radius0 - p->window_r, logit, st));
+      LNR_HIP(launch_search(pref, warped, L.w, L.h, p->window_r, cfg, L.ntx, L.nty,
+                            out->corner_xy, out->disp, out->ssd, out->flags, st, centre, mode, 0));
+      LNR_HIP(launch_search(pref, warped, L.w, L.h, R, cfg, L.ntx, L.nty, out->corner_xy,
+                            out->disp, out->ssd, out->flags, st, nullptr, mode, 1));
+    } else {
+      LNR_HIP(launch_search(pref + L.pix_off, warped, L.w, L.h, R, cfg, L.ntx, L.nty,
+                            out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
+                            out->ssd + L.tile_off, out->flags + L.tile_off, st));
+    }
     LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
                             out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
                             out->H + 9 * l, out->counts + 4 * l, wb, st));
     if (l == 0 && out->warped0)
       LNR_HIP(hipMemcpyAsync(out->warped0, warped, N, hipMemcpyDeviceToDevice, st));
   }
+  const DtShape* ds = nullptr;
+  auto it = ctx->dt_shapes.find(std::make_pair(W, H));
+  if (it != ctx->dt_shapes.end()) ds = &it->second;
   LNR_HIP(launch_flow(out->corner_xy, out->disp, out->flags, g.lv[0].ntx, g.lv[0].nty, p->tile,
-                      pref, W, H, *p, maps, coef, out->flow, out->ntilde, st));
+                      pref, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds));
   LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], src->format == LNR_I420 ? src->plane[1] : nullptr,
                                src->stride[1], src->format == LNR_I420 ? src->plane[2] : nullptr,
                                src->stride[2], psrc, W, H, out->H + 9, out->flow, out->image,
                                out->yeq_warped, st));
   return LNR_OK;
+}
+
+lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                              const lnr_params* p, lnr_registration* out, hipStream_t st) {
+  lnr_status s;
+  if ((s = check_pair(ctx, ref, src, p, out)) != LNR_OK) return s;
+  const PairPlan q = plan_pair(ref->width, ref->height, p);
+  if ((s = ensure_ws(ctx, q.bytes)) != LNR_OK) return s;
+  return enqueue_pair(ctx, ref, src, p, out, q, static_cast<char*>(ctx->ws), st);
 }
 
 lnr_status merge_impl(lnr_ctx* ctx, int n, int ch, int W, int H, const float* const* imgs,
@@ -351,13 +440,19 @@ lnr_status lnr_create(lnr_ctx** ctx, int32_t device) {
 
 void lnr_destroy(lnr_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->ws) {
-    int prev = 0;
-    const bool have_prev = hipGetDevice(&prev) == hipSuccess;
-    if (hipSetDevice(ctx->device) == hipSuccess && hipFree(ctx->ws) != hipSuccess)
-      ctx->err = "hipFree(workspace) failed";
-    if (have_prev && hipSetDevice(prev) != hipSuccess) ctx->err = "hipSetDevice(restore) failed";
+  int prev = 0;
+  const bool have_prev = hipGetDevice(&prev) == hipSuccess;
+  if (hipSetDevice(ctx->device) == hipSuccess) {
+    if (ctx->ws && hipFree(ctx->ws) != hipSuccess) ctx->err = "hipFree(workspace) failed";
+    if (ctx->cnn && hipFree(ctx->cnn) != hipSuccess) ctx->err = "hipFree(network) failed";
+    if (ctx->cnn_packed && hipFree(ctx->cnn_packed) != hipSuccess)
+      ctx->err = "hipFree(network) failed";
+    for (auto& c : ctx->graphs) (void)hipGraphExecDestroy(c.exec);
+    for (hipStream_t w : ctx->workers) (void)hipStreamDestroy(w);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   }
+  if (have_prev && hipSetDevice(prev) != hipSuccess) ctx->err = "hipSetDevice(restore) failed";
   delete ctx;
 }
 
@@ -390,6 +485,9 @@ void lnr_default_params(lnr_params* p) {
   p->ssim_c2 = 0.03 * 0.03;
   p->sigma_e = 0.2;
   p->seed = 0x1504014410ull;
+  p->learned = 0;
+  p->window_r = 2;
+  p->conf_min = 0.5;
 }
 
 lnr_status lnr_query_sizes(int32_t width, int32_t height, int32_t format, const lnr_params* p,
@@ -632,6 +730,362 @@ lnr_status lnr_stage_merge(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   return merge_impl(ctx, n, ch, w, h, imgs, yeqs, ref_index, p, out, (hipStream_t)stream, 0,
                     nullptr);
+}
+
+// ---------------------------------------------------------------- batches
+}  // extern "C"
+
+namespace {
+
+lnr_status ensure_workers(lnr_ctx* ctx, int K) {
+  while ((int)ctx->workers.size() < K) {
+    hipStream_t w = nullptr;
+    LNR_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+    ctx->workers.push_back(w);
+  }
+  while ((int)ctx->events.size() < K + 1) {
+    hipEvent_t e = nullptr;
+    LNR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->events.push_back(e);
+  }
+  if (!ctx->capture) LNR_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+  return LNR_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Longest-processing-time assignment of pairs (by pixel count) to K streams.
+std::vector<std::vector<int>> assign_pairs(const lnr_frame* refs, int n, int K) {
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    const long long na = (long long)refs[a].width * refs[a].height;
+    const long long nb = (long long)refs[b].width * refs[b].height;
+    return na != nb ? na > nb : a < b;
+  });
+  std::vector<std::vector<int>> lists(K);
+  std::vector<long long> load(K, 0);
+  for (int i : order) {
+    int k = 0;
+    for (int j = 1; j < K; ++j)
+      if (load[j] < load[k]) k = j;
+    lists[k].push_back(i);
+    load[k] += (long long)refs[i].width * refs[i].height;
+  }
+  return lists;
+}
+
+// Fork from `origin` to K worker streams, each registering its pairs in its
+// own workspace slot, and join back to `origin`.
+lnr_status enqueue_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_frame* srcs, int n,
+                         const lnr_params* p, lnr_registration* outs,
+                         const std::vector<PairPlan>& plans, size_t slot, int K,
+                         hipStream_t origin) {
+  const auto lists = assign_pairs(refs, n, K);
+  LNR_HIP(hipEventRecord(ctx->events[K], origin));
+  for (int k = 0; k < K; ++k) {
+    LNR_HIP(hipStreamWaitEvent(ctx->workers[k], ctx->events[K], 0));
+    char* base = static_cast<char*>(ctx->ws) + (size_t)k * slot;
+    for (int i : lists[k]) {
+      lnr_status s = enqueue_pair(ctx, &refs[i], &srcs[i], p, &outs[i], plans[i], base,
+                                  ctx->workers[k]);
+      if (s != LNR_OK) return s;
+    }
+    LNR_HIP(hipEventRecord(ctx->events[k], ctx->workers[k]));
+    LNR_HIP(hipStreamWaitEvent(origin, ctx->events[k], 0));
+  }
+  return LNR_OK;
+}
+
+void push_bytes(std::vector<uint64_t>& key, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; i += 8) {
+    uint64_t v = 0;
+    memcpy(&v, c + i, n - i < 8 ? n - i : 8);
+    key.push_back(v);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_frame* srcs,
+                              int32_t n, const lnr_params* p, lnr_registration* outs,
+                              int32_t flags, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  if (!refs || !srcs || !outs || n < 1 || n > 4096)
+    return fail(ctx, LNR_E_ARG, "register_batch needs 1..4096 pairs and their outputs");
+  if (flags & ~(LNR_BATCH_GRAPH | LNR_BATCH_AUTOTUNE))
+    return fail(ctx, LNR_E_ARG, "unknown batch flags");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  lnr_status s;
+  std::vector<PairPlan> plans((size_t)n);
+  size_t slot = 0;
+  for (int i = 0; i < n; ++i) {
+    if ((s = check_pair(ctx, &refs[i], &srcs[i], p, &outs[i])) != LNR_OK) return s;
+    plans[i] = plan_pair(refs[i].width, refs[i].height, p);
+    slot = std::max(slot, round256(plans[i].bytes));
+  }
+  const hipStream_t st = (hipStream_t)stream;
+  // the batch's shape: sizes and parameters (concurrency is tuned per shape)
+  std::vector<uint64_t> shape;
+  push_bytes(shape, p, sizeof(*p));
+  for (int i = 0; i < n; ++i)
+    shape.push_back(((uint64_t)refs[i].width << 32) | (uint32_t)refs[i].height);
+  int K = n < 4 ? n : 4;
+  auto kt = ctx->batch_k.find(shape);
+  if (kt != ctx->batch_k.end()) {
+    K = kt->second;
+  } else if (flags & LNR_BATCH_AUTOTUNE) {
+    // time 1, 2, 4 and 8 concurrent streams on this batch (eager), keep the fastest
+    const int cand[4] = {1, 2, 4, 8};
+    float best = 0.f;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    LNR_HIP(hipEventCreate(&t0));
+    LNR_HIP(hipEventCreate(&t1));
+    for (int c = 0; c < 4; ++c) {
+      const int k = cand[c];
+      if (k > n) break;
+      if ((s = ensure_ws(ctx, (size_t)k * slot)) != LNR_OK) return s;
+      if ((s = ensure_workers(ctx, k)) != LNR_OK) return s;
+      TraceGuard tg(ctx);
+      LNR_HIP(hipEventRecord(t0, st));
+      if ((s = enqueue_batch(ctx, refs, srcs, n, p, outs, plans, slot, k, st)) != LNR_OK) return s;
+      LNR_HIP(hipEventRecord(t1, st));
+      LNR_HIP(hipEventSynchronize(t1));
+      float ms = 0.f;
+      LNR_HIP(hipEventElapsedTime(&ms, t0, t1));
+      if (c == 0 || ms < best) { best = ms; K = k; }
+    }
+    LNR_HIP(hipEventDestroy(t0));
+    LNR_HIP(hipEventDestroy(t1));
+    ctx->batch_k[shape] = K;
+  }
+  if ((s = ensure_ws(ctx, (size_t)K * slot)) != LNR_OK) return s;
+  if ((s = ensure_workers(ctx, K)) != LNR_OK) return s;
+  if (!(flags & LNR_BATCH_GRAPH)) {
+    TraceGuard tg(ctx);
+    return enqueue_batch(ctx, refs, srcs, n, p, outs, plans, slot, K, st);
+  }
+  // graph: the whole batch as one executable graph, cached per inputs and outputs
+  std::vector<uint64_t> key = shape;
+  key.push_back((uint64_t)K);
+  key.push_back((uint64_t)(uintptr_t)ctx->ws);
+  for (int i = 0; i < n; ++i) {
+    push_bytes(key, &refs[i], sizeof(lnr_frame));
+    push_bytes(key, &srcs[i], sizeof(lnr_frame));
+    push_bytes(key, &outs[i], sizeof(lnr_registration));
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto& c : ctx->graphs)
+    if (c.key == key) exec = c.exec;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    LNR_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    s = enqueue_batch(ctx, refs, srcs, n, p, outs, plans, slot, K, ctx->capture);
+    const hipError_t ec = hipStreamEndCapture(ctx->capture, &graph);
+    if (s != LNR_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (ec != hipSuccess) return hip_fail(ctx, ec, "hipStreamEndCapture");
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(ctx, ei, "hipGraphInstantiate");
+    if (ctx->graphs.size() >= 8) {
+      LNR_HIP(hipGraphExecDestroy(ctx->graphs.front().exec));
+      ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(lnr_ctx::Cached{key, exec});
+  }
+  LNR_HIP(hipGraphLaunch(exec, st));
+  return LNR_OK;
+}
+
+lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
+                             int32_t* shape_out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (w < p->tile || h < p->tile || w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad image size");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t N = (size_t)w * h;
+  const int ntx = w / p->tile, nty = h / p->tile, nt = ntx * nty;
+  Plan pl;
+  const size_t o_g = pl.take(N), o_maps = pl.take(3 * N * sizeof(float));
+  const size_t o_flow = pl.take(2 * N * sizeof(float)), o_nt = pl.take(N * sizeof(float));
+  const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
+  const size_t o_cxy = pl.take((size_t)nt * 2 * sizeof(int32_t));
+  const size_t o_d = pl.take((size_t)nt * 2 * sizeof(int32_t)), o_f = pl.take((size_t)nt);
+  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  char* b = static_cast<char*>(ctx->ws);
+  // the kernels' work does not depend on the values: a flat guide and no
+  // matches time them exactly
+  LNR_HIP(hipMemsetAsync(b, 0, pl.off, st));
+  DtShape cand[64];
+  const int nc = dt_shape_candidates(w, h, cand, 64);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  LNR_HIP(hipEventCreate(&t0));
+  LNR_HIP(hipEventCreate(&t1));
+  DtShape best = dt_default_shape(w, h);
+  float best_ms = 0.f;
+  for (int c = 0; c < nc; ++c) {
+    float tot = 0.f;
+    for (int rep = 0; rep < 4; ++rep) {  // the first run warms up
+      LNR_HIP(hipEventRecord(t0, st));
+      LNR_HIP(launch_flow(reinterpret_cast<int32_t*>(b + o_cxy), reinterpret_cast<int32_t*>(b + o_d),
+                          reinterpret_cast<uint8_t*>(b + o_f), ntx, nty, p->tile,
+                          reinterpret_cast<uint8_t*>(b + o_g), w, h, *p,
+                          reinterpret_cast<float*>(b + o_maps), reinterpret_cast<double*>(b + o_coef),
+                          reinterpret_cast<float*>(b + o_flow), reinterpret_cast<float*>(b + o_nt),
+                          st, &cand[c]));
+      LNR_HIP(hipEventRecord(t1, st));
+      LNR_HIP(hipEventSynchronize(t1));
+      float ms = 0.f;
+      LNR_HIP(hipEventElapsedTime(&ms, t0, t1));
+      if (rep) tot += ms;
+    }
+    if (c == 0 || tot < best_ms) { best_ms = tot; best = cand[c]; }
+  }
+  LNR_HIP(hipEventDestroy(t0));
+  LNR_HIP(hipEventDestroy(t1));
+  ctx->dt_shapes[std::make_pair((int)w, (int)h)] = best;
+  if (shape_out) {
+    shape_out[0] = best.seg; shape_out[1] = best.nt; shape_out[2] = best.l;
+    shape_out[3] = best.ncol; shape_out[4] = best.nseg;
+  }
+  return LNR_OK;
+}
+
+lnr_status lnr_stage_search_window(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,
+                                   int32_t w, int32_t h, int32_t R, const int32_t* centre,
+                                   const lnr_params* p, int32_t* corner_xy, int32_t* disp,
+                                   uint32_t* ssd, uint8_t* flags, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (!ref || !warped || !centre || !corner_xy || !disp || !ssd || !flags || w < 1 || h < 1 ||
+      w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad search arguments");
+  if (R < 0 || R > kMaxRadius) return fail(ctx, LNR_E_UNSUPPORTED, "radius must be in [0, 32]");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  // the kernel clamps nothing: centres are checked on the host side of the
+  // caller's contract (|centre| + R <= 32) by reading them back here
+  const int nt = (w / p->tile) * (h / p->tile);
+  if (nt > 0) {
+    std::vector<int32_t> c((size_t)nt * 2);
+    LNR_HIP(hipMemcpyAsync(c.data(), centre, c.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           (hipStream_t)stream));
+    LNR_HIP(hipStreamSynchronize((hipStream_t)stream));
+    for (int32_t v : c)
+      if (v < -kMaxRadius || v > kMaxRadius || std::abs(v) + R > kMaxRadius)
+        return fail(ctx, LNR_E_ARG, "window centre out of range (|centre| + R must be <= 32)");
+  }
+  LNR_HIP(launch_search(ref, warped, w, h, R, search_cfg(*p), w / p->tile, h / p->tile,
+                        corner_xy, disp, ssd, flags, (hipStream_t)stream, centre, nullptr, 0));
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_set(lnr_ctx* ctx, const float* params, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!params) return fail(ctx, LNR_E_ARG, "params is null");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const size_t np = (size_t)cnn_param_count();
+  if (!ctx->cnn) {
+    hipError_t e = hipMalloc(&ctx->cnn, 3 * np * sizeof(float));
+    if (e != hipSuccess) { ctx->cnn = nullptr; return fail(ctx, LNR_E_NOMEM, "network hipMalloc failed"); }
+    e = hipMalloc(&ctx->cnn_packed, cnn_packed_elems() * sizeof(uint16_t));
+    if (e != hipSuccess) {
+      ctx->cnn_packed = nullptr;
+      LNR_HIP(hipFree(ctx->cnn));
+      ctx->cnn = nullptr;
+      return fail(ctx, LNR_E_NOMEM, "network hipMalloc failed");
+    }
+  }
+  const hipStream_t st = (hipStream_t)stream;
+  LNR_HIP(hipMemcpyAsync(ctx->cnn, params, np * sizeof(float), hipMemcpyDeviceToDevice, st));
+  LNR_HIP(hipMemsetAsync(ctx->cnn + np, 0, 2 * np * sizeof(float), st));
+  LNR_HIP(launch_cnn_pack(ctx->cnn, ctx->cnn_packed, st));
+  ctx->cnn_step = 0;
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_get(lnr_ctx* ctx, float* params, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!params) return fail(ctx, LNR_E_ARG, "params is null");
+  if (!ctx->cnn) return fail(ctx, LNR_E_ARG, "no network set");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  LNR_HIP(hipMemcpyAsync(params, ctx->cnn, (size_t)cnn_param_count() * sizeof(float),
+                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_inputs(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,
+                               int32_t w, int32_t h, uint16_t* x, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!ref || !warped || !x || w < 32 || h < 32 || w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad proposal input arguments");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  LNR_HIP(launch_cnn_input(ref, warped, w, w / 32, h / 32, x, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_forward(lnr_ctx* ctx, const uint16_t* x, int32_t n, float* out,
+                                void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!x || !out || n < 0) return fail(ctx, LNR_E_ARG, "bad proposal forward arguments");
+  if (!ctx->cnn) return fail(ctx, LNR_E_ARG, "no network set");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  LNR_HIP(launch_cnn_forward(ctx->cnn_packed, ctx->cnn, x, n, out, nullptr, nullptr, nullptr, 0,
+                             0.f, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_train_step(lnr_ctx* ctx, const uint16_t* x, const int32_t* labels,
+                                   int32_t n, float lr, float wd, float* loss, float* grad,
+                                   void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!x || !labels || n < 1) return fail(ctx, LNR_E_ARG, "bad training arguments");
+  if (!(lr >= 0.f) || !(wd >= 0.f)) return fail(ctx, LNR_E_ARG, "lr and wd must be >= 0");
+  if (!ctx->cnn) return fail(ctx, LNR_E_ARG, "no network set");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const hipStream_t st = (hipStream_t)stream;
+  int pb = 0;
+  const int nb = cnn_grad_blocks(n, &pb);
+  const size_t np = (size_t)cnn_param_count();
+  Plan pl;
+  const size_t o_act = pl.take((size_t)n * cnn_act_elems() * sizeof(uint16_t));
+  const size_t o_dz = pl.take((size_t)n * cnn_dz_elems() * sizeof(uint16_t));
+  const size_t o_out = pl.take((size_t)n * 3 * sizeof(float));
+  const size_t o_dO = pl.take((size_t)n * 3 * sizeof(float));
+  const size_t o_part = pl.take((size_t)nb * np * sizeof(float));
+  lnr_status s;
+  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  char* base = static_cast<char*>(ctx->ws);
+  uint16_t* acts = reinterpret_cast<uint16_t*>(base + o_act);
+  uint16_t* dzs = reinterpret_cast<uint16_t*>(base + o_dz);
+  float* out = reinterpret_cast<float*>(base + o_out);
+  float* dO = reinterpret_cast<float*>(base + o_dO);
+  float* part = reinterpret_cast<float*>(base + o_part);
+  LNR_HIP(launch_cnn_forward(ctx->cnn_packed, ctx->cnn, x, n, out, acts, nullptr, nullptr, 0,
+                             0.f, st));
+  LNR_HIP(launch_cnn_backward(ctx->cnn_packed, ctx->cnn, acts, out, labels, n, dO, loss, dzs,
+                              part, st));
+  const bool update = lr != 0.f || wd != 0.f;
+  if (update) ++ctx->cnn_step;
+  LNR_HIP(launch_cnn_adamw(part, nb, ctx->cnn, ctx->cnn + np, ctx->cnn + 2 * np, lr, wd,
+                           update ? ctx->cnn_step : 1, grad, st));
+  if (update) LNR_HIP(launch_cnn_pack(ctx->cnn, ctx->cnn_packed, st));
+  return LNR_OK;
 }
 
 lnr_status lnr_trace_enable(lnr_ctx* ctx, int32_t on) {

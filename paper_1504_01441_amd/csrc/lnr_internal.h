@@ -61,7 +61,8 @@ hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, ui
                           hipStream_t st);
 hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
-                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st);
+                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st, const int32_t* centre = nullptr,
+                         const uint8_t* mode = nullptr, int want = 0);
 
 // ---- weeding + level homography (k_weed.hip)
 struct WeedBufs {
@@ -76,10 +77,20 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
                            const WeedBufs& b, hipStream_t st);
 
 // ---- domain-transform propagation (k_dt.hip)
+// Kernel shapes: rows of SEG pixels per thread in NT-thread blocks; columns as
+// NCOL columns x NSEG segments of L rows per block. Only the instantiated
+// combinations are valid (dt_shape_valid).
+struct DtShape {
+  int seg, nt;         // row kernel
+  int l, ncol, nseg;   // column kernel
+};
+DtShape dt_default_shape(int W, int H);
+bool dt_shape_valid(const DtShape& s, int W, int H);
+int dt_shape_candidates(int W, int H, DtShape* out, int max);
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
                        int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
                        const lnr_params& p, float* maps /*[3][H][W]*/, double* coef /*[iters][256]*/,
-                       float* flow, float* ntilde, hipStream_t st);
+                       float* flow, float* ntilde, hipStream_t st, const DtShape* shape = nullptr);
 
 // ---- backward warp (k_warp.hip)
 hipError_t launch_backward_warp(const uint8_t* y, int sy, const uint8_t* u, int su,
@@ -103,5 +114,24 @@ int merge_levels(int W, int H);
 hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
                         const float* const* yeqs, int ref_index, const lnr_params& p,
                         const MergeBufs& b, float* out, hipStream_t st);
+
+// ---- learned displacement proposal (k_cnn.hip)
+int cnn_param_count();
+size_t cnn_packed_elems();   // bf16 packed weights
+size_t cnn_act_elems();      // stored activations per sample (bf16)
+size_t cnn_dz_elems();       // activation gradients per sample (bf16)
+int cnn_grad_blocks(int n, int* per_block);
+hipError_t launch_cnn_pack(const float* params, uint16_t* packed, hipStream_t st);
+hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, int ntx, int nty,
+                            uint16_t* x, hipStream_t st);
+hipError_t launch_cnn_forward(const uint16_t* packed, const float* params, const uint16_t* x,
+                              int n, float* out, uint16_t* acts, int32_t* centre,
+                              uint8_t* fallback, int clampc, float conf_logit, hipStream_t st);
+hipError_t launch_cnn_backward(const uint16_t* packed, const float* params,
+                               const uint16_t* acts, const float* out, const int32_t* labels,
+                               int n, float* dO, float* loss, uint16_t* dzs, float* part,
+                               hipStream_t st);
+hipError_t launch_cnn_adamw(const float* part, int nblk, float* params, float* m, float* v,
+                            float lr, float wd, int step, float* grad_out, hipStream_t st);
 
 }  // namespace lnr

@@ -16,3 +16,4 @@ from .scenes import (  # noqa: F401
     make_texture,
     CONFIGS,
 )
+from .proposal import proposal_params, N_PARAMS  # noqa: F401

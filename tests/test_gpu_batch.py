@@ -1,0 +1,108 @@
+"""Batches of uneven-size pairs (streams, cached HIP graphs, autotuning) give
+exactly what one register_pair call per pair gives, and register_pair stays
+within the oracle's tolerance after the domain-transform kernel shapes are
+autotuned."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import registration_parity
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(640, 480), (354, 258), (512, 400), (290, 226), (800, 600), (418, 330)]
+
+
+@pytest.fixture(scope="module")
+def lnr():
+    import paper_1504_01441_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(lnr):
+    return lnr.Context(0)
+
+
+def _pairs(lnr, seed0):
+    out = []
+    for i, (w, h) in enumerate(SIZES):
+        st = synth.make_stack(w, h, seed0 + i, ratios=(1.0, 2.0 + 2 * i), fmt="i420",
+                              shift_range=12)
+        f0, f1 = st.frames
+        out.append((f0, f1, lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure),
+                    lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)))
+    return out
+
+
+FIELDS = ("corner_xy", "disp", "ssd", "flags", "counts", "H", "yeq_ref", "yeq_src", "warped0",
+          "flow", "ntilde", "image", "yeq_warped")
+
+
+def _same(a, b):
+    for f in FIELDS:
+        x, y = getattr(a, f), getattr(b, f)
+        assert torch.equal(x, y), f
+
+
+@pytest.mark.parametrize("graph,autotune", [(False, False), (True, False), (True, True)])
+def test_batch_equals_single_calls(lnr, ctx, graph, autotune):
+    p = lnr.Params(radius0=12, min_level_dim=64)
+    pairs = _pairs(lnr, 700)
+    singles = [lnr.register_pair(ctx, r, s, p) for _, _, r, s in pairs]
+    outs = lnr.register_batch(ctx, [q[2] for q in pairs], [q[3] for q in pairs], p,
+                              graph=graph, autotune=autotune)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, singles):
+        _same(a, b)
+    if graph:
+        # replays of the cached graph, with other work and new contents in between
+        for rep in range(3):
+            for o in outs:
+                o.flow.zero_()
+                o.flags.fill_(255)
+            singles[0].image.add_(1.0)
+            lnr.register_batch(ctx, [q[2] for q in pairs], [q[3] for q in pairs], p, outs=outs,
+                               graph=True, autotune=autotune)
+            torch.cuda.synchronize()
+            for a, b in zip(outs[1:], singles[1:]):
+                _same(a, b)
+            assert torch.equal(outs[0].flow, singles[0].flow)
+            assert torch.equal(outs[0].flags, singles[0].flags)
+
+
+def test_batch_matches_oracle(lnr, ctx):
+    p = lnr.Params(radius0=12, min_level_dim=64)
+    op = oracle.params(radius0=12, min_level_dim=64)
+    pairs = _pairs(lnr, 720)[:3]
+    outs = lnr.register_batch(ctx, [q[2] for q in pairs], [q[3] for q in pairs], p, graph=True)
+    torch.cuda.synchronize()
+    for (f0, f1, _, _), reg in zip(pairs, outs):
+        registration_parity(reg, oracle.register_pair(f0, f1, op))
+
+
+@pytest.mark.parametrize("w,h", [(640, 480), (1296, 972)])
+def test_autotuned_flow_shape_keeps_parity(lnr, ctx, w, h):
+    p = lnr.Params(radius0=12, min_level_dim=64)
+    shape = lnr.autotune_flow(ctx, w, h, p)
+    assert shape[0] * shape[1] >= w and shape[2] * shape[4] >= h
+    st = synth.make_stack(w, h, 730, ratios=(1.0, 4.0), fmt="i420", shift_range=8)
+    f0, f1 = st.frames
+    reg = lnr.register_pair(ctx, lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure),
+                            lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure), p)
+    torch.cuda.synchronize()
+    registration_parity(reg, oracle.register_pair(f0, f1, oracle.params(radius0=12,
+                                                                        min_level_dim=64)))
+
+
+def test_batch_rejects_bad_flags(lnr, ctx):
+    import ctypes as C
+    ref = _pairs(lnr, 740)[0][2]
+    RA = (lnr._Frame * 1)(ref._c())
+    out = lnr.Registration.alloc(ref.width, ref.height, lnr.LNR_I420, lnr.Params())
+    OA = (lnr._Registration * 1)(out._c())
+    rc = lnr.lib().lnr_register_batch(ctx._h, RA, RA, 1, C.byref(lnr.Params()), OA, 8,
+                                      lnr._stream())
+    assert rc == -1

@@ -1,0 +1,202 @@
+"""GPU parity of the learned displacement proposal (an extension beyond the
+paper that narrows the Sec. 2.2 search) against the oracle in
+oracle/proposal_oracle.c, through the C ABI.
+
+Tolerances. The kernels multiply bf16 operands exactly and accumulate in
+fp32; the oracle accumulates the same bf16 values in fp64 and rounds the
+activations (and the back-propagated activation gradients) to bf16 at the
+same points. Differences come from fp32 summation (relative ~1e-6) and from
+the rare activations whose fp32 and fp64 sums round to neighbouring bf16
+values (one bf16 step, 2^-8 relative). Outputs are checked to 1e-2 relative
+(about 2.5 bf16 steps) with a median far below; gradients per tensor to 2 %
+of the tensor's norm (weight gradients sum many nearly cancelling terms, so
+a flipped activation shows up enlarged) with cosine similarity > 0.999."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lnr():
+    import paper_1504_01441_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(lnr):
+    return lnr.Context(0)
+
+
+def _bf16_bits(a):
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).view(torch.int16)
+
+
+def _inputs(seed, n):
+    rng = np.random.default_rng(seed)
+    return oracle.bf16(rng.uniform(-1, 1, (n, 2, 16, 16)))
+
+
+def _offsets():
+    cin = [2, 32, 32, 32]
+    off, o = [], 0
+    for l in range(4):
+        off.append((f"W{l + 1}", o, 32 * cin[l] * 9))
+        o += 32 * cin[l] * 9
+        off.append((f"b{l + 1}", o, 32))
+        o += 32
+    off += [("Wh", o, 1536), ("bh", o + 1536, 3)]
+    return off
+
+
+def test_inputs_bit_exact(lnr, ctx):
+    rng = np.random.default_rng(1)
+    ref = rng.integers(0, 256, (100, 136), np.uint8)   # 4 x 3 tiles, ragged edges
+    wrp = rng.integers(0, 256, (100, 136), np.uint8)
+    x = lnr.proposal_inputs(ctx, torch.from_numpy(ref).cuda(), torch.from_numpy(wrp).cuda())
+    want = oracle.cnn_tile_inputs(ref, wrp, range(12))
+    got = x.view(torch.bfloat16).float().cpu().numpy()
+    assert got.shape == (12, 2, 16, 16)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("seed,n", [(2, 1), (3, 7), (4, 300)])
+def test_forward_parity(lnr, ctx, seed, n):
+    P = synth.proposal_params(seed, head_scale=4.0)
+    lnr.proposal_set(ctx, torch.from_numpy(P))
+    x = _inputs(seed + 50, n)
+    got = lnr.proposal_forward(ctx, _bf16_bits(x).cuda()).cpu().numpy().astype(np.float64)
+    want = oracle.cnn_forward(P.astype(np.float64), x, rnd=True)
+    err = np.abs(got - want) / (1.0 + np.abs(want))
+    assert err.max() <= 1e-2, err.max()
+    assert np.median(err) <= 1e-4, np.median(err)
+
+
+@pytest.mark.parametrize("seed,n", [(5, 3), (6, 130)])
+def test_gradient_parity(lnr, ctx, seed, n):
+    P = synth.proposal_params(seed, head_scale=4.0)
+    lnr.proposal_set(ctx, torch.from_numpy(P))
+    x = _inputs(seed + 60, n)
+    lab = np.random.default_rng(seed + 70).integers(-10, 11, (n, 2)).astype(np.int32)
+    loss, grad = lnr.proposal_train_step(ctx, _bf16_bits(x).cuda(), torch.from_numpy(lab).cuda(),
+                                         0.0, 0.0, want_grad=True)
+    g = grad.cpu().numpy().astype(np.float64)
+    l_o, g_o = oracle.cnn_loss_grad(P.astype(np.float64), x, lab, rnd=True)
+    assert abs(float(loss.double().mean()) - l_o) <= 1e-3 * (1 + abs(l_o))
+    for name, o, k in _offsets():
+        a, b = g[o:o + k], g_o[o:o + k]
+        nb = np.linalg.norm(b)
+        assert np.linalg.norm(a - b) <= 2e-2 * nb + 1e-7, (name, np.linalg.norm(a - b) / nb)
+        assert a @ b >= 0.999 * np.linalg.norm(a) * nb, name
+    # a gradient-only step leaves the parameters unchanged
+    assert np.array_equal(lnr.proposal_get(ctx).cpu().numpy(), P)
+
+
+def test_adamw_first_step(lnr, ctx):
+    P = synth.proposal_params(7, head_scale=4.0)
+    lnr.proposal_set(ctx, torch.from_numpy(P))
+    x = _inputs(8, 64)
+    lab = np.random.default_rng(9).integers(-10, 11, (64, 2)).astype(np.int32)
+    lr = 1e-3
+    lnr.proposal_train_step(ctx, _bf16_bits(x).cuda(), torch.from_numpy(lab).cuda(), lr, 0.0)
+    got = lnr.proposal_get(ctx).cpu().numpy().astype(np.float64)
+    _, g_o = oracle.cnn_loss_grad(P.astype(np.float64), x, lab, rnd=True)
+    w = P.astype(np.float64).copy()
+    oracle.adamw(w, np.zeros_like(w), np.zeros_like(w), g_o, 1, lr)
+    # the first step is lr * sign(g) wherever the gradient is clearly nonzero
+    big = np.abs(g_o) > 1e-3 * np.abs(g_o).max()
+    assert big.sum() > 10000
+    assert np.allclose(got[big], w[big], rtol=0, atol=2e-6)
+    assert np.all(np.abs(got - P) <= lr * 1.0001 + 1e-7)
+
+
+@pytest.mark.parametrize("R", [0, 2, 5])
+def test_window_search_bit_exact(lnr, ctx, R):
+    ref, wimg, _, _ = synth.make_planted_shift_pair(288, 224, 21 + R, 8)
+    p = lnr.Params(radius0=16)
+    op = oracle.params(radius0=16)
+    cx, cy, has = oracle.corners(ref, op)
+    nt = len(cx)
+    rng = np.random.default_rng(30 + R)
+    centre = rng.integers(-(16 - R), 16 - R + 1, (nt, 2)).astype(np.int32)
+    got = lnr.stage_search_window(ctx, torch.from_numpy(ref).cuda(), torch.from_numpy(wimg).cuda(),
+                                  R, torch.from_numpy(centre), p)
+    cxy, disp, ssd, flags = [t.cpu().numpy() for t in got]
+    dx, dy, s, valid = oracle.search_window(ref, wimg, R, centre[:, 0], centre[:, 1], cx, cy, has, op)
+    assert np.array_equal(cxy[:, 0], np.where(has, cx, -1))
+    assert np.array_equal(flags, has.astype(np.uint8) | (valid << 1))
+    assert np.array_equal(disp[:, 0], dx) and np.array_equal(disp[:, 1], dy)
+    assert np.array_equal(ssd.view(np.uint32), s)
+
+
+def test_window_search_rejects_out_of_range_centre(lnr, ctx):
+    img = torch.zeros(64, 64, dtype=torch.uint8, device="cuda")
+    centre = torch.tensor([[31, 0], [0, 0], [0, 0], [0, 0]], dtype=torch.int32)
+    with pytest.raises(lnr.LnrError):
+        lnr.stage_search_window(ctx, img, img, 2, centre, lnr.Params())
+
+
+def _pixel_h(Hn, w, h):
+    B = np.array([[w, 0, w - 1], [0, w, h - 1], [0, 0, 2]], np.float64)
+    Cm = np.array([[2, 0, -(w - 1)], [0, 2, -(h - 1)], [0, 0, w]], np.float64)
+    return B @ (Hn @ Cm)
+
+
+def _epe(reg, st, w, h):
+    """mean distance between the final sample position Hp1(x + F(x)) and the
+    generator's ground truth, over pixels away from the border"""
+    Hp = _pixel_h(reg.H[1].cpu().numpy().reshape(3, 3), w, h)
+    F = reg.flow.cpu().numpy().astype(np.float64)
+    ys, xs = np.mgrid[0:h, 0:w].astype(np.float64)
+    X, Y = xs + F[0], ys + F[1]
+    den = Hp[2, 0] * X + Hp[2, 1] * Y + Hp[2, 2]
+    mx = (Hp[0, 0] * X + Hp[0, 1] * Y + Hp[0, 2]) / den
+    my = (Hp[1, 0] * X + Hp[1, 1] * Y + Hp[1, 2]) / den
+    gx, gy = st.gt_map(1)
+    m = np.zeros((h, w), bool)
+    m[32:-32, 32:-32] = True
+    return float(np.mean(np.hypot(mx - gx, my - gy)[m]))
+
+
+def test_learned_registration_agreement_and_gain(lnr, ctx):
+    """Train on pairs labelled by the exhaustive search, set the confidence
+    threshold on held-out pairs, then register another held-out pair with the
+    learned proposal: at least 99 % of level-0 tiles equal the oracle's
+    exhaustive result, the final warp error equals the plain path's, and the
+    tiles searched in the small window save SSD candidate evaluations."""
+    from paper_1504_01441_amd import proposal as prop
+    pairs = [synth.make_config_pair("c2", s, scale=0.5) for s in range(300, 312)]
+    x, lab = prop.collect(ctx, [tuple(st.frames) for st in pairs[:9]])
+    prop.train(ctx, x, lab, epochs=20, seed=1)
+    xh, lh = prop.collect(ctx, [tuple(st.frames) for st in pairs[9:11]])
+    conf, frac = prop.calibrate(ctx, xh, lh)
+    st = pairs[11]
+    f0, f1 = st.frames
+    w, h = f0.width, f0.height
+    ref = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
+    src = lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)
+    pl = lnr.Params(radius0=16)
+    pq = lnr.Params(radius0=16, learned=1, window_r=2, conf_min=conf)
+    reg_p = lnr.register_pair(ctx, ref, src, pl)
+    reg_l = lnr.register_pair(ctx, ref, src, pq)
+    torch.cuda.synchronize()
+    o = oracle.register_pair(f0, f1, oracle.params(radius0=16))
+    n0 = reg_l.tile_off[1]
+    fl = reg_l.flags.cpu().numpy()[:n0]
+    dl = reg_l.disp.cpu().numpy()[:n0]
+    same = ((fl & 3) == (o["flags"][:n0] & 3)) & (dl[:, 0] == o["dx"][:n0]) & \
+           (dl[:, 1] == o["dy"][:n0])
+    assert same.mean() >= 0.99, same.mean()
+    cornered = (fl & 1) != 0
+    window = cornered & ((fl & 16) == 0)
+    full = (2 * 16 + 1) ** 2
+    cand = window.sum() * 25 + (cornered.sum() - window.sum()) * full
+    print(f"confidence threshold {conf:.4f}; {window.sum()} of {cornered.sum()} tiles in the "
+          f"window; SSD candidates {cand / (cornered.sum() * full):.3f} of the plain search")
+    assert window.sum() >= 1 and cand < cornered.sum() * full
+    e_l, e_p = _epe(reg_l, st, w, h), _epe(reg_p, st, w, h)
+    assert abs(e_l - e_p) <= 0.02, (e_l, e_p)

@@ -132,7 +132,7 @@ def test_gradient_matches_finite_differences(seed):
     lab = rng.integers(-6, 7, (3, 2)).astype(np.int32)
     o = oracle.cnn_forward(P, x, rnd=False)
     ex, ey = 8 * o[:, 0] - lab[:, 0], 8 * o[:, 1] - lab[:, 1]
-    q0 = np.exp(-(ex * ex + ey * ey) / 4.5)
+    q0 = 1.0 / (1.0 + np.exp(-4.0 * (2.5 - np.maximum(np.abs(ex), np.abs(ey)))))
     loss, g = oracle.cnn_loss_grad(P, x, lab, rnd=False)
     assert abs(loss - _frozen_loss(P, x, lab, q0)) < 1e-12 * max(1.0, abs(loss))
     idx = []
