@@ -197,6 +197,49 @@ def main():
     ncorner = int((flags0 & 1).sum())
     search_ops = ncorner * (2 * 16 + 1) ** 2 * 21 * 21
 
+    # learned proposal: the same step with the level-0 search narrowed by the
+    # network trained on the GPU (paper_1504_01441_amd.proposal)
+    learned = None
+    from paper_1504_01441_amd import proposal as prop
+    if os.path.exists(prop.DEFAULT_WEIGHTS):
+        P_net, conf_min = prop.load()
+        lnr.proposal_set(ctx, torch.from_numpy(P_net))
+        pq = lnr.Params(radius0=st.meta["radius0"], learned=1, window_r=2, conf_min=conf_min)
+        reg_l = lnr.Registration.alloc(W, H, lnr.LNR_I420, pq)
+
+        def step_l():
+            lnr.register_pair(ctx, ref, src, pq, out=reg_l)
+            lnr.merge(ctx, [ref, src], 0, [reg_l], pq, out=hdr)
+
+        for _ in range(args.warmup):
+            step_l()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_l()
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - t0) / args.steps * 1e3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lnr.register_pair(ctx, ref, src, pq, out=reg_l)
+        torch.cuda.synchronize()
+        ms_lr = (time.perf_counter() - t0) / args.steps * 1e3
+        n0 = reg.tile_off[1]
+        fl = reg_l.flags.cpu().numpy()[:n0]
+        cornered = (fl & 1) != 0
+        window = cornered & ((fl & 16) == 0)
+        full = (2 * st.meta["radius0"] + 1) ** 2
+        cand = int(window.sum()) * 25 + int(cornered.sum() - window.sum()) * full
+        learned = {"value": round(mpix / (ms_l / 1e3), 2), "unit": "MPix/s",
+                   "ms_per_step": round(ms_l, 4),
+                   "registration_only": {"ms": round(ms_lr, 4),
+                                         "mpix_s": round(mpix / (ms_lr / 1e3), 2)},
+                   "conf_min": round(conf_min, 6),
+                   "tiles_in_window_pct": round(100.0 * window.sum() / max(cornered.sum(), 1), 2),
+                   "ssd_candidates_vs_plain": round(cand / max(int(cornered.sum()) * full, 1), 4),
+                   "_flags": fl, "_disp": reg_l.disp.cpu().numpy()[:n0]}
+
     result = {
         "metric": "registered MPix/s on 5MP pairs, plain vs learned-proposal; % tiles = oracle",
         "value": round(value, 2),
@@ -215,7 +258,8 @@ def main():
                                "+ merge",
                    "width": W, "height": H, "seed": args.seed},
         "registration_only": {"ms": round(ms_reg, 4), "mpix_s": round(mpix / (ms_reg / 1e3), 2)},
-        "learned_proposal": None,
+        "learned_proposal": None if learned is None else
+        {k: v for k, v in learned.items() if not k.startswith("_")},
         "roofline": roof,
         "search_level0": {"pixel_candidate_ops": search_ops,
                           "int_peak_tops": round(INT_PEAK_TOPS, 2)},
@@ -243,6 +287,11 @@ def main():
         same = (g["flags"] == o["flags"]) & (g["disp"][:, 0] == o["dx"]) & \
                (g["disp"][:, 1] == o["dy"])
         result["tiles_equal_oracle_pct"] = round(100.0 * same.mean(), 3)
+        if learned is not None:
+            n0 = len(learned["_flags"])
+            sl = ((learned["_flags"] & 3) == (o["flags"][:n0] & 3)) & \
+                 (learned["_disp"][:, 0] == o["dx"][:n0]) & (learned["_disp"][:, 1] == o["dy"][:n0])
+            result["learned_proposal"]["tiles_equal_oracle_pct"] = round(100.0 * sl.mean(), 3)
     print(json.dumps(result))
 
 

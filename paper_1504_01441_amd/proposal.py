@@ -95,23 +95,26 @@ def train(ctx: Context, x: torch.Tensor, labels: torch.Tensor, epochs: int = 10,
 
 
 def calibrate(ctx: Context, x: torch.Tensor, labels: torch.Tensor, window: int = 2,
-              radius0: int = 16, target: float = 0.995):
-    """Smallest confidence threshold conf_min whose confident tiles (held-out
-    x, labels) have the exhaustive argmin inside the +-window box around the
-    rounded, clamped prediction at least `target` of the time. Returns
-    (conf_min, fraction of tiles that are confident)."""
+              radius0: int = 16, budget: float = 0.005):
+    """Confidence threshold conf_min for held-out tiles (x, labels): the most
+    confident tiles are searched in the +-window box around the rounded,
+    clamped prediction, as many as possible while the tiles whose exhaustive
+    argmin falls outside their box stay within `budget` of all tiles (each
+    such tile is a disagreement with the exhaustive search). Returns
+    (conf_min, fraction of tiles searched in the window)."""
     o = proposal_forward(ctx, x).double().cpu().numpy()
     lab = labels.cpu().numpy()
     c = np.clip(np.floor(8.0 * o[:, :2] + 0.5), -(radius0 - window), radius0 - window)
     inside = np.all(np.abs(c - lab) <= window, axis=1)
-    order = np.argsort(-o[:, 2])           # most confident first
-    ok = np.cumsum(inside[order]) / np.arange(1, len(order) + 1)
-    good = np.nonzero(ok >= target)[0]
+    order = np.argsort(-o[:, 2], kind="stable")   # most confident first
+    misses = np.cumsum(~inside[order])
+    good = np.nonzero(misses <= budget * len(order))[0]
     if len(good) == 0:
         return 1.0 - 1e-9, 0.0
-    k = int(good.max())                     # largest confident prefix meeting the target
-    logit = float(o[order[k], 2])
-    conf = 1.0 / (1.0 + np.exp(-logit))
+    k = int(good.max())
+    # threshold halfway (in logit) to the next tile so that tile k is included
+    z = o[order[k], 2] if k + 1 == len(order) else 0.5 * (o[order[k], 2] + o[order[k + 1], 2])
+    conf = 1.0 / (1.0 + np.exp(-z))
     return float(min(max(conf, 1e-6), 1.0 - 1e-9)), (k + 1) / len(order)
 
 
