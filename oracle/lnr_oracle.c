@@ -458,7 +458,7 @@ int lo_hypothesis_inliers(int ntiles, const int32_t* cx, const int32_t* cy, cons
 }
 
 /* ---------------------------------------------------------------------------
- * Sec. 2.2: the level homography "computed using its corners and matches":
+ * Sec. 2.2: the level homography, from the level's corners and matches:
  * the least-squares DLT (h33 = 1) of G: p -> p + d over a selected set of
  * matches (in the pipeline: the inliers of the weeding iteration with the
  * largest consensus, provided it exceeds delta), composed on the previous
