@@ -300,7 +300,9 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
   uint32_t gpk[NG];
 #pragma unroll
   for (int q = 0; q < NG; ++q) gpk[q] = 0u;
-  double a0[L], a1[L], a2[L];
+  // the segment is held as float (as stored between passes); every recursion
+  // step and carry is computed in double precision
+  float a0[L], a1[L], a2[L];
 #pragma unroll
   for (int j = -1; j <= L; ++j) {
     const int y = r0 + j;
@@ -309,9 +311,9 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     const uint32_t gv = in ? guide[o] : 0u;
     gpk[(j + 1) >> 2] |= gv << (8 * ((j + 1) & 3));
     if (j >= 0 && j < L) {
-      a0[j] = in ? (double)maps[o] : 0.0;
-      a1[j] = in ? (double)maps[plane + o] : 0.0;
-      a2[j] = in ? (double)maps[2 * plane + o] : 0.0;
+      a0[j] = in ? maps[o] : 0.f;
+      a1[j] = in ? maps[plane + o] : 0.f;
+      a2[j] = in ? maps[2 * plane + o] : 0.f;
     }
   }
 #define GB(j) ((int)((gpk[((j) + 1) >> 2] >> (8 * (((j) + 1) & 3))) & 255u))
@@ -322,9 +324,10 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     for (int j = 0; j < L; ++j) {
       if (r0 + j >= H) break;
       const double c = CC(j);
-      t.B0 = a0[j] + c * (t.B0 - a0[j]);
-      t.B1 = a1[j] + c * (t.B1 - a1[j]);
-      t.B2 = a2[j] + c * (t.B2 - a2[j]);
+      const double v0 = a0[j], v1 = a1[j], v2 = a2[j];
+      t.B0 = v0 + c * (t.B0 - v0);
+      t.B1 = v1 + c * (t.B1 - v1);
+      t.B2 = v2 + c * (t.B2 - v2);
       t.A *= c;
     }
     double p0, p1, p2;
@@ -333,9 +336,10 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     for (int j = 0; j < L; ++j) {
       if (r0 + j >= H) break;
       const double c = CC(j);
-      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
-      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
-      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
+      const double v0 = a0[j], v1 = a1[j], v2 = a2[j];
+      p0 = v0 + c * (p0 - v0); a0[j] = (float)p0;
+      p1 = v1 + c * (p1 - v1); a1[j] = (float)p1;
+      p2 = v2 + c * (p2 - v2); a2[j] = (float)p2;
     }
   }
   {
@@ -344,9 +348,10 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     for (int j = L - 1; j >= 0; --j) {
       if (r0 + j >= H) continue;
       const double c = CC(j + 1);
-      t.B0 = a0[j] + c * (t.B0 - a0[j]);
-      t.B1 = a1[j] + c * (t.B1 - a1[j]);
-      t.B2 = a2[j] + c * (t.B2 - a2[j]);
+      const double v0 = a0[j], v1 = a1[j], v2 = a2[j];
+      t.B0 = v0 + c * (t.B0 - v0);
+      t.B1 = v1 + c * (t.B1 - v1);
+      t.B2 = v2 + c * (t.B2 - v2);
       t.A *= c;
     }
     double p0, p1, p2;
@@ -355,9 +360,10 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     for (int j = L - 1; j >= 0; --j) {
       if (r0 + j >= H) continue;
       const double c = CC(j + 1);
-      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
-      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
-      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
+      const double v0 = a0[j], v1 = a1[j], v2 = a2[j];
+      p0 = v0 + c * (p0 - v0); a0[j] = (float)p0;
+      p1 = v1 + c * (p1 - v1); a1[j] = (float)p1;
+      p2 = v2 + c * (p2 - v2); a2[j] = (float)p2;
     }
   }
 #undef CC
@@ -369,12 +375,12 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     if (y >= H) break;
     const size_t o = (size_t)y * W + col;
     if (LAST) {
-      const bool ok = a2[j] > nmin;
-      flow[o] = ok ? (float)(a0[j] / a2[j]) : 0.f;
-      flow[plane + o] = ok ? (float)(a1[j] / a2[j]) : 0.f;
-      if (ntilde) ntilde[o] = (float)a2[j];
+      const bool ok = (double)a2[j] > nmin;
+      flow[o] = ok ? (float)((double)a0[j] / (double)a2[j]) : 0.f;
+      flow[plane + o] = ok ? (float)((double)a1[j] / (double)a2[j]) : 0.f;
+      if (ntilde) ntilde[o] = a2[j];
     } else {
-      maps[o] = (float)a0[j]; maps[plane + o] = (float)a1[j]; maps[2 * plane + o] = (float)a2[j];
+      maps[o] = a0[j]; maps[plane + o] = a1[j]; maps[2 * plane + o] = a2[j];
     }
   }
 }

@@ -54,7 +54,9 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     }
     for (int k = 0; k <= 2 * r; ++k) gw[k] = g[k] / s;
   }
-  const int ox = blockIdx.x * kSsimTW, oy = blockIdx.y * kSsimTH;
+  int bx, by;
+  xcd_block(gridDim.x, gridDim.y, bx, by);
+  const int ox = bx * kSsimTW, oy = by * kSsimTH;
 #pragma unroll 4
   for (int i = tid; i < rows * cols; i += 256) {
     const int yy = i / cols, xx = i % cols;
@@ -79,23 +81,40 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
     hv[i] = m1; hv[n5 + i] = m2; hv[2 * n5 + i] = s11; hv[3 * n5 + i] = s22; hv[4 * n5 + i] = s12;
   }
   __syncthreads();
-  for (int i = tid; i < kSsimTH * kSsimTW; i += 256) {
-    const int yy = i / kSsimTW, xx = i % kSsimTW;
-    const int gy = oy + yy, gx = ox + xx;
-    if (gy >= H || gx >= W) continue;
-    double m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
-    for (int k = 0; k <= 2 * r; ++k) {
+  // vertical sums: a thread owns two consecutive output rows of one column,
+  // so 2r + 2 horizontal sums serve both
+  {
+    const int xx = tid % kSsimTW, yy = 2 * (tid / kSsimTW);  // rows yy, yy + 1
+    double acc[2][5];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int t = 0; t < 5; ++t) acc[q][t] = 0.0;
+    for (int k = 0; k <= 2 * r + 1; ++k) {
       const int j = (yy + k) * kSsimTW + xx;
-      const double wd = gw[k];
-      m1 += wd * hv[j];
-      m2 += wd * hv[n5 + j];
-      s11 += wd * hv[2 * n5 + j];
-      s22 += wd * hv[3 * n5 + j];
-      s12 += wd * hv[4 * n5 + j];
+      double hvv[5];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) hvv[t] = hv[t * n5 + j];
+      if (k <= 2 * r) {
+        const double wd = gw[k];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) acc[0][t] += wd * hvv[t];
+      }
+      if (k >= 1) {
+        const double wd = gw[k - 1];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) acc[1][t] += wd * hvv[t];
+      }
     }
-    const double vx = s11 - m1 * m1, vy = s22 - m2 * m2, cxy = s12 - m1 * m2;
-    out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
-                                       ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int gy = oy + yy + q, gx = ox + xx;
+      if (gy >= H || gx >= W) continue;
+      const double m1 = acc[q][0], m2 = acc[q][1];
+      const double vx = acc[q][2] - m1 * m1, vy = acc[q][3] - m2 * m2, cxy = acc[q][4] - m1 * m2;
+      out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
+                                         ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
+    }
   }
 }
 
@@ -134,20 +153,25 @@ __device__ inline double raw_weight(const FramePtrs& f, int k, int ch, int ref, 
 
 __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int W, int H,
                                                  int ref, float two_se2) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  int bx, y;
+  xcd_block(gridDim.x, gridDim.y, bx, y);  // rows y - 1, y, y + 1 in one L2
+  const int x = bx * blockDim.x + threadIdx.x;
   if (x >= W) return;
   const size_t plane = (size_t)W * H, o = (size_t)y * W + x;
   const size_t oU = (size_t)max(y - 1, 0) * W + x, oD = (size_t)min(y + 1, H - 1) * W + x;
   const size_t oL = (size_t)y * W + max(x - 1, 0), oR = (size_t)y * W + min(x + 1, W - 1);
   // the raw weights keep 24-bit relative precision as floats once the
   // cancelling differences inside them were taken in double precision
+  float wk[16];  // n <= 16; kept in registers (every index is a constant)
   double sum = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const float wk = (float)raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2);
-    f.wout[k][o] = wk;
-    sum += (double)wk;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    wk[k] = k < n ? (float)raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2) : 0.f;
+    sum += (double)wk[k];
   }
-  for (int k = 0; k < n; ++k) f.wout[k][o] = (float)((double)f.wout[k][o] / sum);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k < n) f.wout[k][o] = (float)((double)wk[k] / sum);
 }
 
 struct MapPtrs {
@@ -223,18 +247,32 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
                                                int cw, int chh, int top) {
   extern __shared__ float sm[];
   const int tid = threadIdx.x;
-  const int ox = blockIdx.x * kBW, oy = blockIdx.y * kBH;
+  int bx, by;
+  xcd_block(gridDim.x, gridDim.y, bx, by);
+  const int ox = bx * kBW, oy = by * kBH;
   const int cx0 = (ox >> 1) - 1, cy0 = (oy >> 1) - 1;
   const int nm = top ? 0 : (n + 1) * cg;  // plane m = cc (n + 1) + k, k = n: R
   float* ct = sm;                         // [nm][kCH][kCW] coarse tiles
   float* rx = sm + nm * kCH * kCW;        // [nm][kCH][kBW] expanded along x
   if (!top) {
-    for (int i = tid; i < nm * kCH * kCW; i += 256) {
-      const int m = i / (kCH * kCW), r = (i / kCW) % kCH, q = i % kCW;
-      const int cc = m / (n + 1), k = m % (n + 1);
-      const float* src = k < n ? b.gc[k][c0 + cc] : b.rc[c0 + cc];
-      const int gy = min(max(cy0 + r, 0), chh - 1), gx = min(max(cx0 + q, 0), cw - 1);
-      ct[i] = src[(size_t)gy * cw + gx];
+    const int ntot = nm * kCH * kCW;
+    for (int i0 = tid; i0 < ntot; i0 += 4 * 256) {  // four loads in flight per thread
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 256 * u;
+        v[u] = 0.f;
+        if (i < ntot) {
+          const int m = i / (kCH * kCW), r = (i / kCW) % kCH, q = i % kCW;
+          const int cc = m / (n + 1), k = m % (n + 1);
+          const float* src = k < n ? b.gc[k][c0 + cc] : b.rc[c0 + cc];
+          const int gy = min(max(cy0 + r, 0), chh - 1), gx = min(max(cx0 + q, 0), cw - 1);
+          v[u] = src[(size_t)gy * cw + gx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + 256 * u < ntot) ct[i0 + 256 * u] = v[u];
     }
     __syncthreads();
     for (int i = tid; i < nm * kCH * kBW; i += 256) {
@@ -254,21 +292,30 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
   for (int cc = 0; cc < cg; ++cc)
     for (int q = 0; q < 4; ++q) acc[cc][q] = 0.f;
   for (int k = 0; k < n; ++k) {
-    float wv[4];
+    // this frame's weights and image values first (16 loads in flight)
+    float wv[4], gv[3][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int y = oy + fy0 + 4 * q;
       wv[q] = y < h ? b.w[k][(size_t)y * w + x] : 0.f;
     }
-    for (int cc = 0; cc < cg; ++cc) {
-      const float* g = b.g[k][c0 + cc];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int y = oy + fy0 + 4 * q;
+        gv[cc][q] = cc < cg && y < h ? b.g[k][c0 + cc][(size_t)y * w + x] : 0.f;
+      }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      if (cc >= cg) break;
       const float* col = rx + (cc * (n + 1) + k) * kCH * kBW + fx;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int y = oy + fy0 + 4 * q;
         if (y >= h) break;
         const float e = top ? 0.f : expand_col(col, (y >> 1) - cy0, (y & 1) == 0);
-        acc[cc][q] += wv[q] * (g[(size_t)y * w + x] - e);
+        acc[cc][q] += wv[q] * (gv[cc][q] - e);
       }
     }
   }

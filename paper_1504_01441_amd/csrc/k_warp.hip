@@ -32,7 +32,9 @@ __global__ __launch_bounds__(256) void k_bwarp(const uint8_t* __restrict__ y, in
   __shared__ double hp[9];
   if (threadIdx.x == 0) pixel_homography(Hn, W, H, hp);
   __syncthreads();
-  const int px = blockIdx.x * blockDim.x + threadIdx.x, py = blockIdx.y;
+  int bx, py;
+  xcd_block(gridDim.x, gridDim.y, bx, py);  // neighbouring rows gather from shared source rows
+  const int px = bx * blockDim.x + threadIdx.x;
   if (px >= W) return;
   const size_t plane = (size_t)W * H, o = (size_t)py * W + px;
   const double X = (double)px + (double)flow[o];

@@ -25,6 +25,17 @@ struct TraceScope {
     hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);        \
   } while (0)
 
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// For kernels whose neighbouring blocks read overlapping rows, this maps the
+// dispatch index so that each XCD walks one contiguous band of the grid (in
+// raster order), keeping the shared rows in one L2.
+__device__ inline void xcd_block(int gx, int gy, int& bx, int& by) {
+  const int nb = gx * gy, b = blockIdx.x + gx * blockIdx.y, full = nb / 8 * 8;
+  const int j = b < full ? (b % 8) * (nb / 8) + b / 8 : b;
+  bx = j % gx;
+  by = j / gx;
+}
+
 constexpr int kMaxLevels = 5;
 constexpr int kMaxRadius = 32;
 constexpr int kMaxPatchR = 11;   // patch rows fit in 6 dwords
