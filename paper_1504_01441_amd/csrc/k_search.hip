@@ -64,11 +64,11 @@ __device__ inline uint32_t warp_px(const uint8_t* __restrict__ src, int w, int h
 __global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src, int w, int h,
                                                  const double* __restrict__ Hn,
                                                  uint8_t* __restrict__ out) {
-  __shared__ double hp[9];
-  if (threadIdx.x == 0) pixel_homography(Hn, w, h, hp);
-  __syncthreads();
   const int x = 4 * (blockIdx.x * blockDim.x + threadIdx.x), y = blockIdx.y;
   if (x >= w) return;
+  // every thread forms the pixel homography itself (uniform, no barrier)
+  double hp[9];
+  pixel_homography(Hn, w, h, hp);
   uint8_t* row = out + (size_t)y * w;
   if (x + 4 <= w && ((reinterpret_cast<uintptr_t>(row + x) & 3u) == 0)) {
     uint32_t v = 0;
@@ -114,6 +114,7 @@ __device__ inline void stage_rows(const uint8_t* __restrict__ img, int w, int h,
 
 struct SearchShape {
   int R, nstrips, nthreads;
+  int split;     // patch rows split over this many thread groups (partial SSDs summed in LDS)
   int NR;        // window rows = 2P + 2R + 1
   int wrow;      // window row stride in bytes (multiple of 16)
   int ncand;     // 2R + 1
@@ -271,16 +272,25 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   }
   __syncthreads();
 
-  // 3. SSD of KX candidates per thread ---------------------------------------
+  // 3. SSD of KX candidates per thread (over a group of patch rows) -------
   unsigned long long key = ~0ull;
-  if (tid < sh.nthreads) {
-    const int j = tid / sh.nstrips, s = tid % sh.nstrips;  // dy index, strip
-    uint32_t acc[KX], ew[KX];
+  const int base_threads = sh.ncand * sh.nstrips;
+  const int ncp = sh.nstrips * KX;  // padded candidates per row
+  uint32_t* tot = rowsq + sh.NR * sh.ncand + KX;  // [2][ncand][ncp] when split > 1
+  if (sh.split > 1) {
+    for (int i = tid; i < 2 * sh.ncand * ncp; i += nt) tot[i] = 0u;
+    __syncthreads();
+  }
+  const int grp = tid / base_threads, rem = tid % base_threads;
+  const int j = rem / sh.nstrips, s = rem % sh.nstrips;  // dy index, strip
+  uint32_t acc[KX], ew[KX];
 #pragma unroll
-    for (int k = 0; k < KX; ++k) { acc[k] = 0; ew[k] = 0; }
+  for (int k = 0; k < KX; ++k) { acc[k] = 0; ew[k] = 0; }
+  if (tid < sh.nthreads) {
     const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
     const int rowdw = sh.wrow >> 2;
-    for (int i = 0; i < PW; ++i) {
+    const int i0 = grp * PW / sh.split, i1 = (grp + 1) * PW / sh.split;
+    for (int i = i0; i < i1; ++i) {
       const uint32_t* wr = wdw + (j + i) * rowdw + s * (KX / 4);
       uint32_t wv[KX / 4 + NW + 1];
 #pragma unroll
@@ -308,6 +318,24 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
 #pragma unroll
       for (int k = 0; k < KX; ++k) ew[k] += (s * KX + k < sh.ncand) ? rq[k] : 0u;
     }
+    if (sh.split > 1) {  // exact integer partial sums: any order gives the same totals
+#pragma unroll
+      for (int k = 0; k < KX; ++k) {
+        atomicAdd(&tot[j * ncp + s * KX + k], acc[k]);
+        atomicAdd(&tot[sh.ncand * ncp + j * ncp + s * KX + k], ew[k]);
+      }
+    }
+  }
+  if (sh.split > 1) {
+    __syncthreads();
+    if (tid < base_threads)
+#pragma unroll
+      for (int k = 0; k < KX; ++k) {
+        acc[k] = tot[j * ncp + s * KX + k];
+        ew[k] = tot[sh.ncand * ncp + j * ncp + s * KX + k];
+      }
+  }
+  if (tid < base_threads) {
     const uint32_t er = er_sum;
 #pragma unroll
     for (int k = 0; k < KX; ++k) {
@@ -367,15 +395,25 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
   sh.R = R;
   sh.ncand = 2 * R + 1;
   sh.nstrips = (sh.ncand + KX - 1) / KX;
-  sh.nthreads = sh.ncand * sh.nstrips;
+  // when the level has too few candidate threads to fill the chip (coarse
+  // levels, small windows), split the patch rows so that a tile keeps about
+  // 256 threads busy
+  const int base = sh.ncand * sh.nstrips;
+  sh.split = (long long)ntx * nty * base >= 65536 ? 1 : (256 + base / 2) / base;
+  if (sh.split < 1) sh.split = 1;
+  if (sh.split > 7) sh.split = 7;
+  if (sh.split > 2 * c.P + 1) sh.split = 2 * c.P + 1;
+  sh.nthreads = base * sh.split;
   sh.NR = 2 * c.P + 2 * R + 1;
   // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
   const int need = (sh.nstrips * KX) + 4 * (NW + 1);
   sh.wrow = (need + 15) / 16 * 16;
   int block = (sh.nthreads + 63) / 64 * 64;
   if (block < 64) block = 64;
-  // (+ KX words: the last strip's padded candidates read past the last row)
-  const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4;
+  // (+ KX words: the last strip's padded candidates read past the last row;
+  // + the partial-sum totals when the rows are split)
+  const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
+                     (sh.split > 1 ? (size_t)2 * sh.ncand * sh.nstrips * KX * 4 : 0);
   LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
                      ntx, corner_xy, disp, ssd, flags, centre, mode, want);
   return hipGetLastError();

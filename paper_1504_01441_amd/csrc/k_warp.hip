@@ -29,13 +29,12 @@ __global__ __launch_bounds__(256) void k_bwarp(const uint8_t* __restrict__ y, in
                                                const double* __restrict__ Hn,
                                                const float* __restrict__ flow,
                                                float* __restrict__ img, float* __restrict__ yw) {
-  __shared__ double hp[9];
-  if (threadIdx.x == 0) pixel_homography(Hn, W, H, hp);
-  __syncthreads();
   int bx, py;
   xcd_block(gridDim.x, gridDim.y, bx, py);  // neighbouring rows gather from shared source rows
   const int px = bx * blockDim.x + threadIdx.x;
   if (px >= W) return;
+  double hp[9];  // formed per thread (uniform, no barrier)
+  pixel_homography(Hn, W, H, hp);
   const size_t plane = (size_t)W * H, o = (size_t)py * W + px;
   const double X = (double)px + (double)flow[o];
   const double Y = (double)py + (double)flow[plane + o];
