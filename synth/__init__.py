@@ -12,6 +12,7 @@ from .scenes import (  # noqa: F401
     make_pair,
     make_stack,
     make_config_pair,
+    make_batch_pair,
     make_planted_shift_pair,
     make_texture,
     CONFIGS,

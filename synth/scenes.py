@@ -210,7 +210,7 @@ def make_pair(W, H, seed, ratio=4.0, **kw):
     return make_stack(W, H, seed, ratios=(1.0, ratio), **kw)
 
 
-# Workload shapes (see the design doc for the recipe).
+# Workload shapes: sizes, exposure ratios, planted motion and noise of each case.
 CONFIGS = {
     # 640x480 Y8, exposure ratio 4, rotation <= 2 deg, translation <= 10 px,
     # perspective <= 1e-4, per-tile shifts in [-6, 6]; radius 8 at level 0
@@ -239,6 +239,21 @@ def make_config_pair(name, seed, scale=None):
     st = make_stack(W, H, seed, **cfg)
     st.meta["radius0"] = radius0
     st.meta["config"] = name
+    return st
+
+
+def make_batch_pair(seed):
+    """One pair of the batched workload: width and height drawn uniformly over
+    even sizes from 640x480 to 4032x3024, 8-bit I420, exposure ratio in
+    [2, 16], per-tile translations in [-16, 16]; search radius 16."""
+    rng = np.random.default_rng(seed)
+    W = int(rng.integers(320, 2017)) * 2
+    H = int(rng.integers(240, 1513)) * 2
+    ratio = float(rng.uniform(2.0, 16.0))
+    st = make_stack(W, H, seed, ratios=(1.0, ratio), fmt="i420", shift_range=16,
+                    max_rot_deg=2.0)
+    st.meta["radius0"] = 16
+    st.meta["config"] = "c4"
     return st
 
 
