@@ -108,71 +108,89 @@ __global__ __launch_bounds__(256) void k_cnn_input(const uint8_t* __restrict__ r
   }
 }
 
-// conv1 (2 -> 32, stride 1): K = 18 (tap, ci) padded to 32
+// conv1 (2 -> 32, stride 1): K = 18 (tap, ci) padded to 32; four output
+// tiles at a time share the B fragments
 __device__ void conv1_fwd(const uint16_t* in /*[16][16][2]*/, const uint16_t* W1p,
                           const float* bias, uint16_t* out /*[16][16][32]*/, int lane) {
   const int r = lane & 15, g = lane >> 4;
-  for (int mt = 0; mt < 16; ++mt) {
-    const int m = mt * 16 + r, oy = m >> 4, ox = m & 15;
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  for (int mt0 = 0; mt0 < 16; mt0 += 4) {
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const int t0 = half * 8 + g * 2;  // taps t0, t0 + 1 (channels 0, 1 each)
-      uint32_t v[2] = {0u, 0u};
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int tap = t0 + q;
-        const int iy = oy + tap / 3 - 1, ix = ox + tap % 3 - 1;
-        if (tap < 9 && iy >= 0 && iy < 16 && ix >= 0 && ix < 16)
-          v[q] = *reinterpret_cast<const uint32_t*>(in + (iy * 16 + ix) * 2);
-      }
-      bf16x4 a;
-      a[0] = (short)(v[0] & 0xffff); a[1] = (short)(v[0] >> 16);
-      a[2] = (short)(v[1] & 0xffff); a[3] = (short)(v[1] >> 16);
       const bf16x4 b0 = ld4(W1p + r * 32 + half * 16 + g * 4);
       const bf16x4 b1 = ld4(W1p + (16 + r) * 32 + half * 16 + g * 4);
-      acc0 = mfma(a, b0, acc0);
-      acc1 = mfma(a, b1, acc1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int m = (mt0 + u) * 16 + r, oy = m >> 4, ox = m & 15;
+        uint32_t v[2] = {0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int tap = t0 + q;
+          const int iy = oy + tap / 3 - 1, ix = ox + tap % 3 - 1;
+          if (tap < 9 && iy >= 0 && iy < 16 && ix >= 0 && ix < 16)
+            v[q] = *reinterpret_cast<const uint32_t*>(in + (iy * 16 + ix) * 2);
+        }
+        bf16x4 a;
+        a[0] = (short)(v[0] & 0xffff); a[1] = (short)(v[0] >> 16);
+        a[2] = (short)(v[1] & 0xffff); a[3] = (short)(v[1] >> 16);
+        acc[u][0] = mfma(a, b0, acc[u][0]);
+        acc[u][1] = mfma(a, b1, acc[u][1]);
+      }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int p = mt * 16 + g * 4 + j;
-      out[p * CH + r] = f2bf(fmaxf(acc0[j] + bias[r], 0.f));
-      out[p * CH + 16 + r] = f2bf(fmaxf(acc1[j] + bias[16 + r], 0.f));
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = (mt0 + u) * 16 + g * 4 + j;
+        out[p * CH + r] = f2bf(fmaxf(acc[u][0][j] + bias[r], 0.f));
+        out[p * CH + 16 + r] = f2bf(fmaxf(acc[u][1][j] + bias[16 + r], 0.f));
+      }
   }
 }
 
-// conv 32 -> 32 (3x3, pad 1, stride S), NHWC bf16 in / out, W [co][tap][ci]
+// conv 32 -> 32 (3x3, pad 1, stride S), NHWC bf16 in / out, W [co][tap][ci].
+// MG output-position tiles at a time: each B fragment serves MG MFMAs and the
+// 2 * MG accumulators are independent chains.
 template <int HIN, int HOUT, int S>
 __device__ void conv_fwd(const uint16_t* in, const uint16_t* W, const float* bias, uint16_t* out,
                          int lane) {
   const int r = lane & 15, g = lane >> 4;
   constexpr int MT = HOUT * HOUT / 16;
+  constexpr int MG = MT < 4 ? MT : 4;
   const bf16x4 zero = {0, 0, 0, 0};
-  for (int mt = 0; mt < MT; ++mt) {
-    const int m = mt * 16 + r, oy = m / HOUT, ox = m % HOUT;
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  for (int mt0 = 0; mt0 < MT; mt0 += MG) {
+    f32x4 acc[MG][2];
+#pragma unroll
+    for (int u = 0; u < MG; ++u) acc[u][0] = acc[u][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
-      const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const int ci = half * 16 + g * 4;
-        const bf16x4 a = ok ? ld4(in + (iy * HIN + ix) * CH + ci) : zero;
         const bf16x4 b0 = ld4(W + (r * 9 + tap) * CH + ci);
         const bf16x4 b1 = ld4(W + ((16 + r) * 9 + tap) * CH + ci);
-        acc0 = mfma(a, b0, acc0);
-        acc1 = mfma(a, b1, acc1);
+#pragma unroll
+        for (int u = 0; u < MG; ++u) {
+          const int m = (mt0 + u) * 16 + r, oy = m / HOUT, ox = m % HOUT;
+          const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+          const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
+          const bf16x4 a = ok ? ld4(in + (iy * HIN + ix) * CH + ci) : zero;
+          acc[u][0] = mfma(a, b0, acc[u][0]);
+          acc[u][1] = mfma(a, b1, acc[u][1]);
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int p = mt * 16 + g * 4 + j;
-      out[p * CH + r] = f2bf(fmaxf(acc0[j] + bias[r], 0.f));
-      out[p * CH + 16 + r] = f2bf(fmaxf(acc1[j] + bias[16 + r], 0.f));
-    }
+    for (int u = 0; u < MG; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = (mt0 + u) * 16 + g * 4 + j;
+        out[p * CH + r] = f2bf(fmaxf(acc[u][0][j] + bias[r], 0.f));
+        out[p * CH + 16 + r] = f2bf(fmaxf(acc[u][1][j] + bias[16 + r], 0.f));
+      }
   }
 }
 
