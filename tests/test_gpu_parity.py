@@ -350,6 +350,29 @@ def test_stack_and_merge_three_frames(ctx):
     assert_close(out.cpu().numpy(), want, 1.0, what="merge")
 
 
+def test_stack_and_merge_three_frames_full_size(ctx):
+    """The 12 MP 3-frame stack at its full size (4000x3000, ratios 1/4/16,
+    rotation up to 3 degrees, shifts +-12, 5 % saturated discs): both
+    registrations against the oracle's, and the merge against the oracle's
+    merge of the same registered planes."""
+    st = synth.make_config_pair("c3", 3)
+    frames = st.frames
+    p, op = params_pair(radius0=16)
+    g = [to_gpu_frame(f) for f in frames]
+    regs, ref = lnr().register_stack(ctx, g, p)
+    out = lnr().merge(ctx, g, ref, regs, p)
+    _sync()
+    assert ref == 0
+    j = 0
+    for k, f in enumerate(frames):
+        if k != ref:
+            registration_parity(regs[j], oracle.register_pair(frames[ref], f, op))
+            j += 1
+    imgs, yeqs = _gpu_merge_inputs(ctx, frames, ref, regs)
+    want = oracle.merge(imgs, yeqs, ref, op)
+    assert_close(out.cpu().numpy(), want, 1.0, what="merge")
+
+
 def test_register_rejects_bad_arguments(ctx):
     st = synth.make_config_pair("c1", 16)
     a = to_gpu_frame(st.frames[0])
