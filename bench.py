@@ -150,6 +150,9 @@ def main():
     reg = lnr.Registration.alloc(W, H, lnr.LNR_I420, p)
     hdr = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
 
+    # the library's autotuner picks the propagation kernel shape for this size
+    dt_shape = lnr.autotune_flow(ctx, W, H, p)
+
     def step():
         lnr.register_pair(ctx, ref, src, p, out=reg)
         lnr.merge(ctx, [ref, src], 0, [reg], p, out=hdr)
@@ -291,6 +294,9 @@ def main():
                                "+ merge",
                    "width": W, "height": H, "seed": args.seed},
         "registration_only": {"ms": round(ms_reg, 4), "mpix_s": round(mpix / (ms_reg / 1e3), 2)},
+        "autotuned_dt_shape": {"row_seg": dt_shape[0], "row_block": dt_shape[1],
+                               "col_rows": dt_shape[2], "col_cols": dt_shape[3],
+                               "col_segments": dt_shape[4]},
         "learned_proposal": None if learned is None else
         {k: v for k, v in learned.items() if not k.startswith("_")},
         "roofline": roof,

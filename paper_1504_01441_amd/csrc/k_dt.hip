@@ -159,7 +159,10 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
   }
   __syncthreads();
   const int xb = tid * SEG;
-  double a0[SEG], a1[SEG], a2[SEG], cc[SEG + 1];  // cc[j]: between xb+j-1 and xb+j
+  // the segment is held as float (as stored between passes); every recursion
+  // step and carry is computed in double precision
+  float a0[SEG], a1[SEG], a2[SEG];
+  double cc[SEG + 1];  // cc[j]: between xb+j-1 and xb+j
   int gp = xb > 0 && xb - 1 < W ? g[xb - 1] : 0;
 #pragma unroll
   for (int j = 0; j <= SEG; ++j) {
@@ -168,9 +171,9 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
     cc[j] = (x > 0 && x < W) ? coef_at(cf, gp, gc) : 0.0;
     gp = gc;
     if (j < SEG) {
-      a0[j] = x < W ? (double)v0[x] : 0.0;
-      a1[j] = x < W ? (double)v1[x] : 0.0;
-      a2[j] = x < W ? (double)v2[x] : 0.0;
+      a0[j] = x < W ? v0[x] : 0.f;
+      a1[j] = x < W ? v1[x] : 0.f;
+      a2[j] = x < W ? v2[x] : 0.f;
     }
   }
   // causal: J[x] = J[x] + c (J[x-1] - J[x])
@@ -180,9 +183,10 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
     for (int j = 0; j < SEG; ++j) {
       if (xb + j >= W) continue;
       const double c = cc[j];
-      t.B0 = a0[j] + c * (t.B0 - a0[j]);
-      t.B1 = a1[j] + c * (t.B1 - a1[j]);
-      t.B2 = a2[j] + c * (t.B2 - a2[j]);
+      const double u0 = a0[j], u1 = a1[j], u2 = a2[j];
+      t.B0 = u0 + c * (t.B0 - u0);
+      t.B1 = u1 + c * (t.B1 - u1);
+      t.B2 = u2 + c * (t.B2 - u2);
       t.A *= c;
     }
     double p0, p1, p2;
@@ -191,9 +195,10 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
     for (int j = 0; j < SEG; ++j) {
       if (xb + j >= W) continue;
       const double c = cc[j];
-      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
-      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
-      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
+      const double u0 = a0[j], u1 = a1[j], u2 = a2[j];
+      p0 = u0 + c * (p0 - u0); a0[j] = (float)p0;
+      p1 = u1 + c * (p1 - u1); a1[j] = (float)p1;
+      p2 = u2 + c * (p2 - u2); a2[j] = (float)p2;
     }
   }
   // anti-causal: J[x] = J[x] + c (J[x+1] - J[x]), c between x and x+1
@@ -203,9 +208,10 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
     for (int j = SEG - 1; j >= 0; --j) {
       if (xb + j >= W) continue;
       const double c = cc[j + 1];
-      t.B0 = a0[j] + c * (t.B0 - a0[j]);
-      t.B1 = a1[j] + c * (t.B1 - a1[j]);
-      t.B2 = a2[j] + c * (t.B2 - a2[j]);
+      const double u0 = a0[j], u1 = a1[j], u2 = a2[j];
+      t.B0 = u0 + c * (t.B0 - u0);
+      t.B1 = u1 + c * (t.B1 - u1);
+      t.B2 = u2 + c * (t.B2 - u2);
       t.A *= c;
     }
     double p0, p1, p2;
@@ -214,15 +220,16 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
     for (int j = SEG - 1; j >= 0; --j) {
       if (xb + j >= W) continue;
       const double c = cc[j + 1];
-      p0 = a0[j] + c * (p0 - a0[j]); a0[j] = p0;
-      p1 = a1[j] + c * (p1 - a1[j]); a1[j] = p1;
-      p2 = a2[j] + c * (p2 - a2[j]); a2[j] = p2;
+      const double u0 = a0[j], u1 = a1[j], u2 = a2[j];
+      p0 = u0 + c * (p0 - u0); a0[j] = (float)p0;
+      p1 = u1 + c * (p1 - u1); a1[j] = (float)p1;
+      p2 = u2 + c * (p2 - u2); a2[j] = (float)p2;
     }
   }
 #pragma unroll
   for (int j = 0; j < SEG; ++j) {
     const int x = xb + j;
-    if (x < W) { v0[x] = (float)a0[j]; v1[x] = (float)a1[j]; v2[x] = (float)a2[j]; }
+    if (x < W) { v0[x] = a0[j]; v1[x] = a1[j]; v2[x] = a2[j]; }
   }
   __syncthreads();
   for (int x = tid; x < W; x += NT) {
