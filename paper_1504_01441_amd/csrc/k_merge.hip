@@ -243,8 +243,19 @@ __device__ inline float expand_col(const float* col, int lj, bool even) {
               : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
 }
 
+__device__ inline float4 expand_col4(const float* col, int lj, bool even) {
+  const float4 m = *reinterpret_cast<const float4*>(col + lj * kBW);
+  const float4 p = *reinterpret_cast<const float4*>(col + (lj + 1) * kBW);
+  if (even) {
+    const float4 a = *reinterpret_cast<const float4*>(col + (lj - 1) * kBW);
+    return make_float4((a.x + 6.f * m.x + p.x) / 8.f, (a.y + 6.f * m.y + p.y) / 8.f,
+                       (a.z + 6.f * m.z + p.z) / 8.f, (a.w + 6.f * m.w + p.w) / 8.f);
+  }
+  return make_float4((m.x + p.x) / 2.f, (m.y + p.y) / 2.f, (m.z + p.z) / 2.f, (m.w + p.w) / 2.f);
+}
+
 __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int cg, int w, int h,
-                                               int cw, int chh, int top) {
+                                               int cw, int chh, int top, int vec) {
   extern __shared__ float sm[];
   const int tid = threadIdx.x;
   int bx, by;
@@ -283,6 +294,48 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
                                     : (row[li] + row[li + 1]) / 2.f;
     }
     __syncthreads();
+  }
+  if (vec) {
+    // rows of 16-byte aligned planes, width a multiple of 4: a thread owns four
+    // consecutive pixels of one row (float4 loads and stores)
+    const int xq = 4 * (tid & 15), y = oy + (tid >> 4);
+    const int x = ox + xq;
+    if (x >= w || y >= h) return;
+    const size_t o = (size_t)y * w + x;
+    const int lj = (y >> 1) - cy0;
+    const bool even = (y & 1) == 0;
+    float4 acc[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) acc[cc] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = 0; k < n; ++k) {
+      const float4 wv = *reinterpret_cast<const float4*>(b.w[k] + o);
+      float4 gv[3];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        gv[cc] = cc < cg ? *reinterpret_cast<const float4*>(b.g[k][c0 + cc] + o)
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        if (cc >= cg) break;
+        const float4 e = top ? make_float4(0.f, 0.f, 0.f, 0.f)
+                             : expand_col4(rx + (cc * (n + 1) + k) * kCH * kBW + xq, lj, even);
+        acc[cc].x += wv.x * (gv[cc].x - e.x);
+        acc[cc].y += wv.y * (gv[cc].y - e.y);
+        acc[cc].z += wv.z * (gv[cc].z - e.z);
+        acc[cc].w += wv.w * (gv[cc].w - e.w);
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      if (cc >= cg) break;
+      float4 v = acc[cc];
+      if (!top) {
+        const float4 e = expand_col4(rx + (cc * (n + 1) + n) * kCH * kBW + xq, lj, even);
+        v.x += e.x; v.y += e.y; v.z += e.z; v.w += e.w;
+      }
+      *reinterpret_cast<float4*>(b.out[c0 + cc] + o) = v;
+    }
+    return;
   }
   // thread = one column of the tile (lanes are consecutive pixels), 4 rows
   const int fx = tid & 63, fy0 = tid >> 6;
@@ -431,8 +484,16 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     for (int c0 = 0; c0 < ch; c0 += cg) {
       const int g = min(cg, ch - c0);
       const size_t lds = top ? 0 : (size_t)(n + 1) * g * per_plane;
+      // float4 path: width a multiple of 4 and every plane 16-byte aligned
+      bool vec = lw[l] % 4 == 0;
+      auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+      for (int k = 0; k < n && vec; ++k) {
+        vec = vec && al(bp.w[k]);
+        for (int c = c0; c < c0 + g; ++c) vec = vec && al(bp.g[k][c]);
+      }
+      for (int c = c0; c < c0 + g; ++c) vec = vec && al(bp.out[c]);
       LNR_LAUNCH(k_blend, dim3((lw[l] + kBW - 1) / kBW, (lh[l] + kBH - 1) / kBH), dim3(256),
-                 lds, st, bp, n, c0, g, lw[l], lh[l], cw, chh, top);
+                 lds, st, bp, n, c0, g, lw[l], lh[l], cw, chh, top, vec ? 1 : 0);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
