@@ -267,10 +267,10 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
   float* rx = sm + nm * kCH * kCW;        // [nm][kCH][kBW] expanded along x
   if (!top) {
     const int ntot = nm * kCH * kCW;
-    for (int i0 = tid; i0 < ntot; i0 += 4 * 256) {  // four loads in flight per thread
-      float v[4];
+    for (int i0 = tid; i0 < ntot; i0 += 12 * 256) {  // twelve loads in flight per thread
+      float v[12];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 12; ++u) {
         const int i = i0 + 256 * u;
         v[u] = 0.f;
         if (i < ntot) {
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 12; ++u)
         if (i0 + 256 * u < ntot) ct[i0 + 256 * u] = v[u];
     }
     __syncthreads();

@@ -399,7 +399,7 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
   // levels, small windows), split the patch rows so that a tile keeps about
   // 256 threads busy
   const int base = sh.ncand * sh.nstrips;
-  sh.split = (long long)ntx * nty * base >= 65536 ? 1 : (256 + base / 2) / base;
+  sh.split = (long long)ntx * nty * base >= 262144 ? 1 : (256 + base / 2) / base;
   if (sh.split < 1) sh.split = 1;
   if (sh.split > 7) sh.split = 7;
   if (sh.split > 2 * c.P + 1) sh.split = 2 * c.P + 1;
