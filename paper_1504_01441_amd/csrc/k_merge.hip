@@ -3,13 +3,14 @@
 // between the equalised reference and each warped frame (Wang et al.:
 // Gaussian window, five filterings), blended with Laplacian pyramids.
 //
-//  k_ssim:    32x16 output tile; the two luma maps (+ halo) are staged in LDS,
-//             the five horizontal Gaussian sums are kept in LDS, then the
-//             vertical sums give SSIM. The sums are double precision: SSIM
+//  k_ssim:    4 output rows x (256 - 2r) columns per block: the vertical
+//             Gaussian sums of each input column are built in registers, the
+//             horizontal ones from LDS. The sums are double precision: SSIM
 //             divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat
 //             regions) and the fusion weights amplify them again.
 //  k_weights: per pixel, every frame's C * S * E (* max(SSIM, 0)) + 1e-12,
-//             normalised over the frames.
+//             normalised over the frames; threads walk down columns so that
+//             the Laplacian's rows are read once.
 //  k_reduce:  REDUCE ([1 4 6 4 1]/16 separable, clamped, even samples) of
 //             every weight and image plane of one level, through LDS.
 //  k_blend:   from the top level down, R_l = sum_k W_k,l (G_k,l - E(G_k,l+1))
@@ -28,150 +29,183 @@ struct FramePtrs {
 };
 
 constexpr int kMaxMaps = 64;
-constexpr int kSsimTW = 32, kSsimTH = 16, kSsimMaxR = 8;
+constexpr int kSsimMaxR = 8, kSsimTH = 4;
 
-// The five Gaussian sums (x, y, x^2, y^2, xy) are accumulated in double
-// precision: SSIM divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat
-// regions) and the fusion weights amplify them again near SSIM = 0, so float
-// sums of E[x^2] - E[x]^2 are not accurate enough there.
+// normalised Gaussian window taps g[0 .. 2r]
+struct SsimWin {
+  double g[2 * kSsimMaxR + 1];
+};
+
+// One block: kSsimTH output rows by 256 - 2R output columns. The five
+// Gaussian sums (x, y, x^2, y^2, xy) are accumulated in double precision:
+// SSIM divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat regions)
+// and the fusion weights amplify them again near SSIM = 0, so float sums of
+// E[x^2] - E[x]^2 are not accurate enough there.
+//  1. vertical: thread t owns input column ox - R + t (clamped) and reads its
+//     kSsimTH + 2R rows straight from global memory (a wave reads 64
+//     consecutive floats per row); each row's values and products are
+//     scattered into the kSsimTH outputs they belong to, all in registers;
+//  2. the vertical sums go to LDS, and thread t (< 256 - 2R) takes the
+//     horizontal window of output column t for every row of the tile.
+template <int R>
 __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
-                                              const float* __restrict__ b, int W, int H, int r,
-                                              double sigma, double c1, double c2,
+                                              const float* __restrict__ b, int W, int H,
+                                              SsimWin win, double c1, double c2,
                                               float* __restrict__ out) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int tid = threadIdx.x;
-  const int rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
-  const int n5 = rows * kSsimTW;
-  double* hv = reinterpret_cast<double*>(smem);                  // [5][rows][TW]
-  float* sa = reinterpret_cast<float*>(hv + 5 * n5);            // [rows][cols]
-  float* sb = sa + rows * cols;
-  __shared__ double gw[2 * kSsimMaxR + 1];
-  if (tid == 0) {
-    double g[2 * kSsimMaxR + 1], s = 0;
-    for (int k = -r; k <= r; ++k) {
-      g[k + r] = exp(-(double)(k * k) / (2.0 * sigma * sigma));
-      s += g[k + r];
-    }
-    for (int k = 0; k <= 2 * r; ++k) gw[k] = g[k] / s;
-  }
+  constexpr int TW = 256 - 2 * R, NR = kSsimTH + 2 * R;
+  __shared__ double vs[5][kSsimTH][256];
   int bx, by;
   xcd_block(gridDim.x, gridDim.y, bx, by);
-  const int ox = bx * kSsimTW, oy = by * kSsimTH;
-#pragma unroll 4
-  for (int i = tid; i < rows * cols; i += 256) {
-    const int yy = i / cols, xx = i % cols;
-    const int gy = min(max(oy + yy - r, 0), H - 1), gx = min(max(ox + xx - r, 0), W - 1);
-    sa[i] = a[(size_t)gy * W + gx];
-    sb[i] = b[(size_t)gy * W + gx];
-  }
-  __syncthreads();
-  for (int i = tid; i < n5; i += 256) {
-    const int yy = i / kSsimTW, xx = i % kSsimTW;
-    double m1 = 0, m2 = 0, s11 = 0, s22 = 0, s12 = 0;
-    const float* ra = sa + yy * cols + xx;
-    const float* rb = sb + yy * cols + xx;
-    for (int k = 0; k <= 2 * r; ++k) {
-      const double p = ra[k], q = rb[k], wd = gw[k];
-      m1 += wd * p;
-      m2 += wd * q;
-      s11 += wd * (p * p);
-      s22 += wd * (q * q);
-      s12 += wd * (p * q);
-    }
-    hv[i] = m1; hv[n5 + i] = m2; hv[2 * n5 + i] = s11; hv[3 * n5 + i] = s22; hv[4 * n5 + i] = s12;
-  }
-  __syncthreads();
-  // vertical sums: a thread owns two consecutive output rows of one column,
-  // so 2r + 2 horizontal sums serve both
+  const int tid = threadIdx.x;
+  const int ox = bx * TW, oy = by * kSsimTH;
   {
-    const int xx = tid % kSsimTW, yy = 2 * (tid / kSsimTW);  // rows yy, yy + 1
-    double acc[2][5];
+    const int gx = min(max(ox - R + tid, 0), W - 1);
+    float pa[NR], pb[NR];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int i = 0; i < NR; ++i) {  // every load in flight before the sums
+      const size_t o = (size_t)min(max(oy - R + i, 0), H - 1) * W + gx;
+      pa[i] = a[o];
+      pb[i] = b[o];
+    }
+    double acc[kSsimTH][5];
 #pragma unroll
-      for (int t = 0; t < 5; ++t) acc[q][t] = 0.0;
-    for (int k = 0; k <= 2 * r + 1; ++k) {
-      const int j = (yy + k) * kSsimTW + xx;
-      double hvv[5];
+    for (int o = 0; o < kSsimTH; ++o)
 #pragma unroll
-      for (int t = 0; t < 5; ++t) hvv[t] = hv[t * n5 + j];
-      if (k <= 2 * r) {
-        const double wd = gw[k];
+      for (int t = 0; t < 5; ++t) acc[o][t] = 0.0;
 #pragma unroll
-        for (int t = 0; t < 5; ++t) acc[0][t] += wd * hvv[t];
-      }
-      if (k >= 1) {
-        const double wd = gw[k - 1];
+    for (int i = 0; i < NR; ++i) {
+      const double p = pa[i], q = pb[i];
+      const double pp = p * p, qq = q * q, pq = p * q;
 #pragma unroll
-        for (int t = 0; t < 5; ++t) acc[1][t] += wd * hvv[t];
+      for (int o = 0; o < kSsimTH; ++o) {
+        const int k = i - o;  // tap of input row oy - R + i for output row oy + o
+        if (k < 0 || k > 2 * R) continue;
+        const double wd = win.g[k];
+        acc[o][0] += wd * p;
+        acc[o][1] += wd * q;
+        acc[o][2] += wd * pp;
+        acc[o][3] += wd * qq;
+        acc[o][4] += wd * pq;
       }
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int gy = oy + yy + q, gx = ox + xx;
-      if (gy >= H || gx >= W) continue;
-      const double m1 = acc[q][0], m2 = acc[q][1];
-      const double vx = acc[q][2] - m1 * m1, vy = acc[q][3] - m2 * m2, cxy = acc[q][4] - m1 * m2;
-      out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
-                                         ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
+    for (int o = 0; o < kSsimTH; ++o)
+#pragma unroll
+      for (int t = 0; t < 5; ++t) vs[t][o][tid] = acc[o][t];
+  }
+  __syncthreads();
+  const int gx = ox + tid;
+  if (tid >= TW || gx >= W) return;
+#pragma unroll
+  for (int o = 0; o < kSsimTH; ++o) {
+    const int gy = oy + o;
+    if (gy >= H) break;
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) {
+      const double wd = win.g[k];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) s[t] += wd * vs[t][o][tid + k];
     }
+    const double m1 = s[0], m2 = s[1];
+    const double vx = s[2] - m1 * m1, vy = s[3] - m2 * m2, cxy = s[4] - m1 * m2;
+    out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
+                                       ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
   }
 }
 
-__device__ inline double grey_at(const float* I, int ch, size_t plane, size_t o) {
-  return ch == 3 ? (0.299 * (double)I[o] + 0.587 * (double)I[plane + o]) + 0.114 * (double)I[2 * plane + o]
-                 : (double)I[o];
+__device__ inline double grey_of(int ch, float r, float g, float b) {
+  return ch == 3 ? (0.299 * (double)r + 0.587 * (double)g) + 0.114 * (double)b : (double)r;
 }
 
-// C * S * E (* max(SSIM, 0)) of frame k at one pixel. Contrast and saturation
-// are differences of nearly equal values in flat regions, and the normalised
-// weights divide by their sum, which can be ~1e-12 there: they are evaluated
-// in double precision.
-__device__ inline double raw_weight(const FramePtrs& f, int k, int ch, int ref, size_t plane,
-                                    size_t o, size_t oU, size_t oL, size_t oR, size_t oD,
-                                    float two_se2) {
-  const float* I = f.img[k];
-  const double lap = grey_at(I, ch, plane, oU) + grey_at(I, ch, plane, oL) +
-                     grey_at(I, ch, plane, oR) + grey_at(I, ch, plane, oD) -
-                     4.0 * grey_at(I, ch, plane, o);
-  const double C = fabs(lap);
+// C * S * E (* max(SSIM, 0)) of one frame at one pixel, from the grey values
+// of the pixel (gc) and its four neighbours, and the pixel's colour. Contrast
+// and saturation are differences of nearly equal values in flat regions, and
+// the normalised weights divide by their sum, which can be ~1e-12 there: they
+// are evaluated in double precision.
+__device__ inline double raw_weight(int ch, double gu, double gl, double gr, double gd,
+                                    double gc, float R, float G, float B, bool warped,
+                                    float ssim, float two_se2) {
+  const double C = fabs(gu + gl + gr + gd - 4.0 * gc);
   double S = 1.0;
   float e;
   if (ch == 3) {
-    const double R = I[o], G = I[plane + o], B = I[2 * plane + o];
-    const double mu = (R + G + B) * (1.0 / 3.0);
-    const double var = ((R - mu) * (R - mu) + (G - mu) * (G - mu) + (B - mu) * (B - mu)) * (1.0 / 3.0);
+    const double r = R, g = G, b = B;
+    const double mu = (r + g + b) * (1.0 / 3.0);
+    const double var = ((r - mu) * (r - mu) + (g - mu) * (g - mu) + (b - mu) * (b - mu)) * (1.0 / 3.0);
     S = (double)sqrtf((float)var);  // the cancelling differences are in double
-    e = (float)((R - 0.5) * (R - 0.5) + (G - 0.5) * (G - 0.5) + (B - 0.5) * (B - 0.5));
+    e = (float)((r - 0.5) * (r - 0.5) + (g - 0.5) * (g - 0.5) + (b - 0.5) * (b - 0.5));
   } else {
-    e = (float)((I[o] - 0.5) * (I[o] - 0.5));
+    e = (float)(((double)R - 0.5) * ((double)R - 0.5));
   }
   double wt = C * S * (double)expf(-e / two_se2);
-  if (k != ref) wt *= fmax((double)f.ssim[k][o], 0.0);
+  if (warped) wt *= fmax((double)ssim, 0.0);
   return wt + 1e-12;
 }
 
+constexpr int kWeightRows = 8;
+
+// Each thread walks down kWeightRows rows of one column: the grey values of
+// the rows above, at and below the pixel stay in registers, so every colour
+// sample is fetched from memory once (the left / right neighbours come from
+// the same cache lines as the neighbouring threads' own pixels).
+template <int NMAX>
 __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int W, int H,
                                                  int ref, float two_se2) {
-  int bx, y;
-  xcd_block(gridDim.x, gridDim.y, bx, y);  // rows y - 1, y, y + 1 in one L2
-  const int x = bx * blockDim.x + threadIdx.x;
+  int bx, by;
+  xcd_block(gridDim.x, gridDim.y, bx, by);
+  const int x = bx * 256 + threadIdx.x;
   if (x >= W) return;
-  const size_t plane = (size_t)W * H, o = (size_t)y * W + x;
-  const size_t oU = (size_t)max(y - 1, 0) * W + x, oD = (size_t)min(y + 1, H - 1) * W + x;
-  const size_t oL = (size_t)y * W + max(x - 1, 0), oR = (size_t)y * W + min(x + 1, W - 1);
-  // the raw weights keep 24-bit relative precision as floats once the
-  // cancelling differences inside them were taken in double precision
-  float wk[16];  // n <= 16; kept in registers (every index is a constant)
-  double sum = 0.0;
+  const int y0 = by * kWeightRows, y1 = min(y0 + kWeightRows, H);
+  const size_t plane = (size_t)W * H;
+  const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
+  auto ld = [&](const float* I, size_t o, float& r, float& g, float& b) {
+    r = I[o];
+    g = ch == 3 ? I[plane + o] : 0.f;
+    b = ch == 3 ? I[2 * plane + o] : 0.f;
+  };
+  double gu[NMAX], gc[NMAX];
+  float cr[NMAX], cg[NMAX], cb[NMAX];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    wk[k] = k < n ? (float)raw_weight(f, k, ch, ref, plane, o, oU, oL, oR, oD, two_se2) : 0.f;
-    sum += (double)wk[k];
+  for (int k = 0; k < NMAX; ++k) {
+    if (k >= n) continue;
+    float r, g, b;
+    ld(f.img[k], (size_t)max(y0 - 1, 0) * W + x, r, g, b);
+    gu[k] = grey_of(ch, r, g, b);
+    ld(f.img[k], (size_t)y0 * W + x, cr[k], cg[k], cb[k]);
+    gc[k] = grey_of(ch, cr[k], cg[k], cb[k]);
   }
+  for (int y = y0; y < y1; ++y) {
+    const size_t o = (size_t)y * W + x, od = (size_t)min(y + 1, H - 1) * W + x;
+    const size_t ol = (size_t)y * W + xl, orr = (size_t)y * W + xr;
+    // the raw weights keep 24-bit relative precision as floats once the
+    // cancelling differences inside them were taken in double precision
+    float wk[NMAX];
+    double sum = 0.0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (k < n) f.wout[k][o] = (float)((double)wk[k] / sum);
+    for (int k = 0; k < NMAX; ++k) {
+      if (k >= n) continue;
+      const float* I = f.img[k];
+      float dr, dg, db, lr, lg, lb, rr, rg, rb;
+      ld(I, od, dr, dg, db);
+      ld(I, ol, lr, lg, lb);
+      ld(I, orr, rr, rg, rb);
+      const bool warped = k != ref;
+      const float sv = warped ? f.ssim[k][o] : 0.f;
+      const double gd = grey_of(ch, dr, dg, db);
+      wk[k] = (float)raw_weight(ch, gu[k], grey_of(ch, lr, lg, lb), grey_of(ch, rr, rg, rb), gd,
+                                gc[k], cr[k], cg[k], cb[k], warped, sv, two_se2);
+      sum += (double)wk[k];
+      gu[k] = gc[k];
+      gc[k] = gd;
+      cr[k] = dr; cg[k] = dg; cb[k] = db;
+    }
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+      if (k >= n) continue;
+      f.wout[k][o] = (float)((double)wk[k] / sum);
+    }
+  }
 }
 
 struct MapPtrs {
@@ -427,16 +461,43 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     fp.ssim[k] = bufs.ssim + (size_t)k * N;
     fp.wout[k] = bufs.w0 + (size_t)k * N;
     if (k == ref_index) continue;
-    dim3 g((W + kSsimTW - 1) / kSsimTW, (H + kSsimTH - 1) / kSsimTH);
-    const int r = p.ssim_radius, rows = kSsimTH + 2 * r, cols = kSsimTW + 2 * r;
-    const size_t lds = (size_t)rows * kSsimTW * 5 * 8 + (size_t)rows * cols * 8;
-    LNR_LAUNCH(k_ssim, g, dim3(256), lds, st, yeqs[ref_index], yeqs[k], W, H,
-                       p.ssim_radius, p.ssim_sigma, p.ssim_c1, p.ssim_c2,
-                       bufs.ssim + (size_t)k * N);
+    const int r = p.ssim_radius;
+    SsimWin win;
+    double gs = 0.0;
+    for (int j = -r; j <= r; ++j) {
+      win.g[j + r] = exp(-(double)(j * j) / (2.0 * p.ssim_sigma * p.ssim_sigma));
+      gs += win.g[j + r];
+    }
+    for (int j = 0; j <= 2 * r; ++j) win.g[j] /= gs;
+    const int tw = 256 - 2 * r;
+    dim3 g((W + tw - 1) / tw, (H + kSsimTH - 1) / kSsimTH);
+    const float* ya = yeqs[ref_index];
+    const float* yb = yeqs[k];
+    float* so = bufs.ssim + (size_t)k * N;
+    switch (r) {
+#define SSIM_CASE(R_)                                                                          \
+  case R_:                                                                                     \
+    LNR_LAUNCH(k_ssim<R_>, g, dim3(256), 0, st, ya, yb, W, H, win, p.ssim_c1, p.ssim_c2, so); \
+    break;
+      SSIM_CASE(1) SSIM_CASE(2) SSIM_CASE(3) SSIM_CASE(4)
+      SSIM_CASE(5) SSIM_CASE(6) SSIM_CASE(7) SSIM_CASE(8)
+#undef SSIM_CASE
+      default: return hipErrorInvalidValue;
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  LNR_LAUNCH(k_weights, dim3((W + 255) / 256, H), dim3(256), 0, st, fp, n, ch, W, H,
-                     ref_index, (float)(2.0 * p.sigma_e * p.sigma_e));
+  {
+    const dim3 g((W + 255) / 256, (H + kWeightRows - 1) / kWeightRows);
+    const float two_se2 = (float)(2.0 * p.sigma_e * p.sigma_e);
+    if (n <= 2)
+      LNR_LAUNCH(k_weights<2>, g, dim3(256), 0, st, fp, n, ch, W, H, ref_index, two_se2);
+    else if (n <= 4)
+      LNR_LAUNCH(k_weights<4>, g, dim3(256), 0, st, fp, n, ch, W, H, ref_index, two_se2);
+    else if (n <= 8)
+      LNR_LAUNCH(k_weights<8>, g, dim3(256), 0, st, fp, n, ch, W, H, ref_index, two_se2);
+    else
+      LNR_LAUNCH(k_weights<16>, g, dim3(256), 0, st, fp, n, ch, W, H, ref_index, two_se2);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // Gaussian pyramids of every weight and image plane
   const int maps = n * (ch + 1);

@@ -239,6 +239,26 @@ def test_merge_vs_oracle(ctx, n, ch, shape):
     assert_close(got.cpu().numpy(), want, 1.0, what="merge")
 
 
+@pytest.mark.parametrize("r,sigma", [(1, 0.7), (3, 1.0), (8, 2.5)])
+def test_merge_ssim_window_sizes(ctx, r, sigma):
+    """SSIM windows other than the default 11 x 11 (one kernel build per radius),
+    on a width that leaves a ragged last column tile."""
+    rng = np.random.default_rng(40 + r)
+    h, w = 133, 517
+    import scipy.ndimage as ndi
+    imgs = [np.clip(ndi.gaussian_filter(rng.uniform(0, 1, (3, h, w)), (0, 1.2, 1.2)) * 1.6 - 0.3,
+                    0, 1) for _ in range(2)]
+    yeqs = [np.clip(ndi.gaussian_filter(rng.uniform(0, 1, (h, w)), 1.0) * 2 - 0.5, 0, 1)
+            for _ in range(2)]
+    p, op = params_pair(ssim_radius=r, ssim_sigma=sigma)
+    got = lnr().stage_merge(ctx, [_t(i.astype(np.float32)) for i in imgs],
+                            [_t(y.astype(np.float32)) for y in yeqs], 0, p)
+    _sync()
+    want = oracle.merge([i.astype(np.float32).astype(np.float64) for i in imgs],
+                        [y.astype(np.float32).astype(np.float64) for y in yeqs], 0, op)
+    assert_close(got.cpu().numpy(), want, 1.0, what="merge")
+
+
 # ------------------------------------------------------------------ end to end
 
 @pytest.mark.parametrize("seed", [1, 2])
