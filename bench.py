@@ -70,10 +70,8 @@ def algo_bytes_per_step(W, H, fmt_i420, n, ch, reg_sizes, blend_levels, launches
             add(base, cnt * 25 * N)
         elif base == "k_bwarp":         # F, Y, UV, Y_eq in; RGB + warped Y_eq out
             add(base, cnt * (8 + 1 + chroma + 1 + 4 * ch + 4) * N)
-        elif base == "k_frame_rgb":
-            add(base, cnt * (1 + chroma + 4 * ch) * N)
-        elif base == "k_u8_unit":
-            add(base, cnt * 5 * N)
+        elif base == "k_frame_rgb4":    # reference YUV in, RGB out; equalised luma u8 in, f32 out
+            add(base, cnt * (1 + chroma + 4 * ch + 1 + 4) * N)
         elif base == "k_ssim":          # two luma maps in, SSIM out
             add(base, cnt * 12 * N)
         elif base == "k_weights":       # all frames' planes + SSIM in, weights out

@@ -31,8 +31,15 @@ struct DtArgs {
 
 // c_i[k] = a_i ^ (1 + ratio * k / 255),  a_i = exp(-sqrt(2) / sigma_i),
 // sigma_i = sigma_s sqrt(3) 2^(n - i) / sqrt(4^n - 1)  (i = 1..n)
-__global__ void k_dt_coef(DtArgs a, double* __restrict__ coef) {
+// Block 0 also clears zero[0, nzero) and sets ident to the identity (the
+// registration's first launch does this set-up with the tables).
+__global__ void k_dt_coef(DtArgs a, double* __restrict__ coef, uint32_t* __restrict__ zero,
+                          int nzero, double* __restrict__ ident) {
   const int i = blockIdx.x + 1, k = threadIdx.x;
+  if (blockIdx.x == 0) {
+    for (int j = k; j < nzero; j += 256) zero[j] = 0u;
+    if (ident && k < 9) ident[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  }
   const double sig = a.sigma_s * sqrt(3.0) * pow(2.0, (double)(a.iters - i)) /
                      sqrt(pow(4.0, (double)a.iters) - 1.0);
   const double ai = exp(-sqrt(2.0) / sig);
@@ -114,6 +121,8 @@ __device__ inline double coef_at(const double* cf, int gprev, int gcur) {
   return cf[abs(gcur - gprev)];
 }
 
+constexpr int kStageU = 4;
+
 // ---------------------------------------------------------------------------
 // Horizontal pass: one block per row; the row is staged in LDS (coalesced),
 // each thread keeps a segment of SEG consecutive pixels in registers.
@@ -135,12 +144,27 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
   const int y = blockIdx.x, tid = threadIdx.x;
   const size_t plane = (size_t)W * H, ro = (size_t)y * W;
   if (tid < 256) cf[tid] = coef[tid];
-  for (int x = tid; x < W; x += NT) {
-    g[x] = guide[ro + x];
-    if (FIRST) {
-      v0[x] = 0.f; v1[x] = 0.f; v2[x] = 0.f;
-    } else {
-      v0[x] = maps[ro + x]; v1[x] = maps[plane + ro + x]; v2[x] = maps[2 * plane + ro + x];
+  // staging: several loads in flight per thread (batches of kStageU per
+  // thread, issued before the LDS stores)
+  for (int x0 = 0; x0 < W; x0 += kStageU * NT) {
+    uint8_t tg[kStageU];
+    float t0[kStageU], t1[kStageU], t2[kStageU];
+#pragma unroll
+    for (int u = 0; u < kStageU; ++u) {
+      const int xc = min(x0 + u * NT + tid, W - 1);  // in bounds; stored only if x < W
+      tg[u] = guide[ro + xc];
+      if (!FIRST) {
+        t0[u] = maps[ro + xc]; t1[u] = maps[plane + ro + xc]; t2[u] = maps[2 * plane + ro + xc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kStageU; ++u) {
+      const int x = x0 + u * NT + tid;
+      if (x >= W) break;
+      g[x] = tg[u];
+      v0[x] = FIRST ? 0.f : t0[u];
+      v1[x] = FIRST ? 0.f : t1[u];
+      v2[x] = FIRST ? 0.f : t2[u];
     }
   }
   if (FIRST) {
@@ -232,6 +256,7 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
     if (x < W) { v0[x] = a0[j]; v1[x] = a1[j]; v2[x] = a2[j]; }
   }
   __syncthreads();
+#pragma unroll 4
   for (int x = tid; x < W; x += NT) {
     maps[ro + x] = v0[x]; maps[plane + ro + x] = v1[x]; maps[2 * plane + ro + x] = v2[x];
   }
@@ -492,18 +517,25 @@ DtShape dt_default_shape(int W, int H) {
   return s;
 }
 
-hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
-                       int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
-                       const lnr_params& p, float* maps, double* coef, float* flow,
-                       float* ntilde, hipStream_t st, const DtShape* shape) {
+hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int nzero,
+                          double* ident, hipStream_t st) {
   DtArgs a;
   a.iters = p.dt_iters;
   a.sigma_s = p.sigma_s;
   a.ratio = p.sigma_s / p.sigma_r;
+  LNR_LAUNCH(k_dt_coef, dim3(a.iters), dim3(256), 0, st, a, coef, zero, nzero, ident);
+  return hipGetLastError();
+}
+
+hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
+                       int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
+                       const lnr_params& p, float* maps, double* coef, float* flow,
+                       float* ntilde, hipStream_t st, const DtShape* shape, bool coef_ready) {
+  DtArgs a;
+  a.iters = p.dt_iters;
   const DtShape sh = shape && dt_shape_valid(*shape, W, H) ? *shape : dt_default_shape(W, H);
-  LNR_LAUNCH(k_dt_coef, dim3(a.iters), dim3(256), 0, st, a, coef);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (!coef_ready && (e = launch_dt_coef(p, coef, nullptr, 0, nullptr, st)) != hipSuccess) return e;
   const double nmin = p.n_min;
   for (int i = 0; i < a.iters; ++i) {
     const double* cf = coef + 256 * i;

@@ -2,17 +2,17 @@
 // every input before matching: paper Sec. 3 opening) and the matching pyramid
 // (Sec. 2.2 / 2.6: up to 5 levels, 2x2 box mean rounded half up).
 //
-// k_hist: LDS histograms (16 copies; a wave per row, 32-bit loads), one global
-// atomic add per bin per block.
-// k_lut_pyr: each block rebuilds the 256-entry LUT from the histogram (prefix
-// sum in LDS), equalises a 64x64 block of Y and writes pyramid levels 1..L-1
+// k_hist: LDS histograms (16 copies; a wave per row, two rows per wave, 32-bit
+// loads), one global atomic add per bin per block.
+// k_lut_pyr: each block rebuilds the 256-entry LUT from the histogram (wave
+// prefix sums), equalises a 64x64 block of Y and writes pyramid levels 1..L-1
 // of that block from LDS, so the pyramid costs no extra pass over HBM.
 #include "lnr_internal.h"
 
 namespace lnr {
 namespace {
 
-constexpr int kHistRows = 4;  // rows per block, one wave per row
+constexpr int kHistRows = 8;  // rows per block, two per wave
 
 constexpr int kCopies = 16, kCopyStride = 257;  // odd stride: copies hit different banks
 
@@ -28,8 +28,8 @@ __global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ y0, in
   const uint8_t* img = blockIdx.y ? y1 : y0;
   const int stride = blockIdx.y ? s1 : s0;
   uint32_t* mine = bins + (lane & (kCopies - 1)) * kCopyStride;
-  const int row = blockIdx.x * kHistRows + wave;
-  if (row < H) {
+  for (int row = blockIdx.x * kHistRows + wave; row < min(H, (blockIdx.x + 1) * kHistRows);
+       row += 4) {
     // the row as aligned 32-bit words plus unaligned head and tail bytes
     const uint8_t* p = img + (size_t)row * stride;
     const int head = min(W, (int)((4 - ((uintptr_t)p & 3)) & 3));
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ y0, in
     for (int i0 = lane; i0 < nw; i0 += 64 * 4) {
       uint32_t v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = i0 + 64 * u < nw ? pw[i0 + 64 * u] : 0u;
+      for (int u = 0; u < 4; ++u) v[u] = pw[min(i0 + 64 * u, nw - 1)];  // in bounds, used if < nw
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (i0 + 64 * u < nw) {
@@ -59,26 +59,38 @@ __global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ y0, in
 }
 
 // LUT[v] = round-half-up(255 (cdf[v] - cdf_min) / (n - cdf_min)), cdf_min the
-// cdf at the first occupied bin; identity when the image has one value.
-__device__ void build_lut(const uint32_t* __restrict__ hist, uint8_t* lut, uint32_t* scan) {
-  const int v = threadIdx.x;
-  scan[v] = hist[v];
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    uint32_t add = v >= off ? scan[v - off] : 0u;
-    __syncthreads();
-    scan[v] += add;
-    __syncthreads();
+// cdf at the first occupied bin; identity when the image has one value. The
+// cdf is a wave scan per 64 bins plus the wave totals.
+__device__ void build_lut(const uint32_t* __restrict__ hist, uint8_t* lut) {
+  __shared__ uint32_t wsum[4];
+  __shared__ int wfirst[4];
+  const int v = threadIdx.x, lane = v & 63, wave = v >> 6;
+  const uint32_t h = hist[v];
+  uint32_t incl = h;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
   }
-  __shared__ uint32_t c0s;
-  const uint32_t cdf = scan[v];
-  const uint32_t prev = v ? scan[v - 1] : 0u;
-  if (cdf != 0u && prev == 0u) c0s = cdf;  // exactly one bin is the first occupied
+  const unsigned long long occ = __ballot(h != 0u);
+  if (lane == 63) {
+    wsum[wave] = incl;
+    wfirst[wave] = occ ? wave * 64 + __ffsll((long long)occ) - 1 : 256;
+  }
   __syncthreads();
-  const int64_t n = scan[255], c0 = c0s;
+  uint32_t before = 0, n = 0;
+  int first = 256;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    before += q < wave ? wsum[q] : 0u;
+    n += wsum[q];
+    first = min(first, wfirst[q]);
+  }
+  const uint32_t cdf = before + incl;
+  const int64_t c0 = first < 256 ? (int64_t)hist[first] : 0;  // cdf at the first occupied bin
   int64_t num = (int64_t)cdf - c0;
   if (num < 0) num = 0;
-  const int64_t den = n - c0;
+  const int64_t den = (int64_t)n - c0;
   lut[v] = den == 0 ? (uint8_t)v : (uint8_t)((2 * 255 * num + den) / (2 * den));
   __syncthreads();
 }
@@ -94,36 +106,63 @@ __global__ __launch_bounds__(256) void k_lut_pyr(const uint8_t* __restrict__ y0,
                                                  const uint32_t* __restrict__ hist,
                                                  LevelGeom g, uint8_t* __restrict__ pyr0,
                                                  uint8_t* __restrict__ pyr1,
-                                                 uint8_t* __restrict__ lut_out) {
-  __shared__ uint32_t scan[256];
+                                                 uint8_t* __restrict__ lut_out,
+                                                 uint8_t* __restrict__ out0,
+                                                 uint8_t* __restrict__ out1) {
   __shared__ uint8_t lut[256];
   __shared__ uint8_t tileA[64 * 64];
   __shared__ uint8_t tileB[32 * 32];
   const int f = blockIdx.z, tid = threadIdx.x;
-  build_lut(hist + f * 256, lut, scan);
+  build_lut(hist + f * 256, lut);
   if (lut_out && blockIdx.x == 0 && blockIdx.y == 0) lut_out[f * 256 + tid] = lut[tid];
   const uint8_t* img = f ? y1 : y0;
   const int stride = f ? s1 : s0;
   uint8_t* pyr = f ? pyr1 : pyr0;
+  uint8_t* cpy = f ? out1 : out0;  // optional second copy of level 0
   const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
   const int W = g.w[0], H = g.h[0];
-  // level 0: 64 x 64 block, 16 pixels per thread (4 bytes x 4 rows)
-  for (int i = tid; i < 64 * 16; i += 256) {
-    const int r = i >> 4, c4 = (i & 15) * 4;
-    const int y = by + r;
-    uint32_t packed = 0;
-    if (y < H) {
-      const uint8_t* src = img + (size_t)y * stride;
-      uint8_t* dst = pyr + g.off[0] + (size_t)y * W;
+  // level 0: 64 x 64 block, four 4-byte groups per thread (one 32-bit load
+  // and store each where the row allows, all loads in flight first)
+  uint32_t raw[4];
+  bool wide[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int x = bx + c4 + k;
-        if (x < W) {
-          const uint8_t e = lut[src[x]];
-          dst[x] = e;
-          packed |= (uint32_t)e << (8 * k);
+  for (int u = 0; u < 4; ++u) {
+    const int i = tid + 256 * u;
+    const int r = i >> 4, c4 = (i & 15) * 4;
+    const int y = min(by + r, H - 1), x = bx + c4;
+    const uint8_t* src = img + (size_t)y * stride + x;
+    wide[u] = x + 4 <= W && ((reinterpret_cast<uintptr_t>(src) & 3u) == 0);
+    raw[u] = 0u;
+    if (wide[u]) {
+      raw[u] = *reinterpret_cast<const uint32_t*>(src);
+    } else {
+      for (int k = 0; k < 4; ++k)
+        if (x + k < W) raw[u] |= (uint32_t)src[k] << (8 * k);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = tid + 256 * u;
+    const int r = i >> 4, c4 = (i & 15) * 4;
+    const int y = by + r, x = bx + c4;
+    uint32_t packed = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (x + k < W) packed |= (uint32_t)lut[(raw[u] >> (8 * k)) & 255u] << (8 * k);
+    if (y < H) {
+      for (int c = 0; c < 2; ++c) {
+        uint8_t* dst = c == 0 ? pyr + g.off[0] + (size_t)y * W + x
+                              : (cpy ? cpy + (size_t)y * W + x : nullptr);
+        if (!dst) break;
+        if (wide[u] && ((reinterpret_cast<uintptr_t>(dst) & 3u) == 0)) {
+          *reinterpret_cast<uint32_t*>(dst) = packed;
+        } else {
+          for (int k = 0; k < 4; ++k)
+            if (x + k < W) dst[k] = (uint8_t)(packed >> (8 * k));
         }
       }
+    } else {
+      packed = 0;
     }
     *reinterpret_cast<uint32_t*>(&tileA[r * 64 + c4]) = packed;
   }
@@ -164,7 +203,8 @@ hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int
 
 hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
                           const uint32_t* hist, const Geometry& geo, uint8_t* pyr0,
-                          uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st) {
+                          uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st,
+                          uint8_t* out0, uint8_t* out1) {
   LevelGeom g;
   g.levels = geo.levels;
   for (int l = 0; l < kMaxLevels; ++l) {
@@ -174,7 +214,7 @@ hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
   }
   dim3 grid((geo.W + 63) / 64, (geo.H + 63) / 64, nframes);
   LNR_LAUNCH(k_lut_pyr, grid, dim3(256), 0, st, y0, s0, y1, s1, hist, g, pyr0, pyr1,
-                     lut_out);
+                     lut_out, out0, out1);
   return hipGetLastError();
 }
 

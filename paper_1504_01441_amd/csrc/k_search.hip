@@ -61,9 +61,17 @@ __device__ inline uint32_t warp_px(const uint8_t* __restrict__ src, int w, int h
 }
 
 // Four consecutive pixels per thread, one 32-bit store when the row allows it.
+// Block (0, 0) also clears the level's valid-match bits vbz[0, nwords) and
+// least-squares sums (the search that follows fills the bits).
 __global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src, int w, int h,
                                                  const double* __restrict__ Hn,
-                                                 uint8_t* __restrict__ out) {
+                                                 uint8_t* __restrict__ out,
+                                                 unsigned long long* __restrict__ vbz, int nwords,
+                                                 long long* __restrict__ sums) {
+  if (vbz && blockIdx.x == 0 && blockIdx.y == 0) {
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) vbz[i] = 0ull;
+    if (threadIdx.x < 24) sums[threadIdx.x] = 0;
+  }
   const int x = 4 * (blockIdx.x * blockDim.x + threadIdx.x), y = blockIdx.y;
   if (x >= w) return;
   // every thread forms the pixel homography itself (uniform, no barrier)
@@ -137,7 +145,8 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
                                                  uint32_t* __restrict__ ssd_out,
                                                  uint8_t* __restrict__ flags,
                                                  const int32_t* __restrict__ centre,
-                                                 const uint8_t* __restrict__ mode, int want) {
+                                                 const uint8_t* __restrict__ mode, int want,
+                                                 unsigned long long* __restrict__ vb) {
   extern __shared__ __align__(16) uint8_t dyn[];
   __shared__ uint8_t reg[kRegion * kRegion];
   __shared__ uint32_t qsum[4 * 49];
@@ -373,6 +382,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - 64;
       ssd_out[tile] = (uint32_t)(b >> 32);
       flags[tile] = (uint8_t)(3 | (mode && want ? 16 : 0));
+      if (vb) atomicOr(vb + (tile >> 6), 1ull << (tile & 63));
     }
   }
 }
@@ -380,16 +390,18 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
 }  // namespace
 
 hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
-                          hipStream_t st) {
+                          hipStream_t st, const WeedBufs* wb, int nwords) {
   dim3 grid((w + 1023) / 1024, h);
-  LNR_LAUNCH(k_warp_q8, grid, dim3(256), 0, st, src, w, h, Hn, out);
+  LNR_LAUNCH(k_warp_q8, grid, dim3(256), 0, st, src, w, h, Hn, out, wb ? wb->vb : nullptr,
+             nwords, wb ? wb->sums : nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
                          int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st,
-                         const int32_t* centre, const uint8_t* mode, int want) {
+                         const int32_t* centre, const uint8_t* mode, int want,
+                         unsigned long long* vb) {
   if (ntx * nty == 0) return hipSuccess;
   SearchShape sh;
   sh.R = R;
@@ -415,7 +427,7 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
   const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
                      (sh.split > 1 ? (size_t)2 * sh.ncand * sh.nstrips * KX * 4 : 0);
   LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
-                     ntx, corner_xy, disp, ssd, flags, centre, mode, want);
+                     ntx, corner_xy, disp, ssd, flags, centre, mode, want, vb);
   return hipGetLastError();
 }
 

@@ -72,30 +72,75 @@ __global__ __launch_bounds__(256) void k_bwarp(const uint8_t* __restrict__ y, in
   img[2 * plane + o] = b;
 }
 
-__global__ __launch_bounds__(256) void k_frame_rgb(const uint8_t* __restrict__ y, int sy,
-                                                   const uint8_t* __restrict__ u, int su,
-                                                   const uint8_t* __restrict__ v, int sv, int W,
-                                                   int H, float* __restrict__ img) {
-  const int px = blockIdx.x * blockDim.x + threadIdx.x, py = blockIdx.y;
+// Four consecutive pixels per thread: 32-bit luma loads and 128-bit stores
+// where the row allows; with yin, the 8-bit plane yin is also mapped to
+// [0, 1] into yout (the merge's equalised reference luma).
+__global__ __launch_bounds__(256) void k_frame_rgb4(const uint8_t* __restrict__ y, int sy,
+                                                    const uint8_t* __restrict__ u, int su,
+                                                    const uint8_t* __restrict__ v, int sv, int W,
+                                                    int H, float* __restrict__ img,
+                                                    const uint8_t* __restrict__ yin,
+                                                    float* __restrict__ yout) {
+  int bx, py;
+  xcd_block(gridDim.x, gridDim.y, bx, py);
+  const int px = 4 * (bx * blockDim.x + threadIdx.x);
   if (px >= W) return;
   const size_t plane = (size_t)W * H, o = (size_t)py * W + px;
-  const float Yv = y[(size_t)py * sy + px];
-  if (!u) {
-    img[o] = Yv / 255.f;
-    return;
+  const uint8_t* yr = y + (size_t)py * sy + px;
+  const bool full = px + 4 <= W;
+  const bool vin = full && ((reinterpret_cast<uintptr_t>(yr) & 3u) == 0);
+  const bool vout = full && ((reinterpret_cast<uintptr_t>(img + o) & 15u) == 0);
+  float Yv[4], r[4], g[4], b[4];
+  if (vin) {
+    const uint32_t w4 = *reinterpret_cast<const uint32_t*>(yr);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Yv[k] = (float)((w4 >> (8 * k)) & 255u);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Yv[k] = px + k < W ? (float)yr[k] : 0.f;
   }
-  float r, g, b;
-  yuv_rgb(Yv, u[(size_t)(py >> 1) * su + (px >> 1)], v[(size_t)(py >> 1) * sv + (px >> 1)], r, g,
-          b);
-  img[o] = r;
-  img[plane + o] = g;
-  img[2 * plane + o] = b;
-}
-
-__global__ __launch_bounds__(256) void k_u8_unit(const uint8_t* __restrict__ in, size_t n,
-                                                 float* __restrict__ out) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = in[i] / 255.f;
+  if (u) {
+    const uint8_t* ur = u + (size_t)(py >> 1) * su + (px >> 1);
+    const uint8_t* vr = v + (size_t)(py >> 1) * sv + (px >> 1);
+    const int nc = full ? 2 : (W - px + 1) / 2;  // chroma samples of these pixels
+    float U[2] = {128.f, 128.f}, V[2] = {128.f, 128.f};
+    for (int c = 0; c < nc; ++c) {
+      U[c] = ur[c];
+      V[c] = vr[c];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) yuv_rgb(Yv[k], U[k >> 1], V[k >> 1], r[k], g[k], b[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = Yv[k] / 255.f;
+  }
+  if (vout) {
+    *reinterpret_cast<float4*>(img + o) = make_float4(r[0], r[1], r[2], r[3]);
+    if (u) {
+      *reinterpret_cast<float4*>(img + plane + o) = make_float4(g[0], g[1], g[2], g[3]);
+      *reinterpret_cast<float4*>(img + 2 * plane + o) = make_float4(b[0], b[1], b[2], b[3]);
+    }
+  } else {
+    for (int k = 0; k < 4 && px + k < W; ++k) {
+      img[o + k] = r[k];
+      if (u) {
+        img[plane + o + k] = g[k];
+        img[2 * plane + o + k] = b[k];
+      }
+    }
+  }
+  if (yin) {
+    const uint8_t* q = yin + o;
+    if (vout && ((reinterpret_cast<uintptr_t>(q) & 3u) == 0) &&
+        ((reinterpret_cast<uintptr_t>(yout + o) & 15u) == 0)) {
+      const uint32_t w4 = *reinterpret_cast<const uint32_t*>(q);
+      *reinterpret_cast<float4*>(yout + o) =
+          make_float4((float)(w4 & 255u) / 255.f, (float)((w4 >> 8) & 255u) / 255.f,
+                      (float)((w4 >> 16) & 255u) / 255.f, (float)(w4 >> 24) / 255.f);
+    } else {
+      for (int k = 0; k < 4 && px + k < W; ++k) yout[o + k] = q[k] / 255.f;
+    }
+  }
 }
 
 }  // namespace
@@ -110,17 +155,11 @@ hipError_t launch_backward_warp(const uint8_t* y, int sy, const uint8_t* u, int 
   return hipGetLastError();
 }
 
-hipError_t launch_frame_rgb(const uint8_t* y, int sy, const uint8_t* u, int su,
-                            const uint8_t* v, int sv, int W, int H, float* image,
-                            hipStream_t st) {
-  dim3 grid((W + 255) / 256, H);
-  LNR_LAUNCH(k_frame_rgb, grid, dim3(256), 0, st, y, sy, u, su, v, sv, W, H, image);
-  return hipGetLastError();
-}
-
-hipError_t launch_u8_to_unit(const uint8_t* in, int W, int H, float* out, hipStream_t st) {
-  const size_t n = (size_t)W * H;
-  LNR_LAUNCH(k_u8_unit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, n, out);
+hipError_t launch_frame_rgb_unit(const uint8_t* y, int sy, const uint8_t* u, int su,
+                                 const uint8_t* v, int sv, int W, int H, float* image,
+                                 const uint8_t* yin, float* yout, hipStream_t st) {
+  dim3 grid((W + 1023) / 1024, H);
+  LNR_LAUNCH(k_frame_rgb4, grid, dim3(256), 0, st, y, sy, u, su, v, sv, W, H, image, yin, yout);
   return hipGetLastError();
 }
 

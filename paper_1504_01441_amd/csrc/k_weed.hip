@@ -3,21 +3,29 @@
 // valid tiles of the level, indexed in tile order (centred level coordinates:
 // source side p + d - c, reference side p - c).
 //
-// k_hyp:  one lane per iteration. Each wave counts the valid tiles, draws four
-//         distinct match indices from the counter-based SplitMix64 stream,
-//         maps them to tiles with a rank-select over ballot masks, and solves
-//         the 8x8 system in double precision (partial pivoting, fixed
-//         operation order) with the matrix in registers.
+// k_valid: the valid-match bits of the tiles, one 64-bit word per 64 tiles
+//         (a wave ballot each); also clears the fit sums. In a registration
+//         the level's warp clears them and its search sets the bits instead.
+// k_hyp:  one lane per iteration, one wave per block. Each wave prefix-sums
+//         the words' popcounts, draws four distinct match indices from the
+//         counter-based SplitMix64 stream, maps them to tiles with a
+//         rank-select over the words, and solves the 8x8 system in double
+//         precision (partial pivoting, fixed operation order) with the matrix
+//         in registers.
 // k_test: a (256 tiles x 8 iterations) block tests its tiles against its
 //         hypotheses; wave ballots form each iteration's inlier bitmask row,
 //         and the block's count per iteration is added atomically.
-// k_fit:  one block sums the counts, takes M as the union of the rows whose
-//         count exceeds delta (any split of the iterations gives the same M,
-//         as the paper notes), finds the best consensus (most inliers, lowest
-//         iteration), sums the least-squares normal equations of G: p -> p + d
-//         over that hypothesis' inliers exactly in int64 (order-free), and
-//         solves and composes H_l = H_{l+1} o G in double precision.
-// The three are ordered by the stream; no block waits for another.
+// k_union: a wave per word of 64 tiles. Every block reads the counts, takes
+//         the accepted iterations (count above delta) and the best consensus
+//         (most inliers, lowest iteration); a wave ORs the accepted rows of
+//         its word (M is the union of those rows; any split of the
+//         iterations gives the same M, as the paper notes), writes its tiles'
+//         flags and adds their terms of the least-squares normal equations of
+//         G: p -> p + d over the best hypothesis' inliers exactly in int64
+//         (order-free) to the level's sums.
+// k_solve: one lane solves the normal equations in double precision (the
+//         solver of k_hyp) and composes H_l = H_{l+1} o G.
+// The kernels are ordered by the stream; no block waits for another.
 #include "lnr_device.h"
 #include "lnr_internal.h"
 
@@ -119,43 +127,55 @@ __device__ inline int select_bit(unsigned long long m, int k) {
   return pos;
 }
 
-constexpr int kHypThreads = 256;
+constexpr int kValidThreads = 256;
+constexpr int kHypThreads = 64;
 constexpr int kItPerBlock = 8;
 constexpr int kTestThreads = 256;
-constexpr int kFitThreads = 512;  // the final solve needs ~160 VGPRs
+constexpr int kUnionThreads = 512;
 constexpr int kMaxIters = 65536;  // the parameter check's bound on weed_iters
 constexpr int kMaxWords = 2304;   // tile bitmask words: (6144 / 16)^2 tiles
 
+// word wi of vb = valid-match bits of tiles 64 wi .. 64 wi + 63; block 0
+// also clears the level's least-squares sums
+__global__ __launch_bounds__(kValidThreads) void k_valid(const uint8_t* __restrict__ flags,
+                                                         int ntiles, int nwords,
+                                                         unsigned long long* __restrict__ vb,
+                                                         long long* __restrict__ sums) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wi = blockIdx.x * (kValidThreads / 64) + (tid >> 6);
+  if (blockIdx.x == 0 && tid < 24) sums[tid] = 0;
+  if (wi >= nwords) return;  // whole waves
+  const int t = wi * 64 + lane;
+  const unsigned long long m = __ballot(t < ntiles && (flags[t] & 2));
+  if (lane == 0) vb[wi] = m;
+}
+
 __global__ __launch_bounds__(kHypThreads) void k_hyp(
-    const uint8_t* __restrict__ flags, const int32_t* __restrict__ cxy,
-    const int32_t* __restrict__ disp, int ntiles, int w, int h, WeedArgs a,
+    const unsigned long long* __restrict__ vbg, const int32_t* __restrict__ cxy,
+    const int32_t* __restrict__ disp, int nwords, int w, int h, WeedArgs a,
     double* __restrict__ G, int32_t* __restrict__ cnt, int32_t* __restrict__ nmatch) {
   __shared__ unsigned long long vb[kMaxWords];  // valid-tile bits, tile order
   __shared__ int wpre[kMaxWords + 1];            // valid tiles before each word
-  __shared__ int wsum[kHypThreads / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NW = kHypThreads / 64;
-  const int nwords = (ntiles + 63) >> 6;
-  // word wi = ballot of tiles 64 wi .. 64 wi + 63 (one coalesced byte load per lane)
-  for (int w0 = wave; w0 < nwords; w0 += 8 * NW) {
-    uint8_t f[8];  // eight loads in flight, then the ballots
+  const int lane = threadIdx.x;
+  for (int q0 = 0; q0 < nwords; q0 += 8 * 64) {
+    unsigned long long r[8];  // eight loads in flight per lane
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int t = (w0 + u * NW) * 64 + lane;
-      f[u] = t < ntiles ? flags[t] : 0;
+      const int wi = q0 + u * 64 + lane;
+      r[u] = wi < nwords ? vbg[wi] : 0ull;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const unsigned long long m = __ballot(f[u] & 2);
-      if (lane == 0 && w0 + u * NW < nwords) vb[w0 + u * NW] = m;
+      const int wi = q0 + u * 64 + lane;
+      if (wi < nwords) vb[wi] = r[u];
     }
   }
   __syncthreads();
-  // exclusive prefix of the words' popcounts: thread owns a run of K words
-  const int K = (nwords + kHypThreads - 1) / kHypThreads;
+  // exclusive prefix of the words' popcounts: lane owns a run of K words
+  const int K = (nwords + 63) / 64;
   int c = 0;
   for (int j = 0; j < K; ++j) {
-    const int wi = tid * K + j;
+    const int wi = lane * K + j;
     if (wi < nwords) c += __popcll(vb[wi]);
   }
   int incl = c;
@@ -164,25 +184,19 @@ __global__ __launch_bounds__(kHypThreads) void k_hyp(
     const int o = __shfl_up(incl, off);
     if (lane >= off) incl += o;
   }
-  if (lane == 63) wsum[wave] = incl;
-  __syncthreads();
-  int before = 0, N = 0;
-  for (int q = 0; q < NW; ++q) {
-    before += q < wave ? wsum[q] : 0;
-    N += wsum[q];
-  }
-  int run = before + incl - c;
+  const int N = __shfl(incl, 63);
+  int run = incl - c;
   for (int j = 0; j < K; ++j) {
-    const int wi = tid * K + j;
+    const int wi = lane * K + j;
     if (wi < nwords) {
       wpre[wi] = run;
       run += __popcll(vb[wi]);
     }
   }
-  if (tid == 0) wpre[nwords] = N;
+  if (lane == 0) wpre[nwords] = N;
   __syncthreads();
-  if (blockIdx.x == 0 && tid == 0) *nmatch = N;
-  const int it = blockIdx.x * kHypThreads + tid;
+  if (blockIdx.x == 0 && lane == 0) *nmatch = N;
+  const int it = blockIdx.x * kHypThreads + lane;
   bool ok = N >= 4 && it < a.iters;
   int pk[4] = {-1, -1, -1, -1};
   if (ok) {
@@ -326,96 +340,42 @@ __device__ inline long long normal_rhs(const long long* T, int i) {
   }
 }
 
-// The 8x8 solve of solve8 with one row per lane (lanes 0-7 of a wave; the
-// other lanes mirror row 7 and are ignored): identical arithmetic per entry,
-// the pivot search as a first-largest reduction. Every lane returns the same.
-__device__ inline bool solve8_wave(double (&row)[9], double (&x)[8]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    // first largest |a[r][c]| over r >= c; a NaN below the pivot row is never
-    // larger, a NaN in the pivot row fails
-    const double ac = fabs(row[c]);
-    double v = (lane >= c && lane < 8) ? ac : -1.0;
-    if (lane != c && !(v >= 0.0)) v = -1.0;
-    int idx = lane < 8 ? lane : 8;
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) {
-      const double v2 = __shfl_xor(v, o);
-      const int i2 = __shfl_xor(idx, o);
-      if (v2 > v || (v2 == v && i2 < idx)) { v = v2; idx = i2; }
-    }
-    const double best = __shfl(v, 0);
-    const int piv = __shfl(idx, 0);
-    const double diag = __shfl(ac, c);
-    if (!(diag == diag) || !(best >= 1e-12)) return false;
-    const int src = lane == c ? piv : (lane == piv ? c : lane);
-#pragma unroll
-    for (int j = c; j < 9; ++j) row[j] = __shfl(row[j], src);
-    double pr[9];
-#pragma unroll
-    for (int j = c; j < 9; ++j) pr[j] = __shfl(row[j], c);
-    if (lane > c && lane < 8) {
-      const double f = row[c] / pr[c];
-#pragma unroll
-      for (int j = c; j < 9; ++j) row[j] = row[j] - f * pr[j];
-    }
-  }
-#pragma unroll
-  for (int c = 7; c >= 0; --c) {
-    double s = row[8];
-#pragma unroll
-    for (int j = c + 1; j < 8; ++j) s = s - row[j] * x[j];
-    x[c] = __shfl(s / row[c], c);
-  }
-  return true;
-}
-
-// One block: union M, best consensus, least-squares level homography, and
-// the per-tile flags 4 (in M) and 8 (in the fit).
-__global__ __launch_bounds__(kFitThreads) void k_fit(
+// Wave wd of the grid owns tile word wd: union M over the accepted rows,
+// flags 4 (in M) and 8 (in the fit) of its tiles, and their least-squares
+// terms, added exactly to the level's sums.
+__global__ __launch_bounds__(kUnionThreads) void k_union(
     const int32_t* __restrict__ cxy, const int32_t* __restrict__ disp,
     uint8_t* __restrict__ flags, int ntiles, int w, int h, WeedArgs a,
-    const int32_t* __restrict__ nmatch, const double* __restrict__ G,
-    const int32_t* __restrict__ cnt, const unsigned long long* __restrict__ bal, int wstride,
-    const double* __restrict__ Hprev, double* __restrict__ Hout, int32_t* __restrict__ counts) {
-  extern __shared__ unsigned long long mw[];  // [wstride] union bitmask M
+    const int32_t* __restrict__ nmatch, const int32_t* __restrict__ cnt,
+    const unsigned long long* __restrict__ bal, int wstride, long long* __restrict__ sums,
+    int32_t* __restrict__ counts) {
   __shared__ unsigned int accw[kMaxIters / 32];  // accepted iterations
-  __shared__ unsigned long long kmax[kFitThreads / 64];
-  __shared__ long long part[kFitThreads / 64][kSums];
-  __shared__ long long tot[kSums];
-  constexpr int NWV = kFitThreads / 64, TPT = 16;
+  __shared__ unsigned long long kmax[kUnionThreads / 64];
+  __shared__ long long part[kUnionThreads / 64][kSums];
+  constexpr int NWV = kUnionThreads / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // The phases below depend on each other (counts -> union and best row ->
-  // fit), so each issues all of its loads before using any; the first batch
-  // of tile data is loaded up front.
-  uint8_t tf[TPT];
-  int tpx[TPT], tpy[TPT], tdx[TPT], tdy[TPT];
-#pragma unroll
-  for (int j = 0; j < TPT; ++j) {
-    const int t = tid + j * kFitThreads;
-    const bool in = t < ntiles;
-    tf[j] = in ? flags[t] : 0;
-    tpx[j] = in ? cxy[2 * t] : 0;
-    tpy[j] = in ? cxy[2 * t + 1] : 0;
-    tdx[j] = in ? disp[2 * t] : 0;
-    tdy[j] = in ? disp[2 * t + 1] : 0;
-  }
+  const int wd = blockIdx.x * NWV + wave;
+  const int t = wd * 64 + lane;
+  const bool in = wd < wstride && t < ntiles;
+  // this lane's tile, in flight with the counts
+  const uint8_t tf = in ? flags[t] : 0;
+  const int tpx = in ? cxy[2 * t] : 0, tpy = in ? cxy[2 * t + 1] : 0;
+  const int tdx = in ? disp[2 * t] : 0, tdy = in ? disp[2 * t + 1] : 0;
   const int N = *nmatch;
   const int delta = weed_delta(N, a);
-  // per-iteration counts, acceptance bits, best key
+  // per-iteration counts -> acceptance bits and the best key
   unsigned long long kb = 0ull;
-  for (int i0 = 0; i0 < a.iters; i0 += 2 * kFitThreads) {
+  for (int i0 = 0; i0 < a.iters; i0 += 2 * kUnionThreads) {
     int c[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const int i = i0 + r * kFitThreads + tid;
+      const int i = i0 + r * kUnionThreads + tid;
       c[r] = i < a.iters && N >= 4 ? cnt[i] : -1;
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const int i = i0 + r * kFitThreads + tid;
-      const int ib = i0 + r * kFitThreads + wave * 64;
+      const int i = i0 + r * kUnionThreads + tid;
+      const int ib = i0 + r * kUnionThreads + wave * 64;
       const unsigned long long acc = __ballot(c[r] > delta);
       if (lane == 0 && ib < a.iters) {
         accw[ib >> 5] = (unsigned int)acc;
@@ -436,126 +396,102 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(
   const int bc = N >= 4 && bkey ? (int)(bkey >> 32) : -1;
   const int bi = N >= 4 && bkey ? (int)(~(uint32_t)(bkey & 0xffffffffull)) : -1;
   const bool fit = bc > delta;
-  // the best hypothesis' inlier bits for the first tile batch
-  unsigned long long brow[TPT];
-#pragma unroll
-  for (int j = 0; j < TPT; ++j) {
-    const int t = tid + j * kFitThreads;
-    brow[j] = fit && t < ntiles ? bal[(size_t)(t >> 6) * a.iters + bi] : 0ull;
+  if (blockIdx.x == 0 && tid == 0) {
+    counts[0] = N;
+    counts[2] = bc;
+    counts[3] = bi;
   }
-  // M: OR of the accepted rows; a wave per word (two at a time), its lanes
-  // over the iterations
-  for (int w0 = wave; w0 < wstride; w0 += 2 * NWV) {
-    const int w1 = w0 + NWV;
-    unsigned long long v0 = 0ull, v1 = 0ull;
-    for (int i0 = 0; i0 < a.iters; i0 += 64 * 16) {
-      unsigned long long r0[16], r1[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int i = i0 + u * 64 + lane;
-        r0[u] = i < a.iters ? bal[(size_t)w0 * a.iters + i] : 0ull;
-        r1[u] = i < a.iters && w1 < wstride ? bal[(size_t)w1 * a.iters + i] : 0ull;
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int i = i0 + u * 64 + lane;
-        if (i < a.iters && ((accw[i >> 5] >> (i & 31)) & 1u)) {
-          v0 |= r0[u];
-          v1 |= r1[u];
-        }
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      v0 |= __shfl_xor(v0, o);
-      v1 |= __shfl_xor(v1, o);
-    }
-    if (lane == 0) {
-      mw[w0] = v0;
-      if (w1 < wstride) mw[w1] = v1;
-    }
-  }
-  __syncthreads();
-  // normal equations of G: (x, y) -> (u, v), reference side to source side,
-  // over the best hypothesis' inliers; the 8x8 matrix has 23 distinct sums
   long long s[kSums];
 #pragma unroll
   for (int i = 0; i < kSums; ++i) s[i] = 0;
-  const int ox = w / 2, oy = h / 2;
-  for (int t0 = 0; t0 < ntiles; t0 += TPT * kFitThreads) {
-    if (t0 > 0) {  // later batches (levels with more than 8192 tiles)
+  if (wd < wstride) {  // whole waves
+    const unsigned long long brow = fit ? bal[(size_t)wd * a.iters + bi] : 0ull;
+    unsigned long long v = 0ull;
+    for (int i0 = 0; i0 < a.iters; i0 += 64 * 16) {
+      unsigned long long r[16];
 #pragma unroll
-      for (int j = 0; j < TPT; ++j) {
-        const int t = t0 + tid + j * kFitThreads;
-        const bool in = t < ntiles;
-        tf[j] = in ? flags[t] : 0;
-        tpx[j] = in ? cxy[2 * t] : 0;
-        tpy[j] = in ? cxy[2 * t + 1] : 0;
-        tdx[j] = in ? disp[2 * t] : 0;
-        tdy[j] = in ? disp[2 * t + 1] : 0;
-        brow[j] = fit && in ? bal[(size_t)(t >> 6) * a.iters + bi] : 0ull;
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u * 64 + lane;
+        r[u] = i < a.iters ? bal[(size_t)wd * a.iters + i] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u * 64 + lane;
+        if (i < a.iters && ((accw[i >> 5] >> (i & 31)) & 1u)) v |= r[u];
       }
     }
 #pragma unroll
-    for (int j = 0; j < TPT; ++j) {
-      const int t = t0 + tid + j * kFitThreads;
-      if (t >= ntiles || !(tf[j] & 2)) continue;
-      const bool inM = (mw[t >> 6] >> (t & 63)) & 1ull;
-      const bool sel = (brow[j] >> (t & 63)) & 1ull;
-      flags[t] = (uint8_t)((tf[j] & 0x13) | (inM ? 4 : 0) | (sel ? 8 : 0));
-      if (!sel) continue;
-      const long long x = tpx[j] - ox, y = tpy[j] - oy, u = x + tdx[j], v = y + tdy[j];
-      const long long xx = x * x, xy = x * y, yy = y * y, q = u * u + v * v;
-      s[0] += 1;       s[1] += x;       s[2] += y;
-      s[3] += xx;      s[4] += xy;      s[5] += yy;
-      s[6] += u;       s[7] += v;
-      s[8] += x * u;   s[9] += y * u;   s[10] += x * v;  s[11] += y * v;
-      s[12] += xx * u; s[13] += xy * u; s[14] += yy * u;
-      s[15] += xx * v; s[16] += xy * v; s[17] += yy * v;
-      s[18] += x * q;  s[19] += y * q;
-      s[20] += xx * q; s[21] += xy * q; s[22] += yy * q;
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    if (in && (tf & 2)) {
+      const bool inM = (v >> lane) & 1ull;
+      const bool sel = (brow >> lane) & 1ull;
+      flags[t] = (uint8_t)((tf & 0x13) | (inM ? 4 : 0) | (sel ? 8 : 0));
+      if (sel) {
+        // normal equations of G: (x, y) -> (u, v), reference side to source
+        // side; the 8x8 matrix has 23 distinct sums
+        const long long x = tpx - w / 2, y = tpy - h / 2, u = x + tdx, vv = y + tdy;
+        const long long xx = x * x, xy = x * y, yy = y * y, q = u * u + vv * vv;
+        s[0] = 1;        s[1] = x;        s[2] = y;
+        s[3] = xx;       s[4] = xy;       s[5] = yy;
+        s[6] = u;        s[7] = vv;
+        s[8] = x * u;    s[9] = y * u;    s[10] = x * vv;  s[11] = y * vv;
+        s[12] = xx * u;  s[13] = xy * u;  s[14] = yy * u;
+        s[15] = xx * vv; s[16] = xy * vv; s[17] = yy * vv;
+        s[18] = x * q;   s[19] = y * q;
+        s[20] = xx * q;  s[21] = xy * q;  s[22] = yy * q;
+      }
     }
   }
   // exact (order-free) int64 reduction
+  if (__ballot(s[0] != 0)) {
 #pragma unroll
-  for (int i = 0; i < kSums; ++i) s[i] = wave_sum_i64(s[i]);
+    for (int i = 0; i < kSums; ++i) s[i] = wave_sum_i64(s[i]);
+  }
   if (lane == 0)
     for (int i = 0; i < kSums; ++i) part[wave][i] = s[i];
   __syncthreads();
   if (tid < kSums) {
     long long z = 0;
-    for (int q = 0; q < kFitThreads / 64; ++q) z += part[q][tid];
-    tot[tid] = z;
+    for (int q = 0; q < NWV; ++q) z += part[q][tid];
+    if (z != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(sums + tid), (unsigned long long)z);
   }
+}
+
+// The level fit from the sums (A^T A and A^T b of the rows
+// (x, y, 1, 0, 0, 0, -xu, -yu | u) and (0, 0, 0, x, y, 1, -xv, -yv | v),
+// scaled by powers of two), solved by one lane with the matrix in registers,
+// then H_l = H_{l+1} o G; H_l = H_{l+1} when fewer than 4 matches were fitted
+// or the solve fails.
+__global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __restrict__ sums,
+                                              const double* __restrict__ Hprev,
+                                              double* __restrict__ Hout,
+                                              int32_t* __restrict__ counts) {
+  __shared__ long long tot[kSums];
+  const int lane = threadIdx.x;
+  if (lane < kSums) tot[lane] = sums[lane];
   __syncthreads();
-  if (wave != 0) return;
+  if (lane != 0) return;
   const int msel = (int)tot[0];
-  if (lane == 0) {
-    counts[0] = N;
-    counts[1] = msel;
-    counts[2] = bc;
-    counts[3] = bi;
-    for (int i = 0; i < 9; ++i) Hout[i] = Hprev[i];
-  }
+  counts[1] = msel;
+  for (int i = 0; i < 9; ++i) Hout[i] = Hprev[i];
   if (msel < 4) return;
-  // A^T A and A^T b of the rows (x, y, 1, 0, 0, 0, -xu, -yu | u) and
-  // (0, 0, 0, x, y, 1, -xv, -yv | v), scaled by powers of two; lane r < 8
-  // holds row r
+  const int ox = w / 2, oy = h / 2;
   int k = 0;
   const int mx = ox > oy ? (ox > 1 ? ox : 1) : (oy > 1 ? oy : 1);
   while ((1 << k) < mx) ++k;
   const int deg[8] = {1, 1, 0, 1, 1, 0, 2, 2};
-  const int r = lane < 8 ? lane : 7;
-  double row[9];
+  double A[72];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    const long long v = j < 8 ? normal_entry(tot, r, j) : normal_rhs(tot, r);
-    const int e = j < 8 ? -k * (deg_of(r) + deg[j]) : -k * (deg_of(r) + 1);
-    row[j] = ldexp((double)v, e);
-  }
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const long long v = j < 8 ? normal_entry(tot, r, j) : normal_rhs(tot, r);
+      const int e = j < 8 ? -k * (deg_of(r) + deg[j]) : -k * (deg_of(r) + 1);
+      A[r * 9 + j] = ldexp((double)v, e);
+    }
   double hs[8];
-  if (!solve8_wave(row, hs)) return;
-  if (lane != 0) return;
+  if (!solve8(A, hs)) return;
   double Gc[9];
   for (int i = 0; i < 8; ++i) Gc[i] = ldexp(hs[i], k * (1 - deg[i]));
   Gc[8] = 1.0;
@@ -582,7 +518,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
                            const double* H_prev, double* H_out, int32_t* counts,
-                           const WeedBufs& b, hipStream_t st) {
+                           const WeedBufs& b, hipStream_t st, bool vb_ready) {
   WeedArgs a;
   a.iters = p.weed_iters;
   a.level = level;
@@ -594,17 +530,25 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
   const int chunks = ntiles > 0 ? (ntiles + kTestThreads - 1) / kTestThreads : 1;
   const int groups = (a.iters + kItPerBlock - 1) / kItPerBlock;
   if (words > kMaxWords || a.iters > kMaxIters) return hipErrorInvalidValue;
+  hipError_t e;
+  if (!vb_ready) {  // else the level's search set the bits (and its warp cleared the sums)
+    LNR_LAUNCH(k_valid, dim3((words + kValidThreads / 64 - 1) / (kValidThreads / 64)),
+               dim3(kValidThreads), 0, st, flags, ntiles, words, b.vb, b.sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   LNR_LAUNCH(k_hyp, dim3((a.iters + kHypThreads - 1) / kHypThreads), dim3(kHypThreads), 0, st,
-             flags, corner_xy, disp, ntiles, w, h, a, b.G, b.cnt, b.nmatch);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+             b.vb, corner_xy, disp, words, w, h, a, b.G, b.cnt, b.nmatch);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ntiles > 0) {
     LNR_LAUNCH(k_test, dim3(chunks, groups), dim3(kTestThreads), 0, st, corner_xy, disp, flags,
                ntiles, w, h, a, b.G, b.cnt, b.bal, words);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  LNR_LAUNCH(k_fit, dim3(1), dim3(kFitThreads), (size_t)words * 8, st, corner_xy, disp, flags,
-             ntiles, w, h, a, b.nmatch, b.G, b.cnt, b.bal, words, H_prev, H_out, counts);
+  LNR_LAUNCH(k_union, dim3((words + kUnionThreads / 64 - 1) / (kUnionThreads / 64)),
+             dim3(kUnionThreads), 0, st, corner_xy, disp, flags, ntiles, w, h, a, b.nmatch,
+             b.cnt, b.bal, words, b.sums, counts);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  LNR_LAUNCH(k_solve, dim3(1), dim3(64), 0, st, w, h, b.sums, H_prev, H_out, counts);
   return hipGetLastError();
 }
 

@@ -102,10 +102,6 @@ struct TraceGuard {
   ~TraceGuard() { g_tracer = nullptr; }
 };
 
-__global__ void k_set_identity(double* H) {
-  if (threadIdx.x < 9) H[threadIdx.x] = (threadIdx.x % 4 == 0) ? 1.0 : 0.0;
-}
-
 lnr_status fail(lnr_ctx* ctx, lnr_status s, const std::string& msg) {
   if (ctx) ctx->err = msg;
   return s;
@@ -245,7 +241,7 @@ lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes) {
 }
 
 struct WeedPlan {
-  size_t nmatch, G, cnt, bal;
+  size_t nmatch, G, cnt, bal, vb, sums;
 };
 
 WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
@@ -255,6 +251,8 @@ WeedPlan plan_weed(Plan& pl, int ntiles, int iters) {
   w.G = pl.take(sizeof(double) * 8 * (size_t)iters);
   w.cnt = pl.take(sizeof(int32_t) * (size_t)iters);
   w.bal = pl.take(sizeof(unsigned long long) * (size_t)iters * ((nt + 63) / 64));
+  w.vb = pl.take(sizeof(unsigned long long) * (size_t)((nt + 63) / 64));
+  w.sums = pl.take(sizeof(long long) * 24);
   return w;
 }
 
@@ -264,6 +262,8 @@ WeedBufs weed_bufs(char* base, const WeedPlan& w) {
   b.G = reinterpret_cast<double*>(base + w.G);
   b.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
   b.bal = reinterpret_cast<unsigned long long*>(base + w.bal);
+  b.vb = reinterpret_cast<unsigned long long*>(base + w.vb);
+  b.sums = reinterpret_cast<long long*>(base + w.sums);
   return b;
 }
 
@@ -325,7 +325,6 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
                         char* base, hipStream_t st) {
   const Geometry& g = q.g;
   const int W = ref->width, H = ref->height;
-  const size_t N = (size_t)W * H;
   uint32_t* hist = reinterpret_cast<uint32_t*>(base + q.o_hist);
   uint8_t* pref = reinterpret_cast<uint8_t*>(base + q.o_pref);
   uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
@@ -334,21 +333,23 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
   float* maps = reinterpret_cast<float*>(base + q.o_maps);
   double* coef = reinterpret_cast<double*>(base + q.o_coef);
 
-  LNR_LAUNCH(k_zero_u32, dim3(2), dim3(256), 0, st, hist, 512);
-  LNR_HIP(hipGetLastError());
+  // set-up in one launch: the propagation's coefficient tables, the cleared
+  // histograms and the identity above the top level
+  LNR_HIP(launch_dt_coef(*p, coef, hist, 512, out->H + 9 * g.levels, st));
   LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
+  // level 0 of both pyramids is also written to the outputs (no copies)
   LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
-                         pref, psrc, nullptr, 2, st));
-  LNR_HIP(hipMemcpyAsync(out->yeq_ref, pref, N, hipMemcpyDeviceToDevice, st));
-  if (out->yeq_src) LNR_HIP(hipMemcpyAsync(out->yeq_src, psrc, N, hipMemcpyDeviceToDevice, st));
-  LNR_LAUNCH(k_set_identity, dim3(1), dim3(64), 0, st, out->H + 9 * g.levels);
-  LNR_HIP(hipGetLastError());
+                         pref, psrc, nullptr, 2, st, out->yeq_ref, out->yeq_src));
   const SearchCfg cfg = search_cfg(*p);
   for (int l = g.levels - 1; l >= 0; --l) {
     const Level& L = g.lv[l];
     const int R = l == 0 ? p->radius0 : p->radius_coarse;
     const int nt = L.ntx * L.nty;
-    LNR_HIP(launch_warp_q8(psrc + L.pix_off, L.w, L.h, out->H + 9 * (l + 1), warped, st));
+    const int words = nt > 0 ? (nt + 63) / 64 : 1;
+    // level 0 is warped straight into the output when it is wanted
+    if (l == 0 && out->warped0) warped = out->warped0;
+    LNR_HIP(launch_warp_q8(psrc + L.pix_off, L.w, L.h, out->H + 9 * (l + 1), warped, st, &wb,
+                           words));
     if (l == 0 && p->learned) {
       // the network proposes a window per tile; confident tiles scan it,
       // the others fall back to the exhaustive search (flag 16)
@@ -360,25 +361,25 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
       LNR_HIP(launch_cnn_forward(ctx->cnn_packed, ctx->cnn, x, nt, nullptr, nullptr, centre, mode,
                                  p->radius0 - p->window_r, logit, st));
       LNR_HIP(launch_search(pref, warped, L.w, L.h, p->window_r, cfg, L.ntx, L.nty,
-                            out->corner_xy, out->disp, out->ssd, out->flags, st, centre, mode, 0));
+                            out->corner_xy, out->disp, out->ssd, out->flags, st, centre, mode, 0,
+                            wb.vb));
       LNR_HIP(launch_search(pref, warped, L.w, L.h, R, cfg, L.ntx, L.nty, out->corner_xy,
-                            out->disp, out->ssd, out->flags, st, nullptr, mode, 1));
+                            out->disp, out->ssd, out->flags, st, nullptr, mode, 1, wb.vb));
     } else {
       LNR_HIP(launch_search(pref + L.pix_off, warped, L.w, L.h, R, cfg, L.ntx, L.nty,
                             out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
-                            out->ssd + L.tile_off, out->flags + L.tile_off, st));
+                            out->ssd + L.tile_off, out->flags + L.tile_off, st, nullptr,
+                            nullptr, 0, wb.vb));
     }
     LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
                             out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
-                            out->H + 9 * l, out->counts + 4 * l, wb, st));
-    if (l == 0 && out->warped0)
-      LNR_HIP(hipMemcpyAsync(out->warped0, warped, N, hipMemcpyDeviceToDevice, st));
+                            out->H + 9 * l, out->counts + 4 * l, wb, st, true));
   }
   const DtShape* ds = nullptr;
   auto it = ctx->dt_shapes.find(std::make_pair(W, H));
   if (it != ctx->dt_shapes.end()) ds = &it->second;
   LNR_HIP(launch_flow(out->corner_xy, out->disp, out->flags, g.lv[0].ntx, g.lv[0].nty, p->tile,
-                      pref, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds));
+                      pref, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds, true));
   LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], src->format == LNR_I420 ? src->plane[1] : nullptr,
                                src->stride[1], src->format == LNR_I420 ? src->plane[2] : nullptr,
                                src->stride[2], psrc, W, H, out->H + 9, out->flow, out->image,
@@ -580,14 +581,18 @@ lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t r
   char* base = static_cast<char*>(ctx->ws);
   float* ref_img = reinterpret_cast<float*>(base);
   float* ref_yeq = reinterpret_cast<float*>(base + ((ch * N * sizeof(float) + 255) & ~(size_t)255));
-  LNR_HIP(launch_frame_rgb(rf.plane[0], rf.stride[0], ch == 3 ? rf.plane[1] : nullptr, rf.stride[1],
-                           ch == 3 ? rf.plane[2] : nullptr, rf.stride[2], W, H, ref_img, st));
+  // the reference's RGB and (with registrations) its equalised luma in [0, 1]
+  LNR_HIP(launch_frame_rgb_unit(rf.plane[0], rf.stride[0], ch == 3 ? rf.plane[1] : nullptr,
+                                rf.stride[1], ch == 3 ? rf.plane[2] : nullptr, rf.stride[2], W,
+                                H, ref_img, n > 1 ? regs[0].yeq_ref : nullptr,
+                                n > 1 ? ref_yeq : nullptr, st));
   const float* imgs[16];
   const float* yeqs[16];
-  if (n > 1) {
-    LNR_HIP(launch_u8_to_unit(regs[0].yeq_ref, W, H, ref_yeq, st));
-  } else {
-    LNR_HIP(hipMemsetAsync(ref_yeq, 0, N * sizeof(float), st));
+  if (n == 1) {
+    // a fill kernel, not a memset node, so that the call can be graph-captured
+    LNR_LAUNCH(k_zero_u32, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+               reinterpret_cast<uint32_t*>(ref_yeq), (int)N);
+    LNR_HIP(hipGetLastError());
   }
   int j = 0;
   for (int k = 0; k < n; ++k) {
@@ -619,7 +624,8 @@ lnr_status lnr_stage_equalize(lnr_ctx* ctx, const uint8_t* img, int32_t w, int32
   memset(&g, 0, sizeof(g));
   g.W = w; g.H = h; g.levels = 1;
   g.lv[0].w = w; g.lv[0].h = h; g.lv[0].pix_off = 0;
-  LNR_HIP(hipMemsetAsync(hist, 0, 256 * sizeof(uint32_t), st));
+  LNR_LAUNCH(k_zero_u32, dim3(1), dim3(256), 0, st, hist, 256);
+  LNR_HIP(hipGetLastError());
   LNR_HIP(launch_hist(img, stride, img, stride, w, h, hist, 1, st));
   LNR_HIP(launch_lut_pyr(img, stride, img, stride, hist, g, out, out, lut, 1, st));
   return LNR_OK;

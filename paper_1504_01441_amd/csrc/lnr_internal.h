@@ -63,17 +63,23 @@ struct SearchCfg {
 // ---- equalisation + pyramid (k_equalize.hip)
 hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int W, int H,
                        uint32_t* hist /*[nframes][256]*/, int nframes, hipStream_t st);
+// out0 / out1 (optional): second copies of the equalised level 0
 hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
                           const uint32_t* hist, const Geometry& g, uint8_t* pyr0,
-                          uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st);
+                          uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st,
+                          uint8_t* out0 = nullptr, uint8_t* out1 = nullptr);
 
 // ---- warp + search (k_search.hip)
+struct WeedBufs;
+// wb (optional): the level's weeding buffers, whose valid-match bits and
+// least-squares sums the warp clears and the search then fills
 hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
-                          hipStream_t st);
+                          hipStream_t st, const WeedBufs* wb = nullptr, int nwords = 0);
 hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
                          int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st, const int32_t* centre = nullptr,
-                         const uint8_t* mode = nullptr, int want = 0);
+                         const uint8_t* mode = nullptr, int want = 0,
+                         unsigned long long* vb = nullptr);
 
 // ---- weeding + level homography (k_weed.hip)
 struct WeedBufs {
@@ -81,11 +87,13 @@ struct WeedBufs {
   double* G;                // [iters][8] hypothesis homographies
   int32_t* cnt;             // [iters] inlier counts (-1: hypothesis unusable)
   unsigned long long* bal;  // [ceil(ntiles/64)][iters] inlier bitmask rows
+  unsigned long long* vb;   // [ceil(ntiles/64)] valid-match bits, tile order
+  long long* sums;          // [23] least-squares sums of the level fit
 };
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
                            const double* H_prev, double* H_out, int32_t* counts,
-                           const WeedBufs& b, hipStream_t st);
+                           const WeedBufs& b, hipStream_t st, bool vb_ready = false);
 
 // ---- domain-transform propagation (k_dt.hip)
 // Kernel shapes: rows of SEG pixels per thread in NT-thread blocks; columns as
@@ -101,17 +109,22 @@ int dt_shape_candidates(int W, int H, DtShape* out, int max);
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
                        int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
                        const lnr_params& p, float* maps /*[3][H][W]*/, double* coef /*[iters][256]*/,
-                       float* flow, float* ntilde, hipStream_t st, const DtShape* shape = nullptr);
+                       float* flow, float* ntilde, hipStream_t st, const DtShape* shape = nullptr,
+                       bool coef_ready = false);
+// the propagation's coefficient tables (coef [iters][256]); the first block
+// also clears zero[0, nzero) and sets ident (optional) to the 3x3 identity
+hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int nzero,
+                          double* ident, hipStream_t st);
 
 // ---- backward warp (k_warp.hip)
 hipError_t launch_backward_warp(const uint8_t* y, int sy, const uint8_t* u, int su,
                                 const uint8_t* v, int sv, const uint8_t* yeq, int W, int H,
                                 const double* Hn, const float* flow, float* image,
                                 float* yeq_w, hipStream_t st);
-hipError_t launch_frame_rgb(const uint8_t* y, int sy, const uint8_t* u, int su,
-                            const uint8_t* v, int sv, int W, int H, float* image,
-                            hipStream_t st);
-hipError_t launch_u8_to_unit(const uint8_t* in, int W, int H, float* out, hipStream_t st);
+// RGB of a frame plus, optionally, an 8-bit plane yin mapped to [0, 1] in yout
+hipError_t launch_frame_rgb_unit(const uint8_t* y, int sy, const uint8_t* u, int su,
+                                 const uint8_t* v, int sv, int W, int H, float* image,
+                                 const uint8_t* yin, float* yout, hipStream_t st);
 
 // ---- merge (k_merge.hip)
 struct MergeBufs {
