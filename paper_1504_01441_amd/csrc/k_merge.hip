@@ -148,7 +148,9 @@ constexpr int kWeightRows = 8;
 // Each thread walks down kWeightRows rows of one column: the grey values of
 // the rows above, at and below the pixel stay in registers, so every colour
 // sample is fetched from memory once (the left / right neighbours come from
-// the same cache lines as the neighbouring threads' own pixels).
+// the same cache lines as the neighbouring threads' own pixels). The samples
+// of the next row are loaded before the current row's weights are formed and
+// stored, so one row's loads are always in flight.
 template <int NMAX>
 __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int W, int H,
                                                  int ref, float two_se2) {
@@ -164,6 +166,22 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
     g = ch == 3 ? I[plane + o] : 0.f;
     b = ch == 3 ? I[2 * plane + o] : 0.f;
   };
+  // samples of row y: d* below, l* / r* left and right, s the SSIM
+  float dr[NMAX], dg[NMAX], db[NMAX], lr[NMAX], lg[NMAX], lb[NMAX], rr[NMAX], rg[NMAX],
+      rb[NMAX], sv[NMAX];
+  auto fetch = [&](int y) {  // y < H
+    const size_t o = (size_t)y * W;
+    const size_t od = (size_t)min(y + 1, H - 1) * W + x;
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+      if (k >= n) continue;
+      const float* I = f.img[k];
+      ld(I, od, dr[k], dg[k], db[k]);
+      ld(I, o + xl, lr[k], lg[k], lb[k]);
+      ld(I, o + xr, rr[k], rg[k], rb[k]);
+      sv[k] = k != ref ? f.ssim[k][o + x] : 0.f;
+    }
+  };
   double gu[NMAX], gc[NMAX];
   float cr[NMAX], cg[NMAX], cb[NMAX];
 #pragma unroll
@@ -175,9 +193,25 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
     ld(f.img[k], (size_t)y0 * W + x, cr[k], cg[k], cb[k]);
     gc[k] = grey_of(ch, cr[k], cg[k], cb[k]);
   }
+  // stacks of up to 4 frames keep the next row's samples in flight; larger
+  // ones (whose samples would not fit the registers) load each frame's
+  // samples where they are used
+  constexpr bool kAhead = NMAX <= 4;
+  if constexpr (kAhead) fetch(y0);
   for (int y = y0; y < y1; ++y) {
-    const size_t o = (size_t)y * W + x, od = (size_t)min(y + 1, H - 1) * W + x;
-    const size_t ol = (size_t)y * W + xl, orr = (size_t)y * W + xr;
+    const size_t o = (size_t)y * W + x;
+    float Dr[NMAX], Dg[NMAX], Db[NMAX], Lr[NMAX], Lg[NMAX], Lb[NMAX], Rr[NMAX], Rg[NMAX],
+        Rb[NMAX], S[NMAX];
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k) {
+        Dr[k] = dr[k]; Dg[k] = dg[k]; Db[k] = db[k];
+        Lr[k] = lr[k]; Lg[k] = lg[k]; Lb[k] = lb[k];
+        Rr[k] = rr[k]; Rg[k] = rg[k]; Rb[k] = rb[k];
+        S[k] = sv[k];
+      }
+      if (y + 1 < y1) fetch(y + 1);
+    }
     // the raw weights keep 24-bit relative precision as floats once the
     // cancelling differences inside them were taken in double precision
     float wk[NMAX];
@@ -185,20 +219,22 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
       if (k >= n) continue;
-      const float* I = f.img[k];
-      float dr, dg, db, lr, lg, lb, rr, rg, rb;
-      ld(I, od, dr, dg, db);
-      ld(I, ol, lr, lg, lb);
-      ld(I, orr, rr, rg, rb);
+      if constexpr (!kAhead) {
+        const float* I = f.img[k];
+        ld(I, (size_t)min(y + 1, H - 1) * W + x, Dr[k], Dg[k], Db[k]);
+        ld(I, (size_t)y * W + xl, Lr[k], Lg[k], Lb[k]);
+        ld(I, (size_t)y * W + xr, Rr[k], Rg[k], Rb[k]);
+        S[k] = k != ref ? f.ssim[k][o] : 0.f;
+      }
       const bool warped = k != ref;
-      const float sv = warped ? f.ssim[k][o] : 0.f;
-      const double gd = grey_of(ch, dr, dg, db);
-      wk[k] = (float)raw_weight(ch, gu[k], grey_of(ch, lr, lg, lb), grey_of(ch, rr, rg, rb), gd,
-                                gc[k], cr[k], cg[k], cb[k], warped, sv, two_se2);
+      const double gd = grey_of(ch, Dr[k], Dg[k], Db[k]);
+      wk[k] = (float)raw_weight(ch, gu[k], grey_of(ch, Lr[k], Lg[k], Lb[k]),
+                                grey_of(ch, Rr[k], Rg[k], Rb[k]), gd, gc[k], cr[k], cg[k], cb[k],
+                                warped, S[k], two_se2);
       sum += (double)wk[k];
       gu[k] = gc[k];
       gc[k] = gd;
-      cr[k] = dr; cg[k] = dg; cb[k] = db;
+      cr[k] = Dr[k]; cg[k] = Dg[k]; cb[k] = Db[k];
     }
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
