@@ -160,10 +160,7 @@ __global__ __launch_bounds__(kHypThreads) void k_hyp(
   for (int q0 = 0; q0 < nwords; q0 += 8 * 64) {
     unsigned long long r[8];  // eight loads in flight per lane
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int wi = q0 + u * 64 + lane;
-      r[u] = wi < nwords ? vbg[wi] : 0ull;
-    }
+    for (int u = 0; u < 8; ++u) r[u] = vbg[min(q0 + u * 64 + lane, nwords - 1)];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int wi = q0 + u * 64 + lane;
@@ -260,17 +257,23 @@ __global__ __launch_bounds__(kTestThreads) void k_test(
   __shared__ int wc[kItPerBlock][kTestThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int it0 = blockIdx.y * kItPerBlock;
+  // the tile, the hypotheses and their usability are loaded together
+  const int t = blockIdx.x * kTestThreads + tid;
+  const int tc = t < ntiles ? t : ntiles - 1;  // ntiles >= 1 here
+  const uint8_t tf = flags[tc];
+  const int4 mt = tile_match(cxy, disp, tc, w / 2, h / 2);
+  if (tid < 8 * kItPerBlock) {  // one coefficient per thread
+    const int it = min(it0 + (tid >> 3), a.iters - 1);
+    gs[tid >> 3][tid & 7] = G[(size_t)it * 8 + (tid & 7)];
+  }
   if (tid < kItPerBlock) {
     const int it = it0 + tid;
     // usable hypotheses start at 0 and only grow, so the sign is stable
-    const bool good = it < a.iters && __atomic_load_n(&cnt[it], __ATOMIC_RELAXED) >= 0;
-    ok[tid] = good;
-    for (int i = 0; i < 8; ++i) gs[tid][i] = good ? G[(size_t)it * 8 + i] : 0.0;
+    ok[tid] = it < a.iters && __atomic_load_n(&cnt[min(it, a.iters - 1)], __ATOMIC_RELAXED) >= 0;
   }
   __syncthreads();
-  const int t = blockIdx.x * kTestThreads + tid;
-  const bool valid = t < ntiles && (flags[t] & 2);
-  const int4 m = valid ? tile_match(cxy, disp, t, w / 2, h / 2) : make_int4(0, 0, 0, 0);
+  const bool valid = t < ntiles && (tf & 2);
+  const int4 m = valid ? mt : make_int4(0, 0, 0, 0);
   const int word = t >> 6;
   for (int q = 0; q < kItPerBlock; ++q) {
     if (!ok[q]) continue;
@@ -368,9 +371,14 @@ __global__ __launch_bounds__(kUnionThreads) void k_union(
   for (int i0 = 0; i0 < a.iters; i0 += 2 * kUnionThreads) {
     int c[2];
 #pragma unroll
+    for (int r = 0; r < 2; ++r) {  // loads in flight with the match count
+      const int i = i0 + r * kUnionThreads + tid;
+      c[r] = cnt[min(i, a.iters - 1)];
+    }
+#pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int i = i0 + r * kUnionThreads + tid;
-      c[r] = i < a.iters && N >= 4 ? cnt[i] : -1;
+      if (i >= a.iters || N < 4) c[r] = -1;
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -412,7 +420,7 @@ __global__ __launch_bounds__(kUnionThreads) void k_union(
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int i = i0 + u * 64 + lane;
-        r[u] = i < a.iters ? bal[(size_t)wd * a.iters + i] : 0ull;
+        r[u] = bal[(size_t)wd * a.iters + min(i, a.iters - 1)];  // used only if i < iters
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -470,11 +478,13 @@ __global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __r
   __shared__ long long tot[kSums];
   const int lane = threadIdx.x;
   if (lane < kSums) tot[lane] = sums[lane];
+  double Hp[9];  // loaded with the sums
+  for (int i = 0; i < 9; ++i) Hp[i] = Hprev[i];
   __syncthreads();
   if (lane != 0) return;
   const int msel = (int)tot[0];
   counts[1] = msel;
-  for (int i = 0; i < 9; ++i) Hout[i] = Hprev[i];
+  for (int i = 0; i < 9; ++i) Hout[i] = Hp[i];
   if (msel < 4) return;
   const int ox = w / 2, oy = h / 2;
   int k = 0;
@@ -498,8 +508,7 @@ __global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __r
   const double pox = (double)(2 * ox - (w - 1)), poy = (double)(2 * oy - (h - 1));
   const double Pm[9] = {2, 0, pox, 0, 2, poy, 0, 0, (double)w};
   const double Qm[9] = {(double)w, 0, -pox, 0, (double)w, -poy, 0, 0, 2};
-  double T1[9], T2[9], T3[9], Hp[9];
-  for (int i = 0; i < 9; ++i) Hp[i] = Hprev[i];
+  double T1[9], T2[9], T3[9];
   mat3_mul(Pm, Gc, T1);
   mat3_mul(T1, Qm, T2);
   mat3_mul(Hp, T2, T3);
