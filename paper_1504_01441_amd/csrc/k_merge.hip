@@ -16,7 +16,8 @@
 //  k_blend:   from the top level down, R_l = sum_k W_k,l (G_k,l - E(G_k,l+1))
 //             + E(R_l+1), E the EXPAND rule, on 64x16 tiles whose coarse
 //             neighbourhoods are staged (and row-expanded) in LDS; level 0
-//             goes to the output.
+//             goes to the output. Small levels use k_blend_px instead (one
+//             thread per pixel and channel, samples read directly).
 #include "lnr_internal.h"
 
 namespace lnr {
@@ -300,6 +301,7 @@ struct BlendPtrs {
 };
 
 constexpr int kBW = 64, kBH = 16;                 // fine output tile
+constexpr size_t kBlendPxMax = 1 << 18;           // levels up to this size: k_blend_px
 constexpr int kCW = kBW / 2 + 2, kCH = kBH / 2 + 2;  // coarse tile with its EXPAND halo
 
 // One 64 x 16 tile of level l, channels [c0, c0 + cg):
@@ -454,6 +456,40 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
   }
 }
 
+// A pixel of EXPAND(c) at (x, y) of the finer level: rows of the coarse plane
+// (cw x chh, clamped indices) expanded along x first, then along y, with the
+// arithmetic of k_blend's LDS path.
+__device__ inline float expand_px(const float* __restrict__ c, int cw, int chh, int x, int y) {
+  const int i = x >> 1, j = y >> 1;
+  const int xa = max(i - 1, 0), xm = min(i, cw - 1), xp = min(i + 1, cw - 1);
+  float rv[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float* row = c + (size_t)min(max(j - 1 + q, 0), chh - 1) * cw;
+    const float a = row[xa], m = row[xm], p = row[xp];
+    rv[q] = (x & 1) == 0 ? (a + 6.f * m + p) / 8.f : (m + p) / 2.f;
+  }
+  return (y & 1) == 0 ? (rv[0] + 6.f * rv[1] + rv[2]) / 8.f : (rv[1] + rv[2]) / 2.f;
+}
+
+// Small levels: one thread per pixel and channel (blockIdx.y), every sample
+// read straight from memory (all in flight together) instead of staged
+// tiles, which leave too few workgroups to hide their latency.
+__global__ __launch_bounds__(256) void k_blend_px(BlendPtrs b, int n, int w, int h, int cw,
+                                                  int chh, int top) {
+  const int pix = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (pix >= w * h) return;
+  const int x = pix % w, y = pix / w;
+  float acc = 0.f;
+  for (int k = 0; k < n; ++k) {
+    const float wv = b.w[k][pix], gv = b.g[k][c][pix];
+    const float e = top ? 0.f : expand_px(b.gc[k][c], cw, chh, x, y);
+    acc += wv * (gv - e);
+  }
+  if (!top) acc += expand_px(b.rc[c], cw, chh, x, y);
+  b.out[c][pix] = acc;
+}
+
 }  // namespace
 
 int merge_levels(int W, int H) {
@@ -577,6 +613,12 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)((n + 1) * per_plane));
       if (e != hipSuccess) return e;
+    }
+    if ((size_t)lw[l] * lh[l] <= kBlendPxMax) {
+      LNR_LAUNCH(k_blend_px, dim3((lw[l] * lh[l] + 255) / 256, ch), dim3(256), 0, st, bp, n,
+                 lw[l], lh[l], cw, chh, top);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      continue;
     }
     for (int c0 = 0; c0 < ch; c0 += cg) {
       const int g = min(cg, ch - c0);
