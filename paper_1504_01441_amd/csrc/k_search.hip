@@ -124,7 +124,7 @@ struct SearchShape {
   int R, nstrips, nthreads;
   int split;     // patch rows split over this many thread groups (partial SSDs summed in LDS)
   int NR;        // window rows = 2P + 2R + 1
-  int wrow;      // window row stride in bytes (multiple of 16)
+  int wrow;      // window row stride in bytes (an odd number of dwords)
   int ncand;     // 2R + 1
 };
 
@@ -419,7 +419,10 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
   sh.NR = 2 * c.P + 2 * R + 1;
   // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
   const int need = (sh.nstrips * KX) + 4 * (NW + 1);
-  sh.wrow = (need + 15) / 16 * 16;
+  // an odd number of dwords per row: the threads of a wave read rows
+  // (j + i) at dword offsets 2 s, which an even stride maps onto the same banks
+  sh.wrow = (need + 3) / 4 * 4;
+  if ((sh.wrow / 4) % 2 == 0) sh.wrow += 4;
   int block = (sh.nthreads + 63) / 64 * 64;
   if (block < 64) block = 64;
   // (+ KX words: the last strip's padded candidates read past the last row;
