@@ -15,7 +15,9 @@
 //
 //  k_cnn_pack     fp32 master parameters -> bf16 weight layouts for the kernels
 //  k_cnn_input    tile pairs -> network input (2x2 sums, bf16)
-//  k_cnn_fwd      per-wave sample pipeline, weights and activations in LDS;
+//  k_cnn_fwd      four samples per workgroup at a time, four waves per sample
+//                 (each a quarter of every layer's output tiles), weights
+//                 shared in LDS;
 //                 inference writes the proposal (window centre, fallback
 //                 flag), training writes the activations and outputs
 //  k_cnn_loss     loss and output gradient per sample
@@ -34,7 +36,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int CH = 32;
 constexpr int kWave = 64;
-constexpr int kFwdWaves = 4;
+constexpr int kFwdWaves = 16;     // forward workgroup: 4 samples at a time,
+constexpr int kFwdGroupWaves = 4;  // four waves per sample
 
 // flat parameter vector: W1[32][2][3][3] b1 W2[32][32][3][3] b2 W3 b3 W4 b4
 // Wh[3][512] bh[3]
@@ -108,90 +111,93 @@ __global__ __launch_bounds__(256) void k_cnn_input(const uint8_t* __restrict__ r
   }
 }
 
-// conv1 (2 -> 32, stride 1): K = 18 (tap, ci) padded to 32; four output
-// tiles at a time share the B fragments
-__device__ void conv1_fwd(const uint16_t* in /*[16][16][2]*/, const uint16_t* W1p,
-                          const float* bias, uint16_t* out /*[16][16][32]*/, int lane) {
+// The forward layers, each computed by the four waves of a sample (part):
+// conv1 (2 -> 32, stride 1; K = 18 (tap, ci) padded to 32) four of its 16
+// position tiles per wave, the 32 -> 32 layers (3x3, pad 1, stride S, NHWC
+// bf16 in / out, W [co][tap][ci]) one position tile per wave, and the last
+// layer's two channel halves on parts 0 and 1. Every output element sums its
+// MFMA products in (tap, channel half) order.
+// In LDS a position's 32 channels take kPS elements (80 bytes) and a weight
+// row [tap][ci] kWS elements (592 bytes): the padding spreads the 16 rows of
+// an MFMA operand over the banks (unpadded, activation reads conflict ~6-way
+// and weight reads 4-way).
+constexpr int kPS = 40;
+constexpr int kWS = 9 * CH + 8;
+
+__device__ void conv1_fwd_part(const uint16_t* in, const uint16_t* W1p, const float* bias,
+                               uint16_t* out, int lane, int part) {
   const int r = lane & 15, g = lane >> 4;
-  for (int mt0 = 0; mt0 < 16; mt0 += 4) {
-    f32x4 acc[4][2];
+  const int mt0 = 4 * part;
+  f32x4 acc[4][2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int t0 = half * 8 + g * 2;  // taps t0, t0 + 1 (channels 0, 1 each)
-      const bf16x4 b0 = ld4(W1p + r * 32 + half * 16 + g * 4);
-      const bf16x4 b1 = ld4(W1p + (16 + r) * 32 + half * 16 + g * 4);
+  for (int half = 0; half < 2; ++half) {
+    const int t0 = half * 8 + g * 2;  // taps t0, t0 + 1 (channels 0, 1 each)
+    const bf16x4 b0 = ld4(W1p + r * 32 + half * 16 + g * 4);
+    const bf16x4 b1 = ld4(W1p + (16 + r) * 32 + half * 16 + g * 4);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int m = (mt0 + u) * 16 + r, oy = m >> 4, ox = m & 15;
-        uint32_t v[2] = {0u, 0u};
+    for (int u = 0; u < 4; ++u) {
+      const int m = (mt0 + u) * 16 + r, oy = m >> 4, ox = m & 15;
+      uint32_t v[2] = {0u, 0u};
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int tap = t0 + q;
-          const int iy = oy + tap / 3 - 1, ix = ox + tap % 3 - 1;
-          if (tap < 9 && iy >= 0 && iy < 16 && ix >= 0 && ix < 16)
-            v[q] = *reinterpret_cast<const uint32_t*>(in + (iy * 16 + ix) * 2);
-        }
-        bf16x4 a;
-        a[0] = (short)(v[0] & 0xffff); a[1] = (short)(v[0] >> 16);
-        a[2] = (short)(v[1] & 0xffff); a[3] = (short)(v[1] >> 16);
-        acc[u][0] = mfma(a, b0, acc[u][0]);
-        acc[u][1] = mfma(a, b1, acc[u][1]);
+      for (int q = 0; q < 2; ++q) {
+        const int tap = t0 + q;
+        const int iy = oy + tap / 3 - 1, ix = ox + tap % 3 - 1;
+        if (tap < 9 && iy >= 0 && iy < 16 && ix >= 0 && ix < 16)
+          v[q] = *reinterpret_cast<const uint32_t*>(in + (iy * 16 + ix) * 2);
       }
+      bf16x4 a;
+      a[0] = (short)(v[0] & 0xffff); a[1] = (short)(v[0] >> 16);
+      a[2] = (short)(v[1] & 0xffff); a[3] = (short)(v[1] >> 16);
+      acc[u][0] = mfma(a, b0, acc[u][0]);
+      acc[u][1] = mfma(a, b1, acc[u][1]);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int p = (mt0 + u) * 16 + g * 4 + j;
-        out[p * CH + r] = f2bf(fmaxf(acc[u][0][j] + bias[r], 0.f));
-        out[p * CH + 16 + r] = f2bf(fmaxf(acc[u][1][j] + bias[16 + r], 0.f));
-      }
   }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = (mt0 + u) * 16 + g * 4 + j;
+      out[p * kPS + r] = f2bf(fmaxf(acc[u][0][j] + bias[r], 0.f));
+      out[p * kPS + 16 + r] = f2bf(fmaxf(acc[u][1][j] + bias[16 + r], 0.f));
+    }
 }
 
-// conv 32 -> 32 (3x3, pad 1, stride S), NHWC bf16 in / out, W [co][tap][ci].
-// MG output-position tiles at a time: each B fragment serves MG MFMAs and the
-// 2 * MG accumulators are independent chains.
 template <int HIN, int HOUT, int S>
-__device__ void conv_fwd(const uint16_t* in, const uint16_t* W, const float* bias, uint16_t* out,
-                         int lane) {
+__device__ void conv_fwd_part(const uint16_t* in, const uint16_t* W, const float* bias,
+                              uint16_t* out, int lane, int part) {
   const int r = lane & 15, g = lane >> 4;
   constexpr int MT = HOUT * HOUT / 16;
-  constexpr int MG = MT < 4 ? MT : 4;
+  static_assert(MT == 4 || MT == 1, "position tiles per sample");
+  // MT == 4: position tile `part`, both channel halves; MT == 1: channel half
+  // `part` of the single position tile (parts 2, 3 idle)
+  if (MT == 1 && part >= 2) return;
+  const int mt = MT == 4 ? part : 0;
+  const int n0 = MT == 4 ? 0 : part, n1 = MT == 4 ? 2 : part + 1;
   const bf16x4 zero = {0, 0, 0, 0};
-  for (int mt0 = 0; mt0 < MT; mt0 += MG) {
-    f32x4 acc[MG][2];
+  f32x4 acc[2] = {(f32x4){0.f, 0.f, 0.f, 0.f}, (f32x4){0.f, 0.f, 0.f, 0.f}};
+  const int m = mt * 16 + r, oy = m / HOUT, ox = m % HOUT;
 #pragma unroll
-    for (int u = 0; u < MG; ++u) acc[u][0] = acc[u][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < 9; ++tap) {
+    const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+    const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int ci = half * 16 + g * 4;
-        const bf16x4 b0 = ld4(W + (r * 9 + tap) * CH + ci);
-        const bf16x4 b1 = ld4(W + ((16 + r) * 9 + tap) * CH + ci);
-#pragma unroll
-        for (int u = 0; u < MG; ++u) {
-          const int m = (mt0 + u) * 16 + r, oy = m / HOUT, ox = m % HOUT;
-          const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
-          const bool ok = iy >= 0 && iy < HIN && ix >= 0 && ix < HIN;
-          const bf16x4 a = ok ? ld4(in + (iy * HIN + ix) * CH + ci) : zero;
-          acc[u][0] = mfma(a, b0, acc[u][0]);
-          acc[u][1] = mfma(a, b1, acc[u][1]);
-        }
+    for (int half = 0; half < 2; ++half) {
+      const int ci = half * 16 + g * 4;
+      const bf16x4 a = ok ? ld4(in + (iy * HIN + ix) * kPS + ci) : zero;
+      for (int nt = n0; nt < n1; ++nt) {
+        const bf16x4 b = ld4(W + (nt * 16 + r) * kWS + tap * CH + ci);
+        acc[nt - n0] = mfma(a, b, acc[nt - n0]);
       }
     }
-#pragma unroll
-    for (int u = 0; u < MG; ++u)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int p = (mt0 + u) * 16 + g * 4 + j;
-        out[p * CH + r] = f2bf(fmaxf(acc[u][0][j] + bias[r], 0.f));
-        out[p * CH + 16 + r] = f2bf(fmaxf(acc[u][1][j] + bias[16 + r], 0.f));
-      }
   }
+  for (int nt = n0; nt < n1; ++nt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = mt * 16 + g * 4 + j;
+      out[p * kPS + nt * 16 + r] = f2bf(fmaxf(acc[nt - n0][j] + bias[nt * 16 + r], 0.f));
+    }
 }
 
 struct ProposalOut {
@@ -201,11 +207,16 @@ struct ProposalOut {
   float conf_logit;   // window search when the logit is >= this
 };
 
-// LDS: packed weights (W1p, W2..W4), biases, head, then per wave a 16 KB and
-// a 4 KB activation buffer (x -> a1 -> a2 -> a3 -> a4 ping-pong).
-constexpr int kFwdLdsWeights = (kW1p + 3 * kWp) * 2 + 4 * CH * 4 + 3 * 512 * 4 + 4 * 4;
-constexpr int kFwdLdsWave = (8192 + 2048) * 2;
-constexpr int kFwdLds = kFwdLdsWeights + kFwdWaves * kFwdLdsWave;
+// LDS: packed weights (W1p, then W2..W4 with padded rows) and biases, shared
+// by the workgroup's 16 waves; then per sample in flight a 256-position and a
+// 64-position activation buffer (x -> a1 -> a2 -> a3 -> a4 ping-pong). The
+// head's weights are read from global memory.
+constexpr int kFwdLdsWeights = (kW1p + 3 * CH * kWS) * 2 + 4 * CH * 4;
+constexpr int kFwdBufA = 256 * kPS, kFwdBufB = 64 * kPS;  // elements
+constexpr int kFwdLdsSample = (kFwdBufA + kFwdBufB) * 2;
+constexpr int kFwdSamples = kFwdWaves / kFwdGroupWaves;
+constexpr int kFwdLds = kFwdLdsWeights + kFwdSamples * kFwdLdsSample;
+static_assert(kFwdLds <= 160 * 1024, "forward workgroup LDS");
 
 template <bool TRAIN>
 __global__ __launch_bounds__(kFwdWaves * kWave) void k_cnn_fwd(
@@ -213,73 +224,97 @@ __global__ __launch_bounds__(kFwdWaves * kWave) void k_cnn_fwd(
     int n, float* __restrict__ out, uint16_t* __restrict__ acts, ProposalOut po) {
   extern __shared__ __align__(16) uint8_t sm[];
   uint16_t* sW1 = reinterpret_cast<uint16_t*>(sm);
-  uint16_t* sW = sW1 + kW1p;  // [3][32][9][32]
-  float* sb = reinterpret_cast<float*>(sW + 3 * kWp);  // [4][32]
-  float* sWh = sb + 4 * CH;                            // [3][512]
-  float* sbh = sWh + 3 * 512;
+  uint16_t* sW = sW1 + kW1p;  // [3][32 co][kWS]: [9 tap][32 ci] + padding
+  float* sb = reinterpret_cast<float*>(sW + 3 * CH * kWS);  // [4][32]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = wave / kFwdGroupWaves, part = wave % kFwdGroupWaves;
+  const int gt = part * kWave + lane;  // thread index within the sample's group
+  constexpr int GT = kFwdGroupWaves * kWave;
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(pk);
     uint32_t* dst = reinterpret_cast<uint32_t*>(sm);
-    for (int i = tid; i < (kW1p + 3 * kWp) / 2; i += blockDim.x) dst[i] = src[i];
+    for (int i = tid; i < kW1p / 2; i += blockDim.x) dst[i] = src[i];
+    // W2..W4 rows (96 rows of 144 dwords) into the padded rows
+    uint32_t* dw = reinterpret_cast<uint32_t*>(sW);
+    const uint32_t* sw = src + kW1p / 2;
+    for (int i = tid; i < 3 * CH * (9 * CH / 2); i += blockDim.x) {
+      const int row = i / (9 * CH / 2), q = i % (9 * CH / 2);
+      dw[row * (kWS / 2) + q] = sw[i];
+    }
     for (int i = tid; i < 4 * CH; i += blockDim.x) sb[i] = P[kOffB[i / CH] + i % CH];
-    for (int i = tid; i < 3 * 512; i += blockDim.x) sWh[i] = P[kOffWh + i];
-    if (tid < 3) sbh[tid] = P[kOffBh + tid];
   }
-  __syncthreads();
-  uint16_t* bufA = reinterpret_cast<uint16_t*>(sm + kFwdLdsWeights + wave * kFwdLdsWave);
-  uint16_t* bufB = bufA + 8192;
-  for (int s = blockIdx.x * kFwdWaves + wave; s < n; s += gridDim.x * kFwdWaves) {
-    // x: NCHW [2][16][16] -> NHWC [16][16][2] in bufB
-    const uint16_t* xs = x + (size_t)s * 512;
-    for (int i = lane; i < 256; i += kWave) {
-      bufB[2 * i] = xs[i];
-      bufB[2 * i + 1] = xs[256 + i];
-    }
-    if (TRAIN)
-      for (int i = lane; i < 512; i += kWave) acts[(size_t)s * kActN + kActX + i] = bufB[i];
-    conv1_fwd(bufB, sW1, sb, bufA, lane);                     // a1 -> bufA
-    conv_fwd<16, 8, 2>(bufA, sW, sb + CH, bufB, lane);         // a2 -> bufB
-    if (TRAIN) {
-      uint16_t* a = acts + (size_t)s * kActN;
-      for (int i = lane; i < 8192; i += kWave) a[kActA1 + i] = bufA[i];
-      for (int i = lane; i < 2048; i += kWave) a[kActA2 + i] = bufB[i];
-    }
-    conv_fwd<8, 8, 1>(bufB, sW + kWp, sb + 2 * CH, bufA, lane);       // a3 -> bufA
-    conv_fwd<8, 4, 2>(bufA, sW + 2 * kWp, sb + 3 * CH, bufB, lane);   // a4 -> bufB
-    if (TRAIN) {
-      uint16_t* a = acts + (size_t)s * kActN;
-      for (int i = lane; i < 2048; i += kWave) a[kActA3 + i] = bufA[i];
-      for (int i = lane; i < 512; i += kWave) a[kActA4 + i] = bufB[i];
-    }
-    // head (fp32): f = p * 32 + c, eight features per lane
-    float o[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int f = lane * 8 + k;
-      const float a = bf2f(bufB[f]);
-#pragma unroll
-      for (int j = 0; j < 3; ++j) o[j] += sWh[j * 512 + f] * a;
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) o[j] += __shfl_xor(o[j], off);
-    if (lane == 0) {
-      const float o0 = o[0] + sbh[0], o1 = o[1] + sbh[1], o2 = o[2] + sbh[2];
-      if (out) {
-        out[(size_t)s * 3] = o0;
-        out[(size_t)s * 3 + 1] = o1;
-        out[(size_t)s * 3 + 2] = o2;
+  uint16_t* bufA = reinterpret_cast<uint16_t*>(sm + kFwdLdsWeights + grp * kFwdLdsSample);
+  uint16_t* bufB = bufA + kFwdBufA;
+  // every group runs the same number of rounds (the barriers are block-wide);
+  // a group past the last sample idles through its round
+  for (int s0 = blockIdx.x * kFwdSamples; s0 < n; s0 += gridDim.x * kFwdSamples) {
+    const int s = s0 + grp;
+    const bool act = s < n;
+    __syncthreads();  // weights loaded / previous round's buffers free
+    if (act) {
+      // x: NCHW [2][16][16] -> NHWC [16][16][2] in bufB
+      const uint16_t* xs = x + (size_t)s * 512;
+      for (int i = gt; i < 256; i += GT) {
+        bufB[2 * i] = xs[i];
+        bufB[2 * i + 1] = xs[256 + i];
       }
-      if (po.centre) {
-        // window centre: prediction rounded half up, kept inside the search range
-        int cx = (int)floorf(8.f * o0 + 0.5f), cy = (int)floorf(8.f * o1 + 0.5f);
-        cx = min(max(cx, -po.clampc), po.clampc);
-        cy = min(max(cy, -po.clampc), po.clampc);
-        po.centre[2 * s] = cx;
-        po.centre[2 * s + 1] = cy;
-        po.fallback[s] = o2 >= po.conf_logit ? 0 : 1;
+    }
+    __syncthreads();
+    if (act) {
+      if (TRAIN)
+        for (int i = gt; i < 512; i += GT) acts[(size_t)s * kActN + kActX + i] = bufB[i];
+      conv1_fwd_part(bufB, sW1, sb, bufA, lane, part);  // a1 -> bufA
+    }
+    __syncthreads();
+    if (act) conv_fwd_part<16, 8, 2>(bufA, sW, sb + CH, bufB, lane, part);  // a2 -> bufB
+    __syncthreads();
+    if (act) {
+      if (TRAIN) {  // stored unpadded: position * 32 + channel
+        uint16_t* a = acts + (size_t)s * kActN;
+        for (int i = gt; i < 8192; i += GT) a[kActA1 + i] = bufA[(i >> 5) * kPS + (i & 31)];
+        for (int i = gt; i < 2048; i += GT) a[kActA2 + i] = bufB[(i >> 5) * kPS + (i & 31)];
+      }
+    }
+    __syncthreads();  // a1 copied out before a3 overwrites it
+    if (act) conv_fwd_part<8, 8, 1>(bufB, sW + CH * kWS, sb + 2 * CH, bufA, lane, part);  // a3 -> bufA
+    __syncthreads();
+    if (act) conv_fwd_part<8, 4, 2>(bufA, sW + 2 * CH * kWS, sb + 3 * CH, bufB, lane, part);  // a4 -> bufB
+    __syncthreads();
+    if (act && TRAIN) {
+      uint16_t* a = acts + (size_t)s * kActN;
+      for (int i = gt; i < 2048; i += GT) a[kActA3 + i] = bufA[(i >> 5) * kPS + (i & 31)];
+      for (int i = gt; i < 512; i += GT) a[kActA4 + i] = bufB[(i >> 5) * kPS + (i & 31)];
+    }
+    if (act && part == 0) {
+      // head (fp32): f = p * 32 + c, eight features per lane
+      float o[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int f = lane * 8 + k;
+        const float a = bf2f(bufB[(f >> 5) * kPS + (f & 31)]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) o[j] += P[kOffWh + j * 512 + f] * a;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) o[j] += __shfl_xor(o[j], off);
+      if (lane == 0) {
+        const float o0 = o[0] + P[kOffBh], o1 = o[1] + P[kOffBh + 1], o2 = o[2] + P[kOffBh + 2];
+        if (out) {
+          out[(size_t)s * 3] = o0;
+          out[(size_t)s * 3 + 1] = o1;
+          out[(size_t)s * 3 + 2] = o2;
+        }
+        if (po.centre) {
+          // window centre: prediction rounded half up, kept inside the search range
+          int cx = (int)floorf(8.f * o0 + 0.5f), cy = (int)floorf(8.f * o1 + 0.5f);
+          cx = min(max(cx, -po.clampc), po.clampc);
+          cy = min(max(cy, -po.clampc), po.clampc);
+          po.centre[2 * s] = cx;
+          po.centre[2 * s + 1] = cy;
+          po.fallback[s] = o2 >= po.conf_logit ? 0 : 1;
+        }
       }
     }
   }
@@ -543,9 +578,11 @@ hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, in
   return hipGetLastError();
 }
 
+// one workgroup per CU at most (each loads the weights once), looping over
+// the samples four at a time
 static int fwd_blocks(int n) {
-  int b = (n + kFwdWaves - 1) / kFwdWaves;
-  return b < 1024 ? (b < 1 ? 1 : b) : 1024;
+  int b = (n + kFwdSamples - 1) / kFwdSamples;
+  return b < 256 ? (b < 1 ? 1 : b) : 256;
 }
 
 hipError_t launch_cnn_forward(const uint16_t* packed, const float* params, const uint16_t* x,
