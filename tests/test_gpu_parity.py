@@ -335,6 +335,20 @@ def test_register_pair_c2_full_size(ctx):
     assert_close(hdr.cpu().numpy(), want, 1.0, what="merge")
 
 
+@pytest.mark.parametrize("size", [(6144, 1024), (1024, 6144)])
+def test_register_pair_maximum_side(ctx, size):
+    """The largest supported side (6144) in each direction: rows wider than the
+    default 64 KB of workgroup memory in the row propagation, the tallest
+    column shape, 192 tiles per level-0 row or column."""
+    w, h = size
+    st = synth.make_stack(w, h, 21, ratios=(1.0, 4.0), fmt="i420", shift_range=6)
+    p, op = params_pair(radius0=8)
+    reg = lnr().register_pair(ctx, to_gpu_frame(st.frames[0]), to_gpu_frame(st.frames[1]), p)
+    _sync()
+    o = oracle.register_pair(st.frames[0], st.frames[1], op)
+    registration_parity(reg, o)
+
+
 def test_register_deterministic(ctx):
     st = synth.make_config_pair("c1", 15)
     p = lnr().Params(radius0=8)
@@ -407,3 +421,8 @@ def test_register_rejects_bad_arguments(ctx):
     with pytest.raises(lnr().LnrError) as e:
         lnr().register_pair(ctx, tiny, tiny, lnr().Params())
     assert e.value.status == -3
+    # one pixel past the largest supported side
+    wide = lnr().Frame.from_numpy(np.zeros((64, 6145), np.uint8))
+    with pytest.raises(lnr().LnrError) as e:
+        lnr().register_pair(ctx, wide, wide, lnr().Params(radius0=8))
+    assert e.value.status == -2
