@@ -73,6 +73,35 @@ def test_batch_equals_single_calls(lnr, ctx, graph, autotune):
             assert torch.equal(outs[0].flags, singles[0].flags)
 
 
+def test_learned_batch_equals_single_calls(lnr, ctx):
+    """The learned proposal inside a graph-captured batch (network inference
+    and the windowed / fallback searches on the pairs' streams) gives exactly
+    what one learned register_pair call per pair gives, over several replays."""
+    from paper_1504_01441_amd import proposal as prop
+    P, conf = prop.load()
+    lnr.proposal_set(ctx, torch.from_numpy(P).cuda())
+    p = lnr.Params(radius0=12, min_level_dim=64, learned=1, window_r=2, conf_min=conf)
+    pairs = _pairs(lnr, 760)
+    singles = [lnr.register_pair(ctx, r, s, p) for _, _, r, s in pairs]
+    outs = lnr.register_batch(ctx, [q[2] for q in pairs], [q[3] for q in pairs], p, graph=True)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, singles):
+        _same(a, b)
+    for rep in range(2):
+        for o in outs:
+            o.disp.zero_()
+            o.flags.fill_(255)
+        lnr.register_batch(ctx, [q[2] for q in pairs], [q[3] for q in pairs], p, outs=outs,
+                           graph=True)
+        torch.cuda.synchronize()
+        for a, b in zip(outs, singles):
+            _same(a, b)
+    # some tiles took the window and some the fallback
+    fl = np.concatenate([o.flags.cpu().numpy()[: o.tile_off[1]] for o in outs])
+    cornered = (fl & 1) != 0
+    assert (cornered & ((fl & 16) == 0)).any() and (cornered & ((fl & 16) != 0)).any()
+
+
 def test_batch_matches_oracle(lnr, ctx):
     p = lnr.Params(radius0=12, min_level_dim=64)
     op = oracle.params(radius0=12, min_level_dim=64)
