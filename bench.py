@@ -151,8 +151,10 @@ def main():
     reg = lnr.Registration.alloc(W, H, lnr.LNR_I420, p)
     hdr = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
 
-    # the library's autotuner picks the propagation kernel shape for this size
+    # the library's autotuners pick the propagation kernel shape and the
+    # search's workgroup shape per level for this size
     dt_shape = lnr.autotune_flow(ctx, W, H, p)
+    search_split = lnr.autotune_search(ctx, W, H, p)
 
     def step():
         lnr.register_pair(ctx, ref, src, p, out=reg)
@@ -298,6 +300,7 @@ def main():
         "autotuned_dt_shape": {"row_seg": dt_shape[0], "row_block": dt_shape[1],
                                "col_rows": dt_shape[2], "col_cols": dt_shape[3],
                                "col_segments": dt_shape[4]},
+        "autotuned_search_split_per_level": list(search_split),
         "learned_proposal": None if learned is None else
         {k: v for k, v in learned.items() if not k.startswith("_")},
         "roofline": roof,

@@ -219,6 +219,13 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
  * column segment, columns per block, segments per column. Synchronises. */
 lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
                              int32_t* shape_out, void* stream);
+/* Time every workgroup shape of the matcher's search (Sec. 2.2: how many
+ * thread groups share a tile's patch rows) at each pyramid level of a w x h
+ * pair, on a synthetic texture, and use the fastest for those level sizes and
+ * radii from then on (results do not depend on it). splits_out[5]
+ * (optional): the choice per level, 0 past the last level. Synchronises. */
+lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
+                               int32_t* splits_out, void* stream);
 
 /* ---- learned displacement proposal (an extension beyond the paper; it
  * narrows the Sec. 2.2 search). The network: per level-0 tile of 32 x 32 the

@@ -129,6 +129,7 @@ def lib():
         L.lnr_register_batch.argtypes = [vp, C.POINTER(_Frame), C.POINTER(_Frame), i32,
                                          C.POINTER(Params), C.POINTER(_Registration), i32, vp]
         L.lnr_autotune_flow.argtypes = [vp, i32, i32, C.POINTER(Params), vp, vp]
+        L.lnr_autotune_search.argtypes = [vp, i32, i32, C.POINTER(Params), vp, vp]
         L.lnr_trace_enable.argtypes = [vp, i32]
         L.lnr_trace_read.argtypes = [vp, C.POINTER(_TraceEntry), i32]
         for name in ("lnr_trace_enable", "lnr_trace_read", "lnr_create", "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack",
@@ -136,7 +137,8 @@ def lib():
                      "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
                      "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
-                     "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow"):
+                     "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow",
+                     "lnr_autotune_search"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -149,7 +151,7 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_stage_merge", "lnr_trace_enable", "lnr_trace_read",
             "lnr_stage_search_window", "lnr_proposal_set", "lnr_proposal_get",
             "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
-            "lnr_register_batch", "lnr_autotune_flow")
+            "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -504,6 +506,15 @@ def register_batch(ctx: Context, refs, srcs, params: Params | None = None, outs=
     flags = (BATCH_GRAPH if graph else 0) | (BATCH_AUTOTUNE if autotune else 0)
     ctx.check(lib().lnr_register_batch(ctx._h, RA, SA, n, C.byref(p), OA, flags, _stream()))
     return outs
+
+
+def autotune_search(ctx: Context, w: int, h: int, params: Params | None = None):
+    """Pick the fastest search workgroup shape (patch-row split) for each
+    pyramid level of a w x h pair; returns the split per level."""
+    p = params or Params()
+    out = (C.c_int32 * 5)()
+    ctx.check(lib().lnr_autotune_search(ctx._h, w, h, C.byref(p), out, _stream()))
+    return tuple(v for v in out if v)
 
 
 def autotune_flow(ctx: Context, w: int, h: int, params: Params | None = None):

@@ -387,6 +387,16 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   }
 }
 
+// A random 8-bit texture (every tile has corners): the search autotuner's input.
+__global__ __launch_bounds__(256) void k_texture(uint8_t* __restrict__ p, int n, uint32_t seed) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint32_t z = (uint32_t)i * 0x9E3779B1u ^ seed;
+  z = (z ^ (z >> 15)) * 0x2C1B3C6Du;
+  z = (z ^ (z >> 12)) * 0x297A2D39u;
+  p[i] = (uint8_t)(z ^ (z >> 15));
+}
+
 }  // namespace
 
 hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
@@ -397,24 +407,43 @@ hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, ui
   return hipGetLastError();
 }
 
+int search_split_candidates(int R, const SearchCfg& c, int* out, int max) {
+  const int ncand = 2 * R + 1, base = ncand * ((ncand + KX - 1) / KX);
+  int n = 0;
+  for (int s = 1; s <= 7 && s <= 2 * c.P + 1 && n < max; ++s)
+    if (base * s <= 1024) out[n++] = s;
+  return n;
+}
+
+hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  LNR_LAUNCH(k_texture, dim3((n + 255) / 256), dim3(256), 0, st, p, n, seed);
+  return hipGetLastError();
+}
+
 hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
                          int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st,
                          const int32_t* centre, const uint8_t* mode, int want,
-                         unsigned long long* vb) {
+                         unsigned long long* vb, int split) {
   if (ntx * nty == 0) return hipSuccess;
   SearchShape sh;
   sh.R = R;
   sh.ncand = 2 * R + 1;
   sh.nstrips = (sh.ncand + KX - 1) / KX;
-  // when the level has too few candidate threads to fill the chip (coarse
-  // levels, small windows), split the patch rows so that a tile keeps about
-  // 256 threads busy
   const int base = sh.ncand * sh.nstrips;
-  sh.split = (long long)ntx * nty * base >= 262144 ? 1 : (256 + base / 2) / base;
+  if (split > 0) {  // a tuned split (the results do not depend on it)
+    sh.split = split;
+  } else {
+    // when the level has too few candidate threads to fill the chip (coarse
+    // levels, small windows), split the patch rows so that a tile keeps about
+    // 256 threads busy
+    sh.split = (long long)ntx * nty * base >= 262144 ? 1 : (256 + base / 2) / base;
+  }
   if (sh.split < 1) sh.split = 1;
   if (sh.split > 7) sh.split = 7;
   if (sh.split > 2 * c.P + 1) sh.split = 2 * c.P + 1;
+  while (sh.split > 1 && base * sh.split > 1024) --sh.split;
   sh.nthreads = base * sh.split;
   sh.NR = 2 * c.P + 2 * R + 1;
   // bytes read per row: the last strip's (KX/4 + NW + 1) dwords

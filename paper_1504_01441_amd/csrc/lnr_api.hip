@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -91,6 +92,8 @@ struct lnr_ctx {
   };
   std::vector<Cached> graphs;
   std::map<std::vector<uint64_t>, int> batch_k;  // autotuned concurrency per batch
+  // search splits picked by the autotuner, per (level width, height, radius)
+  std::map<std::tuple<int, int, int>, int> search_split;
 };
 
 namespace lnr {
@@ -341,6 +344,10 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
   LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
                          pref, psrc, nullptr, 2, st, out->yeq_ref, out->yeq_src));
   const SearchCfg cfg = search_cfg(*p);
+  auto tuned = [&](int w, int h, int R) {
+    auto it = ctx->search_split.find(std::make_tuple(w, h, R));
+    return it == ctx->search_split.end() ? 0 : it->second;
+  };
   for (int l = g.levels - 1; l >= 0; --l) {
     const Level& L = g.lv[l];
     const int R = l == 0 ? p->radius0 : p->radius_coarse;
@@ -364,12 +371,13 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
                             out->corner_xy, out->disp, out->ssd, out->flags, st, centre, mode, 0,
                             wb.vb));
       LNR_HIP(launch_search(pref, warped, L.w, L.h, R, cfg, L.ntx, L.nty, out->corner_xy,
-                            out->disp, out->ssd, out->flags, st, nullptr, mode, 1, wb.vb));
+                            out->disp, out->ssd, out->flags, st, nullptr, mode, 1, wb.vb,
+                            tuned(L.w, L.h, R)));
     } else {
       LNR_HIP(launch_search(pref + L.pix_off, warped, L.w, L.h, R, cfg, L.ntx, L.nty,
                             out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
                             out->ssd + L.tile_off, out->flags + L.tile_off, st, nullptr,
-                            nullptr, 0, wb.vb));
+                            nullptr, 0, wb.vb, tuned(L.w, L.h, R)));
     }
     LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
                             out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
@@ -844,6 +852,14 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
   if (kt != ctx->batch_k.end()) {
     K = kt->second;
   } else if (flags & LNR_BATCH_AUTOTUNE) {
+    // the search's workgroup shape per level, for every size not tuned yet
+    for (int i = 0; i < n; ++i) {
+      const auto key = std::make_tuple((int)refs[i].width, (int)refs[i].height, (int)p->radius0);
+      if (ctx->search_split.count(key)) continue;
+      if ((s = lnr_autotune_search(ctx, refs[i].width, refs[i].height, p, nullptr, stream)) !=
+          LNR_OK)
+        return s;
+    }
     // time 1, 2, 4 and 8 concurrent streams on this batch (eager), keep the fastest
     const int cand[4] = {1, 2, 4, 8};
     float best = 0.f;
@@ -963,6 +979,68 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
     shape_out[0] = best.seg; shape_out[1] = best.nt; shape_out[2] = best.l;
     shape_out[3] = best.ncol; shape_out[4] = best.nseg;
   }
+  return LNR_OK;
+}
+
+lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
+                               int32_t* splits_out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (w < p->tile || h < p->tile || w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad image size");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const hipStream_t st = (hipStream_t)stream;
+  const Geometry g = make_geometry(w, h, *p);
+  const SearchCfg cfg = search_cfg(*p);
+  // level 0 is the largest: its buffers serve every level
+  const size_t N = (size_t)w * h;
+  const int nt = g.lv[0].ntx * g.lv[0].nty;
+  Plan pl;
+  const size_t o_a = pl.take(N), o_b = pl.take(N);
+  const size_t o_cxy = pl.take((size_t)nt * 2 * sizeof(int32_t));
+  const size_t o_d = pl.take((size_t)nt * 2 * sizeof(int32_t));
+  const size_t o_s = pl.take((size_t)nt * sizeof(uint32_t)), o_f = pl.take((size_t)nt);
+  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  char* b = static_cast<char*>(ctx->ws);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  LNR_HIP(hipEventCreate(&t0));
+  LNR_HIP(hipEventCreate(&t1));
+  for (int l = 0; l < g.levels; ++l) {
+    const Level& L = g.lv[l];
+    const int R = l == 0 ? p->radius0 : p->radius_coarse;
+    const int n = L.w * L.h;
+    // a textured reference and an identical "warped" source: every tile has
+    // corners and every candidate is scored, as on real frames
+    LNR_HIP(launch_texture(reinterpret_cast<uint8_t*>(b + o_a), n, 0x5eedu + (uint32_t)l, st));
+    LNR_HIP(hipMemcpyAsync(b + o_b, b + o_a, (size_t)n, hipMemcpyDeviceToDevice, st));
+    int cand[8];
+    const int nc = search_split_candidates(R, cfg, cand, 8);
+    int best = cand[0];
+    float best_ms = 0.f;
+    for (int c = 0; c < nc; ++c) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 4; ++rep) {  // the first run warms up
+        LNR_HIP(hipEventRecord(t0, st));
+        LNR_HIP(launch_search(reinterpret_cast<uint8_t*>(b + o_a), reinterpret_cast<uint8_t*>(b + o_b),
+                              L.w, L.h, R, cfg, L.ntx, L.nty, reinterpret_cast<int32_t*>(b + o_cxy),
+                              reinterpret_cast<int32_t*>(b + o_d), reinterpret_cast<uint32_t*>(b + o_s),
+                              reinterpret_cast<uint8_t*>(b + o_f), st, nullptr, nullptr, 0, nullptr,
+                              cand[c]));
+        LNR_HIP(hipEventRecord(t1, st));
+        LNR_HIP(hipEventSynchronize(t1));
+        float ms = 0.f;
+        LNR_HIP(hipEventElapsedTime(&ms, t0, t1));
+        if (rep) tot += ms;
+      }
+      if (c == 0 || tot < best_ms) { best_ms = tot; best = cand[c]; }
+    }
+    ctx->search_split[std::make_tuple(L.w, L.h, R)] = best;
+    if (splits_out) splits_out[l] = best;
+  }
+  for (int l = g.levels; l < kMaxLevels && splits_out; ++l) splits_out[l] = 0;
+  LNR_HIP(hipEventDestroy(t0));
+  LNR_HIP(hipEventDestroy(t1));
   return LNR_OK;
 }
 

@@ -79,7 +79,11 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
                          int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st, const int32_t* centre = nullptr,
                          const uint8_t* mode = nullptr, int want = 0,
-                         unsigned long long* vb = nullptr);
+                         unsigned long long* vb = nullptr, int split = 0);
+// splits (patch rows per thread group) that launch_search accepts for radius
+// R, ascending; and a random 8-bit texture for timing the search
+int search_split_candidates(int R, const SearchCfg& c, int* out, int max);
+hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st);
 
 // ---- weeding + level homography (k_weed.hip)
 struct WeedBufs {

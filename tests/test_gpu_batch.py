@@ -126,6 +126,26 @@ def test_autotuned_flow_shape_keeps_parity(lnr, ctx, w, h):
                                                                         min_level_dim=64)))
 
 
+@pytest.mark.parametrize("w,h,radius0", [(640, 480, 12), (1296, 972, 24)])
+def test_autotuned_search_split_keeps_results(lnr, w, h, radius0):
+    # a fresh context: the untuned run uses the default split, the second the tuned one
+    c = lnr.Context(0)
+    p = lnr.Params(radius0=radius0, min_level_dim=64)
+    st = synth.make_stack(w, h, 750 + radius0, ratios=(1.0, 4.0), fmt="i420", shift_range=8)
+    f0, f1 = st.frames
+    F0 = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
+    F1 = lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)
+    before = lnr.register_pair(c, F0, F1, p)
+    torch.cuda.synchronize()
+    splits = lnr.autotune_search(c, w, h, p)
+    assert len(splits) >= 2 and all(1 <= s <= 7 for s in splits)
+    after = lnr.register_pair(c, F0, F1, p)
+    torch.cuda.synchronize()
+    _same(before, after)
+    registration_parity(after, oracle.register_pair(
+        f0, f1, oracle.params(radius0=radius0, min_level_dim=64)))
+
+
 def test_batch_rejects_bad_flags(lnr, ctx):
     import ctypes as C
     ref = _pairs(lnr, 740)[0][2]
