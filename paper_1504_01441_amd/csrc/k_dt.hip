@@ -12,13 +12,19 @@
 // passes): with c close to 1 (sigma_s = 400) a float recursion amplifies
 // rounding by ~1/(1 - c), which would move the flow by ~1e-4 px.
 //
+// Between passes a pixel is one 16-byte record: the three maps (float bits)
+// and the guide byte, so that a column pass reads whole 32-128 byte runs of
+// neighbouring columns rather than 8-32 byte pieces of three planes and the
+// guide.
+//
 //  k_dt_row: one workgroup per row; the row is staged in LDS with coalesced
 //          loads, each of the 256 or 512 threads keeps a segment in registers, and
 //          wave shuffles + LDS combine the segment maps. The first pass writes
-//          the sparse maps itself from the tile list (no zero-fill pass).
+//          the sparse maps itself from the tile list (no zero-fill pass) and
+//          copies the guide into the records.
 //  k_dt_col: one workgroup per strip of 2-8 columns over the full height, as
-//          128 or 256 segments per column held in registers; the maps are read and
-//          written once per pass. The last pass writes F (and N~) instead.
+//          128 or 256 segments per column held in registers; the records are read
+//          and written once per pass. The last pass writes F (and N~) instead.
 #include "lnr_internal.h"
 
 namespace lnr {
@@ -127,7 +133,7 @@ constexpr int kStageU = 4;
 // Horizontal pass: one block per row; the row is staged in LDS (coalesced),
 // each thread keeps a segment of SEG consecutive pixels in registers.
 template <int SEG, int NT, bool FIRST>
-__global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
+__global__ __launch_bounds__(NT) void k_dt_row(uint4* __restrict__ maps,
                                                 const uint8_t* __restrict__ guide, int W, int H,
                                                 const double* __restrict__ coef,
                                                 const int32_t* __restrict__ cxy,
@@ -142,29 +148,26 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
   float* v2 = sm + 2 * W;
   uint8_t* g = reinterpret_cast<uint8_t*>(sm + 3 * W);
   const int y = blockIdx.x, tid = threadIdx.x;
-  const size_t plane = (size_t)W * H, ro = (size_t)y * W;
+  const size_t ro = (size_t)y * W;
   if (tid < 256) cf[tid] = coef[tid];
   // staging: several loads in flight per thread (batches of kStageU per
   // thread, issued before the LDS stores)
   for (int x0 = 0; x0 < W; x0 += kStageU * NT) {
-    uint8_t tg[kStageU];
-    float t0[kStageU], t1[kStageU], t2[kStageU];
+    uint4 t[kStageU];
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int xc = min(x0 + u * NT + tid, W - 1);  // in bounds; stored only if x < W
-      tg[u] = guide[ro + xc];
-      if (!FIRST) {
-        t0[u] = maps[ro + xc]; t1[u] = maps[plane + ro + xc]; t2[u] = maps[2 * plane + ro + xc];
-      }
+      if (FIRST) t[u] = make_uint4(0u, 0u, 0u, guide[ro + xc]);
+      else t[u] = maps[ro + xc];
     }
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int x = x0 + u * NT + tid;
       if (x >= W) break;
-      g[x] = tg[u];
-      v0[x] = FIRST ? 0.f : t0[u];
-      v1[x] = FIRST ? 0.f : t1[u];
-      v2[x] = FIRST ? 0.f : t2[u];
+      g[x] = (uint8_t)t[u].w;
+      v0[x] = __uint_as_float(t[u].x);
+      v1[x] = __uint_as_float(t[u].y);
+      v2[x] = __uint_as_float(t[u].z);
     }
   }
   if (FIRST) {
@@ -257,9 +260,9 @@ __global__ __launch_bounds__(NT) void k_dt_row(float* __restrict__ maps,
   }
   __syncthreads();
 #pragma unroll 4
-  for (int x = tid; x < W; x += NT) {
-    maps[ro + x] = v0[x]; maps[plane + ro + x] = v1[x]; maps[2 * plane + ro + x] = v2[x];
-  }
+  for (int x = tid; x < W; x += NT)
+    maps[ro + x] = make_uint4(__float_as_uint(v0[x]), __float_as_uint(v1[x]),
+                              __float_as_uint(v2[x]), (uint32_t)g[x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,7 +311,7 @@ __device__ void seg_carry(Aff v, bool fwd, Aff* wt /*[NSEG*NCOL/64][NCOL]*/, dou
 }
 
 template <int L, int NCOL, int NSEG, bool LAST>
-__global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps,
+__global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(uint4* __restrict__ maps,
                                                         const uint8_t* __restrict__ guide, int W,
                                                         int H, const double* __restrict__ coef,
                                                         float* __restrict__ flow,
@@ -326,8 +329,10 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
   const size_t plane = (size_t)W * H;
   for (int i = tid; i < 256; i += NCOL * NSEG) cf[i] = coef[i];
   __syncthreads();
-  // guide bytes of rows r0-1 .. r0+L, four per register; the coefficient
-  // between rows r0+j-1 and r0+j is looked up when needed (0 at the ends)
+  // guide bytes of rows r0-1 .. r0+L, four per register (the two halo rows
+  // from the guide image, the segment's own from the records); the
+  // coefficient between rows r0+j-1 and r0+j is looked up when needed (0 at
+  // the ends)
   constexpr int NG = (L + 2 + 3) / 4;
   uint32_t gpk[NG];
 #pragma unroll
@@ -340,13 +345,17 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     const int y = r0 + j;
     const bool in = act && y >= 0 && y < H;
     const size_t o = (size_t)y * W + col;
-    const uint32_t gv = in ? guide[o] : 0u;
-    gpk[(j + 1) >> 2] |= gv << (8 * ((j + 1) & 3));
+    uint32_t gv;
     if (j >= 0 && j < L) {
-      a0[j] = in ? maps[o] : 0.f;
-      a1[j] = in ? maps[plane + o] : 0.f;
-      a2[j] = in ? maps[2 * plane + o] : 0.f;
+      const uint4 r = in ? maps[o] : make_uint4(0u, 0u, 0u, 0u);
+      a0[j] = __uint_as_float(r.x);
+      a1[j] = __uint_as_float(r.y);
+      a2[j] = __uint_as_float(r.z);
+      gv = r.w;
+    } else {
+      gv = in ? guide[o] : 0u;
     }
+    gpk[(j + 1) >> 2] |= gv << (8 * ((j + 1) & 3));
   }
 #define GB(j) ((int)((gpk[((j) + 1) >> 2] >> (8 * (((j) + 1) & 3))) & 255u))
 #define CC(j) ((r0 + (j) > 0 && r0 + (j) < H) ? cf[abs(GB(j) - GB((j) - 1))] : 0.0)
@@ -399,7 +408,6 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
     }
   }
 #undef CC
-#undef GB
   if (!act) return;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
@@ -412,13 +420,15 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(float* __restrict__ maps
       flow[plane + o] = ok ? (float)((double)a1[j] / (double)a2[j]) : 0.f;
       if (ntilde) ntilde[o] = a2[j];
     } else {
-      maps[o] = a0[j]; maps[plane + o] = a1[j]; maps[2 * plane + o] = a2[j];
+      maps[o] = make_uint4(__float_as_uint(a0[j]), __float_as_uint(a1[j]), __float_as_uint(a2[j]),
+                           (uint32_t)GB(j));
     }
   }
+#undef GB
 }
 
 template <int SEG, int NT>
-hipError_t launch_row(bool first, float* maps, const uint8_t* guide, int W, int H,
+hipError_t launch_row(bool first, uint4* maps, const uint8_t* guide, int W, int H,
                       const double* cf, const int32_t* cxy, const int32_t* disp,
                       const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
   const size_t lds = (size_t)W * 3 * sizeof(float) + (size_t)W + 16;
@@ -438,7 +448,7 @@ hipError_t launch_row(bool first, float* maps, const uint8_t* guide, int W, int 
 }
 
 template <int L, int NCOL, int NSEG>
-hipError_t launch_col(bool last, float* maps, const uint8_t* guide, int W, int H,
+hipError_t launch_col(bool last, uint4* maps, const uint8_t* guide, int W, int H,
                       const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
   const dim3 grid((W + NCOL - 1) / NCOL);
   if (last)
@@ -459,7 +469,7 @@ const DtShape kColShapes[] = {{0, 0, 8, 8, 128},  {0, 0, 8, 4, 128},  {0, 0, 16,
                               {0, 0, 8, 2, 256},  {0, 0, 24, 4, 128}, {0, 0, 16, 2, 256},
                               {0, 0, 24, 2, 256}};
 
-hipError_t row_pass(const DtShape& s, bool first, float* maps, const uint8_t* guide, int W, int H,
+hipError_t row_pass(const DtShape& s, bool first, uint4* maps, const uint8_t* guide, int W, int H,
                     const double* cf, const int32_t* cxy, const int32_t* disp,
                     const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
 #define ROW(SEG, NT)                                                                           \
@@ -470,7 +480,7 @@ hipError_t row_pass(const DtShape& s, bool first, float* maps, const uint8_t* gu
   return hipErrorInvalidValue;
 }
 
-hipError_t col_pass(const DtShape& s, bool last, float* maps, const uint8_t* guide, int W, int H,
+hipError_t col_pass(const DtShape& s, bool last, uint4* maps, const uint8_t* guide, int W, int H,
                     const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
 #define COL(L, NC, NS)                                                              \
   if (s.l == L && s.ncol == NC && s.nseg == NS)                                      \
@@ -529,8 +539,9 @@ hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int
 
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
                        int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
-                       const lnr_params& p, float* maps, double* coef, float* flow,
+                       const lnr_params& p, void* maps_v, double* coef, float* flow,
                        float* ntilde, hipStream_t st, const DtShape* shape, bool coef_ready) {
+  uint4* maps = static_cast<uint4*>(maps_v);
   DtArgs a;
   a.iters = p.dt_iters;
   const DtShape sh = shape && dt_shape_valid(*shape, W, H) ? *shape : dt_default_shape(W, H);

@@ -306,7 +306,7 @@ PairPlan plan_pair(int W, int H, const lnr_params* p) {
   q.o_psrc = pl.take(q.g.pyr_bytes);
   q.o_warp = pl.take(N);
   q.wp = plan_weed(pl, q.g.lv[0].ntx * q.g.lv[0].nty, p->weed_iters);
-  q.o_maps = pl.take(3 * N * sizeof(float));
+  q.o_maps = pl.take(dt_maps_bytes(N));
   q.o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   const size_t nt0 = (size_t)q.g.lv[0].ntx * q.g.lv[0].nty;
   q.o_cx = p->learned ? pl.take(nt0 * 512 * sizeof(uint16_t)) : 0;
@@ -333,7 +333,7 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
   uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
   uint8_t* warped = reinterpret_cast<uint8_t*>(base + q.o_warp);
   const WeedBufs wb = weed_bufs(base, q.wp);
-  float* maps = reinterpret_cast<float*>(base + q.o_maps);
+  void* maps = base + q.o_maps;
   double* coef = reinterpret_cast<double*>(base + q.o_coef);
 
   // set-up in one launch: the propagation's coefficient tables, the cleared
@@ -702,12 +702,12 @@ lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t*
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   const size_t N = (size_t)w * h;
   Plan pl;
-  const size_t o_maps = pl.take(3 * N * sizeof(float));
+  const size_t o_maps = pl.take(dt_maps_bytes(N));
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
   char* base = static_cast<char*>(ctx->ws);
   LNR_HIP(launch_flow(corner_xy, disp, flags, w / p->tile, h / p->tile, p->tile, guide, w, h, *p,
-                      reinterpret_cast<float*>(base + o_maps), reinterpret_cast<double*>(base + o_coef),
+                      base + o_maps, reinterpret_cast<double*>(base + o_coef),
                       flow, ntilde, (hipStream_t)stream));
   return LNR_OK;
 }
@@ -937,7 +937,7 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
   const size_t N = (size_t)w * h;
   const int ntx = w / p->tile, nty = h / p->tile, nt = ntx * nty;
   Plan pl;
-  const size_t o_g = pl.take(N), o_maps = pl.take(3 * N * sizeof(float));
+  const size_t o_g = pl.take(N), o_maps = pl.take(dt_maps_bytes(N));
   const size_t o_flow = pl.take(2 * N * sizeof(float)), o_nt = pl.take(N * sizeof(float));
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   const size_t o_cxy = pl.take((size_t)nt * 2 * sizeof(int32_t));
@@ -961,7 +961,7 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
       LNR_HIP(launch_flow(reinterpret_cast<int32_t*>(b + o_cxy), reinterpret_cast<int32_t*>(b + o_d),
                           reinterpret_cast<uint8_t*>(b + o_f), ntx, nty, p->tile,
                           reinterpret_cast<uint8_t*>(b + o_g), w, h, *p,
-                          reinterpret_cast<float*>(b + o_maps), reinterpret_cast<double*>(b + o_coef),
+                          b + o_maps, reinterpret_cast<double*>(b + o_coef),
                           reinterpret_cast<float*>(b + o_flow), reinterpret_cast<float*>(b + o_nt),
                           st, &cand[c]));
       LNR_HIP(hipEventRecord(t1, st));

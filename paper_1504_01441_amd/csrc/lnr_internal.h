@@ -110,9 +110,13 @@ struct DtShape {
 DtShape dt_default_shape(int W, int H);
 bool dt_shape_valid(const DtShape& s, int W, int H);
 int dt_shape_candidates(int W, int H, DtShape* out, int max);
+// The propagation's working maps: one 16-byte record per pixel (the three
+// maps as float bits, then the guide byte), so a column pass reads whole
+// records of neighbouring columns.
+inline size_t dt_maps_bytes(size_t npix) { return npix * 16; }
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
                        int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
-                       const lnr_params& p, float* maps /*[3][H][W]*/, double* coef /*[iters][256]*/,
+                       const lnr_params& p, void* maps /*[H][W] records*/, double* coef /*[iters][256]*/,
                        float* flow, float* ntilde, hipStream_t st, const DtShape* shape = nullptr,
                        bool coef_ready = false);
 // the propagation's coefficient tables (coef [iters][256]); the first block
