@@ -12,16 +12,15 @@
 // passes): with c close to 1 (sigma_s = 400) a float recursion amplifies
 // rounding by ~1/(1 - c), which would move the flow by ~1e-4 px.
 //
-// Between passes a pixel is one 16-byte record: the three maps (float bits)
-// and the guide byte, so that a column pass reads whole 32-128 byte runs of
-// neighbouring columns rather than 8-32 byte pieces of three planes and the
-// guide.
+// Between passes a pixel is one 12-byte record of the three maps, so that a
+// column pass reads whole 24-96 byte runs of neighbouring columns rather than
+// 8-32 byte pieces of three planes; the column pass takes the guide from a
+// column-major copy (a segment's rows are one aligned load).
 //
 //  k_dt_row: one workgroup per row; the row is staged in LDS with coalesced
 //          loads, each of the 256 or 512 threads keeps a segment in registers, and
 //          wave shuffles + LDS combine the segment maps. The first pass writes
-//          the sparse maps itself from the tile list (no zero-fill pass) and
-//          copies the guide into the records.
+//          the sparse maps itself from the tile list (no zero-fill pass).
 //  k_dt_col: one workgroup per strip of 2-8 columns over the full height, as
 //          128 or 256 segments per column held in registers; the records are read
 //          and written once per pass. The last pass writes F (and N~) instead.
@@ -51,6 +50,10 @@ __global__ void k_dt_coef(DtArgs a, double* __restrict__ coef, uint32_t* __restr
   const double ai = exp(-sqrt(2.0) / sig);
   coef[blockIdx.x * 256 + k] = pow(ai, 1.0 + a.ratio * ((double)k / 255.0));
 }
+
+struct Rec {  // one pixel of the three maps between passes
+  float m0, m1, m2;
+};
 
 struct Aff {  // z -> A z + B (three channels share A)
   double A, B0, B1, B2;
@@ -133,7 +136,7 @@ constexpr int kStageU = 4;
 // Horizontal pass: one block per row; the row is staged in LDS (coalesced),
 // each thread keeps a segment of SEG consecutive pixels in registers.
 template <int SEG, int NT, bool FIRST>
-__global__ __launch_bounds__(NT) void k_dt_row(uint4* __restrict__ maps,
+__global__ __launch_bounds__(NT) void k_dt_row(Rec* __restrict__ maps,
                                                 const uint8_t* __restrict__ guide, int W, int H,
                                                 const double* __restrict__ coef,
                                                 const int32_t* __restrict__ cxy,
@@ -153,21 +156,23 @@ __global__ __launch_bounds__(NT) void k_dt_row(uint4* __restrict__ maps,
   // staging: several loads in flight per thread (batches of kStageU per
   // thread, issued before the LDS stores)
   for (int x0 = 0; x0 < W; x0 += kStageU * NT) {
-    uint4 t[kStageU];
+    uint8_t tg[kStageU];
+    Rec t[kStageU];
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int xc = min(x0 + u * NT + tid, W - 1);  // in bounds; stored only if x < W
-      if (FIRST) t[u] = make_uint4(0u, 0u, 0u, guide[ro + xc]);
+      tg[u] = guide[ro + xc];
+      if (FIRST) t[u] = Rec{0.f, 0.f, 0.f};
       else t[u] = maps[ro + xc];
     }
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int x = x0 + u * NT + tid;
       if (x >= W) break;
-      g[x] = (uint8_t)t[u].w;
-      v0[x] = __uint_as_float(t[u].x);
-      v1[x] = __uint_as_float(t[u].y);
-      v2[x] = __uint_as_float(t[u].z);
+      g[x] = tg[u];
+      v0[x] = t[u].m0;
+      v1[x] = t[u].m1;
+      v2[x] = t[u].m2;
     }
   }
   if (FIRST) {
@@ -260,9 +265,7 @@ __global__ __launch_bounds__(NT) void k_dt_row(uint4* __restrict__ maps,
   }
   __syncthreads();
 #pragma unroll 4
-  for (int x = tid; x < W; x += NT)
-    maps[ro + x] = make_uint4(__float_as_uint(v0[x]), __float_as_uint(v1[x]),
-                              __float_as_uint(v2[x]), (uint32_t)g[x]);
+  for (int x = tid; x < W; x += NT) maps[ro + x] = Rec{v0[x], v1[x], v2[x]};
 }
 
 // ---------------------------------------------------------------------------
@@ -311,9 +314,10 @@ __device__ void seg_carry(Aff v, bool fwd, Aff* wt /*[NSEG*NCOL/64][NCOL]*/, dou
 }
 
 template <int L, int NCOL, int NSEG, bool LAST>
-__global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(uint4* __restrict__ maps,
-                                                        const uint8_t* __restrict__ guide, int W,
-                                                        int H, const double* __restrict__ coef,
+__global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(Rec* __restrict__ maps,
+                                                        const uint8_t* __restrict__ gt, int hp,
+                                                        int W, int H,
+                                                        const double* __restrict__ coef,
                                                         float* __restrict__ flow,
                                                         float* __restrict__ ntilde, double nmin) {
   __shared__ double cf[256];
@@ -329,35 +333,47 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(uint4* __restrict__ maps
   const size_t plane = (size_t)W * H;
   for (int i = tid; i < 256; i += NCOL * NSEG) cf[i] = coef[i];
   __syncthreads();
-  // guide bytes of rows r0-1 .. r0+L, four per register (the two halo rows
-  // from the guide image, the segment's own from the records); the
+  // guide bytes of rows r0 .. r0+L-1, four per register, as one aligned load
+  // from the column-major copy (r0 is a multiple of L, a multiple of 8, and
+  // the copy's rows run past r0 + L), plus the rows r0-1 and r0+L; the
   // coefficient between rows r0+j-1 and r0+j is looked up when needed (0 at
   // the ends)
-  constexpr int NG = (L + 2 + 3) / 4;
+  static_assert(L % 8 == 0, "segments are whole 8-byte guide words");
+  constexpr int NG = L / 4;
   uint32_t gpk[NG];
+  uint32_t gup = 0u, gdn = 0u;
+  const bool seg_in = act && r0 < H;
+  const uint8_t* gcol = gt + (size_t)col * hp;
+  if (seg_in) {
+    const uint2* gw = reinterpret_cast<const uint2*>(gcol + r0);
 #pragma unroll
-  for (int q = 0; q < NG; ++q) gpk[q] = 0u;
+    for (int q = 0; q < NG / 2; ++q) {
+      const uint2 v = gw[q];
+      gpk[2 * q] = v.x;
+      gpk[2 * q + 1] = v.y;
+    }
+    if (r0 > 0) gup = gcol[r0 - 1];
+    if (r0 + L < H) gdn = gcol[r0 + L];
+  } else {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) gpk[q] = 0u;
+  }
   // the segment is held as float (as stored between passes); every recursion
   // step and carry is computed in double precision
   float a0[L], a1[L], a2[L];
 #pragma unroll
-  for (int j = -1; j <= L; ++j) {
+  for (int j = 0; j < L; ++j) {
     const int y = r0 + j;
-    const bool in = act && y >= 0 && y < H;
-    const size_t o = (size_t)y * W + col;
-    uint32_t gv;
-    if (j >= 0 && j < L) {
-      const uint4 r = in ? maps[o] : make_uint4(0u, 0u, 0u, 0u);
-      a0[j] = __uint_as_float(r.x);
-      a1[j] = __uint_as_float(r.y);
-      a2[j] = __uint_as_float(r.z);
-      gv = r.w;
-    } else {
-      gv = in ? guide[o] : 0u;
-    }
-    gpk[(j + 1) >> 2] |= gv << (8 * ((j + 1) & 3));
+    const bool in = act && y < H;
+    const Rec r = in ? maps[(size_t)y * W + col] : Rec{0.f, 0.f, 0.f};
+    a0[j] = r.m0;
+    a1[j] = r.m1;
+    a2[j] = r.m2;
   }
-#define GB(j) ((int)((gpk[((j) + 1) >> 2] >> (8 * (((j) + 1) & 3))) & 255u))
+#define GB(j)                                                              \
+  ((j) < 0 ? (int)gup                                                      \
+   : (j) >= L ? (int)gdn                                                   \
+              : (int)((gpk[((j) >= 0 && (j) < L ? (j) : 0) >> 2] >> (8 * ((j) & 3))) & 255u))
 #define CC(j) ((r0 + (j) > 0 && r0 + (j) < H) ? cf[abs(GB(j) - GB((j) - 1))] : 0.0)
   {
     Aff t{1.0, 0.0, 0.0, 0.0};
@@ -408,6 +424,7 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(uint4* __restrict__ maps
     }
   }
 #undef CC
+#undef GB
   if (!act) return;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
@@ -420,15 +437,28 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(uint4* __restrict__ maps
       flow[plane + o] = ok ? (float)((double)a1[j] / (double)a2[j]) : 0.f;
       if (ntilde) ntilde[o] = a2[j];
     } else {
-      maps[o] = make_uint4(__float_as_uint(a0[j]), __float_as_uint(a1[j]), __float_as_uint(a2[j]),
-                           (uint32_t)GB(j));
+      maps[o] = Rec{a0[j], a1[j], a2[j]};
     }
   }
-#undef GB
+}
+
+// The guide's column-major copy for the column pass, one 64 x 64 tile per
+// block (used when the equalisation did not write it).
+__global__ __launch_bounds__(256) void k_guide_columns(const uint8_t* __restrict__ guide, int W,
+                                                       int H, int hp, uint8_t* __restrict__ gt) {
+  __shared__ uint8_t tile[64 * 64];
+  const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int i = threadIdx.x + 256 * u, r = i >> 6, c = i & 63;
+    tile[i] = (by + r < H && bx + c < W) ? guide[(size_t)(by + r) * W + bx + c] : 0;
+  }
+  __syncthreads();
+  store_tile_columns(tile, bx, by, W, hp, gt);
 }
 
 template <int SEG, int NT>
-hipError_t launch_row(bool first, uint4* maps, const uint8_t* guide, int W, int H,
+hipError_t launch_row(bool first, Rec* maps, const uint8_t* guide, int W, int H,
                       const double* cf, const int32_t* cxy, const int32_t* disp,
                       const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
   const size_t lds = (size_t)W * 3 * sizeof(float) + (size_t)W + 16;
@@ -448,14 +478,15 @@ hipError_t launch_row(bool first, uint4* maps, const uint8_t* guide, int W, int 
 }
 
 template <int L, int NCOL, int NSEG>
-hipError_t launch_col(bool last, uint4* maps, const uint8_t* guide, int W, int H,
+hipError_t launch_col(bool last, Rec* maps, const uint8_t* gt, int W, int H,
                       const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
   const dim3 grid((W + NCOL - 1) / NCOL);
+  const int hp = dt_guide_stride(H);
   if (last)
-    LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, true>), grid, dim3(NCOL * NSEG), 0, st, maps, guide, W, H,
-               cf, flow, ntilde, nmin);
+    LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, true>), grid, dim3(NCOL * NSEG), 0, st, maps, gt, hp, W,
+               H, cf, flow, ntilde, nmin);
   else
-    LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, false>), grid, dim3(NCOL * NSEG), 0, st, maps, guide, W,
+    LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, false>), grid, dim3(NCOL * NSEG), 0, st, maps, gt, hp, W,
                H, cf, flow, ntilde, nmin);
   return hipGetLastError();
 }
@@ -469,7 +500,7 @@ const DtShape kColShapes[] = {{0, 0, 8, 8, 128},  {0, 0, 8, 4, 128},  {0, 0, 16,
                               {0, 0, 8, 2, 256},  {0, 0, 24, 4, 128}, {0, 0, 16, 2, 256},
                               {0, 0, 24, 2, 256}};
 
-hipError_t row_pass(const DtShape& s, bool first, uint4* maps, const uint8_t* guide, int W, int H,
+hipError_t row_pass(const DtShape& s, bool first, Rec* maps, const uint8_t* guide, int W, int H,
                     const double* cf, const int32_t* cxy, const int32_t* disp,
                     const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
 #define ROW(SEG, NT)                                                                           \
@@ -480,11 +511,11 @@ hipError_t row_pass(const DtShape& s, bool first, uint4* maps, const uint8_t* gu
   return hipErrorInvalidValue;
 }
 
-hipError_t col_pass(const DtShape& s, bool last, uint4* maps, const uint8_t* guide, int W, int H,
+hipError_t col_pass(const DtShape& s, bool last, Rec* maps, const uint8_t* gt, int W, int H,
                     const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
 #define COL(L, NC, NS)                                                              \
   if (s.l == L && s.ncol == NC && s.nseg == NS)                                      \
-    return launch_col<L, NC, NS>(last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    return launch_col<L, NC, NS>(last, maps, gt, W, H, cf, flow, ntilde, nmin, st);
   COL(8, 8, 128) COL(8, 4, 128) COL(16, 4, 128) COL(8, 2, 256) COL(24, 4, 128)
   COL(16, 2, 256) COL(24, 2, 256)
 #undef COL
@@ -538,10 +569,17 @@ hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int
 }
 
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
-                       int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
-                       const lnr_params& p, void* maps_v, double* coef, float* flow,
-                       float* ntilde, hipStream_t st, const DtShape* shape, bool coef_ready) {
-  uint4* maps = static_cast<uint4*>(maps_v);
+                       int ntx, int nty, int tile, const uint8_t* guide, uint8_t* guide_t,
+                       int W, int H, const lnr_params& p, void* maps_v, double* coef,
+                       float* flow, float* ntilde, hipStream_t st, const DtShape* shape,
+                       bool coef_ready, bool guide_t_ready) {
+  Rec* maps = static_cast<Rec*>(maps_v);
+  if (!guide_t_ready) {
+    LNR_LAUNCH(k_guide_columns, dim3((W + 63) / 64, (H + 63) / 64), dim3(256), 0, st, guide, W, H,
+               dt_guide_stride(H), guide_t);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+  }
   DtArgs a;
   a.iters = p.dt_iters;
   const DtShape sh = shape && dt_shape_valid(*shape, W, H) ? *shape : dt_default_shape(W, H);
@@ -553,7 +591,7 @@ hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint
     const bool first = i == 0, last = i + 1 == a.iters;
     e = row_pass(sh, first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
     if (e != hipSuccess) return e;
-    e = col_pass(sh, last, maps, guide, W, H, cf, flow, ntilde, nmin, st);
+    e = col_pass(sh, last, maps, guide_t, W, H, cf, flow, ntilde, nmin, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

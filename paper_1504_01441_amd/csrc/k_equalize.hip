@@ -6,7 +6,8 @@
 // loads), one global atomic add per bin per block.
 // k_lut_pyr: each block rebuilds the 256-entry LUT from the histogram (wave
 // prefix sums), equalises a 64x64 block of Y and writes pyramid levels 1..L-1
-// of that block from LDS, so the pyramid costs no extra pass over HBM.
+// of that block from LDS, so the pyramid costs no extra pass over HBM; the
+// reference's block is also written column-major for the propagation.
 #include "lnr_internal.h"
 
 namespace lnr {
@@ -108,7 +109,8 @@ __global__ __launch_bounds__(256) void k_lut_pyr(const uint8_t* __restrict__ y0,
                                                  uint8_t* __restrict__ pyr1,
                                                  uint8_t* __restrict__ lut_out,
                                                  uint8_t* __restrict__ out0,
-                                                 uint8_t* __restrict__ out1) {
+                                                 uint8_t* __restrict__ out1,
+                                                 uint8_t* __restrict__ gt0, int hp) {
   __shared__ uint8_t lut[256];
   __shared__ uint8_t tileA[64 * 64];
   __shared__ uint8_t tileB[32 * 32];
@@ -167,6 +169,7 @@ __global__ __launch_bounds__(256) void k_lut_pyr(const uint8_t* __restrict__ y0,
     *reinterpret_cast<uint32_t*>(&tileA[r * 64 + c4]) = packed;
   }
   __syncthreads();
+  if (f == 0 && gt0) store_tile_columns(tileA, bx, by, W, hp, gt0);
   // levels 1.. from the block in LDS; level l of this block covers
   // [bx >> l, (bx >> l) + (64 >> l)) and only pixels inside the level are kept.
   uint8_t* cur = tileA;
@@ -204,7 +207,7 @@ hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int
 hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
                           const uint32_t* hist, const Geometry& geo, uint8_t* pyr0,
                           uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st,
-                          uint8_t* out0, uint8_t* out1) {
+                          uint8_t* out0, uint8_t* out1, uint8_t* gt0) {
   LevelGeom g;
   g.levels = geo.levels;
   for (int l = 0; l < kMaxLevels; ++l) {
@@ -214,7 +217,7 @@ hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
   }
   dim3 grid((geo.W + 63) / 64, (geo.H + 63) / 64, nframes);
   LNR_LAUNCH(k_lut_pyr, grid, dim3(256), 0, st, y0, s0, y1, s1, hist, g, pyr0, pyr1,
-                     lut_out, out0, out1);
+                     lut_out, out0, out1, gt0, dt_guide_stride(geo.H));
   return hipGetLastError();
 }
 

@@ -273,7 +273,7 @@ WeedBufs weed_bufs(char* base, const WeedPlan& w) {
 // Workspace layout of one registration (offsets from the pair's base).
 struct PairPlan {
   Geometry g;
-  size_t bytes, o_hist, o_pref, o_psrc, o_warp, o_maps, o_coef, o_cx, o_cc, o_cm;
+  size_t bytes, o_hist, o_pref, o_psrc, o_warp, o_maps, o_gt, o_coef, o_cx, o_cc, o_cm;
   WeedPlan wp;
 };
 
@@ -307,6 +307,7 @@ PairPlan plan_pair(int W, int H, const lnr_params* p) {
   q.o_warp = pl.take(N);
   q.wp = plan_weed(pl, q.g.lv[0].ntx * q.g.lv[0].nty, p->weed_iters);
   q.o_maps = pl.take(dt_maps_bytes(N));
+  q.o_gt = pl.take(dt_guide_t_bytes(W, H));
   q.o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   const size_t nt0 = (size_t)q.g.lv[0].ntx * q.g.lv[0].nty;
   q.o_cx = p->learned ? pl.take(nt0 * 512 * sizeof(uint16_t)) : 0;
@@ -334,6 +335,7 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
   uint8_t* warped = reinterpret_cast<uint8_t*>(base + q.o_warp);
   const WeedBufs wb = weed_bufs(base, q.wp);
   void* maps = base + q.o_maps;
+  uint8_t* guide_t = reinterpret_cast<uint8_t*>(base + q.o_gt);
   double* coef = reinterpret_cast<double*>(base + q.o_coef);
 
   // set-up in one launch: the propagation's coefficient tables, the cleared
@@ -342,7 +344,7 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
   LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
   // level 0 of both pyramids is also written to the outputs (no copies)
   LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
-                         pref, psrc, nullptr, 2, st, out->yeq_ref, out->yeq_src));
+                         pref, psrc, nullptr, 2, st, out->yeq_ref, out->yeq_src, guide_t));
   const SearchCfg cfg = search_cfg(*p);
   auto tuned = [&](int w, int h, int R) {
     auto it = ctx->search_split.find(std::make_tuple(w, h, R));
@@ -387,7 +389,8 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
   auto it = ctx->dt_shapes.find(std::make_pair(W, H));
   if (it != ctx->dt_shapes.end()) ds = &it->second;
   LNR_HIP(launch_flow(out->corner_xy, out->disp, out->flags, g.lv[0].ntx, g.lv[0].nty, p->tile,
-                      pref, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds, true));
+                      pref, guide_t, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds, true,
+                      true));
   LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], src->format == LNR_I420 ? src->plane[1] : nullptr,
                                src->stride[1], src->format == LNR_I420 ? src->plane[2] : nullptr,
                                src->stride[2], psrc, W, H, out->H + 9, out->flow, out->image,
@@ -703,10 +706,12 @@ lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t*
   const size_t N = (size_t)w * h;
   Plan pl;
   const size_t o_maps = pl.take(dt_maps_bytes(N));
+  const size_t o_gt = pl.take(dt_guide_t_bytes(w, h));
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
   char* base = static_cast<char*>(ctx->ws);
-  LNR_HIP(launch_flow(corner_xy, disp, flags, w / p->tile, h / p->tile, p->tile, guide, w, h, *p,
+  LNR_HIP(launch_flow(corner_xy, disp, flags, w / p->tile, h / p->tile, p->tile, guide,
+                      reinterpret_cast<uint8_t*>(base + o_gt), w, h, *p,
                       base + o_maps, reinterpret_cast<double*>(base + o_coef),
                       flow, ntilde, (hipStream_t)stream));
   return LNR_OK;
@@ -938,6 +943,7 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
   const int ntx = w / p->tile, nty = h / p->tile, nt = ntx * nty;
   Plan pl;
   const size_t o_g = pl.take(N), o_maps = pl.take(dt_maps_bytes(N));
+  const size_t o_gt = pl.take(dt_guide_t_bytes(w, h));
   const size_t o_flow = pl.take(2 * N * sizeof(float)), o_nt = pl.take(N * sizeof(float));
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   const size_t o_cxy = pl.take((size_t)nt * 2 * sizeof(int32_t));
@@ -960,7 +966,8 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
       LNR_HIP(hipEventRecord(t0, st));
       LNR_HIP(launch_flow(reinterpret_cast<int32_t*>(b + o_cxy), reinterpret_cast<int32_t*>(b + o_d),
                           reinterpret_cast<uint8_t*>(b + o_f), ntx, nty, p->tile,
-                          reinterpret_cast<uint8_t*>(b + o_g), w, h, *p,
+                          reinterpret_cast<uint8_t*>(b + o_g), reinterpret_cast<uint8_t*>(b + o_gt),
+                          w, h, *p,
                           b + o_maps, reinterpret_cast<double*>(b + o_coef),
                           reinterpret_cast<float*>(b + o_flow), reinterpret_cast<float*>(b + o_nt),
                           st, &cand[c]));

@@ -63,11 +63,14 @@ struct SearchCfg {
 // ---- equalisation + pyramid (k_equalize.hip)
 hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int W, int H,
                        uint32_t* hist /*[nframes][256]*/, int nframes, hipStream_t st);
-// out0 / out1 (optional): second copies of the equalised level 0
+// out0 / out1 (optional): second copies of the equalised level 0;
+// gt0 (optional): column-major copy of frame 0's equalised level 0, column x
+// at gt0 + x * dt_guide_stride(H) (the propagation's column-pass guide)
 hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
                           const uint32_t* hist, const Geometry& g, uint8_t* pyr0,
                           uint8_t* pyr1, uint8_t* lut_out, int nframes, hipStream_t st,
-                          uint8_t* out0 = nullptr, uint8_t* out1 = nullptr);
+                          uint8_t* out0 = nullptr, uint8_t* out1 = nullptr,
+                          uint8_t* gt0 = nullptr);
 
 // ---- warp + search (k_search.hip)
 struct WeedBufs;
@@ -110,15 +113,40 @@ struct DtShape {
 DtShape dt_default_shape(int W, int H);
 bool dt_shape_valid(const DtShape& s, int W, int H);
 int dt_shape_candidates(int W, int H, DtShape* out, int max);
-// The propagation's working maps: one 16-byte record per pixel (the three
-// maps as float bits, then the guide byte), so a column pass reads whole
-// records of neighbouring columns.
-inline size_t dt_maps_bytes(size_t npix) { return npix * 16; }
+// The propagation's working maps: one 12-byte record per pixel (the three
+// maps), so that a column pass reads whole runs of neighbouring columns.
+inline size_t dt_maps_bytes(size_t npix) { return npix * 12; }
+// The column pass reads the guide column-major: column x at x * stride, the
+// rows padded to a multiple of 64 plus one more 64-row block (so that a
+// segment's aligned load never leaves the column).
+inline int dt_guide_stride(int H) { return ((H + 63) / 64 + 1) * 64; }
+inline size_t dt_guide_t_bytes(int W, int H) { return (size_t)W * dt_guide_stride(H); }
+// guide_t: dt_guide_t_bytes(W, H) of workspace; filled here from guide
+// unless guide_t_ready (k_lut_pyr wrote it)
 hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint8_t* flags,
-                       int ntx, int nty, int tile, const uint8_t* guide, int W, int H,
-                       const lnr_params& p, void* maps /*[H][W] records*/, double* coef /*[iters][256]*/,
-                       float* flow, float* ntilde, hipStream_t st, const DtShape* shape = nullptr,
-                       bool coef_ready = false);
+                       int ntx, int nty, int tile, const uint8_t* guide, uint8_t* guide_t,
+                       int W, int H, const lnr_params& p, void* maps /*[H][W] records*/,
+                       double* coef /*[iters][256]*/, float* flow, float* ntilde,
+                       hipStream_t st, const DtShape* shape = nullptr, bool coef_ready = false,
+                       bool guide_t_ready = false);
+// Column-major copy of a 64 x 64 byte tile held in LDS (row r at tile + 64 r,
+// rows past the image zero): column bx + c gets rows [by, by + 64) at
+// gt + (bx + c) * hp + by. Called by all 256 threads of a block.
+__device__ inline void store_tile_columns(const uint8_t* tile, int bx, int by, int W, int hp,
+                                          uint8_t* __restrict__ gt) {
+  const int c = threadIdx.x >> 2, q = threadIdx.x & 3;
+  if (bx + c >= W) return;
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) v |= (uint32_t)tile[(16 * q + 4 * k + b) * 64 + c] << (8 * b);
+    w[k] = v;
+  }
+  *reinterpret_cast<uint4*>(gt + (size_t)(bx + c) * hp + by + 16 * q) =
+      make_uint4(w[0], w[1], w[2], w[3]);
+}
 // the propagation's coefficient tables (coef [iters][256]); the first block
 // also clears zero[0, nzero) and sets ident (optional) to the 3x3 identity
 hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int nzero,
