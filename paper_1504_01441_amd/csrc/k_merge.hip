@@ -5,9 +5,10 @@
 //
 //  k_ssim:    4 output rows x (256 - 2r) columns per block: the vertical
 //             Gaussian sums of each input column are built in registers, the
-//             horizontal ones from LDS. The sums are double precision: SSIM
-//             divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat
-//             regions) and the fusion weights amplify them again.
+//             horizontal ones from LDS, two output columns per thread. The
+//             sums (x, y, xy, x^2 + y^2) are double precision: SSIM divides
+//             covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat regions)
+//             and the fusion weights amplify them again.
 //  k_weights: per pixel, every frame's C * S * E (* max(SSIM, 0)) + 1e-12,
 //             normalised over the frames; threads walk down columns so that
 //             the Laplacian's rows are read once.
@@ -37,24 +38,27 @@ struct SsimWin {
   double g[2 * kSsimMaxR + 1];
 };
 
-// One block: kSsimTH output rows by 256 - 2R output columns. The five
-// Gaussian sums (x, y, x^2, y^2, xy) are accumulated in double precision:
-// SSIM divides covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat regions)
-// and the fusion weights amplify them again near SSIM = 0, so float sums of
+// One block: kSsimTH output rows by 256 - 2R output columns. SSIM needs the
+// Gaussian sums of x, y, xy and of x^2 + y^2 (only the sum of the two
+// variances enters it), accumulated in double precision: SSIM divides
+// covariance errors by sx^2 + sy^2 + C2 (~1e-3 in flat regions) and the
+// fusion weights amplify them again near SSIM = 0, so float sums of
 // E[x^2] - E[x]^2 are not accurate enough there.
 //  1. vertical: thread t owns input column ox - R + t (clamped) and reads its
 //     kSsimTH + 2R rows straight from global memory (a wave reads 64
 //     consecutive floats per row); each row's values and products are
 //     scattered into the kSsimTH outputs they belong to, all in registers;
-//  2. the vertical sums go to LDS, and thread t (< 256 - 2R) takes the
-//     horizontal window of output column t for every row of the tile.
+//  2. the vertical sums go to LDS; thread t takes output columns 2t and 2t+1
+//     of half the tile's rows, reading the shared window as aligned pairs of
+//     doubles (16-byte LDS reads, half the reads of one column per thread).
 template <int R>
 __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
                                               const float* __restrict__ b, int W, int H,
                                               SsimWin win, double c1, double c2,
                                               float* __restrict__ out) {
-  constexpr int TW = 256 - 2 * R, NR = kSsimTH + 2 * R;
-  __shared__ double vs[5][kSsimTH][256];
+  constexpr int TW = 256 - 2 * R, NR = kSsimTH + 2 * R, NS = 4;
+  static_assert(kSsimTH % 2 == 0, "two row halves");
+  __shared__ double2 vs[NS][kSsimTH][128];  // column pairs of the vertical sums
   int bx, by;
   xcd_block(gridDim.x, gridDim.y, bx, by);
   const int tid = threadIdx.x;
@@ -68,15 +72,15 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
       pa[i] = a[o];
       pb[i] = b[o];
     }
-    double acc[kSsimTH][5];
+    double acc[kSsimTH][NS];
 #pragma unroll
     for (int o = 0; o < kSsimTH; ++o)
 #pragma unroll
-      for (int t = 0; t < 5; ++t) acc[o][t] = 0.0;
+      for (int t = 0; t < NS; ++t) acc[o][t] = 0.0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       const double p = pa[i], q = pb[i];
-      const double pp = p * p, qq = q * q, pq = p * q;
+      const double ss = p * p + q * q, pq = p * q;
 #pragma unroll
       for (int o = 0; o < kSsimTH; ++o) {
         const int k = i - o;  // tap of input row oy - R + i for output row oy + o
@@ -84,34 +88,52 @@ __global__ __launch_bounds__(256) void k_ssim(const float* __restrict__ a,
         const double wd = win.g[k];
         acc[o][0] += wd * p;
         acc[o][1] += wd * q;
-        acc[o][2] += wd * pp;
-        acc[o][3] += wd * qq;
-        acc[o][4] += wd * pq;
+        acc[o][2] += wd * ss;
+        acc[o][3] += wd * pq;
       }
     }
+    double* vd = reinterpret_cast<double*>(vs);
 #pragma unroll
     for (int o = 0; o < kSsimTH; ++o)
 #pragma unroll
-      for (int t = 0; t < 5; ++t) vs[t][o][tid] = acc[o][t];
+      for (int t = 0; t < NS; ++t) vd[(t * kSsimTH + o) * 256 + tid] = acc[o][t];
   }
   __syncthreads();
-  const int gx = ox + tid;
-  if (tid >= TW || gx >= W) return;
+  const int pr = tid & 127, half = tid >> 7;  // column pair, row half
+  const int gx = ox + 2 * pr;
+  if (2 * pr >= TW || gx >= W) return;
+  const bool two = 2 * pr + 1 < TW && gx + 1 < W;
 #pragma unroll
-  for (int o = 0; o < kSsimTH; ++o) {
+  for (int oo = 0; oo < kSsimTH / 2; ++oo) {
+    const int o = half * (kSsimTH / 2) + oo;
     const int gy = oy + o;
     if (gy >= H) break;
-    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double s0[NS] = {0.0, 0.0, 0.0, 0.0}, s1[NS] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k <= 2 * R; ++k) {
-      const double wd = win.g[k];
+    for (int m = 0; m <= R; ++m) {  // inputs 2pr + 2m and 2pr + 2m + 1
+      const double wl = win.g[2 * m];
+      const double wr = 2 * m + 1 <= 2 * R ? win.g[2 * m + 1] : 0.0;
+      const double wp = m > 0 ? win.g[2 * m - 1] : 0.0;
 #pragma unroll
-      for (int t = 0; t < 5; ++t) s[t] += wd * vs[t][o][tid + k];
+      for (int t = 0; t < NS; ++t) {
+        const double2 v = vs[t][o][pr + m];
+        // output 2pr takes taps 2m (v.x) and 2m + 1 (v.y); output 2pr + 1
+        // takes taps 2m - 1 (v.x) and 2m (v.y)
+        s0[t] += wl * v.x;
+        if (2 * m + 1 <= 2 * R) s0[t] += wr * v.y;
+        if (m > 0) s1[t] += wp * v.x;
+        s1[t] += wl * v.y;
+      }
     }
-    const double m1 = s[0], m2 = s[1];
-    const double vx = s[2] - m1 * m1, vy = s[3] - m2 * m2, cxy = s[4] - m1 * m2;
-    out[(size_t)gy * W + gx] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
-                                       ((m1 * m1 + m2 * m2 + c1) * (vx + vy + c2)));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (c == 1 && !two) break;
+      const double* sv = c ? s1 : s0;
+      const double m1 = sv[0], m2 = sv[1];
+      const double vxy = sv[2] - m1 * m1 - m2 * m2, cxy = sv[3] - m1 * m2;
+      out[(size_t)gy * W + gx + c] = (float)(((2.0 * m1 * m2 + c1) * (2.0 * cxy + c2)) /
+                                             ((m1 * m1 + m2 * m2 + c1) * (vxy + c2)));
+    }
   }
 }
 
