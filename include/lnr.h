@@ -38,7 +38,9 @@ typedef enum {
   LNR_E_UNSUPPORTED = -2,  /* parameter outside the supported range     */
   LNR_E_TOO_SMALL = -3,    /* image smaller than one tile               */
   LNR_E_HIP = -4,          /* a HIP runtime call failed                  */
-  LNR_E_NOMEM = -5         /* workspace allocation failed               */
+  LNR_E_NOMEM = -5,        /* workspace allocation failed               */
+  LNR_E_WEIGHTS = -6       /* network file unreadable, of another format
+                              or size, or holding non-finite values     */
 } lnr_status;
 
 typedef enum { LNR_Y8 = 0, LNR_I420 = 1 } lnr_format;
@@ -245,6 +247,16 @@ lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_par
 lnr_status lnr_proposal_set(lnr_ctx* ctx, const float* params, void* stream);
 /* Copy the context's parameters to params[LNR_PROPOSAL_PARAMS] (device). */
 lnr_status lnr_proposal_get(lnr_ctx* ctx, float* params, void* stream);
+/* Network file (host path; little-endian): the 4 bytes "LNRP", uint32
+ * version 1, uint32 parameter count (LNR_PROPOSAL_PARAMS), uint32 0, then
+ * the fp32 parameters in the order above. lnr_proposal_save writes the
+ * context's network (LNR_E_ARG without one; LNR_E_WEIGHTS when the file
+ * cannot be written); it waits for `stream`. lnr_proposal_load reads a file,
+ * checks its header, size and that every value is finite (LNR_E_WEIGHTS
+ * otherwise, before the context's network is touched), then loads it as
+ * lnr_proposal_set does; it waits for the host-to-device copy. */
+lnr_status lnr_proposal_save(lnr_ctx* ctx, const char* path, void* stream);
+lnr_status lnr_proposal_load(lnr_ctx* ctx, const char* path, void* stream);
 /* Network inputs of every full 32 x 32 tile of two dense [h][w] 8-bit
  * images (raster tile order): x[ntiles][2][16][16], bf16 bit patterns. */
 lnr_status lnr_proposal_inputs(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,

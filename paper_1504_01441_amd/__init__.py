@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "liblnr.so")
 
 LNR_Y8, LNR_I420 = 0, 1
 _STATUS = {0: "LNR_OK", -1: "LNR_E_ARG", -2: "LNR_E_UNSUPPORTED", -3: "LNR_E_TOO_SMALL",
-           -4: "LNR_E_HIP", -5: "LNR_E_NOMEM"}
+           -4: "LNR_E_HIP", -5: "LNR_E_NOMEM", -6: "LNR_E_WEIGHTS"}
 
 
 class LnrError(RuntimeError):
@@ -123,6 +123,8 @@ def lib():
                                               vp, vp, vp, vp, vp]
         L.lnr_proposal_set.argtypes = [vp, vp, vp]
         L.lnr_proposal_get.argtypes = [vp, vp, vp]
+        L.lnr_proposal_save.argtypes = [vp, C.c_char_p, vp]
+        L.lnr_proposal_load.argtypes = [vp, C.c_char_p, vp]
         L.lnr_proposal_inputs.argtypes = [vp, vp, vp, i32, i32, vp, vp]
         L.lnr_proposal_forward.argtypes = [vp, vp, i32, vp, vp]
         L.lnr_proposal_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.c_float, vp, vp, vp]
@@ -138,7 +140,7 @@ def lib():
                      "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
                      "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow",
-                     "lnr_autotune_search"):
+                     "lnr_autotune_search", "lnr_proposal_save", "lnr_proposal_load"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -151,7 +153,8 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_stage_merge", "lnr_trace_enable", "lnr_trace_read",
             "lnr_stage_search_window", "lnr_proposal_set", "lnr_proposal_get",
             "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
-            "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search")
+            "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search",
+            "lnr_proposal_save", "lnr_proposal_load")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -454,6 +457,16 @@ def proposal_get(ctx) -> torch.Tensor:
     out = torch.empty(PROPOSAL_PARAMS, dtype=torch.float32, device="cuda")
     ctx.check(lib().lnr_proposal_get(ctx._h, _ptr(out), _stream()))
     return out
+
+
+def proposal_save(ctx, path: str):
+    """Write the context's network to a file (the library's network file format)."""
+    ctx.check(lib().lnr_proposal_save(ctx._h, os.fsencode(path), _stream()))
+
+
+def proposal_load(ctx, path: str):
+    """Load a network file written by proposal_save and reset AdamW."""
+    ctx.check(lib().lnr_proposal_load(ctx._h, os.fsencode(path), _stream()))
 
 
 def proposal_inputs(ctx, ref: torch.Tensor, warped: torch.Tensor) -> torch.Tensor:

@@ -2,6 +2,7 @@
 // workspace, and the order in which the kernels of one registration or merge
 // are enqueued on the caller's stream. No entry point synchronises the device
 // (the homographies and match counts stay in device memory between levels).
+#include <stdio.h>
 #include <string.h>
 
 #include <new>
@@ -1081,11 +1082,11 @@ lnr_status lnr_stage_search_window(lnr_ctx* ctx, const uint8_t* ref, const uint8
   return LNR_OK;
 }
 
-lnr_status lnr_proposal_set(lnr_ctx* ctx, const float* params, void* stream) {
-  if (!ctx) return LNR_E_ARG;
-  TraceGuard tg(ctx);
-  if (!params) return fail(ctx, LNR_E_ARG, "params is null");
-  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+}  // extern "C"
+
+namespace {
+// the context's network buffers (parameters, AdamW moments, packed bf16)
+lnr_status ensure_cnn(lnr_ctx* ctx) {
   const size_t np = (size_t)cnn_param_count();
   if (!ctx->cnn) {
     hipError_t e = hipMalloc(&ctx->cnn, 3 * np * sizeof(float));
@@ -1098,6 +1099,23 @@ lnr_status lnr_proposal_set(lnr_ctx* ctx, const float* params, void* stream) {
       return fail(ctx, LNR_E_NOMEM, "network hipMalloc failed");
     }
   }
+  return LNR_OK;
+}
+
+constexpr uint32_t kNetMagic = 0x50524e4cu;  // "LNRP" little-endian
+constexpr uint32_t kNetVersion = 1u;
+}  // namespace
+
+extern "C" {
+
+lnr_status lnr_proposal_set(lnr_ctx* ctx, const float* params, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!params) return fail(ctx, LNR_E_ARG, "params is null");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const size_t np = (size_t)cnn_param_count();
+  lnr_status s;
+  if ((s = ensure_cnn(ctx)) != LNR_OK) return s;
   const hipStream_t st = (hipStream_t)stream;
   LNR_HIP(hipMemcpyAsync(ctx->cnn, params, np * sizeof(float), hipMemcpyDeviceToDevice, st));
   LNR_HIP(hipMemsetAsync(ctx->cnn + np, 0, 2 * np * sizeof(float), st));
@@ -1114,6 +1132,58 @@ lnr_status lnr_proposal_get(lnr_ctx* ctx, float* params, void* stream) {
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   LNR_HIP(hipMemcpyAsync(params, ctx->cnn, (size_t)cnn_param_count() * sizeof(float),
                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_save(lnr_ctx* ctx, const char* path, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  if (!path) return fail(ctx, LNR_E_ARG, "path is null");
+  if (!ctx->cnn) return fail(ctx, LNR_E_ARG, "no network set");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const size_t np = (size_t)cnn_param_count();
+  std::vector<float> host(np);
+  const hipStream_t st = (hipStream_t)stream;
+  LNR_HIP(hipMemcpyAsync(host.data(), ctx->cnn, np * sizeof(float), hipMemcpyDeviceToHost, st));
+  LNR_HIP(hipStreamSynchronize(st));
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(ctx, LNR_E_WEIGHTS, "cannot open the network file for writing");
+  const uint32_t hdr[4] = {kNetMagic, kNetVersion, (uint32_t)np, 0u};
+  const bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+                  fwrite(host.data(), sizeof(float), np, f) == np;
+  const bool closed = fclose(f) == 0;
+  if (!ok || !closed) return fail(ctx, LNR_E_WEIGHTS, "writing the network file failed");
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_load(lnr_ctx* ctx, const char* path, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!path) return fail(ctx, LNR_E_ARG, "path is null");
+  const size_t np = (size_t)cnn_param_count();
+  std::vector<float> host(np);
+  {
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(ctx, LNR_E_WEIGHTS, "cannot open the network file");
+    uint32_t hdr[4] = {0u, 0u, 0u, 0u};
+    bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == kNetMagic &&
+              hdr[1] == kNetVersion && hdr[2] == (uint32_t)np && hdr[3] == 0u &&
+              fread(host.data(), sizeof(float), np, f) == np;
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;  // nothing after the parameters
+    fclose(f);
+    if (!ok) return fail(ctx, LNR_E_WEIGHTS, "not a network file of this version and size");
+  }
+  for (size_t i = 0; i < np; ++i)
+    if (!std::isfinite(host[i])) return fail(ctx, LNR_E_WEIGHTS, "non-finite network parameter");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  lnr_status s;
+  if ((s = ensure_cnn(ctx)) != LNR_OK) return s;
+  const hipStream_t st = (hipStream_t)stream;
+  LNR_HIP(hipMemcpyAsync(ctx->cnn, host.data(), np * sizeof(float), hipMemcpyHostToDevice, st));
+  LNR_HIP(hipMemsetAsync(ctx->cnn + np, 0, 2 * np * sizeof(float), st));
+  LNR_HIP(launch_cnn_pack(ctx->cnn, ctx->cnn_packed, st));
+  LNR_HIP(hipStreamSynchronize(st));  // the host copy is freed on return
+  ctx->cnn_step = 0;
   return LNR_OK;
 }
 

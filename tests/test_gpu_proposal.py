@@ -209,3 +209,40 @@ def test_learned_registration_agreement_and_gain(lnr, ctx):
     # locally; the error itself is the method's on this workload)
     e_l, e_p = _epe(reg_l, st, w, h), _epe(reg_p, st, w, h)
     assert abs(e_l - e_p) <= 0.01 * e_p + 0.02, (e_l, e_p)
+
+
+def test_network_file_roundtrip_and_rejects(lnr, tmp_path):
+    # a context of its own: the module's context keeps its network
+    c = lnr.Context(0)
+    params = torch.from_numpy(synth.proposal_params(11, head_scale=4.0)).cuda()
+    lnr.proposal_set(c, params)
+    f = tmp_path / "net.bin"
+    lnr.proposal_save(c, str(f))
+    raw = f.read_bytes()
+    hdr = np.frombuffer(raw[:16], "<u4")
+    assert raw[:4] == b"LNRP" and list(hdr[1:]) == [1, lnr.PROPOSAL_PARAMS, 0]
+    assert len(raw) == 16 + 4 * lnr.PROPOSAL_PARAMS
+    assert np.array_equal(np.frombuffer(raw[16:], "<f4"), params.cpu().numpy())
+    x = _bf16_bits(_inputs(3, 64)).cuda()
+    want = lnr.proposal_forward(c, x)
+    lnr.proposal_set(c, torch.zeros_like(params))
+    lnr.proposal_load(c, str(f))
+    torch.cuda.synchronize()
+    assert torch.equal(lnr.proposal_get(c), params)
+    assert torch.equal(lnr.proposal_forward(c, x), want)
+    nan = np.full(lnr.PROPOSAL_PARAMS, np.nan, "<f4").tobytes()
+    bad = {"truncated": raw[:-4], "magic": b"XXXX" + raw[4:], "trailing": raw + b"\0",
+           "version": raw[:4] + np.array([2], "<u4").tobytes() + raw[8:],
+           "count": raw[:8] + np.array([7], "<u4").tobytes() + raw[12:],
+           "nan": raw[:16] + nan}
+    for name, content in bad.items():
+        p = tmp_path / f"bad_{name}.bin"
+        p.write_bytes(content)
+        with pytest.raises(lnr.LnrError) as e:
+            lnr.proposal_load(c, str(p))
+        assert e.value.status == -6, name
+        assert torch.equal(lnr.proposal_get(c), params), name
+    with pytest.raises(lnr.LnrError) as e:
+        lnr.proposal_load(c, str(tmp_path / "missing.bin"))
+    assert e.value.status == -6
+    c.close()
