@@ -43,13 +43,16 @@ typedef enum {
                               or size, or holding non-finite values     */
 } lnr_status;
 
-typedef enum { LNR_Y8 = 0, LNR_I420 = 1 } lnr_format;
+typedef enum { LNR_Y8 = 0, LNR_I420 = 1, LNR_NV12 = 2 } lnr_format;
 
 typedef struct {
   int32_t width, height;
   int32_t format;            /* lnr_format                                      */
   int32_t reserved;
-  const uint8_t* plane[3];   /* Y, U, V (device); U, V null for LNR_Y8          */
+  const uint8_t* plane[3];   /* Y, U, V (device); U, V null for LNR_Y8; for
+                                LNR_NV12 plane[1] holds U and V interleaved
+                                (U first, W bytes per row, H/2 rows) and
+                                plane[2] is unused                             */
   int32_t stride[3];         /* bytes per row of each plane                     */
   float exposure;            /* relative exposure; the shortest is the reference */
 } lnr_frame;

@@ -27,7 +27,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblnr.so")
 
-LNR_Y8, LNR_I420 = 0, 1
+LNR_Y8, LNR_I420, LNR_NV12 = 0, 1, 2
 _STATUS = {0: "LNR_OK", -1: "LNR_E_ARG", -2: "LNR_E_UNSUPPORTED", -3: "LNR_E_TOO_SMALL",
            -4: "LNR_E_HIP", -5: "LNR_E_NOMEM", -6: "LNR_E_WEIGHTS"}
 
@@ -209,20 +209,29 @@ class Context:
 
 @dataclass
 class Frame:
-    """An 8-bit Y8 or I420 frame whose planes are uint8 tensors on the GPU."""
+    """An 8-bit Y8, I420 or NV12 frame whose planes are uint8 tensors on the
+    GPU (NV12: u holds the interleaved U, V plane [H/2, W] and v is None)."""
     y: torch.Tensor
     u: torch.Tensor | None = None
     v: torch.Tensor | None = None
     exposure: float = 1.0
+    nv12: bool = False
 
     @staticmethod
     def from_numpy(y, u=None, v=None, exposure=1.0, device="cuda"):
         t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
         return Frame(t(y), t(u), t(v), float(exposure))
 
+    @staticmethod
+    def nv12_from_numpy(y, uv, exposure=1.0, device="cuda"):
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return Frame(t(y), t(uv), None, float(exposure), True)
+
     @property
     def fmt(self):
-        return LNR_Y8 if self.u is None else LNR_I420
+        if self.u is None:
+            return LNR_Y8
+        return LNR_NV12 if self.nv12 else LNR_I420
 
     @property
     def width(self):
@@ -331,7 +340,7 @@ def merge(ctx: Context, frames, ref_index: int, regs, params: Params | None = No
     p = params or Params()
     n = len(frames)
     f0 = frames[ref_index]
-    ch = 3 if f0.fmt == LNR_I420 else 1
+    ch = 1 if f0.fmt == LNR_Y8 else 3
     out = out if out is not None else torch.empty(ch, f0.height, f0.width, dtype=torch.float32,
                                                   device=f0.y.device)
     FA = (_Frame * n)(*[f._c() for f in frames])
@@ -400,7 +409,7 @@ def stage_flow(ctx, corner_xy, disp, flags, guide: torch.Tensor, params=None):
 
 def stage_backward_warp(ctx, src: Frame, yeq: torch.Tensor, H: torch.Tensor,
                         flow: torch.Tensor):
-    ch = 3 if src.fmt == LNR_I420 else 1
+    ch = 1 if src.fmt == LNR_Y8 else 3
     dev = src.y.device
     img = torch.empty(ch, src.height, src.width, dtype=torch.float32, device=dev)
     yw = torch.empty(src.height, src.width, dtype=torch.float32, device=dev)

@@ -24,7 +24,7 @@ __device__ inline void yuv_rgb(float Y, float U, float V, float& r, float& g, fl
 
 __global__ __launch_bounds__(256) void k_bwarp(const uint8_t* __restrict__ y, int sy,
                                                const uint8_t* __restrict__ u, int su,
-                                               const uint8_t* __restrict__ v, int sv,
+                                               const uint8_t* __restrict__ v, int sv, int cs,
                                                const uint8_t* __restrict__ yeq, int W, int H,
                                                const double* __restrict__ Hn,
                                                const float* __restrict__ flow,
@@ -59,10 +59,11 @@ __global__ __launch_bounds__(256) void k_bwarp(const uint8_t* __restrict__ y, in
     img[o] = Yv / 255.f;
     return;
   }
-  const size_t c00u = (size_t)(y0 >> 1) * su + (x0 >> 1), c10u = (size_t)(y0 >> 1) * su + (x1 >> 1);
-  const size_t c01u = (size_t)(y1 >> 1) * su + (x0 >> 1), c11u = (size_t)(y1 >> 1) * su + (x1 >> 1);
-  const size_t c00v = (size_t)(y0 >> 1) * sv + (x0 >> 1), c10v = (size_t)(y0 >> 1) * sv + (x1 >> 1);
-  const size_t c01v = (size_t)(y1 >> 1) * sv + (x0 >> 1), c11v = (size_t)(y1 >> 1) * sv + (x1 >> 1);
+  const size_t cx0 = (size_t)(x0 >> 1) * cs, cx1 = (size_t)(x1 >> 1) * cs;
+  const size_t c00u = (size_t)(y0 >> 1) * su + cx0, c10u = (size_t)(y0 >> 1) * su + cx1;
+  const size_t c01u = (size_t)(y1 >> 1) * su + cx0, c11u = (size_t)(y1 >> 1) * su + cx1;
+  const size_t c00v = (size_t)(y0 >> 1) * sv + cx0, c10v = (size_t)(y0 >> 1) * sv + cx1;
+  const size_t c01v = (size_t)(y1 >> 1) * sv + cx0, c11v = (size_t)(y1 >> 1) * sv + cx1;
   const float Uv = bil(u[c00u], u[c10u], u[c01u], u[c11u], ax, ay);
   const float Vv = bil(v[c00v], v[c10v], v[c01v], v[c11v], ax, ay);
   float r, g, b;
@@ -77,7 +78,8 @@ __global__ __launch_bounds__(256) void k_bwarp(const uint8_t* __restrict__ y, in
 // [0, 1] into yout (the merge's equalised reference luma).
 __global__ __launch_bounds__(256) void k_frame_rgb4(const uint8_t* __restrict__ y, int sy,
                                                     const uint8_t* __restrict__ u, int su,
-                                                    const uint8_t* __restrict__ v, int sv, int W,
+                                                    const uint8_t* __restrict__ v, int sv, int cs,
+                                                    int W,
                                                     int H, float* __restrict__ img,
                                                     const uint8_t* __restrict__ yin,
                                                     float* __restrict__ yout) {
@@ -100,13 +102,13 @@ __global__ __launch_bounds__(256) void k_frame_rgb4(const uint8_t* __restrict__ 
     for (int k = 0; k < 4; ++k) Yv[k] = px + k < W ? (float)yr[k] : 0.f;
   }
   if (u) {
-    const uint8_t* ur = u + (size_t)(py >> 1) * su + (px >> 1);
-    const uint8_t* vr = v + (size_t)(py >> 1) * sv + (px >> 1);
+    const uint8_t* ur = u + (size_t)(py >> 1) * su + (size_t)(px >> 1) * cs;
+    const uint8_t* vr = v + (size_t)(py >> 1) * sv + (size_t)(px >> 1) * cs;
     const int nc = full ? 2 : (W - px + 1) / 2;  // chroma samples of these pixels
     float U[2] = {128.f, 128.f}, V[2] = {128.f, 128.f};
     for (int c = 0; c < nc; ++c) {
-      U[c] = ur[c];
-      V[c] = vr[c];
+      U[c] = ur[c * cs];
+      V[c] = vr[c * cs];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) yuv_rgb(Yv[k], U[k >> 1], V[k >> 1], r[k], g[k], b[k]);
@@ -145,21 +147,20 @@ __global__ __launch_bounds__(256) void k_frame_rgb4(const uint8_t* __restrict__ 
 
 }  // namespace
 
-hipError_t launch_backward_warp(const uint8_t* y, int sy, const uint8_t* u, int su,
-                                const uint8_t* v, int sv, const uint8_t* yeq, int W, int H,
-                                const double* Hn, const float* flow, float* image, float* yeq_w,
-                                hipStream_t st) {
+hipError_t launch_backward_warp(const uint8_t* y, int sy, const Chroma& c, const uint8_t* yeq,
+                                int W, int H, const double* Hn, const float* flow, float* image,
+                                float* yeq_w, hipStream_t st) {
   dim3 grid((W + 255) / 256, H);
-  LNR_LAUNCH(k_bwarp, grid, dim3(256), 0, st, y, sy, u, su, v, sv, yeq, W, H, Hn, flow,
-                     image, yeq_w);
+  LNR_LAUNCH(k_bwarp, grid, dim3(256), 0, st, y, sy, c.u, c.su, c.v, c.sv, c.cs, yeq, W, H, Hn,
+             flow, image, yeq_w);
   return hipGetLastError();
 }
 
-hipError_t launch_frame_rgb_unit(const uint8_t* y, int sy, const uint8_t* u, int su,
-                                 const uint8_t* v, int sv, int W, int H, float* image,
-                                 const uint8_t* yin, float* yout, hipStream_t st) {
+hipError_t launch_frame_rgb_unit(const uint8_t* y, int sy, const Chroma& c, int W, int H,
+                                 float* image, const uint8_t* yin, float* yout, hipStream_t st) {
   dim3 grid((W + 1023) / 1024, H);
-  LNR_LAUNCH(k_frame_rgb4, grid, dim3(256), 0, st, y, sy, u, su, v, sv, W, H, image, yin, yout);
+  LNR_LAUNCH(k_frame_rgb4, grid, dim3(256), 0, st, y, sy, c.u, c.su, c.v, c.sv, c.cs, W, H,
+             image, yin, yout);
   return hipGetLastError();
 }
 

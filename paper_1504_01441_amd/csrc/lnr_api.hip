@@ -159,7 +159,7 @@ constexpr int kMaxSide = 6144;  // int64 normal equations and row LDS stay in ra
 
 lnr_status check_frame(lnr_ctx* ctx, const lnr_frame* f, const char* name) {
   if (!f) return fail(ctx, LNR_E_ARG, std::string(name) + " is null");
-  if (f->format != LNR_Y8 && f->format != LNR_I420)
+  if (f->format != LNR_Y8 && f->format != LNR_I420 && f->format != LNR_NV12)
     return fail(ctx, LNR_E_UNSUPPORTED, std::string(name) + ": unknown format");
   if (f->width < 1 || f->height < 1 || f->width > kMaxSide || f->height > kMaxSide)
     return fail(ctx, LNR_E_UNSUPPORTED, std::string(name) + ": width/height must be in [1, 6144]");
@@ -171,7 +171,27 @@ lnr_status check_frame(lnr_ctx* ctx, const lnr_frame* f, const char* name) {
     if (!f->plane[1] || !f->plane[2] || f->stride[1] < f->width / 2 || f->stride[2] < f->width / 2)
       return fail(ctx, LNR_E_ARG, std::string(name) + ": bad chroma planes");
   }
+  if (f->format == LNR_NV12) {
+    if (f->width % 2 || f->height % 2)
+      return fail(ctx, LNR_E_ARG, std::string(name) + ": NV12 needs even width and height");
+    if (!f->plane[1] || f->stride[1] < f->width)
+      return fail(ctx, LNR_E_ARG, std::string(name) + ": bad interleaved chroma plane");
+  }
   return LNR_OK;
+}
+
+// the frame's chroma samples (none for luma-only frames)
+Chroma chroma_of(const lnr_frame& f) {
+  Chroma c;
+  if (f.format == LNR_I420) {
+    c.u = f.plane[1]; c.su = f.stride[1];
+    c.v = f.plane[2]; c.sv = f.stride[2];
+  } else if (f.format == LNR_NV12) {
+    c.u = f.plane[1]; c.v = f.plane[1] + 1;
+    c.su = c.sv = f.stride[1];
+    c.cs = 2;
+  }
+  return c;
 }
 
 Geometry make_geometry(int W, int H, const lnr_params& p) {
@@ -392,10 +412,8 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
   LNR_HIP(launch_flow(out->corner_xy, out->disp, out->flags, g.lv[0].ntx, g.lv[0].nty, p->tile,
                       pref, guide_t, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds, true,
                       true));
-  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], src->format == LNR_I420 ? src->plane[1] : nullptr,
-                               src->stride[1], src->format == LNR_I420 ? src->plane[2] : nullptr,
-                               src->stride[2], psrc, W, H, out->H + 9, out->flow, out->image,
-                               out->yeq_warped, st));
+  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], chroma_of(*src), psrc, W, H,
+                               out->H + 9, out->flow, out->image, out->yeq_warped, st));
   return LNR_OK;
 }
 
@@ -517,7 +535,7 @@ lnr_status lnr_query_sizes(int32_t width, int32_t height, int32_t format, const 
     out->level_w[l] = g.lv[l].w;
     out->level_h[l] = g.lv[l].h;
   }
-  out->channels = format == LNR_I420 ? 3 : 1;
+  out->channels = format == LNR_I420 || format == LNR_NV12 ? 3 : 1;
   out->blend_levels = merge_levels(width, height);
   return LNR_OK;
 }
@@ -565,7 +583,7 @@ lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t r
   for (int k = 0; k < n; ++k)
     if ((s = check_frame(ctx, &frames[k], "frame")) != LNR_OK) return s;
   const lnr_frame& rf = frames[ref_index];
-  const int W = rf.width, H = rf.height, ch = rf.format == LNR_I420 ? 3 : 1;
+  const int W = rf.width, H = rf.height, ch = rf.format == LNR_Y8 ? 1 : 3;
   for (int k = 0; k < n; ++k)
     if (frames[k].width != W || frames[k].height != H || frames[k].format != rf.format)
       return fail(ctx, LNR_E_ARG, "frames differ in size or format");
@@ -594,10 +612,9 @@ lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t r
   float* ref_img = reinterpret_cast<float*>(base);
   float* ref_yeq = reinterpret_cast<float*>(base + ((ch * N * sizeof(float) + 255) & ~(size_t)255));
   // the reference's RGB and (with registrations) its equalised luma in [0, 1]
-  LNR_HIP(launch_frame_rgb_unit(rf.plane[0], rf.stride[0], ch == 3 ? rf.plane[1] : nullptr,
-                                rf.stride[1], ch == 3 ? rf.plane[2] : nullptr, rf.stride[2], W,
-                                H, ref_img, n > 1 ? regs[0].yeq_ref : nullptr,
-                                n > 1 ? ref_yeq : nullptr, st));
+  LNR_HIP(launch_frame_rgb_unit(rf.plane[0], rf.stride[0], chroma_of(rf), W, H, ref_img,
+                                n > 1 ? regs[0].yeq_ref : nullptr, n > 1 ? ref_yeq : nullptr,
+                                st));
   const float* imgs[16];
   const float* yeqs[16];
   if (n == 1) {
@@ -727,11 +744,8 @@ lnr_status lnr_stage_backward_warp(lnr_ctx* ctx, const lnr_frame* src, const uin
   if ((s = check_frame(ctx, src, "src")) != LNR_OK) return s;
   if (!yeq || !H || !flow || !image || !yeq_warped) return fail(ctx, LNR_E_ARG, "bad warp arguments");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
-  const bool c = src->format == LNR_I420;
-  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], c ? src->plane[1] : nullptr,
-                               src->stride[1], c ? src->plane[2] : nullptr, src->stride[2], yeq,
-                               src->width, src->height, H, flow, image, yeq_warped,
-                               (hipStream_t)stream));
+  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], chroma_of(*src), yeq, src->width,
+                               src->height, H, flow, image, yeq_warped, (hipStream_t)stream));
   return LNR_OK;
 }
 

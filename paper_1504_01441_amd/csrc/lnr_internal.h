@@ -153,14 +153,20 @@ hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int
                           double* ident, hipStream_t st);
 
 // ---- backward warp (k_warp.hip)
-hipError_t launch_backward_warp(const uint8_t* y, int sy, const uint8_t* u, int su,
-                                const uint8_t* v, int sv, const uint8_t* yeq, int W, int H,
-                                const double* Hn, const float* flow, float* image,
+// Chroma of a 4:2:0 frame: U at u[(y/2) su + (x/2) cs], V likewise (I420: two
+// planes, cs = 1; NV12: one interleaved plane, v = u + 1, cs = 2); u null for
+// luma-only frames.
+struct Chroma {
+  const uint8_t* u = nullptr;
+  const uint8_t* v = nullptr;
+  int su = 0, sv = 0, cs = 1;
+};
+hipError_t launch_backward_warp(const uint8_t* y, int sy, const Chroma& c, const uint8_t* yeq,
+                                int W, int H, const double* Hn, const float* flow, float* image,
                                 float* yeq_w, hipStream_t st);
 // RGB of a frame plus, optionally, an 8-bit plane yin mapped to [0, 1] in yout
-hipError_t launch_frame_rgb_unit(const uint8_t* y, int sy, const uint8_t* u, int su,
-                                 const uint8_t* v, int sv, int W, int H, float* image,
-                                 const uint8_t* yin, float* yout, hipStream_t st);
+hipError_t launch_frame_rgb_unit(const uint8_t* y, int sy, const Chroma& c, int W, int H,
+                                 float* image, const uint8_t* yin, float* yout, hipStream_t st);
 
 // ---- merge (k_merge.hip)
 struct MergeBufs {

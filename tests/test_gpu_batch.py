@@ -146,6 +146,39 @@ def test_autotuned_search_split_keeps_results(lnr, w, h, radius0):
         f0, f1, oracle.params(radius0=radius0, min_level_dim=64)))
 
 
+def test_nv12_equals_i420(lnr, ctx):
+    # the same pixels as interleaved chroma (with a padded row stride) give the
+    # same registration and merge, bit for bit
+    w, h = 418, 330
+    p = lnr.Params(radius0=12, min_level_dim=64)
+    st = synth.make_stack(w, h, 760, ratios=(1.0, 4.0), fmt="i420", shift_range=8)
+    f0, f1 = st.frames
+
+    def nv12(f):
+        uv = torch.zeros(h // 2, w + 64, dtype=torch.uint8)
+        uv[:, 0:w:2] = torch.from_numpy(f.u)
+        uv[:, 1:w:2] = torch.from_numpy(f.v)
+        fr = lnr.Frame.nv12_from_numpy(f.y, np.zeros((1, 1), np.uint8), f.exposure)
+        fr.u = uv.cuda()[:, :w]
+        return fr
+
+    I0 = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
+    I1 = lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)
+    N0, N1 = nv12(f0), nv12(f1)
+    assert N0.fmt == lnr.LNR_NV12 and N0.u.stride(0) == w + 64
+    a = lnr.register_pair(ctx, I0, I1, p)
+    b = lnr.register_pair(ctx, N0, N1, p)
+    torch.cuda.synchronize()
+    _same(a, b)
+    ha = lnr.merge(ctx, [I0, I1], 0, [a], p)
+    hb = lnr.merge(ctx, [N0, N1], 0, [b], p)
+    torch.cuda.synchronize()
+    assert ha.shape == (3, h, w) and torch.equal(ha, hb)
+    # mixed formats are rejected
+    with pytest.raises(lnr.LnrError):
+        lnr.register_pair(ctx, I0, N1, p)
+
+
 def test_batch_rejects_bad_flags(lnr, ctx):
     import ctypes as C
     ref = _pairs(lnr, 740)[0][2]
