@@ -39,7 +39,9 @@ typedef enum {
   LNR_E_TOO_SMALL = -3,    /* image smaller than one tile               */
   LNR_E_HIP = -4,          /* a HIP runtime call failed                  */
   LNR_E_NOMEM = -5,        /* workspace allocation failed               */
-  LNR_E_WEIGHTS = -6       /* network file unreadable, of another format
+  LNR_E_CAPTURE = -6,      /* the workspace would have to grow while the
+                              stream is being captured into a graph     */
+  LNR_E_WEIGHTS = -7       /* network file unreadable, of another format
                               or size, or holding non-finite values     */
 } lnr_status;
 
@@ -141,7 +143,10 @@ lnr_status lnr_query_sizes(int32_t width, int32_t height, int32_t format,
 /* Register `src` to `ref` (paper Sec. 2.2 - 2.4): equalise both, estimate the
  * pyramid homographies (matcher + weeding per level), search level 0, weed,
  * propagate the kept matches to a dense residual flow, and warp the source
- * backwards. Both frames must share size and format. */
+ * backwards. Both frames must share size and format. Only kernel launches are
+ * enqueued (no host round trip, no memset), so the call can be captured into
+ * a graph once a call of the same size has sized the workspace outside the
+ * capture; otherwise it returns LNR_E_CAPTURE. */
 lnr_status lnr_register_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
                              const lnr_params* p, lnr_registration* out, void* stream);
 

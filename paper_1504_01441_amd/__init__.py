@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "liblnr.so")
 
 LNR_Y8, LNR_I420, LNR_NV12 = 0, 1, 2
 _STATUS = {0: "LNR_OK", -1: "LNR_E_ARG", -2: "LNR_E_UNSUPPORTED", -3: "LNR_E_TOO_SMALL",
-           -4: "LNR_E_HIP", -5: "LNR_E_NOMEM", -6: "LNR_E_WEIGHTS"}
+           -4: "LNR_E_HIP", -5: "LNR_E_NOMEM", -6: "LNR_E_CAPTURE", -7: "LNR_E_WEIGHTS"}
 
 
 class LnrError(RuntimeError):

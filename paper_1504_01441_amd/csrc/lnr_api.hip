@@ -246,8 +246,16 @@ struct Plan {
   }
 };
 
-lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes) {
+// Grows the workspace; a stream under graph capture cannot allocate, so a
+// call that needs more workspace there fails with LNR_E_CAPTURE (size it
+// with one call outside the capture first).
+lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes, hipStream_t st) {
   if (bytes <= ctx->ws_size) return LNR_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return fail(ctx, LNR_E_CAPTURE,
+                "the workspace must grow, which a captured stream cannot do: run the call "
+                "once outside the capture first");
   if (ctx->ws) {
     hipError_t e = hipFree(ctx->ws);  // waits for work that may still use it
     ctx->ws = nullptr;
@@ -422,7 +430,7 @@ lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
   lnr_status s;
   if ((s = check_pair(ctx, ref, src, p, out)) != LNR_OK) return s;
   const PairPlan q = plan_pair(ref->width, ref->height, p);
-  if ((s = ensure_ws(ctx, q.bytes)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, q.bytes, st)) != LNR_OK) return s;
   return enqueue_pair(ctx, ref, src, p, out, q, static_cast<char*>(ctx->ws), st);
 }
 
@@ -438,7 +446,7 @@ lnr_status merge_impl(lnr_ctx* ctx, int n, int ch, int W, int H, const float* co
   const size_t o_pyr = pl.take((size_t)n * (ch + 1) * (tot ? tot : 1) * sizeof(float));
   const size_t o_acc = pl.take((size_t)ch * (tot ? tot : 1) * sizeof(float));
   lnr_status s;
-  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, pl.off, st)) != LNR_OK) return s;
   char* base = static_cast<char*>(ctx->ws);
   MergeBufs b;
   b.ssim = reinterpret_cast<float*>(base + o_ssim);
@@ -606,7 +614,7 @@ lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t r
     pl.take((size_t)n * N * 4);
     pl.take((size_t)n * (ch + 1) * (tot ? tot : 1) * 4);
     pl.take((size_t)ch * (tot ? tot : 1) * 4);
-    if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+    if ((s = ensure_ws(ctx, pl.off, st)) != LNR_OK) return s;
   }
   char* base = static_cast<char*>(ctx->ws);
   float* ref_img = reinterpret_cast<float*>(base);
@@ -647,7 +655,7 @@ lnr_status lnr_stage_equalize(lnr_ctx* ctx, const uint8_t* img, int32_t w, int32
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   lnr_status s;
-  if ((s = ensure_ws(ctx, 256 * sizeof(uint32_t))) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, 256 * sizeof(uint32_t), st)) != LNR_OK) return s;
   uint32_t* hist = static_cast<uint32_t*>(ctx->ws);
   Geometry g;
   memset(&g, 0, sizeof(g));
@@ -702,7 +710,7 @@ lnr_status lnr_stage_weed_fit(lnr_ctx* ctx, const int32_t* corner_xy, const int3
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   Plan pl;
   const WeedPlan wp = plan_weed(pl, ntiles, p->weed_iters);
-  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, pl.off, (hipStream_t)stream)) != LNR_OK) return s;
   const WeedBufs wb = weed_bufs(static_cast<char*>(ctx->ws), wp);
   LNR_HIP(launch_weed_fit(corner_xy, disp, flags, ntiles, w, h, level, *p, H_prev, H_out, counts,
                           wb, (hipStream_t)stream));
@@ -726,7 +734,7 @@ lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t*
   const size_t o_maps = pl.take(dt_maps_bytes(N));
   const size_t o_gt = pl.take(dt_guide_t_bytes(w, h));
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
-  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, pl.off, (hipStream_t)stream)) != LNR_OK) return s;
   char* base = static_cast<char*>(ctx->ws);
   LNR_HIP(launch_flow(corner_xy, disp, flags, w / p->tile, h / p->tile, p->tile, guide,
                       reinterpret_cast<uint8_t*>(base + o_gt), w, h, *p,
@@ -889,7 +897,7 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
     for (int c = 0; c < 4; ++c) {
       const int k = cand[c];
       if (k > n) break;
-      if ((s = ensure_ws(ctx, (size_t)k * slot)) != LNR_OK) return s;
+      if ((s = ensure_ws(ctx, (size_t)k * slot, st)) != LNR_OK) return s;
       if ((s = ensure_workers(ctx, k)) != LNR_OK) return s;
       TraceGuard tg(ctx);
       LNR_HIP(hipEventRecord(t0, st));
@@ -904,7 +912,7 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
     LNR_HIP(hipEventDestroy(t1));
     ctx->batch_k[shape] = K;
   }
-  if ((s = ensure_ws(ctx, (size_t)K * slot)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, (size_t)K * slot, st)) != LNR_OK) return s;
   if ((s = ensure_workers(ctx, K)) != LNR_OK) return s;
   if (!(flags & LNR_BATCH_GRAPH)) {
     TraceGuard tg(ctx);
@@ -963,7 +971,7 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   const size_t o_cxy = pl.take((size_t)nt * 2 * sizeof(int32_t));
   const size_t o_d = pl.take((size_t)nt * 2 * sizeof(int32_t)), o_f = pl.take((size_t)nt);
-  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, pl.off, st)) != LNR_OK) return s;
   char* b = static_cast<char*>(ctx->ws);
   // the kernels' work does not depend on the values: a flat guide and no
   // matches time them exactly
@@ -1023,7 +1031,7 @@ lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_par
   const size_t o_cxy = pl.take((size_t)nt * 2 * sizeof(int32_t));
   const size_t o_d = pl.take((size_t)nt * 2 * sizeof(int32_t));
   const size_t o_s = pl.take((size_t)nt * sizeof(uint32_t)), o_f = pl.take((size_t)nt);
-  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, pl.off, st)) != LNR_OK) return s;
   char* b = static_cast<char*>(ctx->ws);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   LNR_HIP(hipEventCreate(&t0));
@@ -1244,7 +1252,7 @@ lnr_status lnr_proposal_train_step(lnr_ctx* ctx, const uint16_t* x, const int32_
   const size_t o_dO = pl.take((size_t)n * 3 * sizeof(float));
   const size_t o_part = pl.take((size_t)nb * np * sizeof(float));
   lnr_status s;
-  if ((s = ensure_ws(ctx, pl.off)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, pl.off, st)) != LNR_OK) return s;
   char* base = static_cast<char*>(ctx->ws);
   uint16_t* acts = reinterpret_cast<uint16_t*>(base + o_act);
   uint16_t* dzs = reinterpret_cast<uint16_t*>(base + o_dz);

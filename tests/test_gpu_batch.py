@@ -179,6 +179,45 @@ def test_nv12_equals_i420(lnr, ctx):
         lnr.register_pair(ctx, I0, N1, p)
 
 
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_register_pair_graph_capture(lnr):
+    # a caller's own graph of one registration: a fresh context cannot grow its
+    # workspace under capture (clean error, nothing enqueued); after one call
+    # outside the capture, every replay equals the eager result, with other
+    # eager work on the same context between the replays
+    c = lnr.Context(0)
+    w, h = 640, 480
+    p = lnr.Params(radius0=12, min_level_dim=64)
+    pairs = []
+    for seed in (770, 771):
+        st = synth.make_stack(w, h, seed, ratios=(1.0, 4.0), fmt="i420", shift_range=8)
+        f0, f1 = st.frames
+        pairs.append((lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure),
+                      lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)))
+    (A0, A1), (B0, B1) = pairs
+    out = lnr.Registration.alloc(w, h, lnr.LNR_I420, p)
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(lnr.LnrError) as e:
+        with torch.cuda.graph(g):
+            lnr.register_pair(c, A0, A1, p, out=out)
+    assert e.value.status == -6
+    torch.cuda.synchronize()
+    want_a = lnr.register_pair(c, A0, A1, p)
+    want_b = lnr.register_pair(c, B0, B1, p)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        lnr.register_pair(c, A0, A1, p, out=out)
+    for _ in range(3):
+        other = lnr.register_pair(c, B0, B1, p)
+        torch.cuda.synchronize()
+        _same(other, want_b)
+        g.replay()
+        torch.cuda.synchronize()
+        _same(out, want_a)
+    c.close()
+
+
 def test_batch_rejects_bad_flags(lnr, ctx):
     import ctypes as C
     ref = _pairs(lnr, 740)[0][2]

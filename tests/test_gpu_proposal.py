@@ -240,9 +240,9 @@ def test_network_file_roundtrip_and_rejects(lnr, tmp_path):
         p.write_bytes(content)
         with pytest.raises(lnr.LnrError) as e:
             lnr.proposal_load(c, str(p))
-        assert e.value.status == -6, name
+        assert e.value.status == -7, name
         assert torch.equal(lnr.proposal_get(c), params), name
     with pytest.raises(lnr.LnrError) as e:
         lnr.proposal_load(c, str(tmp_path / "missing.bin"))
-    assert e.value.status == -6
+    assert e.value.status == -7
     c.close()
