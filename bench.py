@@ -113,9 +113,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "sweep"],
                     help="c2: the 5 MP pair (default); c4: 64 uneven pairs in one batched call; "
-                         "c5: 16 5 MP pairs in one batched call, learned proposal vs plain")
+                         "c5: 16 5 MP pairs in one batched call, learned proposal vs plain; "
+                         "sweep: registration time from VGA to 12 MP")
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the c4 batch")
     ap.add_argument("--calib-copy", action="store_true",
                     help="one 256 MiB device-to-device copy before the steps (the reference "
@@ -131,6 +132,8 @@ def main():
         return batch_main(args)
     if args.workload == "c5":
         return learned_batch_main(args)
+    if args.workload == "sweep":
+        return sweep_main(args)
 
     import numpy as np
     import torch
@@ -398,6 +401,83 @@ def batch_main(args):
         "sequential_register_pair": {"ms": round(ms_s, 3),
                                      "mpix_s": round(mpix / (ms_s / 1e3), 2)},
         "first_call_s (autotune + capture)": round(t_setup, 2),
+    }
+    print(json.dumps(result))
+
+
+def _sweep_pair(wh):
+    import synth
+    return synth.make_sweep_pair(wh[0], wh[1], 1)
+
+
+def sweep_main(args):
+    """Registration (and registration + merge) time of one pair at six sizes
+    from VGA to 12 MP with the 5 MP pair's recipe, each size autotuned; the
+    exponent of time against pixel count (least squares in log-log) says how
+    the path scales (below 1: sublinear, fixed per-level costs dominate small
+    images)."""
+    import concurrent.futures as cf
+    import synth
+    t0 = time.time()
+    sizes = list(synth.SWEEP_SIZES)
+    with cf.ProcessPoolExecutor(min(6, os.cpu_count() or 1)) as ex:
+        stacks = list(ex.map(_sweep_pair, sizes))
+    print(f"[bench] generated {len(stacks)} pairs in {time.time() - t0:.0f} s", file=sys.stderr,
+          flush=True)
+    import numpy as np
+    import torch
+    import paper_1504_01441_amd as lnr
+    ctx = lnr.Context(0)
+    rows = []
+    for st in stacks:
+        f0, f1 = st.frames
+        W, H = f0.width, f0.height
+        p = lnr.Params(radius0=st.meta["radius0"])
+        ref = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
+        src = lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)
+        reg = lnr.Registration.alloc(W, H, lnr.LNR_I420, p)
+        hdr = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
+        lnr.autotune_flow(ctx, W, H, p)
+        lnr.autotune_search(ctx, W, H, p)
+
+        def timed(fn):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - a) / args.steps * 1e3
+
+        ms_reg = timed(lambda: lnr.register_pair(ctx, ref, src, p, out=reg))
+        ms_all = timed(lambda: (lnr.register_pair(ctx, ref, src, p, out=reg),
+                                lnr.merge(ctx, [ref, src], 0, [reg], p, out=hdr)))
+        mp = W * H / 1e6
+        rows.append({"width": W, "height": H, "mpix": round(mp, 3),
+                     "registration_ms": round(ms_reg, 4),
+                     "registration_mpix_s": round(mp / (ms_reg / 1e3), 1),
+                     "with_merge_ms": round(ms_all, 4),
+                     "with_merge_mpix_s": round(mp / (ms_all / 1e3), 1)})
+        print(f"[bench] {W}x{H}: registration {ms_reg:.3f} ms, with merge {ms_all:.3f} ms",
+              file=sys.stderr, flush=True)
+    x = np.log([r["mpix"] for r in rows])
+    y = np.log([r["registration_ms"] for r in rows])
+    slope = float(np.polyfit(x, y, 1)[0])
+    ym = np.log([r["with_merge_ms"] for r in rows])
+    slope_m = float(np.polyfit(x, ym, 1)[0])
+    result = {
+        "metric": "exponent of registration time against pixel count, VGA to 12 MP",
+        "value": round(slope, 4), "unit": "d log t / d log N", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": rows[-1]["registration_ms"], "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "u8+f32", "data": "synthetic",
+        "config": {"workload": "one pair per size, 640x480 .. 4000x3000 I420, the 5 MP pair's "
+                               "recipe (ratio 8, noise sigma 2 DN, 10% movers, radius 16), "
+                               "seed 1; each size autotuned; ms_per_step is the 12 MP "
+                               "registration"},
+        "with_merge_exponent": round(slope_m, 4),
+        "sizes": rows,
     }
     print(json.dumps(result))
 

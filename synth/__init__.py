@@ -13,6 +13,8 @@ from .scenes import (  # noqa: F401
     make_stack,
     make_config_pair,
     make_batch_pair,
+    make_sweep_pair,
+    SWEEP_SIZES,
     make_planted_shift_pair,
     make_texture,
     CONFIGS,

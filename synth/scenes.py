@@ -242,6 +242,23 @@ def make_config_pair(name, seed, scale=None):
     return st
 
 
+# Pixel-count sweep, VGA to 12 MP (4:3), for runtime against image size
+SWEEP_SIZES = ((640, 480), (1280, 960), (2048, 1536), (2592, 1944), (3264, 2448), (4000, 3000))
+
+
+def make_sweep_pair(W, H, seed):
+    """The 5 MP pair's recipe (I420, ratio 8, noise sigma 2 DN, 10% mover
+    tiles, radius 16) at another size."""
+    cfg = dict(CONFIGS["c2"])
+    radius0 = cfg.pop("radius0")
+    cfg.pop("W")
+    cfg.pop("H")
+    st = make_stack(W, H, seed, **cfg)
+    st.meta["radius0"] = radius0
+    st.meta["config"] = "sweep"
+    return st
+
+
 def make_batch_pair(seed):
     """One pair of the batched workload: width and height drawn uniformly over
     even sizes from 640x480 to 4032x3024, 8-bit I420, exposure ratio in

@@ -349,6 +349,20 @@ def test_register_pair_maximum_side(ctx, size):
     registration_parity(reg, o)
 
 
+@pytest.mark.parametrize("size", [(1280, 960), (3264, 2448)])
+def test_sweep_sizes_match_oracle(ctx, size):
+    """Pairs of the pixel-count sweep (the 5 MP recipe at other sizes), in the
+    autotuned launch configuration the sweep times."""
+    w, h = size
+    st = synth.make_sweep_pair(w, h, 1)
+    p, op = params_pair(radius0=16)
+    lnr().autotune_flow(ctx, w, h, p)
+    lnr().autotune_search(ctx, w, h, p)
+    reg = lnr().register_pair(ctx, to_gpu_frame(st.frames[0]), to_gpu_frame(st.frames[1]), p)
+    _sync()
+    registration_parity(reg, oracle.register_pair(st.frames[0], st.frames[1], op))
+
+
 def test_register_deterministic(ctx):
     st = synth.make_config_pair("c1", 15)
     p = lnr().Params(radius0=8)
