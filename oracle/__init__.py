@@ -83,6 +83,9 @@ def lib():
         _lib.lo_hypothesis_inliers.restype = C.c_int
         _lib.lo_register_pair.restype = C.c_int
         _lib.lo_merge.restype = C.c_int
+        _lib.lo_irradiance.restype = C.c_int
+        _lib.lo_hat_weight.restype = C.c_double
+        _lib.lo_hat_weight.argtypes = [C.c_double]
         _lib.lo_num_blend_levels.restype = C.c_int
     return _lib
 
@@ -328,6 +331,29 @@ def merge(imgs, yeqs, ref_index, p=None):
     if rc:
         raise ValueError("lo_merge failed")
     return out
+
+
+def irradiance(imgs, yeqs, exposures, ref_index, p=None):
+    """HDR irradiance map (reference units) of frames imgs ([ch][H][W] in
+    [0, 1]) with relative exposures, deghosted by SSIM of yeqs; see
+    lo_irradiance."""
+    p = p or params()
+    imgs = [_c(i, np.float64) for i in imgs]
+    yeqs = [_c(y, np.float64) for y in yeqs]
+    ex = _c(np.asarray(exposures, np.float64), np.float64)
+    n = len(imgs)
+    ch, h, w = imgs[0].shape
+    out = np.zeros((ch, h, w), np.float64)
+    IA = (C.c_void_p * n)(*[_p(i) for i in imgs])
+    YA = (C.c_void_p * n)(*[_p(y) for y in yeqs])
+    rc = lib().lo_irradiance(n, ch, w, h, IA, YA, _p(ex), ref_index, C.byref(p), _p(out))
+    if rc:
+        raise ValueError("lo_irradiance failed")
+    return out
+
+
+def hat_weight(v):
+    return lib().lo_hat_weight(float(v))
 
 
 # --------------------------------------------------------------------------- whole pair

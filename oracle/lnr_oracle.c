@@ -879,6 +879,55 @@ int lo_merge(int n, int ch, int w, int h, const double* const* imgs,
 }
 
 /* ---------------------------------------------------------------------------
+ * HDR irradiance map of the registered stack. In its quality comparison
+ * (Sec. 3.1) the paper merges the warped frames into an irradiance map
+ * (then tonemaps it) instead of running its error-tolerant fusion, without
+ * giving the merge's formula. Reading: the frames are linear in irradiance;
+ * frame k's value v in [0, 1], divided by its exposure relative to the
+ * reference, estimates the irradiance in the reference's units; the
+ * estimates are averaged per channel with the hat weight min(v, 1 - v)
+ * (0 for black and saturated samples), and each non-reference frame's
+ * weight is multiplied by max(SSIM_k, 0) against the reference, the
+ * deghosting weight of the fusion (Sec. 2.5). Where every weight is 0 the
+ * reference's own value is kept.
+ * ------------------------------------------------------------------------- */
+double lo_hat_weight(double v) {
+  const double a = v < 1.0 - v ? v : 1.0 - v;
+  return a > 0.0 ? a : 0.0;
+}
+
+int lo_irradiance(int n, int ch, int w, int h, const double* const* imgs,
+                  const double* const* yeqs, const double* exposures, int ref_index,
+                  const lo_params* p, double* out) {
+  if (n < 1 || ref_index < 0 || ref_index >= n) return -1;
+  for (int k = 0; k < n; ++k)
+    if (!(exposures[k] > 0.0)) return -1;
+  const size_t np = (size_t)w * h;
+  double** ssim = (double**)calloc((size_t)n, sizeof(double*));
+  for (int k = 0; k < n; ++k)
+    if (k != ref_index) {
+      ssim[k] = (double*)malloc(sizeof(double) * np);
+      lo_ssim(yeqs[ref_index], yeqs[k], w, h, p, ssim[k]);
+    }
+  for (int c = 0; c < ch; ++c)
+    for (size_t i = 0; i < np; ++i) {
+      double sw = 0.0, se = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double v = imgs[k][c * np + i];
+        double wk = lo_hat_weight(v);
+        if (k != ref_index) wk *= ssim[k][i] > 0.0 ? ssim[k][i] : 0.0;
+        const double t = exposures[k] / exposures[ref_index];
+        sw += wk;
+        se += wk * (v / t);
+      }
+      out[c * np + i] = sw > 0.0 ? se / sw : imgs[ref_index][c * np + i];
+    }
+  for (int k = 0; k < n; ++k) free(ssim[k]);
+  free(ssim);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
  * One registration (Sec. 2.2 - 2.4): equalise both frames, build the
  * pyramids, then from the coarsest level down: corners on the reference,
  * warp the source level by H^{l+1}, SSD search (radius 10 on coarse levels,

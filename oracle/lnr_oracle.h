@@ -141,6 +141,12 @@ int  lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t*
 /* deghosted merge (Sec. 2.5) of n frames; imgs/yeqs as produced above */
 int  lo_merge(int n, int ch, int w, int h, const double* const* imgs,
               const double* const* yeqs, int ref_index, const lo_params* p, double* out);
+/* HDR irradiance map of the registered frames (the paper's comparison output,
+ * Sec. 3.1; formula: reading, see lnr_oracle.c); exposures[k] > 0 */
+double lo_hat_weight(double v);
+int  lo_irradiance(int n, int ch, int w, int h, const double* const* imgs,
+                   const double* const* yeqs, const double* exposures, int ref_index,
+                   const lo_params* p, double* out);
 
 /* ---- learned displacement proposal (proposal_oracle.c; an extension, not
  * part of the paper: it narrows the search of Sec. 2.2) ---------------------- */

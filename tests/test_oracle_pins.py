@@ -793,3 +793,57 @@ def test_register_planted_homography_quality():
             e = _ap(Hp1, r["corner_x"][t] + r["dx"][t], r["corner_y"][t] + r["dy"][t])
             ok.append(np.hypot(g[0] - e[0], g[1] - e[1]) < 1.5)
     assert np.mean(ok) > 0.7
+
+
+# ---------------------------------------------------------------- irradiance map
+# The irradiance map's formula is a reading (the paper merges the warped frames
+# into an irradiance map in its Sec. 3.1 comparison without stating how); these
+# pins fix it by what a linear stack and the deghosting weight must give.
+
+def test_hat_weight_closed_form():
+    for v, want in [(0.0, 0.0), (0.25, 0.25), (0.5, 0.5), (0.75, 0.25), (1.0, 0.0),
+                    (-0.2, 0.0), (1.3, 0.0)]:
+        assert oracle.hat_weight(v) == want, v
+
+
+def _irr_scene(seed, h=40, w=56):
+    rng = np.random.default_rng(seed)
+    E = rng.uniform(0.02, 0.4, (3, h, w))          # irradiance, reference units
+    yeq = rng.uniform(0.0, 1.0, (h, w))             # textured guide
+    return E, yeq
+
+
+def test_irradiance_recovers_linear_stack():
+    # absolute exposures 2 and 4: the source is twice as bright; dividing each
+    # value by its exposure relative to the reference recovers E exactly
+    E, yeq = _irr_scene(1)
+    imgs = [E * 1.0, E * 2.0]
+    got = oracle.irradiance(imgs, [yeq, yeq], [2.0, 4.0], 0)
+    assert np.abs(got - E).max() < 1e-12
+    # the reference need not be frame 0: a brighter reference is divided too
+    got2 = oracle.irradiance([E * 2.0, E * 1.0], [yeq, yeq], [4.0, 2.0], 1)
+    assert np.abs(got2 - E).max() < 1e-12
+
+
+def test_irradiance_drops_saturated_and_ghost_samples():
+    E, yeq = _irr_scene(2)
+    ref = E.copy()
+    src = np.minimum(E * 4.0, 1.0)
+    src[:, :10, :] = 1.0                            # saturated band
+    # a saturated source sample has weight 0: the reference's own value stays
+    got = oracle.irradiance([ref, src], [yeq, yeq], [1.0, 4.0], 0)
+    assert np.allclose(got[:, :10, :], ref[:, :10, :], rtol=1e-14, atol=0)
+    # a ghost (source luma anti-correlated with the reference: SSIM < 0) has
+    # weight 0 everywhere, whatever its values
+    ghost = np.clip(E * 4.0 + 0.1, 0, 0.9)
+    got_g = oracle.irradiance([ref, ghost], [yeq, 1.0 - yeq], [1.0, 4.0], 0)
+    s = oracle.ssim(yeq, 1.0 - yeq)
+    assert (s < 0).all()
+    assert np.allclose(got_g, ref, rtol=1e-14, atol=0)
+
+
+def test_irradiance_all_saturated_keeps_reference():
+    _, yeq = _irr_scene(3, 8, 8)
+    one = np.ones((3, 8, 8))
+    got = oracle.irradiance([one, one], [yeq, yeq], [1.0, 2.0], 0)
+    assert np.array_equal(got, one)
