@@ -316,6 +316,35 @@ def main():
         # all five levels' searches; the level-0 share dominates
         result["search_level0"]["ms_all_levels"] = round(per_step["k_search"][1], 4)
 
+    # the irradiance map of the registered pair (the alternative output to
+    # the fusion): SSIM of the warped frame plus one pass over both frames
+    irr = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
+    lnr.register_pair(ctx, ref, src, p, out=reg)
+    for _ in range(args.warmup):
+        lnr.merge_irradiance(ctx, [ref, src], 0, [reg], p, out=irr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lnr.merge_irradiance(ctx, [ref, src], 0, [reg], p, out=irr)
+    torch.cuda.synchronize()
+    ms_irr = (time.perf_counter() - t0) / args.steps * 1e3
+    ctx.trace(True)
+    for _ in range(args.steps):
+        lnr.merge_irradiance(ctx, [ref, src], 0, [reg], p, out=irr)
+    torch.cuda.synchronize()
+    tri = {kernel_key(k)[0]: (c / args.steps, ms / args.steps) for k, (c, ms) in
+           ctx.trace_read().items()}
+    ctx.trace(False)
+    irr_entry = {"ms": round(ms_irr, 4), "mpix_s": round(mpix / (ms_irr / 1e3), 2),
+                 "kernels_ms": {k: round(v[1], 4) for k, v in tri.items()}}
+    if "k_irradiance" in tri:
+        # two frames of three float planes and one SSIM map in, three planes out
+        b_irr = W * H * (2 * 3 * 4 + 4 + 3 * 4)
+        gbs = b_irr / (tri["k_irradiance"][1] / tri["k_irradiance"][0] / 1e3) / 1e9
+        irr_entry["k_irradiance"] = {"algo_bytes": b_irr, "gbs": round(gbs, 1),
+                                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    result["irradiance_map"] = irr_entry
+
     if not args.no_cpu_baseline:
         import oracle
         op = oracle.params(radius0=st.meta["radius0"])

@@ -166,6 +166,17 @@ lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
 lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t ref_index,
                      const lnr_registration* regs, const lnr_params* p, float* out,
                      void* stream);
+/* HDR irradiance map of the registered frames, the paper's alternative output
+ * in its quality comparison (Sec. 3.1), in place of the fusion: per channel
+ * the average of value / (exposure / reference exposure) weighted by
+ * min(v, 1 - v) (0 at black and saturation), non-reference weights times
+ * max(SSIM, 0) against the reference as in Sec. 2.5; the reference's value
+ * where every weight is 0. Arguments as lnr_merge; out [ch][H][W] fp32 in
+ * the reference's units (1 = the reference's white). Every exposure must be
+ * positive and finite (LNR_E_ARG). */
+lnr_status lnr_merge_irradiance(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
+                                int32_t ref_index, const lnr_registration* regs,
+                                const lnr_params* p, float* out, void* stream);
 
 /* ---- stage entry points: one stage on caller-given inputs (used to check
  * each kernel on exactly the inputs the oracle sees). -------------------- */
@@ -208,6 +219,12 @@ lnr_status lnr_stage_backward_warp(lnr_ctx* ctx, const lnr_frame* src, const uin
 lnr_status lnr_stage_merge(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32_t h,
                            const float* const* imgs, const float* const* yeqs,
                            int32_t ref_index, const lnr_params* p, float* out, void* stream);
+/* The irradiance map of lnr_merge_irradiance from n float images and luma
+ * maps as lnr_stage_merge takes them; exposures: n positive values (host). */
+lnr_status lnr_stage_irradiance(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32_t h,
+                                const float* const* imgs, const float* const* yeqs,
+                                const float* exposures, int32_t ref_index, const lnr_params* p,
+                                float* out, void* stream);
 
 /* ---- batches: several pairs of any sizes in one call (streams, graphs,
  * autotuning; no new method). -------------------------------------------- */

@@ -108,6 +108,8 @@ def lib():
                                          C.POINTER(_Registration), C.POINTER(i32), vp]
         L.lnr_merge.argtypes = [vp, C.POINTER(_Frame), i32, i32, C.POINTER(_Registration),
                                 C.POINTER(Params), vp, vp]
+        L.lnr_merge_irradiance.argtypes = [vp, C.POINTER(_Frame), i32, i32, C.POINTER(_Registration),
+                                C.POINTER(Params), vp, vp]
         L.lnr_stage_equalize.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
         L.lnr_stage_warp_q8.argtypes = [vp, vp, i32, i32, vp, vp, vp]
         L.lnr_stage_search.argtypes = [vp, vp, vp, i32, i32, i32, C.POINTER(Params), vp, vp, vp,
@@ -119,6 +121,8 @@ def lib():
         L.lnr_stage_backward_warp.argtypes = [vp, C.POINTER(_Frame), vp, vp, vp, vp, vp, vp]
         L.lnr_stage_merge.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, C.POINTER(Params),
                                       vp, vp]
+        L.lnr_stage_irradiance.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, i32,
+                                           C.POINTER(Params), vp, vp]
         L.lnr_stage_search_window.argtypes = [vp, vp, vp, i32, i32, i32, vp, C.POINTER(Params),
                                               vp, vp, vp, vp, vp]
         L.lnr_proposal_set.argtypes = [vp, vp, vp]
@@ -140,7 +144,8 @@ def lib():
                      "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
                      "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow",
-                     "lnr_autotune_search", "lnr_proposal_save", "lnr_proposal_load"):
+                     "lnr_autotune_search", "lnr_proposal_save", "lnr_proposal_load",
+                     "lnr_merge_irradiance", "lnr_stage_irradiance"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -154,7 +159,8 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_stage_search_window", "lnr_proposal_set", "lnr_proposal_get",
             "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
             "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search",
-            "lnr_proposal_save", "lnr_proposal_load")
+            "lnr_proposal_save", "lnr_proposal_load", "lnr_merge_irradiance",
+            "lnr_stage_irradiance")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -349,6 +355,23 @@ def merge(ctx: Context, frames, ref_index: int, regs, params: Params | None = No
     return out
 
 
+def merge_irradiance(ctx: Context, frames, ref_index: int, regs, params: Params | None = None,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """HDR irradiance map of the registered frames (reference units); see
+    lnr_merge_irradiance."""
+    p = params or Params()
+    n = len(frames)
+    f0 = frames[ref_index]
+    ch = 1 if f0.fmt == LNR_Y8 else 3
+    out = out if out is not None else torch.empty(ch, f0.height, f0.width, dtype=torch.float32,
+                                                  device=f0.y.device)
+    FA = (_Frame * n)(*[f._c() for f in frames])
+    RA = (_Registration * max(n - 1, 1))(*[r._c() for r in regs])
+    ctx.check(lib().lnr_merge_irradiance(ctx._h, FA, n, ref_index, RA, C.byref(p), _ptr(out),
+                                         _stream()))
+    return out
+
+
 # ----------------------------------------------------------------- stage entry points
 
 def stage_equalize(ctx, img: torch.Tensor):
@@ -430,6 +453,19 @@ def stage_merge(ctx, imgs, yeqs, ref_index, params=None):
     YA = (C.c_void_p * n)(*[y.data_ptr() for y in yeqs])
     ctx.check(lib().lnr_stage_merge(ctx._h, n, ch, w, h, IA, YA, ref_index, C.byref(p),
                                     _ptr(out), _stream()))
+    return out
+
+
+def stage_irradiance(ctx, imgs, yeqs, exposures, ref_index, params=None):
+    p = params or Params()
+    n = len(imgs)
+    ch, h, w = imgs[0].shape
+    out = torch.empty(ch, h, w, dtype=torch.float32, device=imgs[0].device)
+    IA = (C.c_void_p * n)(*[i.data_ptr() for i in imgs])
+    YA = (C.c_void_p * n)(*[y.data_ptr() for y in yeqs])
+    EA = (C.c_float * n)(*[float(e) for e in exposures])
+    ctx.check(lib().lnr_stage_irradiance(ctx._h, n, ch, w, h, IA, YA, EA, ref_index, C.byref(p),
+                                         _ptr(out), _stream()))
     return out
 
 

@@ -267,6 +267,53 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
   }
 }
 
+// Irradiance map of the registered frames, one pixel per thread and every
+// channel: each frame's value over its relative exposure, averaged with the
+// hat weight min(v, 1 - v) (0 at black and saturation), non-reference
+// frames' weights times max(SSIM, 0); the reference's value where every
+// weight is 0.
+struct IrrPtrs {
+  const float* img[16];
+  const float* ssim[16];
+  float rel[16];  // exposure relative to the reference
+};
+
+__device__ inline float hat_weight(float v) {
+  const float a = v < 1.f - v ? v : 1.f - v;
+  return a > 0.f ? a : 0.f;
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(256) void k_irradiance(IrrPtrs f, int n, int ch, int ref,
+                                                    long long npix, float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npix) return;
+  float s[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) {
+    s[k] = 1.f;
+    if (k < n && k != ref) {
+      const float q = f.ssim[k][i];
+      s[k] = q > 0.f ? q : 0.f;
+    }
+  }
+  for (int c = 0; c < ch; ++c) {
+    const long long o = (long long)c * npix + i;
+    float v[NMAX];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) v[k] = k < n ? f.img[k][o] : 0.f;  // all loads in flight
+    float sw = 0.f, se = 0.f;
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+      if (k >= n) continue;
+      const float wk = hat_weight(v[k]) * s[k];
+      sw += wk;
+      se += wk * (v[k] / f.rel[k]);
+    }
+    out[o] = sw > 0.f ? se / sw : f.img[ref][o];
+  }
+}
+
 struct MapPtrs {
   const float* in[kMaxMaps];
   float* out[kMaxMaps];
@@ -533,6 +580,42 @@ size_t merge_pyr_elems(int W, int H, int levels) {
   return tot;
 }
 
+// SSIM of every frame but the reference against the reference, into
+// ssim + k * W * H
+hipError_t launch_ssim_maps(int n, int W, int H, const float* const* yeqs, int ref_index,
+                            const lnr_params& p, float* ssim, hipStream_t st) {
+  const size_t N = (size_t)W * H;
+  hipError_t e;
+  for (int k = 0; k < n; ++k) {
+    if (k == ref_index) continue;
+    const int r = p.ssim_radius;
+    SsimWin win;
+    double gs = 0.0;
+    for (int j = -r; j <= r; ++j) {
+      win.g[j + r] = exp(-(double)(j * j) / (2.0 * p.ssim_sigma * p.ssim_sigma));
+      gs += win.g[j + r];
+    }
+    for (int j = 0; j <= 2 * r; ++j) win.g[j] /= gs;
+    const int tw = 256 - 2 * r;
+    dim3 g((W + tw - 1) / tw, (H + kSsimTH - 1) / kSsimTH);
+    const float* ya = yeqs[ref_index];
+    const float* yb = yeqs[k];
+    float* so = ssim + (size_t)k * N;
+    switch (r) {
+#define SSIM_CASE(R_)                                                                          \
+  case R_:                                                                                     \
+    LNR_LAUNCH(k_ssim<R_>, g, dim3(256), 0, st, ya, yb, W, H, win, p.ssim_c1, p.ssim_c2, so); \
+    break;
+      SSIM_CASE(1) SSIM_CASE(2) SSIM_CASE(3) SSIM_CASE(4)
+      SSIM_CASE(5) SSIM_CASE(6) SSIM_CASE(7) SSIM_CASE(8)
+#undef SSIM_CASE
+      default: return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
                         const float* const* yeqs, int ref_index, const lnr_params& p,
                         const MergeBufs& bufs, float* out, hipStream_t st) {
@@ -548,38 +631,13 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     loff[l + 1] = loff[l] + (size_t)lw[l] * lh[l];
   }
   hipError_t e;
-  // SSIM of every warped frame against the reference
   FramePtrs fp;
   for (int k = 0; k < n; ++k) {
     fp.img[k] = imgs[k];
     fp.ssim[k] = bufs.ssim + (size_t)k * N;
     fp.wout[k] = bufs.w0 + (size_t)k * N;
-    if (k == ref_index) continue;
-    const int r = p.ssim_radius;
-    SsimWin win;
-    double gs = 0.0;
-    for (int j = -r; j <= r; ++j) {
-      win.g[j + r] = exp(-(double)(j * j) / (2.0 * p.ssim_sigma * p.ssim_sigma));
-      gs += win.g[j + r];
-    }
-    for (int j = 0; j <= 2 * r; ++j) win.g[j] /= gs;
-    const int tw = 256 - 2 * r;
-    dim3 g((W + tw - 1) / tw, (H + kSsimTH - 1) / kSsimTH);
-    const float* ya = yeqs[ref_index];
-    const float* yb = yeqs[k];
-    float* so = bufs.ssim + (size_t)k * N;
-    switch (r) {
-#define SSIM_CASE(R_)                                                                          \
-  case R_:                                                                                     \
-    LNR_LAUNCH(k_ssim<R_>, g, dim3(256), 0, st, ya, yb, W, H, win, p.ssim_c1, p.ssim_c2, so); \
-    break;
-      SSIM_CASE(1) SSIM_CASE(2) SSIM_CASE(3) SSIM_CASE(4)
-      SSIM_CASE(5) SSIM_CASE(6) SSIM_CASE(7) SSIM_CASE(8)
-#undef SSIM_CASE
-      default: return hipErrorInvalidValue;
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  if ((e = launch_ssim_maps(n, W, H, yeqs, ref_index, p, bufs.ssim, st)) != hipSuccess) return e;
   {
     const dim3 g((W + 255) / 256, (H + kWeightRows - 1) / kWeightRows);
     const float two_se2 = (float)(2.0 * p.sigma_e * p.sigma_e);
@@ -659,6 +717,30 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     }
   }
   return hipSuccess;
+}
+
+hipError_t launch_irradiance(int n, int ch, int W, int H, const float* const* imgs,
+                             const float* const* yeqs, const float* rel, int ref_index,
+                             const lnr_params& p, float* ssim, float* out, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_ssim_maps(n, W, H, yeqs, ref_index, p, ssim, st)) != hipSuccess) return e;
+  const long long N = (long long)W * H;
+  IrrPtrs f;
+  for (int k = 0; k < 16; ++k) {
+    f.img[k] = k < n ? imgs[k] : nullptr;
+    f.ssim[k] = k < n && k != ref_index ? ssim + (size_t)k * N : nullptr;
+    f.rel[k] = k < n ? rel[k] : 1.f;
+  }
+  const dim3 g((unsigned)((N + 255) / 256));
+  if (n <= 2)
+    LNR_LAUNCH(k_irradiance<2>, g, dim3(256), 0, st, f, n, ch, ref_index, N, out);
+  else if (n <= 4)
+    LNR_LAUNCH(k_irradiance<4>, g, dim3(256), 0, st, f, n, ch, ref_index, N, out);
+  else if (n <= 8)
+    LNR_LAUNCH(k_irradiance<8>, g, dim3(256), 0, st, f, n, ch, ref_index, N, out);
+  else
+    LNR_LAUNCH(k_irradiance<16>, g, dim3(256), 0, st, f, n, ch, ref_index, N, out);
+  return hipGetLastError();
 }
 
 }  // namespace lnr

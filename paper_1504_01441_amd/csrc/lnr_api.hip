@@ -434,9 +434,12 @@ lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
   return enqueue_pair(ctx, ref, src, p, out, q, static_cast<char*>(ctx->ws), st);
 }
 
+// rel (host, n values): exposures relative to the reference for the
+// irradiance map; null for the exposure fusion
 lnr_status merge_impl(lnr_ctx* ctx, int n, int ch, int W, int H, const float* const* imgs,
                       const float* const* yeqs, int ref_index, const lnr_params* p, float* out,
-                      hipStream_t st, size_t extra_bytes, size_t* extra_off) {
+                      hipStream_t st, size_t extra_bytes, size_t* extra_off,
+                      const float* rel = nullptr) {
   const int L = merge_levels(W, H);
   const size_t N = (size_t)W * H, tot = merge_pyr_elems(W, H, L);
   Plan pl;
@@ -454,7 +457,10 @@ lnr_status merge_impl(lnr_ctx* ctx, int n, int ch, int W, int H, const float* co
   b.pyr = reinterpret_cast<float*>(base + o_pyr);
   b.acc = reinterpret_cast<float*>(base + o_acc);
   (void)extra_off;
-  LNR_HIP(launch_merge(n, ch, W, H, imgs, yeqs, ref_index, *p, b, out, st));
+  if (rel)
+    LNR_HIP(launch_irradiance(n, ch, W, H, imgs, yeqs, rel, ref_index, *p, b.ssim, out, st));
+  else
+    LNR_HIP(launch_merge(n, ch, W, H, imgs, yeqs, ref_index, *p, b, out, st));
   return LNR_OK;
 }
 
@@ -579,9 +585,15 @@ lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
   return LNR_OK;
 }
 
-lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t ref_index,
-                     const lnr_registration* regs, const lnr_params* p, float* out,
-                     void* stream) {
+}  // extern "C"
+
+namespace {
+// The registered frames' images (the reference converted here, the others
+// the registrations' warped images) merged by the fusion, or into the
+// irradiance map when `irradiance`.
+lnr_status merge_frames(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t ref_index,
+                        const lnr_registration* regs, const lnr_params* p, float* out,
+                        void* stream, bool irradiance) {
   if (!ctx) return LNR_E_ARG;
   TraceGuard tg(ctx);
   lnr_status s;
@@ -643,7 +655,31 @@ lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t r
     }
   }
   size_t extra_off = 0;
-  return merge_impl(ctx, n, ch, W, H, imgs, yeqs, ref_index, p, out, st, ref_bytes, &extra_off);
+  if (!irradiance)
+    return merge_impl(ctx, n, ch, W, H, imgs, yeqs, ref_index, p, out, st, ref_bytes, &extra_off);
+  float rel[16];
+  for (int k = 0; k < n; ++k) rel[k] = (float)((double)frames[k].exposure / (double)rf.exposure);
+  return merge_impl(ctx, n, ch, W, H, imgs, yeqs, ref_index, p, out, st, ref_bytes, &extra_off,
+                    rel);
+}
+}  // namespace
+
+extern "C" {
+
+lnr_status lnr_merge(lnr_ctx* ctx, const lnr_frame* frames, int32_t n, int32_t ref_index,
+                     const lnr_registration* regs, const lnr_params* p, float* out,
+                     void* stream) {
+  return merge_frames(ctx, frames, n, ref_index, regs, p, out, stream, false);
+}
+
+lnr_status lnr_merge_irradiance(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
+                                int32_t ref_index, const lnr_registration* regs,
+                                const lnr_params* p, float* out, void* stream) {
+  if (ctx && frames && n >= 1 && n <= 16)
+    for (int k = 0; k < n; ++k)
+      if (!(frames[k].exposure > 0.f) || !std::isfinite(frames[k].exposure))
+        return fail(ctx, LNR_E_ARG, "the irradiance map needs positive exposures");
+  return merge_frames(ctx, frames, n, ref_index, regs, p, out, stream, true);
 }
 
 lnr_status lnr_stage_equalize(lnr_ctx* ctx, const uint8_t* img, int32_t w, int32_t h,
@@ -772,6 +808,29 @@ lnr_status lnr_stage_merge(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   return merge_impl(ctx, n, ch, w, h, imgs, yeqs, ref_index, p, out, (hipStream_t)stream, 0,
                     nullptr);
+}
+
+lnr_status lnr_stage_irradiance(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32_t h,
+                                const float* const* imgs, const float* const* yeqs,
+                                const float* exposures, int32_t ref_index, const lnr_params* p,
+                                float* out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_params(ctx, p)) != LNR_OK) return s;
+  if (n < 1 || n > 16 || (ch != 1 && ch != 3) || w < 1 || h < 1 || w > kMaxSide ||
+      h > kMaxSide || !imgs || !yeqs || !exposures || !out || ref_index < 0 || ref_index >= n)
+    return fail(ctx, LNR_E_ARG, "bad irradiance arguments");
+  for (int k = 0; k < n; ++k) {
+    if (!imgs[k] || !yeqs[k]) return fail(ctx, LNR_E_ARG, "null image or luma pointer");
+    if (!(exposures[k] > 0.f) || !std::isfinite(exposures[k]))
+      return fail(ctx, LNR_E_ARG, "the irradiance map needs positive exposures");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  float rel[16];
+  for (int k = 0; k < n; ++k) rel[k] = (float)((double)exposures[k] / (double)exposures[ref_index]);
+  return merge_impl(ctx, n, ch, w, h, imgs, yeqs, ref_index, p, out, (hipStream_t)stream, 0,
+                    nullptr, rel);
 }
 
 // ---------------------------------------------------------------- batches

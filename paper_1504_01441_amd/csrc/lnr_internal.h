@@ -180,6 +180,11 @@ int merge_levels(int W, int H);
 hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
                         const float* const* yeqs, int ref_index, const lnr_params& p,
                         const MergeBufs& b, float* out, hipStream_t st);
+// HDR irradiance map (reference units) of n frames with exposures rel[k]
+// relative to the reference; ssim: n * W * H floats of scratch
+hipError_t launch_irradiance(int n, int ch, int W, int H, const float* const* imgs,
+                             const float* const* yeqs, const float* rel, int ref_index,
+                             const lnr_params& p, float* ssim, float* out, hipStream_t st);
 
 // ---- learned displacement proposal (k_cnn.hip)
 int cnn_param_count();

@@ -363,6 +363,55 @@ def test_sweep_sizes_match_oracle(ctx, size):
     registration_parity(reg, oracle.register_pair(st.frames[0], st.frames[1], op))
 
 
+@pytest.mark.parametrize("n,ch,shape,ref", [(2, 3, (37, 53), 0), (3, 3, (120, 203), 1),
+                                             (5, 1, (64, 257), 2), (16, 3, (33, 70), 7)])
+def test_irradiance_vs_oracle(ctx, n, ch, shape, ref):
+    """Irradiance map of synthetic linear stacks (saturated and black samples,
+    a ghost frame with anti-correlated luma), same float32 planes on both
+    sides, on ragged sizes."""
+    rng = np.random.default_rng(900 + n * 10 + ch)
+    h, w = shape
+    import scipy.ndimage as ndi
+    E = ndi.gaussian_filter(rng.uniform(0, 1, (ch, h, w)), (0, 1.5, 1.5)) * 0.5 + 0.01
+    rel = [2.0 ** (k - ref) for k in range(n)]
+    expo = [0.5 * r for r in rel]                   # absolute; only ratios matter
+    imgs = [np.clip(E * r + rng.normal(0, 0.003, E.shape), 0, 1).astype(np.float32)
+            for r in rel]
+    base = ndi.gaussian_filter(rng.uniform(0, 1, (h, w)), 1.0)
+    yeqs = [np.clip(base + rng.normal(0, 0.02, (h, w)), 0, 1).astype(np.float32)
+            for _ in range(n)]
+    if n > 2:
+        yeqs[0 if ref else 1] = (1.0 - yeqs[ref]).astype(np.float32)   # a ghost
+    p, op = params_pair()
+    got = lnr().stage_irradiance(ctx, [_t(i) for i in imgs], [_t(y) for y in yeqs], expo, ref, p)
+    _sync()
+    want = oracle.irradiance([i.astype(np.float64) for i in imgs],
+                             [y.astype(np.float64) for y in yeqs], expo, ref, op)
+    assert_close(got.cpu().numpy(), want, 1.0, what="irradiance")
+
+
+def test_merge_irradiance_full_path(ctx):
+    """A registered pair's irradiance map against the oracle's map of the
+    oracle's own registration."""
+    st = synth.make_config_pair("c2", 3, scale=0.25)
+    p, op = params_pair(radius0=16)
+    g = [to_gpu_frame(f) for f in st.frames]
+    reg = lnr().register_pair(ctx, g[0], g[1], p)
+    got = lnr().merge_irradiance(ctx, g, 0, [reg], p)
+    _sync()
+    o = oracle.register_pair(st.frames[0], st.frames[1], op)
+    registration_parity(reg, o)
+    f0 = st.frames[0]
+    ref_rgb = oracle.frame_to_rgb(f0.y, f0.u, f0.v)
+    want = oracle.irradiance([ref_rgb, o["rgb"]],
+                             [o["yeq_ref"].astype(np.float64) / 255.0, o["yeq_warped"]],
+                             [f.exposure for f in st.frames], 0, op)
+    assert_close(got.cpu().numpy(), want, 1.0, what="irradiance map")
+    # the map is in the reference's units: where the reference is neither black
+    # nor saturated and no ghost, it is close to the reference's own values
+    assert np.isfinite(got.cpu().numpy()).all()
+
+
 def test_register_deterministic(ctx):
     st = synth.make_config_pair("c1", 15)
     p = lnr().Params(radius0=8)
