@@ -84,6 +84,9 @@ def lib():
         _lib.lo_register_pair.restype = C.c_int
         _lib.lo_merge.restype = C.c_int
         _lib.lo_irradiance.restype = C.c_int
+        _lib.lo_meter.restype = C.c_int
+        _lib.lo_meter.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float,
+                                  C.c_float, C.c_void_p]
         _lib.lo_hat_weight.restype = C.c_double
         _lib.lo_hat_weight.argtypes = [C.c_double]
         _lib.lo_num_blend_levels.restype = C.c_int
@@ -350,6 +353,15 @@ def irradiance(imgs, yeqs, exposures, ref_index, p=None):
     if rc:
         raise ValueError("lo_irradiance failed")
     return out
+
+
+def meter(y, dark=16, frac3=0.05, frac4=0.20):
+    """(stops, under-exposed count) for the ETTR first frame's 8-bit luma y."""
+    y = _c(y, np.uint8)
+    h, w = y.shape
+    n = C.c_longlong(0)
+    stops = lib().lo_meter(_p(y), w, h, w, int(dark), float(frac3), float(frac4), C.byref(n))
+    return stops, n.value
 
 
 def hat_weight(v):

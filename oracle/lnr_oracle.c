@@ -879,6 +879,27 @@ int lo_merge(int n, int ch, int w, int h, const double* const* imgs,
 }
 
 /* ---------------------------------------------------------------------------
+ * Metering (Sec. 2.1): the first frame is exposed to the right, and the
+ * second is made 2, 3 or 4 stops brighter the more under-exposed pixels the
+ * first has. The paper does not say where the steps fall. Reading: a pixel
+ * is under-exposed when its 8-bit luma is below `dark`; with n_dark of the
+ * w h pixels under-exposed, the choice is 2 stops when n_dark <= frac3 w h,
+ * 3 when n_dark <= frac4 w h, else 4 (the products in double precision).
+ * ------------------------------------------------------------------------- */
+int lo_meter(const uint8_t* y, int w, int h, int stride, int dark, float frac3, float frac4,
+             long long* n_dark) {
+  long long n = 0;
+  for (int r = 0; r < h; ++r)
+    for (int c = 0; c < w; ++c)
+      if ((int)y[(size_t)r * stride + c] < dark) ++n;
+  if (n_dark) *n_dark = n;
+  const double npix = (double)w * (double)h;
+  if ((double)n <= (double)frac3 * npix) return 2;
+  if ((double)n <= (double)frac4 * npix) return 3;
+  return 4;
+}
+
+/* ---------------------------------------------------------------------------
  * HDR irradiance map of the registered stack. In its quality comparison
  * (Sec. 3.1) the paper merges the warped frames into an irradiance map
  * (then tonemaps it) instead of running its error-tolerant fusion, without

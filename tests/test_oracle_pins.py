@@ -847,3 +847,32 @@ def test_irradiance_all_saturated_keeps_reference():
     one = np.ones((3, 8, 8))
     got = oracle.irradiance([one, one], [yeq, yeq], [1.0, 2.0], 0)
     assert np.array_equal(got, one)
+
+
+# --------------------------------------------------------------------- metering
+# Sec. 2.1: 2, 3 or 4 stops by the under-exposed count (thresholds: readings).
+
+def _with_dark(n_dark, h=40, w=50, seed=0):
+    rng = np.random.default_rng(seed)
+    y = rng.integers(16, 256, (h, w)).astype(np.uint8)
+    idx = rng.permutation(h * w)[:n_dark]
+    y.reshape(-1)[idx] = rng.integers(0, 16, n_dark)
+    return y
+
+
+def test_meter_steps_at_the_thresholds():
+    N = 40 * 50                                       # 5 % = 100, 20 % = 400 pixels
+    for n_dark, want in [(0, 2), (100, 2), (101, 3), (400, 3), (401, 4), (N, 4)]:
+        y = _with_dark(n_dark)
+        stops, n = oracle.meter(y)
+        assert n == n_dark == int((y < 16).sum())
+        assert stops == want, (n_dark, stops)
+
+
+def test_meter_is_monotone_in_the_dark_count():
+    last = 2
+    for n_dark in range(0, 2001, 50):
+        stops, _ = oracle.meter(_with_dark(n_dark, seed=n_dark))
+        assert stops >= last
+        last = stops
+    assert last == 4
