@@ -345,6 +345,16 @@ def main():
                                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
     result["irradiance_map"] = irr_entry
 
+    # metering of the second exposure from the first (reference) frame's luma
+    for _ in range(args.warmup):
+        stops = lnr.meter(ctx, ref.y)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stops = lnr.meter(ctx, ref.y)
+    ms_meter = (time.perf_counter() - t0) / args.steps * 1e3
+    result["metering"] = {"ms_with_readback": round(ms_meter, 4), "stops": stops[0],
+                          "under_exposed": stops[1]}
+
     if not args.no_cpu_baseline:
         import oracle
         op = oracle.params(radius0=st.meta["radius0"])

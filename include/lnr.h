@@ -185,6 +185,15 @@ lnr_status lnr_merge_irradiance(lnr_ctx* ctx, const lnr_frame* frames, int32_t n
  * out[h][w] (dense). */
 lnr_status lnr_stage_equalize(lnr_ctx* ctx, const uint8_t* img, int32_t w, int32_t h,
                               int32_t stride, uint8_t* lut, uint8_t* out, void* stream);
+/* Metering of the second exposure (Sec. 2.1): the first frame is exposed to
+ * the right; the second is 2, 3 or 4 stops brighter the more under-exposed
+ * pixels the first has. y: the first frame's 8-bit luma (device, w x h,
+ * row stride). A pixel is under-exposed below `dark`; with n of the w h
+ * pixels under-exposed the choice is 2 stops when n <= frac3 w h, 3 when
+ * n <= frac4 w h, else 4 (the thresholds are readings; defaults 16, 0.05,
+ * 0.20). Writes out[0] = stops and out[1] = n (device int32[2]). */
+lnr_status lnr_meter(lnr_ctx* ctx, const uint8_t* y, int32_t w, int32_t h, int32_t stride,
+                     int32_t dark, float frac3, float frac4, int32_t* out, void* stream);
 /* Q8 bilinear warp of a level image through the normalised homography
  * H[9] (device, double), Eq. 3 frame (Sec. 2.2). */
 lnr_status lnr_stage_warp_q8(lnr_ctx* ctx, const uint8_t* src, int32_t w, int32_t h,

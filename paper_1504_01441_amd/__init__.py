@@ -121,6 +121,7 @@ def lib():
         L.lnr_stage_backward_warp.argtypes = [vp, C.POINTER(_Frame), vp, vp, vp, vp, vp, vp]
         L.lnr_stage_merge.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, C.POINTER(Params),
                                       vp, vp]
+        L.lnr_meter.argtypes = [vp, vp, i32, i32, i32, i32, C.c_float, C.c_float, vp, vp]
         L.lnr_stage_irradiance.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, i32,
                                            C.POINTER(Params), vp, vp]
         L.lnr_stage_search_window.argtypes = [vp, vp, vp, i32, i32, i32, vp, C.POINTER(Params),
@@ -145,7 +146,7 @@ def lib():
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
                      "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow",
                      "lnr_autotune_search", "lnr_proposal_save", "lnr_proposal_load",
-                     "lnr_merge_irradiance", "lnr_stage_irradiance"):
+                     "lnr_merge_irradiance", "lnr_stage_irradiance", "lnr_meter"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -160,7 +161,7 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
             "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search",
             "lnr_proposal_save", "lnr_proposal_load", "lnr_merge_irradiance",
-            "lnr_stage_irradiance")
+            "lnr_stage_irradiance", "lnr_meter")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -381,6 +382,17 @@ def stage_equalize(ctx, img: torch.Tensor):
     ctx.check(lib().lnr_stage_equalize(ctx._h, _ptr(img), w, h, img.stride(0), _ptr(lut),
                                        _ptr(out), _stream()))
     return lut, out
+
+
+def meter(ctx, y: torch.Tensor, dark=16, frac3=0.05, frac4=0.20):
+    """(stops, under-exposed count) for the ETTR first frame's luma y
+    (uint8 [h, w] on the GPU, unit column stride); see lnr_meter."""
+    h, w = y.shape
+    out = torch.zeros(2, dtype=torch.int32, device=y.device)
+    ctx.check(lib().lnr_meter(ctx._h, _ptr(y), w, h, y.stride(0), int(dark), float(frac3),
+                              float(frac4), _ptr(out), _stream()))
+    o = out.cpu()
+    return int(o[0]), int(o[1])
 
 
 def stage_warp_q8(ctx, src: torch.Tensor, H: torch.Tensor):

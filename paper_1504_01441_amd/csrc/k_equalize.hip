@@ -195,7 +195,32 @@ __global__ __launch_bounds__(256) void k_lut_pyr(const uint8_t* __restrict__ y0,
   }
 }
 
+// Metering decision (Sec. 2.1) from a 256-bin luma histogram: the pixels
+// below `dark`, and 2, 3 or 4 stops by their share of npix (compared in
+// double precision). One wave.
+__global__ __launch_bounds__(64) void k_meter(const uint32_t* __restrict__ hist, int dark,
+                                              float frac3, float frac4, long long npix,
+                                              int32_t* __restrict__ out) {
+  const int lane = threadIdx.x;
+  unsigned long long c = 0;
+  for (int v = lane; v < 256; v += 64)
+    if (v < dark) c += hist[v];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (lane == 0) {
+    const double n = (double)npix;
+    out[0] = (double)c <= (double)frac3 * n ? 2 : ((double)c <= (double)frac4 * n ? 3 : 4);
+    out[1] = (int32_t)c;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_meter(const uint32_t* hist, int dark, float frac3, float frac4,
+                        long long npix, int32_t* out, hipStream_t st) {
+  LNR_LAUNCH(k_meter, dim3(1), dim3(64), 0, st, hist, dark, frac3, frac4, npix, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int W, int H,
                        uint32_t* hist, int nframes, hipStream_t st) {

@@ -704,6 +704,26 @@ lnr_status lnr_stage_equalize(lnr_ctx* ctx, const uint8_t* img, int32_t w, int32
   return LNR_OK;
 }
 
+lnr_status lnr_meter(lnr_ctx* ctx, const uint8_t* y, int32_t w, int32_t h, int32_t stride,
+                     int32_t dark, float frac3, float frac4, int32_t* out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!y || !out || w < 1 || h < 1 || stride < w || w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad metering image");
+  if (dark < 0 || dark > 256 || !(frac3 >= 0.f) || !(frac4 >= frac3) || !(frac4 <= 1.f))
+    return fail(ctx, LNR_E_ARG, "metering needs 0 <= dark <= 256 and 0 <= frac3 <= frac4 <= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  lnr_status s;
+  if ((s = ensure_ws(ctx, 256 * sizeof(uint32_t), st)) != LNR_OK) return s;
+  uint32_t* hist = static_cast<uint32_t*>(ctx->ws);
+  LNR_LAUNCH(k_zero_u32, dim3(1), dim3(256), 0, st, hist, 256);
+  LNR_HIP(hipGetLastError());
+  LNR_HIP(launch_hist(y, stride, y, stride, w, h, hist, 1, st));
+  LNR_HIP(launch_meter(hist, dark, frac3, frac4, (long long)w * h, out, st));
+  return LNR_OK;
+}
+
 lnr_status lnr_stage_warp_q8(lnr_ctx* ctx, const uint8_t* src, int32_t w, int32_t h,
                              const double* H, uint8_t* out, void* stream) {
   if (!ctx) return LNR_E_ARG;

@@ -63,6 +63,10 @@ struct SearchCfg {
 // ---- equalisation + pyramid (k_equalize.hip)
 hipError_t launch_hist(const uint8_t* y0, int s0, const uint8_t* y1, int s1, int W, int H,
                        uint32_t* hist /*[nframes][256]*/, int nframes, hipStream_t st);
+// the metering decision from a luma histogram: out[0] = stops, out[1] = the
+// pixels below dark
+hipError_t launch_meter(const uint32_t* hist, int dark, float frac3, float frac4,
+                        long long npix, int32_t* out, hipStream_t st);
 // out0 / out1 (optional): second copies of the equalised level 0;
 // gt0 (optional): column-major copy of frame 0's equalised level 0, column x
 // at gt0 + x * dt_guide_stride(H) (the propagation's column-pass guide)

@@ -412,6 +412,32 @@ def test_merge_irradiance_full_path(ctx):
     assert np.isfinite(got.cpu().numpy()).all()
 
 
+@pytest.mark.parametrize("h,w,n_dark", [(40, 50, 0), (40, 50, 100), (40, 50, 101),
+                                         (40, 50, 400), (40, 50, 401), (40, 50, 2000),
+                                         (1944, 2592, 500000), (487, 613, 14000)])
+def test_meter_vs_oracle(ctx, h, w, n_dark):
+    """Metering decision and under-exposed count, exact, on padded rows."""
+    rng = np.random.default_rng(h + n_dark)
+    y = rng.integers(16, 256, (h, w)).astype(np.uint8)
+    idx = rng.permutation(h * w)[:n_dark]
+    y.reshape(-1)[idx] = rng.integers(0, 16, n_dark)
+    buf = torch.zeros(h, w + 37, dtype=torch.uint8)
+    buf[:, :w] = torch.from_numpy(y)
+    got = lnr().meter(ctx, buf.cuda()[:, :w])
+    assert got == oracle.meter(y)
+    assert got[1] == n_dark
+    for dark, f3, f4 in [(8, 0.01, 0.5), (64, 0.3, 0.3), (256, 0.0, 1.0)]:
+        assert lnr().meter(ctx, buf.cuda()[:, :w], dark, f3, f4) == oracle.meter(y, dark, f3, f4)
+
+
+def test_meter_rejects_bad_thresholds(ctx):
+    y = torch.zeros(8, 8, dtype=torch.uint8, device="cuda")
+    for dark, f3, f4 in [(-1, 0.05, 0.2), (257, 0.05, 0.2), (16, 0.3, 0.2), (16, -0.1, 0.2),
+                         (16, 0.05, 1.5), (16, float("nan"), 0.2)]:
+        with pytest.raises(lnr().LnrError):
+            lnr().meter(ctx, y, dark, f3, f4)
+
+
 def test_register_deterministic(ctx):
     st = synth.make_config_pair("c1", 15)
     p = lnr().Params(radius0=8)
