@@ -84,6 +84,7 @@ def lib():
         _lib.lo_register_pair.restype = C.c_int
         _lib.lo_merge.restype = C.c_int
         _lib.lo_irradiance.restype = C.c_int
+        _lib.lo_fusion_weight_sum.restype = C.c_int
         _lib.lo_meter.restype = C.c_int
         _lib.lo_meter.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float,
                                   C.c_float, C.c_void_p]
@@ -333,6 +334,21 @@ def merge(imgs, yeqs, ref_index, p=None):
     rc = lib().lo_merge(n, ch, w, h, IA, YA, ref_index, C.byref(p), _p(out))
     if rc:
         raise ValueError("lo_merge failed")
+    return out
+
+
+def fusion_weight_sum(imgs, yeqs, ref_index, p=None):
+    """[H][W] sum of the raw fusion weights before normalisation."""
+    p = p or params()
+    imgs = [_c(i, np.float64) for i in imgs]
+    yeqs = [_c(y, np.float64) for y in yeqs]
+    n = len(imgs)
+    ch, h, w = imgs[0].shape
+    out = np.zeros((h, w), np.float64)
+    IA = (C.c_void_p * n)(*[_p(i) for i in imgs])
+    YA = (C.c_void_p * n)(*[_p(y) for y in yeqs])
+    if lib().lo_fusion_weight_sum(n, ch, w, h, IA, YA, ref_index, C.byref(p), _p(out)):
+        raise ValueError("lo_fusion_weight_sum failed")
     return out
 
 

@@ -716,8 +716,9 @@ void lo_ssim(const double* a, const double* b, int w, int h, const lo_params* p,
  * NULL), plus 1e-12, normalised over the frames. Grey = 0.299 R + 0.587 G +
  * 0.114 B; a luma-only stack (ch = 1) has no saturation term.
  * ------------------------------------------------------------------------- */
-void lo_fusion_weights(int n, int ch, int w, int h, const double* const* imgs,
-                       const double* const* ssim, const lo_params* p, double* const* wout) {
+static void fusion_weights(int n, int ch, int w, int h, const double* const* imgs,
+                           const double* const* ssim, const lo_params* p, double* const* wout,
+                           double* raw_sum) {
   const size_t np = (size_t)w * h;
   double* grey = (double*)malloc(sizeof(double) * np);
   for (int k = 0; k < n; ++k) {
@@ -751,9 +752,39 @@ void lo_fusion_weights(int n, int ch, int w, int h, const double* const* imgs,
   for (size_t o = 0; o < np; ++o) {
     double s = 0;
     for (int k = 0; k < n; ++k) s += wout[k][o];
+    if (raw_sum) raw_sum[o] = s;
     for (int k = 0; k < n; ++k) wout[k][o] = wout[k][o] / s;
   }
   free(grey);
+}
+
+void lo_fusion_weights(int n, int ch, int w, int h, const double* const* imgs,
+                       const double* const* ssim, const lo_params* p, double* const* wout) {
+  fusion_weights(n, ch, w, h, imgs, ssim, p, wout, NULL);
+}
+
+/* The sum of the frames' fusion weights at each pixel before normalisation:
+ * where it is tiny the normalised weights divide rounding noise, so two
+ * merges of inputs that differ by rounding can differ there. */
+int lo_fusion_weight_sum(int n, int ch, int w, int h, const double* const* imgs,
+                         const double* const* yeqs, int ref_index, const lo_params* p,
+                         double* out) {
+  if (n < 1 || ref_index < 0 || ref_index >= n) return -1;
+  const size_t np = (size_t)w * h;
+  double** ssim = (double**)calloc((size_t)n, sizeof(double*));
+  double** wts = (double**)calloc((size_t)n, sizeof(double*));
+  for (int k = 0; k < n; ++k) {
+    wts[k] = (double*)malloc(sizeof(double) * np);
+    if (k != ref_index) {
+      ssim[k] = (double*)malloc(sizeof(double) * np);
+      lo_ssim(yeqs[ref_index], yeqs[k], w, h, p, ssim[k]);
+    }
+  }
+  fusion_weights(n, ch, w, h, imgs, (const double* const*)ssim, p, wts, out);
+  for (int k = 0; k < n; ++k) { free(ssim[k]); free(wts[k]); }
+  free(ssim);
+  free(wts);
+  return 0;
 }
 
 /* ---------------------------------------------------------------------------

@@ -141,6 +141,10 @@ int  lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t*
 /* deghosted merge (Sec. 2.5) of n frames; imgs/yeqs as produced above */
 int  lo_merge(int n, int ch, int w, int h, const double* const* imgs,
               const double* const* yeqs, int ref_index, const lo_params* p, double* out);
+/* the fusion weights' sum per pixel before normalisation (its conditioning) */
+int  lo_fusion_weight_sum(int n, int ch, int w, int h, const double* const* imgs,
+                          const double* const* yeqs, int ref_index, const lo_params* p,
+                          double* out);
 /* Metering of the second exposure (Sec. 2.1; thresholds: readings, see
  * lnr_oracle.c): 2, 3 or 4 stops; *n_dark receives the under-exposed count */
 int  lo_meter(const uint8_t* y, int w, int h, int stride, int dark, float frac3, float frac4,

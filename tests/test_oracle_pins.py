@@ -876,3 +876,13 @@ def test_meter_is_monotone_in_the_dark_count():
         assert stops >= last
         last = stops
     assert last == 4
+
+
+def test_fusion_weight_sum_of_flat_frames():
+    # a flat image has no contrast (zero Laplacian): every raw weight is the
+    # 1e-12 floor, so the sum over n frames is n * 1e-12
+    n, h, w = 3, 12, 17
+    imgs = [np.full((3, h, w), 0.2 + 0.1 * k) for k in range(n)]
+    yeqs = [np.full((h, w), 0.5) for _ in range(n)]
+    s = oracle.fusion_weight_sum(imgs, yeqs, 1)
+    assert np.allclose(s, n * 1e-12, rtol=1e-12, atol=0)
