@@ -345,6 +345,32 @@ def main():
                                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
     result["irradiance_map"] = irr_entry
 
+    # the level-0 search alone, on the registration's own level-0 inputs (the
+    # equalised reference and the Q8-warped source), against the int VALU
+    # peak: one v_dot4 lane-instruction forms four byte products, so the
+    # cross-term peak is 4 x 39.3 T pixel-candidate products per second
+    R0 = st.meta["radius0"]
+    yq, wq = reg.yeq_ref.contiguous(), reg.warped0.contiguous()
+    for _ in range(args.warmup):
+        lnr.stage_search(ctx, yq, wq, R0, p)
+    torch.cuda.synchronize()
+    ctx.trace(True)
+    for _ in range(args.steps):
+        lnr.stage_search(ctx, yq, wq, R0, p)
+    torch.cuda.synchronize()
+    trs = ctx.trace_read()
+    ctx.trace(False)
+    if "k_search" in trs:
+        c_s, ms_s = trs["k_search"]
+        t_l0 = ms_s / c_s / 1e3
+        peak_pc = 4 * INT_PEAK_TOPS
+        ach = search_ops / t_l0 / 1e12
+        result["search_roofline"] = {
+            "kernel": "k_search (level 0)", "bound": "alu", "achieved": round(ach, 2),
+            "peak": round(peak_pc, 2), "unit": "T pixel-candidate products/s",
+            "frac": round(ach / peak_pc, 4), "avg_launch_us": round(t_l0 * 1e6, 2),
+            "products_per_launch": search_ops}
+
     # metering of the second exposure from the first (reference) frame's luma
     for _ in range(args.warmup):
         stops = lnr.meter(ctx, ref.y)
