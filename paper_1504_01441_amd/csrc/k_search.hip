@@ -19,7 +19,9 @@
 //     window energies are column sums of LDS row energies (also v_dot4).
 //  Staging reads aligned dwords (realigned in registers), several in flight
 //  per thread: the kernel's latency, not its arithmetic, bounds the coarse
-//  levels, which have few tiles.
+//  levels, which have few tiles. The region, its row sums and the window
+//  share one dynamic allocation sized for the parameters (about 14 KB at
+//  level 0), so that ten 3-wave workgroups fit on a CU.
 //  4. The argmin key (ssd << 32 | (|dx|+|dy|) << 16 | (dy+R) << 8 | (dx+R)) is
 //     reduced with wave shuffles and LDS; equal keys cannot occur, so the
 //     result does not depend on the reduction order.
@@ -31,7 +33,6 @@ namespace {
 
 constexpr int KX = 8;        // candidates per thread (consecutive dx)
 constexpr int NW = 6;        // patch row dwords (2P+1 <= 24)
-constexpr int kRegion = 64;  // max staged reference region side
 
 __device__ inline long long q8(double s) {
   double q = floor(s * 256.0 + 0.5);
@@ -126,6 +127,9 @@ struct SearchShape {
   int NR;        // window rows = 2P + 2R + 1
   int wrow;      // window row stride in bytes (an odd number of dwords)
   int ncand;     // 2R + 1
+  // workgroup memory, sized for these parameters: the reference region
+  // (rows of rs bytes), the quadrant row sums, then the window
+  int rs, off_hsum, off_win;
 };
 
 __device__ inline unsigned long long wave_min_u64(unsigned long long v) {
@@ -148,9 +152,9 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
                                                  const uint8_t* __restrict__ mode, int want,
                                                  unsigned long long* __restrict__ vb) {
   extern __shared__ __align__(16) uint8_t dyn[];
-  __shared__ uint8_t reg[kRegion * kRegion];
+  uint8_t* reg = dyn;
+  uint32_t* hsum = reinterpret_cast<uint32_t*>(dyn + sh.off_hsum);
   __shared__ uint32_t qsum[4 * 49];
-  __shared__ uint32_t hsum[64 * 14];
   __shared__ uint32_t best_key;
   __shared__ uint32_t refp[(2 * kMaxPatchR + 1) * NW];
   __shared__ uint32_t er_sum;
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
 
   // 1. corners (Eq. 1-2) ----------------------------------------------------
   // the region lies inside the tile; dword-aligned loads realigned in registers
-  stage_rows(ref, w, h, rx0, ry0, side, (side + 3) / 4, reg, kRegion, tid, nt);
+  stage_rows(ref, w, h, rx0, ry0, side, (side + 3) / 4, reg, sh.rs, tid, nt);
   if (tid == 0) { best_key = 0u; er_sum = 0u; }
   __syncthreads();
   const int nc1 = 2 * c.K + 1, ncand = nc1 * nc1;
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       const int row = i / nxo, xo = i % nxo;
       const int a = xo >> 1;
       const int X0 = ext + c.g * (a - c.K) - ((xo & 1) ? 0 : c.r);
-      const uint32_t* rp = rdw + (yo + row) * (kRegion / 4) + (X0 >> 2);
+      const uint32_t* rp = rdw + (yo + row) * (sh.rs / 4) + (X0 >> 2);
       const int rsh = X0 & 3;
       uint32_t s = 0;
       for (int m = 0; m < nd; ++m) {
@@ -245,12 +249,12 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
     uint32_t v = 0;
     for (int k = 0; k < 4; ++k) {
       const int col = dw * 4 + k;
-      if (col < PW) v |= (uint32_t)reg[(pry - P + row) * kRegion + prx - P + col] << (8 * k);
+      if (col < PW) v |= (uint32_t)reg[(pry - P + row) * sh.rs + prx - P + col] << (8 * k);
     }
     refp[i] = v;
   }
-  uint8_t* win = dyn;
-  uint32_t* rowsq = reinterpret_cast<uint32_t*>(dyn + sh.NR * sh.wrow);
+  uint8_t* win = dyn + sh.off_win;
+  uint32_t* rowsq = reinterpret_cast<uint32_t*>(win + sh.NR * sh.wrow);
   const int wx0 = px + cdx - P - R, wy0 = py + cdy - P - R;
   stage_rows(wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
   __syncthreads();
@@ -454,9 +458,20 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
   if ((sh.wrow / 4) % 2 == 0) sh.wrow += 4;
   int block = (sh.nthreads + 63) / 64 * 64;
   if (block < 64) block = 64;
+  // the reference region: side rows of rs bytes, rs covering the realigned
+  // dword reads of the quadrant sums (up to 6 bytes past a row's end) and one
+  // spare row after the last; the quadrant row sums: 2 (K g + r) rows of
+  // 2 (2K + 1) words
+  const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
+  const int side = 2 * ext + 1;
+  sh.rs = (side + 8 + 3) / 4 * 4;
+  const int hsum_words = 2 * (c.K * c.g + c.r) * 2 * (2 * c.K + 1);
+  sh.off_hsum = (sh.rs * (side + 1) + 15) / 16 * 16;
+  sh.off_win = (sh.off_hsum + hsum_words * 4 + 15) / 16 * 16;
   // (+ KX words: the last strip's padded candidates read past the last row;
   // + the partial-sum totals when the rows are split)
-  const size_t lds = (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
+  const size_t lds = (size_t)sh.off_win + (size_t)sh.NR * sh.wrow +
+                     (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
                      (sh.split > 1 ? (size_t)2 * sh.ncand * sh.nstrips * KX * 4 : 0);
   LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
                      ntx, corner_xy, disp, ssd, flags, centre, mode, want, vb);
