@@ -11,7 +11,8 @@
 //             and the fusion weights amplify them again.
 //  k_weights: per pixel, every frame's C * S * E (* max(SSIM, 0)) + 1e-12,
 //             normalised over the frames; threads walk down columns so that
-//             the Laplacian's rows are read once.
+//             the Laplacian's rows are read once, and take the left and right
+//             neighbours from the adjacent lanes.
 //  k_reduce:  REDUCE ([1 4 6 4 1]/16 separable, clamped, even samples) of
 //             every weight and image plane of one level, through LDS.
 //  k_blend:   from the top level down, R_l = sum_k W_k,l (G_k,l - E(G_k,l+1))
@@ -167,42 +168,42 @@ __device__ inline double raw_weight(int ch, double gu, double gl, double gr, dou
 }
 
 constexpr int kWeightRows = 8;
+constexpr int kWeightCols = 62;  // output columns per wave (lanes 1..62)
 
 // Each thread walks down kWeightRows rows of one column: the grey values of
 // the rows above, at and below the pixel stay in registers, so every colour
-// sample is fetched from memory once (the left / right neighbours come from
-// the same cache lines as the neighbouring threads' own pixels). The samples
-// of the next row are loaded before the current row's weights are formed and
-// stored, so one row's loads are always in flight.
+// sample is fetched from memory once. A wave covers 62 columns and two halo
+// lanes (0 and 63, clamped at the image border like the pixels' own
+// neighbours); the left and right neighbours' grey values come from the
+// adjacent lanes by shuffle. The samples of the next row are loaded before
+// the current row's weights are formed and stored, so one row's loads are
+// always in flight.
 template <int NMAX>
 __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int W, int H,
                                                  int ref, float two_se2) {
   int bx, by;
   xcd_block(gridDim.x, gridDim.y, bx, by);
-  const int x = bx * 256 + threadIdx.x;
-  if (x >= W) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = (bx * 4 + wave) * kWeightCols + lane - 1;
+  const int xc = min(max(x, 0), W - 1);
+  const bool writes = lane >= 1 && lane <= kWeightCols && x < W;
+  const int lsrc = lane > 0 ? lane - 1 : 0, rsrc = lane < 63 ? lane + 1 : 63;
   const int y0 = by * kWeightRows, y1 = min(y0 + kWeightRows, H);
   const size_t plane = (size_t)W * H;
-  const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
   auto ld = [&](const float* I, size_t o, float& r, float& g, float& b) {
     r = I[o];
     g = ch == 3 ? I[plane + o] : 0.f;
     b = ch == 3 ? I[2 * plane + o] : 0.f;
   };
-  // samples of row y: d* below, l* / r* left and right, s the SSIM
-  float dr[NMAX], dg[NMAX], db[NMAX], lr[NMAX], lg[NMAX], lb[NMAX], rr[NMAX], rg[NMAX],
-      rb[NMAX], sv[NMAX];
+  // samples of row y: d* the row below, s the SSIM
+  float dr[NMAX], dg[NMAX], db[NMAX], sv[NMAX];
   auto fetch = [&](int y) {  // y < H
-    const size_t o = (size_t)y * W;
-    const size_t od = (size_t)min(y + 1, H - 1) * W + x;
+    const size_t od = (size_t)min(y + 1, H - 1) * W + xc;
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
       if (k >= n) continue;
-      const float* I = f.img[k];
-      ld(I, od, dr[k], dg[k], db[k]);
-      ld(I, o + xl, lr[k], lg[k], lb[k]);
-      ld(I, o + xr, rr[k], rg[k], rb[k]);
-      sv[k] = k != ref ? f.ssim[k][o + x] : 0.f;
+      ld(f.img[k], od, dr[k], dg[k], db[k]);
+      sv[k] = k != ref ? f.ssim[k][(size_t)y * W + xc] : 0.f;
     }
   };
   double gu[NMAX], gc[NMAX];
@@ -211,9 +212,9 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
   for (int k = 0; k < NMAX; ++k) {
     if (k >= n) continue;
     float r, g, b;
-    ld(f.img[k], (size_t)max(y0 - 1, 0) * W + x, r, g, b);
+    ld(f.img[k], (size_t)max(y0 - 1, 0) * W + xc, r, g, b);
     gu[k] = grey_of(ch, r, g, b);
-    ld(f.img[k], (size_t)y0 * W + x, cr[k], cg[k], cb[k]);
+    ld(f.img[k], (size_t)y0 * W + xc, cr[k], cg[k], cb[k]);
     gc[k] = grey_of(ch, cr[k], cg[k], cb[k]);
   }
   // stacks of up to 4 frames keep the next row's samples in flight; larger
@@ -222,15 +223,12 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
   constexpr bool kAhead = NMAX <= 4;
   if constexpr (kAhead) fetch(y0);
   for (int y = y0; y < y1; ++y) {
-    const size_t o = (size_t)y * W + x;
-    float Dr[NMAX], Dg[NMAX], Db[NMAX], Lr[NMAX], Lg[NMAX], Lb[NMAX], Rr[NMAX], Rg[NMAX],
-        Rb[NMAX], S[NMAX];
+    const size_t o = (size_t)y * W + xc;
+    float Dr[NMAX], Dg[NMAX], Db[NMAX], S[NMAX];
     if constexpr (kAhead) {
 #pragma unroll
       for (int k = 0; k < NMAX; ++k) {
         Dr[k] = dr[k]; Dg[k] = dg[k]; Db[k] = db[k];
-        Lr[k] = lr[k]; Lg[k] = lg[k]; Lb[k] = lb[k];
-        Rr[k] = rr[k]; Rg[k] = rg[k]; Rb[k] = rb[k];
         S[k] = sv[k];
       }
       if (y + 1 < y1) fetch(y + 1);
@@ -243,26 +241,25 @@ __global__ __launch_bounds__(256) void k_weights(FramePtrs f, int n, int ch, int
     for (int k = 0; k < NMAX; ++k) {
       if (k >= n) continue;
       if constexpr (!kAhead) {
-        const float* I = f.img[k];
-        ld(I, (size_t)min(y + 1, H - 1) * W + x, Dr[k], Dg[k], Db[k]);
-        ld(I, (size_t)y * W + xl, Lr[k], Lg[k], Lb[k]);
-        ld(I, (size_t)y * W + xr, Rr[k], Rg[k], Rb[k]);
+        ld(f.img[k], (size_t)min(y + 1, H - 1) * W + xc, Dr[k], Dg[k], Db[k]);
         S[k] = k != ref ? f.ssim[k][o] : 0.f;
       }
       const bool warped = k != ref;
       const double gd = grey_of(ch, Dr[k], Dg[k], Db[k]);
-      wk[k] = (float)raw_weight(ch, gu[k], grey_of(ch, Lr[k], Lg[k], Lb[k]),
-                                grey_of(ch, Rr[k], Rg[k], Rb[k]), gd, gc[k], cr[k], cg[k], cb[k],
-                                warped, S[k], two_se2);
+      const double gl = __shfl(gc[k], lsrc), gr = __shfl(gc[k], rsrc);
+      wk[k] = (float)raw_weight(ch, gu[k], gl, gr, gd, gc[k], cr[k], cg[k], cb[k], warped, S[k],
+                                two_se2);
       sum += (double)wk[k];
       gu[k] = gc[k];
       gc[k] = gd;
       cr[k] = Dr[k]; cg[k] = Dg[k]; cb[k] = Db[k];
     }
+    if (writes) {
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) {
-      if (k >= n) continue;
-      f.wout[k][o] = (float)((double)wk[k] / sum);
+      for (int k = 0; k < NMAX; ++k) {
+        if (k >= n) continue;
+        f.wout[k][o] = (float)((double)wk[k] / sum);
+      }
     }
   }
 }
@@ -639,7 +636,8 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
   }
   if ((e = launch_ssim_maps(n, W, H, yeqs, ref_index, p, bufs.ssim, st)) != hipSuccess) return e;
   {
-    const dim3 g((W + 255) / 256, (H + kWeightRows - 1) / kWeightRows);
+    const dim3 g((W + 4 * kWeightCols - 1) / (4 * kWeightCols),
+                 (H + kWeightRows - 1) / kWeightRows);
     const float two_se2 = (float)(2.0 * p.sigma_e * p.sigma_e);
     if (n <= 2)
       LNR_LAUNCH(k_weights<2>, g, dim3(256), 0, st, fp, n, ch, W, H, ref_index, two_se2);
