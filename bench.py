@@ -113,10 +113,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "sweep"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "sweep", "flow-widths"],
                     help="c2: the 5 MP pair (default); c4: 64 uneven pairs in one batched call; "
                          "c5: 16 5 MP pairs in one batched call, learned proposal vs plain; "
-                         "sweep: registration time from VGA to 12 MP")
+                         "sweep: registration time from VGA to 12 MP; flow-widths: the "
+                         "propagation passes at height 1944 and widths 512..4096")
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the c4 batch")
     ap.add_argument("--calib-copy", action="store_true",
                     help="one 256 MiB device-to-device copy before the steps (the reference "
@@ -134,6 +135,8 @@ def main():
         return learned_batch_main(args)
     if args.workload == "sweep":
         return sweep_main(args)
+    if args.workload == "flow-widths":
+        return flow_widths_main(args)
 
     import numpy as np
     import torch
@@ -544,6 +547,58 @@ def sweep_main(args):
         "with_merge_exponent": round(slope_m, 4),
         "sizes": rows,
     }
+    print(json.dumps(result))
+
+
+def flow_widths_main(args):
+    """The propagation alone (lnr_stage_flow, default kernel shapes) on a
+    random guide of height 1944 at widths 512 .. 4096: per-launch times of the
+    row and column passes. The column pass keeps a whole column strip in
+    registers, so its time steps up once the strips no longer fit the chip in
+    one round of resident workgroups."""
+    import torch
+    import paper_1504_01441_amd as lnr
+    ctx = lnr.Context(0)
+    p = lnr.Params()
+    H = 1944
+    rows = []
+    for W in (512, 1024, 2048, 2304, 2592, 3072, 4096):
+        g = torch.randint(0, 256, (H, W), dtype=torch.uint8,
+                          generator=torch.Generator().manual_seed(W)).cuda()
+        nt = (W // p.tile) * (H // p.tile)
+        cxy = torch.zeros(nt, 2, dtype=torch.int32, device="cuda")
+        d = torch.zeros(nt, 2, dtype=torch.int32, device="cuda")
+        f = torch.zeros(nt, dtype=torch.uint8, device="cuda")
+        for _ in range(args.warmup):
+            lnr.stage_flow(ctx, cxy, d, f, g, p)
+        torch.cuda.synchronize()
+        ctx.trace(True)
+        for _ in range(args.steps):
+            lnr.stage_flow(ctx, cxy, d, f, g, p)
+        torch.cuda.synchronize()
+        tr = ctx.trace_read()
+        ctx.trace(False)
+        per = {}
+        for k, (c, ms) in tr.items():
+            base, flag = kernel_key(k)
+            if base == "k_dt_col":
+                key = "k_dt_col_last" if flag else "k_dt_col"
+            elif base == "k_dt_row":
+                key = "k_dt_row_first" if flag else "k_dt_row"
+            else:
+                key = base
+            per[key] = round(ms / c * 1e3, 2)
+        rows.append({"width": W, "height": H, "us_per_launch": per,
+                     "column_blocks": (W + 3) // 4})
+        print(f"[bench] {W}x{H}: {per}", file=sys.stderr, flush=True)
+    result = {"metric": "propagation pass time against image width at height 1944",
+              "value": rows[-3]["us_per_launch"].get("k_dt_col"), "unit": "us per column pass "
+              "at 2592 wide", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": False, "data": "synthetic",
+              "config": {"workload": "lnr_stage_flow on a random 8-bit guide, no matches, "
+                                     "the default kernel shapes for each size (columns at "
+                                     "height 1944: 4 columns x 128 segments of 16 rows)"},
+              "widths": rows}
     print(json.dumps(result))
 
 
