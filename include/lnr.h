@@ -255,6 +255,14 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
  * column segment, columns per block, segments per column. Synchronises. */
 lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
                              int32_t* shape_out, void* stream);
+/* Use one propagation kernel shape (five values, in the order of
+ * lnr_autotune_flow's shape_out) for w x h from now on, in place of the
+ * default or tuned one: for reproducible configurations. LNR_E_UNSUPPORTED
+ * unless it is one of the shapes lnr_flow_shapes lists for w x h. */
+lnr_status lnr_set_flow_shape(lnr_ctx* ctx, int32_t w, int32_t h, const int32_t* shape);
+/* The propagation shapes that cover w x h (host only): writes up to max of
+ * them to shapes[5 * i ...] (may be null) and returns how many there are. */
+int32_t lnr_flow_shapes(int32_t w, int32_t h, int32_t* shapes, int32_t max);
 /* Time every workgroup shape of the matcher's search (Sec. 2.2: how many
  * thread groups share a tile's patch rows) at each pyramid level of a w x h
  * pair, on a synthetic texture, and use the fastest for those level sizes and

@@ -137,6 +137,9 @@ def lib():
                                          C.POINTER(Params), C.POINTER(_Registration), i32, vp]
         L.lnr_autotune_flow.argtypes = [vp, i32, i32, C.POINTER(Params), vp, vp]
         L.lnr_autotune_search.argtypes = [vp, i32, i32, C.POINTER(Params), vp, vp]
+        L.lnr_set_flow_shape.argtypes = [vp, i32, i32, vp]
+        L.lnr_flow_shapes.argtypes = [i32, i32, vp, i32]
+        L.lnr_flow_shapes.restype = C.c_int32
         L.lnr_trace_enable.argtypes = [vp, i32]
         L.lnr_trace_read.argtypes = [vp, C.POINTER(_TraceEntry), i32]
         for name in ("lnr_trace_enable", "lnr_trace_read", "lnr_create", "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack",
@@ -146,7 +149,8 @@ def lib():
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
                      "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow",
                      "lnr_autotune_search", "lnr_proposal_save", "lnr_proposal_load",
-                     "lnr_merge_irradiance", "lnr_stage_irradiance", "lnr_meter"):
+                     "lnr_merge_irradiance", "lnr_stage_irradiance", "lnr_meter",
+                     "lnr_set_flow_shape"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -161,7 +165,7 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
             "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search",
             "lnr_proposal_save", "lnr_proposal_load", "lnr_merge_irradiance",
-            "lnr_stage_irradiance", "lnr_meter")
+            "lnr_stage_irradiance", "lnr_meter", "lnr_set_flow_shape", "lnr_flow_shapes")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -585,6 +589,19 @@ def autotune_search(ctx: Context, w: int, h: int, params: Params | None = None):
     out = (C.c_int32 * 5)()
     ctx.check(lib().lnr_autotune_search(ctx._h, w, h, C.byref(p), out, _stream()))
     return tuple(v for v in out if v)
+
+
+def flow_shapes(w: int, h: int):
+    """The propagation kernel shapes that cover w x h (5-tuples)."""
+    n = lib().lnr_flow_shapes(w, h, None, 0)
+    buf = (C.c_int32 * (5 * max(n, 1)))()
+    lib().lnr_flow_shapes(w, h, buf, n)
+    return [tuple(buf[5 * i:5 * i + 5]) for i in range(n)]
+
+
+def set_flow_shape(ctx: Context, w: int, h: int, shape):
+    arr = (C.c_int32 * 5)(*[int(v) for v in shape])
+    ctx.check(lib().lnr_set_flow_shape(ctx._h, w, h, arr))
 
 
 def autotune_flow(ctx: Context, w: int, h: int, params: Params | None = None):

@@ -495,7 +495,8 @@ hipError_t launch_col(bool last, Rec* maps, const uint8_t* gt, int W, int H,
 
 namespace {
 const DtShape kRowShapes[] = {{4, 256, 0, 0, 0}, {8, 256, 0, 0, 0}, {12, 256, 0, 0, 0},
-                              {4, 512, 0, 0, 0}, {8, 512, 0, 0, 0}, {12, 512, 0, 0, 0}};
+                              {4, 512, 0, 0, 0}, {6, 512, 0, 0, 0}, {8, 512, 0, 0, 0},
+                              {12, 512, 0, 0, 0}};
 const DtShape kColShapes[] = {{0, 0, 8, 8, 128},  {0, 0, 8, 4, 128},  {0, 0, 16, 4, 128},
                               {0, 0, 8, 2, 256},  {0, 0, 24, 4, 128}, {0, 0, 16, 2, 256},
                               {0, 0, 24, 2, 256}};
@@ -506,7 +507,7 @@ hipError_t row_pass(const DtShape& s, bool first, Rec* maps, const uint8_t* guid
 #define ROW(SEG, NT)                                                                           \
   if (s.seg == SEG && s.nt == NT)                                                              \
     return launch_row<SEG, NT>(first, maps, guide, W, H, cf, cxy, disp, flags, ntx, nty, tile, st);
-  ROW(4, 256) ROW(8, 256) ROW(12, 256) ROW(4, 512) ROW(8, 512) ROW(12, 512)
+  ROW(4, 256) ROW(8, 256) ROW(12, 256) ROW(4, 512) ROW(6, 512) ROW(8, 512) ROW(12, 512)
 #undef ROW
   return hipErrorInvalidValue;
 }

@@ -1032,6 +1032,28 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
   return LNR_OK;
 }
 
+lnr_status lnr_set_flow_shape(lnr_ctx* ctx, int32_t w, int32_t h, const int32_t* shape) {
+  if (!ctx) return LNR_E_ARG;
+  if (!shape || w < 1 || h < 1 || w > kMaxSide || h > kMaxSide)
+    return fail(ctx, LNR_E_ARG, "bad flow shape arguments");
+  DtShape s;
+  s.seg = shape[0]; s.nt = shape[1]; s.l = shape[2]; s.ncol = shape[3]; s.nseg = shape[4];
+  if (!dt_shape_valid(s, w, h))
+    return fail(ctx, LNR_E_UNSUPPORTED, "not an instantiated propagation shape covering w x h");
+  ctx->dt_shapes[std::make_pair((int)w, (int)h)] = s;
+  return LNR_OK;
+}
+
+int32_t lnr_flow_shapes(int32_t w, int32_t h, int32_t* shapes, int32_t max) {
+  DtShape c[64];
+  const int n = dt_shape_candidates(w, h, c, 64);
+  for (int i = 0; i < n && i < max && shapes; ++i) {
+    shapes[5 * i] = c[i].seg; shapes[5 * i + 1] = c[i].nt; shapes[5 * i + 2] = c[i].l;
+    shapes[5 * i + 3] = c[i].ncol; shapes[5 * i + 4] = c[i].nseg;
+  }
+  return n;
+}
+
 lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
                              int32_t* shape_out, void* stream) {
   if (!ctx) return LNR_E_ARG;

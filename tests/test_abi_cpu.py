@@ -77,3 +77,16 @@ def test_create_without_device_fails_cleanly(lnr):
     h = C.c_void_p()
     rc = lnr.lib().lnr_create(C.byref(h), 1 << 20)
     assert rc == -1 and not h.value
+
+
+def test_flow_shapes_cover_the_image(lnr):
+    """Host-only listing of the propagation shapes: every listed shape covers
+    the image (row segments x threads >= W, column segments x rows >= H), and
+    the listing is exactly the covering subset of the shape table."""
+    for w, h in [(640, 480), (2592, 1944), (6144, 1024), (1024, 6144)]:
+        shapes = lnr.flow_shapes(w, h)
+        assert shapes, (w, h)
+        for seg, nt, rows, ncol, nseg in shapes:
+            assert seg * nt >= w and rows * nseg >= h
+    assert len(lnr.flow_shapes(640, 480)) == 49      # every row x column shape
+    assert len(lnr.flow_shapes(2592, 1944)) == 20

@@ -218,6 +218,32 @@ def test_register_pair_graph_capture(lnr):
     c.close()
 
 
+def test_every_flow_shape_keeps_parity(lnr):
+    """Each of the 49 propagation shapes (row segment x threads, column rows x
+    columns x segments) pinned for a 640 x 480 pair gives the oracle's
+    registration; shapes only regroup the recursions' scans."""
+    c = lnr.Context(0)
+    w, h = 640, 480
+    p = lnr.Params(radius0=12, min_level_dim=64)
+    st = synth.make_stack(w, h, 780, ratios=(1.0, 4.0), fmt="i420", shift_range=8)
+    f0, f1 = st.frames
+    F0 = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
+    F1 = lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)
+    o = oracle.register_pair(f0, f1, oracle.params(radius0=12, min_level_dim=64))
+    shapes = lnr.flow_shapes(w, h)
+    assert len(shapes) == 49
+    for shp in shapes:
+        lnr.set_flow_shape(c, w, h, shp)
+        reg = lnr.register_pair(c, F0, F1, p)
+        torch.cuda.synchronize()
+        registration_parity(reg, o)
+    with pytest.raises(lnr.LnrError):
+        lnr.set_flow_shape(c, w, h, (5, 256, 8, 8, 128))    # not in the table
+    with pytest.raises(lnr.LnrError):
+        lnr.set_flow_shape(c, 4096, 480, (4, 256, 8, 8, 128))  # does not cover the width
+    c.close()
+
+
 def test_batch_rejects_bad_flags(lnr, ctx):
     import ctypes as C
     ref = _pairs(lnr, 740)[0][2]
