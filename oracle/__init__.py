@@ -309,6 +309,24 @@ def num_blend_levels(w, h):
     return lib().lo_num_blend_levels(w, h)
 
 
+def reduce(img):
+    """The blend's REDUCE step on one 2-D plane."""
+    img = _c(img, np.float64)
+    h, w = img.shape
+    out = np.zeros(((h + 1) // 2, (w + 1) // 2), np.float64)
+    lib().lo_reduce(_p(img), w, h, _p(out))
+    return out
+
+
+def expand(coarse, w, h):
+    """The blend's EXPAND step of a coarse 2-D plane to w x h."""
+    coarse = _c(coarse, np.float64)
+    ch_, cw = coarse.shape
+    out = np.zeros((h, w), np.float64)
+    lib().lo_expand(_p(coarse), cw, ch_, w, h, _p(out))
+    return out
+
+
 def blend(imgs, weights):
     imgs = [_c(i, np.float64) for i in imgs]
     wts = [_c(x, np.float64) for x in weights]

@@ -801,7 +801,7 @@ int lo_num_blend_levels(int w, int h) {
   return 1 + k;
 }
 
-static void reduce(const double* in, int w, int h, double* out) {
+void lo_reduce(const double* in, int w, int h, double* out) {
   static const double kf[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
   int w2 = (w + 1) / 2, h2 = (h + 1) / 2;
   double* tmp = (double*)malloc(sizeof(double) * (size_t)w2 * h);
@@ -828,7 +828,7 @@ static double expand1(const double* c, int n, int x) {
 }
 
 /* coarse (cw x chh) -> fine (w x h): rows first, then columns */
-static void expand(const double* c, int cw, int chh, int w, int h, double* out) {
+void lo_expand(const double* c, int cw, int chh, int w, int h, double* out) {
   double* tmp = (double*)malloc(sizeof(double) * (size_t)w * chh);
   double* col = (double*)malloc(sizeof(double) * (size_t)chh);
   for (int j = 0; j < chh; ++j)
@@ -862,12 +862,12 @@ void lo_blend(int n, int ch, int w, int h, const double* const* imgs,
       memcpy(gw, weights[k], sizeof(double) * (size_t)w * h);
       memcpy(gi, imgs[k] + (size_t)c * w * h, sizeof(double) * (size_t)w * h);
       for (int l = 1; l < L; ++l) {
-        reduce(gw + loff[l - 1], lw[l - 1], lh[l - 1], gw + loff[l]);
-        reduce(gi + loff[l - 1], lw[l - 1], lh[l - 1], gi + loff[l]);
+        lo_reduce(gw + loff[l - 1], lw[l - 1], lh[l - 1], gw + loff[l]);
+        lo_reduce(gi + loff[l - 1], lw[l - 1], lh[l - 1], gi + loff[l]);
       }
       for (int l = 0; l < L; ++l) {
         size_t np = (size_t)lw[l] * lh[l];
-        if (l + 1 < L) expand(gi + loff[l + 1], lw[l + 1], lh[l + 1], lw[l], lh[l], ex);
+        if (l + 1 < L) lo_expand(gi + loff[l + 1], lw[l + 1], lh[l + 1], lw[l], lh[l], ex);
         for (size_t o = 0; o < np; ++o) {
           double lap = gi[loff[l] + o] - (l + 1 < L ? ex[o] : 0.0);
           acc[loff[l] + o] += gw[loff[l] + o] * lap;
@@ -876,7 +876,7 @@ void lo_blend(int n, int ch, int w, int h, const double* const* imgs,
     }
     /* collapse: R_top = B_top, R_l = B_l + EXPAND(R_{l+1}) */
     for (int l = L - 2; l >= 0; --l) {
-      expand(acc + loff[l + 1], lw[l + 1], lh[l + 1], lw[l], lh[l], ex);
+      lo_expand(acc + loff[l + 1], lw[l + 1], lh[l + 1], lw[l], lh[l], ex);
       size_t np = (size_t)lw[l] * lh[l];
       for (size_t o = 0; o < np; ++o) acc[loff[l] + o] += ex[o];
     }

@@ -132,6 +132,10 @@ void lo_fusion_weights(int n, int ch, int w, int h, const double* const* imgs,
                        const double* const* ssim, const lo_params* p, double* const* wout);
 /* Sec. 2.5: multiresolution blend of n images with normalised weights */
 int  lo_num_blend_levels(int w, int h);
+/* the blend's pyramid steps: REDUCE of a w x h plane to ceil(w/2) x ceil(h/2),
+ * and EXPAND of a cw x chh plane to the finer w x h */
+void lo_reduce(const double* in, int w, int h, double* out);
+void lo_expand(const double* c, int cw, int chh, int w, int h, double* out);
 void lo_blend(int n, int ch, int w, int h, const double* const* imgs,
               const double* const* weights, double* out);
 /* whole pair (Sec. 2.2 - 2.4 + warp) */

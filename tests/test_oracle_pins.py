@@ -712,29 +712,104 @@ def test_blend_levels_rule():
     assert oracle.num_blend_levels(16, 16) == 2
 
 
-def test_reduce_matches_library_filter():
-    """REDUCE = [1 4 6 4 1]/16 separable with clamped borders, then decimate."""
-    rng = np.random.default_rng(26)
-    img = rng.uniform(0, 1, (1, 30, 41))
-    # a single frame with a weight that is 1 on level 0 only matters via the
-    # pyramid; check REDUCE through blend's linearity instead: compare the
-    # blend of two frames whose weights are constant per frame.
-    k = np.array([1, 4, 6, 4, 1]) / 16.0
-    red = ndi.convolve1d(ndi.convolve1d(img[0], k, axis=1, mode="nearest"), k, axis=0,
-                         mode="nearest")[::2, ::2]
-    # EXPAND of red with the even/odd rule, on interior pixels, against
-    # zero-insertion + [1 4 6 4 1]/8 filtering (its standard definition)
-    up = np.zeros((30, 41))
-    up[::2, ::2] = red
-    k2 = np.array([1, 4, 6, 4, 1]) / 8.0
-    exp_ref = ndi.convolve1d(ndi.convolve1d(up, k2, axis=1, mode="constant"), k2, axis=0,
-                             mode="constant")
-    # reconstruct via the oracle: blend of one frame returns the input exactly,
-    # so use the pyramid identity G0 = L0 + EXPAND(G1) on interior pixels
-    lap = img[0] - exp_ref
-    assert np.allclose((lap + exp_ref)[3:-3, 3:-3], img[0][3:-3, 3:-3])
-    out = oracle.blend([img], [np.ones((30, 41))])
-    assert np.allclose(out, img, atol=1e-12)
+# Burt & Adelson's pyramid steps written out in their two-dimensional form
+# (the generating kernel w = [1 4 6 4 1] / 16 in each direction), with the
+# image borders replicated. The oracle computes them separably (rows, then
+# columns) with its own index rules; these loops share nothing with it.
+_BA = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
+
+
+def _ba_reduce(g):
+    """G_l(i, j) = sum_{m,n} w(m) w(n) G_{l-1}(2i + m, 2j + n), borders replicated."""
+    h, w = g.shape
+    h2, w2 = (h + 1) // 2, (w + 1) // 2
+    out = np.zeros((h2, w2))
+    ii, jj = np.mgrid[0:h2, 0:w2]
+    for m in range(-2, 3):
+        for n in range(-2, 3):
+            yy = np.clip(2 * ii + m, 0, h - 1)
+            xx = np.clip(2 * jj + n, 0, w - 1)
+            out += _BA[m + 2] * _BA[n + 2] * g[yy, xx]
+    return out
+
+
+def _ba_expand(c, w, h):
+    """G_{l,1}(i, j) = 4 sum_{m,n} w(m) w(n) G_l((i - m) / 2, (j - n) / 2) over
+    the terms with integer coarse indices, coarse indices replicated past the
+    border."""
+    ch_, cw = c.shape
+    out = np.zeros((h, w))
+    ii, jj = np.mgrid[0:h, 0:w]
+    for m in range(-2, 3):
+        for n in range(-2, 3):
+            ok = ((ii - m) % 2 == 0) & ((jj - n) % 2 == 0)
+            yy = np.clip((ii - m) // 2, 0, ch_ - 1)
+            xx = np.clip((jj - n) // 2, 0, cw - 1)
+            out += np.where(ok, 4.0 * _BA[m + 2] * _BA[n + 2] * c[yy, xx], 0.0)
+    return out
+
+
+def _ba_blend(imgs, weights, levels):
+    """Mertens et al.'s blend: sum_k G(W_k)_l L(I_k)_l per level, collapsed."""
+    ch, h, w = imgs[0].shape
+    out = np.zeros((ch, h, w))
+    for c in range(ch):
+        acc = None
+        for I, Wt in zip(imgs, weights):
+            gi, gw = [I[c]], [Wt]
+            for _ in range(1, levels):
+                gi.append(_ba_reduce(gi[-1]))
+                gw.append(_ba_reduce(gw[-1]))
+            lap = [gi[l] - _ba_expand(gi[l + 1], gi[l].shape[1], gi[l].shape[0])
+                   for l in range(levels - 1)] + [gi[-1]]
+            terms = [gw[l] * lap[l] for l in range(levels)]
+            acc = terms if acc is None else [a + t for a, t in zip(acc, terms)]
+        r = acc[-1]
+        for l in range(levels - 2, -1, -1):
+            r = acc[l] + _ba_expand(r, acc[l].shape[1], acc[l].shape[0])
+        out[c] = r
+    return out
+
+
+@pytest.mark.parametrize("shape", [(30, 41), (31, 40), (33, 33), (7, 1), (1, 6), (2, 3), (5, 5)])
+def test_reduce_is_burt_adelson(shape):
+    """The blend's REDUCE equals the 5-tap generating kernel applied in 2-D at
+    the even samples, borders included (odd and tiny sizes)."""
+    g = np.random.default_rng(26).uniform(0, 1, shape)
+    got = oracle.reduce(g)
+    assert got.shape == ((shape[0] + 1) // 2, (shape[1] + 1) // 2)
+    assert np.allclose(got, _ba_reduce(g), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("fine", [(30, 41), (31, 40), (33, 33), (7, 1), (1, 6), (2, 3), (5, 5)])
+def test_expand_is_burt_adelson(fine):
+    """EXPAND back to the finer size equals Burt and Adelson's interpolation
+    (even and odd output phases, borders) for every fine size whose REDUCE
+    gives that coarse size."""
+    h, w = fine
+    c = np.random.default_rng(27).uniform(0, 1, ((h + 1) // 2, (w + 1) // 2))
+    assert np.allclose(oracle.expand(c, w, h), _ba_expand(c, w, h), rtol=0, atol=1e-14)
+
+
+def test_blend_step_edge_weights_against_pyramid_definition():
+    """Two frames blended with a step-edge weight (and a smooth second
+    channel's frames): the oracle's blend equals the pyramid blend built from
+    the definitions above, so a wrong filter, phase or collapse order fails."""
+    rng = np.random.default_rng(28)
+    h, w = 37, 53
+    a = rng.uniform(0, 1, (2, h, w))
+    b = rng.uniform(0, 1, (2, h, w))
+    w0 = np.zeros((h, w))
+    w0[:, : w // 2 + 3] = 1.0          # step edge off the pyramid's even grid
+    w0[5:9, 40:] = 0.3
+    w1 = 1.0 - w0
+    L = oracle.num_blend_levels(w, h)
+    assert L == 3
+    want = _ba_blend([a, b], [w0, w1], L)
+    got = oracle.blend([a, b], [w0, w1])
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+    # not a plain per-pixel mix: the pyramid smooths the seam
+    assert np.abs(got - (w0 * a + w1 * b)).max() > 1e-2
 
 
 # ---------------------------------------------------------------- whole pair
