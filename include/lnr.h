@@ -95,7 +95,9 @@ typedef struct {
    * confidence is below conf_min. Needs lnr_proposal_set() first and tile 32. */
   int32_t learned;         /* 0: plain method (default), 1: learned proposal    */
   int32_t window_r;        /* window radius, 0..radius0 (default 2)             */
-  double conf_min;         /* confidence threshold in (0, 1) (default 0.5)      */
+  double conf_min;         /* confidence threshold in [0, 1] (default 0.5): 0
+                              windows every cornered tile, 1 searches every
+                              tile exhaustively (the plain method's result) */
 } lnr_params;
 
 typedef struct {
@@ -151,9 +153,13 @@ lnr_status lnr_register_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame
                              const lnr_params* p, lnr_registration* out, void* stream);
 
 /* Register an n-frame stack (paper Sec. 2: n - 1 registrations): the
- * reference is the frame with the smallest exposure (lowest index on ties),
- * written to *ref_index; outs[k] receives the registration of the k-th
- * non-reference frame, in frame order. */
+ * reference is the frame with the smallest exposure (Sec. 2.1; lowest index
+ * on ties), written to *ref_index; outs[k] receives the registration of the
+ * k-th non-reference frame, in frame order. When the exposures are not known
+ * (not every one positive and finite) the darkest frame is the reference:
+ * the lowest mean luma (lowest index on ties); that case reads the frames'
+ * histograms back and waits for `stream` once. All frames must share size
+ * and format. */
 lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
                               const lnr_params* p, lnr_registration* outs,
                               int32_t* ref_index, void* stream);

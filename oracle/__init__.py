@@ -327,6 +327,16 @@ def expand(coarse, w, h):
     return out
 
 
+def pick_reference(exposures, ys):
+    """Index of the stack's reference frame from its exposures and luma planes."""
+    ys = [_c(y, np.uint8) for y in ys]
+    n = len(ys)
+    h, w = ys[0].shape
+    ex = _c(exposures, np.float32)
+    YA = (C.c_void_p * n)(*[_p(y) for y in ys])
+    return lib().lo_pick_reference(n, _p(ex), YA, w, h, w)
+
+
 def blend(imgs, weights):
     imgs = [_c(i, np.float64) for i in imgs]
     wts = [_c(x, np.float64) for x in weights]

@@ -987,6 +987,35 @@ int lo_irradiance(int n, int ch, int w, int h, const double* const* imgs,
  * are propagated to a dense residual flow, and the source is warped
  * backwards through H^1 and that flow.
  * ------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------
+ * Reference frame of a stack (Sec. 2.1, Sec. 2 opening): the shortest exposure,
+ * the lowest index on ties. When the exposures are not known (not every one
+ * positive and finite), the darkest frame stands in for the shortest: the
+ * lowest mean luma, compared as exact integer sums over equal-size frames,
+ * the lowest index on ties.
+ * ------------------------------------------------------------------------- */
+int lo_pick_reference(int n, const float* exposure, const uint8_t* const* ys, int w, int h,
+                      int stride) {
+  if (n < 1) return -1;
+  int known = 1;
+  for (int k = 0; k < n; ++k)
+    if (!(exposure[k] > 0.0f) || !isfinite(exposure[k])) known = 0;
+  int r = 0;
+  if (known) {
+    for (int k = 1; k < n; ++k)
+      if (exposure[k] < exposure[r]) r = k;
+    return r;
+  }
+  int64_t best = -1;
+  for (int k = 0; k < n; ++k) {
+    int64_t sum = 0;
+    for (int y = 0; y < h; ++y)
+      for (int x = 0; x < w; ++x) sum += ys[k][(size_t)y * stride + x];
+    if (best < 0 || sum < best) { best = sum; r = k; }
+  }
+  return r;
+}
+
 int lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t* src_u,
                      const uint8_t* src_v, int w, int h, const lo_params* p,
                      const double* H_init, lo_registration* out) {

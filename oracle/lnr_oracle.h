@@ -138,6 +138,10 @@ void lo_reduce(const double* in, int w, int h, double* out);
 void lo_expand(const double* c, int cw, int chh, int w, int h, double* out);
 void lo_blend(int n, int ch, int w, int h, const double* const* imgs,
               const double* const* weights, double* out);
+/* Sec. 2.1: reference of an n-frame stack (shortest exposure; without known
+ * exposures the lowest mean luma), lowest index on ties */
+int  lo_pick_reference(int n, const float* exposure, const uint8_t* const* ys, int w, int h,
+                       int stride);
 /* whole pair (Sec. 2.2 - 2.4 + warp) */
 int  lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t* src_u,
                       const uint8_t* src_v, int w, int h, const lo_params* p,

@@ -53,6 +53,7 @@ struct Tracer {
 
 thread_local Tracer* g_tracer = nullptr;
 
+
 TraceScope::TraceScope(const char* name, hipStream_t st) {
   if (!g_tracer) return;
   Tracer& t = *g_tracer;
@@ -149,8 +150,8 @@ lnr_status check_params(lnr_ctx* ctx, const lnr_params* p) {
     if (p->tile != 32) return fail(ctx, LNR_E_UNSUPPORTED, "the learned proposal needs tile 32");
     if (p->window_r < 0 || p->window_r > p->radius0)
       return fail(ctx, LNR_E_UNSUPPORTED, "window_r must be in [0, radius0]");
-    if (!(p->conf_min > 0.0 && p->conf_min < 1.0))
-      return fail(ctx, LNR_E_UNSUPPORTED, "conf_min must be in (0, 1)");
+    if (!(p->conf_min >= 0.0 && p->conf_min <= 1.0))
+      return fail(ctx, LNR_E_UNSUPPORTED, "conf_min must be in [0, 1]");
   }
   return LNR_OK;
 }
@@ -394,7 +395,11 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
       uint16_t* x = reinterpret_cast<uint16_t*>(base + q.o_cx);
       int32_t* centre = reinterpret_cast<int32_t*>(base + q.o_cc);
       uint8_t* mode = reinterpret_cast<uint8_t*>(base + q.o_cm);
-      const float logit = (float)std::log(p->conf_min / (1.0 - p->conf_min));
+      // the window is taken where the logit is >= this: conf_min 0 windows
+      // every tile, conf_min 1 (a NaN bound, no logit compares >= it) none
+      const float logit = p->conf_min <= 0.0 ? -INFINITY
+                          : p->conf_min >= 1.0 ? NAN
+                          : (float)std::log(p->conf_min / (1.0 - p->conf_min));
       LNR_HIP(launch_cnn_input(pref, warped, W, L.ntx, L.nty, x, st));
       LNR_HIP(launch_cnn_forward(ctx->cnn_packed, ctx->cnn, x, nt, nullptr, nullptr, centre, mode,
                                  p->radius0 - p->window_r, logit, st));
@@ -569,12 +574,46 @@ lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
   TraceGuard tg(ctx);
   if (!frames || n < 2 || n > 16 || !outs || !ref_index)
     return fail(ctx, LNR_E_ARG, "register_stack needs 2..16 frames, outputs and ref_index");
-  // Sec. 2.1: the shortest exposure is the reference (lowest index on ties)
-  int r = 0;
+  lnr_status s0;
+  for (int k = 0; k < n; ++k)
+    if ((s0 = check_frame(ctx, &frames[k], "frame")) != LNR_OK) return s0;
   for (int k = 1; k < n; ++k)
-    if (frames[k].exposure < frames[r].exposure) r = k;
-  *ref_index = r;
+    if (frames[k].width != frames[0].width || frames[k].height != frames[0].height)
+      return fail(ctx, LNR_E_ARG, "stack frames differ in size");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  // Sec. 2.1: the shortest exposure is the reference (lowest index on ties);
+  // without known exposures (not every one positive and finite) the darkest
+  // frame, by mean luma (exact integer sums from the frames' histograms;
+  // this case waits for the stream once)
+  bool known = true;
+  for (int k = 0; k < n; ++k)
+    if (!(frames[k].exposure > 0.f) || !std::isfinite(frames[k].exposure)) known = false;
+  int r = 0;
+  if (known) {
+    for (int k = 1; k < n; ++k)
+      if (frames[k].exposure < frames[r].exposure) r = k;
+  } else {
+    const hipStream_t st = (hipStream_t)stream;
+    if ((s0 = ensure_ws(ctx, (size_t)n * 256 * sizeof(uint32_t), st)) != LNR_OK) return s0;
+    uint32_t* hist = static_cast<uint32_t*>(ctx->ws);
+    LNR_LAUNCH(k_zero_u32, dim3((n * 256 + 255) / 256), dim3(256), 0, st, hist, n * 256);
+    LNR_HIP(hipGetLastError());
+    const int W = frames[0].width, H = frames[0].height;
+    for (int k = 0; k < n; ++k)
+      LNR_HIP(launch_hist(frames[k].plane[0], frames[k].stride[0], frames[k].plane[0],
+                          frames[k].stride[0], W, H, hist + 256 * k, 1, st));
+    std::vector<uint32_t> hh((size_t)n * 256);
+    LNR_HIP(hipMemcpyAsync(hh.data(), hist, hh.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           st));
+    LNR_HIP(hipStreamSynchronize(st));
+    long long best = -1;
+    for (int k = 0; k < n; ++k) {
+      long long sum = 0;
+      for (int v = 0; v < 256; ++v) sum += (long long)v * hh[(size_t)k * 256 + v];
+      if (best < 0 || sum < best) { best = sum; r = k; }
+    }
+  }
+  *ref_index = r;
   int j = 0;
   for (int k = 0; k < n; ++k) {
     if (k == r) continue;

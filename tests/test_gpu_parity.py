@@ -506,6 +506,26 @@ def test_stack_and_merge_three_frames(ctx):
     _check_full_merge(ctx, frames, ref, regs, regs_o, out, p, op)
 
 
+def test_stack_reference_without_exposures(ctx):
+    """Exposures unknown (all 0): register_stack takes the darkest frame (the
+    oracle's pick, lowest mean luma) as the reference, and registers the
+    others to it as the oracle does."""
+    st = synth.make_config_pair("c3", 4, scale=0.2)
+    frames = st.frames[::-1]                # darkest last: index 2
+    p, op = params_pair(radius0=16, min_level_dim=64)
+    g = [lnr().Frame.from_numpy(f.y, f.u, f.v, 0.0) for f in frames]
+    regs, ref = lnr().register_stack(ctx, g, p)
+    _sync()
+    want = oracle.pick_reference([0.0] * 3, [f.y for f in frames])
+    print(f"reference {ref}, oracle {want}", flush=True)
+    assert ref == want == 2
+    j = 0
+    for k, f in enumerate(frames):
+        if k != ref:
+            registration_parity(regs[j], oracle.register_pair(frames[ref], f, op))
+            j += 1
+
+
 def test_stack_and_merge_three_frames_full_size(ctx):
     """The 12 MP 3-frame stack at its full size (4000x3000, ratios 1/4/16,
     rotation up to 3 degrees, shifts +-12, 5 % saturated discs): both

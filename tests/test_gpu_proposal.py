@@ -246,3 +246,33 @@ def test_network_file_roundtrip_and_rejects(lnr, tmp_path):
         lnr.proposal_load(c, str(tmp_path / "missing.bin"))
     assert e.value.status == -7
     c.close()
+
+
+@pytest.mark.parametrize("conf_min", [0.0, 1.0])
+def test_confidence_threshold_edges(lnr, conf_min):
+    """conf_min = 1: every cornered tile falls back to the exhaustive search,
+    so the registration is the plain method's bit for bit (flag 16 aside);
+    conf_min = 0: no tile falls back."""
+    c = lnr.Context(0)
+    lnr.proposal_set(c, torch.from_numpy(synth.proposal_params(5)).cuda())
+    st = synth.make_stack(640, 480, 31, ratios=(1.0, 4.0), fmt="i420", shift_range=6)
+    f0, f1 = st.frames
+    ref = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
+    src = lnr.Frame.from_numpy(f1.y, f1.u, f1.v, f1.exposure)
+    pl = lnr.Params(radius0=8)
+    pq = lnr.Params(radius0=8, learned=1, window_r=2, conf_min=conf_min)
+    reg_p = lnr.register_pair(c, ref, src, pl)
+    reg_l = lnr.register_pair(c, ref, src, pq)
+    torch.cuda.synchronize()
+    n0 = reg_l.tile_off[1]
+    fl = reg_l.flags.cpu().numpy()[:n0]
+    cornered = (fl & 1) != 0
+    assert cornered.sum() > 50
+    if conf_min == 1.0:
+        assert np.all((fl[cornered] & 16) != 0)
+        assert np.array_equal(reg_l.flags.cpu().numpy() & ~np.uint8(16), reg_p.flags.cpu().numpy())
+        for k in ("corner_xy", "disp", "ssd", "counts", "H", "flow", "image"):
+            assert torch.equal(getattr(reg_l, k), getattr(reg_p, k)), k
+    else:
+        assert not np.any(fl & 16)
+    c.close()

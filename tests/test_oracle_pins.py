@@ -961,3 +961,25 @@ def test_fusion_weight_sum_of_flat_frames():
     yeqs = [np.full((h, w), 0.5) for _ in range(n)]
     s = oracle.fusion_weight_sum(imgs, yeqs, 1)
     assert np.allclose(s, n * 1e-12, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- reference pick (Sec. 2.1)
+
+def test_pick_reference_shortest_exposure_and_ties():
+    rng = np.random.default_rng(40)
+    ys = [rng.integers(0, 256, (12, 17), np.uint8) for _ in range(4)]
+    assert oracle.pick_reference([4.0, 1.0, 16.0, 2.0], ys) == 1
+    assert oracle.pick_reference([2.0, 1.0, 1.0, 8.0], ys) == 1       # lowest index on ties
+    assert oracle.pick_reference([3.0, 3.0, 3.0, 3.0], ys) == 0
+
+
+def test_pick_reference_without_exposures_is_darkest_mean():
+    """Unknown exposures (any not positive and finite): the frame with the
+    lowest mean luma, computed here by numpy, lowest index on ties."""
+    rng = np.random.default_rng(41)
+    ys = [np.clip(rng.normal(m, 20, (30, 41)), 0, 255).astype(np.uint8) for m in (120, 60, 200)]
+    means = [y.astype(np.int64).mean() for y in ys]
+    for ex in ([0.0, 0.0, 0.0], [1.0, 0.0, 4.0], [1.0, float("nan"), 2.0], [-1.0, 2.0, 3.0]):
+        assert oracle.pick_reference(ex, ys) == int(np.argmin(means)) == 1
+    tie = [ys[2], ys[1].copy(), ys[1].copy()]
+    assert oracle.pick_reference([0.0] * 3, tie) == 1
