@@ -84,7 +84,10 @@ typedef struct {
   double n_min;            /* F = P~/N~ only where N~ > n_min (Sec. 2.4)         */
   double ssim_sigma;       /* SSIM Gaussian window sigma                         */
   int32_t ssim_radius;     /* SSIM window radius, 1..8                          */
-  int32_t reserved0;
+  int32_t search_frame;    /* 0: each level searches the source warped by the
+                              previous level's homography; 1 (Eq. 3 as
+                              printed, the unwarped source around round(H x))
+                              is rejected with LNR_E_UNSUPPORTED for now   */
   double ssim_c1, ssim_c2; /* SSIM stabilisers                                   */
   double sigma_e;          /* Mertens well-exposedness sigma                     */
   uint64_t seed;           /* weeding sampler seed                               */

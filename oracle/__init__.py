@@ -44,7 +44,7 @@ class Params(C.Structure):
         ("weed_delta_min", C.c_int32), ("weed_delta_pct", C.c_int32), ("dt_iters", C.c_int32),
         ("weed_eps", C.c_double), ("sigma_s", C.c_double), ("sigma_r", C.c_double),
         ("n_min", C.c_double), ("ssim_sigma", C.c_double), ("ssim_radius", C.c_int32),
-        ("pad0", C.c_int32), ("ssim_c1", C.c_double), ("ssim_c2", C.c_double),
+        ("search_frame", C.c_int32), ("ssim_c1", C.c_double), ("ssim_c2", C.c_double),
         ("sigma_e", C.c_double), ("seed", C.c_uint64),
     ]
 
@@ -78,6 +78,7 @@ def lib():
         _lib.lo_num_levels.restype = C.c_int
         _lib.lo_weed.restype = C.c_int
         _lib.lo_fit_level.restype = C.c_int
+        _lib.lo_fit_level_absolute.restype = C.c_int
         _lib.lo_fit4.restype = C.c_int
         _lib.lo_weed_delta.restype = C.c_int
         _lib.lo_hypothesis_inliers.restype = C.c_int
@@ -192,6 +193,25 @@ def search(ref, wimg, R, cx, cy, has, p=None):
     return dx[:nt], dy[:nt], ssd[:nt], valid[:nt]
 
 
+def search_unwarped(ref, src, R, Hp, cx, cy, has, p=None):
+    """The search of Eq. 3 as printed: around round(Hp x) in the unwarped
+    source; returns absolute displacements (dx, dy), ssd, valid."""
+    p = p or params()
+    ref = _c(ref, np.uint8)
+    src = _c(src, np.uint8)
+    h, w = ref.shape
+    nt = (w // p.tile) * (h // p.tile)
+    Hp = _c(Hp, np.float64).reshape(9)
+    cx, cy, has = _c(cx, np.int32), _c(cy, np.int32), _c(has, np.uint8)
+    dx = np.zeros(max(nt, 1), np.int32)
+    dy = np.zeros(max(nt, 1), np.int32)
+    ssd = np.zeros(max(nt, 1), np.uint32)
+    valid = np.zeros(max(nt, 1), np.uint8)
+    lib().lo_search_unwarped(_p(ref), _p(src), w, h, C.byref(p), R, _p(Hp), _p(cx), _p(cy),
+                             _p(has), _p(dx), _p(dy), _p(ssd), _p(valid))
+    return dx[:nt], dy[:nt], ssd[:nt], valid[:nt]
+
+
 def weed(cx, cy, dx, dy, valid, w, h, level, p=None, it0=0, it1=None, inM=None):
     """Returns (inM, N, best_count, best_iter)."""
     p = p or params()
@@ -238,6 +258,17 @@ def fit_level(cx, cy, dx, dy, sel, w, h, Hprev):
     Hprev = _c(Hprev, np.float64).reshape(9)
     Hout = np.zeros(9, np.float64)
     m = lib().lo_fit_level(len(cx), *[_p(a) for a in args], _p(inM), w, h, _p(Hprev), _p(Hout))
+    return Hout.reshape(3, 3), m
+
+
+def fit_level_absolute(cx, cy, dx, dy, sel, w, h, Hprev):
+    """Level homography fitted to absolute matches (Hprev kept on failure)."""
+    args = [_c(a, np.int32) for a in (cx, cy, dx, dy)]
+    inM = _c(sel, np.uint8)
+    Hprev = _c(Hprev, np.float64).reshape(9)
+    Hout = np.zeros(9, np.float64)
+    m = lib().lo_fit_level_absolute(len(cx), *[_p(a) for a in args], _p(inM), w, h, _p(Hprev),
+                                    _p(Hout))
     return Hout.reshape(3, 3), m
 
 

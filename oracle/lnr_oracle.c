@@ -263,6 +263,63 @@ void lo_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, const lo_p
   }
 }
 
+/* Sec. 2.2 with Eq. 3 taken as printed: the previous level's homography
+ * predicts where each reference corner x lies in the *unwarped* source,
+ * q = (floor(sx + 0.5), floor(sy + 0.5)) with (sx, sy) = Hp x, and the SSD
+ * search runs over q + d, d in [-R, R]^2, against the unwarped source. Same
+ * patch, skip rule and tie order (on d) as lo_search; the match is the
+ * absolute correspondence x -> q + d, stored as dx, dy = q + d - x. */
+static int32_t round_pred(double s) {
+  double q = floor(s + 0.5);
+  if (!(q > -1048576.0)) q = -1048576.0; /* also maps NaN */
+  if (q > 1048576.0) q = 1048576.0;
+  return (int32_t)q;
+}
+
+void lo_search_unwarped(const uint8_t* ref, const uint8_t* src, int w, int h,
+                        const lo_params* p, int R, const double Hp[9], const int32_t* cx,
+                        const int32_t* cy, const uint8_t* has, int32_t* dx, int32_t* dy,
+                        uint32_t* ssd, uint8_t* valid) {
+  const int S = p->tile, P = p->patch_r;
+  const int ntiles = (w / S) * (h / S);
+  for (int t = 0; t < ntiles; ++t) {
+    valid[t] = 0;
+    dx[t] = 0;
+    dy[t] = 0;
+    ssd[t] = 0;
+    if (!has[t]) continue;
+    const int px = cx[t], py = cy[t];
+    double sx, sy;
+    apply_h(Hp, (double)px, (double)py, &sx, &sy);
+    const int qx = round_pred(sx), qy = round_pred(sy);
+    int found = 0;
+    uint32_t bs = 0;
+    int bl = 0, bdx = 0, bdy = 0;
+    for (int ddy = -R; ddy <= R; ++ddy)
+      for (int ddx = -R; ddx <= R; ++ddx) {
+        const int sx0 = qx + ddx, sy0 = qy + ddy;  /* candidate centre in the source */
+        if (sx0 - P < 0 || sx0 + P > w - 1 || sy0 - P < 0 || sy0 + P > h - 1) continue;
+        uint32_t s = 0;
+        for (int j = -P; j <= P; ++j)
+          for (int i = -P; i <= P; ++i) {
+            int a = ref[(size_t)(py + j) * w + (px + i)];
+            int b = src[(size_t)(sy0 + j) * w + (sx0 + i)];
+            s += (uint32_t)((a - b) * (a - b));
+          }
+        int l1 = abs(ddx) + abs(ddy);
+        int better = !found || s < bs || (s == bs && (l1 < bl || (l1 == bl && (ddy < bdy ||
+                     (ddy == bdy && ddx < bdx)))));
+        if (better) { found = 1; bs = s; bl = l1; bdx = ddx; bdy = ddy; }
+      }
+    if (found) {
+      valid[t] = 1;
+      dx[t] = qx + bdx - px;
+      dy[t] = qy + bdy - py;
+      ssd[t] = bs;
+    }
+  }
+}
+
 /* ---------------------------------------------------------------------------
  * Dense 8x8 linear solve, Gaussian elimination with partial pivoting (first
  * largest |pivot|), rows updated as a[r][j] - f * a[c][j]; a pivot below
@@ -470,9 +527,11 @@ int lo_hypothesis_inliers(int ntiles, const int32_t* cx, const int32_t* cy, cons
  * ox = 2(w/2) - (w-1), Gn = Pm Gc Qm, Qm = [[w,0,-ox],[0,w,-oy],[0,0,2]].
  * Fewer than 4 matches, a singular system or a degenerate product keeps H^{l+1}.
  * ------------------------------------------------------------------------- */
-int lo_fit_level(int ntiles, const int32_t* cx, const int32_t* cy, const int32_t* dx,
-                 const int32_t* dy, const uint8_t* sel, int w, int h,
-                 const double Hprev[9], double Hout[9]) {
+/* Hbase: the map the fitted G is composed on (H^{l+1}, or the identity when
+ * the matches are absolute); Hprev is the result when the fit fails. */
+static int fit_level(int ntiles, const int32_t* cx, const int32_t* cy, const int32_t* dx,
+                     const int32_t* dy, const uint8_t* sel, int w, int h,
+                     const double Hprev[9], const double Hbase[9], double Hout[9]) {
   const int ox = w / 2, oy = h / 2;
   int64_t ata[8][8], atb[8];
   memset(ata, 0, sizeof(ata));
@@ -511,7 +570,7 @@ int lo_fit_level(int ntiles, const int32_t* cx, const int32_t* cy, const int32_t
   double T1[9], T2[9], T3[9];
   mat3_mul(Pm, Gc, T1);
   mat3_mul(T1, Qm, T2);
-  mat3_mul(Hprev, T2, T3);
+  mat3_mul(Hbase, T2, T3);
   double d = T3[8];
   double Hn[9];
   int ok = d != 0.0;
@@ -521,6 +580,19 @@ int lo_fit_level(int ntiles, const int32_t* cx, const int32_t* cy, const int32_t
   }
   if (ok) memcpy(Hout, Hn, sizeof(Hn));
   return m;
+}
+
+int lo_fit_level(int ntiles, const int32_t* cx, const int32_t* cy, const int32_t* dx,
+                 const int32_t* dy, const uint8_t* sel, int w, int h,
+                 const double Hprev[9], double Hout[9]) {
+  return fit_level(ntiles, cx, cy, dx, dy, sel, w, h, Hprev, Hprev, Hout);
+}
+
+int lo_fit_level_absolute(int ntiles, const int32_t* cx, const int32_t* cy,
+                          const int32_t* dx, const int32_t* dy, const uint8_t* sel, int w,
+                          int h, const double Hprev[9], double Hout[9]) {
+  static const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  return fit_level(ntiles, cx, cy, dx, dy, sel, w, h, Hprev, I3, Hout);
 }
 
 /* ---------------------------------------------------------------------------
@@ -980,14 +1052,6 @@ int lo_irradiance(int n, int ch, int w, int h, const double* const* imgs,
 }
 
 /* ---------------------------------------------------------------------------
- * One registration (Sec. 2.2 - 2.4): equalise both frames, build the
- * pyramids, then from the coarsest level down: corners on the reference,
- * warp the source level by H^{l+1}, SSD search (radius 10 on coarse levels,
- * radius0 on level 0), weeding, level homography. Level 0's kept matches
- * are propagated to a dense residual flow, and the source is warped
- * backwards through H^1 and that flow.
- * ------------------------------------------------------------------------- */
-/* ---------------------------------------------------------------------------
  * Reference frame of a stack (Sec. 2.1, Sec. 2 opening): the shortest exposure,
  * the lowest index on ties. When the exposures are not known (not every one
  * positive and finite), the darkest frame stands in for the shortest: the
@@ -1016,11 +1080,26 @@ int lo_pick_reference(int n, const float* exposure, const uint8_t* const* ys, in
   return r;
 }
 
+/* ---------------------------------------------------------------------------
+ * One registration (Sec. 2.2 - 2.4): equalise both frames, build the
+ * pyramids, then from the coarsest level down: corners on the reference,
+ * warp the source level by H^{l+1}, SSD search (radius 10 on coarse levels,
+ * radius0 on level 0), weeding, level homography. Level 0's kept matches
+ * are propagated to a dense residual flow, and the source is warped
+ * backwards through H^1 and that flow.
+ * With search_frame 1 (Eq. 3 as printed) no level is warped: each level
+ * searches the unwarped source around round(H^{l+1} x), the level
+ * homography is fitted to those absolute matches directly (H^{l+1} kept when
+ * the fit fails), and level 0's absolute displacements are propagated, so
+ * the source is sampled at x + F(x) without a homography; warped0 is not
+ * written.
+ * ------------------------------------------------------------------------- */
 int lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t* src_u,
                      const uint8_t* src_v, int w, int h, const lo_params* p,
                      const double* H_init, lo_registration* out) {
   if (w < 1 || h < 1) return -1;
   const int L = lo_num_levels(w, h, p);
+  const int literal = p->search_frame == 1;
   out->levels = L;
   int lw[6], lh[6];
   size_t poff[7];
@@ -1057,13 +1136,18 @@ int lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t* 
     lo_corners(pyr_ref + poff[l], lw[l], lh[l], p, out->corner_x + o, out->corner_y + o,
                out->flags + o);
     lo_pixel_homography(out->H + 9 * (l + 1), lw[l], lh[l], Hp);
-    lo_warp_q8(pyr_src + poff[l], lw[l], lh[l], Hp, warped);
+    if (!literal) lo_warp_q8(pyr_src + poff[l], lw[l], lh[l], Hp, warped);
     uint8_t* has = (uint8_t*)malloc((size_t)nt + 1);
     uint8_t* valid = (uint8_t*)malloc((size_t)nt + 1);
     uint8_t* inM = (uint8_t*)calloc((size_t)nt + 1, 1);
     memcpy(has, out->flags + o, (size_t)nt);
-    lo_search(pyr_ref + poff[l], warped, lw[l], lh[l], p, R, out->corner_x + o,
-              out->corner_y + o, has, out->dx + o, out->dy + o, out->ssd + o, valid);
+    if (literal)
+      lo_search_unwarped(pyr_ref + poff[l], pyr_src + poff[l], lw[l], lh[l], p, R, Hp,
+                         out->corner_x + o, out->corner_y + o, has, out->dx + o, out->dy + o,
+                         out->ssd + o, valid);
+    else
+      lo_search(pyr_ref + poff[l], warped, lw[l], lh[l], p, R, out->corner_x + o,
+                out->corner_y + o, has, out->dx + o, out->dy + o, out->ssd + o, valid);
     int32_t bc = -1, bi = -1;
     out->n_valid[l] = lo_weed(nt, out->corner_x + o, out->corner_y + o, out->dx + o,
                               out->dy + o, valid, lw[l], lh[l], l, p, 0, p->weed_iters, inM,
@@ -1072,14 +1156,14 @@ int lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t* 
     if (bc > lo_weed_delta(out->n_valid[l], p))
       lo_hypothesis_inliers(nt, out->corner_x + o, out->corner_y + o, out->dx + o, out->dy + o,
                             valid, lw[l], lh[l], l, p, bi, sel);
-    out->n_inliers[l] = lo_fit_level(nt, out->corner_x + o, out->corner_y + o, out->dx + o,
-                                     out->dy + o, sel, lw[l], lh[l], out->H + 9 * (l + 1),
-                                     out->H + 9 * l);
+    out->n_inliers[l] = (literal ? lo_fit_level_absolute : lo_fit_level)(
+        nt, out->corner_x + o, out->corner_y + o, out->dx + o, out->dy + o, sel, lw[l], lh[l],
+        out->H + 9 * (l + 1), out->H + 9 * l);
     out->best_iter[l] = bi;
     for (int t = 0; t < nt; ++t)
       out->flags[o + t] =
           (uint8_t)((has[t] ? 1 : 0) | (valid[t] ? 2 : 0) | (inM[t] ? 4 : 0) | (sel[t] ? 8 : 0));
-    if (l == 0) memcpy(out->warped0, warped, (size_t)w * h);
+    if (l == 0 && !literal) memcpy(out->warped0, warped, (size_t)w * h);
     free(sel);
     free(has);
     free(valid);
@@ -1093,8 +1177,11 @@ int lo_register_pair(const uint8_t* ref_y, const uint8_t* src_y, const uint8_t* 
     lo_sparse_to_dense(nt, out->corner_x, out->corner_y, out->dx, out->dy, inM, pyr_ref, w, h,
                        p, out->flow_u, out->flow_v, out->ntilde);
     free(inM);
+    /* the absolute flow of the paper-literal search is the whole mapping */
+    static const double I3p[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     double Hp1[9];
-    lo_pixel_homography(out->H + 9, w, h, Hp1);
+    if (literal) memcpy(Hp1, I3p, sizeof(Hp1));
+    else lo_pixel_homography(out->H + 9, w, h, Hp1);
     lo_backward_warp(src_y, src_u, src_v, pyr_src, w, h, Hp1, out->flow_u, out->flow_v,
                      out->rgb, out->yeq_warped);
   }

@@ -43,7 +43,9 @@ typedef struct {
   double n_min;          /* flow defined where filtered N > n_min (Sec. 2.4)  */
   double ssim_sigma;     /* SSIM Gaussian window (Wang et al.)                */
   int32_t ssim_radius;
-  int32_t pad0;
+  int32_t search_frame;  /* 0: search the source warped by H^{l+1}; 1: Eq. 3 as
+                            printed, around round(H^{l+1} x) in the unwarped
+                            source, matches and flow absolute               */
   double ssim_c1, ssim_c2;
   double sigma_e;        /* Mertens well-exposedness sigma                    */
   uint64_t seed;         /* weeding sampler seed                              */
@@ -90,6 +92,14 @@ void lo_warp_q8(const uint8_t* src, int w, int h, const double Hp[9], uint8_t* o
 void lo_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, const lo_params* p,
                int R, const int32_t* cx, const int32_t* cy, const uint8_t* has,
                int32_t* dx, int32_t* dy, uint32_t* ssd, uint8_t* valid);
+/* Sec. 2.2, Eq. 3 as printed: the same search, in the unwarped source around
+ * the predicted position q = round(Hp x) of each corner (Hp: the previous
+ * level's pixel homography); dx, dy receive the absolute displacement
+ * q + d - x, the tie order applies to d */
+void lo_search_unwarped(const uint8_t* ref, const uint8_t* src, int w, int h,
+                        const lo_params* p, int R, const double Hp[9], const int32_t* cx,
+                        const int32_t* cy, const uint8_t* has, int32_t* dx, int32_t* dy,
+                        uint32_t* ssd, uint8_t* valid);
 /* Sec. 2.3, Eq. 5: union-of-inliers filter over iterations [it0, it1).
  * inM is OR-ed (not cleared), so chunks can be merged by repeated calls.
  * best_count / best_iter: the largest inlier count and its iteration (lowest
@@ -113,6 +123,11 @@ int  lo_fit4(const double sx[4], const double sy[4], const double tx[4],
 int  lo_fit_level(int ntiles, const int32_t* cx, const int32_t* cy, const int32_t* dx,
                   const int32_t* dy, const uint8_t* sel, int w, int h,
                   const double Hprev[9], double Hout[9]);
+/* the same fit when the matches are absolute (paper-literal search): the
+ * level homography is the fitted map itself; Hprev is kept on failure */
+int  lo_fit_level_absolute(int ntiles, const int32_t* cx, const int32_t* cy,
+                           const int32_t* dx, const int32_t* dy, const uint8_t* sel, int w,
+                           int h, const double Hprev[9], double Hout[9]);
 /* Sec. 2.4, Eq. 6-7: edge-aware sparse-to-dense flow */
 void lo_sparse_to_dense(int ntiles, const int32_t* cx, const int32_t* cy, const int32_t* dx,
                         const int32_t* dy, const uint8_t* inM, const uint8_t* guide,

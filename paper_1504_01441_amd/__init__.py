@@ -47,7 +47,7 @@ class Params(C.Structure):
         ("weed_delta_min", C.c_int32), ("weed_delta_pct", C.c_int32), ("dt_iters", C.c_int32),
         ("weed_eps", C.c_double), ("sigma_s", C.c_double), ("sigma_r", C.c_double),
         ("n_min", C.c_double), ("ssim_sigma", C.c_double), ("ssim_radius", C.c_int32),
-        ("reserved0", C.c_int32), ("ssim_c1", C.c_double), ("ssim_c2", C.c_double),
+        ("search_frame", C.c_int32), ("ssim_c1", C.c_double), ("ssim_c2", C.c_double),
         ("sigma_e", C.c_double), ("seed", C.c_uint64),
         ("learned", C.c_int32), ("window_r", C.c_int32), ("conf_min", C.c_double),
     ]

@@ -146,6 +146,8 @@ lnr_status check_params(lnr_ctx* ctx, const lnr_params* p) {
     return fail(ctx, LNR_E_UNSUPPORTED, "SSIM window out of range");
   if (!(p->sigma_e > 0)) return fail(ctx, LNR_E_UNSUPPORTED, "sigma_e must be > 0");
   if (p->learned != 0 && p->learned != 1) return fail(ctx, LNR_E_UNSUPPORTED, "learned must be 0 or 1");
+  if (p->search_frame != 0)
+    return fail(ctx, LNR_E_UNSUPPORTED, "search_frame 1 (the unwarped-source search) is not built");
   if (p->learned) {
     if (p->tile != 32) return fail(ctx, LNR_E_UNSUPPORTED, "the learned proposal needs tile 32");
     if (p->window_r < 0 || p->window_r > p->radius0)

@@ -41,8 +41,6 @@ def test_every_declared_symbol_is_exported(lnr):
 def test_defaults_agree_with_oracle(lnr):
     p, op = lnr.Params(), oracle.params()
     for name, _ in op._fields_:
-        if name in ("pad0",):
-            continue
         assert getattr(p, name) == getattr(op, name), name
 
 
