@@ -155,6 +155,23 @@ lnr_status lnr_query_sizes(int32_t width, int32_t height, int32_t format,
 lnr_status lnr_register_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
                              const lnr_params* p, lnr_registration* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lnr_register_pair
+ * with the same arguments, results and kernels, but its scratch (pyramids,
+ * warped level, weeding buffers, propagation maps, network inputs) comes from
+ * a fixed device array of LNR_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, instead of the context's
+ * workspace. It calls no allocating routine and never grows anything: a job
+ * that needs more scratch (a 5 MP pair needs about 85 MB; much larger frames do
+ * not fit) returns LNR_E_NOMEM before any launch. Every call on one GPU,
+ * from any context, uses that GPU's one array, so such calls must not
+ * overlap in time (calls on different streams race); the kernels clear what
+ * must start at zero, so a call does not depend on the previous contents.
+ * Tracing (lnr_trace_enable) does not apply to it. */
+#define LNR_NOALLOC_SCRATCH_BYTES ((uint64_t)96 << 20)
+lnr_status lnr_register_pair_noalloc(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                                     const lnr_params* p, lnr_registration* out, void* stream);
+
 /* Register an n-frame stack (paper Sec. 2: n - 1 registrations): the
  * reference is the frame with the smallest exposure (Sec. 2.1; lowest index
  * on ties), written to *ref_index; outs[k] receives the registration of the

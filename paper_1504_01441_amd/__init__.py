@@ -104,6 +104,8 @@ def lib():
         L.lnr_query_sizes.argtypes = [i32, i32, i32, C.POINTER(Params), C.POINTER(_Sizes)]
         L.lnr_register_pair.argtypes = [vp, C.POINTER(_Frame), C.POINTER(_Frame),
                                         C.POINTER(Params), C.POINTER(_Registration), vp]
+        L.lnr_register_pair_noalloc.argtypes = [vp, C.POINTER(_Frame), C.POINTER(_Frame),
+                                                C.POINTER(Params), C.POINTER(_Registration), vp]
         L.lnr_register_stack.argtypes = [vp, C.POINTER(_Frame), i32, C.POINTER(Params),
                                          C.POINTER(_Registration), C.POINTER(i32), vp]
         L.lnr_merge.argtypes = [vp, C.POINTER(_Frame), i32, i32, C.POINTER(_Registration),
@@ -143,7 +145,7 @@ def lib():
         L.lnr_trace_enable.argtypes = [vp, i32]
         L.lnr_trace_read.argtypes = [vp, C.POINTER(_TraceEntry), i32]
         for name in ("lnr_trace_enable", "lnr_trace_read", "lnr_create", "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack",
-                     "lnr_merge", "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
+                     "lnr_register_pair_noalloc", "lnr_merge", "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
                      "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
                      "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
@@ -165,7 +167,8 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
             "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search",
             "lnr_proposal_save", "lnr_proposal_load", "lnr_merge_irradiance",
-            "lnr_stage_irradiance", "lnr_meter", "lnr_set_flow_shape", "lnr_flow_shapes")
+            "lnr_stage_irradiance", "lnr_meter", "lnr_set_flow_shape", "lnr_flow_shapes",
+            "lnr_register_pair_noalloc")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -328,6 +331,21 @@ def register_pair(ctx: Context, ref: Frame, src: Frame, params: Params | None = 
     rf, sf, rr = ref._c(), src._c(), out._c()
     ctx.check(lib().lnr_register_pair(ctx._h, C.byref(rf), C.byref(sf), C.byref(p),
                                       C.byref(rr), _stream()))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 96 << 20
+
+
+def register_pair_noalloc(ctx: Context, ref: Frame, src: Frame, params: Params | None = None,
+                          out: Registration | None = None) -> Registration:
+    """register_pair on the library's fixed device scratch (no allocation by
+    the library; `out` is the caller's); calls on one GPU must not overlap."""
+    p = params or Params()
+    out = out or Registration.alloc(ref.width, ref.height, ref.fmt, p, ref.y.device)
+    rf, sf, rr = ref._c(), src._c(), out._c()
+    ctx.check(lib().lnr_register_pair_noalloc(ctx._h, C.byref(rf), C.byref(sf), C.byref(p),
+                                              C.byref(rr), _stream()))
     return out
 
 

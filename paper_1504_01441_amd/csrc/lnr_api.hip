@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -76,6 +77,10 @@ struct lnr_ctx {
   std::string err;
   void* ws = nullptr;
   size_t ws_size = 0;
+  // this device's copy of the fixed scratch of lnr_register_pair_noalloc
+  // (null when its address could not be obtained; scratch_err says why)
+  void* scratch = nullptr;
+  std::string scratch_err;
   bool tracing = false;
   lnr::Tracer tracer;
   // learned proposal: fp32 parameters, AdamW moments, packed bf16 weights
@@ -273,6 +278,35 @@ lnr_status ensure_ws(lnr_ctx* ctx, size_t bytes, hipStream_t st) {
   }
   ctx->ws_size = want;
   return LNR_OK;
+}
+
+// Fixed scratch of lnr_register_pair_noalloc: one copy on every GPU the
+// library runs on, held until the process ends. On the host this name only
+// identifies the symbol; its device address comes from hipGetSymbolAddress,
+// taken once per device (lnr_create) and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[LNR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Called with `device` current.
+void bind_scratch(lnr_ctx* c, int device) {
+  if (device >= kMaxDevices) {
+    c->scratch_err = "device index beyond the scratch table";
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      c->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  c->scratch = g_scratch_ptr[device];
 }
 
 struct WeedPlan {
@@ -486,6 +520,11 @@ lnr_status lnr_create(lnr_ctx** ctx, int32_t device) {
   lnr_ctx* c = new (std::nothrow) lnr_ctx();
   if (!c) return LNR_E_NOMEM;
   c->device = device;
+  int prev = 0;
+  const bool have_prev = hipGetDevice(&prev) == hipSuccess;
+  if (hipSetDevice(device) == hipSuccess) bind_scratch(c, device);
+  else c->scratch_err = "hipSetDevice failed in lnr_create";
+  if (have_prev) (void)hipSetDevice(prev);
   *ctx = c;
   return LNR_OK;
 }
@@ -567,6 +606,24 @@ lnr_status lnr_register_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame
   TraceGuard tg(ctx);
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   return register_pair_impl(ctx, ref, src, p, out, (hipStream_t)stream);
+}
+
+lnr_status lnr_register_pair_noalloc(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                                     const lnr_params* p, lnr_registration* out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(nullptr);  // tracing would create events
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  lnr_status s;
+  if ((s = check_pair(ctx, ref, src, p, out)) != LNR_OK) return s;
+  if (!ctx->scratch) return fail(ctx, LNR_E_HIP, "no scratch on this device: " + ctx->scratch_err);
+  const PairPlan q = plan_pair(ref->width, ref->height, p);
+  if (q.bytes > (size_t)LNR_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, LNR_E_NOMEM,
+                "the registration needs " + std::to_string(q.bytes) +
+                    " bytes of scratch; the fixed scratch holds " +
+                    std::to_string((size_t)LNR_NOALLOC_SCRATCH_BYTES));
+  return enqueue_pair(ctx, ref, src, p, out, q, static_cast<char*>(ctx->scratch),
+                      (hipStream_t)stream);
 }
 
 lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
