@@ -10,11 +10,18 @@ warp) followed by the deghosted merge. `value` = W*H / step time.
 Besides the JSON line's throughput, the run
   * times every kernel with HIP events on its launch stream over a second,
     traced pass of the same K steps (the library's lnr_trace_* calls), and
-    reports the dominant kernel against its roofline;
-  * runs the CPU oracle once on the same pair (single thread): its time is
-    `cpu_baseline`, and its tiles give the % of tiles equal to the oracle.
+    reports the kernel with the largest time per step against its roofline
+    (`roofline`; every modelled kernel in `rooflines`);
+  * runs the CPU oracle on the same pair on every host core (one pair per
+    process, started before the GPU is touched): the aggregate rate is
+    `cpu_baseline`, and the oracle's tiles give the % of tiles equal to it;
+  * reports the mean end-point error of the final mapping against the
+    generator's ground truth, for the plain and the learned method.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       [--only-step] [--dt-shape a,b,c,d,e]
+(--only-step: the timed and traced steps only, for profiler runs; --dt-shape:
+pin the propagation kernel shape instead of autotuning it.)
 """
 import argparse
 import json
@@ -27,6 +34,75 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes x 2.4 GHz, 1 op/lane/clk
+# one v_dot4_u32_u8 lane-instruction forms four byte products
+DOT4_PEAK_TPS = 4 * INT_PEAK_TOPS
+MAX_CPU_WORKERS = 16           # the host share of one GPU
+
+
+def search_products(flags, tile_off, levels, radius0, radius_coarse, patch_r):
+    """Pixel-candidate products of the exhaustive search of one pair, per
+    level: cornered tiles x (2R + 1)^2 candidates x (2P + 1)^2 pixels."""
+    out = []
+    for l in range(levels):
+        c = int((flags[tile_off[l]:tile_off[l + 1]] & 1).sum())
+        R = radius0 if l == 0 else radius_coarse
+        out.append(c * (2 * R + 1) ** 2 * (2 * patch_r + 1) ** 2)
+    return out
+
+
+def mean_epe(H1, flow, gt):
+    """Mean distance between the final sample position Hp1(x + F(x)) and the
+    generator's ground truth (planted homography and tile shifts), over
+    pixels at least one tile from the border."""
+    import numpy as np
+    h, w = flow.shape[1:]
+    B = np.array([[w, 0, w - 1], [0, w, h - 1], [0, 0, 2]], np.float64)
+    Cm = np.array([[2, 0, -(w - 1)], [0, 2, -(h - 1)], [0, 0, w]], np.float64)
+    Hp = B @ (H1.reshape(3, 3) @ Cm)
+    ys, xs = np.mgrid[32:h - 32, 32:w - 32].astype(np.float64)
+    X = xs + flow[0, 32:h - 32, 32:w - 32]
+    Y = ys + flow[1, 32:h - 32, 32:w - 32]
+    den = Hp[2, 0] * X + Hp[2, 1] * Y + Hp[2, 2]
+    mx = (Hp[0, 0] * X + Hp[0, 1] * Y + Hp[0, 2]) / den
+    my = (Hp[1, 0] * X + Hp[1, 1] * Y + Hp[1, 2]) / den
+    gx, gy = gt
+    return float(np.mean(np.hypot(mx - gx[32:h - 32, 32:w - 32], my - gy[32:h - 32, 32:w - 32])))
+
+
+def _oracle_job(job):
+    """One oracle registration + merge of the pair (runs in a child process)."""
+    f0, f1, radius0 = job
+    import oracle
+    op = oracle.params(radius0=radius0)
+    t0 = time.time()
+    o = oracle.register_pair(f0, f1, op)
+    ref_rgb = oracle.frame_to_rgb(f0.y, f0.u, f0.v)
+    oracle.merge([ref_rgb, o["rgb"]], [o["yeq_ref"] / 255.0, o["yeq_warped"]], 0, op)
+    return t0, time.time(), o["flags"], o["dx"], o["dy"]
+
+
+def cpu_baseline(f0, f1, radius0):
+    """The oracle on every host core: one copy of the pair per process, all
+    started together; rate = copies x pixels / (last end - first start).
+    Runs before the GPU is touched (children are spawned, not forked)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, MAX_CPU_WORKERS))
+    with cf.ProcessPoolExecutor(cores, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(abs, range(cores)))        # start the workers first
+        res = list(ex.map(_oracle_job, [(f0, f1, radius0)] * cores))
+    t0 = min(r[0] for r in res)
+    t1 = max(r[1] for r in res)
+    mpix = f0.width * f0.height / 1e6
+    return {"value": round(cores * mpix / (t1 - t0), 4), "unit": "MPix/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{cores} copies of the full {f0.width}x{f0.height} pair (registration + "
+                      f"merge), one per process on {cores} cores, {t1 - t0:.1f} s wall; "
+                      f"single copy {min(r[1] - r[0] for r in res):.1f} s"}, res[0][2:]
 
 
 def kernel_key(name):
@@ -119,6 +195,12 @@ def main():
                          "sweep: registration time from VGA to 12 MP; flow-widths: the "
                          "propagation passes at height 1944 and widths 512..4096")
     ap.add_argument("--pairs", type=int, default=64, help="pairs of the c4 batch")
+    ap.add_argument("--only-step", action="store_true",
+                    help="time and trace the steps only (no learned step, irradiance map, "
+                         "search-only pass, metering or oracle): for profiler runs")
+    ap.add_argument("--dt-shape", default=None,
+                    help="pin the propagation kernel shape (five integers, as reported in "
+                         "autotuned_dt_shape) instead of autotuning it")
     ap.add_argument("--calib-copy", action="store_true",
                     help="one 256 MiB device-to-device copy before the steps (the reference "
                          "transfer for scaling HBM byte counters)")
@@ -150,6 +232,12 @@ def main():
     W, H = f0.width, f0.height
     print(f"[bench] generated 2592x1944 pair in {time.time() - t_gen:.1f}s", file=sys.stderr,
           flush=True)
+    cpu = None
+    if not args.no_cpu_baseline and not args.only_step:
+        t_cpu = time.time()
+        cpu = cpu_baseline(f0, f1, st.meta["radius0"])
+        print(f"[bench] oracle on {cpu[0]['cores']} cores in {time.time() - t_cpu:.1f}s",
+              file=sys.stderr, flush=True)
     ctx = lnr.Context(0)
     p = lnr.Params(radius0=st.meta["radius0"])
     ref = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
@@ -159,7 +247,11 @@ def main():
 
     # the library's autotuners pick the propagation kernel shape and the
     # search's workgroup shape per level for this size
-    dt_shape = lnr.autotune_flow(ctx, W, H, p)
+    if args.dt_shape:
+        dt_shape = tuple(int(v) for v in args.dt_shape.split(","))
+        lnr.set_flow_shape(ctx, W, H, dt_shape)
+    else:
+        dt_shape = lnr.autotune_flow(ctx, W, H, p)
     search_split = lnr.autotune_search(ctx, W, H, p)
 
     def step():
@@ -222,31 +314,47 @@ def main():
             hbm[base] = {"ms": round(ms, 4), "launches": round(cnt, 2),
                          "algo_bytes": int(model[base]), "gbs": round(gbs, 1),
                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    roof = None
-    dom = max(by_base.items(), key=lambda kv: kv[1][1])[0] if by_base else None
-    # the dominant kernel with a bandwidth model (the search is reported apart)
-    cands = sorted(hbm.items(), key=lambda kv: -kv[1]["ms"])
-    if cands:
-        base, h = cands[0]
-        avg_s = by_base[base][1] / by_base[base][0] / 1e3
-        per_launch = h["algo_bytes"] / by_base[base][0]
-        roof = {"kernel": base, "bound": "hbm", "achieved": h["gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": h["frac"], "traffic": measured_traffic(base),
-                "avg_launch_us": round(avg_s * 1e6, 2),
-                "algo_bytes_per_launch": int(per_launch),
-                "dominant_overall": dom}
-    # level-0 search against the int-VALU peak (pixel-candidate operations)
-    out_reg = reg
+    # the search is priced in pixel-candidate products (dot4 peak) per level
     torch.cuda.synchronize()
-    flags0 = out_reg.flags.cpu().numpy()[: reg.tile_off[1]]
-    ncorner = int((flags0 & 1).sum())
-    search_ops = ncorner * (2 * 16 + 1) ** 2 * 21 * 21
+    flags_all = reg.flags.cpu().numpy()
+    prods = search_products(flags_all, reg.tile_off, reg.levels, p.radius0, p.radius_coarse,
+                            p.patch_r)
+    search_ops = prods[0]
+    rooflines = {}
+    for base, h in hbm.items():
+        cnt = by_base[base][0]
+        rooflines[base] = {"kernel": base, "bound": "hbm", "achieved": h["gbs"],
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": h["frac"],
+                           "traffic": measured_traffic(base),
+                           "avg_launch_us": round(by_base[base][1] / cnt * 1e3, 2),
+                           "algo_bytes_per_launch": int(h["algo_bytes"] / cnt),
+                           "ms_per_step": h["ms"], "launches_per_step": round(cnt, 2)}
+    if "k_search" in by_base:
+        cnt, ms = by_base["k_search"]
+        ach = sum(prods) / (ms / 1e3) / 1e12
+        rooflines["k_search"] = {
+            "kernel": "k_search", "bound": "alu", "achieved": round(ach, 2),
+            "peak": round(DOT4_PEAK_TPS, 2), "unit": "T pixel-candidate products/s (v_dot4)",
+            "frac": round(ach / DOT4_PEAK_TPS, 4), "traffic": None,
+            "avg_launch_us": round(ms / cnt * 1e3, 2),
+            "products_per_launch": int(sum(prods) / cnt), "ms_per_step": round(ms, 4),
+            "launches_per_step": round(cnt, 2), "products_per_level": prods}
+    # the kernel with the largest time per step (all its launches)
+    dom = max(by_base.items(), key=lambda kv: kv[1][1])[0] if by_base else None
+    if dom in rooflines:
+        roof = dict(rooflines[dom])
+    else:
+        best = max(rooflines.values(), key=lambda r: r["ms_per_step"]) if rooflines else None
+        roof = None if best is None else dict(best, dominant_overall=dom)
+
+    gt = st.gt_map(1)
+    epe_plain = mean_epe(reg.H[1].cpu().numpy(), reg.flow.cpu().numpy().astype(np.float64), gt)
 
     # learned proposal: the same step with the level-0 search narrowed by the
     # network trained on the GPU (paper_1504_01441_amd.proposal)
     learned = None
     from paper_1504_01441_amd import proposal as prop
-    if os.path.exists(prop.DEFAULT_WEIGHTS):
+    if os.path.exists(prop.DEFAULT_WEIGHTS) and not args.only_step:
         P_net, conf_min = prop.load()
         lnr.proposal_set(ctx, torch.from_numpy(P_net))
         pq = lnr.Params(radius0=st.meta["radius0"], learned=1, window_r=2, conf_min=conf_min)
@@ -283,7 +391,31 @@ def main():
                    "conf_min": round(conf_min, 6),
                    "tiles_in_window_pct": round(100.0 * window.sum() / max(cornered.sum(), 1), 2),
                    "ssd_candidates_vs_plain": round(cand / max(int(cornered.sum()) * full, 1), 4),
+                   "mean_epe_px": round(mean_epe(reg_l.H[1].cpu().numpy(),
+                                                 reg_l.flow.cpu().numpy().astype(np.float64),
+                                                 gt), 4),
                    "_flags": fl, "_disp": reg_l.disp.cpu().numpy()[:n0]}
+
+    # the paper-literal search frame (Eq. 3 as printed): the same pair
+    # registered with every level searching the unwarped source around its
+    # prediction and the absolute flow propagated
+    literal = None
+    if not args.only_step:
+        pt = lnr.Params(radius0=st.meta["radius0"], search_frame=1)
+        reg_t = lnr.Registration.alloc(W, H, lnr.LNR_I420, pt)
+        for _ in range(args.warmup):
+            lnr.register_pair(ctx, ref, src, pt, out=reg_t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lnr.register_pair(ctx, ref, src, pt, out=reg_t)
+        torch.cuda.synchronize()
+        ms_t = (time.perf_counter() - t0) / args.steps * 1e3
+        eye = np.eye(3).reshape(9)
+        literal = {"registration_only": {"ms": round(ms_t, 4),
+                                         "mpix_s": round(mpix / (ms_t / 1e3), 2)},
+                   "mean_epe_px": round(mean_epe(eye, reg_t.flow.cpu().numpy().astype(np.float64),
+                                                 gt), 4)}
 
     result = {
         "metric": "registered MPix/s on 5MP pairs, plain vs learned-proposal; % tiles = oracle",
@@ -303,21 +435,27 @@ def main():
                                "+ merge",
                    "width": W, "height": H, "seed": args.seed},
         "registration_only": {"ms": round(ms_reg, 4), "mpix_s": round(mpix / (ms_reg / 1e3), 2)},
+        "mean_epe_px": round(epe_plain, 4),
         "autotuned_dt_shape": {"row_seg": dt_shape[0], "row_block": dt_shape[1],
                                "col_rows": dt_shape[2], "col_cols": dt_shape[3],
                                "col_segments": dt_shape[4]},
         "autotuned_search_split_per_level": list(search_split),
+        "paper_literal_search": literal,
         "learned_proposal": None if learned is None else
         {k: v for k, v in learned.items() if not k.startswith("_")},
         "roofline": roof,
+        "rooflines": rooflines,
         "search_level0": {"pixel_candidate_ops": search_ops,
                           "int_peak_tops": round(INT_PEAK_TOPS, 2)},
         "kernels_ms_per_step": {k: round(v[1], 4) for k, v in kernels},
         "hbm_kernels": hbm,
     }
-    if "k_search" in per_step:
+    if "k_search" in by_base:
         # all five levels' searches; the level-0 share dominates
-        result["search_level0"]["ms_all_levels"] = round(per_step["k_search"][1], 4)
+        result["search_level0"]["ms_all_levels"] = round(by_base["k_search"][1], 4)
+    if args.only_step:
+        print(json.dumps(result))
+        return
 
     # the irradiance map of the registered pair (the alternative output to
     # the fusion): SSIM of the warped frame plus one pass over both frames
@@ -361,12 +499,16 @@ def main():
     for _ in range(args.steps):
         lnr.stage_search(ctx, yq, wq, R0, p)
     torch.cuda.synchronize()
-    trs = ctx.trace_read()
+    trs = {}
+    for k, (c_, ms_) in ctx.trace_read().items():
+        b_ = kernel_key(k)[0]
+        c0, m0 = trs.get(b_, (0, 0.0))
+        trs[b_] = (c0 + c_, m0 + ms_)
     ctx.trace(False)
     if "k_search" in trs:
         c_s, ms_s = trs["k_search"]
         t_l0 = ms_s / c_s / 1e3
-        peak_pc = 4 * INT_PEAK_TOPS
+        peak_pc = DOT4_PEAK_TPS
         ach = search_ops / t_l0 / 1e12
         result["search_roofline"] = {
             "kernel": "k_search (level 0)", "bound": "alu", "achieved": round(ach, 2),
@@ -384,27 +526,17 @@ def main():
     result["metering"] = {"ms_with_readback": round(ms_meter, 4), "stops": stops[0],
                           "under_exposed": stops[1]}
 
-    if not args.no_cpu_baseline:
-        import oracle
-        op = oracle.params(radius0=st.meta["radius0"])
-        t0 = time.perf_counter()
-        o = oracle.register_pair(f0, f1, op)
-        ref_rgb = oracle.frame_to_rgb(f0.y, f0.u, f0.v)
-        oracle.merge([ref_rgb, o["rgb"]], [o["yeq_ref"] / 255.0, o["yeq_warped"]], 0, op)
-        secs = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": round(mpix / secs, 4), "unit": "MPix/s", "cores": 1,
-                                  "kind": "oracle",
-                                  "sample": "one full 2592x1944 pair (registration + merge), "
-                                            f"{secs:.1f} s single-threaded"}
-        T = len(o["flags"])
+    if cpu is not None:
+        result["cpu_baseline"] = cpu[0]
+        oflags, odx, ody = cpu[1]
+        T = len(oflags)
         g = {"flags": reg.flags.cpu().numpy()[:T], "disp": reg.disp.cpu().numpy()[:T]}
-        same = (g["flags"] == o["flags"]) & (g["disp"][:, 0] == o["dx"]) & \
-               (g["disp"][:, 1] == o["dy"])
+        same = (g["flags"] == oflags) & (g["disp"][:, 0] == odx) & (g["disp"][:, 1] == ody)
         result["tiles_equal_oracle_pct"] = round(100.0 * same.mean(), 3)
         if learned is not None:
             n0 = len(learned["_flags"])
-            sl = ((learned["_flags"] & 3) == (o["flags"][:n0] & 3)) & \
-                 (learned["_disp"][:, 0] == o["dx"][:n0]) & (learned["_disp"][:, 1] == o["dy"][:n0])
+            sl = ((learned["_flags"] & 3) == (oflags[:n0] & 3)) & \
+                 (learned["_disp"][:, 0] == odx[:n0]) & (learned["_disp"][:, 1] == ody[:n0])
             result["learned_proposal"]["tiles_equal_oracle_pct"] = round(100.0 * sl.mean(), 3)
     print(json.dumps(result))
 

@@ -85,9 +85,13 @@ typedef struct {
   double ssim_sigma;       /* SSIM Gaussian window sigma                         */
   int32_t ssim_radius;     /* SSIM window radius, 1..8                          */
   int32_t search_frame;    /* 0: each level searches the source warped by the
-                              previous level's homography; 1 (Eq. 3 as
-                              printed, the unwarped source around round(H x))
-                              is rejected with LNR_E_UNSUPPORTED for now   */
+                              previous level's homography; 1: Eq. 3 as
+                              printed: each level searches the unwarped
+                              source around round(Hp x), fits its
+                              homography to those absolute matches, and the
+                              absolute level-0 flow is propagated (the
+                              source is sampled at x + F(x); warped0 is not
+                              written). 1 with learned = 1 is rejected   */
   double ssim_c1, ssim_c2; /* SSIM stabilisers                                   */
   double sigma_e;          /* Mertens well-exposedness sigma                     */
   uint64_t seed;           /* weeding sampler seed                               */
@@ -325,6 +329,21 @@ lnr_status lnr_proposal_get(lnr_ctx* ctx, float* params, void* stream);
  * lnr_proposal_set does; it waits for the host-to-device copy. */
 lnr_status lnr_proposal_save(lnr_ctx* ctx, const char* path, void* stream);
 lnr_status lnr_proposal_load(lnr_ctx* ctx, const char* path, void* stream);
+/* Training checkpoint (host path; little-endian): "LNRK", uint32 version 1,
+ * uint32 parameter count, uint32 AdamW step count, uint64 `counter`, then the
+ * fp32 parameters, first moments and second moments (each in the order
+ * above). `counter` is the caller's position in its data order (the training
+ * pipeline stores its global step), returned by the load, so that training
+ * resumed from a checkpoint repeats the uninterrupted run bit for bit.
+ * Save: LNR_E_ARG without a network, LNR_E_WEIGHTS when the file cannot be
+ * written; waits for `stream`. Load: header, size, finite values and
+ * non-negative second moments are checked (LNR_E_WEIGHTS otherwise, before
+ * the context's network is touched); then parameters, moments and step count
+ * replace the context's; waits for the copy. */
+lnr_status lnr_proposal_checkpoint_save(lnr_ctx* ctx, const char* path, uint64_t counter,
+                                        void* stream);
+lnr_status lnr_proposal_checkpoint_load(lnr_ctx* ctx, const char* path, uint64_t* counter,
+                                        void* stream);
 /* Network inputs of every full 32 x 32 tile of two dense [h][w] 8-bit
  * images (raster tile order): x[ntiles][2][16][16], bf16 bit patterns. */
 lnr_status lnr_proposal_inputs(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,

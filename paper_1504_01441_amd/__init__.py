@@ -132,6 +132,8 @@ def lib():
         L.lnr_proposal_get.argtypes = [vp, vp, vp]
         L.lnr_proposal_save.argtypes = [vp, C.c_char_p, vp]
         L.lnr_proposal_load.argtypes = [vp, C.c_char_p, vp]
+        L.lnr_proposal_checkpoint_save.argtypes = [vp, C.c_char_p, C.c_uint64, vp]
+        L.lnr_proposal_checkpoint_load.argtypes = [vp, C.c_char_p, C.POINTER(C.c_uint64), vp]
         L.lnr_proposal_inputs.argtypes = [vp, vp, vp, i32, i32, vp, vp]
         L.lnr_proposal_forward.argtypes = [vp, vp, i32, vp, vp]
         L.lnr_proposal_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.c_float, vp, vp, vp]
@@ -145,7 +147,8 @@ def lib():
         L.lnr_trace_enable.argtypes = [vp, i32]
         L.lnr_trace_read.argtypes = [vp, C.POINTER(_TraceEntry), i32]
         for name in ("lnr_trace_enable", "lnr_trace_read", "lnr_create", "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack",
-                     "lnr_register_pair_noalloc", "lnr_merge", "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
+                     "lnr_register_pair_noalloc", "lnr_merge",
+                     "lnr_proposal_checkpoint_save", "lnr_proposal_checkpoint_load", "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
                      "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
                      "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
@@ -168,7 +171,8 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search",
             "lnr_proposal_save", "lnr_proposal_load", "lnr_merge_irradiance",
             "lnr_stage_irradiance", "lnr_meter", "lnr_set_flow_shape", "lnr_flow_shapes",
-            "lnr_register_pair_noalloc")
+            "lnr_register_pair_noalloc", "lnr_proposal_checkpoint_save",
+            "lnr_proposal_checkpoint_load")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -546,6 +550,21 @@ def proposal_save(ctx, path: str):
 def proposal_load(ctx, path: str):
     """Load a network file written by proposal_save and reset AdamW."""
     ctx.check(lib().lnr_proposal_load(ctx._h, os.fsencode(path), _stream()))
+
+
+def proposal_checkpoint_save(ctx, path: str, counter: int):
+    """Write parameters, AdamW moments and step count, and `counter` (the
+    caller's data-order position) to a checkpoint file."""
+    ctx.check(lib().lnr_proposal_checkpoint_save(ctx._h, os.fsencode(path), int(counter),
+                                                 _stream()))
+
+
+def proposal_checkpoint_load(ctx, path: str) -> int:
+    """Restore a checkpoint written by proposal_checkpoint_save; returns its counter."""
+    c = C.c_uint64(0)
+    ctx.check(lib().lnr_proposal_checkpoint_load(ctx._h, os.fsencode(path), C.byref(c),
+                                                 _stream()))
+    return int(c.value)
 
 
 def proposal_inputs(ctx, ref: torch.Tensor, warped: torch.Tensor) -> torch.Tensor:

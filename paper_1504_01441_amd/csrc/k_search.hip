@@ -25,6 +25,10 @@
 //  4. The argmin key (ssd << 32 | (|dx|+|dy|) << 16 | (dy+R) << 8 | (dx+R)) is
 //     reduced with wave shuffles and LDS; equal keys cannot occur, so the
 //     result does not depend on the reduction order.
+// With `Hlit` (Eq. 3 taken literally) the window is the unwarped source
+// around q = round(Hp x) for the tile's corner x, Hp the pixel homography of
+// the previous level; ties are ordered on the offset from q and the result
+// is the absolute displacement q + d - x.
 #include "lnr_device.h"
 #include "lnr_internal.h"
 
@@ -132,6 +136,15 @@ struct SearchShape {
   int rs, off_hsum, off_win;
 };
 
+// nearest integer of a predicted source coordinate (half up), clamped far
+// outside any image (NaN too)
+__device__ inline int round_pred(double s) {
+  double q = floor(s + 0.5);
+  if (!(q > -1048576.0)) q = -1048576.0;
+  if (q > 1048576.0) q = 1048576.0;
+  return (int)q;
+}
+
 __device__ inline unsigned long long wave_min_u64(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -150,7 +163,8 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
                                                  uint8_t* __restrict__ flags,
                                                  const int32_t* __restrict__ centre,
                                                  const uint8_t* __restrict__ mode, int want,
-                                                 unsigned long long* __restrict__ vb) {
+                                                 unsigned long long* __restrict__ vb,
+                                                 const double* __restrict__ Hlit) {
   extern __shared__ __align__(16) uint8_t dyn[];
   uint8_t* reg = dyn;
   uint32_t* hsum = reinterpret_cast<uint32_t*>(dyn + sh.off_hsum);
@@ -164,7 +178,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   const int tile = blockIdx.x;
   // with a proposal, each tile is searched by the launch of its mode only
   if (mode && mode[tile] != want) return;
-  const int cdx = centre ? centre[2 * tile] : 0, cdy = centre ? centre[2 * tile + 1] : 0;
+  int cdx = centre ? centre[2 * tile] : 0, cdy = centre ? centre[2 * tile + 1] : 0;
   const int tx = tile % ntx, ty = tile / ntx;
   const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
   const int side = 2 * ext + 1;
@@ -241,6 +255,16 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
   const int ba = bci % nc1 - c.K, bb = bci / nc1 - c.K;
   const int px = cx0 + c.g * ba, py = cy0 + c.g * bb;  // corner, level coordinates
   const int prx = ext + c.g * ba, pry = ext + c.g * bb;  // corner, region coordinates
+  if (Hlit) {  // every thread predicts the corner's source position itself
+    double hp[9];
+    pixel_homography(Hlit, w, h, hp);
+    const double X = (double)px, Y = (double)py;
+    const double den = (hp[6] * X + hp[7] * Y) + hp[8];
+    const double sx = ((hp[0] * X + hp[1] * Y) + hp[2]) / den;
+    const double sy = ((hp[3] * X + hp[4] * Y) + hp[5]) / den;
+    cdx = round_pred(sx) - px;
+    cdy = round_pred(sy) - py;
+  }
 
   // 2. packed reference patch and the warped window ------------------------
   const int P = c.P, PW = 2 * P + 1, R = sh.R;
@@ -358,12 +382,15 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       if (px + dx - P < 0 || px + dx + P > w - 1 || py + dy - P < 0 || py + dy + P > h - 1)
         continue;
       const uint32_t ssd = er + ew[k] - 2u * acc[k];
-      const uint32_t l1 = (uint32_t)((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy));
+      // ties on the absolute displacement, or on the offset from the
+      // predicted position when the window is centred on a prediction
+      const int kx = Hlit ? dxi - R : dx, ky = Hlit ? j - R : dy;
+      const uint32_t l1 = (uint32_t)((kx < 0 ? -kx : kx) + (ky < 0 ? -ky : ky));
       // (ssd, |dx| + |dy|, dy, dx), displacements biased by 64 (|d| <= 64)
       const unsigned long long kk = ((unsigned long long)ssd << 32) |
                                     ((unsigned long long)l1 << 16) |
-                                    ((unsigned long long)(dy + 64) << 8) |
-                                    (unsigned long long)(dx + 64);
+                                    ((unsigned long long)(ky + 64) << 8) |
+                                    (unsigned long long)(kx + 64);
       key = kk < key ? kk : key;
     }
   }
@@ -382,8 +409,8 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       ssd_out[tile] = 0;
       flags[tile] = (uint8_t)(1 | (mode && want ? 16 : 0));
     } else {
-      disp[2 * tile] = (int)(b & 255ull) - 64;
-      disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - 64;
+      disp[2 * tile] = (int)(b & 255ull) - 64 + (Hlit ? cdx : 0);
+      disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - 64 + (Hlit ? cdy : 0);
       ssd_out[tile] = (uint32_t)(b >> 32);
       flags[tile] = (uint8_t)(3 | (mode && want ? 16 : 0));
       if (vb) atomicOr(vb + (tile >> 6), 1ull << (tile & 63));
@@ -429,7 +456,7 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
                          int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st,
                          const int32_t* centre, const uint8_t* mode, int want,
-                         unsigned long long* vb, int split) {
+                         unsigned long long* vb, int split, const double* Hlit) {
   if (ntx * nty == 0) return hipSuccess;
   SearchShape sh;
   sh.R = R;
@@ -474,7 +501,7 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
                      (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
                      (sh.split > 1 ? (size_t)2 * sh.ncand * sh.nstrips * KX * 4 : 0);
   LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
-                     ntx, corner_xy, disp, ssd, flags, centre, mode, want, vb);
+                     ntx, corner_xy, disp, ssd, flags, centre, mode, want, vb, Hlit);
   return hipGetLastError();
 }
 

@@ -469,17 +469,20 @@ __global__ __launch_bounds__(kUnionThreads) void k_union(
 // The level fit from the sums (A^T A and A^T b of the rows
 // (x, y, 1, 0, 0, 0, -xu, -yu | u) and (0, 0, 0, x, y, 1, -xv, -yv | v),
 // scaled by powers of two), solved by one lane with the matrix in registers,
-// then H_l = H_{l+1} o G; H_l = H_{l+1} when fewer than 4 matches were fitted
-// or the solve fails.
+// then H_l = Hbase o G with Hbase = H_{l+1} (matches relative to the warped
+// source) or the identity (absolute matches); H_l = H_{l+1} when fewer than
+// 4 matches were fitted or the solve fails.
 __global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __restrict__ sums,
                                               const double* __restrict__ Hprev,
+                                              const double* __restrict__ Hbase,
                                               double* __restrict__ Hout,
                                               int32_t* __restrict__ counts) {
   __shared__ long long tot[kSums];
   const int lane = threadIdx.x;
   if (lane < kSums) tot[lane] = sums[lane];
-  double Hp[9];  // loaded with the sums
+  double Hp[9], Hb[9];  // loaded with the sums
   for (int i = 0; i < 9; ++i) Hp[i] = Hprev[i];
+  for (int i = 0; i < 9; ++i) Hb[i] = Hbase[i];
   __syncthreads();
   if (lane != 0) return;
   const int msel = (int)tot[0];
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __r
   double T1[9], T2[9], T3[9];
   mat3_mul(Pm, Gc, T1);
   mat3_mul(T1, Qm, T2);
-  mat3_mul(Hp, T2, T3);
+  mat3_mul(Hb, T2, T3);
   const double d = T3[8];
   if (d == 0.0) return;
   double Hn[9];
@@ -527,7 +530,8 @@ __global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __r
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
                            const double* H_prev, double* H_out, int32_t* counts,
-                           const WeedBufs& b, hipStream_t st, bool vb_ready) {
+                           const WeedBufs& b, hipStream_t st, bool vb_ready,
+                           const double* H_base) {
   WeedArgs a;
   a.iters = p.weed_iters;
   a.level = level;
@@ -557,7 +561,8 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
              dim3(kUnionThreads), 0, st, corner_xy, disp, flags, ntiles, w, h, a, b.nmatch,
              b.cnt, b.bal, words, b.sums, counts);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  LNR_LAUNCH(k_solve, dim3(1), dim3(64), 0, st, w, h, b.sums, H_prev, H_out, counts);
+  LNR_LAUNCH(k_solve, dim3(1), dim3(64), 0, st, w, h, b.sums, H_prev,
+             H_base ? H_base : H_prev, H_out, counts);
   return hipGetLastError();
 }
 

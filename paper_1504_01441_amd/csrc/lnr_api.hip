@@ -151,8 +151,11 @@ lnr_status check_params(lnr_ctx* ctx, const lnr_params* p) {
     return fail(ctx, LNR_E_UNSUPPORTED, "SSIM window out of range");
   if (!(p->sigma_e > 0)) return fail(ctx, LNR_E_UNSUPPORTED, "sigma_e must be > 0");
   if (p->learned != 0 && p->learned != 1) return fail(ctx, LNR_E_UNSUPPORTED, "learned must be 0 or 1");
-  if (p->search_frame != 0)
-    return fail(ctx, LNR_E_UNSUPPORTED, "search_frame 1 (the unwarped-source search) is not built");
+  if (p->search_frame != 0 && p->search_frame != 1)
+    return fail(ctx, LNR_E_UNSUPPORTED, "search_frame must be 0 or 1");
+  if (p->search_frame == 1 && p->learned)
+    return fail(ctx, LNR_E_UNSUPPORTED,
+                "the learned proposal is defined on the warped-source search (search_frame 0)");
   if (p->learned) {
     if (p->tile != 32) return fail(ctx, LNR_E_UNSUPPORTED, "the learned proposal needs tile 32");
     if (p->window_r < 0 || p->window_r > p->radius0)
@@ -416,11 +419,27 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
     auto it = ctx->search_split.find(std::make_tuple(w, h, R));
     return it == ctx->search_split.end() ? 0 : it->second;
   };
+  // search_frame 1 (Eq. 3 as printed): no level is warped; each level searches
+  // the unwarped source around its prediction, the fits are absolute (composed
+  // on the identity above the top level) and so is the propagated flow
+  const bool literal = p->search_frame == 1;
+  const double* identity = out->H + 9 * g.levels;
   for (int l = g.levels - 1; l >= 0; --l) {
     const Level& L = g.lv[l];
     const int R = l == 0 ? p->radius0 : p->radius_coarse;
     const int nt = L.ntx * L.nty;
     const int words = nt > 0 ? (nt + 63) / 64 : 1;
+    if (literal) {
+      // the weeding builds the valid-match bits from the flags (k_valid)
+      LNR_HIP(launch_search(pref + L.pix_off, psrc + L.pix_off, L.w, L.h, R, cfg, L.ntx, L.nty,
+                            out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
+                            out->ssd + L.tile_off, out->flags + L.tile_off, st, nullptr,
+                            nullptr, 0, nullptr, tuned(L.w, L.h, R), out->H + 9 * (l + 1)));
+      LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
+                              out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
+                              out->H + 9 * l, out->counts + 4 * l, wb, st, false, identity));
+      continue;
+    }
     // level 0 is warped straight into the output when it is wanted
     if (l == 0 && out->warped0) warped = out->warped0;
     LNR_HIP(launch_warp_q8(psrc + L.pix_off, L.w, L.h, out->H + 9 * (l + 1), warped, st, &wb,
@@ -462,7 +481,8 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
                       pref, guide_t, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds, true,
                       true));
   LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], chroma_of(*src), psrc, W, H,
-                               out->H + 9, out->flow, out->image, out->yeq_warped, st));
+                               literal ? identity : out->H + 9, out->flow, out->image,
+                               out->yeq_warped, st));
   return LNR_OK;
 }
 
@@ -1325,6 +1345,8 @@ lnr_status ensure_cnn(lnr_ctx* ctx) {
 
 constexpr uint32_t kNetMagic = 0x50524e4cu;  // "LNRP" little-endian
 constexpr uint32_t kNetVersion = 1u;
+constexpr uint32_t kCkptMagic = 0x4b524e4cu;  // "LNRK" little-endian
+constexpr uint32_t kCkptVersion = 1u;
 }  // namespace
 
 extern "C" {
@@ -1405,6 +1427,66 @@ lnr_status lnr_proposal_load(lnr_ctx* ctx, const char* path, void* stream) {
   LNR_HIP(launch_cnn_pack(ctx->cnn, ctx->cnn_packed, st));
   LNR_HIP(hipStreamSynchronize(st));  // the host copy is freed on return
   ctx->cnn_step = 0;
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_checkpoint_save(lnr_ctx* ctx, const char* path, uint64_t counter,
+                                        void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  if (!path) return fail(ctx, LNR_E_ARG, "path is null");
+  if (!ctx->cnn) return fail(ctx, LNR_E_ARG, "no network set");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  const size_t np = (size_t)cnn_param_count();
+  std::vector<float> host(3 * np);  // parameters, first and second moments
+  const hipStream_t st = (hipStream_t)stream;
+  LNR_HIP(hipMemcpyAsync(host.data(), ctx->cnn, 3 * np * sizeof(float), hipMemcpyDeviceToHost,
+                         st));
+  LNR_HIP(hipStreamSynchronize(st));
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(ctx, LNR_E_WEIGHTS, "cannot open the checkpoint file for writing");
+  const uint32_t hdr[4] = {kCkptMagic, kCkptVersion, (uint32_t)np, (uint32_t)ctx->cnn_step};
+  const bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+                  fwrite(&counter, sizeof(counter), 1, f) == 1 &&
+                  fwrite(host.data(), sizeof(float), 3 * np, f) == 3 * np;
+  const bool closed = fclose(f) == 0;
+  if (!ok || !closed) return fail(ctx, LNR_E_WEIGHTS, "writing the checkpoint file failed");
+  return LNR_OK;
+}
+
+lnr_status lnr_proposal_checkpoint_load(lnr_ctx* ctx, const char* path, uint64_t* counter,
+                                        void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  if (!path) return fail(ctx, LNR_E_ARG, "path is null");
+  const size_t np = (size_t)cnn_param_count();
+  std::vector<float> host(3 * np);
+  uint32_t hdr[4] = {0u, 0u, 0u, 0u};
+  uint64_t ctr = 0;
+  {
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(ctx, LNR_E_WEIGHTS, "cannot open the checkpoint file");
+    bool ok = fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == kCkptMagic &&
+              hdr[1] == kCkptVersion && hdr[2] == (uint32_t)np && hdr[3] <= 0x7fffffffu &&
+              fread(&ctr, sizeof(ctr), 1, f) == 1 &&
+              fread(host.data(), sizeof(float), 3 * np, f) == 3 * np;
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;  // nothing after the moments
+    fclose(f);
+    if (!ok) return fail(ctx, LNR_E_WEIGHTS, "not a checkpoint file of this version and size");
+  }
+  for (size_t i = 0; i < 3 * np; ++i)
+    if (!std::isfinite(host[i]) || (i >= 2 * np && host[i] < 0.f))
+      return fail(ctx, LNR_E_WEIGHTS, "non-finite checkpoint value or negative second moment");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  lnr_status s;
+  if ((s = ensure_cnn(ctx)) != LNR_OK) return s;
+  const hipStream_t st = (hipStream_t)stream;
+  LNR_HIP(hipMemcpyAsync(ctx->cnn, host.data(), 3 * np * sizeof(float), hipMemcpyHostToDevice,
+                         st));
+  LNR_HIP(launch_cnn_pack(ctx->cnn, ctx->cnn_packed, st));
+  LNR_HIP(hipStreamSynchronize(st));  // the host copy is freed on return
+  ctx->cnn_step = (int)hdr[3];
+  if (counter) *counter = ctr;
   return LNR_OK;
 }
 

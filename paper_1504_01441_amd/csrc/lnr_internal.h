@@ -86,7 +86,8 @@ hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, 
                          const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
                          int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st, const int32_t* centre = nullptr,
                          const uint8_t* mode = nullptr, int want = 0,
-                         unsigned long long* vb = nullptr, int split = 0);
+                         unsigned long long* vb = nullptr, int split = 0,
+                         const double* Hlit = nullptr);
 // splits (patch rows per thread group) that launch_search accepts for radius
 // R, ascending; and a random 8-bit texture for timing the search
 int search_split_candidates(int R, const SearchCfg& c, int* out, int max);
@@ -104,7 +105,8 @@ struct WeedBufs {
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
                            const double* H_prev, double* H_out, int32_t* counts,
-                           const WeedBufs& b, hipStream_t st, bool vb_ready = false);
+                           const WeedBufs& b, hipStream_t st, bool vb_ready = false,
+                           const double* H_base = nullptr);
 
 // ---- domain-transform propagation (k_dt.hip)
 // Kernel shapes: rows of SEG pixels per thread in NT-thread blocks; columns as

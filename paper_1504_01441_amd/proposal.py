@@ -63,14 +63,24 @@ def _dihedral(x: torch.Tensor, lab: torch.Tensor, k: int):
 
 def train(ctx: Context, x: torch.Tensor, labels: torch.Tensor, epochs: int = 10,
           batch: int = 256, lr: float = 3e-3, wd: float = 1e-4, seed: int = 0,
-          init: torch.Tensor | None = None, augment: bool = True, log=None):
+          init: torch.Tensor | None = None, augment: bool = True, log=None,
+          start_step: int = 0, stop_step: int | None = None):
     """AdamW training on the GPU (cosine learning-rate decay; with `augment`,
     each batch is one of the 8 flips / transposes of its tiles); returns the
-    per-epoch mean loss."""
-    if init is None:
-        from synth import proposal_params  # seeded initial parameters
-        init = torch.from_numpy(proposal_params(seed))
-    proposal_set(ctx, init.cuda())
+    per-epoch mean loss.
+
+    start_step / stop_step run only the global steps [start_step, stop_step)
+    of this schedule: the data order, flips and learning rates are those of
+    the whole run (replayed from the seed), so a run stopped at step k,
+    checkpointed (proposal_checkpoint_save with counter k) and resumed with
+    start_step = k after proposal_checkpoint_load ends with the same network
+    bit for bit. With start_step > 0 the context must already hold the
+    checkpoint (init is not applied)."""
+    if start_step == 0:
+        if init is None:
+            from synth import proposal_params  # seeded initial parameters
+            init = torch.from_numpy(proposal_params(seed))
+        proposal_set(ctx, init.cuda())
     g = torch.Generator(device="cpu").manual_seed(seed)
     n = x.shape[0]
     steps = epochs * ((n + batch - 1) // batch)
@@ -80,11 +90,15 @@ def train(ctx: Context, x: torch.Tensor, labels: torch.Tensor, epochs: int = 10,
         perm = torch.randperm(n, generator=g).cuda()
         tot = torch.zeros((), dtype=torch.float64, device="cuda")
         for i in range(0, n, batch):
+            flip = int(torch.randint(8, (1,), generator=g)) if augment else 0
+            if k < start_step or (stop_step is not None and k >= stop_step):
+                k += 1
+                continue
             idx = perm[i:i + batch]
             cur = lr * 0.5 * (1.0 + np.cos(np.pi * k / max(steps, 1)))
             xb, lb = x[idx], labels[idx]
             if augment:
-                xb, lb = _dihedral(xb, lb, int(torch.randint(8, (1,), generator=g)))
+                xb, lb = _dihedral(xb, lb, flip)
             loss, _ = proposal_train_step(ctx, xb, lb, cur, wd)
             tot += loss.double().sum()
             k += 1

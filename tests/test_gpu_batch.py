@@ -253,3 +253,58 @@ def test_batch_rejects_bad_flags(lnr, ctx):
     rc = lnr.lib().lnr_register_batch(ctx._h, RA, RA, 1, C.byref(lnr.Params()), OA, 8,
                                       lnr._stream())
     assert rc == -1
+
+
+# the batched workload's extremes and three sizes between them (the 64-pair
+# batch draws widths from 640..4032 and heights from 480..3024)
+C4_SIZES = [(4032, 3024), (640, 480), (2590, 1000), (1218, 2888), (3000, 2250)]
+
+
+def test_c4_batch_full_range_matches_oracle(lnr, ctx):
+    """A graph-captured, autotuned batch over the batched workload's whole
+    size range (tile shifts +-16, exposure ratios 2-16, radius 16): every
+    pair's registration against the oracle (tiles and H bit-exact, float
+    outputs within 1e-4)."""
+    p = lnr.Params(radius0=16)
+    op = oracle.params(radius0=16)
+    stacks = []
+    for i, (w, h) in enumerate(C4_SIZES):
+        stacks.append(synth.make_stack(w, h, 7100 + i, ratios=(1.0, 2.0 + 3.5 * i), fmt="i420",
+                                       shift_range=16, max_rot_deg=2.0))
+    refs = [lnr.Frame.from_numpy(s.frames[0].y, s.frames[0].u, s.frames[0].v, 1.0)
+            for s in stacks]
+    srcs = [lnr.Frame.from_numpy(s.frames[1].y, s.frames[1].u, s.frames[1].v,
+                                 s.frames[1].exposure) for s in stacks]
+    print("c4 batch sizes " + ", ".join(f"{w}x{h}" for w, h in C4_SIZES), flush=True)
+    outs = lnr.register_batch(ctx, refs, srcs, p, graph=True, autotune=True)
+    torch.cuda.synchronize()
+    # a replay of the cached graph gives the same
+    outs = lnr.register_batch(ctx, refs, srcs, p, outs=outs, graph=True)
+    torch.cuda.synchronize()
+    for st, reg, (w, h) in zip(stacks, outs, C4_SIZES):
+        print(f"oracle {w}x{h}", flush=True)
+        registration_parity(reg, oracle.register_pair(st.frames[0], st.frames[1], op))
+
+
+def test_c5_learned_batch_full_size_equals_single_calls(lnr, ctx):
+    """Three full 5 MP pairs of the benchmark recipe in one graph-captured
+    learned batch give exactly what one learned register_pair call per pair
+    gives."""
+    from paper_1504_01441_amd import proposal as prop
+    P, conf = prop.load()
+    lnr.proposal_set(ctx, torch.from_numpy(P).cuda())
+    p = lnr.Params(radius0=16, learned=1, window_r=2, conf_min=conf)
+    stacks = [synth.make_config_pair("c2", s) for s in (21, 22, 23)]
+    refs = [lnr.Frame.from_numpy(s.frames[0].y, s.frames[0].u, s.frames[0].v, 1.0)
+            for s in stacks]
+    srcs = [lnr.Frame.from_numpy(s.frames[1].y, s.frames[1].u, s.frames[1].v,
+                                 s.frames[1].exposure) for s in stacks]
+    singles = [lnr.register_pair(ctx, r, s, p) for r, s in zip(refs, srcs)]
+    outs = lnr.register_batch(ctx, refs, srcs, p, graph=True, autotune=True)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, singles):
+        _same(a, b)
+    outs = lnr.register_batch(ctx, refs, srcs, p, outs=outs, graph=True)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, singles):
+        _same(a, b)

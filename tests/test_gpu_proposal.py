@@ -276,3 +276,49 @@ def test_confidence_threshold_edges(lnr, conf_min):
     else:
         assert not np.any(fl & 16)
     c.close()
+
+
+def test_checkpoint_resume_bit_exact(lnr, tmp_path):
+    """Training stopped after 4 of 10 steps, checkpointed (parameters, AdamW
+    moments and step count, data-order counter), loaded into a fresh context
+    and resumed ends with the same network as the uninterrupted run, bit for
+    bit; damaged checkpoints are rejected before the network is touched."""
+    from paper_1504_01441_amd import proposal as prop
+    rng = np.random.default_rng(77)
+    x = _bf16_bits(_inputs(8, 600)).cuda()
+    lab = torch.from_numpy(rng.integers(-10, 11, (600, 2)).astype(np.int32)).cuda()
+    kw = dict(epochs=2, batch=128, seed=3)
+    c1 = lnr.Context(0)
+    prop.train(c1, x, lab, **kw)
+    want = lnr.proposal_get(c1)
+    c2 = lnr.Context(0)
+    prop.train(c2, x, lab, stop_step=4, **kw)
+    path = tmp_path / "ckpt.bin"
+    lnr.proposal_checkpoint_save(c2, str(path), 4)
+    c3 = lnr.Context(0)
+    ctr = lnr.proposal_checkpoint_load(c3, str(path))
+    assert ctr == 4
+    prop.train(c3, x, lab, start_step=ctr, **kw)
+    torch.cuda.synchronize()
+    got = lnr.proposal_get(c3)
+    assert torch.equal(got, want)
+    assert not torch.equal(got, lnr.proposal_get(c2))  # training did move it
+    raw = path.read_bytes()
+    hdr = np.frombuffer(raw[:16], "<u4")
+    assert raw[:4] == b"LNRK" and list(hdr[1:]) == [1, lnr.PROPOSAL_PARAMS, 4]
+    assert np.frombuffer(raw[16:24], "<u8")[0] == 4
+    assert len(raw) == 24 + 12 * lnr.PROPOSAL_PARAMS
+    nan = np.float32(np.nan).tobytes()
+    neg = np.float32(-1.0).tobytes()
+    bad = {"truncated": raw[:-4], "magic": b"XXXX" + raw[4:], "trailing": raw + b"\0",
+           "nan": raw[:24] + nan + raw[28:],
+           "negative_v": raw[:len(raw) - 4] + neg}
+    for name, content in bad.items():
+        p = tmp_path / f"bad_{name}.bin"
+        p.write_bytes(content)
+        with pytest.raises(lnr.LnrError) as e:
+            lnr.proposal_checkpoint_load(c3, str(p))
+        assert e.value.status == -7, name
+        assert torch.equal(lnr.proposal_get(c3), want), name
+    for c in (c1, c2, c3):
+        c.close()
