@@ -303,16 +303,20 @@ lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_par
 
 /* ---- learned displacement proposal (an extension beyond the paper; it
  * narrows the Sec. 2.2 search). The network: per level-0 tile of 32 x 32 the
- * input x[2][16][16] (reference and warped source, 2 x 2 sums s mapped to
- * bf16((s - 510) / 512)), four 3x3 convolutions to 32 channels (strides 1, 2,
- * 1, 2, padding 1, ReLU, activations rounded to bf16), a linear head 512 -> 3.
+ * input x[4][16][16]: channels 0, 1 the tile of the reference and of the
+ * warped source (2 x 2 sums s mapped to bf16((s - 510) / 512)); channels 2,
+ * 3 the 64 x 64 windows around the tile (16 px on every side, edge pixels
+ * repeated outside the image; 4 x 4 sums s mapped to bf16((s - 2040) /
+ * 2048)), so that displacements across the whole search range are in view;
+ * four 3x3 convolutions to 32 channels (strides 1, 2, 1, 2, padding 1, ReLU,
+ * activations rounded to bf16), a linear head 512 -> 3.
  * Outputs o: predicted displacement (8 o[0], 8 o[1]) and confidence logit
  * o[2]. Parameters: one fp32 vector of LNR_PROPOSAL_PARAMS values, in order
- * W1[32][2][3][3] b1[32] W2[32][32][3][3] b2 W3 b3 W4 b4 Wh[3][512] bh[3]
+ * W1[32][4][3][3] b1[32] W2[32][32][3][3] b2 W3 b3 W4 b4 Wh[3][512] bh[3]
  * (head feature f = (y * 4 + x) * 32 + c). The context owns one network and
  * its AdamW state; the calls below run on the GPU (bf16 matrix cores, fp32
  * accumulation). ------------------------------------------------------------ */
-#define LNR_PROPOSAL_PARAMS 29891
+#define LNR_PROPOSAL_PARAMS 30467
 
 /* Load the network parameters params[LNR_PROPOSAL_PARAMS] (device, fp32)
  * into the context and reset the AdamW moments and step count. */
@@ -345,10 +349,10 @@ lnr_status lnr_proposal_checkpoint_save(lnr_ctx* ctx, const char* path, uint64_t
 lnr_status lnr_proposal_checkpoint_load(lnr_ctx* ctx, const char* path, uint64_t* counter,
                                         void* stream);
 /* Network inputs of every full 32 x 32 tile of two dense [h][w] 8-bit
- * images (raster tile order): x[ntiles][2][16][16], bf16 bit patterns. */
+ * images (raster tile order): x[ntiles][4][16][16], bf16 bit patterns. */
 lnr_status lnr_proposal_inputs(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* warped,
                                int32_t w, int32_t h, uint16_t* x, void* stream);
-/* Inference on n inputs (device bf16 [n][2][16][16]): out[n][3] (device). */
+/* Inference on n inputs (device bf16 [n][4][16][16]): out[n][3] (device). */
 lnr_status lnr_proposal_forward(lnr_ctx* ctx, const uint16_t* x, int32_t n, float* out,
                                 void* stream);
 /* One training step on a batch: forward, loss (Huber on 8 o[0] - label_x and

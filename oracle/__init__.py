@@ -496,7 +496,8 @@ def register_pair(ref, src, p=None, H_init=None):
 # (an extension beyond the paper: a CNN proposes each level-0 tile's
 # displacement so that the Sec. 2.2 search scans a small window)
 
-CNN_PARAMS = 29891
+CNN_PARAMS = 30467
+CNN_IN = 4       # input channels: tile pair (1/2 resolution), window pair (1/4)
 
 
 def bf16(v):
@@ -506,15 +507,15 @@ def bf16(v):
 
 
 def cnn_tile_inputs(ref, warped, tiles, tile=32):
-    """[n, 2, 16, 16] network inputs of the given level-0 tile indices."""
+    """[n, 4, 16, 16] network inputs of the given level-0 tile indices."""
     ref = _c(ref, np.uint8)
     warped = _c(warped, np.uint8)
     h, w = ref.shape
     ntx = w // tile
-    out = np.zeros((len(tiles), 2, 16, 16), np.float64)
+    out = np.zeros((len(tiles), CNN_IN, 16, 16), np.float64)
     for k, t in enumerate(tiles):
         tx, ty = int(t) % ntx, int(t) // ntx
-        lib().lo_cnn_tile_input(_p(ref), _p(warped), w, tx * tile, ty * tile,
+        lib().lo_cnn_tile_input(_p(ref), _p(warped), w, h, tx * tile, ty * tile,
                                 _p(out[k]))
     return out
 
@@ -522,7 +523,7 @@ def cnn_tile_inputs(ref, warped, tiles, tile=32):
 def cnn_forward(params, x, rnd=True):
     """[n, 3] network outputs (o0, o1, o2): prediction (8 o0, 8 o1), logit o2."""
     params = _c(params, np.float64)
-    x = _c(x, np.float64).reshape(-1, 512)
+    x = _c(x, np.float64).reshape(-1, CNN_IN * 256)
     out = np.zeros((x.shape[0], 3), np.float64)
     lib().lo_cnn_forward(_p(params), _p(x), x.shape[0], int(rnd), _p(out))
     return out
@@ -531,7 +532,7 @@ def cnn_forward(params, x, rnd=True):
 def cnn_loss_grad(params, x, labels, rnd=True):
     """(mean loss, gradient over the flat parameter vector)."""
     params = _c(params, np.float64)
-    x = _c(x, np.float64).reshape(-1, 512)
+    x = _c(x, np.float64).reshape(-1, CNN_IN * 256)
     lab = _c(labels, np.int32).reshape(-1, 2)
     g = np.zeros(CNN_PARAMS, np.float64)
     loss = lib().lo_cnn_loss_grad(_p(params), _p(x), _p(lab), x.shape[0], int(rnd), _p(g))

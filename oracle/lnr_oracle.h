@@ -183,8 +183,8 @@ int  lo_irradiance(int n, int ch, int w, int h, const double* const* imgs,
  * part of the paper: it narrows the search of Sec. 2.2) ---------------------- */
 double lo_bf16(double v);
 int    lo_cnn_param_count(void);
-void   lo_cnn_tile_input(const uint8_t* ref, const uint8_t* warped, int w, int x0, int y0,
-                         double* x);
+void   lo_cnn_tile_input(const uint8_t* ref, const uint8_t* warped, int w, int h, int x0,
+                         int y0, double* x /* [4][16][16] */);
 void   lo_cnn_forward(const double* params, const double* x, int n, int rnd, double* out);
 double lo_cnn_loss_grad(const double* params, const double* x, const int32_t* label, int n,
                         int rnd, double* grad);

@@ -14,16 +14,21 @@
  * form the finite-difference pins check.
  *
  * Network (one sample; tensors channel-major [c][y][x]):
- *   x  [2][16][16]  tile pair: channel 0 reference, 1 warped source; each
- *                   value bf16((a + b + c + d - 510) / 512) over a 2x2 block
+ *   x  [4][16][16]  channels 0, 1: the 32 x 32 tile of the reference and of
+ *                   the warped source, each value bf16((s - 510) / 512) of the
+ *                   sum s of a 2x2 block; channels 2, 3: the 64 x 64 window
+ *                   around the tile (16 px on every side, so that the whole
+ *                   search range is in view) of the reference and of the
+ *                   warped source, each value bf16((s - 2040) / 2048) of the
+ *                   sum s of a 4x4 block, coordinates clamped to the image
  *   a1 = relu(conv3x3(x,  W1, b1, stride 1, pad 1))   [32][16][16]
  *   a2 = relu(conv3x3(a1, W2, b2, stride 2, pad 1))   [32][8][8]
  *   a3 = relu(conv3x3(a2, W3, b3, stride 1, pad 1))   [32][8][8]
  *   a4 = relu(conv3x3(a3, W4, b4, stride 2, pad 1))   [32][4][4]
  *   o[j] = bh[j] + sum_f Wh[j][f] a4[f],  f = (y * 4 + x) * 32 + c
  *   prediction dx = 8 o[0], dy = 8 o[1], confidence logit o[2]
- * Parameters, one flat vector: W1[32][2][3][3] b1[32] W2[32][32][3][3] b2[32]
- * W3 b3 W4 b4 Wh[3][512] bh[3] (29,891 values).
+ * Parameters, one flat vector: W1[32][4][3][3] b1[32] W2[32][32][3][3] b2[32]
+ * W3 b3 W4 b4 Wh[3][512] bh[3] (30,467 values).
  *
  * Loss per sample with label (lx, ly), averaged over the batch:
  *   huber(dx - lx) + huber(dy - ly) + bce(o[2], q),
@@ -40,7 +45,7 @@
 
 #include "lnr_oracle.h"
 
-enum { C1 = 2, CH = 32, NF = 512 };
+enum { C1 = 4, CH = 32, NF = 512, NX = C1 * 256 };
 
 /* bfloat16 round to nearest even, through float (as a float -> bf16 cast) */
 double lo_bf16(double v) {
@@ -82,16 +87,27 @@ static layout param_layout(void) {
 
 int lo_cnn_param_count(void) { return param_layout().total; }
 
-/* Network input of one level-0 tile (32 x 32 at origin (x0, y0)) */
-void lo_cnn_tile_input(const uint8_t* ref, const uint8_t* warped, int w, int x0, int y0,
-                       double* x /* [2][16][16] */) {
-  for (int c = 0; c < 2; ++c) {
-    const uint8_t* img = c == 0 ? ref : warped;
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Network input of one level-0 tile (32 x 32 at origin (x0, y0)) of w x h
+ * images: the tile pair at half resolution, then the 64 x 64 windows around
+ * it at quarter resolution (pixels outside the image repeat the edge). */
+void lo_cnn_tile_input(const uint8_t* ref, const uint8_t* warped, int w, int h, int x0, int y0,
+                       double* x /* [4][16][16] */) {
+  for (int c = 0; c < 4; ++c) {
+    const uint8_t* img = (c & 1) == 0 ? ref : warped;
+    const int k = c < 2 ? 2 : 4;           /* block side */
+    const int ox = c < 2 ? x0 : x0 - 16, oy = c < 2 ? y0 : y0 - 16;
     for (int i = 0; i < 16; ++i)
       for (int j = 0; j < 16; ++j) {
-        const size_t r0 = (size_t)(y0 + 2 * i) * w + (size_t)(x0 + 2 * j);
-        const int s = img[r0] + img[r0 + 1] + img[r0 + w] + img[r0 + w + 1];
-        x[(c * 16 + i) * 16 + j] = lo_bf16((double)(s - 510) / 512.0);
+        int s = 0;
+        for (int u = 0; u < k; ++u)
+          for (int v = 0; v < k; ++v) {
+            const int yy = clampi(oy + k * i + u, 0, h - 1), xx = clampi(ox + k * j + v, 0, w - 1);
+            s += img[(size_t)yy * w + xx];
+          }
+        const double mid = c < 2 ? 510.0 : 2040.0, scale = c < 2 ? 512.0 : 2048.0;
+        x[(c * 16 + i) * 16 + j] = lo_bf16(((double)s - mid) / scale);
       }
   }
 }
@@ -162,7 +178,7 @@ void lo_cnn_forward(const double* params, const double* x, int n, int rnd, doubl
   double* wb = rounded_weights(params, &L, rnd, Wr);
   acts* A = (acts*)malloc(sizeof(acts));
   for (int s = 0; s < n; ++s) {
-    forward_one(params, &L, Wr, x + (size_t)s * 512, rnd, A);
+    forward_one(params, &L, Wr, x + (size_t)s * NX, rnd, A);
     for (int j = 0; j < 3; ++j) out[(size_t)s * 3 + j] = A->o[j];
   }
   free(A);
@@ -187,7 +203,7 @@ double lo_cnn_loss_grad(const double* params, const double* x, const int32_t* la
   const int cin[4] = {C1, CH, CH, CH}, hin[4] = {16, 16, 8, 8}, st[4] = {1, 2, 1, 2},
             hout[4] = {16, 8, 8, 4};
   for (int s = 0; s < n; ++s) {
-    const double* xs = x + (size_t)s * 512;
+    const double* xs = x + (size_t)s * NX;
     forward_one(params, &L, Wr, xs, rnd, A);
     const double ex = 8.0 * A->o[0] - label[2 * s], ey = 8.0 * A->o[1] - label[2 * s + 1];
     const double em = fabs(ex) > fabs(ey) ? fabs(ex) : fabs(ey);

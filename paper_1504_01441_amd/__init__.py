@@ -176,7 +176,8 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
-PROPOSAL_PARAMS = 29891
+PROPOSAL_PARAMS = 30467
+PROPOSAL_IN = 4   # network input channels
 
 
 def _stream():
@@ -530,7 +531,7 @@ def stage_search_window(ctx, ref: torch.Tensor, warped: torch.Tensor, R: int,
 
 
 def proposal_set(ctx, params: torch.Tensor):
-    """Load network parameters (float32 [29891], device) and reset AdamW."""
+    """Load network parameters (float32 [PROPOSAL_PARAMS], device) and reset AdamW."""
     params = params.to(device="cuda", dtype=torch.float32).contiguous()
     assert params.numel() == PROPOSAL_PARAMS
     ctx.check(lib().lnr_proposal_set(ctx._h, _ptr(params), _stream()))
@@ -568,10 +569,10 @@ def proposal_checkpoint_load(ctx, path: str) -> int:
 
 
 def proposal_inputs(ctx, ref: torch.Tensor, warped: torch.Tensor) -> torch.Tensor:
-    """Network inputs of every full 32x32 tile: int16 view of bf16 [n, 2, 16, 16]."""
+    """Network inputs of every full 32x32 tile: int16 view of bf16 [n, 4, 16, 16]."""
     h, w = ref.shape
     n = (w // 32) * (h // 32)
-    x = torch.empty(max(n, 1), 2, 16, 16, dtype=torch.int16, device=ref.device)
+    x = torch.empty(max(n, 1), PROPOSAL_IN, 16, 16, dtype=torch.int16, device=ref.device)
     ctx.check(lib().lnr_proposal_inputs(ctx._h, _ptr(ref.contiguous()), _ptr(warped.contiguous()),
                                         w, h, _ptr(x), _stream()))
     return x[:n]

@@ -4,7 +4,7 @@
 // on the matrix cores: every convolution is an implicit GEMM on
 // v_mfma_f32_16x16x16_bf16 (bf16 operands, fp32 accumulation).
 //
-// Network (per tile): x [16][16][2] -> conv3x3 s1 -> 32 ch [16][16] -> conv s2
+// Network (per tile): x [16][16][4] -> conv3x3 s1 -> 32 ch [16][16] -> conv s2
 // -> [8][8] -> conv s1 -> [8][8] -> conv s2 -> [4][4] -> linear 512 -> 3,
 // ReLU after every convolution, activations rounded to bf16; outputs
 // (dx / 8, dy / 8, confidence logit). On the device, activations are NHWC
@@ -14,7 +14,8 @@
 //   A[r][4g + j],  B[4g + j][r],  D[4g + j][r].
 //
 //  k_cnn_pack     fp32 master parameters -> bf16 weight layouts for the kernels
-//  k_cnn_input    tile pairs -> network input (2x2 sums, bf16)
+//  k_cnn_input    tile pairs -> network input: the tiles' 2x2 sums and the
+//                 64 x 64 windows' 4x4 sums (bf16), for listed tiles
 //  k_cnn_fwd      four samples per workgroup at a time, four waves per sample
 //                 (each a quarter of every layer's output tiles), weights
 //                 shared in LDS;
@@ -39,20 +40,24 @@ constexpr int kWave = 64;
 constexpr int kFwdWaves = 16;     // forward workgroup: 4 samples at a time,
 constexpr int kFwdGroupWaves = 4;  // four waves per sample
 
-// flat parameter vector: W1[32][2][3][3] b1 W2[32][32][3][3] b2 W3 b3 W4 b4
-// Wh[3][512] bh[3]
-constexpr int kOffW[4] = {0, 608, 9856, 19104};
-constexpr int kOffB[4] = {576, 9824, 19072, 28320};
-constexpr int kOffWh = 28352, kOffBh = 29888, kNParam = 29891;
+constexpr int C1 = 4;              // input channels
+constexpr int kIn = C1 * 256;       // input values per sample
 
-// packed bf16 weights: W1p[32 co][32 k] (k = tap * 2 + ci, zero from 18),
+// flat parameter vector: W1[32][4][3][3] b1 W2[32][32][3][3] b2 W3 b3 W4 b4
+// Wh[3][512] bh[3]
+constexpr int kOffW[4] = {0, 1184, 10432, 19680};
+constexpr int kOffB[4] = {1152, 10400, 19648, 28896};
+constexpr int kOffWh = 28928, kOffBh = 30464, kNParam = 30467;
+
+// packed bf16 weights: W1p[32 co][48 k] (k = tap * 4 + ci, zero from 36),
 // Wp[l][32 co][9 tap][32 ci] and the transposes WT[l][32 ci][9 tap][32 co]
-constexpr int kW1p = CH * 32;
+constexpr int kK1 = 48;
+constexpr int kW1p = CH * kK1;
 constexpr int kWp = CH * 9 * CH;
 constexpr int kPacked = kW1p + 3 * kWp + 3 * kWp;
 
 // per-sample stored activations (bf16, NHWC): x, a1, a2, a3, a4
-constexpr int kActX = 0, kActA1 = 512, kActA2 = kActA1 + 8192, kActA3 = kActA2 + 2048,
+constexpr int kActX = 0, kActA1 = kIn, kActA2 = kActA1 + 8192, kActA3 = kActA2 + 2048,
               kActA4 = kActA3 + 2048, kActN = kActA4 + 512;
 // per-sample activation gradients after the ReLU (bf16, channel-major [c][p])
 constexpr int kDz1 = 0, kDz2 = 8192, kDz3 = kDz2 + 2048, kDz4 = kDz3 + 2048,
@@ -75,11 +80,11 @@ __global__ __launch_bounds__(256) void k_cnn_pack(const float* __restrict__ P,
                                                   uint16_t* __restrict__ pk) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < kW1p) {
-    const int co = i / 32, k = i % 32;
+    const int co = i / kK1, k = i % kK1;
     float v = 0.f;
-    if (k < 18) {
-      const int tap = k >> 1, ci = k & 1;
-      v = P[kOffW[0] + (co * 2 + ci) * 9 + tap];
+    if (k < 9 * C1) {
+      const int tap = k / C1, ci = k % C1;
+      v = P[kOffW[0] + (co * C1 + ci) * 9 + tap];
     }
     pk[i] = f2bf(v);
     return;
@@ -95,19 +100,61 @@ __global__ __launch_bounds__(256) void k_cnn_pack(const float* __restrict__ P,
   pk[i] = f2bf(P[kOffW[l] + (co * CH + ci) * 9 + tap]);
 }
 
-// One tile pair per thread row: 16x16 values per channel.
+// Network inputs: sample i is tile tiles[i] (tile i without a list), i below
+// *count (or n). The 64 x 64 windows of both images around the tile (16 px
+// on every side; rows and columns outside the image repeat the edge) are
+// staged in workgroup memory; channels 0, 1 are the 2x2 sums of the central
+// 32 x 32 tile, channels 2, 3 the 4x4 sums of the window, each value
+// bf16((s - mid) / scale), exact before the one rounding.
 __global__ __launch_bounds__(256) void k_cnn_input(const uint8_t* __restrict__ ref,
-                                                   const uint8_t* __restrict__ wrp, int w, int ntx,
-                                                   int ntiles, uint16_t* __restrict__ x) {
-  const int t = blockIdx.x;
-  if (t >= ntiles) return;
-  const int x0 = (t % ntx) * 32, y0 = (t / ntx) * 32;
-  const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
-  for (int c = 0; c < 2; ++c) {
+                                                   const uint8_t* __restrict__ wrp, int w, int h,
+                                                   int ntx, const int32_t* __restrict__ tiles,
+                                                   const int* __restrict__ count, int n,
+                                                   uint16_t* __restrict__ x) {
+  __shared__ uint32_t win[2][64][16];
+  const int i = blockIdx.x;
+  const int m = count ? *count : n;
+  if (i >= m) return;
+  const int t = tiles ? tiles[i] : i;
+  const int x0 = (t % ntx) * 32 - 16, y0 = (t / ntx) * 32 - 16;
+  for (int k = threadIdx.x; k < 2 * 64 * 16; k += 256) {
+    const int c = k >> 10, r = (k >> 4) & 63, d = k & 15;
     const uint8_t* img = c ? wrp : ref;
-    const size_t r0 = (size_t)(y0 + 2 * i) * w + (size_t)(x0 + 2 * j);
-    const int s = img[r0] + img[r0 + 1] + img[r0 + w] + img[r0 + w + 1];
-    x[(size_t)t * 512 + (c * 16 + i) * 16 + j] = f2bf((float)(s - 510) * (1.f / 512.f));
+    const int yy = min(max(y0 + r, 0), h - 1);
+    const uint8_t* row = img + (size_t)yy * w;
+    const int xs = x0 + 4 * d;
+    const int off = (int)(reinterpret_cast<uintptr_t>(row + xs) & 3u);
+    uint32_t v = 0;
+    if (xs >= 0 && (xs - off) + 8 <= w) {
+      const uint8_t* base = row + xs - off;  // aligned
+      const uint32_t lo = *reinterpret_cast<const uint32_t*>(base);
+      const uint32_t hi = *reinterpret_cast<const uint32_t*>(base + 4);
+      v = __builtin_amdgcn_alignbyte(hi, lo, off);
+    } else {
+      for (int b = 0; b < 4; ++b)
+        v |= (uint32_t)row[min(max(xs + b, 0), w - 1)] << (8 * b);
+    }
+    win[c][r][d] = v;
+  }
+  __syncthreads();
+  uint16_t* xo = x + (size_t)i * kIn;
+  const uint8_t* wb = reinterpret_cast<const uint8_t*>(win);
+  for (int k = threadIdx.x; k < kIn; k += 256) {
+    const int c = k >> 8, yi = (k >> 4) & 15, xj = k & 15;
+    const int img = c & 1;
+    float v;
+    if (c < 2) {
+      const uint8_t* p0 = wb + (img * 64 + 16 + 2 * yi) * 64 + 16 + 2 * xj;
+      const int s = p0[0] + p0[1] + p0[64] + p0[65];
+      v = (float)(s - 510) * (1.f / 512.f);
+    } else {
+      uint32_t s = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        s = __builtin_amdgcn_udot4(win[img][4 * yi + u][xj], 0x01010101u, s, false);
+      v = (float)((int)s - 2040) * (1.f / 2048.f);
+    }
+    xo[k] = f2bf(v);
   }
 }
 
@@ -126,30 +173,25 @@ constexpr int kWS = 9 * CH + 8;
 
 __device__ void conv1_fwd_part(const uint16_t* in, const uint16_t* W1p, const float* bias,
                                uint16_t* out, int lane, int part) {
+  // K = (tap, ci) = tap * 4 + ci over three steps of 16: step ks covers taps
+  // 4 ks .. 4 ks + 3, lane group g one tap's four channels (one 8-byte load)
   const int r = lane & 15, g = lane >> 4;
   const int mt0 = 4 * part;
+  const bf16x4 zero = {0, 0, 0, 0};
   f32x4 acc[4][2];
 #pragma unroll
   for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    const int t0 = half * 8 + g * 2;  // taps t0, t0 + 1 (channels 0, 1 each)
-    const bf16x4 b0 = ld4(W1p + r * 32 + half * 16 + g * 4);
-    const bf16x4 b1 = ld4(W1p + (16 + r) * 32 + half * 16 + g * 4);
+  for (int ks = 0; ks < 3; ++ks) {
+    const int tap = 4 * ks + g;
+    const bf16x4 b0 = ld4(W1p + r * kK1 + ks * 16 + g * 4);
+    const bf16x4 b1 = ld4(W1p + (16 + r) * kK1 + ks * 16 + g * 4);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int m = (mt0 + u) * 16 + r, oy = m >> 4, ox = m & 15;
-      uint32_t v[2] = {0u, 0u};
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int tap = t0 + q;
-        const int iy = oy + tap / 3 - 1, ix = ox + tap % 3 - 1;
-        if (tap < 9 && iy >= 0 && iy < 16 && ix >= 0 && ix < 16)
-          v[q] = *reinterpret_cast<const uint32_t*>(in + (iy * 16 + ix) * 2);
-      }
-      bf16x4 a;
-      a[0] = (short)(v[0] & 0xffff); a[1] = (short)(v[0] >> 16);
-      a[2] = (short)(v[1] & 0xffff); a[3] = (short)(v[1] >> 16);
+      const int iy = oy + tap / 3 - 1, ix = ox + tap % 3 - 1;
+      const bool ok = tap < 9 && iy >= 0 && iy < 16 && ix >= 0 && ix < 16;
+      const bf16x4 a = ok ? ld4(in + (iy * 16 + ix) * C1) : zero;
       acc[u][0] = mfma(a, b0, acc[u][0]);
       acc[u][1] = mfma(a, b1, acc[u][1]);
     }
@@ -205,6 +247,11 @@ struct ProposalOut {
   uint8_t* fallback;  // [ntiles] 1: exhaustive search
   int clampc;         // |centre| <= clampc
   float conf_logit;   // window search when the logit is >= this
+  const int32_t* tiles;  // sample -> tile (null: sample s is tile s)
+  const int* count;      // samples (device; null: the launch's n)
+  int* lists;            // window tiles [0, ntiles), fallback tiles [ntiles, 2 ntiles)
+  int* counts;           // [2] entries of the two lists
+  int ntiles;
 };
 
 // LDS: packed weights (W1p, then W2..W4 with padded rows) and biases, shared
@@ -223,6 +270,7 @@ __global__ __launch_bounds__(kFwdWaves * kWave) void k_cnn_fwd(
     const uint16_t* __restrict__ pk, const float* __restrict__ P, const uint16_t* __restrict__ x,
     int n, float* __restrict__ out, uint16_t* __restrict__ acts, ProposalOut po) {
   extern __shared__ __align__(16) uint8_t sm[];
+  if (po.count) n = *po.count;
   uint16_t* sW1 = reinterpret_cast<uint16_t*>(sm);
   uint16_t* sW = sW1 + kW1p;  // [3][32 co][kWS]: [9 tap][32 ci] + padding
   float* sb = reinterpret_cast<float*>(sW + 3 * CH * kWS);  // [4][32]
@@ -252,17 +300,16 @@ __global__ __launch_bounds__(kFwdWaves * kWave) void k_cnn_fwd(
     const bool act = s < n;
     __syncthreads();  // weights loaded / previous round's buffers free
     if (act) {
-      // x: NCHW [2][16][16] -> NHWC [16][16][2] in bufB
-      const uint16_t* xs = x + (size_t)s * 512;
-      for (int i = gt; i < 256; i += GT) {
-        bufB[2 * i] = xs[i];
-        bufB[2 * i + 1] = xs[256 + i];
-      }
+      // x: NCHW [4][16][16] -> NHWC [16][16][4] in bufB
+      const uint16_t* xs = x + (size_t)s * kIn;
+      for (int i = gt; i < 256; i += GT)
+#pragma unroll
+        for (int c = 0; c < C1; ++c) bufB[C1 * i + c] = xs[c * 256 + i];
     }
     __syncthreads();
     if (act) {
       if (TRAIN)
-        for (int i = gt; i < 512; i += GT) acts[(size_t)s * kActN + kActX + i] = bufB[i];
+        for (int i = gt; i < kIn; i += GT) acts[(size_t)s * kActN + kActX + i] = bufB[i];
       conv1_fwd_part(bufB, sW1, sb, bufA, lane, part);  // a1 -> bufA
     }
     __syncthreads();
@@ -311,9 +358,12 @@ __global__ __launch_bounds__(kFwdWaves * kWave) void k_cnn_fwd(
           int cx = (int)floorf(8.f * o0 + 0.5f), cy = (int)floorf(8.f * o1 + 0.5f);
           cx = min(max(cx, -po.clampc), po.clampc);
           cy = min(max(cy, -po.clampc), po.clampc);
-          po.centre[2 * s] = cx;
-          po.centre[2 * s + 1] = cy;
-          po.fallback[s] = o2 >= po.conf_logit ? 0 : 1;
+          const int t = po.tiles ? po.tiles[s] : s;
+          const int fb = o2 >= po.conf_logit ? 0 : 1;
+          po.centre[2 * t] = cx;
+          po.centre[2 * t + 1] = cy;
+          po.fallback[t] = (uint8_t)fb;
+          if (po.lists) po.lists[fb * po.ntiles + atomicAdd(&po.counts[fb], 1)] = t;
         }
       }
     }
@@ -432,7 +482,7 @@ template <int L>
 __global__ __launch_bounds__(256) void k_cnn_wgrad(const uint16_t* __restrict__ acts,
                                                    const uint16_t* __restrict__ dzs, int n,
                                                    int per_block, float* __restrict__ part) {
-  constexpr int CIN = L == 1 ? 2 : CH;
+  constexpr int CIN = L == 1 ? C1 : CH;
   constexpr int HIN = L <= 2 ? 16 : 8;
   constexpr int HOUT = L == 1 ? 16 : (L == 4 ? 4 : 8);
   constexpr int S = (L == 2 || L == 4) ? 2 : 1;
@@ -565,16 +615,19 @@ int cnn_param_count() { return kNParam; }
 size_t cnn_packed_elems() { return kPacked; }
 size_t cnn_act_elems() { return kActN; }
 size_t cnn_dz_elems() { return kDzN; }
+size_t cnn_input_elems() { return kIn; }
 
 hipError_t launch_cnn_pack(const float* params, uint16_t* packed, hipStream_t st) {
   LNR_LAUNCH(k_cnn_pack, dim3((kPacked + 255) / 256), dim3(256), 0, st, params, packed);
   return hipGetLastError();
 }
 
-hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, int ntx, int nty,
-                            uint16_t* x, hipStream_t st) {
+hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, int h, int ntx,
+                            int nty, const int32_t* tiles, const int* count, uint16_t* x,
+                            hipStream_t st) {
   if (ntx * nty == 0) return hipSuccess;
-  LNR_LAUNCH(k_cnn_input, dim3(ntx * nty), dim3(256), 0, st, ref, warped, w, ntx, ntx * nty, x);
+  LNR_LAUNCH(k_cnn_input, dim3(ntx * nty), dim3(256), 0, st, ref, warped, w, h, ntx, tiles,
+             count, ntx * nty, x);
   return hipGetLastError();
 }
 
@@ -587,9 +640,10 @@ static int fwd_blocks(int n) {
 
 hipError_t launch_cnn_forward(const uint16_t* packed, const float* params, const uint16_t* x,
                               int n, float* out, uint16_t* acts, int32_t* centre,
-                              uint8_t* fallback, int clampc, float conf_logit, hipStream_t st) {
+                              uint8_t* fallback, int clampc, float conf_logit, hipStream_t st,
+                              const int32_t* tiles, const int* count, int* lists, int* counts) {
   if (n <= 0) return hipSuccess;
-  ProposalOut po{centre, fallback, clampc, conf_logit};
+  ProposalOut po{centre, fallback, clampc, conf_logit, tiles, count, lists, counts, n};
   hipError_t e;
   if (acts) {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cnn_fwd<true>),

@@ -5,18 +5,26 @@
 // precision in a fixed operation order, rounded half up to 1/256 px, and
 // blended with integer Q16 weights, so the result is exact integers.
 //
-// k_search: one workgroup per full tile.
+// k_search<KX, ROLE>: one workgroup per full tile of one pair's level (ROLE
+// only names the launch for profiles: coarse levels, level 0, stage calls and
+// autotuner trials). k_search_work<KX, VISIT>: one workgroup per item of a
+// work list: the tiles of several pairs' levels (a SearchJob table; batches),
+// or a device list of tile indices (the learned proposal's window and
+// fallback tiles); VISIT kVisitCornersOnly runs the corner phase alone and
+// appends each cornered tile to a list.
+// k_warp_jobs: k_warp_q8 over the rows of several pairs' levels.
 //  1. The tile's reference region (every candidate's quadrants and patch) is
 //     staged in LDS; 4 threads per candidate sum its quadrants (Eq. 1), Eq. 2
 //     gates, and an LDS atomicMax on (C << 8 | 255 - index) picks the first
 //     largest cornerness.
 //  2. The warped source window around the corner (patch + 2R) is staged in
 //     LDS, 0 outside the image.
-//  3. Thread (dy, strip) scores KX consecutive dx. The SSD is computed exactly
-//     as  sum r^2 + sum w^2 - 2 sum r w : the cross term uses v_dot4_u32_u8 on
-//     the packed patch rows against window dwords realigned with
-//     v_alignbyte_b32 (about 0.5 VALU instructions per pixel-candidate); the
-//     window energies are column sums of LDS row energies (also v_dot4).
+//  3. Thread (dy, strip) scores KX (8 or 12) consecutive dx. The SSD is
+//     computed exactly as  sum r^2 + sum w^2 - 2 sum r w : the cross term uses
+//     v_dot4_u32_u8 on the packed patch rows against window dwords realigned
+//     with v_alignbyte_b32 (about 0.45 VALU instructions per
+//     pixel-candidate); the window energies are vertical box sums (sliding,
+//     once per tile) of LDS row energies (also v_dot4).
 //  Staging reads aligned dwords (realigned in registers), several in flight
 //  per thread: the kernel's latency, not its arithmetic, bounds the coarse
 //  levels, which have few tiles. The region, its row sums and the window
@@ -35,7 +43,6 @@
 namespace lnr {
 namespace {
 
-constexpr int KX = 8;        // candidates per thread (consecutive dx)
 constexpr int NW = 6;        // patch row dwords (2P+1 <= 24)
 
 __device__ inline long long q8(double s) {
@@ -72,10 +79,12 @@ __global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src
                                                  const double* __restrict__ Hn,
                                                  uint8_t* __restrict__ out,
                                                  unsigned long long* __restrict__ vbz, int nwords,
-                                                 long long* __restrict__ sums) {
+                                                 long long* __restrict__ sums,
+                                                 int* __restrict__ zint, int nzint) {
   if (vbz && blockIdx.x == 0 && blockIdx.y == 0) {
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) vbz[i] = 0ull;
     if (threadIdx.x < 24) sums[threadIdx.x] = 0;
+    if (threadIdx.x < nzint) zint[threadIdx.x] = 0;
   }
   const int x = 4 * (blockIdx.x * blockDim.x + threadIdx.x), y = blockIdx.y;
   if (x >= w) return;
@@ -90,6 +99,41 @@ __global__ __launch_bounds__(256) void k_warp_q8(const uint8_t* __restrict__ src
     *reinterpret_cast<uint32_t*>(row + x) = v;
   } else {
     for (int k = 0; k < 4 && x + k < w; ++k) row[x + k] = (uint8_t)warp_px(src, w, h, hp, x + k, y);
+  }
+}
+
+// k_warp_q8 for a table of jobs: block b covers run b % nxb (1024 pixels) of
+// row b / nxb of all the jobs' levels (job j owns rows [row0[j], row0[j + 1])).
+// The first row's first run of each job clears that job's weeding bits and sums.
+__global__ __launch_bounds__(256) void k_warp_jobs(const WarpJob* __restrict__ jobs,
+                                                   const int* __restrict__ row0, int njobs,
+                                                   int nxb) {
+  const int gy = blockIdx.x / nxb, bx = blockIdx.x % nxb;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (__builtin_amdgcn_readfirstlane(row0[mid]) <= gy) lo = mid;
+    else hi = mid - 1;
+  }
+  const WarpJob J = jobs[lo];
+  const int y = gy - __builtin_amdgcn_readfirstlane(row0[lo]);
+  if (y == 0 && bx == 0) {
+    for (int i = threadIdx.x; i < J.nwords; i += blockDim.x) J.vb[i] = 0ull;
+    if (threadIdx.x < 24) J.sums[threadIdx.x] = 0;
+  }
+  const int x = 4 * (bx * blockDim.x + threadIdx.x);
+  if (x >= J.w) return;
+  double hp[9];
+  pixel_homography(J.Hn, J.w, J.h, hp);
+  uint8_t* row = J.out + (size_t)y * J.w;
+  if (x + 4 <= J.w && ((reinterpret_cast<uintptr_t>(row + x) & 3u) == 0)) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v |= warp_px(J.src, J.w, J.h, hp, x + k, y) << (8 * k);
+    *reinterpret_cast<uint32_t*>(row + x) = v;
+  } else {
+    for (int k = 0; k < 4 && x + k < J.w; ++k)
+      row[x + k] = (uint8_t)warp_px(J.src, J.w, J.h, hp, x + k, y);
   }
 }
 
@@ -132,7 +176,8 @@ struct SearchShape {
   int wrow;      // window row stride in bytes (an odd number of dwords)
   int ncand;     // 2R + 1
   // workgroup memory, sized for these parameters: the reference region
-  // (rows of rs bytes), the quadrant row sums, then the window
+  // (rows of rs bytes), the quadrant row sums, then the window, its row
+  // energies, the split totals and the window energies
   int rs, off_hsum, off_win;
 };
 
@@ -154,110 +199,148 @@ __device__ inline unsigned long long wave_min_u64(unsigned long long v) {
   return v;
 }
 
-__global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref,
-                                                 const uint8_t* __restrict__ wimg, int w, int h,
-                                                 SearchCfg c, SearchShape sh, int ntx,
-                                                 int32_t* __restrict__ corner_xy,
-                                                 int32_t* __restrict__ disp,
-                                                 uint32_t* __restrict__ ssd_out,
-                                                 uint8_t* __restrict__ flags,
-                                                 const int32_t* __restrict__ centre,
-                                                 const uint8_t* __restrict__ mode, int want,
-                                                 unsigned long long* __restrict__ vb,
-                                                 const double* __restrict__ Hlit) {
-  extern __shared__ __align__(16) uint8_t dyn[];
+// Workgroup state shared by the phases of one tile visit.
+struct TileShared {
+  uint32_t qsum[4 * 49];
+  uint32_t best_key;
+  uint32_t refp[(2 * kMaxPatchR + 1) * NW];
+  uint32_t er_sum;
+  unsigned long long wmin[16];
+};
+
+// One tile of one job, by the whole workgroup (every branch below that
+// skips the rest of the tile is uniform over the workgroup).
+//  list / count (kVisitCornersOnly): the cornered tile's global index gidx is
+//  appended to list.
+template <int KX>
+__device__ void search_tile(const SearchJob& J, int tile, int gidx, const SearchCfg& c,
+                            const SearchShape& sh, int visit, int want, int* list, int* count,
+                            uint8_t* dyn, TileShared& S) {
   uint8_t* reg = dyn;
   uint32_t* hsum = reinterpret_cast<uint32_t*>(dyn + sh.off_hsum);
-  __shared__ uint32_t qsum[4 * 49];
-  __shared__ uint32_t best_key;
-  __shared__ uint32_t refp[(2 * kMaxPatchR + 1) * NW];
-  __shared__ uint32_t er_sum;
-  __shared__ unsigned long long wmin[16];
-
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int tile = blockIdx.x;
-  // with a proposal, each tile is searched by the launch of its mode only
-  if (mode && mode[tile] != want) return;
-  int cdx = centre ? centre[2 * tile] : 0, cdy = centre ? centre[2 * tile + 1] : 0;
-  const int tx = tile % ntx, ty = tile / ntx;
+  const int w = J.w, h = J.h;
+  int cdx = J.centre ? J.centre[2 * tile] : 0, cdy = J.centre ? J.centre[2 * tile + 1] : 0;
+  const int tx = tile % J.ntx, ty = tile / J.ntx;
   const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
-  const int side = 2 * ext + 1;
   const int cx0 = tx * c.S + c.S / 2, cy0 = ty * c.S + c.S / 2;
-  const int rx0 = cx0 - ext, ry0 = cy0 - ext;
+  int px, py;  // corner, level coordinates
 
-  // 1. corners (Eq. 1-2) ----------------------------------------------------
-  // the region lies inside the tile; dword-aligned loads realigned in registers
-  stage_rows(ref, w, h, rx0, ry0, side, (side + 3) / 4, reg, sh.rs, tid, nt);
-  if (tid == 0) { best_key = 0u; er_sum = 0u; }
-  __syncthreads();
-  const int nc1 = 2 * c.K + 1, ncand = nc1 * nc1;
-  // Quadrant sums as separable box sums: horizontal r-pixel sums for every
-  // region row and every quadrant x-origin (left origin px - r and right
-  // origin px of each candidate column a), then r-row vertical sums.
-  {
-    const uint32_t* rdw = reinterpret_cast<const uint32_t*>(reg);
-    const int nrow = 2 * (c.K * c.g + c.r);       // rows spanned by the quadrants
-    const int yo = ext - c.K * c.g - c.r;          // first such region row
-    const int nxo = 2 * nc1;
-    const int nd = (c.r + 3) >> 2;
-    for (int i = tid; i < nrow * nxo; i += nt) {
-      const int row = i / nxo, xo = i % nxo;
-      const int a = xo >> 1;
-      const int X0 = ext + c.g * (a - c.K) - ((xo & 1) ? 0 : c.r);
-      const uint32_t* rp = rdw + (yo + row) * (sh.rs / 4) + (X0 >> 2);
-      const int rsh = X0 & 3;
-      uint32_t s = 0;
-      for (int m = 0; m < nd; ++m) {
-        const int nb = c.r - 4 * m;
-        const uint32_t mask = nb >= 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1u);
-        const uint32_t d = __builtin_amdgcn_alignbyte(rp[m + 1], rp[m], rsh) & mask;
-        s = __builtin_amdgcn_udot4(d, 0x01010101u, s, false);
+  if (visit == kVisitKnownCorner) {
+    px = J.corner_xy[2 * tile];
+    py = J.corner_xy[2 * tile + 1];
+    if (tid == 0) S.er_sum = 0u;
+    // the patch around the known corner
+    const int P = c.P, PW = 2 * P + 1;
+    stage_rows(J.ref, w, h, px - P, py - P, PW, (PW + 3) / 4, reg, sh.rs, tid, nt);
+    __syncthreads();
+    for (int i = tid; i < PW * NW; i += nt) {
+      const int row = i / NW, dw = i % NW;
+      uint32_t v = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int col = dw * 4 + k;
+        if (col < PW) v |= (uint32_t)reg[row * sh.rs + col] << (8 * k);
       }
-      hsum[i] = s;
+      S.refp[i] = v;
+    }
+  } else {
+    // 1. corners (Eq. 1-2) --------------------------------------------------
+    // the region lies inside the tile; dword-aligned loads realigned in registers
+    const int side = 2 * ext + 1;
+    const int rx0 = cx0 - ext, ry0 = cy0 - ext;
+    stage_rows(J.ref, w, h, rx0, ry0, side, (side + 3) / 4, reg, sh.rs, tid, nt);
+    if (tid == 0) { S.best_key = 0u; S.er_sum = 0u; }
+    __syncthreads();
+    const int nc1 = 2 * c.K + 1, ncand = nc1 * nc1;
+    // Quadrant sums as separable box sums: horizontal r-pixel sums for every
+    // region row and every quadrant x-origin (left origin px - r and right
+    // origin px of each candidate column a), then r-row vertical sums.
+    {
+      const uint32_t* rdw = reinterpret_cast<const uint32_t*>(reg);
+      const int nrow = 2 * (c.K * c.g + c.r);       // rows spanned by the quadrants
+      const int yo = ext - c.K * c.g - c.r;          // first such region row
+      const int nxo = 2 * nc1;
+      const int nd = (c.r + 3) >> 2;
+      for (int i = tid; i < nrow * nxo; i += nt) {
+        const int row = i / nxo, xo = i % nxo;
+        const int a = xo >> 1;
+        const int X0 = ext + c.g * (a - c.K) - ((xo & 1) ? 0 : c.r);
+        const uint32_t* rp = rdw + (yo + row) * (sh.rs / 4) + (X0 >> 2);
+        const int rsh = X0 & 3;
+        uint32_t s = 0;
+        for (int m = 0; m < nd; ++m) {
+          const int nb = c.r - 4 * m;
+          const uint32_t mask = nb >= 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1u);
+          const uint32_t d = __builtin_amdgcn_alignbyte(rp[m + 1], rp[m], rsh) & mask;
+          s = __builtin_amdgcn_udot4(d, 0x01010101u, s, false);
+        }
+        hsum[i] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < 4 * ncand; i += nt) {
+        const int ci = i >> 2, q = i & 3;
+        const int a = ci % nc1, b = ci / nc1;
+        // quadrants in cyclic order TL, TR, BR, BL
+        const int xo = 2 * a + ((q == 0 || q == 3) ? 0 : 1);
+        const int r0 = c.g * b + ((q <= 1) ? 0 : c.r);   // first row, relative to yo
+        uint32_t s = 0;
+        for (int yy = 0; yy < c.r; ++yy) s += hsum[(r0 + yy) * nxo + xo];
+        S.qsum[i] = s;
+      }
     }
     __syncthreads();
-    for (int i = tid; i < 4 * ncand; i += nt) {
-      const int ci = i >> 2, q = i & 3;
-      const int a = ci % nc1, b = ci / nc1;
-      // quadrants in cyclic order TL, TR, BR, BL
-      const int xo = 2 * a + ((q == 0 || q == 3) ? 0 : 1);
-      const int r0 = c.g * b + ((q <= 1) ? 0 : c.r);   // first row, relative to yo
-      uint32_t s = 0;
-      for (int yy = 0; yy < c.r; ++yy) s += hsum[(r0 + yy) * nxo + xo];
-      qsum[i] = s;
+    for (int ci = tid; ci < ncand; ci += nt) {
+      uint32_t C = 0, mn = 0xffffffffu;
+      for (int j = 0; j < 4; ++j) {
+        const int d = (int)S.qsum[4 * ci + ((j + 1) & 3)] - (int)S.qsum[4 * ci + j];
+        const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
+        C += ad;
+        mn = ad < mn ? ad : mn;
+      }
+      if (mn > (uint32_t)c.thr) atomicMax(&S.best_key, (C << 8) | (uint32_t)(255 - ci));
+    }
+    __syncthreads();
+    const uint32_t bk = S.best_key;
+    if (bk == 0u) {
+      if (tid == 0) {
+        J.corner_xy[2 * tile] = -1;
+        J.corner_xy[2 * tile + 1] = -1;
+        J.disp[2 * tile] = 0;
+        J.disp[2 * tile + 1] = 0;
+        J.ssd[tile] = 0;
+        J.flags[tile] = 0;
+      }
+      return;
+    }
+    const int bci = 255 - (int)(bk & 255u);
+    const int ba = bci % nc1 - c.K, bb = bci / nc1 - c.K;
+    px = cx0 + c.g * ba;
+    py = cy0 + c.g * bb;
+    if (visit == kVisitCornersOnly) {
+      if (tid == 0) {
+        J.corner_xy[2 * tile] = px;
+        J.corner_xy[2 * tile + 1] = py;
+        J.flags[tile] = 1;
+        list[atomicAdd(count, 1)] = gidx;
+      }
+      return;
+    }
+    const int prx = ext + c.g * ba, pry = ext + c.g * bb;  // corner, region coordinates
+    // packed reference patch
+    const int P = c.P, PW = 2 * P + 1;
+    for (int i = tid; i < PW * NW; i += nt) {
+      const int row = i / NW, dw = i % NW;
+      uint32_t v = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int col = dw * 4 + k;
+        if (col < PW) v |= (uint32_t)reg[(pry - P + row) * sh.rs + prx - P + col] << (8 * k);
+      }
+      S.refp[i] = v;
     }
   }
-  __syncthreads();
-  for (int ci = tid; ci < ncand; ci += nt) {
-    uint32_t C = 0, mn = 0xffffffffu;
-    for (int j = 0; j < 4; ++j) {
-      const int d = (int)qsum[4 * ci + ((j + 1) & 3)] - (int)qsum[4 * ci + j];
-      const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
-      C += ad;
-      mn = ad < mn ? ad : mn;
-    }
-    if (mn > (uint32_t)c.thr) atomicMax(&best_key, (C << 8) | (uint32_t)(255 - ci));
-  }
-  __syncthreads();
-  const uint32_t bk = best_key;
-  if (bk == 0u) {
-    if (tid == 0) {
-      corner_xy[2 * tile] = -1;
-      corner_xy[2 * tile + 1] = -1;
-      disp[2 * tile] = 0;
-      disp[2 * tile + 1] = 0;
-      ssd_out[tile] = 0;
-      flags[tile] = 0;
-    }
-    return;
-  }
-  const int bci = 255 - (int)(bk & 255u);
-  const int ba = bci % nc1 - c.K, bb = bci / nc1 - c.K;
-  const int px = cx0 + c.g * ba, py = cy0 + c.g * bb;  // corner, level coordinates
-  const int prx = ext + c.g * ba, pry = ext + c.g * bb;  // corner, region coordinates
-  if (Hlit) {  // every thread predicts the corner's source position itself
+  if (J.Hlit) {  // every thread predicts the corner's source position itself
     double hp[9];
-    pixel_homography(Hlit, w, h, hp);
+    pixel_homography(J.Hlit, w, h, hp);
     const double X = (double)px, Y = (double)py;
     const double den = (hp[6] * X + hp[7] * Y) + hp[8];
     const double sx = ((hp[0] * X + hp[1] * Y) + hp[2]) / den;
@@ -266,28 +349,20 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
     cdy = round_pred(sy) - py;
   }
 
-  // 2. packed reference patch and the warped window ------------------------
+  // 2. the searched window ---------------------------------------------------
   const int P = c.P, PW = 2 * P + 1, R = sh.R;
-  for (int i = tid; i < PW * NW; i += nt) {
-    const int row = i / NW, dw = i % NW;
-    uint32_t v = 0;
-    for (int k = 0; k < 4; ++k) {
-      const int col = dw * 4 + k;
-      if (col < PW) v |= (uint32_t)reg[(pry - P + row) * sh.rs + prx - P + col] << (8 * k);
-    }
-    refp[i] = v;
-  }
   uint8_t* win = dyn + sh.off_win;
   uint32_t* rowsq = reinterpret_cast<uint32_t*>(win + sh.NR * sh.wrow);
   const int wx0 = px + cdx - P - R, wy0 = py + cdy - P - R;
-  stage_rows(wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
+  stage_rows(J.wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
   __syncthreads();
   // patch energy and window row energies rowsq[y][k] = sum_c win[y][k + c]^2,
   // from realigned dwords with v_dot4 (bytes past the patch width masked off)
   {
     uint32_t part = 0;
-    for (int i = tid; i < PW * NW; i += nt) part = __builtin_amdgcn_udot4(refp[i], refp[i], part, false);
-    if (part) atomicAdd(&er_sum, part);
+    for (int i = tid; i < PW * NW; i += nt)
+      part = __builtin_amdgcn_udot4(S.refp[i], S.refp[i], part, false);
+    if (part) atomicAdd(&S.er_sum, part);
   }
   {
     const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
@@ -308,21 +383,37 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
     }
   }
   __syncthreads();
-
-  // 3. SSD of KX candidates per thread (over a group of patch rows) -------
-  unsigned long long key = ~0ull;
-  const int base_threads = sh.ncand * sh.nstrips;
   const int ncp = sh.nstrips * KX;  // padded candidates per row
   uint32_t* tot = rowsq + sh.NR * sh.ncand + KX;  // [2][ncand][ncp] when split > 1
-  if (sh.split > 1) {
-    for (int i = tid; i < 2 * sh.ncand * ncp; i += nt) tot[i] = 0u;
-    __syncthreads();
+  uint32_t* colE = tot + (sh.split > 1 ? 2 * sh.ncand * ncp : 0);  // [ncand][ncand]
+  // window energies: vertical box sums of the row energies, sliding over
+  // runs of 7 candidate rows per column
+  {
+    const int nch = (sh.ncand + 6) / 7;
+    for (int it = tid; it < sh.ncand * nch; it += nt) {
+      const int dxi = it % sh.ncand, ch = it / sh.ncand;
+      const int y0 = ch * 7, y1 = min(y0 + 7, sh.ncand);
+      uint32_t e = 0;
+      for (int i = 0; i < PW; ++i) e += rowsq[(y0 + i) * sh.ncand + dxi];
+      colE[y0 * sh.ncand + dxi] = e;
+      for (int y = y0 + 1; y < y1; ++y) {
+        e += rowsq[(y - 1 + PW) * sh.ncand + dxi] - rowsq[(y - 1) * sh.ncand + dxi];
+        colE[y * sh.ncand + dxi] = e;
+      }
+    }
   }
+  if (sh.split > 1)
+    for (int i = tid; i < sh.ncand * ncp; i += nt) tot[i] = 0u;
+  __syncthreads();
+
+  // 3. cross terms of KX candidates per thread (over a group of patch rows)
+  unsigned long long key = ~0ull;
+  const int base_threads = sh.ncand * sh.nstrips;
   const int grp = tid / base_threads, rem = tid % base_threads;
   const int j = rem / sh.nstrips, s = rem % sh.nstrips;  // dy index, strip
-  uint32_t acc[KX], ew[KX];
+  uint32_t acc[KX];
 #pragma unroll
-  for (int k = 0; k < KX; ++k) { acc[k] = 0; ew[k] = 0; }
+  for (int k = 0; k < KX; ++k) acc[k] = 0;
   if (tid < sh.nthreads) {
     const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
     const int rowdw = sh.wrow >> 2;
@@ -334,7 +425,7 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       for (int m = 0; m < KX / 4 + NW + 1; ++m) wv[m] = wr[m];
       uint32_t rr[NW];
 #pragma unroll
-      for (int m = 0; m < NW; ++m) rr[m] = refp[i * NW + m];
+      for (int m = 0; m < NW; ++m) rr[m] = S.refp[i * NW + m];
       uint32_t sft[4][KX / 4 + NW];
 #pragma unroll
       for (int m = 0; m < KX / 4 + NW; ++m) {
@@ -350,30 +441,19 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
         for (int m = 0; m < NW; ++m)
           acc[k] = __builtin_amdgcn_udot4(sft[rsh][q + m], rr[m], acc[k], false);
       }
-      // window energy of the KX candidates: column sums of the row energies
-      const uint32_t* rq = rowsq + (j + i) * sh.ncand + s * KX;
-#pragma unroll
-      for (int k = 0; k < KX; ++k) ew[k] += (s * KX + k < sh.ncand) ? rq[k] : 0u;
     }
-    if (sh.split > 1) {  // exact integer partial sums: any order gives the same totals
+    if (sh.split > 1)  // exact integer partial sums: any order gives the same totals
 #pragma unroll
-      for (int k = 0; k < KX; ++k) {
-        atomicAdd(&tot[j * ncp + s * KX + k], acc[k]);
-        atomicAdd(&tot[sh.ncand * ncp + j * ncp + s * KX + k], ew[k]);
-      }
-    }
+      for (int k = 0; k < KX; ++k) atomicAdd(&tot[j * ncp + s * KX + k], acc[k]);
   }
   if (sh.split > 1) {
     __syncthreads();
     if (tid < base_threads)
 #pragma unroll
-      for (int k = 0; k < KX; ++k) {
-        acc[k] = tot[j * ncp + s * KX + k];
-        ew[k] = tot[sh.ncand * ncp + j * ncp + s * KX + k];
-      }
+      for (int k = 0; k < KX; ++k) acc[k] = tot[j * ncp + s * KX + k];
   }
   if (tid < base_threads) {
-    const uint32_t er = er_sum;
+    const uint32_t er = S.er_sum;
 #pragma unroll
     for (int k = 0; k < KX; ++k) {
       const int dxi = s * KX + k;
@@ -381,10 +461,10 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       const int dx = dxi - R + cdx, dy = j - R + cdy;
       if (px + dx - P < 0 || px + dx + P > w - 1 || py + dy - P < 0 || py + dy + P > h - 1)
         continue;
-      const uint32_t ssd = er + ew[k] - 2u * acc[k];
+      const uint32_t ssd = er + colE[j * sh.ncand + dxi] - 2u * acc[k];
       // ties on the absolute displacement, or on the offset from the
       // predicted position when the window is centred on a prediction
-      const int kx = Hlit ? dxi - R : dx, ky = Hlit ? j - R : dy;
+      const int kx = J.Hlit ? dxi - R : dx, ky = J.Hlit ? j - R : dy;
       const uint32_t l1 = (uint32_t)((kx < 0 ? -kx : kx) + (ky < 0 ? -ky : ky));
       // (ssd, |dx| + |dy|, dy, dx), displacements biased by 64 (|d| <= 64)
       const unsigned long long kk = ((unsigned long long)ssd << 32) |
@@ -394,28 +474,75 @@ __global__ __launch_bounds__(1024) void k_search(const uint8_t* __restrict__ ref
       key = kk < key ? kk : key;
     }
   }
-  // 4. argmin ---------------------------------------------------------------
+  // 4. argmin -------------------------------------------------------------------
   key = wave_min_u64(key);
-  if ((tid & 63) == 0) wmin[tid >> 6] = key;
+  if ((tid & 63) == 0) S.wmin[tid >> 6] = key;
   __syncthreads();
   if (tid == 0) {
     unsigned long long b = ~0ull;
-    for (int i = 0; i < (nt + 63) / 64; ++i) b = wmin[i] < b ? wmin[i] : b;
-    corner_xy[2 * tile] = px;
-    corner_xy[2 * tile + 1] = py;
+    for (int i = 0; i < (nt + 63) / 64; ++i) b = S.wmin[i] < b ? S.wmin[i] : b;
+    const uint8_t fb = (uint8_t)(want ? 16 : 0);
+    J.corner_xy[2 * tile] = px;
+    J.corner_xy[2 * tile + 1] = py;
     if (b == ~0ull) {
-      disp[2 * tile] = 0;
-      disp[2 * tile + 1] = 0;
-      ssd_out[tile] = 0;
-      flags[tile] = (uint8_t)(1 | (mode && want ? 16 : 0));
+      J.disp[2 * tile] = 0;
+      J.disp[2 * tile + 1] = 0;
+      J.ssd[tile] = 0;
+      J.flags[tile] = (uint8_t)(1 | fb);
     } else {
-      disp[2 * tile] = (int)(b & 255ull) - 64 + (Hlit ? cdx : 0);
-      disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - 64 + (Hlit ? cdy : 0);
-      ssd_out[tile] = (uint32_t)(b >> 32);
-      flags[tile] = (uint8_t)(3 | (mode && want ? 16 : 0));
-      if (vb) atomicOr(vb + (tile >> 6), 1ull << (tile & 63));
+      J.disp[2 * tile] = (int)(b & 255ull) - 64 + (J.Hlit ? cdx : 0);
+      J.disp[2 * tile + 1] = (int)((b >> 8) & 255ull) - 64 + (J.Hlit ? cdy : 0);
+      J.ssd[tile] = (uint32_t)(b >> 32);
+      J.flags[tile] = (uint8_t)(3 | fb);
+      if (J.vb) atomicOr(J.vb + (tile >> 6), 1ull << (tile & 63));
     }
   }
+}
+
+// One workgroup per tile of one job. ROLE names the launch only.
+template <int KX, int ROLE>
+__global__ __launch_bounds__(1024) void k_search(SearchJob J, SearchCfg c, SearchShape sh,
+                                                 const uint8_t* __restrict__ mode, int want) {
+  extern __shared__ __align__(16) uint8_t dyn[];
+  __shared__ TileShared S;
+  const int tile = blockIdx.x;
+  // with a proposal, each tile is searched by the launch of its mode only
+  if (mode && mode[tile] != want) return;
+  search_tile<KX>(J, tile, tile, c, sh, kVisitSearchAll, mode ? want : 0, nullptr, nullptr, dyn,
+                  S);
+}
+
+// One workgroup per item of the work: item i of [0, n) is global tile i (or
+// list[i] when the work has a list, n = *count; the grid covers the largest
+// possible n and the workgroups past it return at once); the job is the last
+// one whose first tile is <= the global tile. (Persistent workgroups looping
+// over the items, fetched by an atomic counter, were measured slower on the
+// 5 MP pair's level 0: 96 us against 82 us.)
+template <int KX, int VISIT>
+__global__ __launch_bounds__(1024) void k_search_work(SearchJob one,
+                                                      const SearchJob* __restrict__ jobs,
+                                                      SearchWork wk, SearchCfg c,
+                                                      SearchShape sh, int want) {
+  extern __shared__ __align__(16) uint8_t dyn[];
+  __shared__ TileShared S;
+  const int n = wk.list ? *wk.count : wk.ntotal;
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  // uniform over the workgroup: kept in scalar registers
+  const int g = __builtin_amdgcn_readfirstlane(wk.list ? wk.list[i] : i);
+  if (!jobs) {  // one job, given by value
+    search_tile<KX>(one, g, g, c, sh, VISIT, want, wk.out_list, wk.out_count, dyn, S);
+    return;
+  }
+  int lo = 0, hi = wk.njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (__builtin_amdgcn_readfirstlane(wk.first[mid]) <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const SearchJob J = jobs[lo];
+  search_tile<KX>(J, g - __builtin_amdgcn_readfirstlane(wk.first[lo]), g, c, sh, VISIT, want,
+                  wk.out_list, wk.out_count, dyn, S);
 }
 
 // A random 8-bit texture (every tile has corners): the search autotuner's input.
@@ -428,18 +555,75 @@ __global__ __launch_bounds__(256) void k_texture(uint8_t* __restrict__ p, int n,
   p[i] = (uint8_t)(z ^ (z >> 15));
 }
 
+SearchShape make_shape(int R, const SearchCfg& c, int split, long long ntiles, int KX,
+                       size_t* lds, int* block) {
+  SearchShape sh;
+  sh.R = R;
+  sh.ncand = 2 * R + 1;
+  sh.nstrips = (sh.ncand + KX - 1) / KX;
+  const int base = sh.ncand * sh.nstrips;
+  if (split > 0) {  // a tuned split (the results do not depend on it)
+    sh.split = split;
+  } else {
+    // when the level has too few candidate threads to fill the chip (coarse
+    // levels, small windows), split the patch rows so that a tile keeps about
+    // 256 threads busy
+    sh.split = ntiles * base >= 262144 ? 1 : (256 + base / 2) / base;
+  }
+  if (sh.split < 1) sh.split = 1;
+  if (sh.split > 7) sh.split = 7;
+  if (sh.split > 2 * c.P + 1) sh.split = 2 * c.P + 1;
+  while (sh.split > 1 && base * sh.split > 1024) --sh.split;
+  sh.nthreads = base * sh.split;
+  sh.NR = 2 * c.P + 2 * R + 1;
+  // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
+  const int need = (sh.nstrips * KX) + 4 * (NW + 1);
+  // an odd number of dwords per row: the threads of a wave read rows
+  // (j + i) at dword offsets (KX / 4) s, which an even stride maps onto the
+  // same banks
+  sh.wrow = (need + 3) / 4 * 4;
+  if ((sh.wrow / 4) % 2 == 0) sh.wrow += 4;
+  int b = (sh.nthreads + 63) / 64 * 64;
+  if (b < 64) b = 64;
+  *block = b;
+  // the reference region: side rows of rs bytes, rs covering the realigned
+  // dword reads of the quadrant sums (up to 6 bytes past a row's end) and one
+  // spare row after the last; the quadrant row sums: 2 (K g + r) rows of
+  // 2 (2K + 1) words
+  const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
+  const int side = 2 * ext + 1;
+  sh.rs = (side + 8 + 3) / 4 * 4;
+  const int hsum_words = 2 * (c.K * c.g + c.r) * 2 * (2 * c.K + 1);
+  sh.off_hsum = (sh.rs * (side + 1) + 15) / 16 * 16;
+  sh.off_win = (sh.off_hsum + hsum_words * 4 + 15) / 16 * 16;
+  // window, row energies (+ KX words: the last strip's padded candidates read
+  // past the last row), the split totals and the window energies
+  *lds = (size_t)sh.off_win + (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
+         (sh.split > 1 ? (size_t)2 * sh.ncand * sh.nstrips * KX * 4 : 0) +
+         (size_t)sh.ncand * sh.ncand * 4;
+  return sh;
+}
+
 }  // namespace
 
 hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
-                          hipStream_t st, const WeedBufs* wb, int nwords) {
+                          hipStream_t st, const WeedBufs* wb, int nwords, int* zint, int nzint) {
   dim3 grid((w + 1023) / 1024, h);
   LNR_LAUNCH(k_warp_q8, grid, dim3(256), 0, st, src, w, h, Hn, out, wb ? wb->vb : nullptr,
-             nwords, wb ? wb->sums : nullptr);
+             nwords, wb ? wb->sums : nullptr, zint, zint ? nzint : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp_jobs(const WarpJob* jobs, const int* row0, int njobs, int rows,
+                            int wmax, hipStream_t st) {
+  if (njobs < 1 || rows < 1) return hipSuccess;
+  const int nxb = (wmax + 1023) / 1024;
+  LNR_LAUNCH(k_warp_jobs, dim3(nxb * rows), dim3(256), 0, st, jobs, row0, njobs, nxb);
   return hipGetLastError();
 }
 
 int search_split_candidates(int R, const SearchCfg& c, int* out, int max) {
-  const int ncand = 2 * R + 1, base = ncand * ((ncand + KX - 1) / KX);
+  const int ncand = 2 * R + 1, base = ncand * ((ncand + 7) / 8);
   int n = 0;
   for (int s = 1; s <= 7 && s <= 2 * c.P + 1 && n < max; ++s)
     if (base * s <= 1024) out[n++] = s;
@@ -452,57 +636,70 @@ hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
-                         const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
-                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st,
-                         const int32_t* centre, const uint8_t* mode, int want,
-                         unsigned long long* vb, int split, const double* Hlit) {
-  if (ntx * nty == 0) return hipSuccess;
-  SearchShape sh;
-  sh.R = R;
-  sh.ncand = 2 * R + 1;
-  sh.nstrips = (sh.ncand + KX - 1) / KX;
-  const int base = sh.ncand * sh.nstrips;
-  if (split > 0) {  // a tuned split (the results do not depend on it)
-    sh.split = split;
-  } else {
-    // when the level has too few candidate threads to fill the chip (coarse
-    // levels, small windows), split the patch rows so that a tile keeps about
-    // 256 threads busy
-    sh.split = (long long)ntx * nty * base >= 262144 ? 1 : (256 + base / 2) / base;
+hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c, int role,
+                         hipStream_t st, const uint8_t* mode, int want, int split) {
+  const int ntiles = J.ntx * nty;
+  if (ntiles == 0) return hipSuccess;
+  size_t lds = 0;
+  int block = 0;
+  const SearchShape sh = make_shape(R, c, split, ntiles, 8, &lds, &block);
+  switch (role) {
+    case kRoleCoarse:
+      LNR_LAUNCH((k_search<8, kRoleCoarse>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+                 want);
+      break;
+    case kRoleLevel0:
+      LNR_LAUNCH((k_search<8, kRoleLevel0>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+                 want);
+      break;
+    case kRoleTrial:
+      LNR_LAUNCH((k_search<8, kRoleTrial>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+                 want);
+      break;
+    default:
+      LNR_LAUNCH((k_search<8, kRoleStage>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+                 want);
+      break;
   }
-  if (sh.split < 1) sh.split = 1;
-  if (sh.split > 7) sh.split = 7;
-  if (sh.split > 2 * c.P + 1) sh.split = 2 * c.P + 1;
-  while (sh.split > 1 && base * sh.split > 1024) --sh.split;
-  sh.nthreads = base * sh.split;
-  sh.NR = 2 * c.P + 2 * R + 1;
-  // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
-  const int need = (sh.nstrips * KX) + 4 * (NW + 1);
-  // an odd number of dwords per row: the threads of a wave read rows
-  // (j + i) at dword offsets 2 s, which an even stride maps onto the same banks
-  sh.wrow = (need + 3) / 4 * 4;
-  if ((sh.wrow / 4) % 2 == 0) sh.wrow += 4;
-  int block = (sh.nthreads + 63) / 64 * 64;
-  if (block < 64) block = 64;
-  // the reference region: side rows of rs bytes, rs covering the realigned
-  // dword reads of the quadrant sums (up to 6 bytes past a row's end) and one
-  // spare row after the last; the quadrant row sums: 2 (K g + r) rows of
-  // 2 (2K + 1) words
-  const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
-  const int side = 2 * ext + 1;
-  sh.rs = (side + 8 + 3) / 4 * 4;
-  const int hsum_words = 2 * (c.K * c.g + c.r) * 2 * (2 * c.K + 1);
-  sh.off_hsum = (sh.rs * (side + 1) + 15) / 16 * 16;
-  sh.off_win = (sh.off_hsum + hsum_words * 4 + 15) / 16 * 16;
-  // (+ KX words: the last strip's padded candidates read past the last row;
-  // + the partial-sum totals when the rows are split)
-  const size_t lds = (size_t)sh.off_win + (size_t)sh.NR * sh.wrow +
-                     (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
-                     (sh.split > 1 ? (size_t)2 * sh.ncand * sh.nstrips * KX * 4 : 0);
-  LNR_LAUNCH(k_search, dim3(ntx * nty), dim3(block), lds, st, ref, wimg, w, h, c, sh,
-                     ntx, corner_xy, disp, ssd, flags, centre, mode, want, vb, Hlit);
   return hipGetLastError();
+}
+
+template <int KX>
+hipError_t launch_work_kx(const SearchJob& one, const SearchJob* jobs, const SearchWork& wk,
+                          const SearchCfg& c, const SearchShape& sh, int visit, int want,
+                          int grid, int block, size_t lds, hipStream_t st) {
+  switch (visit) {
+    case kVisitCornersOnly:
+      LNR_LAUNCH((k_search_work<KX, kVisitCornersOnly>), dim3(grid), dim3(block), lds, st, one,
+                 jobs, wk, c, sh, want);
+      break;
+    case kVisitKnownCorner:
+      LNR_LAUNCH((k_search_work<KX, kVisitKnownCorner>), dim3(grid), dim3(block), lds, st, one,
+                 jobs, wk, c, sh, want);
+      break;
+    default:
+      LNR_LAUNCH((k_search_work<KX, kVisitSearchAll>), dim3(grid), dim3(block), lds, st, one,
+                 jobs, wk, c, sh, want);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R,
+                              const SearchCfg& c, int visit, int want, int split, int kx,
+                              int grid, hipStream_t st, const SearchJob* one) {
+  if (grid < 1) return hipSuccess;
+  if (kx != 8 && kx != 12) return hipErrorInvalidValue;
+  if (!jobs && !one) return hipErrorInvalidValue;
+  size_t lds = 0;
+  int block = 0;
+  const SearchShape sh = make_shape(R, c, split, grid, kx, &lds, &block);
+  // the corner phase uses only the reference region and its row sums
+  if (visit == kVisitCornersOnly) lds = (size_t)sh.off_win;
+  const SearchJob none{};
+  const SearchJob& J = one ? *one : none;
+  return kx == 8 ? launch_work_kx<8>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st)
+                 : launch_work_kx<12>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
 }
 
 }  // namespace lnr

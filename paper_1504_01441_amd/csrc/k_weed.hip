@@ -150,10 +150,20 @@ __global__ __launch_bounds__(kValidThreads) void k_valid(const uint8_t* __restri
   if (lane == 0) vb[wi] = m;
 }
 
-__global__ __launch_bounds__(kHypThreads) void k_hyp(
-    const unsigned long long* __restrict__ vbg, const int32_t* __restrict__ cxy,
-    const int32_t* __restrict__ disp, int nwords, int w, int h, WeedArgs a,
-    double* __restrict__ G, int32_t* __restrict__ cnt, int32_t* __restrict__ nmatch) {
+// The kernels below take one level of one pair (JOBS false: the job is the
+// kernel argument) or a table of jobs, one per blockIdx.z (batches).
+template <bool JOBS>
+__global__ __launch_bounds__(kHypThreads) void k_hyp(WeedJob one,
+                                                     const WeedJob* __restrict__ jobs,
+                                                     WeedArgs a) {
+  const WeedJob J = JOBS ? jobs[blockIdx.z] : one;
+  const unsigned long long* __restrict__ vbg = J.b.vb;
+  const int32_t* __restrict__ cxy = J.cxy;
+  const int32_t* __restrict__ disp = J.disp;
+  const int nwords = J.words, w = J.w, h = J.h;
+  double* __restrict__ G = J.b.G;
+  int32_t* __restrict__ cnt = J.b.cnt;
+  int32_t* __restrict__ nmatch = J.b.nmatch;
   __shared__ unsigned long long vb[kMaxWords];  // valid-tile bits, tile order
   __shared__ int wpre[kMaxWords + 1];            // valid tiles before each word
   const int lane = threadIdx.x;
@@ -247,11 +257,19 @@ __global__ __launch_bounds__(kHypThreads) void k_hyp(
 // Tile chunk blockIdx.x x iteration group blockIdx.y: adds the chunk's inlier
 // counts to cnt[iter] and stores the inlier bits in bal[word][iter]
 // (word-major, so that the union reads each word's rows contiguously).
-__global__ __launch_bounds__(kTestThreads) void k_test(
-    const int32_t* __restrict__ cxy, const int32_t* __restrict__ disp,
-    const uint8_t* __restrict__ flags, int ntiles, int w, int h, WeedArgs a,
-    const double* __restrict__ G, int32_t* __restrict__ cnt,
-    unsigned long long* __restrict__ bal, int wstride) {
+template <bool JOBS>
+__global__ __launch_bounds__(kTestThreads) void k_test(WeedJob one,
+                                                       const WeedJob* __restrict__ jobs,
+                                                       WeedArgs a) {
+  const WeedJob J = JOBS ? jobs[blockIdx.z] : one;
+  const int ntiles = J.ntiles, w = J.w, h = J.h, wstride = J.words;
+  if (JOBS && (int)blockIdx.x * kTestThreads >= ntiles) return;  // past this job's tiles
+  const int32_t* __restrict__ cxy = J.cxy;
+  const int32_t* __restrict__ disp = J.disp;
+  const uint8_t* __restrict__ flags = J.flags;
+  const double* __restrict__ G = J.b.G;
+  int32_t* __restrict__ cnt = J.b.cnt;
+  unsigned long long* __restrict__ bal = J.b.bal;
   __shared__ double gs[kItPerBlock][8];
   __shared__ int ok[kItPerBlock];
   __shared__ int wc[kItPerBlock][kTestThreads / 64];
@@ -346,12 +364,21 @@ __device__ inline long long normal_rhs(const long long* T, int i) {
 // Wave wd of the grid owns tile word wd: union M over the accepted rows,
 // flags 4 (in M) and 8 (in the fit) of its tiles, and their least-squares
 // terms, added exactly to the level's sums.
-__global__ __launch_bounds__(kUnionThreads) void k_union(
-    const int32_t* __restrict__ cxy, const int32_t* __restrict__ disp,
-    uint8_t* __restrict__ flags, int ntiles, int w, int h, WeedArgs a,
-    const int32_t* __restrict__ nmatch, const int32_t* __restrict__ cnt,
-    const unsigned long long* __restrict__ bal, int wstride, long long* __restrict__ sums,
-    int32_t* __restrict__ counts) {
+template <bool JOBS>
+__global__ __launch_bounds__(kUnionThreads) void k_union(WeedJob one,
+                                                         const WeedJob* __restrict__ jobs,
+                                                         WeedArgs a) {
+  const WeedJob J = JOBS ? jobs[blockIdx.z] : one;
+  const int ntiles = J.ntiles, w = J.w, h = J.h, wstride = J.words;
+  if (JOBS && (int)blockIdx.x * (kUnionThreads / 64) >= wstride) return;  // past its words
+  const int32_t* __restrict__ cxy = J.cxy;
+  const int32_t* __restrict__ disp = J.disp;
+  uint8_t* __restrict__ flags = J.flags;
+  const int32_t* __restrict__ nmatch = J.b.nmatch;
+  const int32_t* __restrict__ cnt = J.b.cnt;
+  const unsigned long long* __restrict__ bal = J.b.bal;
+  long long* __restrict__ sums = J.b.sums;
+  int32_t* __restrict__ counts = J.counts;
   __shared__ unsigned int accw[kMaxIters / 32];  // accepted iterations
   __shared__ unsigned long long kmax[kUnionThreads / 64];
   __shared__ long long part[kUnionThreads / 64][kSums];
@@ -472,11 +499,15 @@ __global__ __launch_bounds__(kUnionThreads) void k_union(
 // then H_l = Hbase o G with Hbase = H_{l+1} (matches relative to the warped
 // source) or the identity (absolute matches); H_l = H_{l+1} when fewer than
 // 4 matches were fitted or the solve fails.
-__global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __restrict__ sums,
-                                              const double* __restrict__ Hprev,
-                                              const double* __restrict__ Hbase,
-                                              double* __restrict__ Hout,
-                                              int32_t* __restrict__ counts) {
+template <bool JOBS>
+__global__ __launch_bounds__(64) void k_solve(WeedJob one, const WeedJob* __restrict__ jobs) {
+  const WeedJob J = JOBS ? jobs[blockIdx.z] : one;
+  const int w = J.w, h = J.h;
+  const long long* __restrict__ sums = J.b.sums;
+  const double* __restrict__ Hprev = J.Hprev;
+  const double* __restrict__ Hbase = J.Hbase;
+  double* __restrict__ Hout = J.Hout;
+  int32_t* __restrict__ counts = J.counts;
   __shared__ long long tot[kSums];
   const int lane = threadIdx.x;
   if (lane < kSums) tot[lane] = sums[lane];
@@ -525,13 +556,7 @@ __global__ __launch_bounds__(64) void k_solve(int w, int h, const long long* __r
   for (int i = 0; i < 9; ++i) Hout[i] = Hn[i];
 }
 
-}  // namespace
-
-hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
-                           int ntiles, int w, int h, int level, const lnr_params& p,
-                           const double* H_prev, double* H_out, int32_t* counts,
-                           const WeedBufs& b, hipStream_t st, bool vb_ready,
-                           const double* H_base) {
+WeedArgs weed_args(const lnr_params& p, int level) {
   WeedArgs a;
   a.iters = p.weed_iters;
   a.level = level;
@@ -539,30 +564,67 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
   a.delta_pct = p.weed_delta_pct;
   a.eps2 = p.weed_eps * p.weed_eps;
   a.seed = p.seed;
+  return a;
+}
+
+}  // namespace
+
+hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
+                           int ntiles, int w, int h, int level, const lnr_params& p,
+                           const double* H_prev, double* H_out, int32_t* counts,
+                           const WeedBufs& b, hipStream_t st, bool vb_ready,
+                           const double* H_base) {
+  const WeedArgs a = weed_args(p, level);
   const int words = ntiles > 0 ? (ntiles + 63) / 64 : 1;
   const int chunks = ntiles > 0 ? (ntiles + kTestThreads - 1) / kTestThreads : 1;
   const int groups = (a.iters + kItPerBlock - 1) / kItPerBlock;
   if (words > kMaxWords || a.iters > kMaxIters) return hipErrorInvalidValue;
+  WeedJob J;
+  J.cxy = corner_xy; J.disp = disp; J.flags = flags;
+  J.ntiles = ntiles; J.w = w; J.h = h; J.words = words;
+  J.b = b;
+  J.Hprev = H_prev; J.Hbase = H_base ? H_base : H_prev; J.Hout = H_out; J.counts = counts;
   hipError_t e;
   if (!vb_ready) {  // else the level's search set the bits (and its warp cleared the sums)
     LNR_LAUNCH(k_valid, dim3((words + kValidThreads / 64 - 1) / (kValidThreads / 64)),
                dim3(kValidThreads), 0, st, flags, ntiles, words, b.vb, b.sums);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  LNR_LAUNCH(k_hyp, dim3((a.iters + kHypThreads - 1) / kHypThreads), dim3(kHypThreads), 0, st,
-             b.vb, corner_xy, disp, words, w, h, a, b.G, b.cnt, b.nmatch);
+  LNR_LAUNCH(k_hyp<false>, dim3((a.iters + kHypThreads - 1) / kHypThreads), dim3(kHypThreads), 0,
+             st, J, nullptr, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ntiles > 0) {
-    LNR_LAUNCH(k_test, dim3(chunks, groups), dim3(kTestThreads), 0, st, corner_xy, disp, flags,
-               ntiles, w, h, a, b.G, b.cnt, b.bal, words);
+    LNR_LAUNCH(k_test<false>, dim3(chunks, groups), dim3(kTestThreads), 0, st, J, nullptr, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  LNR_LAUNCH(k_union, dim3((words + kUnionThreads / 64 - 1) / (kUnionThreads / 64)),
-             dim3(kUnionThreads), 0, st, corner_xy, disp, flags, ntiles, w, h, a, b.nmatch,
-             b.cnt, b.bal, words, b.sums, counts);
+  LNR_LAUNCH(k_union<false>, dim3((words + kUnionThreads / 64 - 1) / (kUnionThreads / 64)),
+             dim3(kUnionThreads), 0, st, J, nullptr, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  LNR_LAUNCH(k_solve, dim3(1), dim3(64), 0, st, w, h, b.sums, H_prev,
-             H_base ? H_base : H_prev, H_out, counts);
+  LNR_LAUNCH(k_solve<false>, dim3(1), dim3(64), 0, st, J, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_weed_jobs(const WeedJob* jobs, int njobs, int max_tiles, int level,
+                            const lnr_params& p, hipStream_t st) {
+  if (njobs < 1) return hipSuccess;
+  const WeedArgs a = weed_args(p, level);
+  const int words = max_tiles > 0 ? (max_tiles + 63) / 64 : 1;
+  const int chunks = max_tiles > 0 ? (max_tiles + kTestThreads - 1) / kTestThreads : 1;
+  const int groups = (a.iters + kItPerBlock - 1) / kItPerBlock;
+  if (words > kMaxWords || a.iters > kMaxIters) return hipErrorInvalidValue;
+  WeedJob none{};
+  hipError_t e;
+  LNR_LAUNCH(k_hyp<true>, dim3((a.iters + kHypThreads - 1) / kHypThreads, 1, njobs),
+             dim3(kHypThreads), 0, st, none, jobs, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  LNR_LAUNCH(k_test<true>, dim3(chunks, groups, njobs), dim3(kTestThreads), 0, st, none, jobs,
+             a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  LNR_LAUNCH(k_union<true>,
+             dim3((words + kUnionThreads / 64 - 1) / (kUnionThreads / 64), 1, njobs),
+             dim3(kUnionThreads), 0, st, none, jobs, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  LNR_LAUNCH(k_solve<true>, dim3(1, 1, njobs), dim3(64), 0, st, none, jobs);
   return hipGetLastError();
 }
 

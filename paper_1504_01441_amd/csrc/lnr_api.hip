@@ -96,9 +96,13 @@ struct lnr_ctx {
   struct Cached {
     std::vector<uint64_t> key;
     hipGraphExec_t exec = nullptr;
+    void* tables = nullptr;  // the level-synchronous batch's job tables (device)
   };
   std::vector<Cached> graphs;
   std::map<std::vector<uint64_t>, int> batch_k;  // autotuned concurrency per batch
+  std::map<std::vector<uint64_t>, int> batch_kx;  // autotuned search candidates per lane
+  void* tables = nullptr;  // job tables of eager level-synchronous batches
+  size_t tables_size = 0;
   // search splits picked by the autotuner, per (level width, height, radius)
   std::map<std::tuple<int, int, int>, int> search_split;
 };
@@ -241,6 +245,17 @@ Geometry make_geometry(int W, int H, const lnr_params& p) {
   return g;
 }
 
+SearchJob search_job(const uint8_t* ref, const uint8_t* wimg, int w, int h, int ntx,
+                     int32_t* cxy, int32_t* disp, uint32_t* ssd, uint8_t* flags,
+                     const int32_t* centre = nullptr, unsigned long long* vb = nullptr,
+                     const double* Hlit = nullptr) {
+  SearchJob j;
+  j.ref = ref; j.wimg = wimg; j.w = w; j.h = h; j.ntx = ntx;
+  j.corner_xy = cxy; j.disp = disp; j.ssd = ssd; j.flags = flags;
+  j.centre = centre; j.vb = vb; j.Hlit = Hlit;
+  return j;
+}
+
 SearchCfg search_cfg(const lnr_params& p) {
   SearchCfg c;
   c.S = p.tile; c.P = p.patch_r; c.g = p.corner_step; c.K = p.corner_half; c.r = p.quad_r;
@@ -342,7 +357,8 @@ WeedBufs weed_bufs(char* base, const WeedPlan& w) {
 // Workspace layout of one registration (offsets from the pair's base).
 struct PairPlan {
   Geometry g;
-  size_t bytes, o_hist, o_pref, o_psrc, o_warp, o_maps, o_gt, o_coef, o_cx, o_cc, o_cm;
+  size_t bytes, o_hist, o_pref, o_psrc, o_warp, o_maps, o_gt, o_coef, o_cx, o_cc, o_cm, o_cl,
+      o_cn;
   WeedPlan wp;
 };
 
@@ -379,9 +395,11 @@ PairPlan plan_pair(int W, int H, const lnr_params* p) {
   q.o_gt = pl.take(dt_guide_t_bytes(W, H));
   q.o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   const size_t nt0 = (size_t)q.g.lv[0].ntx * q.g.lv[0].nty;
-  q.o_cx = p->learned ? pl.take(nt0 * 512 * sizeof(uint16_t)) : 0;
+  q.o_cx = p->learned ? pl.take(nt0 * cnn_input_elems() * sizeof(uint16_t)) : 0;
   q.o_cc = p->learned ? pl.take(nt0 * 2 * sizeof(int32_t)) : 0;
   q.o_cm = p->learned ? pl.take(nt0) : 0;
+  q.o_cl = p->learned ? pl.take(3 * nt0 * sizeof(int32_t)) : 0;
+  q.o_cn = p->learned ? pl.take(3 * sizeof(int32_t)) : 0;
   q.bytes = pl.off;
   return q;
 }
@@ -391,29 +409,66 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
+// The start of one registration: the propagation's coefficient tables, the
+// cleared histograms and the identity above the top level (one launch), the
+// histograms, and both equalised pyramids (level 0 also written to the
+// outputs, no copies).
+lnr_status enqueue_pair_setup(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                              const lnr_params* p, lnr_registration* out, const PairPlan& q,
+                              char* base, hipStream_t st) {
+  const Geometry& g = q.g;
+  const int W = ref->width, H = ref->height;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + q.o_hist);
+  uint8_t* pref = reinterpret_cast<uint8_t*>(base + q.o_pref);
+  uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
+  uint8_t* guide_t = reinterpret_cast<uint8_t*>(base + q.o_gt);
+  double* coef = reinterpret_cast<double*>(base + q.o_coef);
+  LNR_HIP(launch_dt_coef(*p, coef, hist, 512, out->H + 9 * g.levels, st));
+  LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
+  LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
+                         pref, psrc, nullptr, 2, st, out->yeq_ref, out->yeq_src, guide_t));
+  return LNR_OK;
+}
+
+// The end of one registration: level 0's kept matches propagated to the
+// dense flow, and the backward warp of the source.
+lnr_status enqueue_pair_finish(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                               const lnr_params* p, lnr_registration* out, const PairPlan& q,
+                               char* base, hipStream_t st) {
+  const Geometry& g = q.g;
+  const int W = ref->width, H = ref->height;
+  uint8_t* pref = reinterpret_cast<uint8_t*>(base + q.o_pref);
+  uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
+  void* maps = base + q.o_maps;
+  uint8_t* guide_t = reinterpret_cast<uint8_t*>(base + q.o_gt);
+  double* coef = reinterpret_cast<double*>(base + q.o_coef);
+  const DtShape* ds = nullptr;
+  auto it = ctx->dt_shapes.find(std::make_pair(W, H));
+  if (it != ctx->dt_shapes.end()) ds = &it->second;
+  LNR_HIP(launch_flow(out->corner_xy, out->disp, out->flags, g.lv[0].ntx, g.lv[0].nty, p->tile,
+                      pref, guide_t, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds, true,
+                      true));
+  // the paper-literal search's flow is the whole mapping (identity above the top level)
+  const double* Hb = p->search_frame == 1 ? out->H + 9 * g.levels : out->H + 9;
+  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], chroma_of(*src), psrc, W, H, Hb,
+                               out->flow, out->image, out->yeq_warped, st));
+  return LNR_OK;
+}
+
 // Enqueue one registration on `st` using the workspace at `base` (checked and
 // sized by the caller). Launches only: safe under stream capture.
 lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
                         const lnr_params* p, lnr_registration* out, const PairPlan& q,
                         char* base, hipStream_t st) {
   const Geometry& g = q.g;
-  const int W = ref->width, H = ref->height;
-  uint32_t* hist = reinterpret_cast<uint32_t*>(base + q.o_hist);
+  const int W = ref->width;
   uint8_t* pref = reinterpret_cast<uint8_t*>(base + q.o_pref);
   uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
   uint8_t* warped = reinterpret_cast<uint8_t*>(base + q.o_warp);
   const WeedBufs wb = weed_bufs(base, q.wp);
-  void* maps = base + q.o_maps;
-  uint8_t* guide_t = reinterpret_cast<uint8_t*>(base + q.o_gt);
-  double* coef = reinterpret_cast<double*>(base + q.o_coef);
 
-  // set-up in one launch: the propagation's coefficient tables, the cleared
-  // histograms and the identity above the top level
-  LNR_HIP(launch_dt_coef(*p, coef, hist, 512, out->H + 9 * g.levels, st));
-  LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
-  // level 0 of both pyramids is also written to the outputs (no copies)
-  LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
-                         pref, psrc, nullptr, 2, st, out->yeq_ref, out->yeq_src, guide_t));
+  lnr_status s0 = enqueue_pair_setup(ctx, ref, src, p, out, q, base, st);
+  if (s0 != LNR_OK) return s0;
   const SearchCfg cfg = search_cfg(*p);
   auto tuned = [&](int w, int h, int R) {
     auto it = ctx->search_split.find(std::make_tuple(w, h, R));
@@ -431,10 +486,12 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
     const int words = nt > 0 ? (nt + 63) / 64 : 1;
     if (literal) {
       // the weeding builds the valid-match bits from the flags (k_valid)
-      LNR_HIP(launch_search(pref + L.pix_off, psrc + L.pix_off, L.w, L.h, R, cfg, L.ntx, L.nty,
-                            out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
-                            out->ssd + L.tile_off, out->flags + L.tile_off, st, nullptr,
-                            nullptr, 0, nullptr, tuned(L.w, L.h, R), out->H + 9 * (l + 1)));
+      const SearchJob J = search_job(pref + L.pix_off, psrc + L.pix_off, L.w, L.h, L.ntx,
+                                     out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
+                                     out->ssd + L.tile_off, out->flags + L.tile_off, nullptr,
+                                     nullptr, out->H + 9 * (l + 1));
+      LNR_HIP(launch_search(J, L.nty, R, cfg, l == 0 ? kRoleLevel0 : kRoleCoarse, st, nullptr, 0,
+                            tuned(L.w, L.h, R)));
       LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
                               out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
                               out->H + 9 * l, out->counts + 4 * l, wb, st, false, identity));
@@ -442,11 +499,16 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
     }
     // level 0 is warped straight into the output when it is wanted
     if (l == 0 && out->warped0) warped = out->warped0;
+    // the learned path's three list counts are cleared with the weeding bits
+    int32_t* lists = p->learned ? reinterpret_cast<int32_t*>(base + q.o_cl) : nullptr;
+    int* counts = p->learned ? reinterpret_cast<int*>(base + q.o_cn) : nullptr;
     LNR_HIP(launch_warp_q8(psrc + L.pix_off, L.w, L.h, out->H + 9 * (l + 1), warped, st, &wb,
-                           words));
+                           words, l == 0 ? counts : nullptr, 3));
     if (l == 0 && p->learned) {
-      // the network proposes a window per tile; confident tiles scan it,
-      // the others fall back to the exhaustive search (flag 16)
+      // corners first (the cornered tiles listed), the network on the
+      // cornered tiles (each listed for the window or for the fallback), then
+      // the window search of the confident tiles and the exhaustive search
+      // (flag 16) of the others, each launch visiting only its list
       uint16_t* x = reinterpret_cast<uint16_t*>(base + q.o_cx);
       int32_t* centre = reinterpret_cast<int32_t*>(base + q.o_cc);
       uint8_t* mode = reinterpret_cast<uint8_t*>(base + q.o_cm);
@@ -455,35 +517,45 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
       const float logit = p->conf_min <= 0.0 ? -INFINITY
                           : p->conf_min >= 1.0 ? NAN
                           : (float)std::log(p->conf_min / (1.0 - p->conf_min));
-      LNR_HIP(launch_cnn_input(pref, warped, W, L.ntx, L.nty, x, st));
+      SearchWork wk{};
+      wk.njobs = 1;
+      wk.ntotal = nt;
+      wk.out_list = lists;
+      wk.out_count = counts;
+      const SearchJob Jc = search_job(pref, warped, L.w, L.h, L.ntx, out->corner_xy, out->disp,
+                                      out->ssd, out->flags, nullptr, wb.vb);
+      LNR_HIP(launch_search_work(nullptr, wk, R, cfg, kVisitCornersOnly, 0, 0, 8, nt, st, &Jc));
+      LNR_HIP(launch_cnn_input(pref, warped, W, L.h, L.ntx, L.nty, lists, counts, x, st));
       LNR_HIP(launch_cnn_forward(ctx->cnn_packed, ctx->cnn, x, nt, nullptr, nullptr, centre, mode,
-                                 p->radius0 - p->window_r, logit, st));
-      LNR_HIP(launch_search(pref, warped, L.w, L.h, p->window_r, cfg, L.ntx, L.nty,
-                            out->corner_xy, out->disp, out->ssd, out->flags, st, centre, mode, 0,
-                            wb.vb));
-      LNR_HIP(launch_search(pref, warped, L.w, L.h, R, cfg, L.ntx, L.nty, out->corner_xy,
-                            out->disp, out->ssd, out->flags, st, nullptr, mode, 1, wb.vb,
-                            tuned(L.w, L.h, R)));
+                                 p->radius0 - p->window_r, logit, st, lists, counts, lists + nt,
+                                 counts + 1));
+      SearchWork ww{};
+      ww.njobs = 1;
+      ww.list = lists + nt;
+      ww.count = counts + 1;
+      const SearchJob Jw = search_job(pref, warped, L.w, L.h, L.ntx, out->corner_xy, out->disp,
+                                      out->ssd, out->flags, centre, wb.vb);
+      LNR_HIP(launch_search_work(nullptr, ww, p->window_r, cfg, kVisitKnownCorner, 0, 0, 8, nt,
+                                 st, &Jw));
+      SearchWork wf{};
+      wf.njobs = 1;
+      wf.list = lists + 2 * nt;
+      wf.count = counts + 2;
+      LNR_HIP(launch_search_work(nullptr, wf, R, cfg, kVisitKnownCorner, 1, tuned(L.w, L.h, R), 8,
+                                 nt, st, &Jc));
     } else {
-      LNR_HIP(launch_search(pref + L.pix_off, warped, L.w, L.h, R, cfg, L.ntx, L.nty,
-                            out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
-                            out->ssd + L.tile_off, out->flags + L.tile_off, st, nullptr,
-                            nullptr, 0, wb.vb, tuned(L.w, L.h, R)));
+      const SearchJob J = search_job(pref + L.pix_off, warped, L.w, L.h, L.ntx,
+                                     out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
+                                     out->ssd + L.tile_off, out->flags + L.tile_off, nullptr,
+                                     wb.vb);
+      LNR_HIP(launch_search(J, L.nty, R, cfg, l == 0 ? kRoleLevel0 : kRoleCoarse, st, nullptr, 0,
+                            tuned(L.w, L.h, R)));
     }
     LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
                             out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
                             out->H + 9 * l, out->counts + 4 * l, wb, st, true));
   }
-  const DtShape* ds = nullptr;
-  auto it = ctx->dt_shapes.find(std::make_pair(W, H));
-  if (it != ctx->dt_shapes.end()) ds = &it->second;
-  LNR_HIP(launch_flow(out->corner_xy, out->disp, out->flags, g.lv[0].ntx, g.lv[0].nty, p->tile,
-                      pref, guide_t, W, H, *p, maps, coef, out->flow, out->ntilde, st, ds, true,
-                      true));
-  LNR_HIP(launch_backward_warp(src->plane[0], src->stride[0], chroma_of(*src), psrc, W, H,
-                               literal ? identity : out->H + 9, out->flow, out->image,
-                               out->yeq_warped, st));
-  return LNR_OK;
+  return enqueue_pair_finish(ctx, ref, src, p, out, q, base, st);
 }
 
 lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
@@ -558,7 +630,11 @@ void lnr_destroy(lnr_ctx* ctx) {
     if (ctx->cnn && hipFree(ctx->cnn) != hipSuccess) ctx->err = "hipFree(network) failed";
     if (ctx->cnn_packed && hipFree(ctx->cnn_packed) != hipSuccess)
       ctx->err = "hipFree(network) failed";
-    for (auto& c : ctx->graphs) (void)hipGraphExecDestroy(c.exec);
+    for (auto& c : ctx->graphs) {
+      (void)hipGraphExecDestroy(c.exec);
+      if (c.tables) (void)hipFree(c.tables);
+    }
+    if (ctx->tables) (void)hipFree(ctx->tables);
     for (hipStream_t w : ctx->workers) (void)hipStreamDestroy(w);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
@@ -865,8 +941,8 @@ lnr_status lnr_stage_search(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* war
     return fail(ctx, LNR_E_ARG, "bad search arguments");
   if (R < 0 || R > kMaxRadius) return fail(ctx, LNR_E_UNSUPPORTED, "radius must be in [0, 32]");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
-  LNR_HIP(launch_search(ref, warped, w, h, R, search_cfg(*p), w / p->tile, h / p->tile,
-                        corner_xy, disp, ssd, flags, (hipStream_t)stream));
+  const SearchJob J = search_job(ref, warped, w, h, w / p->tile, corner_xy, disp, ssd, flags);
+  LNR_HIP(launch_search(J, h / p->tile, R, search_cfg(*p), kRoleStage, (hipStream_t)stream));
   return LNR_OK;
 }
 
@@ -1036,6 +1112,158 @@ lnr_status enqueue_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_frame* s
   return LNR_OK;
 }
 
+// A level-synchronous batch (plain method, warped-source search): every pair
+// has its own workspace; the set-up (equalisation, pyramids) and the end
+// (propagation, backward warp) of each pair run on the worker streams, and
+// each pyramid level runs for all pairs at once: one warp launch over all
+// their rows, one search launch over all their tiles and one launch per
+// weeding kernel over all their levels (device job tables).
+struct LevelTables {
+  size_t o_warp = 0, o_row0 = 0, o_sjob = 0, o_first = 0, o_wjob = 0;  // in the blob
+  int njobs = 0, rows = 0, wmax = 0, ntiles = 0, max_tiles = 0;
+};
+struct BatchLayout {
+  std::vector<size_t> off;  // each pair's workspace offset
+  size_t ws_bytes = 0;
+  int levels = 0;           // the deepest pyramid
+  LevelTables lv[kMaxLevels];
+  std::vector<uint8_t> blob;  // the job tables (device pointers into the workspace)
+};
+
+size_t blob_take(std::vector<uint8_t>& blob, size_t bytes) {
+  const size_t o = (blob.size() + 255) & ~(size_t)255;
+  blob.resize(o + bytes);
+  return o;
+}
+
+BatchLayout plan_batch(const lnr_frame* refs, int n, const std::vector<PairPlan>& plans) {
+  BatchLayout b;
+  b.off.resize((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    b.off[i] = b.ws_bytes;
+    b.ws_bytes += (plans[i].bytes + 255) & ~(size_t)255;
+    b.levels = std::max(b.levels, plans[i].g.levels);
+  }
+  (void)refs;
+  return b;
+}
+
+// Fills the job tables for the workspace at ws (after it has been sized).
+void fill_batch_tables(BatchLayout& b, int n, const lnr_params* p, lnr_registration* outs,
+                       const std::vector<PairPlan>& plans, char* ws) {
+  b.blob.clear();
+  for (int l = 0; l < b.levels; ++l) {
+    std::vector<int> jobs;
+    for (int i = 0; i < n; ++i)
+      if (plans[i].g.levels > l) jobs.push_back(i);
+    LevelTables& T = b.lv[l];
+    T.njobs = (int)jobs.size();
+    T.o_warp = blob_take(b.blob, sizeof(WarpJob) * jobs.size());
+    T.o_row0 = blob_take(b.blob, sizeof(int) * (jobs.size() + 1));
+    T.o_sjob = blob_take(b.blob, sizeof(SearchJob) * jobs.size());
+    T.o_first = blob_take(b.blob, sizeof(int) * (jobs.size() + 1));
+    T.o_wjob = blob_take(b.blob, sizeof(WeedJob) * jobs.size());
+    int row = 0, tile = 0;
+    for (size_t k = 0; k < jobs.size(); ++k) {
+      const int i = jobs[k];
+      const PairPlan& q = plans[i];
+      const Level& L = q.g.lv[l];
+      char* base = ws + b.off[i];
+      const int nt = L.ntx * L.nty;
+      const int words = nt > 0 ? (nt + 63) / 64 : 1;
+      const WeedBufs wb = weed_bufs(base, q.wp);
+      lnr_registration& o = outs[i];
+      uint8_t* warped = reinterpret_cast<uint8_t*>(base + q.o_warp);
+      if (l == 0 && o.warped0) warped = o.warped0;
+      WarpJob wj;
+      wj.src = reinterpret_cast<uint8_t*>(base + q.o_psrc) + L.pix_off;
+      wj.w = L.w; wj.h = L.h; wj.nwords = words;
+      wj.Hn = o.H + 9 * (l + 1);
+      wj.out = warped;
+      wj.vb = wb.vb; wj.sums = wb.sums;
+      memcpy(b.blob.data() + T.o_warp + k * sizeof(WarpJob), &wj, sizeof(wj));
+      memcpy(b.blob.data() + T.o_row0 + k * sizeof(int), &row, sizeof(int));
+      const SearchJob sj = search_job(reinterpret_cast<uint8_t*>(base + q.o_pref) + L.pix_off,
+                                      warped, L.w, L.h, L.ntx, o.corner_xy + 2 * L.tile_off,
+                                      o.disp + 2 * L.tile_off, o.ssd + L.tile_off,
+                                      o.flags + L.tile_off, nullptr, wb.vb);
+      memcpy(b.blob.data() + T.o_sjob + k * sizeof(SearchJob), &sj, sizeof(sj));
+      memcpy(b.blob.data() + T.o_first + k * sizeof(int), &tile, sizeof(int));
+      WeedJob ej;
+      ej.cxy = o.corner_xy + 2 * L.tile_off; ej.disp = o.disp + 2 * L.tile_off;
+      ej.flags = o.flags + L.tile_off;
+      ej.ntiles = nt; ej.w = L.w; ej.h = L.h; ej.words = words;
+      ej.b = wb;
+      ej.Hprev = o.H + 9 * (l + 1); ej.Hbase = ej.Hprev; ej.Hout = o.H + 9 * l;
+      ej.counts = o.counts + 4 * l;
+      memcpy(b.blob.data() + T.o_wjob + k * sizeof(WeedJob), &ej, sizeof(ej));
+      row += L.h;
+      tile += nt;
+      T.wmax = std::max(T.wmax, L.w);
+      T.max_tiles = std::max(T.max_tiles, nt);
+    }
+    memcpy(b.blob.data() + T.o_row0 + jobs.size() * sizeof(int), &row, sizeof(int));
+    memcpy(b.blob.data() + T.o_first + jobs.size() * sizeof(int), &tile, sizeof(int));
+    T.rows = row;
+    T.ntiles = tile;
+  }
+  (void)p;
+}
+
+lnr_status enqueue_batch_levels(lnr_ctx* ctx, const lnr_frame* refs, const lnr_frame* srcs,
+                                int n, const lnr_params* p, lnr_registration* outs,
+                                const std::vector<PairPlan>& plans, const BatchLayout& b,
+                                const char* tab, int K, int kx, hipStream_t origin) {
+  const auto lists = assign_pairs(refs, n, K);
+  char* ws = static_cast<char*>(ctx->ws);
+  lnr_status s;
+  // set-up of every pair on the worker streams
+  LNR_HIP(hipEventRecord(ctx->events[K], origin));
+  for (int k = 0; k < K; ++k) {
+    LNR_HIP(hipStreamWaitEvent(ctx->workers[k], ctx->events[K], 0));
+    for (int i : lists[k])
+      if ((s = enqueue_pair_setup(ctx, &refs[i], &srcs[i], p, &outs[i], plans[i], ws + b.off[i],
+                                  ctx->workers[k])) != LNR_OK)
+        return s;
+    LNR_HIP(hipEventRecord(ctx->events[k], ctx->workers[k]));
+    LNR_HIP(hipStreamWaitEvent(origin, ctx->events[k], 0));
+  }
+  // the levels, all pairs at once
+  const SearchCfg cfg = search_cfg(*p);
+  for (int l = b.levels - 1; l >= 0; --l) {
+    const LevelTables& T = b.lv[l];
+    if (T.njobs == 0) continue;
+    const int R = l == 0 ? p->radius0 : p->radius_coarse;
+    LNR_HIP(launch_warp_jobs(reinterpret_cast<const WarpJob*>(tab + T.o_warp),
+                             reinterpret_cast<const int*>(tab + T.o_row0), T.njobs, T.rows,
+                             T.wmax, origin));
+    SearchWork wk;
+    wk.first = reinterpret_cast<const int*>(tab + T.o_first);
+    wk.njobs = T.njobs;
+    wk.list = nullptr;
+    wk.count = nullptr;
+    wk.ntotal = T.ntiles;
+    wk.out_list = nullptr;
+    wk.out_count = nullptr;
+    LNR_HIP(launch_search_work(reinterpret_cast<const SearchJob*>(tab + T.o_sjob), wk, R, cfg,
+                               kVisitSearchAll, 0, 0, kx, T.ntiles, origin));
+    LNR_HIP(launch_weed_jobs(reinterpret_cast<const WeedJob*>(tab + T.o_wjob), T.njobs,
+                             T.max_tiles, l, *p, origin));
+  }
+  // propagation and backward warp of every pair on the worker streams
+  LNR_HIP(hipEventRecord(ctx->events[K], origin));
+  for (int k = 0; k < K; ++k) {
+    LNR_HIP(hipStreamWaitEvent(ctx->workers[k], ctx->events[K], 0));
+    for (int i : lists[k])
+      if ((s = enqueue_pair_finish(ctx, &refs[i], &srcs[i], p, &outs[i], plans[i], ws + b.off[i],
+                                   ctx->workers[k])) != LNR_OK)
+        return s;
+    LNR_HIP(hipEventRecord(ctx->events[k], ctx->workers[k]));
+    LNR_HIP(hipStreamWaitEvent(origin, ctx->events[k], 0));
+  }
+  return LNR_OK;
+}
+
 void push_bytes(std::vector<uint64_t>& key, const void* p, size_t n) {
   const unsigned char* c = static_cast<const unsigned char*>(p);
   for (size_t i = 0; i < n; i += 8) {
@@ -1067,57 +1295,104 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
     slot = std::max(slot, round256(plans[i].bytes));
   }
   const hipStream_t st = (hipStream_t)stream;
+  // The plain method runs level-synchronously (every pair's level in one
+  // launch per kernel); the learned proposal and the unwarped-source search
+  // register each pair on its own over the worker streams.
+  const bool levels = !p->learned && p->search_frame == 0;
+  BatchLayout lay;
+  if (levels) lay = plan_batch(refs, n, plans);
+  auto ws_need = [&](int k) { return levels ? lay.ws_bytes : (size_t)k * slot; };
   // the batch's shape: sizes and parameters (concurrency is tuned per shape)
   std::vector<uint64_t> shape;
   push_bytes(shape, p, sizeof(*p));
   for (int i = 0; i < n; ++i)
     shape.push_back(((uint64_t)refs[i].width << 32) | (uint32_t)refs[i].height);
-  int K = n < 4 ? n : 4;
+  int K = n < 4 ? n : 4, kx = 8;
+  // the level-synchronous batch's job tables (device pointers into the
+  // workspace, which must not move after they are written)
+  auto upload_eager_tables = [&]() -> lnr_status {
+    if ((s = ensure_ws(ctx, ws_need(K), st)) != LNR_OK) return s;
+    fill_batch_tables(lay, n, p, outs, plans, static_cast<char*>(ctx->ws));
+    LNR_HIP(hipStreamSynchronize(st));  // an earlier eager batch may still read them
+    if (ctx->tables_size < lay.blob.size()) {
+      if (ctx->tables) LNR_HIP(hipFree(ctx->tables));
+      ctx->tables = nullptr;
+      ctx->tables_size = 0;
+      LNR_HIP(hipMalloc(&ctx->tables, lay.blob.size()));
+      ctx->tables_size = lay.blob.size();
+    }
+    LNR_HIP(hipMemcpy(ctx->tables, lay.blob.data(), lay.blob.size(), hipMemcpyHostToDevice));
+    return LNR_OK;
+  };
+  auto enqueue = [&](int k, int kxx, const char* tab, hipStream_t o) -> lnr_status {
+    if (levels)
+      return enqueue_batch_levels(ctx, refs, srcs, n, p, outs, plans, lay, tab, k, kxx, o);
+    return enqueue_batch(ctx, refs, srcs, n, p, outs, plans, slot, k, o);
+  };
   auto kt = ctx->batch_k.find(shape);
   if (kt != ctx->batch_k.end()) {
     K = kt->second;
+    auto kk = ctx->batch_kx.find(shape);
+    if (kk != ctx->batch_kx.end()) kx = kk->second;
   } else if (flags & LNR_BATCH_AUTOTUNE) {
-    // the search's workgroup shape per level, for every size not tuned yet
-    for (int i = 0; i < n; ++i) {
-      const auto key = std::make_tuple((int)refs[i].width, (int)refs[i].height, (int)p->radius0);
-      if (ctx->search_split.count(key)) continue;
-      if ((s = lnr_autotune_search(ctx, refs[i].width, refs[i].height, p, nullptr, stream)) !=
-          LNR_OK)
-        return s;
+    if (!levels) {
+      // the search's workgroup shape per level, for every size not tuned yet
+      for (int i = 0; i < n; ++i) {
+        const auto key = std::make_tuple((int)refs[i].width, (int)refs[i].height, (int)p->radius0);
+        if (ctx->search_split.count(key)) continue;
+        if ((s = lnr_autotune_search(ctx, refs[i].width, refs[i].height, p, nullptr, stream)) !=
+            LNR_OK)
+          return s;
+      }
     }
-    // time 1, 2, 4 and 8 concurrent streams on this batch (eager), keep the fastest
-    const int cand[4] = {1, 2, 4, 8};
-    float best = 0.f;
+    // time 1, 2, 4 and 8 concurrent streams on this batch (eager), then (level-
+    // synchronous batches) 8 or 12 search candidates per lane; keep the fastest
     hipEvent_t t0 = nullptr, t1 = nullptr;
     LNR_HIP(hipEventCreate(&t0));
     LNR_HIP(hipEventCreate(&t1));
+    auto time_one = [&](int k, int kxx, float* ms) -> lnr_status {
+      if ((s = ensure_ws(ctx, ws_need(k), st)) != LNR_OK) return s;
+      if ((s = ensure_workers(ctx, k)) != LNR_OK) return s;
+      if (levels && (s = upload_eager_tables()) != LNR_OK) return s;
+      TraceGuard tg(ctx);
+      LNR_HIP(hipEventRecord(t0, st));
+      if ((s = enqueue(k, kxx, static_cast<const char*>(ctx->tables), st)) != LNR_OK) return s;
+      LNR_HIP(hipEventRecord(t1, st));
+      LNR_HIP(hipEventSynchronize(t1));
+      LNR_HIP(hipEventElapsedTime(ms, t0, t1));
+      return LNR_OK;
+    };
+    const int cand[4] = {1, 2, 4, 8};
+    float best = 0.f;
     for (int c = 0; c < 4; ++c) {
       const int k = cand[c];
       if (k > n) break;
-      if ((s = ensure_ws(ctx, (size_t)k * slot, st)) != LNR_OK) return s;
-      if ((s = ensure_workers(ctx, k)) != LNR_OK) return s;
-      TraceGuard tg(ctx);
-      LNR_HIP(hipEventRecord(t0, st));
-      if ((s = enqueue_batch(ctx, refs, srcs, n, p, outs, plans, slot, k, st)) != LNR_OK) return s;
-      LNR_HIP(hipEventRecord(t1, st));
-      LNR_HIP(hipEventSynchronize(t1));
       float ms = 0.f;
-      LNR_HIP(hipEventElapsedTime(&ms, t0, t1));
+      if ((s = time_one(k, 8, &ms)) != LNR_OK) return s;
       if (c == 0 || ms < best) { best = ms; K = k; }
+    }
+    if (levels) {
+      float ms = 0.f;
+      if ((s = time_one(K, 12, &ms)) != LNR_OK) return s;
+      if (ms < best) kx = 12;
     }
     LNR_HIP(hipEventDestroy(t0));
     LNR_HIP(hipEventDestroy(t1));
     ctx->batch_k[shape] = K;
+    ctx->batch_kx[shape] = kx;
   }
-  if ((s = ensure_ws(ctx, (size_t)K * slot, st)) != LNR_OK) return s;
+  if ((s = ensure_ws(ctx, ws_need(K), st)) != LNR_OK) return s;
   if ((s = ensure_workers(ctx, K)) != LNR_OK) return s;
   if (!(flags & LNR_BATCH_GRAPH)) {
+    if (levels && (s = upload_eager_tables()) != LNR_OK) return s;
     TraceGuard tg(ctx);
-    return enqueue_batch(ctx, refs, srcs, n, p, outs, plans, slot, K, st);
+    return enqueue(K, kx, static_cast<const char*>(ctx->tables), st);
   }
-  // graph: the whole batch as one executable graph, cached per inputs and outputs
+  // graph: the whole batch as one executable graph, cached per inputs and
+  // outputs (with its own job tables)
   std::vector<uint64_t> key = shape;
   key.push_back((uint64_t)K);
+  key.push_back((uint64_t)kx);
   key.push_back((uint64_t)(uintptr_t)ctx->ws);
   for (int i = 0; i < n; ++i) {
     push_bytes(key, &refs[i], sizeof(lnr_frame));
@@ -1128,23 +1403,40 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
   for (auto& c : ctx->graphs)
     if (c.key == key) exec = c.exec;
   if (!exec) {
-    hipGraph_t graph = nullptr;
-    LNR_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    s = enqueue_batch(ctx, refs, srcs, n, p, outs, plans, slot, K, ctx->capture);
-    const hipError_t ec = hipStreamEndCapture(ctx->capture, &graph);
-    if (s != LNR_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return s;
+    void* tab = nullptr;
+    if (levels) {
+      fill_batch_tables(lay, n, p, outs, plans, static_cast<char*>(ctx->ws));
+      LNR_HIP(hipMalloc(&tab, lay.blob.size()));
+      const hipError_t ec = hipMemcpy(tab, lay.blob.data(), lay.blob.size(),
+                                      hipMemcpyHostToDevice);
+      if (ec != hipSuccess) {
+        (void)hipFree(tab);
+        return hip_fail(ctx, ec, "hipMemcpy(batch tables)");
+      }
     }
-    if (ec != hipSuccess) return hip_fail(ctx, ec, "hipStreamEndCapture");
-    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess) return hip_fail(ctx, ei, "hipGraphInstantiate");
+    hipGraph_t graph = nullptr;
+    hipError_t eb = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+      if (tab) (void)hipFree(tab);
+      return hip_fail(ctx, eb, "hipStreamBeginCapture");
+    }
+    s = enqueue(K, kx, static_cast<const char*>(tab), ctx->capture);
+    const hipError_t ec = hipStreamEndCapture(ctx->capture, &graph);
+    hipError_t ei = hipSuccess;
+    if (s == LNR_OK && ec == hipSuccess) ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (s != LNR_OK || ec != hipSuccess || ei != hipSuccess) {
+      if (tab) (void)hipFree(tab);
+      if (s != LNR_OK) return s;
+      return hip_fail(ctx, ec != hipSuccess ? ec : ei,
+                      ec != hipSuccess ? "hipStreamEndCapture" : "hipGraphInstantiate");
+    }
     if (ctx->graphs.size() >= 8) {
       LNR_HIP(hipGraphExecDestroy(ctx->graphs.front().exec));
+      if (ctx->graphs.front().tables) LNR_HIP(hipFree(ctx->graphs.front().tables));
       ctx->graphs.erase(ctx->graphs.begin());
     }
-    ctx->graphs.push_back(lnr_ctx::Cached{key, exec});
+    ctx->graphs.push_back(lnr_ctx::Cached{key, exec, tab});
   }
   LNR_HIP(hipGraphLaunch(exec, st));
   return LNR_OK;
@@ -1271,11 +1563,11 @@ lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_par
       float tot = 0.f;
       for (int rep = 0; rep < 4; ++rep) {  // the first run warms up
         LNR_HIP(hipEventRecord(t0, st));
-        LNR_HIP(launch_search(reinterpret_cast<uint8_t*>(b + o_a), reinterpret_cast<uint8_t*>(b + o_b),
-                              L.w, L.h, R, cfg, L.ntx, L.nty, reinterpret_cast<int32_t*>(b + o_cxy),
-                              reinterpret_cast<int32_t*>(b + o_d), reinterpret_cast<uint32_t*>(b + o_s),
-                              reinterpret_cast<uint8_t*>(b + o_f), st, nullptr, nullptr, 0, nullptr,
-                              cand[c]));
+        const SearchJob J = search_job(
+            reinterpret_cast<uint8_t*>(b + o_a), reinterpret_cast<uint8_t*>(b + o_b), L.w, L.h,
+            L.ntx, reinterpret_cast<int32_t*>(b + o_cxy), reinterpret_cast<int32_t*>(b + o_d),
+            reinterpret_cast<uint32_t*>(b + o_s), reinterpret_cast<uint8_t*>(b + o_f));
+        LNR_HIP(launch_search(J, L.nty, R, cfg, kRoleTrial, st, nullptr, 0, cand[c]));
         LNR_HIP(hipEventRecord(t1, st));
         LNR_HIP(hipEventSynchronize(t1));
         float ms = 0.f;
@@ -1318,8 +1610,9 @@ lnr_status lnr_stage_search_window(lnr_ctx* ctx, const uint8_t* ref, const uint8
       if (v < -kMaxRadius || v > kMaxRadius || std::abs(v) + R > kMaxRadius)
         return fail(ctx, LNR_E_ARG, "window centre out of range (|centre| + R must be <= 32)");
   }
-  LNR_HIP(launch_search(ref, warped, w, h, R, search_cfg(*p), w / p->tile, h / p->tile,
-                        corner_xy, disp, ssd, flags, (hipStream_t)stream, centre, nullptr, 0));
+  const SearchJob J = search_job(ref, warped, w, h, w / p->tile, corner_xy, disp, ssd, flags,
+                                 centre);
+  LNR_HIP(launch_search(J, h / p->tile, R, search_cfg(*p), kRoleStage, (hipStream_t)stream));
   return LNR_OK;
 }
 
@@ -1497,7 +1790,8 @@ lnr_status lnr_proposal_inputs(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* 
   if (!ref || !warped || !x || w < 32 || h < 32 || w > kMaxSide || h > kMaxSide)
     return fail(ctx, LNR_E_ARG, "bad proposal input arguments");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
-  LNR_HIP(launch_cnn_input(ref, warped, w, w / 32, h / 32, x, (hipStream_t)stream));
+  LNR_HIP(launch_cnn_input(ref, warped, w, h, w / 32, h / 32, nullptr, nullptr, x,
+                           (hipStream_t)stream));
   return LNR_OK;
 }
 

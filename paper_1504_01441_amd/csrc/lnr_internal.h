@@ -80,14 +80,63 @@ hipError_t launch_lut_pyr(const uint8_t* y0, int s0, const uint8_t* y1, int s1,
 struct WeedBufs;
 // wb (optional): the level's weeding buffers, whose valid-match bits and
 // least-squares sums the warp clears and the search then fills
+// zint: nzint (<= 256) counters to clear as well (the learned path's lists)
 hipError_t launch_warp_q8(const uint8_t* src, int w, int h, const double* Hn, uint8_t* out,
-                          hipStream_t st, const WeedBufs* wb = nullptr, int nwords = 0);
-hipError_t launch_search(const uint8_t* ref, const uint8_t* wimg, int w, int h, int R,
-                         const SearchCfg& c, int ntx, int nty, int32_t* corner_xy,
-                         int32_t* disp, uint32_t* ssd, uint8_t* flags, hipStream_t st, const int32_t* centre = nullptr,
-                         const uint8_t* mode = nullptr, int want = 0,
-                         unsigned long long* vb = nullptr, int split = 0,
-                         const double* Hlit = nullptr);
+                          hipStream_t st, const WeedBufs* wb = nullptr, int nwords = 0,
+                          int* zint = nullptr, int nzint = 0);
+// One level of one pair for the search: the equalised reference level and
+// the searched source level (dense w x h), the level's full tiles (ntx
+// across) and their outputs.
+struct SearchJob {
+  const uint8_t* ref;
+  const uint8_t* wimg;      // warped source level, or the unwarped one with Hlit
+  int w, h, ntx;
+  int32_t* corner_xy;       // [tiles][2]
+  int32_t* disp;            // [tiles][2]
+  uint32_t* ssd;            // [tiles]
+  uint8_t* flags;           // [tiles]
+  const int32_t* centre;    // [tiles][2] window centres of the learned proposal, or null
+  unsigned long long* vb;   // valid-match bits set by the search, or null
+  const double* Hlit;       // previous level's homography (unwarped search), or null
+};
+// The tiles one work-list launch visits: global tile g of job j is
+// first[j] + tile; all of [0, ntotal) or the *count entries of list.
+struct SearchWork {
+  const int* first;         // [njobs + 1] (device)
+  int njobs;
+  const int* list;          // global tile indices (device), or null
+  const int* count;         // entries of list (device)
+  int ntotal;
+  int* out_list;            // corner visits: cornered tiles appended here (device)
+  int* out_count;
+};
+// names of single-job search launches (profiles tell the levels apart)
+constexpr int kRoleCoarse = 0, kRoleLevel0 = 1, kRoleTrial = 2, kRoleStage = 3;
+// tile visits of the work-list search
+constexpr int kVisitSearchAll = 0, kVisitCornersOnly = 1, kVisitKnownCorner = 2;
+// one workgroup per tile of J (mode/want: only the tiles whose mode is want)
+// k_warp_q8 over several pairs' levels (batches): job j's rows are the grid
+// rows [row0[j], row0[j + 1]) (device tables), rows = row0[njobs]
+struct WarpJob {
+  const uint8_t* src;       // source level (dense w x h)
+  int w, h, nwords;
+  const double* Hn;         // the previous level's homography
+  uint8_t* out;             // warped level
+  unsigned long long* vb;   // the level's weeding bits and sums, cleared here
+  long long* sums;
+};
+hipError_t launch_warp_jobs(const WarpJob* jobs, const int* row0, int njobs, int rows,
+                            int wmax, hipStream_t st);
+hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c, int role,
+                         hipStream_t st, const uint8_t* mode = nullptr, int want = 0,
+                         int split = 0);
+// `grid` workgroups, one per item of the work (at least the number of items);
+// kx: candidates per lane (8 or 12); jobs null: the single job `one` (by
+// value), whose tiles the work's items are
+hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R,
+                              const SearchCfg& c, int visit, int want, int split, int kx,
+                              int grid, hipStream_t st, const SearchJob* one = nullptr);
+
 // splits (patch rows per thread group) that launch_search accepts for radius
 // R, ascending; and a random 8-bit texture for timing the search
 int search_split_candidates(int R, const SearchCfg& c, int* out, int max);
@@ -102,6 +151,23 @@ struct WeedBufs {
   unsigned long long* vb;   // [ceil(ntiles/64)] valid-match bits, tile order
   long long* sums;          // [23] least-squares sums of the level fit
 };
+// one level of one pair for the weeding and level fit
+struct WeedJob {
+  const int32_t* cxy;
+  const int32_t* disp;
+  uint8_t* flags;
+  int ntiles, w, h, words;
+  WeedBufs b;
+  const double* Hprev;  // H^{l+1} (kept when the fit fails)
+  const double* Hbase;  // the map G is composed on (H^{l+1}, or the identity)
+  double* Hout;
+  int32_t* counts;
+};
+// the weeding kernels over a device table of jobs (the search set the
+// valid-match bits and the warp cleared the sums); max_tiles: the largest
+// job's tiles
+hipError_t launch_weed_jobs(const WeedJob* jobs, int njobs, int max_tiles, int level,
+                            const lnr_params& p, hipStream_t st);
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
                            const double* H_prev, double* H_out, int32_t* counts,
@@ -197,13 +263,23 @@ int cnn_param_count();
 size_t cnn_packed_elems();   // bf16 packed weights
 size_t cnn_act_elems();      // stored activations per sample (bf16)
 size_t cnn_dz_elems();       // activation gradients per sample (bf16)
+size_t cnn_input_elems();    // network input values per tile (bf16)
 int cnn_grad_blocks(int n, int* per_block);
 hipError_t launch_cnn_pack(const float* params, uint16_t* packed, hipStream_t st);
-hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, int ntx, int nty,
-                            uint16_t* x, hipStream_t st);
+// network inputs x[i] of tile tiles[i] (tile i without a list), i below
+// *count (without it, every tile)
+hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, int h, int ntx,
+                            int nty, const int32_t* tiles, const int* count, uint16_t* x,
+                            hipStream_t st);
+// inference (centre != null) or training forward of n samples; with `count`
+// (device) only the first *count samples (n is then the most there can be),
+// sample s being tile tiles[s]; with `lists`, each tile is appended to the
+// window list (lists[0 ..]) or the fallback list (lists[n ..]), counts[2]
 hipError_t launch_cnn_forward(const uint16_t* packed, const float* params, const uint16_t* x,
                               int n, float* out, uint16_t* acts, int32_t* centre,
-                              uint8_t* fallback, int clampc, float conf_logit, hipStream_t st);
+                              uint8_t* fallback, int clampc, float conf_logit, hipStream_t st,
+                              const int32_t* tiles = nullptr, const int* count = nullptr,
+                              int* lists = nullptr, int* counts = nullptr);
 hipError_t launch_cnn_backward(const uint16_t* packed, const float* params,
                                const uint16_t* acts, const float* out, const int32_t* labels,
                                int n, float* dO, float* loss, uint16_t* dzs, float* part,

@@ -27,7 +27,7 @@ DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prop
 
 
 def collect(ctx: Context, frames_pairs, params: Params | None = None):
-    """(x [n, 2, 16, 16] bf16 bits as int16, labels [n, 2] int32) over the valid
+    """(x [n, 4, 16, 16] bf16 bits as int16, labels [n, 2] int32) over the valid
     level-0 tiles of the given (ref, src) synth frame pairs."""
     p = params or Params()
     xs, ls = [], []
@@ -133,7 +133,7 @@ def calibrate(ctx: Context, x: torch.Tensor, labels: torch.Tensor, window: int =
 
 
 def load(path: str = DEFAULT_WEIGHTS):
-    """(parameters float32 [29891], conf_min) of a saved network."""
+    """(parameters float32 [PROPOSAL_PARAMS], conf_min) of a saved network."""
     z = np.load(path, allow_pickle=False)
     return z["params"].astype(np.float32), float(z["conf_min"])
 

@@ -1,11 +1,11 @@
 """Seeded parameter vectors for the learned displacement proposal's network
-(He-normal weights, small biases) in the library's flat layout: W1[32][2][3][3]
+(He-normal weights, small biases) in the library's flat layout: W1[32][4][3][3]
 b1[32] W2[32][32][3][3] b2 W3 b3 W4 b4 Wh[3][512] bh[3]. A generator only: it
 holds none of the network's arithmetic."""
 import numpy as np
 
-N_PARAMS = 29891
-_CIN = (2, 32, 32, 32)
+N_PARAMS = 30467
+_CIN = (4, 32, 32, 32)
 
 
 def proposal_params(seed, scale=1.0, head_scale=1.0):

@@ -38,11 +38,11 @@ def _bf16_bits(a):
 
 def _inputs(seed, n):
     rng = np.random.default_rng(seed)
-    return oracle.bf16(rng.uniform(-1, 1, (n, 2, 16, 16)))
+    return oracle.bf16(rng.uniform(-1, 1, (n, oracle.CNN_IN, 16, 16)))
 
 
 def _offsets():
-    cin = [2, 32, 32, 32]
+    cin = [oracle.CNN_IN, 32, 32, 32]
     off, o = [], 0
     for l in range(4):
         off.append((f"W{l + 1}", o, 32 * cin[l] * 9))
@@ -60,7 +60,7 @@ def test_inputs_bit_exact(lnr, ctx):
     x = lnr.proposal_inputs(ctx, torch.from_numpy(ref).cuda(), torch.from_numpy(wrp).cuda())
     want = oracle.cnn_tile_inputs(ref, wrp, range(12))
     got = x.view(torch.bfloat16).float().cpu().numpy()
-    assert got.shape == (12, 2, 16, 16)
+    assert got.shape == (12, 4, 16, 16)
     assert np.array_equal(got, want)
 
 
@@ -162,23 +162,37 @@ def _epe(reg, st, w, h):
     return float(np.mean(np.hypot(mx - gx, my - gy)[m]))
 
 
+def _median_ms(fn, reps=15):
+    import time
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return 1e3 * float(np.median(ts))
+
+
 def test_learned_registration_agreement_and_gain(lnr, ctx):
     """With the network trained on the GPU (paper_1504_01441_amd.proposal, from
     5 MP pairs labelled by the exhaustive search) and its confidence threshold
     set on held-out pairs: registering another 5 MP pair with the learned
-    proposal gives at least 99 % of level-0 tiles equal to the oracle's
-    exhaustive result, the same final warp error as the plain path, and saves
-    SSD candidate evaluations on the tiles searched in the small window."""
+    proposal searches a sixth or more of the cornered level-0 tiles only in the
+    +-2 window (SSD candidate evaluations at most 0.85 of the plain search's),
+    gives at least 99 % of level-0 tiles equal to the oracle's exhaustive
+    result and the same final warp error as the plain path (within 0.02 px).
+    The times of both are printed: on MI355X the learned registration is
+    slower (its network costs more than the candidates it saves)."""
     import os
     from paper_1504_01441_amd import proposal as prop
     if not os.path.exists(prop.DEFAULT_WEIGHTS):
         pytest.skip("no trained network (python -m paper_1504_01441_amd.proposal)")
-    P, _ = prop.load()
+    P, conf = prop.load()
     lnr.proposal_set(ctx, torch.from_numpy(P))
-    held = [synth.make_config_pair("c2", s) for s in (901, 902)]
-    xh, lh = prop.collect(ctx, [tuple(st.frames) for st in held])
-    conf, frac = prop.calibrate(ctx, xh, lh)
-    st = synth.make_config_pair("c2", 903)
+    st = synth.make_config_pair("c2", 1)   # the benchmark pair (not a training pair)
     f0, f1 = st.frames
     w, h = f0.width, f0.height
     ref = lnr.Frame.from_numpy(f0.y, f0.u, f0.v, f0.exposure)
@@ -198,17 +212,66 @@ def test_learned_registration_agreement_and_gain(lnr, ctx):
     window = cornered & ((fl & 16) == 0)
     full = (2 * 16 + 1) ** 2
     cand = window.sum() * 25 + (cornered.sum() - window.sum()) * full
-    print(f"confidence threshold {conf:.4f} ({100 * frac:.1f} % of held-out tiles); "
-          f"{window.sum()} of {cornered.sum()} tiles in the window; agreement "
-          f"{100 * same.mean():.2f} %; SSD candidates {cand / (cornered.sum() * full):.3f} "
-          f"of the plain search")
-    assert same.mean() >= 0.99, same.mean()
-    assert window.sum() >= 1 and cand < cornered.sum() * full
-    # equal final warp error: the mean distance to the generator's ground
-    # truth moves by at most 1 % (the few disagreeing tiles move the flow
-    # locally; the error itself is the method's on this workload)
+    t_p = _median_ms(lambda: lnr.register_pair(ctx, ref, src, pl, out=reg_p))
+    t_l = _median_ms(lambda: lnr.register_pair(ctx, ref, src, pq, out=reg_l))
     e_l, e_p = _epe(reg_l, st, w, h), _epe(reg_p, st, w, h)
-    assert abs(e_l - e_p) <= 0.01 * e_p + 0.02, (e_l, e_p)
+    print(f"confidence threshold {conf:.4f}; {window.sum()} of {cornered.sum()} tiles in the "
+          f"window; agreement {100 * same.mean():.2f} %; SSD candidates "
+          f"{cand / (cornered.sum() * full):.3f} of the plain search; registration "
+          f"{t_l:.3f} ms learned, {t_p:.3f} ms plain; end-point error {e_l:.4f} / {e_p:.4f} px")
+    assert same.mean() >= 0.99, same.mean()
+    assert window.sum() >= cornered.sum() / 6, (window.sum(), cornered.sum())
+    assert cand <= 0.85 * cornered.sum() * full
+    # equal final warp error against the generator's ground truth
+    assert abs(e_l - e_p) <= 0.02, (e_l, e_p)
+
+
+def test_learned_window_tiles_match_oracle_window_search(lnr, ctx):
+    """Inside a learned registration, every tile searched in the window gives
+    exactly the oracle's window search around the centre that the network
+    proposes for it (the centres recomputed from the network's outputs on the
+    registration's own level-0 inputs, in the kernel's float arithmetic), and
+    every other cornered tile the oracle's exhaustive search."""
+    P = synth.proposal_params(13, head_scale=4.0)
+    c = lnr.Context(0)
+    lnr.proposal_set(c, torch.from_numpy(P).cuda())
+    st = synth.make_stack(640, 480, 41, ratios=(1.0, 4.0), fmt="y8", shift_range=6)
+    f0, f1 = st.frames
+    conf = 0.5
+    pq = lnr.Params(radius0=8, learned=1, window_r=2, conf_min=conf)
+    reg = lnr.register_pair(c, lnr.Frame.from_numpy(f0.y), lnr.Frame.from_numpy(f1.y), pq)
+    x = lnr.proposal_inputs(c, reg.yeq_ref, reg.warped0)
+    out = lnr.proposal_forward(c, x).cpu().numpy()
+    torch.cuda.synchronize()
+    n0 = reg.tile_off[1]
+    fl = reg.flags.cpu().numpy()[:n0]
+    d = reg.disp.cpu().numpy()[:n0]
+    ssd = reg.ssd.cpu().numpy().view(np.uint32)[:n0]
+    cxy = reg.corner_xy.cpu().numpy()[:n0]
+    f32 = np.float32
+    cen = np.floor(f32(8.0) * out[:, :2].astype(f32) + f32(0.5)).astype(np.int64)
+    cen = np.clip(cen, -(8 - 2), 8 - 2).astype(np.int32)
+    logit = np.float32(np.log(conf / (1 - conf)))
+    confident = out[:, 2].astype(f32) >= logit
+    ref_eq = reg.yeq_ref.cpu().numpy()
+    wrp = reg.warped0.cpu().numpy()
+    op = oracle.params(radius0=8)
+    cx, cy, has = oracle.corners(ref_eq, op)
+    assert np.array_equal(cxy[:, 0], np.where(has, cx, -1))
+    assert np.array_equal((fl & 1) != 0, has.astype(bool))
+    win = has.astype(bool) & confident
+    assert win.sum() > 20 and (has.astype(bool) & ~confident).sum() > 20
+    assert np.array_equal((fl & 16) != 0, has.astype(bool) & ~confident)
+    dx, dy, s, valid = oracle.search_window(ref_eq, wrp, 2, cen[:, 0], cen[:, 1], cx, cy, has,
+                                            op)
+    ex, ey, es, evalid = oracle.search_window(ref_eq, wrp, 8, np.zeros(n0), np.zeros(n0), cx, cy,
+                                              has, op)
+    for m, (a, b, sv, v) in ((win, (dx, dy, s, valid)), (~win, (ex, ey, es, evalid))):
+        m = m & has.astype(bool)
+        assert np.array_equal(d[m, 0], a[m]) and np.array_equal(d[m, 1], b[m])
+        assert np.array_equal(ssd[m], sv[m])
+        assert np.array_equal((fl[m] & 2) != 0, v[m].astype(bool))
+    c.close()
 
 
 def test_network_file_roundtrip_and_rejects(lnr, tmp_path):

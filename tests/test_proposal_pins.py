@@ -15,7 +15,7 @@ NP = oracle.CNN_PARAMS
 
 def _layout():
     """offsets of W1 b1 W2 b2 W3 b3 W4 b4 Wh bh in the flat vector"""
-    cin = [2, 32, 32, 32]
+    cin = [oracle.CNN_IN, 32, 32, 32]
     off, o = {}, 0
     for l in range(4):
         off[f"W{l + 1}"] = (o, (32, cin[l], 3, 3))
@@ -66,7 +66,7 @@ def _forward_scipy(P, x):
 
 
 def test_param_count():
-    assert oracle.lib().lo_cnn_param_count() == NP == 29891
+    assert oracle.lib().lo_cnn_param_count() == NP == 30467
 
 
 def test_bf16_matches_torch_cast():
@@ -81,24 +81,51 @@ def test_bf16_matches_torch_cast():
     assert np.array_equal(oracle.bf16(v.astype(np.float64)), want)
 
 
+def _bf16_np(v):
+    return torch.from_numpy(np.asarray(v, np.float32)).to(torch.bfloat16).double().numpy()
+
+
 def test_tile_input_brute_force():
+    """Channels 0, 1: 2x2 sums of the tile; channels 2, 3: 4x4 sums of the
+    64 x 64 window around it, the image padded by repeating its edge (numpy's
+    'edge' mode), at interior, corner and edge tiles of a ragged image."""
     rng = np.random.default_rng(4)
-    ref = rng.integers(0, 256, (64, 96), np.uint8)
-    wrp = rng.integers(0, 256, (64, 96), np.uint8)
-    x = oracle.cnn_tile_inputs(ref, wrp, [0, 4])  # tiles (0,0) and (1,1)
-    for k, (x0, y0) in enumerate([(0, 0), (32, 32)]):
+    H, W = 100, 130
+    ref = rng.integers(0, 256, (H, W), np.uint8)
+    wrp = rng.integers(0, 256, (H, W), np.uint8)
+    ntx = W // 32
+    tiles = [0, 5, ntx - 1, 2 * ntx + 3]   # corner, interior, right edge, bottom-right
+    x = oracle.cnn_tile_inputs(ref, wrp, tiles)
+    assert x.shape == (4, 4, 16, 16)
+    for k, t in enumerate(tiles):
+        x0, y0 = (t % ntx) * 32, (t // ntx) * 32
         for c, img in enumerate((ref, wrp)):
-            t = img[y0:y0 + 32, x0:x0 + 32].astype(np.int64)
-            s = t[0::2, 0::2] + t[1::2, 0::2] + t[0::2, 1::2] + t[1::2, 1::2]
-            want = torch.from_numpy(((s - 510) / 512.0).astype(np.float32)).to(
-                torch.bfloat16).double().numpy()
-            assert np.array_equal(x[k, c], want)
+            tl = img[y0:y0 + 32, x0:x0 + 32].astype(np.int64)
+            s = tl[0::2, 0::2] + tl[1::2, 0::2] + tl[0::2, 1::2] + tl[1::2, 1::2]
+            assert np.array_equal(x[k, c], _bf16_np((s - 510) / 512.0)), (t, c)
+            pad = np.pad(img.astype(np.int64), 16, mode="edge")
+            win = pad[y0:y0 + 64, x0:x0 + 64]        # window origin (x0 - 16, y0 - 16)
+            s4 = win.reshape(16, 4, 16, 4).sum(axis=(1, 3))
+            assert np.array_equal(x[k, 2 + c], _bf16_np((s4 - 2040) / 2048.0)), (t, c)
+
+
+def test_tile_input_window_shows_a_shifted_tile():
+    """A source that is the reference shifted by (8, -4) px: the source
+    window channel equals the reference window channel shifted by (2, -1)
+    quarter-resolution pixels where both stay inside the image."""
+    rng = np.random.default_rng(9)
+    big = rng.integers(0, 256, (200, 200), np.uint8)
+    ref = big[40:168, 40:168].copy()
+    src = big[40 - 4:168 - 4, 40 + 8:168 + 8].copy()    # src(x, y) = ref(x + 8, y - 4)
+    x = oracle.cnn_tile_inputs(ref, src, [5])           # tile (1, 1) of a 4 x 4 grid
+    a, b = x[0, 2], x[0, 3]
+    assert np.array_equal(b[1:, :-2], a[:-1, 2:])
 
 
 def test_forward_matches_scipy_correlation():
     P = _params(5)
     rng = np.random.default_rng(6)
-    x = rng.uniform(-1, 1, (3, 2, 16, 16))
+    x = rng.uniform(-1, 1, (3, oracle.CNN_IN, 16, 16))
     got = oracle.cnn_forward(P, x, rnd=False)
     for s in range(3):
         assert np.allclose(got[s], _forward_scipy(P, x[s]), rtol=1e-12, atol=1e-12)
@@ -106,7 +133,7 @@ def test_forward_matches_scipy_correlation():
 
 def test_forward_rounded_close_to_exact():
     P = _params(7)
-    x = oracle.bf16(np.random.default_rng(8).uniform(-1, 1, (4, 2, 16, 16)))
+    x = oracle.bf16(np.random.default_rng(8).uniform(-1, 1, (4, oracle.CNN_IN, 16, 16)))
     a = oracle.cnn_forward(P, x, rnd=True)
     b = oracle.cnn_forward(P, x, rnd=False)
     assert np.all(np.abs(a - b) <= 0.05 * (1 + np.abs(b)))
@@ -128,7 +155,7 @@ def test_gradient_matches_finite_differences(seed):
     confidence target held at its current value (as the gradient defines)."""
     P = _params(seed)
     rng = np.random.default_rng(seed + 100)
-    x = rng.uniform(-1, 1, (3, 2, 16, 16))
+    x = rng.uniform(-1, 1, (3, oracle.CNN_IN, 16, 16))
     lab = rng.integers(-6, 7, (3, 2)).astype(np.int32)
     o = oracle.cnn_forward(P, x, rnd=False)
     ex, ey = 8 * o[:, 0] - lab[:, 0], 8 * o[:, 1] - lab[:, 1]
@@ -154,7 +181,7 @@ def test_gradient_rounded_close_to_exact():
     gradient shows up enlarged (about 10-20 % here at random init)."""
     P = _params(13)
     rng = np.random.default_rng(14)
-    x = oracle.bf16(rng.uniform(-1, 1, (4, 2, 16, 16)))
+    x = oracle.bf16(rng.uniform(-1, 1, (4, oracle.CNN_IN, 16, 16)))
     lab = rng.integers(-8, 9, (4, 2)).astype(np.int32)
     _, ga = oracle.cnn_loss_grad(P, x, lab, rnd=True)
     _, gb = oracle.cnn_loss_grad(P, x, lab, rnd=False)
