@@ -378,6 +378,14 @@ def main():
             lnr.register_pair(ctx, ref, src, pq, out=reg_l)
         torch.cuda.synchronize()
         ms_lr = (time.perf_counter() - t0) / args.steps * 1e3
+        # per-kernel times of the learned registration (HIP events)
+        ctx.trace(True)
+        for _ in range(args.steps):
+            lnr.register_pair(ctx, ref, src, pq, out=reg_l)
+        torch.cuda.synchronize()
+        tr_l = ctx.trace_read()
+        ctx.trace(False)
+        ker_l = sorted(((k, ms / args.steps) for k, (c, ms) in tr_l.items()), key=lambda kv: -kv[1])
         n0 = reg.tile_off[1]
         fl = reg_l.flags.cpu().numpy()[:n0]
         cornered = (fl & 1) != 0
@@ -394,6 +402,7 @@ def main():
                    "mean_epe_px": round(mean_epe(reg_l.H[1].cpu().numpy(),
                                                  reg_l.flow.cpu().numpy().astype(np.float64),
                                                  gt), 4),
+                   "registration_kernels_ms": {k: round(v, 4) for k, v in ker_l},
                    "_flags": fl, "_disp": reg_l.disp.cpu().numpy()[:n0]}
 
     # the paper-literal search frame (Eq. 3 as printed): the same pair

@@ -142,6 +142,7 @@ def lib():
         L.lnr_autotune_flow.argtypes = [vp, i32, i32, C.POINTER(Params), vp, vp]
         L.lnr_autotune_search.argtypes = [vp, i32, i32, C.POINTER(Params), vp, vp]
         L.lnr_set_flow_shape.argtypes = [vp, i32, i32, vp]
+        L.lnr_set_search_shape.argtypes = [vp, i32, i32, i32, i32]
         L.lnr_flow_shapes.argtypes = [i32, i32, vp, i32]
         L.lnr_flow_shapes.restype = C.c_int32
         L.lnr_trace_enable.argtypes = [vp, i32]
@@ -155,7 +156,7 @@ def lib():
                      "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow",
                      "lnr_autotune_search", "lnr_proposal_save", "lnr_proposal_load",
                      "lnr_merge_irradiance", "lnr_stage_irradiance", "lnr_meter",
-                     "lnr_set_flow_shape"):
+                     "lnr_set_flow_shape", "lnr_set_search_shape"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -172,7 +173,7 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_proposal_save", "lnr_proposal_load", "lnr_merge_irradiance",
             "lnr_stage_irradiance", "lnr_meter", "lnr_set_flow_shape", "lnr_flow_shapes",
             "lnr_register_pair_noalloc", "lnr_proposal_checkpoint_save",
-            "lnr_proposal_checkpoint_load")
+            "lnr_proposal_checkpoint_load", "lnr_set_search_shape")
 
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -635,6 +636,15 @@ def flow_shapes(w: int, h: int):
     buf = (C.c_int32 * (5 * max(n, 1)))()
     lib().lnr_flow_shapes(w, h, buf, n)
     return [tuple(buf[5 * i:5 * i + 5]) for i in range(n)]
+
+
+SEARCH_KX12 = 16
+
+
+def set_search_shape(ctx: Context, level_w: int, level_h: int, radius: int, shape: int):
+    """Pin the search shape (split 1..7, plus SEARCH_KX12 for 12 candidates per
+    lane) for levels of that size and radius."""
+    ctx.check(lib().lnr_set_search_shape(ctx._h, level_w, level_h, radius, shape))
 
 
 def set_flow_shape(ctx: Context, w: int, h: int, shape):

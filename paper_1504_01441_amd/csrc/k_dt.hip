@@ -36,13 +36,18 @@ struct DtArgs {
 
 // c_i[k] = a_i ^ (1 + ratio * k / 255),  a_i = exp(-sqrt(2) / sigma_i),
 // sigma_i = sigma_s sqrt(3) 2^(n - i) / sqrt(4^n - 1)  (i = 1..n)
-// Block 0 also clears zero[0, nzero) and sets ident to the identity (the
-// registration's first launch does this set-up with the tables).
+// Block 0 also clears zero[0, nzero), zero64[0, nzero64) and sums[0, 24) and
+// sets ident to the identity (the registration's first launch does this
+// set-up with the tables: histograms, the top level's weeding bits and sums).
 __global__ void k_dt_coef(DtArgs a, double* __restrict__ coef, uint32_t* __restrict__ zero,
-                          int nzero, double* __restrict__ ident) {
+                          int nzero, double* __restrict__ ident,
+                          unsigned long long* __restrict__ zero64, int nzero64,
+                          long long* __restrict__ sums) {
   const int i = blockIdx.x + 1, k = threadIdx.x;
   if (blockIdx.x == 0) {
     for (int j = k; j < nzero; j += 256) zero[j] = 0u;
+    for (int j = k; j < nzero64; j += 256) zero64[j] = 0ull;
+    if (sums && k < 24) sums[k] = 0;
     if (ident && k < 9) ident[k] = (k % 4 == 0) ? 1.0 : 0.0;
   }
   const double sig = a.sigma_s * sqrt(3.0) * pow(2.0, (double)(a.iters - i)) /
@@ -560,12 +565,14 @@ DtShape dt_default_shape(int W, int H) {
 }
 
 hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int nzero,
-                          double* ident, hipStream_t st) {
+                          double* ident, hipStream_t st, unsigned long long* zero64,
+                          int nzero64, long long* sums) {
   DtArgs a;
   a.iters = p.dt_iters;
   a.sigma_s = p.sigma_s;
   a.ratio = p.sigma_s / p.sigma_r;
-  LNR_LAUNCH(k_dt_coef, dim3(a.iters), dim3(256), 0, st, a, coef, zero, nzero, ident);
+  LNR_LAUNCH(k_dt_coef, dim3(a.iters), dim3(256), 0, st, a, coef, zero, nzero, ident, zero64,
+             zero64 ? nzero64 : 0, sums);
   return hipGetLastError();
 }
 

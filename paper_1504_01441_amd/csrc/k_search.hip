@@ -169,6 +169,23 @@ __device__ inline void stage_rows(const uint8_t* __restrict__ img, int w, int h,
   }
 }
 
+// The window rows [y0, y0 + nrows) x bytes [x0, x0 + 4 * ndw) of the level
+// warped on the fly: each pixel inside the level is warp_px of the unwarped
+// source (the value k_warp_q8 stores there), 0 outside, as stage_rows reads
+// the stored warped level.
+__device__ inline void stage_warped(const uint8_t* __restrict__ src, int w, int h,
+                                    const double* hp, int x0, int y0, int nrows, int ndw,
+                                    uint8_t* dst, int ldst, int tid, int nt) {
+  const int total = nrows * ndw * 4;
+  for (int i = tid; i < total; i += nt) {
+    const int r = i / (4 * ndw), b = i % (4 * ndw);
+    const int gy = y0 + r, gx = x0 + b;
+    uint32_t v = 0;
+    if (gy >= 0 && gy < h && gx >= 0 && gx < w) v = warp_px(src, w, h, hp, gx, gy);
+    dst[r * ldst + b] = (uint8_t)v;
+  }
+}
+
 struct SearchShape {
   int R, nstrips, nthreads;
   int split;     // patch rows split over this many thread groups (partial SSDs summed in LDS)
@@ -354,7 +371,13 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   uint8_t* win = dyn + sh.off_win;
   uint32_t* rowsq = reinterpret_cast<uint32_t*>(win + sh.NR * sh.wrow);
   const int wx0 = px + cdx - P - R, wy0 = py + cdy - P - R;
-  stage_rows(J.wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
+  if (J.Hwarp) {
+    double hp[9];
+    pixel_homography(J.Hwarp, w, h, hp);
+    stage_warped(J.wimg, w, h, hp, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
+  } else {
+    stage_rows(J.wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
+  }
   __syncthreads();
   // patch energy and window row energies rowsq[y][k] = sum_c win[y][k + c]^2,
   // from realigned dwords with v_dot4 (bytes past the patch width masked off)
@@ -623,10 +646,13 @@ hipError_t launch_warp_jobs(const WarpJob* jobs, const int* row0, int njobs, int
 }
 
 int search_split_candidates(int R, const SearchCfg& c, int* out, int max) {
-  const int ncand = 2 * R + 1, base = ncand * ((ncand + 7) / 8);
+  const int ncand = 2 * R + 1;
   int n = 0;
-  for (int s = 1; s <= 7 && s <= 2 * c.P + 1 && n < max; ++s)
-    if (base * s <= 1024) out[n++] = s;
+  for (int kx = 8; kx <= 12; kx += 4) {
+    const int base = ncand * ((ncand + kx - 1) / kx);
+    for (int s = 1; s <= 7 && s <= 2 * c.P + 1 && n < max; ++s)
+      if (base * s <= 1024) out[n++] = s | (kx == 12 ? kSearchKx12 : 0);
+  }
   return n;
 }
 
@@ -636,32 +662,42 @@ hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c, int role,
-                         hipStream_t st, const uint8_t* mode, int want, int split) {
-  const int ntiles = J.ntx * nty;
-  if (ntiles == 0) return hipSuccess;
-  size_t lds = 0;
-  int block = 0;
-  const SearchShape sh = make_shape(R, c, split, ntiles, 8, &lds, &block);
+template <int KX>
+hipError_t launch_search_kx(const SearchJob& J, int ntiles, const SearchCfg& c,
+                            const SearchShape& sh, int role, int block, size_t lds,
+                            hipStream_t st, const uint8_t* mode, int want) {
   switch (role) {
     case kRoleCoarse:
-      LNR_LAUNCH((k_search<8, kRoleCoarse>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleCoarse>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
     case kRoleLevel0:
-      LNR_LAUNCH((k_search<8, kRoleLevel0>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleLevel0>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
     case kRoleTrial:
-      LNR_LAUNCH((k_search<8, kRoleTrial>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleTrial>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
     default:
-      LNR_LAUNCH((k_search<8, kRoleStage>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleStage>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c, int role,
+                         hipStream_t st, const uint8_t* mode, int want, int split) {
+  const int ntiles = J.ntx * nty;
+  if (ntiles == 0) return hipSuccess;
+  // a tuned choice: the split (1..7), plus kSearchKx12 for 12 candidates per lane
+  const int kx = (split & kSearchKx12) ? 12 : 8;
+  size_t lds = 0;
+  int block = 0;
+  const SearchShape sh = make_shape(R, c, split & ~kSearchKx12, ntiles, kx, &lds, &block);
+  return kx == 12 ? launch_search_kx<12>(J, ntiles, c, sh, role, block, lds, st, mode, want)
+                  : launch_search_kx<8>(J, ntiles, c, sh, role, block, lds, st, mode, want);
 }
 
 template <int KX>

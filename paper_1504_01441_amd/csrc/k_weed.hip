@@ -515,6 +515,10 @@ __global__ __launch_bounds__(64) void k_solve(WeedJob one, const WeedJob* __rest
   for (int i = 0; i < 9; ++i) Hp[i] = Hprev[i];
   for (int i = 0; i < 9; ++i) Hb[i] = Hbase[i];
   __syncthreads();
+  if (J.clear_vb) {  // the next level's search sets bits and its weeding adds sums
+    for (int i = lane; i < J.clear_words; i += 64) J.clear_vb[i] = 0ull;
+    if (lane < 24) J.b.sums[lane] = 0;
+  }
   if (lane != 0) return;
   const int msel = (int)tot[0];
   counts[1] = msel;
@@ -573,7 +577,7 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
                            int ntiles, int w, int h, int level, const lnr_params& p,
                            const double* H_prev, double* H_out, int32_t* counts,
                            const WeedBufs& b, hipStream_t st, bool vb_ready,
-                           const double* H_base) {
+                           const double* H_base, int clear_words) {
   const WeedArgs a = weed_args(p, level);
   const int words = ntiles > 0 ? (ntiles + 63) / 64 : 1;
   const int chunks = ntiles > 0 ? (ntiles + kTestThreads - 1) / kTestThreads : 1;
@@ -584,6 +588,8 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
   J.ntiles = ntiles; J.w = w; J.h = h; J.words = words;
   J.b = b;
   J.Hprev = H_prev; J.Hbase = H_base ? H_base : H_prev; J.Hout = H_out; J.counts = counts;
+  J.clear_vb = clear_words > 0 ? b.vb : nullptr;
+  J.clear_words = clear_words;
   hipError_t e;
   if (!vb_ready) {  // else the level's search set the bits (and its warp cleared the sums)
     LNR_LAUNCH(k_valid, dim3((words + kValidThreads / 64 - 1) / (kValidThreads / 64)),

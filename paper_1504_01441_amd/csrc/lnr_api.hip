@@ -248,12 +248,17 @@ Geometry make_geometry(int W, int H, const lnr_params& p) {
 SearchJob search_job(const uint8_t* ref, const uint8_t* wimg, int w, int h, int ntx,
                      int32_t* cxy, int32_t* disp, uint32_t* ssd, uint8_t* flags,
                      const int32_t* centre = nullptr, unsigned long long* vb = nullptr,
-                     const double* Hlit = nullptr) {
+                     const double* Hlit = nullptr, const double* Hwarp = nullptr) {
   SearchJob j;
   j.ref = ref; j.wimg = wimg; j.w = w; j.h = h; j.ntx = ntx;
   j.corner_xy = cxy; j.disp = disp; j.ssd = ssd; j.flags = flags;
-  j.centre = centre; j.vb = vb; j.Hlit = Hlit;
+  j.centre = centre; j.vb = vb; j.Hlit = Hlit; j.Hwarp = Hwarp;
   return j;
+}
+
+int level_words(const Level& L) {
+  const int nt = L.ntx * L.nty;
+  return nt > 0 ? (nt + 63) / 64 : 1;
 }
 
 SearchCfg search_cfg(const lnr_params& p) {
@@ -404,6 +409,15 @@ PairPlan plan_pair(int W, int H, const lnr_params* p) {
   return q;
 }
 
+__global__ void k_copy_u8(const uint8_t* __restrict__ a, uint8_t* __restrict__ b, size_t n) {
+  const size_t i0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * 16;
+  if (i0 + 16 <= n && ((reinterpret_cast<uintptr_t>(a + i0) | reinterpret_cast<uintptr_t>(b + i0)) & 15) == 0) {
+    *reinterpret_cast<uint4*>(b + i0) = *reinterpret_cast<const uint4*>(a + i0);
+  } else {
+    for (size_t i = i0; i < i0 + 16 && i < n; ++i) b[i] = a[i];
+  }
+}
+
 __global__ void k_zero_u32(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -423,7 +437,10 @@ lnr_status enqueue_pair_setup(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
   uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
   uint8_t* guide_t = reinterpret_cast<uint8_t*>(base + q.o_gt);
   double* coef = reinterpret_cast<double*>(base + q.o_coef);
-  LNR_HIP(launch_dt_coef(*p, coef, hist, 512, out->H + 9 * g.levels, st));
+  // (also cleared: the top level's weeding bits and sums, which its search fills)
+  const WeedBufs wb = weed_bufs(base, q.wp);
+  LNR_HIP(launch_dt_coef(*p, coef, hist, 512, out->H + 9 * g.levels, st, wb.vb,
+                         level_words(g.lv[g.levels - 1]), wb.sums));
   LNR_HIP(launch_hist(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], W, H, hist, 2, st));
   LNR_HIP(launch_lut_pyr(ref->plane[0], ref->stride[0], src->plane[0], src->stride[0], hist, g,
                          pref, psrc, nullptr, 2, st, out->yeq_ref, out->yeq_src, guide_t));
@@ -434,13 +451,14 @@ lnr_status enqueue_pair_setup(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fram
 // dense flow, and the backward warp of the source.
 lnr_status enqueue_pair_finish(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
                                const lnr_params* p, lnr_registration* out, const PairPlan& q,
-                               char* base, hipStream_t st) {
+                               char* base, hipStream_t st, char* ref_base = nullptr) {
   const Geometry& g = q.g;
   const int W = ref->width, H = ref->height;
-  uint8_t* pref = reinterpret_cast<uint8_t*>(base + q.o_pref);
+  if (!ref_base) ref_base = base;
+  uint8_t* pref = reinterpret_cast<uint8_t*>(ref_base + q.o_pref);
   uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
   void* maps = base + q.o_maps;
-  uint8_t* guide_t = reinterpret_cast<uint8_t*>(base + q.o_gt);
+  uint8_t* guide_t = reinterpret_cast<uint8_t*>(ref_base + q.o_gt);
   double* coef = reinterpret_cast<double*>(base + q.o_coef);
   const DtShape* ds = nullptr;
   auto it = ctx->dt_shapes.find(std::make_pair(W, H));
@@ -455,20 +473,59 @@ lnr_status enqueue_pair_finish(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fra
   return LNR_OK;
 }
 
+// The set-up of a source whose reference was prepared with another source
+// (register_stack): the tables and clears, the source's histogram and
+// pyramid only, and the reference's equalised level 0 copied to this output.
+lnr_status enqueue_source_setup(lnr_ctx* ctx, const lnr_frame* src, const lnr_params* p,
+                                lnr_registration* out, const uint8_t* yeq_ref_done,
+                                const PairPlan& q, char* base, hipStream_t st) {
+  const Geometry& g = q.g;
+  const int W = src->width, H = src->height;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + q.o_hist);
+  uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
+  double* coef = reinterpret_cast<double*>(base + q.o_coef);
+  const WeedBufs wb = weed_bufs(base, q.wp);
+  LNR_HIP(launch_dt_coef(*p, coef, hist, 512, out->H + 9 * g.levels, st, wb.vb,
+                         level_words(g.lv[g.levels - 1]), wb.sums));
+  LNR_HIP(launch_hist(src->plane[0], src->stride[0], src->plane[0], src->stride[0], W, H, hist, 1,
+                      st));
+  LNR_HIP(launch_lut_pyr(src->plane[0], src->stride[0], src->plane[0], src->stride[0], hist, g,
+                         psrc, psrc, nullptr, 1, st, out->yeq_src, nullptr, nullptr));
+  const size_t n = (size_t)W * H;
+  LNR_LAUNCH(k_copy_u8, dim3((unsigned)((n + 4095) / 4096)), dim3(256), 0, st, yeq_ref_done,
+             out->yeq_ref, n);
+  LNR_HIP(hipGetLastError());
+  return LNR_OK;
+}
+
+// The pyramid levels of one registration (warp, search, weeding, fit per
+// level); the reference's pyramid is read at ref_base (default: base).
+lnr_status enqueue_pair_levels(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                               const lnr_params* p, lnr_registration* out, const PairPlan& q,
+                               char* base, hipStream_t st, char* ref_base = nullptr);
+
 // Enqueue one registration on `st` using the workspace at `base` (checked and
 // sized by the caller). Launches only: safe under stream capture.
 lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
                         const lnr_params* p, lnr_registration* out, const PairPlan& q,
                         char* base, hipStream_t st) {
+  lnr_status s0 = enqueue_pair_setup(ctx, ref, src, p, out, q, base, st);
+  if (s0 != LNR_OK) return s0;
+  if ((s0 = enqueue_pair_levels(ctx, ref, src, p, out, q, base, st)) != LNR_OK) return s0;
+  return enqueue_pair_finish(ctx, ref, src, p, out, q, base, st);
+}
+
+lnr_status enqueue_pair_levels(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
+                               const lnr_params* p, lnr_registration* out, const PairPlan& q,
+                               char* base, hipStream_t st, char* ref_base) {
   const Geometry& g = q.g;
   const int W = ref->width;
-  uint8_t* pref = reinterpret_cast<uint8_t*>(base + q.o_pref);
+  if (!ref_base) ref_base = base;
+  uint8_t* pref = reinterpret_cast<uint8_t*>(ref_base + q.o_pref);
   uint8_t* psrc = reinterpret_cast<uint8_t*>(base + q.o_psrc);
   uint8_t* warped = reinterpret_cast<uint8_t*>(base + q.o_warp);
   const WeedBufs wb = weed_bufs(base, q.wp);
-
-  lnr_status s0 = enqueue_pair_setup(ctx, ref, src, p, out, q, base, st);
-  if (s0 != LNR_OK) return s0;
+  (void)src;
   const SearchCfg cfg = search_cfg(*p);
   auto tuned = [&](int w, int h, int R) {
     auto it = ctx->search_split.find(std::make_tuple(w, h, R));
@@ -497,13 +554,15 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
                               out->H + 9 * l, out->counts + 4 * l, wb, st, false, identity));
       continue;
     }
-    // level 0 is warped straight into the output when it is wanted
+    // the coarse levels' searches warp their windows on the fly (the set-up or
+    // the previous level's solve cleared the weeding bits and sums); level 0
+    // is warped in full, straight into the output when it is wanted, and the
+    // warp clears the level's weeding buffers and the learned path's counts
     if (l == 0 && out->warped0) warped = out->warped0;
-    // the learned path's three list counts are cleared with the weeding bits
     int32_t* lists = p->learned ? reinterpret_cast<int32_t*>(base + q.o_cl) : nullptr;
     int* counts = p->learned ? reinterpret_cast<int*>(base + q.o_cn) : nullptr;
-    LNR_HIP(launch_warp_q8(psrc + L.pix_off, L.w, L.h, out->H + 9 * (l + 1), warped, st, &wb,
-                           words, l == 0 ? counts : nullptr, 3));
+    if (l == 0)
+      LNR_HIP(launch_warp_q8(psrc, L.w, L.h, out->H + 9, warped, st, &wb, words, counts, 3));
     if (l == 0 && p->learned) {
       // corners first (the cornered tiles listed), the network on the
       // cornered tiles (each listed for the window or for the fallback), then
@@ -544,18 +603,19 @@ lnr_status enqueue_pair(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src
       LNR_HIP(launch_search_work(nullptr, wf, R, cfg, kVisitKnownCorner, 1, tuned(L.w, L.h, R), 8,
                                  nt, st, &Jc));
     } else {
-      const SearchJob J = search_job(pref + L.pix_off, warped, L.w, L.h, L.ntx,
-                                     out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
-                                     out->ssd + L.tile_off, out->flags + L.tile_off, nullptr,
-                                     wb.vb);
+      const SearchJob J = search_job(
+          pref + L.pix_off, l == 0 ? warped : psrc + L.pix_off, L.w, L.h, L.ntx,
+          out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off, out->ssd + L.tile_off,
+          out->flags + L.tile_off, nullptr, wb.vb, nullptr, l == 0 ? nullptr : out->H + 9 * (l + 1));
       LNR_HIP(launch_search(J, L.nty, R, cfg, l == 0 ? kRoleLevel0 : kRoleCoarse, st, nullptr, 0,
                             tuned(L.w, L.h, R)));
     }
     LNR_HIP(launch_weed_fit(out->corner_xy + 2 * L.tile_off, out->disp + 2 * L.tile_off,
                             out->flags + L.tile_off, nt, L.w, L.h, l, *p, out->H + 9 * (l + 1),
-                            out->H + 9 * l, out->counts + 4 * l, wb, st, true));
+                            out->H + 9 * l, out->counts + 4 * l, wb, st, true, nullptr,
+                            l >= 2 ? level_words(g.lv[l - 1]) : 0));
   }
-  return enqueue_pair_finish(ctx, ref, src, p, out, q, base, st);
+  return LNR_OK;
 }
 
 lnr_status register_pair_impl(lnr_ctx* ctx, const lnr_frame* ref, const lnr_frame* src,
@@ -722,6 +782,15 @@ lnr_status lnr_register_pair_noalloc(lnr_ctx* ctx, const lnr_frame* ref, const l
                       (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+namespace {
+lnr_status ensure_workers(lnr_ctx* ctx, int K);
+size_t round256(size_t b);
+}  // namespace
+
+extern "C" {
+
 lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
                               const lnr_params* p, lnr_registration* outs, int32_t* ref_index,
                               void* stream) {
@@ -769,12 +838,42 @@ lnr_status lnr_register_stack(lnr_ctx* ctx, const lnr_frame* frames, int32_t n,
     }
   }
   *ref_index = r;
-  int j = 0;
-  for (int k = 0; k < n; ++k) {
-    if (k == r) continue;
-    lnr_status s = register_pair_impl(ctx, &frames[r], &frames[k], p, &outs[j], (hipStream_t)stream);
-    if (s != LNR_OK) return s;
-    ++j;
+  // n - 1 registrations sharing the reference's equalisation, pyramid and
+  // column-major guide (computed once, with the first source), each source
+  // in its own workspace slot, the levels and propagation of the sources on
+  // the worker streams at once
+  const hipStream_t st = (hipStream_t)stream;
+  std::vector<int> src_of;
+  for (int k = 0; k < n; ++k)
+    if (k != r) src_of.push_back(k);
+  const int m = (int)src_of.size();
+  for (int j = 0; j < m; ++j)
+    if ((s0 = check_pair(ctx, &frames[r], &frames[src_of[j]], p, &outs[j])) != LNR_OK) return s0;
+  const PairPlan q = plan_pair(frames[r].width, frames[r].height, p);
+  const size_t slot = round256(q.bytes);
+  if ((s0 = ensure_ws(ctx, (size_t)m * slot, st)) != LNR_OK) return s0;
+  if ((s0 = ensure_workers(ctx, m)) != LNR_OK) return s0;
+  char* ws = static_cast<char*>(ctx->ws);
+  if ((s0 = enqueue_pair_setup(ctx, &frames[r], &frames[src_of[0]], p, &outs[0], q, ws, st)) !=
+      LNR_OK)
+    return s0;
+  for (int j = 1; j < m; ++j)
+    if ((s0 = enqueue_source_setup(ctx, &frames[src_of[j]], p, &outs[j], outs[0].yeq_ref, q,
+                                   ws + (size_t)j * slot, st)) != LNR_OK)
+      return s0;
+  LNR_HIP(hipEventRecord(ctx->events[m], st));
+  for (int j = 0; j < m; ++j) {
+    const hipStream_t w = ctx->workers[j];
+    LNR_HIP(hipStreamWaitEvent(w, ctx->events[m], 0));
+    char* base = ws + (size_t)j * slot;
+    if ((s0 = enqueue_pair_levels(ctx, &frames[r], &frames[src_of[j]], p, &outs[j], q, base, w,
+                                  ws)) != LNR_OK)
+      return s0;
+    if ((s0 = enqueue_pair_finish(ctx, &frames[r], &frames[src_of[j]], p, &outs[j], q, base, w,
+                                  ws)) != LNR_OK)
+      return s0;
+    LNR_HIP(hipEventRecord(ctx->events[j], w));
+    LNR_HIP(hipStreamWaitEvent(st, ctx->events[j], 0));
   }
   return LNR_OK;
 }
@@ -1183,10 +1282,12 @@ void fill_batch_tables(BatchLayout& b, int n, const lnr_params* p, lnr_registrat
       wj.vb = wb.vb; wj.sums = wb.sums;
       memcpy(b.blob.data() + T.o_warp + k * sizeof(WarpJob), &wj, sizeof(wj));
       memcpy(b.blob.data() + T.o_row0 + k * sizeof(int), &row, sizeof(int));
-      const SearchJob sj = search_job(reinterpret_cast<uint8_t*>(base + q.o_pref) + L.pix_off,
-                                      warped, L.w, L.h, L.ntx, o.corner_xy + 2 * L.tile_off,
-                                      o.disp + 2 * L.tile_off, o.ssd + L.tile_off,
-                                      o.flags + L.tile_off, nullptr, wb.vb);
+      // coarse levels warp their windows on the fly, as in a single registration
+      const SearchJob sj = search_job(
+          reinterpret_cast<uint8_t*>(base + q.o_pref) + L.pix_off,
+          l == 0 ? warped : reinterpret_cast<uint8_t*>(base + q.o_psrc) + L.pix_off, L.w, L.h,
+          L.ntx, o.corner_xy + 2 * L.tile_off, o.disp + 2 * L.tile_off, o.ssd + L.tile_off,
+          o.flags + L.tile_off, nullptr, wb.vb, nullptr, l == 0 ? nullptr : o.H + 9 * (l + 1));
       memcpy(b.blob.data() + T.o_sjob + k * sizeof(SearchJob), &sj, sizeof(sj));
       memcpy(b.blob.data() + T.o_first + k * sizeof(int), &tile, sizeof(int));
       WeedJob ej;
@@ -1196,6 +1297,8 @@ void fill_batch_tables(BatchLayout& b, int n, const lnr_params* p, lnr_registrat
       ej.b = wb;
       ej.Hprev = o.H + 9 * (l + 1); ej.Hbase = ej.Hprev; ej.Hout = o.H + 9 * l;
       ej.counts = o.counts + 4 * l;
+      ej.clear_vb = l >= 2 ? wb.vb : nullptr;
+      ej.clear_words = l >= 2 ? level_words(q.g.lv[l - 1]) : 0;
       memcpy(b.blob.data() + T.o_wjob + k * sizeof(WeedJob), &ej, sizeof(ej));
       row += L.h;
       tile += nt;
@@ -1234,9 +1337,10 @@ lnr_status enqueue_batch_levels(lnr_ctx* ctx, const lnr_frame* refs, const lnr_f
     const LevelTables& T = b.lv[l];
     if (T.njobs == 0) continue;
     const int R = l == 0 ? p->radius0 : p->radius_coarse;
-    LNR_HIP(launch_warp_jobs(reinterpret_cast<const WarpJob*>(tab + T.o_warp),
-                             reinterpret_cast<const int*>(tab + T.o_row0), T.njobs, T.rows,
-                             T.wmax, origin));
+    if (l == 0)  // coarse levels are warped inside their search
+      LNR_HIP(launch_warp_jobs(reinterpret_cast<const WarpJob*>(tab + T.o_warp),
+                               reinterpret_cast<const int*>(tab + T.o_row0), T.njobs, T.rows,
+                               T.wmax, origin));
     SearchWork wk;
     wk.first = reinterpret_cast<const int*>(tab + T.o_first);
     wk.njobs = T.njobs;
@@ -1520,6 +1624,21 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
     shape_out[0] = best.seg; shape_out[1] = best.nt; shape_out[2] = best.l;
     shape_out[3] = best.ncol; shape_out[4] = best.nseg;
   }
+  return LNR_OK;
+}
+
+lnr_status lnr_set_search_shape(lnr_ctx* ctx, int32_t level_w, int32_t level_h, int32_t radius,
+                                int32_t shape) {
+  if (!ctx) return LNR_E_ARG;
+  const int split = shape & ~kSearchKx12;
+  if (level_w < 1 || level_h < 1 || radius < 0 || radius > kMaxRadius || split < 1 || split > 7 ||
+      (shape & ~(kSearchKx12 | 7)))
+    return fail(ctx, LNR_E_ARG, "bad search shape");
+  const int kx = (shape & kSearchKx12) ? 12 : 8;
+  const int ncand = 2 * radius + 1;
+  if (ncand * ((ncand + kx - 1) / kx) * split > 1024)
+    return fail(ctx, LNR_E_ARG, "search shape needs more than 1024 threads");
+  ctx->search_split[std::make_tuple((int)level_w, (int)level_h, (int)radius)] = shape;
   return LNR_OK;
 }
 

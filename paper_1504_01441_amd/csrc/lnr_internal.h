@@ -98,6 +98,8 @@ struct SearchJob {
   const int32_t* centre;    // [tiles][2] window centres of the learned proposal, or null
   unsigned long long* vb;   // valid-match bits set by the search, or null
   const double* Hlit;       // previous level's homography (unwarped search), or null
+  const double* Hwarp;      // previous level's homography: the window is the
+                            // unwarped level wimg warped by it on the fly, or null
 };
 // The tiles one work-list launch visits: global tile g of job j is
 // first[j] + tile; all of [0, ntotal) or the *count entries of list.
@@ -110,11 +112,15 @@ struct SearchWork {
   int* out_list;            // corner visits: cornered tiles appended here (device)
   int* out_count;
 };
+// a tuned search shape: the patch-row split (1..7), plus this flag when the
+// lanes score 12 consecutive candidates instead of 8
+constexpr int kSearchKx12 = 16;
 // names of single-job search launches (profiles tell the levels apart)
 constexpr int kRoleCoarse = 0, kRoleLevel0 = 1, kRoleTrial = 2, kRoleStage = 3;
 // tile visits of the work-list search
 constexpr int kVisitSearchAll = 0, kVisitCornersOnly = 1, kVisitKnownCorner = 2;
-// one workgroup per tile of J (mode/want: only the tiles whose mode is want)
+// one workgroup per tile of J (mode/want: only the tiles whose mode is want);
+// split: 0 (a rule on the level size) or a tuned shape
 // k_warp_q8 over several pairs' levels (batches): job j's rows are the grid
 // rows [row0[j], row0[j + 1]) (device tables), rows = row0[njobs]
 struct WarpJob {
@@ -137,8 +143,9 @@ hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R
                               const SearchCfg& c, int visit, int want, int split, int kx,
                               int grid, hipStream_t st, const SearchJob* one = nullptr);
 
-// splits (patch rows per thread group) that launch_search accepts for radius
-// R, ascending; and a random 8-bit texture for timing the search
+// search shapes that launch_search accepts for radius R (splits of the patch
+// rows over thread groups, with 8 and with 12 candidates per lane); and a
+// random 8-bit texture for timing the search
 int search_split_candidates(int R, const SearchCfg& c, int* out, int max);
 hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st);
 
@@ -162,17 +169,22 @@ struct WeedJob {
   const double* Hbase;  // the map G is composed on (H^{l+1}, or the identity)
   double* Hout;
   int32_t* counts;
+  // cleared by the solve for the next level's search (null: nothing)
+  unsigned long long* clear_vb;
+  int clear_words;
 };
 // the weeding kernels over a device table of jobs (the search set the
 // valid-match bits and the warp cleared the sums); max_tiles: the largest
 // job's tiles
 hipError_t launch_weed_jobs(const WeedJob* jobs, int njobs, int max_tiles, int level,
                             const lnr_params& p, hipStream_t st);
+// clear_words > 0: the solve then clears the first clear_words valid-match
+// words and the sums, for the next level's search
 hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_t* flags,
                            int ntiles, int w, int h, int level, const lnr_params& p,
                            const double* H_prev, double* H_out, int32_t* counts,
                            const WeedBufs& b, hipStream_t st, bool vb_ready = false,
-                           const double* H_base = nullptr);
+                           const double* H_base = nullptr, int clear_words = 0);
 
 // ---- domain-transform propagation (k_dt.hip)
 // Kernel shapes: rows of SEG pixels per thread in NT-thread blocks; columns as
@@ -222,7 +234,8 @@ __device__ inline void store_tile_columns(const uint8_t* tile, int bx, int by, i
 // the propagation's coefficient tables (coef [iters][256]); the first block
 // also clears zero[0, nzero) and sets ident (optional) to the 3x3 identity
 hipError_t launch_dt_coef(const lnr_params& p, double* coef, uint32_t* zero, int nzero,
-                          double* ident, hipStream_t st);
+                          double* ident, hipStream_t st, unsigned long long* zero64 = nullptr,
+                          int nzero64 = 0, long long* sums = nullptr);
 
 // ---- backward warp (k_warp.hip)
 // Chroma of a 4:2:0 frame: U at u[(y/2) su + (x/2) cs], V likewise (I420: two

@@ -120,6 +120,7 @@ def calibrate(ctx: Context, x: torch.Tensor, labels: torch.Tensor, window: int =
     lab = labels.cpu().numpy()
     c = np.clip(np.floor(8.0 * o[:, :2] + 0.5), -(radius0 - window), radius0 - window)
     inside = np.all(np.abs(c - lab) <= window, axis=1)
+    calibrate.inside_fraction = float(inside.mean())  # the most any threshold can window
     order = np.argsort(-o[:, 2], kind="stable")   # most confident first
     misses = np.cumsum(~inside[order])
     good = np.nonzero(misses <= budget * len(order))[0]
@@ -146,6 +147,9 @@ def main():
     ap.add_argument("--seed0", type=int, default=100)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--budget", type=float, default=0.005,
+                    help="held-out tiles whose argmin may fall outside their window")
+    ap.add_argument("--lr", type=float, default=3e-3)
     args = ap.parse_args()
     import concurrent.futures as cf
     t0 = time.time()
@@ -169,11 +173,14 @@ def main():
     xh, lh = torch.cat(xs[-nh:]), torch.cat(ls[-nh:])
     print(f"[train] {x.shape[0]} labelled tiles, {xh.shape[0]} held out", flush=True)
     t1 = time.time()
-    train(ctx, x, lab, epochs=args.epochs, log=lambda m: print("[train] " + m, flush=True))
+    train(ctx, x, lab, epochs=args.epochs, lr=args.lr,
+          log=lambda m: print("[train] " + m, flush=True))
     torch.cuda.synchronize()
     print(f"[train] {args.epochs} epochs in {time.time() - t1:.1f} s", flush=True)
-    conf, frac = calibrate(ctx, xh, lh)
-    print(f"[train] conf_min {conf:.6f}: {100 * frac:.1f} % of held-out tiles confident", flush=True)
+    conf, frac = calibrate(ctx, xh, lh, budget=args.budget)
+    print(f"[train] conf_min {conf:.6f}: {100 * frac:.1f} % of held-out tiles confident; "
+          f"{100 * calibrate.inside_fraction:.1f} % have their argmin in the window",
+          flush=True)
     np.savez(args.out, params=proposal_get(ctx).cpu().numpy(), conf_min=np.float64(conf))
     print(f"[train] saved {args.out}", flush=True)
 

@@ -138,7 +138,7 @@ def test_autotuned_search_split_keeps_results(lnr, w, h, radius0):
     before = lnr.register_pair(c, F0, F1, p)
     torch.cuda.synchronize()
     splits = lnr.autotune_search(c, w, h, p)
-    assert len(splits) >= 2 and all(1 <= s <= 7 for s in splits)
+    assert len(splits) >= 2 and all(1 <= (s & 15) <= 7 and s & ~31 == 0 for s in splits)
     after = lnr.register_pair(c, F0, F1, p)
     torch.cuda.synchronize()
     _same(before, after)
@@ -308,3 +308,29 @@ def test_c5_learned_batch_full_size_equals_single_calls(lnr, ctx):
     torch.cuda.synchronize()
     for a, b in zip(outs, singles):
         _same(a, b)
+
+
+@pytest.mark.parametrize("shape", [1, 3, 16 | 1, 16 | 2, 16 | 7])
+def test_every_search_shape_keeps_results(lnr, shape):
+    """Each pinned search shape (patch-row split, 8 or 12 candidates per lane)
+    at every level gives the untuned registration bit for bit."""
+    p = lnr.Params(radius0=16)
+    st = synth.make_stack(640, 480, 777, ratios=(1.0, 4.0), fmt="y8", shift_range=8)
+    f0, f1 = st.frames
+    F0, F1 = lnr.Frame.from_numpy(f0.y), lnr.Frame.from_numpy(f1.y)
+    base = lnr.register_pair(lnr.Context(0), F0, F1, p)
+    c = lnr.Context(0)
+    s = lnr.query_sizes(640, 480, lnr.LNR_Y8, p)
+    for l in range(s.levels):
+        R = p.radius0 if l == 0 else p.radius_coarse
+        lnr.set_search_shape(c, s.level_w[l], s.level_h[l], R, shape)
+    got = lnr.register_pair(c, F0, F1, p)
+    torch.cuda.synchronize()
+    _same(base, got)
+
+
+def test_search_shape_rejects_bad_shapes(lnr):
+    c = lnr.Context(0)
+    for bad in (0, 8, 16, 32 | 1, 64):
+        with pytest.raises(lnr.LnrError):
+            lnr.set_search_shape(c, 640, 480, 16, bad)
