@@ -37,6 +37,11 @@
 // around q = round(Hp x) for the tile's corner x, Hp the pixel homography of
 // the previous level; ties are ordered on the offset from q and the result
 // is the absolute displacement q + d - x.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "lnr_device.h"
 #include "lnr_internal.h"
 
@@ -387,22 +392,43 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       part = __builtin_amdgcn_udot4(S.refp[i], S.refp[i], part, false);
     if (part) atomicAdd(&S.er_sum, part);
   }
+  // (one thread per window row: the first sum from dwords, then sliding by
+  // one pixel four candidates at a time, from the dword holding the pixels
+  // that leave and the realigned dword holding those that enter; exact in
+  // integers. The step is written as (b - a)(b + a): hipcc folds
+  // e + b*b - a*a on two bytes into one v_dot4_u32_u8 of the packed pair,
+  // which adds a*a instead of subtracting it.)
   {
     const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
     const int rowdw = sh.wrow >> 2;
-    for (int i = tid; i < sh.NR * sh.ncand; i += nt) {
-      const int yy = i / sh.ncand, k = i % sh.ncand;
-      const uint32_t* rp = wdw + yy * rowdw + (k >> 2);
-      const int rsh = k & 3;
-      uint32_t s2 = 0;
+    for (int yy = tid; yy < sh.NR; yy += nt) {
+      const uint32_t* rp = wdw + yy * rowdw;
+      uint32_t e = 0;
 #pragma unroll
       for (int m = 0; m < NW; ++m) {
         const int nb = PW - 4 * m;
         const uint32_t mask = nb >= 4 ? 0xffffffffu : (nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u));
-        const uint32_t d = __builtin_amdgcn_alignbyte(rp[m + 1], rp[m], rsh) & mask;
-        s2 = __builtin_amdgcn_udot4(d, d, s2, false);
+        const uint32_t d = rp[m] & mask;
+        e = __builtin_amdgcn_udot4(d, d, e, false);
       }
-      rowsq[i] = s2;
+      uint32_t* out = rowsq + yy * sh.ncand;
+      out[0] = e;
+      // candidate k + 1 = candidate k - pixel k + pixel k + PW
+      for (int k0 = 0; k0 + 1 < sh.ncand; k0 += 4) {
+        const uint32_t A = rp[k0 >> 2];
+        const int bq = (k0 + PW) >> 2;
+        const uint32_t B = __builtin_amdgcn_alignbyte(rp[bq + 1], rp[bq], (k0 + PW) & 3);
+        uint32_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int a = (int)((A >> (8 * q)) & 255u), b = (int)((B >> (8 * q)) & 255u);
+          e += (uint32_t)((b - a) * (b + a));
+          v[q] = e;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k0 + q + 1 < sh.ncand) out[k0 + q + 1] = v[q];
+      }
     }
   }
   __syncthreads();
@@ -578,6 +604,41 @@ __global__ __launch_bounds__(256) void k_texture(uint8_t* __restrict__ p, int n,
   p[i] = (uint8_t)(z ^ (z >> 15));
 }
 
+// Most distinct dwords that one bank serves for the SSD loop's first window
+// read, over the half-waves of a workgroup, at row stride d dwords.
+int bank_degree(int d, int ncand, int nstrips, int split, int KX, int rows_per_grp) {
+  const int base = ncand * nstrips, nthr = base * split;
+  int deg = 0;
+  for (int h0 = 0; h0 < nthr; h0 += 32) {
+    int addr[32], n = 0;
+    for (int t = h0; t < h0 + 32 && t < nthr; ++t) {
+      const int grp = t / base, rem = t % base;
+      addr[n++] = (rem / nstrips + grp * rows_per_grp) * d + (rem % nstrips) * (KX / 4);
+    }
+    std::sort(addr, addr + n);
+    const int u = (int)(std::unique(addr, addr + n) - addr);
+    int per_bank[32] = {0};
+    for (int k = 0; k < u; ++k) deg = std::max(deg, ++per_bank[addr[k] % 32]);
+  }
+  return deg;
+}
+
+int window_stride(int d0, int ncand, int nstrips, int split, int KX, int rows_per_grp) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int, int, int>, int> memo;
+  const auto key = std::make_tuple(d0, ncand, nstrips, split, KX, rows_per_grp);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = memo.find(key);
+  if (it != memo.end()) return it->second;
+  int best = d0, best_deg = 1 << 30;
+  for (int d = d0; d < d0 + 8; ++d) {  // at most 28 bytes more per row
+    const int deg = bank_degree(d, ncand, nstrips, split, KX, rows_per_grp);
+    if (deg < best_deg) { best_deg = deg; best = d; }
+  }
+  memo[key] = best;
+  return best;
+}
+
 SearchShape make_shape(int R, const SearchCfg& c, int split, long long ntiles, int KX,
                        size_t* lds, int* block) {
   SearchShape sh;
@@ -601,11 +662,12 @@ SearchShape make_shape(int R, const SearchCfg& c, int split, long long ntiles, i
   sh.NR = 2 * c.P + 2 * R + 1;
   // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
   const int need = (sh.nstrips * KX) + 4 * (NW + 1);
-  // an odd number of dwords per row: the threads of a wave read rows
-  // (j + i) at dword offsets (KX / 4) s, which an even stride maps onto the
-  // same banks
-  sh.wrow = (need + 3) / 4 * 4;
-  if ((sh.wrow / 4) % 2 == 0) sh.wrow += 4;
+  // The row stride: the lanes of a wave read window rows (j + i) at dword
+  // offsets (KX / 4) s; of the strides that hold a row (and up to 7 dwords
+  // more), the one whose half-waves (32 lanes, 32 banks) hit a bank with the
+  // fewest distinct dwords (then the shortest)
+  sh.wrow = 4 * window_stride((need + 3) / 4, sh.ncand, sh.nstrips, sh.split, KX,
+                              (2 * c.P + 1) / sh.split);
   int b = (sh.nthreads + 63) / 64 * 64;
   if (b < 64) b = 64;
   *block = b;
