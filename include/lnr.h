@@ -294,18 +294,25 @@ lnr_status lnr_set_flow_shape(lnr_ctx* ctx, int32_t w, int32_t h, const int32_t*
  * them to shapes[5 * i ...] (may be null) and returns how many there are. */
 int32_t lnr_flow_shapes(int32_t w, int32_t h, int32_t* shapes, int32_t max);
 /* Time every workgroup shape of the matcher's search (Sec. 2.2: how many
- * thread groups share a tile's patch rows, and whether each lane scores 8 or
- * 12 consecutive candidates) at each pyramid level of a w x h pair, on a
- * synthetic texture, and use the fastest for those level sizes and radii
- * from then on (results do not depend on it). splits_out[5] (optional): the
- * choice per level, the split (1..7) plus 16 where 12 candidates per lane
- * were faster, 0 past the last level. Synchronises. */
+ * thread groups share a tile's patch rows, and whether the SSD cross terms
+ * run as 8-bit dot products with each lane scoring 8 or 12 consecutive
+ * candidates, or on the matrix cores) at each pyramid level of a w x h pair,
+ * on a synthetic texture, and use the fastest for those level sizes and
+ * radii from then on (results do not depend on it). splits_out[5]
+ * (optional): the choice per level, the split (1..7) plus 16 where 12
+ * candidates per lane or 32 where the matrix cores were faster, 0 past the
+ * last level. Synchronises. */
 lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_params* p,
                                int32_t* splits_out, void* stream);
 /* Pin the search shape (as lnr_autotune_search reports it: a split 1..7,
- * plus 16 for 12 candidates per lane) for pyramid levels of level_w x
- * level_h searched at `radius` (host only; LNR_E_ARG for a shape the
- * search does not have). Results do not depend on it. */
+ * plus 16 for 12 candidates per lane or 32 for the matrix cores) for pyramid
+ * levels of level_w x level_h searched at `radius` (host only; LNR_E_ARG
+ * for a shape the search does not have, or one that needs more than 1024
+ * threads or 64 KB of workgroup memory with the default parameters; with
+ * other patch and corner parameters a shape that does not fit falls back to
+ * the automatic one). Results do not depend on it. lnr_stage_search and
+ * lnr_stage_search_window use the shape pinned or tuned for their size and
+ * radius. */
 lnr_status lnr_set_search_shape(lnr_ctx* ctx, int32_t level_w, int32_t level_h, int32_t radius,
                                 int32_t shape);
 

@@ -639,11 +639,13 @@ def flow_shapes(w: int, h: int):
 
 
 SEARCH_KX12 = 16
+SEARCH_MFMA = 32
 
 
 def set_search_shape(ctx: Context, level_w: int, level_h: int, radius: int, shape: int):
     """Pin the search shape (split 1..7, plus SEARCH_KX12 for 12 candidates per
-    lane) for levels of that size and radius."""
+    lane or SEARCH_MFMA for matrix-core cross terms) for levels of that size
+    and radius."""
     ctx.check(lib().lnr_set_search_shape(ctx._h, level_w, level_h, radius, shape))
 
 

@@ -49,6 +49,7 @@ namespace lnr {
 namespace {
 
 constexpr int NW = 6;        // patch row dwords (2P+1 <= 24)
+constexpr int kMaxNB = 5;    // blocks of 16 candidates per axis (2R + 1 <= 65)
 
 __device__ inline long long q8(double s) {
   double q = floor(s * 256.0 + 0.5);
@@ -147,7 +148,8 @@ __global__ __launch_bounds__(256) void k_warp_jobs(const WarpJob* __restrict__ j
 // as two aligned dwords realigned with v_alignbyte_b32, unrolled so that
 // several loads are in flight per thread.
 __device__ inline void stage_rows(const uint8_t* __restrict__ img, int w, int h, int x0, int y0,
-                                  int nrows, int ndw, uint8_t* dst, int ldst, int tid, int nt) {
+                                  int nrows, int ndw, uint8_t* dst, int ldst, int tid, int nt,
+                                  uint32_t flip = 0u) {
   const int total = nrows * ndw;
 #pragma unroll 4
   for (int i = tid; i < total; i += nt) {
@@ -170,24 +172,24 @@ __device__ inline void stage_rows(const uint8_t* __restrict__ img, int w, int h,
         }
       }
     }
-    *reinterpret_cast<uint32_t*>(dst + r * ldst + 4 * j) = v;
+    *reinterpret_cast<uint32_t*>(dst + r * ldst + 4 * j) = v ^ flip;
   }
 }
 
 // The window rows [y0, y0 + nrows) x bytes [x0, x0 + 4 * ndw) of the level
 // warped on the fly: each pixel inside the level is warp_px of the unwarped
 // source (the value k_warp_q8 stores there), 0 outside, as stage_rows reads
-// the stored warped level.
+// the stored warped level; every byte XOR flip.
 __device__ inline void stage_warped(const uint8_t* __restrict__ src, int w, int h,
                                     const double* hp, int x0, int y0, int nrows, int ndw,
-                                    uint8_t* dst, int ldst, int tid, int nt) {
+                                    uint8_t* dst, int ldst, int tid, int nt, uint32_t flip) {
   const int total = nrows * ndw * 4;
   for (int i = tid; i < total; i += nt) {
     const int r = i / (4 * ndw), b = i % (4 * ndw);
     const int gy = y0 + r, gx = x0 + b;
     uint32_t v = 0;
     if (gy >= 0 && gy < h && gx >= 0 && gx < w) v = warp_px(src, w, h, hp, gx, gy);
-    dst[r * ldst + b] = (uint8_t)v;
+    dst[r * ldst + b] = (uint8_t)(v ^ flip);
   }
 }
 
@@ -195,12 +197,17 @@ struct SearchShape {
   int R, nstrips, nthreads;
   int split;     // patch rows split over this many thread groups (partial SSDs summed in LDS)
   int NR;        // window rows = 2P + 2R + 1
-  int wrow;      // window row stride in bytes (an odd number of dwords)
+  int wrow;      // window row stride in bytes
+  int stage_dw;  // dwords staged per window row
   int ncand;     // 2R + 1
+  // matrix-core cross terms: candidate blocks of 16 (dy and dx), 64-byte
+  // chunks of a window row, the patch rows' zero padding (bytes, before the
+  // patch) and their length (dwords)
+  int NB, KC, padB, LB;
   // workgroup memory, sized for these parameters: the reference region
   // (rows of rs bytes), the quadrant row sums, then the window, its row
-  // energies, the split totals and the window energies
-  int rs, off_hsum, off_win;
+  // energies, the split totals, the window energies and the padded patch
+  int rs, off_hsum, off_win, off_rowsq, off_tot, off_colE, off_pb;
 };
 
 // nearest integer of a predicted source coordinate (half up), clamped far
@@ -229,6 +236,32 @@ struct TileShared {
   uint32_t er_sum;
   unsigned long long wmin[16];
 };
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Cross terms of one wave over patch rows [i0, i1) (see search_tile): ar is
+// the wave's first A row, pr0 its first padded patch dword; every row's
+// loads are issued before its NBT matrix products.
+template <int NBT>
+__device__ inline void cross_mfma(const uint8_t* ar, const uint32_t* pr0, int LB, int bs,
+                                  int wrow, int i0, int i1, v4i* acc) {
+#pragma unroll 2
+  for (int i = i0; i < i1; ++i) {
+    const uint32_t* pr = pr0 + i * LB;
+    const uint32_t e0 = pr[0], e1 = pr[1], e2 = pr[2], e3 = pr[3], e4 = pr[4];
+    const uint8_t* ai = ar + i * wrow;
+    v4i A[NBT];
+#pragma unroll
+    for (int mb = 0; mb < NBT; ++mb) A[mb] = *reinterpret_cast<const v4i*>(ai + 16 * mb * wrow);
+    const v4i B = v4i{(int)__builtin_amdgcn_alignbyte(e1, e0, bs),
+                      (int)__builtin_amdgcn_alignbyte(e2, e1, bs),
+                      (int)__builtin_amdgcn_alignbyte(e3, e2, bs),
+                      (int)__builtin_amdgcn_alignbyte(e4, e3, bs)};
+#pragma unroll
+    for (int mb = 0; mb < NBT; ++mb)
+      acc[mb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mb], B, acc[mb], 0, 0, 0);
+  }
+}
 
 // One tile of one job, by the whole workgroup (every branch below that
 // skips the rest of the tile is uniform over the workgroup).
@@ -261,7 +294,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       uint32_t v = 0;
       for (int k = 0; k < 4; ++k) {
         const int col = dw * 4 + k;
-        if (col < PW) v |= (uint32_t)reg[row * sh.rs + col] << (8 * k);
+        if (col < PW) v |= (uint32_t)(reg[row * sh.rs + col] ^ 0x80u) << (8 * k);
       }
       S.refp[i] = v;
     }
@@ -348,14 +381,16 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       return;
     }
     const int prx = ext + c.g * ba, pry = ext + c.g * bb;  // corner, region coordinates
-    // packed reference patch
+    // packed reference patch, centred (pixel - 128 as a signed byte; 0 past
+    // the patch width)
     const int P = c.P, PW = 2 * P + 1;
     for (int i = tid; i < PW * NW; i += nt) {
       const int row = i / NW, dw = i % NW;
       uint32_t v = 0;
       for (int k = 0; k < 4; ++k) {
         const int col = dw * 4 + k;
-        if (col < PW) v |= (uint32_t)reg[(pry - P + row) * sh.rs + prx - P + col] << (8 * k);
+        if (col < PW)
+          v |= (uint32_t)(reg[(pry - P + row) * sh.rs + prx - P + col] ^ 0x80u) << (8 * k);
       }
       S.refp[i] = v;
     }
@@ -373,15 +408,29 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
 
   // 2. the searched window ---------------------------------------------------
   const int P = c.P, PW = 2 * P + 1, R = sh.R;
+  // Window and patch are held centred (pixel - 128 as a signed byte; a pixel
+  // outside the image is 0, i.e. -128): r - w is unchanged, so the SSD is
+  // sum r'^2 + sum w'^2 - 2 sum r'w' exactly, and the cross term fits the
+  // signed 8-bit dot products and matrix-core operands.
   uint8_t* win = dyn + sh.off_win;
-  uint32_t* rowsq = reinterpret_cast<uint32_t*>(win + sh.NR * sh.wrow);
+  uint32_t* rowsq = reinterpret_cast<uint32_t*>(dyn + sh.off_rowsq);
   const int wx0 = px + cdx - P - R, wy0 = py + cdy - P - R;
   if (J.Hwarp) {
     double hp[9];
     pixel_homography(J.Hwarp, w, h, hp);
-    stage_warped(J.wimg, w, h, hp, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
+    stage_warped(J.wimg, w, h, hp, wx0, wy0, sh.NR, sh.stage_dw, win, sh.wrow, tid, nt, 0x80u);
   } else {
-    stage_rows(J.wimg, w, h, wx0, wy0, sh.NR, sh.wrow / 4, win, sh.wrow, tid, nt);
+    stage_rows(J.wimg, w, h, wx0, wy0, sh.NR, sh.stage_dw, win, sh.wrow, tid, nt, 0x80808080u);
+  }
+  if constexpr (KX == 0) {
+    // the patch rows with zero padding for the matrix-core operands:
+    // dword d of row i holds patch dword d - padB / 4 (0 outside the patch)
+    uint32_t* pb = reinterpret_cast<uint32_t*>(dyn + sh.off_pb);
+    const int d0 = sh.padB >> 2;
+    for (int q = tid; q < PW * sh.LB; q += nt) {
+      const int i = q / sh.LB, d = q - i * sh.LB - d0;
+      pb[q] = (d >= 0 && d < NW) ? S.refp[i * NW + d] : 0u;
+    }
   }
   __syncthreads();
   // patch energy and window row energies rowsq[y][k] = sum_c win[y][k + c]^2,
@@ -389,7 +438,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   {
     uint32_t part = 0;
     for (int i = tid; i < PW * NW; i += nt)
-      part = __builtin_amdgcn_udot4(S.refp[i], S.refp[i], part, false);
+      part = (uint32_t)__builtin_amdgcn_sdot4((int)S.refp[i], (int)S.refp[i], (int)part, false);
     if (part) atomicAdd(&S.er_sum, part);
   }
   // (one thread per window row: the first sum from dwords, then sliding by
@@ -408,8 +457,8 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       for (int m = 0; m < NW; ++m) {
         const int nb = PW - 4 * m;
         const uint32_t mask = nb >= 4 ? 0xffffffffu : (nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u));
-        const uint32_t d = rp[m] & mask;
-        e = __builtin_amdgcn_udot4(d, d, e, false);
+        const int d = (int)(rp[m] & mask);
+        e = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)e, false);
       }
       uint32_t* out = rowsq + yy * sh.ncand;
       out[0] = e;
@@ -421,7 +470,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
         uint32_t v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int a = (int)((A >> (8 * q)) & 255u), b = (int)((B >> (8 * q)) & 255u);
+          const int a = (int)(int8_t)(A >> (8 * q)), b = (int)(int8_t)(B >> (8 * q));
           e += (uint32_t)((b - a) * (b + a));
           v[q] = e;
         }
@@ -432,9 +481,8 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
     }
   }
   __syncthreads();
-  const int ncp = sh.nstrips * KX;  // padded candidates per row
-  uint32_t* tot = rowsq + sh.NR * sh.ncand + KX;  // [2][ncand][ncp] when split > 1
-  uint32_t* colE = tot + (sh.split > 1 ? 2 * sh.ncand * ncp : 0);  // [ncand][ncand]
+  uint32_t* tot = reinterpret_cast<uint32_t*>(dyn + sh.off_tot);    // split partial sums
+  uint32_t* colE = reinterpret_cast<uint32_t*>(dyn + sh.off_colE);  // [ncand][ncand]
   // window energies: vertical box sums of the row energies, sliding over
   // runs of 7 candidate rows per column
   {
@@ -451,76 +499,141 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       }
     }
   }
+  const int ncp = KX == 0 ? sh.ncand : sh.nstrips * KX;  // candidates per row of tot
   if (sh.split > 1)
     for (int i = tid; i < sh.ncand * ncp; i += nt) tot[i] = 0u;
   __syncthreads();
 
-  // 3. cross terms of KX candidates per thread (over a group of patch rows)
   unsigned long long key = ~0ull;
-  const int base_threads = sh.ncand * sh.nstrips;
-  const int grp = tid / base_threads, rem = tid % base_threads;
-  const int j = rem / sh.nstrips, s = rem % sh.nstrips;  // dy index, strip
-  uint32_t acc[KX];
+  const uint32_t er = S.er_sum;
+  // candidate (dy index j, dx index dxi) with cross term x: its key, if its
+  // patch lies inside the level
+  auto score = [&](int j, int dxi, uint32_t x) {
+    const int dx = dxi - R + cdx, dy = j - R + cdy;
+    if (px + dx - P < 0 || px + dx + P > w - 1 || py + dy - P < 0 || py + dy + P > h - 1) return;
+    // exact modulo 2^32, and the SSD itself is below 2^32
+    const uint32_t ssd = er + colE[j * sh.ncand + dxi] - 2u * x;
+    // ties on the absolute displacement, or on the offset from the
+    // predicted position when the window is centred on a prediction
+    const int kx = J.Hlit ? dxi - R : dx, ky = J.Hlit ? j - R : dy;
+    const uint32_t l1 = (uint32_t)((kx < 0 ? -kx : kx) + (ky < 0 ? -ky : ky));
+    // (ssd, |dx| + |dy|, dy, dx), displacements biased by 64 (|d| <= 64)
+    const unsigned long long kk = ((unsigned long long)ssd << 32) |
+                                  ((unsigned long long)l1 << 16) |
+                                  ((unsigned long long)(ky + 64) << 8) |
+                                  (unsigned long long)(kx + 64);
+    key = kk < key ? kk : key;
+  };
+
+  if constexpr (KX == 0) {
+    // 3. cross terms on the matrix cores. For patch row i the cross term of
+    // every candidate is a product of two small matrices,
+    //   X[dy][dx] += sum_x win[i + dy][x] * pat[i][x - dx],
+    // the window rows i .. i + 16 NB - 1 (A: 16 dy x 64 columns) times the
+    // Toeplitz matrix of patch row i (B: 64 columns x 16 dx, zero where
+    // x - dx falls outside the patch): v_mfma_i32_16x16x64_i8, exact in
+    // int32. Wave (group sp, dx block nb) accumulates the NB dy blocks of
+    // its dx block over its group's patch rows; lane (r, g) supplies A row
+    // dy = 16 mb + r, B column dx = 16 nb + r and bytes 16 g .. 16 g + 15 of
+    // each 64-byte chunk, and receives X[16 mb + 4 g + t][16 nb + r].
+    const int lane = tid & 63, wv = tid >> 6;
+    const int nb = wv % sh.NB, sp = wv / sh.NB;
+    const int r16 = lane & 15, cg = lane >> 4;
+    const uint32_t* pb = reinterpret_cast<const uint32_t*>(dyn + sh.off_pb);
+    v4i acc[kMaxNB];
 #pragma unroll
-  for (int k = 0; k < KX; ++k) acc[k] = 0;
-  if (tid < sh.nthreads) {
-    const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
-    const int rowdw = sh.wrow >> 2;
-    const int i0 = grp * PW / sh.split, i1 = (grp + 1) * PW / sh.split;
-    for (int i = i0; i < i1; ++i) {
-      const uint32_t* wr = wdw + (j + i) * rowdw + s * (KX / 4);
-      uint32_t wv[KX / 4 + NW + 1];
-#pragma unroll
-      for (int m = 0; m < KX / 4 + NW + 1; ++m) wv[m] = wr[m];
-      uint32_t rr[NW];
-#pragma unroll
-      for (int m = 0; m < NW; ++m) rr[m] = S.refp[i * NW + m];
-      uint32_t sft[4][KX / 4 + NW];
-#pragma unroll
-      for (int m = 0; m < KX / 4 + NW; ++m) {
-        sft[0][m] = wv[m];
-        sft[1][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 1);
-        sft[2][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 2);
-        sft[3][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 3);
-      }
-#pragma unroll
-      for (int k = 0; k < KX; ++k) {
-        const int q = k >> 2, rsh = k & 3;
-#pragma unroll
-        for (int m = 0; m < NW; ++m)
-          acc[k] = __builtin_amdgcn_udot4(sft[rsh][q + m], rr[m], acc[k], false);
+    for (int mb = 0; mb < kMaxNB; ++mb) acc[mb] = v4i{0, 0, 0, 0};
+    const int i0 = sp * PW / sh.split, i1 = (sp + 1) * PW / sh.split;
+    for (int kc = 0; kc < sh.KC; ++kc) {
+      // B bytes: patch row i at columns x - dx, x = 64 kc + 16 g + 0..15,
+      // i.e. bytes qb .. qb + 15 of the padded row (qb >= 1)
+      const int qb = 64 * kc + 16 * cg - (16 * nb + r16) + sh.padB;
+      const uint8_t* ar = win + r16 * sh.wrow + 64 * kc + 16 * cg;
+      const uint32_t* pr0 = pb + (qb >> 2);
+      switch (sh.NB) {
+        case 1: cross_mfma<1>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        case 2: cross_mfma<2>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        case 3: cross_mfma<3>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        case 4: cross_mfma<4>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        default: cross_mfma<5>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
       }
     }
-    if (sh.split > 1)  // exact integer partial sums: any order gives the same totals
+    const int dxi = 16 * nb + r16;
+    if (sh.split > 1) {  // exact integer partial sums: any order gives the same totals
 #pragma unroll
-      for (int k = 0; k < KX; ++k) atomicAdd(&tot[j * ncp + s * KX + k], acc[k]);
-  }
-  if (sh.split > 1) {
-    __syncthreads();
-    if (tid < base_threads)
+      for (int mb = 0; mb < kMaxNB; ++mb)
 #pragma unroll
-      for (int k = 0; k < KX; ++k) acc[k] = tot[j * ncp + s * KX + k];
-  }
-  if (tid < base_threads) {
-    const uint32_t er = S.er_sum;
+        for (int t = 0; t < 4; ++t) {
+          const int j = 16 * mb + 4 * cg + t;
+          if (mb < sh.NB && j < sh.ncand && dxi < sh.ncand)
+            atomicAdd(&tot[j * ncp + dxi], (uint32_t)acc[mb][t]);
+        }
+      __syncthreads();
+    }
+    if (sp == 0 && dxi < sh.ncand) {
 #pragma unroll
-    for (int k = 0; k < KX; ++k) {
-      const int dxi = s * KX + k;
-      if (dxi >= sh.ncand) continue;
-      const int dx = dxi - R + cdx, dy = j - R + cdy;
-      if (px + dx - P < 0 || px + dx + P > w - 1 || py + dy - P < 0 || py + dy + P > h - 1)
-        continue;
-      const uint32_t ssd = er + colE[j * sh.ncand + dxi] - 2u * acc[k];
-      // ties on the absolute displacement, or on the offset from the
-      // predicted position when the window is centred on a prediction
-      const int kx = J.Hlit ? dxi - R : dx, ky = J.Hlit ? j - R : dy;
-      const uint32_t l1 = (uint32_t)((kx < 0 ? -kx : kx) + (ky < 0 ? -ky : ky));
-      // (ssd, |dx| + |dy|, dy, dx), displacements biased by 64 (|d| <= 64)
-      const unsigned long long kk = ((unsigned long long)ssd << 32) |
-                                    ((unsigned long long)l1 << 16) |
-                                    ((unsigned long long)(ky + 64) << 8) |
-                                    (unsigned long long)(kx + 64);
-      key = kk < key ? kk : key;
+      for (int mb = 0; mb < kMaxNB; ++mb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int j = 16 * mb + 4 * cg + t;
+          if (mb >= sh.NB || j >= sh.ncand) continue;
+          score(j, dxi, sh.split > 1 ? tot[j * ncp + dxi] : (uint32_t)acc[mb][t]);
+        }
+    }
+  } else {
+    // 3. cross terms of KX candidates per thread (over a group of patch
+    // rows), signed 8-bit dot products of the centred bytes
+    const int base_threads = sh.ncand * sh.nstrips;
+    const int grp = tid / base_threads, rem = tid % base_threads;
+    const int j = rem / sh.nstrips, s = rem % sh.nstrips;  // dy index, strip
+    uint32_t acc[KX];
+#pragma unroll
+    for (int k = 0; k < KX; ++k) acc[k] = 0;
+    if (tid < sh.nthreads) {
+      const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
+      const int rowdw = sh.wrow >> 2;
+      const int i0 = grp * PW / sh.split, i1 = (grp + 1) * PW / sh.split;
+      for (int i = i0; i < i1; ++i) {
+        const uint32_t* wr = wdw + (j + i) * rowdw + s * (KX / 4);
+        uint32_t wv[KX / 4 + NW + 1];
+#pragma unroll
+        for (int m = 0; m < KX / 4 + NW + 1; ++m) wv[m] = wr[m];
+        uint32_t rr[NW];
+#pragma unroll
+        for (int m = 0; m < NW; ++m) rr[m] = S.refp[i * NW + m];
+        uint32_t sft[4][KX / 4 + NW];
+#pragma unroll
+        for (int m = 0; m < KX / 4 + NW; ++m) {
+          sft[0][m] = wv[m];
+          sft[1][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 1);
+          sft[2][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 2);
+          sft[3][m] = __builtin_amdgcn_alignbyte(wv[m + 1], wv[m], 3);
+        }
+#pragma unroll
+        for (int k = 0; k < KX; ++k) {
+          const int q = k >> 2, rsh = k & 3;
+#pragma unroll
+          for (int m = 0; m < NW; ++m)
+            acc[k] = (uint32_t)__builtin_amdgcn_sdot4((int)sft[rsh][q + m], (int)rr[m],
+                                                       (int)acc[k], false);
+        }
+      }
+      if (sh.split > 1)  // exact integer partial sums: any order gives the same totals
+#pragma unroll
+        for (int k = 0; k < KX; ++k) atomicAdd(&tot[j * ncp + s * KX + k], acc[k]);
+    }
+    if (sh.split > 1) {
+      __syncthreads();
+      if (tid < base_threads)
+#pragma unroll
+        for (int k = 0; k < KX; ++k) acc[k] = tot[j * ncp + s * KX + k];
+    }
+    if (tid < base_threads) {
+#pragma unroll
+      for (int k = 0; k < KX; ++k) {
+        const int dxi = s * KX + k;
+        if (dxi < sh.ncand) score(j, dxi, acc[k]);
+      }
     }
   }
   // 4. argmin -------------------------------------------------------------------
@@ -641,11 +754,15 @@ int window_stride(int d0, int ncand, int nstrips, int split, int KX, int rows_pe
 
 SearchShape make_shape(int R, const SearchCfg& c, int split, long long ntiles, int KX,
                        size_t* lds, int* block) {
-  SearchShape sh;
+  SearchShape sh{};
   sh.R = R;
   sh.ncand = 2 * R + 1;
-  sh.nstrips = (sh.ncand + KX - 1) / KX;
-  const int base = sh.ncand * sh.nstrips;
+  const int PW = 2 * c.P + 1;
+  // threads of one patch-row group: a lane per (dy, strip of KX dx), or a
+  // wave per block of 16 dx (matrix cores)
+  sh.NB = (sh.ncand + 15) / 16;
+  sh.nstrips = KX == 0 ? 0 : (sh.ncand + KX - 1) / KX;
+  const int base = KX == 0 ? 64 * sh.NB : sh.ncand * sh.nstrips;
   if (split > 0) {  // a tuned split (the results do not depend on it)
     sh.split = split;
   } else {
@@ -656,18 +773,32 @@ SearchShape make_shape(int R, const SearchCfg& c, int split, long long ntiles, i
   }
   if (sh.split < 1) sh.split = 1;
   if (sh.split > 7) sh.split = 7;
-  if (sh.split > 2 * c.P + 1) sh.split = 2 * c.P + 1;
+  if (sh.split > PW) sh.split = PW;
   while (sh.split > 1 && base * sh.split > 1024) --sh.split;
   sh.nthreads = base * sh.split;
   sh.NR = 2 * c.P + 2 * R + 1;
-  // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
-  const int need = (sh.nstrips * KX) + 4 * (NW + 1);
-  // The row stride: the lanes of a wave read window rows (j + i) at dword
-  // offsets (KX / 4) s; of the strides that hold a row (and up to 7 dwords
-  // more), the one whose half-waves (32 lanes, 32 banks) hit a bank with the
-  // fewest distinct dwords (then the shortest)
-  sh.wrow = 4 * window_stride((need + 3) / 4, sh.ncand, sh.nstrips, sh.split, KX,
-                              (2 * c.P + 1) / sh.split);
+  int nrows = sh.NR;  // window rows held
+  if (KX == 0) {
+    // A reads 64-byte chunks of rows up to i + 16 NB - 1 (the rows and
+    // columns past the window only meet zero B entries or unused outputs)
+    const int wc = sh.ncand - 1 + PW;
+    sh.KC = (wc + 63) / 64;
+    sh.wrow = 64 * sh.KC + 16;  // 16-byte aligned rows, shifted by 4 banks
+    sh.stage_dw = (wc + 3) / 4;
+    nrows = std::max(sh.NR, 16 * sh.NB + PW - 1);
+    sh.padB = 16 * sh.NB;
+    sh.LB = 16 * sh.KC + 4 * sh.NB + 1;
+  } else {
+    // bytes read per row: the last strip's (KX/4 + NW + 1) dwords
+    const int need = (sh.nstrips * KX) + 4 * (NW + 1);
+    // The row stride: the lanes of a wave read window rows (j + i) at dword
+    // offsets (KX / 4) s; of the strides that hold a row (and up to 7 dwords
+    // more), the one whose half-waves (32 lanes, 32 banks) hit a bank with the
+    // fewest distinct dwords (then the shortest)
+    sh.wrow = 4 * window_stride((need + 3) / 4, sh.ncand, sh.nstrips, sh.split, KX,
+                                PW / sh.split);
+    sh.stage_dw = sh.wrow / 4;
+  }
   int b = (sh.nthreads + 63) / 64 * 64;
   if (b < 64) b = 64;
   *block = b;
@@ -682,10 +813,14 @@ SearchShape make_shape(int R, const SearchCfg& c, int split, long long ntiles, i
   sh.off_hsum = (sh.rs * (side + 1) + 15) / 16 * 16;
   sh.off_win = (sh.off_hsum + hsum_words * 4 + 15) / 16 * 16;
   // window, row energies (+ KX words: the last strip's padded candidates read
-  // past the last row), the split totals and the window energies
-  *lds = (size_t)sh.off_win + (size_t)sh.NR * sh.wrow + (size_t)sh.NR * sh.ncand * 4 + KX * 4 +
-         (sh.split > 1 ? (size_t)2 * sh.ncand * sh.nstrips * KX * 4 : 0) +
-         (size_t)sh.ncand * sh.ncand * 4;
+  // past the last row), the split totals, the window energies, the padded
+  // patch rows
+  sh.off_rowsq = sh.off_win + nrows * sh.wrow;
+  sh.off_tot = sh.off_rowsq + (sh.NR * sh.ncand + KX) * 4;
+  const int ncp = KX == 0 ? sh.ncand : sh.nstrips * KX;
+  sh.off_colE = sh.off_tot + (sh.split > 1 ? sh.ncand * ncp * 4 : 0);
+  sh.off_pb = (sh.off_colE + sh.ncand * sh.ncand * 4 + 15) / 16 * 16;
+  *lds = (size_t)sh.off_pb + (KX == 0 ? (size_t)PW * sh.LB * 4 : 0);
   return sh;
 }
 
@@ -707,14 +842,20 @@ hipError_t launch_warp_jobs(const WarpJob* jobs, const int* row0, int njobs, int
   return hipGetLastError();
 }
 
+bool search_shape_fits(int R, const SearchCfg& c, int code) {
+  const int split = code & kSearchSplitMask;
+  if (split < 1 || split > 7 || split > 2 * c.P + 1 || search_threads(R, code) > 1024) return false;
+  size_t lds = 0;
+  int block = 0;
+  make_shape(R, c, split, 1, shape_kx(code, 8), &lds, &block);
+  return lds + sizeof(TileShared) <= 65536;
+}
+
 int search_split_candidates(int R, const SearchCfg& c, int* out, int max) {
-  const int ncand = 2 * R + 1;
   int n = 0;
-  for (int kx = 8; kx <= 12; kx += 4) {
-    const int base = ncand * ((ncand + kx - 1) / kx);
-    for (int s = 1; s <= 7 && s <= 2 * c.P + 1 && n < max; ++s)
-      if (base * s <= 1024) out[n++] = s | (kx == 12 ? kSearchKx12 : 0);
-  }
+  for (const int code : {0, kSearchKx12, kSearchMfma})
+    for (int s = 1; s <= 7 && n < max; ++s)
+      if (search_shape_fits(R, c, s | code)) out[n++] = s | code;
   return n;
 }
 
@@ -753,13 +894,20 @@ hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c,
                          hipStream_t st, const uint8_t* mode, int want, int split) {
   const int ntiles = J.ntx * nty;
   if (ntiles == 0) return hipSuccess;
-  // a tuned choice: the split (1..7), plus kSearchKx12 for 12 candidates per lane
-  const int kx = (split & kSearchKx12) ? 12 : 8;
+  // a tuned choice: the split (1..7), plus kSearchKx12 (12 candidates per
+  // lane) or kSearchMfma (matrix-core cross terms)
+  const int kx = shape_kx(split, 8);
+  // (a shape that does not fit these patch and corner parameters: the
+  // automatic split)
+  if (split && !search_shape_fits(R, c, split)) split &= ~kSearchSplitMask;
   size_t lds = 0;
   int block = 0;
-  const SearchShape sh = make_shape(R, c, split & ~kSearchKx12, ntiles, kx, &lds, &block);
-  return kx == 12 ? launch_search_kx<12>(J, ntiles, c, sh, role, block, lds, st, mode, want)
-                  : launch_search_kx<8>(J, ntiles, c, sh, role, block, lds, st, mode, want);
+  const SearchShape sh = make_shape(R, c, split & kSearchSplitMask, ntiles, kx, &lds, &block);
+  switch (kx) {
+    case 0: return launch_search_kx<0>(J, ntiles, c, sh, role, block, lds, st, mode, want);
+    case 12: return launch_search_kx<12>(J, ntiles, c, sh, role, block, lds, st, mode, want);
+    default: return launch_search_kx<8>(J, ntiles, c, sh, role, block, lds, st, mode, want);
+  }
 }
 
 template <int KX>
@@ -787,7 +935,10 @@ hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R
                               const SearchCfg& c, int visit, int want, int split, int kx,
                               int grid, hipStream_t st, const SearchJob* one) {
   if (grid < 1) return hipSuccess;
-  if (kx != 8 && kx != 12) return hipErrorInvalidValue;
+  kx = shape_kx(split, kx);  // flags in a tuned shape code take precedence
+  if ((split & kSearchSplitMask) && !search_shape_fits(R, c, split)) split = 0;
+  split &= kSearchSplitMask;
+  if (kx != 0 && kx != 8 && kx != 12) return hipErrorInvalidValue;
   if (!jobs && !one) return hipErrorInvalidValue;
   size_t lds = 0;
   int block = 0;
@@ -796,8 +947,11 @@ hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R
   if (visit == kVisitCornersOnly) lds = (size_t)sh.off_win;
   const SearchJob none{};
   const SearchJob& J = one ? *one : none;
-  return kx == 8 ? launch_work_kx<8>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st)
-                 : launch_work_kx<12>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
+  switch (kx) {
+    case 0: return launch_work_kx<0>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
+    case 12: return launch_work_kx<12>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
+    default: return launch_work_kx<8>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
+  }
 }
 
 }  // namespace lnr

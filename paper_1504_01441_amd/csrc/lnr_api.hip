@@ -268,6 +268,13 @@ SearchCfg search_cfg(const lnr_params& p) {
   return c;
 }
 
+// the search shape tuned or pinned in this context for levels of w x h
+// searched at radius R (0: the automatic shape)
+int pinned_search_shape(const lnr_ctx* ctx, int w, int h, int R) {
+  auto it = ctx->search_split.find(std::make_tuple(w, h, R));
+  return it == ctx->search_split.end() ? 0 : it->second;
+}
+
 struct Plan {
   size_t off = 0;
   size_t take(size_t bytes) {
@@ -527,10 +534,7 @@ lnr_status enqueue_pair_levels(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fra
   const WeedBufs wb = weed_bufs(base, q.wp);
   (void)src;
   const SearchCfg cfg = search_cfg(*p);
-  auto tuned = [&](int w, int h, int R) {
-    auto it = ctx->search_split.find(std::make_tuple(w, h, R));
-    return it == ctx->search_split.end() ? 0 : it->second;
-  };
+  auto tuned = [&](int w, int h, int R) { return pinned_search_shape(ctx, w, h, R); };
   // search_frame 1 (Eq. 3 as printed): no level is warped; each level searches
   // the unwarped source around its prediction, the fits are absolute (composed
   // on the identity above the top level) and so is the propagated flow
@@ -1041,7 +1045,8 @@ lnr_status lnr_stage_search(lnr_ctx* ctx, const uint8_t* ref, const uint8_t* war
   if (R < 0 || R > kMaxRadius) return fail(ctx, LNR_E_UNSUPPORTED, "radius must be in [0, 32]");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
   const SearchJob J = search_job(ref, warped, w, h, w / p->tile, corner_xy, disp, ssd, flags);
-  LNR_HIP(launch_search(J, h / p->tile, R, search_cfg(*p), kRoleStage, (hipStream_t)stream));
+  LNR_HIP(launch_search(J, h / p->tile, R, search_cfg(*p), kRoleStage, (hipStream_t)stream,
+                        nullptr, 0, pinned_search_shape(ctx, w, h, R)));
   return LNR_OK;
 }
 
@@ -1450,7 +1455,8 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
       }
     }
     // time 1, 2, 4 and 8 concurrent streams on this batch (eager), then (level-
-    // synchronous batches) 8 or 12 search candidates per lane; keep the fastest
+    // synchronous batches) 8 or 12 search candidates per lane or the matrix
+    // cores; keep the fastest
     hipEvent_t t0 = nullptr, t1 = nullptr;
     LNR_HIP(hipEventCreate(&t0));
     LNR_HIP(hipEventCreate(&t1));
@@ -1475,11 +1481,12 @@ lnr_status lnr_register_batch(lnr_ctx* ctx, const lnr_frame* refs, const lnr_fra
       if ((s = time_one(k, 8, &ms)) != LNR_OK) return s;
       if (c == 0 || ms < best) { best = ms; K = k; }
     }
-    if (levels) {
-      float ms = 0.f;
-      if ((s = time_one(K, 12, &ms)) != LNR_OK) return s;
-      if (ms < best) kx = 12;
-    }
+    if (levels)
+      for (const int kxx : {12, 0}) {  // 12 candidates per lane, the matrix cores
+        float ms = 0.f;
+        if ((s = time_one(K, kxx, &ms)) != LNR_OK) return s;
+        if (ms < best) { best = ms; kx = kxx; }
+      }
     LNR_HIP(hipEventDestroy(t0));
     LNR_HIP(hipEventDestroy(t1));
     ctx->batch_k[shape] = K;
@@ -1630,14 +1637,15 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
 lnr_status lnr_set_search_shape(lnr_ctx* ctx, int32_t level_w, int32_t level_h, int32_t radius,
                                 int32_t shape) {
   if (!ctx) return LNR_E_ARG;
-  const int split = shape & ~kSearchKx12;
-  if (level_w < 1 || level_h < 1 || radius < 0 || radius > kMaxRadius || split < 1 || split > 7 ||
-      (shape & ~(kSearchKx12 | 7)))
+  const int split = shape & kSearchSplitMask;
+  if (level_w < 1 || level_h < 1 || radius < 0 || radius > kMaxRadius || split < 1 ||
+      (shape & ~(kSearchKx12 | kSearchMfma | kSearchSplitMask)) ||
+      ((shape & kSearchKx12) && (shape & kSearchMfma)))
     return fail(ctx, LNR_E_ARG, "bad search shape");
-  const int kx = (shape & kSearchKx12) ? 12 : 8;
-  const int ncand = 2 * radius + 1;
-  if (ncand * ((ncand + kx - 1) / kx) * split > 1024)
-    return fail(ctx, LNR_E_ARG, "search shape needs more than 1024 threads");
+  lnr_params dp;
+  lnr_default_params(&dp);
+  if (!search_shape_fits(radius, search_cfg(dp), shape))
+    return fail(ctx, LNR_E_ARG, "search shape needs more than 1024 threads or 64 KB");
   ctx->search_split[std::make_tuple((int)level_w, (int)level_h, (int)radius)] = shape;
   return LNR_OK;
 }
@@ -1674,8 +1682,8 @@ lnr_status lnr_autotune_search(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_par
     // corners and every candidate is scored, as on real frames
     LNR_HIP(launch_texture(reinterpret_cast<uint8_t*>(b + o_a), n, 0x5eedu + (uint32_t)l, st));
     LNR_HIP(hipMemcpyAsync(b + o_b, b + o_a, (size_t)n, hipMemcpyDeviceToDevice, st));
-    int cand[8];
-    const int nc = search_split_candidates(R, cfg, cand, 8);
+    int cand[24];
+    const int nc = search_split_candidates(R, cfg, cand, 24);
     int best = cand[0];
     float best_ms = 0.f;
     for (int c = 0; c < nc; ++c) {
@@ -1731,7 +1739,8 @@ lnr_status lnr_stage_search_window(lnr_ctx* ctx, const uint8_t* ref, const uint8
   }
   const SearchJob J = search_job(ref, warped, w, h, w / p->tile, corner_xy, disp, ssd, flags,
                                  centre);
-  LNR_HIP(launch_search(J, h / p->tile, R, search_cfg(*p), kRoleStage, (hipStream_t)stream));
+  LNR_HIP(launch_search(J, h / p->tile, R, search_cfg(*p), kRoleStage, (hipStream_t)stream,
+                        nullptr, 0, pinned_search_shape(ctx, w, h, R)));
   return LNR_OK;
 }
 

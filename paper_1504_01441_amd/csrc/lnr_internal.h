@@ -112,9 +112,20 @@ struct SearchWork {
   int* out_list;            // corner visits: cornered tiles appended here (device)
   int* out_count;
 };
-// a tuned search shape: the patch-row split (1..7), plus this flag when the
-// lanes score 12 consecutive candidates instead of 8
-constexpr int kSearchKx12 = 16;
+// a tuned search shape: the patch-row split (1..7), plus kSearchKx12 when
+// the lanes score 12 consecutive candidates instead of 8, or kSearchMfma
+// when the cross terms run on the matrix cores (a wave per 16 dx)
+constexpr int kSearchKx12 = 16, kSearchMfma = 32, kSearchSplitMask = 7;
+// candidates per lane of a shape code (0: matrix cores), dflt without flags
+inline int shape_kx(int code, int dflt) {
+  return (code & kSearchMfma) ? 0 : (code & kSearchKx12) ? 12 : dflt;
+}
+// threads of one workgroup for radius R and a shape code with a split
+inline int search_threads(int R, int code) {
+  const int ncand = 2 * R + 1, kx = shape_kx(code, 8), split = code & kSearchSplitMask;
+  const int base = kx == 0 ? 64 * ((ncand + 15) / 16) : ncand * ((ncand + kx - 1) / kx);
+  return base * split;
+}
 // names of single-job search launches (profiles tell the levels apart)
 constexpr int kRoleCoarse = 0, kRoleLevel0 = 1, kRoleTrial = 2, kRoleStage = 3;
 // tile visits of the work-list search
@@ -144,8 +155,10 @@ hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R
                               int grid, hipStream_t st, const SearchJob* one = nullptr);
 
 // search shapes that launch_search accepts for radius R (splits of the patch
-// rows over thread groups, with 8 and with 12 candidates per lane); and a
-// random 8-bit texture for timing the search
+// rows over thread groups, with 8 or 12 candidates per lane or the matrix
+// cores: at most 1024 threads and 64 KB of workgroup memory); and a random
+// 8-bit texture for timing the search
+bool search_shape_fits(int R, const SearchCfg& c, int code);
 int search_split_candidates(int R, const SearchCfg& c, int* out, int max);
 hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st);
 

@@ -138,7 +138,9 @@ def test_autotuned_search_split_keeps_results(lnr, w, h, radius0):
     before = lnr.register_pair(c, F0, F1, p)
     torch.cuda.synchronize()
     splits = lnr.autotune_search(c, w, h, p)
-    assert len(splits) >= 2 and all(1 <= (s & 15) <= 7 and s & ~31 == 0 for s in splits)
+    # a split 1..7, plus 16 (12 candidates per lane) or 32 (matrix cores)
+    assert len(splits) >= 2 and all(1 <= (s & 7) <= 7 and s & ~(16 | 32 | 7) == 0 and
+                                    (s & 48) != 48 for s in splits)
     after = lnr.register_pair(c, F0, F1, p)
     torch.cuda.synchronize()
     _same(before, after)
@@ -310,10 +312,11 @@ def test_c5_learned_batch_full_size_equals_single_calls(lnr, ctx):
         _same(a, b)
 
 
-@pytest.mark.parametrize("shape", [1, 3, 16 | 1, 16 | 2, 16 | 7])
+@pytest.mark.parametrize("shape", [1, 3, 16 | 1, 16 | 2, 16 | 7, 32 | 1, 32 | 2, 32 | 5])
 def test_every_search_shape_keeps_results(lnr, shape):
-    """Each pinned search shape (patch-row split, 8 or 12 candidates per lane)
-    at every level gives the untuned registration bit for bit."""
+    """Each pinned search shape (patch-row split; 8 or 12 candidates per lane,
+    or the matrix cores) at every level gives the untuned registration bit
+    for bit."""
     p = lnr.Params(radius0=16)
     st = synth.make_stack(640, 480, 777, ratios=(1.0, 4.0), fmt="y8", shift_range=8)
     f0, f1 = st.frames
@@ -331,6 +334,12 @@ def test_every_search_shape_keeps_results(lnr, shape):
 
 def test_search_shape_rejects_bad_shapes(lnr):
     c = lnr.Context(0)
-    for bad in (0, 8, 16, 32 | 1, 64):
+    for bad in (0, 8, 16, 32, 16 | 32 | 1, 64, 64 | 1):
         with pytest.raises(lnr.LnrError):
             lnr.set_search_shape(c, 640, 480, 16, bad)
+    # more than 64 KB of workgroup memory (radius 32, two patch-row groups on
+    # the matrix cores) or more than 1024 threads (radius 32, 8 per lane, 2 groups)
+    for bad in (32 | 2, 2):
+        with pytest.raises(lnr.LnrError):
+            lnr.set_search_shape(c, 640, 480, 32, bad)
+    lnr.set_search_shape(c, 640, 480, 32, 32 | 1)

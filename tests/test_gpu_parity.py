@@ -127,6 +127,48 @@ def test_search_other_patch_and_grid(ctx):
     assert np.array_equal(flags.cpu().numpy(), has | (valid << 1))
 
 
+@pytest.mark.parametrize("R,shape", [(0, 32 | 1), (3, 32 | 1), (3, 32 | 3), (8, 32 | 2),
+                                     (10, 32 | 1), (10, 32 | 4), (16, 32 | 1), (16, 32 | 3),
+                                     (32, 32 | 1)])
+def test_search_mfma_vs_oracle(R, shape):
+    """The matrix-core cross terms (window rows times the Toeplitz matrix of a
+    patch row, int8 products of the centred pixels), pinned for the level's
+    size, against the oracle's search: corners, displacements, SSDs and flags
+    bit for bit, with and without the patch rows split over wave groups."""
+    c = lnr().Context(0)
+    st, a, b = _eq_pair("c1", 4)
+    p, op = params_pair()
+    h, w = a.shape
+    lnr().set_search_shape(c, w, h, R, shape)
+    cx, cy, has = oracle.corners(a, op)
+    dx, dy, ssd, valid = oracle.search(a, b, R, cx, cy, has, op)
+    cxy, disp, gssd, flags = lnr().stage_search(c, _t(a), _t(b), R, p)
+    _sync()
+    d = disp.cpu().numpy()
+    assert np.array_equal(d[:, 0], dx) and np.array_equal(d[:, 1], dy)
+    assert np.array_equal(gssd.cpu().numpy().view(np.uint32), ssd)
+    assert np.array_equal(flags.cpu().numpy(), has | (valid << 1))
+    c.close()
+
+
+def test_search_mfma_other_patch_and_grid():
+    c = lnr().Context(0)
+    st, a, b = _eq_pair("c1", 6)
+    kw = dict(tile=48, patch_r=7, corner_half=3, corner_step=3, quad_r=8, corner_t=1)
+    p, op = params_pair(**kw)
+    h, w = a.shape
+    lnr().set_search_shape(c, w, h, 12, 32 | 2)
+    cx, cy, has = oracle.corners(a, op)
+    dx, dy, ssd, valid = oracle.search(a, b, 12, cx, cy, has, op)
+    cxy, disp, gssd, flags = lnr().stage_search(c, _t(a), _t(b), 12, p)
+    _sync()
+    d = disp.cpu().numpy()
+    assert np.array_equal(d[:, 0], dx) and np.array_equal(d[:, 1], dy)
+    assert np.array_equal(gssd.cpu().numpy().view(np.uint32), ssd)
+    assert np.array_equal(flags.cpu().numpy(), has | (valid << 1))
+    c.close()
+
+
 def _oracle_level0(cfg, seed, scale=None, **kw):
     st = synth.make_config_pair(cfg, seed, scale=scale)
     kw.setdefault("radius0", st.meta["radius0"])
