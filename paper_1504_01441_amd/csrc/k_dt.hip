@@ -20,7 +20,10 @@
 //  k_dt_row: one workgroup per row; the row is staged in LDS with coalesced
 //          loads, each of the 256 or 512 threads keeps a segment in registers, and
 //          wave shuffles + LDS combine the segment maps. The first pass writes
-//          the sparse maps itself from the tile list (no zero-fill pass).
+//          the sparse maps itself from the tile list (no zero-fill pass); a
+//          row that holds no sample stays exactly zero through it, so that
+//          pass writes only a row flag for it, and the first column pass
+//          reads the records of flagged rows only (the rest are zeros).
 //  k_dt_col: one workgroup per strip of 2-8 columns over the full height, as
 //          128 or 256 segments per column held in registers; the records are read
 //          and written once per pass. The last pass writes F (and N~) instead.
@@ -147,7 +150,8 @@ __global__ __launch_bounds__(NT) void k_dt_row(Rec* __restrict__ maps,
                                                 const int32_t* __restrict__ cxy,
                                                 const int32_t* __restrict__ disp,
                                                 const uint8_t* __restrict__ flags, int ntx,
-                                                int nty, int tile) {
+                                                int nty, int tile,
+                                                uint8_t* __restrict__ rowflag) {
   extern __shared__ float sm[];
   __shared__ double cf[256];
   __shared__ Aff wtot[NT / 64];
@@ -157,6 +161,19 @@ __global__ __launch_bounds__(NT) void k_dt_row(Rec* __restrict__ maps,
   uint8_t* g = reinterpret_cast<uint8_t*>(sm + 3 * W);
   const int y = blockIdx.x, tid = threadIdx.x;
   const size_t ro = (size_t)y * W;
+  if (FIRST) {
+    // the row's samples (kept level-0 matches whose corner lies on it)
+    int has = 0;
+    const int ty = y / tile;
+    if (ty < nty)
+      for (int tx = tid; tx < ntx; tx += NT) {
+        const int t = ty * ntx + tx;
+        has |= (flags[t] & 4) && cxy[2 * t + 1] == y;
+      }
+    has = __syncthreads_or(has);
+    if (tid == 0) rowflag[y] = (uint8_t)(has != 0);
+    if (!has) return;  // all zeros: the column pass does not read this row
+  }
   if (tid < 256) cf[tid] = coef[tid];
   // staging: several loads in flight per thread (batches of kStageU per
   // thread, issued before the LDS stores)
@@ -324,7 +341,8 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(Rec* __restrict__ maps,
                                                         int W, int H,
                                                         const double* __restrict__ coef,
                                                         float* __restrict__ flow,
-                                                        float* __restrict__ ntilde, double nmin) {
+                                                        float* __restrict__ ntilde, double nmin,
+                                                        const uint8_t* __restrict__ rowflag) {
   __shared__ double cf[256];
   __shared__ Aff wt[NSEG * NCOL / 64 * NCOL];
   const int tid = threadIdx.x, cl = tid % NCOL, sg = tid / NCOL;
@@ -363,13 +381,28 @@ __global__ __launch_bounds__(NCOL * NSEG) void k_dt_col(Rec* __restrict__ maps,
 #pragma unroll
     for (int q = 0; q < NG; ++q) gpk[q] = 0u;
   }
+  // first pass: the rows the row pass left at zero are not read (their
+  // flags, as for the guide, one aligned load per 8 rows; the flag buffer
+  // runs past the last row)
+  uint32_t rf[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) rf[q] = 0x01010101u;
+  if (rowflag) {
+    const uint2* rw = reinterpret_cast<const uint2*>(rowflag + r0);
+#pragma unroll
+    for (int q = 0; q < NG / 2; ++q) {
+      const uint2 v = seg_in ? rw[q] : uint2{0u, 0u};
+      rf[2 * q] = v.x;
+      rf[2 * q + 1] = v.y;
+    }
+  }
   // the segment is held as float (as stored between passes); every recursion
   // step and carry is computed in double precision
   float a0[L], a1[L], a2[L];
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     const int y = r0 + j;
-    const bool in = act && y < H;
+    const bool in = act && y < H && ((rf[j >> 2] >> (8 * (j & 3))) & 255u);
     const Rec r = in ? maps[(size_t)y * W + col] : Rec{0.f, 0.f, 0.f};
     a0[j] = r.m0;
     a1[j] = r.m1;
@@ -465,7 +498,8 @@ __global__ __launch_bounds__(256) void k_guide_columns(const uint8_t* __restrict
 template <int SEG, int NT>
 hipError_t launch_row(bool first, Rec* maps, const uint8_t* guide, int W, int H,
                       const double* cf, const int32_t* cxy, const int32_t* disp,
-                      const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
+                      const uint8_t* flags, int ntx, int nty, int tile, uint8_t* rowflag,
+                      hipStream_t st) {
   const size_t lds = (size_t)W * 3 * sizeof(float) + (size_t)W + 16;
   if (lds > 64 * 1024) {  // rows wider than ~5000 px need more than the default LDS
     hipError_t e = hipFuncSetAttribute(
@@ -475,24 +509,25 @@ hipError_t launch_row(bool first, Rec* maps, const uint8_t* guide, int W, int H,
   }
   if (first)
     LNR_LAUNCH((k_dt_row<SEG, NT, true>), dim3(H), dim3(NT), lds, st, maps, guide, W, H, cf, cxy,
-               disp, flags, ntx, nty, tile);
+               disp, flags, ntx, nty, tile, rowflag);
   else
     LNR_LAUNCH((k_dt_row<SEG, NT, false>), dim3(H), dim3(NT), lds, st, maps, guide, W, H, cf, cxy,
-               disp, flags, ntx, nty, tile);
+               disp, flags, ntx, nty, tile, nullptr);
   return hipGetLastError();
 }
 
 template <int L, int NCOL, int NSEG>
 hipError_t launch_col(bool last, Rec* maps, const uint8_t* gt, int W, int H,
-                      const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
+                      const double* cf, float* flow, float* ntilde, double nmin,
+                      const uint8_t* rowflag, hipStream_t st) {
   const dim3 grid((W + NCOL - 1) / NCOL);
   const int hp = dt_guide_stride(H);
   if (last)
     LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, true>), grid, dim3(NCOL * NSEG), 0, st, maps, gt, hp, W,
-               H, cf, flow, ntilde, nmin);
+               H, cf, flow, ntilde, nmin, rowflag);
   else
     LNR_LAUNCH((k_dt_col<L, NCOL, NSEG, false>), grid, dim3(NCOL * NSEG), 0, st, maps, gt, hp, W,
-               H, cf, flow, ntilde, nmin);
+               H, cf, flow, ntilde, nmin, rowflag);
   return hipGetLastError();
 }
 
@@ -508,20 +543,23 @@ const DtShape kColShapes[] = {{0, 0, 8, 8, 128},  {0, 0, 8, 4, 128},  {0, 0, 16,
 
 hipError_t row_pass(const DtShape& s, bool first, Rec* maps, const uint8_t* guide, int W, int H,
                     const double* cf, const int32_t* cxy, const int32_t* disp,
-                    const uint8_t* flags, int ntx, int nty, int tile, hipStream_t st) {
+                    const uint8_t* flags, int ntx, int nty, int tile, uint8_t* rowflag,
+                    hipStream_t st) {
 #define ROW(SEG, NT)                                                                           \
   if (s.seg == SEG && s.nt == NT)                                                              \
-    return launch_row<SEG, NT>(first, maps, guide, W, H, cf, cxy, disp, flags, ntx, nty, tile, st);
+    return launch_row<SEG, NT>(first, maps, guide, W, H, cf, cxy, disp, flags, ntx, nty, tile, \
+                               rowflag, st);
   ROW(4, 256) ROW(8, 256) ROW(12, 256) ROW(4, 512) ROW(6, 512) ROW(8, 512) ROW(12, 512)
 #undef ROW
   return hipErrorInvalidValue;
 }
 
 hipError_t col_pass(const DtShape& s, bool last, Rec* maps, const uint8_t* gt, int W, int H,
-                    const double* cf, float* flow, float* ntilde, double nmin, hipStream_t st) {
-#define COL(L, NC, NS)                                                              \
-  if (s.l == L && s.ncol == NC && s.nseg == NS)                                      \
-    return launch_col<L, NC, NS>(last, maps, gt, W, H, cf, flow, ntilde, nmin, st);
+                    const double* cf, float* flow, float* ntilde, double nmin,
+                    const uint8_t* rowflag, hipStream_t st) {
+#define COL(L, NC, NS)                                                                       \
+  if (s.l == L && s.ncol == NC && s.nseg == NS)                                               \
+    return launch_col<L, NC, NS>(last, maps, gt, W, H, cf, flow, ntilde, nmin, rowflag, st);
   COL(8, 8, 128) COL(8, 4, 128) COL(16, 4, 128) COL(8, 2, 256) COL(24, 4, 128)
   COL(16, 2, 256) COL(24, 2, 256)
 #undef COL
@@ -582,6 +620,7 @@ hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint
                        float* flow, float* ntilde, hipStream_t st, const DtShape* shape,
                        bool coef_ready, bool guide_t_ready) {
   Rec* maps = static_cast<Rec*>(maps_v);
+  uint8_t* rowflag = static_cast<uint8_t*>(maps_v) + dt_rowflag_offset(W, H);
   if (!guide_t_ready) {
     LNR_LAUNCH(k_guide_columns, dim3((W + 63) / 64, (H + 63) / 64), dim3(256), 0, st, guide, W, H,
                dt_guide_stride(H), guide_t);
@@ -597,9 +636,11 @@ hipError_t launch_flow(const int32_t* corner_xy, const int32_t* disp, const uint
   for (int i = 0; i < a.iters; ++i) {
     const double* cf = coef + 256 * i;
     const bool first = i == 0, last = i + 1 == a.iters;
-    e = row_pass(sh, first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile, st);
+    e = row_pass(sh, first, maps, guide, W, H, cf, corner_xy, disp, flags, ntx, nty, tile,
+                 rowflag, st);
     if (e != hipSuccess) return e;
-    e = col_pass(sh, last, maps, guide_t, W, H, cf, flow, ntilde, nmin, st);
+    e = col_pass(sh, last, maps, guide_t, W, H, cf, flow, ntilde, nmin,
+                 first ? rowflag : nullptr, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -58,24 +58,42 @@ __device__ inline long long q8(double s) {
   return (long long)q;
 }
 
-__device__ inline uint32_t warp_px(const uint8_t* __restrict__ src, int w, int h,
-                                   const double* hp, int x, int y) {
+// The Q8 sample of output pixel (x, y): the four clamped taps and the Q8
+// fractions.
+struct Q8Tap {
+  int x0, x1, y0, y1;
+  uint32_t fx, fy;
+};
+
+__device__ inline Q8Tap warp_tap(const double* hp, int w, int h, int x, int y) {
   const double X = (double)x, Y = (double)y;
   const double den = (hp[6] * X + hp[7] * Y) + hp[8];
   const double sx = ((hp[0] * X + hp[1] * Y) + hp[2]) / den;
   const double sy = ((hp[3] * X + hp[4] * Y) + hp[5]) / den;
   const long long QX = q8(sx), QY = q8(sy);
   const long long ix = QX >> 8, iy = QY >> 8;
-  const uint32_t fx = (uint32_t)(QX & 255), fy = (uint32_t)(QY & 255);
-  const int x0 = (int)(ix < 0 ? 0 : (ix > w - 1 ? w - 1 : ix));
-  const int x1 = (int)(ix + 1 < 0 ? 0 : (ix + 1 > w - 1 ? w - 1 : ix + 1));
-  const int y0 = (int)(iy < 0 ? 0 : (iy > h - 1 ? h - 1 : iy));
-  const int y1 = (int)(iy + 1 < 0 ? 0 : (iy + 1 > h - 1 ? h - 1 : iy + 1));
-  const uint32_t p00 = src[(size_t)y0 * w + x0], p10 = src[(size_t)y0 * w + x1];
-  const uint32_t p01 = src[(size_t)y1 * w + x0], p11 = src[(size_t)y1 * w + x1];
+  Q8Tap t;
+  t.fx = (uint32_t)(QX & 255);
+  t.fy = (uint32_t)(QY & 255);
+  t.x0 = (int)(ix < 0 ? 0 : (ix > w - 1 ? w - 1 : ix));
+  t.x1 = (int)(ix + 1 < 0 ? 0 : (ix + 1 > w - 1 ? w - 1 : ix + 1));
+  t.y0 = (int)(iy < 0 ? 0 : (iy > h - 1 ? h - 1 : iy));
+  t.y1 = (int)(iy + 1 < 0 ? 0 : (iy + 1 > h - 1 ? h - 1 : iy + 1));
+  return t;
+}
+
+__device__ inline uint32_t blend_q8(uint32_t p00, uint32_t p10, uint32_t p01, uint32_t p11,
+                                    uint32_t fx, uint32_t fy) {
   const uint32_t acc = (256 - fx) * (256 - fy) * p00 + fx * (256 - fy) * p10 +
                        (256 - fx) * fy * p01 + fx * fy * p11;
   return (acc + 32768u) >> 16;
+}
+
+__device__ inline uint32_t warp_px(const uint8_t* __restrict__ src, int w, int h,
+                                   const double* hp, int x, int y) {
+  const Q8Tap t = warp_tap(hp, w, h, x, y);
+  return blend_q8(src[(size_t)t.y0 * w + t.x0], src[(size_t)t.y0 * w + t.x1],
+                  src[(size_t)t.y1 * w + t.x0], src[(size_t)t.y1 * w + t.x1], t.fx, t.fy);
 }
 
 // Four consecutive pixels per thread, one 32-bit store when the row allows it.
@@ -179,17 +197,44 @@ __device__ inline void stage_rows(const uint8_t* __restrict__ img, int w, int h,
 // The window rows [y0, y0 + nrows) x bytes [x0, x0 + 4 * ndw) of the level
 // warped on the fly: each pixel inside the level is warp_px of the unwarped
 // source (the value k_warp_q8 stores there), 0 outside, as stage_rows reads
-// the stored warped level; every byte XOR flip.
+// the stored warped level; every byte XOR flip. Four pixels per thread at a
+// time: their sample positions first, then all sixteen taps in flight, then
+// the blends.
 __device__ inline void stage_warped(const uint8_t* __restrict__ src, int w, int h,
                                     const double* hp, int x0, int y0, int nrows, int ndw,
                                     uint8_t* dst, int ldst, int tid, int nt, uint32_t flip) {
+  constexpr int U = 4;
   const int total = nrows * ndw * 4;
-  for (int i = tid; i < total; i += nt) {
-    const int r = i / (4 * ndw), b = i % (4 * ndw);
-    const int gy = y0 + r, gx = x0 + b;
-    uint32_t v = 0;
-    if (gy >= 0 && gy < h && gx >= 0 && gx < w) v = warp_px(src, w, h, hp, gx, gy);
-    dst[r * ldst + b] = (uint8_t)(v ^ flip);
+  for (int i0 = tid; i0 < total; i0 += U * nt) {
+    Q8Tap t[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * nt;
+      const int r = i / (4 * ndw), b = i % (4 * ndw);
+      const int gy = y0 + r, gx = x0 + b;
+      in[u] = i < total && gy >= 0 && gy < h && gx >= 0 && gx < w;
+      t[u] = warp_tap(hp, w, h, in[u] ? gx : 0, in[u] ? gy : 0);
+    }
+    uint32_t p[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint8_t* r0 = src + (size_t)t[u].y0 * w;
+      const uint8_t* r1 = src + (size_t)t[u].y1 * w;
+      p[u][0] = r0[t[u].x0];
+      p[u][1] = r0[t[u].x1];
+      p[u][2] = r1[t[u].x0];
+      p[u][3] = r1[t[u].x1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * nt;
+      if (i >= total) break;
+      const int r = i / (4 * ndw), b = i % (4 * ndw);
+      const uint32_t v = in[u] ? blend_q8(p[u][0], p[u][1], p[u][2], p[u][3], t[u].fx, t[u].fy)
+                               : 0u;
+      dst[r * ldst + b] = (uint8_t)(v ^ flip);
+    }
   }
 }
 
@@ -435,35 +480,46 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   __syncthreads();
   // patch energy and window row energies rowsq[y][k] = sum_c win[y][k + c]^2,
   // from realigned dwords with v_dot4 (bytes past the patch width masked off)
+  // (summed over each wave first: one LDS atomic per wave)
   {
     uint32_t part = 0;
     for (int i = tid; i < PW * NW; i += nt)
       part = (uint32_t)__builtin_amdgcn_sdot4((int)S.refp[i], (int)S.refp[i], (int)part, false);
-    if (part) atomicAdd(&S.er_sum, part);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((tid & 63) == 0 && part) atomicAdd(&S.er_sum, part);
   }
-  // (one thread per window row: the first sum from dwords, then sliding by
-  // one pixel four candidates at a time, from the dword holding the pixels
-  // that leave and the realigned dword holding those that enter; exact in
-  // integers. The step is written as (b - a)(b + a): hipcc folds
-  // e + b*b - a*a on two bytes into one v_dot4_u32_u8 of the packed pair,
-  // which adds a*a instead of subtracting it.)
+  // (a thread per run of 8 candidates of a window row: the first sum from
+  // dwords, then sliding by one pixel four candidates at a time, from the
+  // dword holding the pixels that leave and the realigned dword holding those
+  // that enter; exact in integers. The step is written as (b - a)(b + a):
+  // hipcc folds e + b*b - a*a on two bytes into one v_dot4_u32_u8 of the
+  // packed pair, which adds a*a instead of subtracting it. A run's first
+  // dwords may reach a few bytes past the row: those bytes are masked off.)
   {
+    constexpr int CH = 8;
     const uint32_t* wdw = reinterpret_cast<const uint32_t*>(win);
     const int rowdw = sh.wrow >> 2;
-    for (int yy = tid; yy < sh.NR; yy += nt) {
+    const int nch = (sh.ncand + CH - 1) / CH;
+    for (int it = tid; it < sh.NR * nch; it += nt) {
+      const int yy = it / nch, c0 = (it - yy * nch) * CH;
       const uint32_t* rp = wdw + yy * rowdw;
       uint32_t e = 0;
 #pragma unroll
       for (int m = 0; m < NW; ++m) {
         const int nb = PW - 4 * m;
         const uint32_t mask = nb >= 4 ? 0xffffffffu : (nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u));
-        const int d = (int)(rp[m] & mask);
+        const int d = (int)(rp[(c0 >> 2) + m] & mask);
         e = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)e, false);
       }
       uint32_t* out = rowsq + yy * sh.ncand;
-      out[0] = e;
+      out[c0] = e;
+      const int cend = min(c0 + CH, sh.ncand);
       // candidate k + 1 = candidate k - pixel k + pixel k + PW
-      for (int k0 = 0; k0 + 1 < sh.ncand; k0 += 4) {
+#pragma unroll
+      for (int g = 0; g < CH / 4; ++g) {
+        const int k0 = c0 + 4 * g;
+        if (k0 + 1 >= cend) break;
         const uint32_t A = rp[k0 >> 2];
         const int bq = (k0 + PW) >> 2;
         const uint32_t B = __builtin_amdgcn_alignbyte(rp[bq + 1], rp[bq], (k0 + PW) & 3);
@@ -476,7 +532,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (k0 + q + 1 < sh.ncand) out[k0 + q + 1] = v[q];
+          if (k0 + q + 1 < cend) out[k0 + q + 1] = v[q];
       }
     }
   }

@@ -403,7 +403,7 @@ PairPlan plan_pair(int W, int H, const lnr_params* p) {
   q.o_psrc = pl.take(q.g.pyr_bytes);
   q.o_warp = pl.take(N);
   q.wp = plan_weed(pl, q.g.lv[0].ntx * q.g.lv[0].nty, p->weed_iters);
-  q.o_maps = pl.take(dt_maps_bytes(N));
+  q.o_maps = pl.take(dt_maps_bytes(W, H));
   q.o_gt = pl.take(dt_guide_t_bytes(W, H));
   q.o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   const size_t nt0 = (size_t)q.g.lv[0].ntx * q.g.lv[0].nty;
@@ -1083,9 +1083,8 @@ lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t*
       ntiles != (w / p->tile) * (h / p->tile) || (ntiles > 0 && (!corner_xy || !disp || !flags)))
     return fail(ctx, LNR_E_ARG, "bad flow arguments (ntiles must be the level-0 tile count)");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
-  const size_t N = (size_t)w * h;
   Plan pl;
-  const size_t o_maps = pl.take(dt_maps_bytes(N));
+  const size_t o_maps = pl.take(dt_maps_bytes(w, h));
   const size_t o_gt = pl.take(dt_guide_t_bytes(w, h));
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));
   if ((s = ensure_ws(ctx, pl.off, (hipStream_t)stream)) != LNR_OK) return s;
@@ -1587,7 +1586,7 @@ lnr_status lnr_autotune_flow(lnr_ctx* ctx, int32_t w, int32_t h, const lnr_param
   const size_t N = (size_t)w * h;
   const int ntx = w / p->tile, nty = h / p->tile, nt = ntx * nty;
   Plan pl;
-  const size_t o_g = pl.take(N), o_maps = pl.take(dt_maps_bytes(N));
+  const size_t o_g = pl.take(N), o_maps = pl.take(dt_maps_bytes(w, h));
   const size_t o_gt = pl.take(dt_guide_t_bytes(w, h));
   const size_t o_flow = pl.take(2 * N * sizeof(float)), o_nt = pl.take(N * sizeof(float));
   const size_t o_coef = pl.take((size_t)p->dt_iters * 256 * sizeof(double));

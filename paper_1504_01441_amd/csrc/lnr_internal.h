@@ -212,7 +212,14 @@ bool dt_shape_valid(const DtShape& s, int W, int H);
 int dt_shape_candidates(int W, int H, DtShape* out, int max);
 // The propagation's working maps: one 12-byte record per pixel (the three
 // maps), so that a column pass reads whole runs of neighbouring columns.
-inline size_t dt_maps_bytes(size_t npix) { return npix * 12; }
+// The propagation maps (12 bytes per pixel) and, 256-byte aligned after
+// them, one flag byte per row (padded so that 8-row loads stay inside).
+inline size_t dt_rowflag_offset(int W, int H) {
+  return ((size_t)W * H * 12 + 255) / 256 * 256;
+}
+inline size_t dt_maps_bytes(int W, int H) {
+  return dt_rowflag_offset(W, H) + ((size_t)H + 64 + 255) / 256 * 256;
+}
 // The column pass reads the guide column-major: column x at x * stride, the
 // rows padded to a multiple of 64 plus one more 64-row block (so that a
 // segment's aligned load never leaves the column).
