@@ -138,8 +138,10 @@ def algo_bytes_per_step(W, H, fmt_i420, n, ch, reg_sizes, blend_levels, launches
         base, flag = kernel_key(name)
         if base == "k_hist":            # read both frames' luma
             add(base, 2 * N)
-        elif base == "k_lut_pyr":       # read luma, write every pyramid level (both frames)
-            add(base, 2 * N + 2 * sum(reg_px))
+        elif base == "k_lut_pyr":       # read luma; write every pyramid level of both frames,
+            # level 0 again into the outputs (yeq_ref, yeq_src), and the
+            # reference's level 0 column-major for the propagation
+            add(base, 2 * N + 2 * sum(reg_px) + 2 * N + N)
         elif base == "k_dt_row":        # first pass: guide in, 3 maps out; else 3 maps in/out
             add(base, cnt * (13 * N if flag else 25 * N))
         elif base == "k_dt_col":        # 3 maps + guide in; 3 maps (last: F and N~) out

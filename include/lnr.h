@@ -252,6 +252,14 @@ lnr_status lnr_stage_flow(lnr_ctx* ctx, const int32_t* corner_xy, const int32_t*
 lnr_status lnr_stage_backward_warp(lnr_ctx* ctx, const lnr_frame* src, const uint8_t* yeq,
                                    const double* H, const float* flow, float* image,
                                    float* yeq_warped, void* stream);
+/* The merge's conversion of an unwarped frame (the reference, Sec. 2.5):
+ * image [channels][h][w] = BT.601 full-range RGB of f in [0, 1] (Y8: Y / 255;
+ * 4:2:0 chroma by pixel repetition), the same conversion the backward warp
+ * applies to its samples; with yeq (device, [h][w] 8-bit, may be null),
+ * yeq_out = yeq / 255. All pointers device; LNR_E_ARG on a bad frame or a
+ * null image (or yeq given without yeq_out). */
+lnr_status lnr_stage_frame_rgb(lnr_ctx* ctx, const lnr_frame* f, const uint8_t* yeq,
+                               float* image, float* yeq_out, void* stream);
 /* Deghosted merge (Sec. 2.5) of n float images [ch][h][w] in [0, 1] with
  * their equalised luma maps yeqs[k] ([h][w], in [0, 1]); frame ref_index
  * gets no SSIM weight. imgs and yeqs are device pointers held in host arrays. */

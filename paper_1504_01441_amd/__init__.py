@@ -121,6 +121,7 @@ def lib():
         L.lnr_stage_flow.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, C.POINTER(Params), vp,
                                      vp, vp]
         L.lnr_stage_backward_warp.argtypes = [vp, C.POINTER(_Frame), vp, vp, vp, vp, vp, vp]
+        L.lnr_stage_frame_rgb.argtypes = [vp, C.POINTER(_Frame), vp, vp, vp, vp]
         L.lnr_stage_merge.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, C.POINTER(Params),
                                       vp, vp]
         L.lnr_meter.argtypes = [vp, vp, i32, i32, i32, i32, C.c_float, C.c_float, vp, vp]
@@ -151,7 +152,7 @@ def lib():
                      "lnr_register_pair_noalloc", "lnr_merge",
                      "lnr_proposal_checkpoint_save", "lnr_proposal_checkpoint_load", "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
                      "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
-                     "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
+                     "lnr_stage_frame_rgb", "lnr_stage_merge", "lnr_stage_search_window", "lnr_proposal_set",
                      "lnr_proposal_get", "lnr_proposal_inputs", "lnr_proposal_forward",
                      "lnr_proposal_train_step", "lnr_register_batch", "lnr_autotune_flow",
                      "lnr_autotune_search", "lnr_proposal_save", "lnr_proposal_load",
@@ -166,7 +167,7 @@ EXPORTED = ("lnr_create", "lnr_destroy", "lnr_last_error", "lnr_default_params",
             "lnr_query_sizes", "lnr_register_pair", "lnr_register_stack", "lnr_merge",
             "lnr_stage_equalize", "lnr_stage_warp_q8", "lnr_stage_search",
             "lnr_stage_weed_fit", "lnr_stage_flow", "lnr_stage_backward_warp",
-            "lnr_stage_merge", "lnr_trace_enable", "lnr_trace_read",
+            "lnr_stage_frame_rgb", "lnr_stage_merge", "lnr_trace_enable", "lnr_trace_read",
             "lnr_stage_search_window", "lnr_proposal_set", "lnr_proposal_get",
             "lnr_proposal_inputs", "lnr_proposal_forward", "lnr_proposal_train_step",
             "lnr_register_batch", "lnr_autotune_flow", "lnr_autotune_search",
@@ -482,6 +483,19 @@ def stage_backward_warp(ctx, src: Frame, yeq: torch.Tensor, H: torch.Tensor,
                                             _ptr(flow.contiguous()), _ptr(img), _ptr(yw),
                                             _stream()))
     return img, yw
+
+
+def stage_frame_rgb(ctx, f: Frame, yeq: torch.Tensor = None):
+    """The merge's conversion of an unwarped frame: (image [ch][h][w],
+    yeq / 255 or None)."""
+    ch = 1 if f.fmt == LNR_Y8 else 3
+    dev = f.y.device
+    img = torch.empty(ch, f.height, f.width, dtype=torch.float32, device=dev)
+    yo = None if yeq is None else torch.empty(f.height, f.width, dtype=torch.float32, device=dev)
+    ff = f._c()
+    ctx.check(lib().lnr_stage_frame_rgb(ctx._h, C.byref(ff), _ptr(yeq), _ptr(img), _ptr(yo),
+                                        _stream()))
+    return img, yo
 
 
 def stage_merge(ctx, imgs, yeqs, ref_index, params=None):

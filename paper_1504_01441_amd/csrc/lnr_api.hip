@@ -1110,6 +1110,19 @@ lnr_status lnr_stage_backward_warp(lnr_ctx* ctx, const lnr_frame* src, const uin
   return LNR_OK;
 }
 
+lnr_status lnr_stage_frame_rgb(lnr_ctx* ctx, const lnr_frame* f, const uint8_t* yeq,
+                               float* image, float* yeq_out, void* stream) {
+  if (!ctx) return LNR_E_ARG;
+  TraceGuard tg(ctx);
+  lnr_status s;
+  if ((s = check_frame(ctx, f, "frame")) != LNR_OK) return s;
+  if (!image || (yeq && !yeq_out)) return fail(ctx, LNR_E_ARG, "bad frame conversion arguments");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, LNR_E_HIP, "hipSetDevice");
+  LNR_HIP(launch_frame_rgb_unit(f->plane[0], f->stride[0], chroma_of(*f), f->width, f->height,
+                                image, yeq, yeq_out, (hipStream_t)stream));
+  return LNR_OK;
+}
+
 lnr_status lnr_stage_merge(lnr_ctx* ctx, int32_t n, int32_t ch, int32_t w, int32_t h,
                            const float* const* imgs, const float* const* yeqs, int32_t ref_index,
                            const lnr_params* p, float* out, void* stream) {

@@ -79,6 +79,11 @@ def registration_parity(reg, o, flow_mask_nmin=1e-30, warped0=True):
     flow = reg.flow.cpu().numpy()
     assert_close(flow[0], o["flow_u"], 1.0, mask=mask, what="flow u")
     assert_close(flow[1], o["flow_v"], 1.0, mask=mask, what="flow v")
-    assert_close(reg.ntilde.cpu().numpy(), nt, 0.0, rel=1e-3, mask=nt > 1e-20, what="N~")
+    # N~ as every FP32 plane (1e-4 of |N~| + 1), and besides that relative to
+    # its own size down to 1e-20 (the float storage between the recursive
+    # passes keeps about 1e-4 of that)
+    ntg = reg.ntilde.cpu().numpy()
+    assert_close(ntg, nt, 1.0, what="N~")
+    assert_close(ntg, nt, 0.0, rel=1e-3, mask=nt > 1e-20, what="N~ (relative)")
     assert_close(reg.image.cpu().numpy(), o["rgb"], 1.0, what="warped image")
     assert_close(reg.yeq_warped.cpu().numpy(), o["yeq_warped"], 1.0, what="warped Y_eq")

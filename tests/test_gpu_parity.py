@@ -609,3 +609,37 @@ def test_register_rejects_bad_arguments(ctx):
     with pytest.raises(lnr().LnrError) as e:
         lnr().register_pair(ctx, wide, wide, lnr().Params(radius0=8))
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("fmt,w,h", [("i420", 2592, 1944), ("i420", 330, 250), ("y8", 331, 251),
+                                     ("nv12", 642, 482)])
+def test_frame_rgb_vs_oracle(ctx, fmt, w, h):
+    """The merge's conversion of the unwarped reference (k_frame_rgb4, four
+    pixels per thread with a scalar tail) against the oracle's BT.601
+    conversion, and yeq / 255, including ragged widths and a padded NV12
+    chroma row."""
+    L = lnr()
+    rng = np.random.default_rng(w + h)
+    y = rng.integers(0, 256, (h, w), np.uint8)
+    yeq = rng.integers(0, 256, (h, w), np.uint8)
+    if fmt == "y8":
+        f = L.Frame.from_numpy(y)
+        want = oracle.frame_to_rgb(y)
+    else:
+        u = rng.integers(0, 256, (h // 2, w // 2), np.uint8)
+        v = rng.integers(0, 256, (h // 2, w // 2), np.uint8)
+        want = oracle.frame_to_rgb(y, u, v)
+        if fmt == "i420":
+            f = L.Frame.from_numpy(y, u, v)
+        else:
+            uv = torch.zeros(h // 2, w + 64, dtype=torch.uint8)
+            uv[:, 0:w:2] = torch.from_numpy(u)
+            uv[:, 1:w:2] = torch.from_numpy(v)
+            f = L.Frame.nv12_from_numpy(y, np.zeros((1, 1), np.uint8))
+            f.u = uv.cuda()[:, :w]
+    print(f"frame_rgb {fmt} {w}x{h}", flush=True)
+    img, yo = L.stage_frame_rgb(ctx, f, _t(yeq))
+    _sync()
+    assert img.shape == want.shape
+    assert_close(img.cpu().numpy(), want, 1.0, what=f"{fmt} rgb")
+    assert_close(yo.cpu().numpy(), yeq / 255.0, 1.0, what="yeq / 255")

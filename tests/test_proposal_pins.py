@@ -140,6 +140,82 @@ def test_forward_rounded_close_to_exact():
     assert not np.array_equal(a, b)
 
 
+def _rd(t):
+    """bf16 round to nearest even (torch's cast, pinned above), kept in float64"""
+    return t.float().to(torch.bfloat16).double()
+
+
+def _torch_rounded(P, x, lab):
+    """The rounded network written independently with torch's float64
+    convolution primitives: weights and post-ReLU activations rounded to
+    bf16, biases and the fp32 head unrounded; backward through the ReLUs with
+    the gradient rounded where the kernels consume it (dz), then the weight,
+    bias and input gradients of each convolution. Returns outputs and the
+    flat gradient (same layout as the oracle)."""
+    import torch.nn.grad as G
+    import torch.nn.functional as F
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64))  # noqa: E731
+    n = x.shape[0]
+    Ws = [_rd(t(_tensor(P, f"W{l}"))) for l in range(1, 5)]
+    bs = [t(_tensor(P, f"b{l}")) for l in range(1, 5)]
+    Wh, bh = t(_tensor(P, "Wh")), t(_tensor(P, "bh"))
+    strides = (1, 2, 1, 2)
+    acts = [t(x)]
+    for l in range(4):
+        z = F.conv2d(acts[-1], Ws[l], bs[l], stride=strides[l], padding=1)
+        acts.append(_rd(torch.clamp(z, min=0.0)))
+    feat = acts[4].permute(0, 2, 3, 1).reshape(n, -1)  # f = (y * 4 + x) * 32 + c
+    o = feat @ Wh.T + bh
+    labt = t(lab.astype(np.float64))
+    ex, ey = 8 * o[:, 0] - labt[:, 0], 8 * o[:, 1] - labt[:, 1]
+    q = 1 / (1 + torch.exp(-4 * (2.5 - torch.maximum(ex.abs(), ey.abs()))))
+    dO = torch.stack([8 * ex.clamp(-1, 1), 8 * ey.clamp(-1, 1), torch.sigmoid(o[:, 2]) - q],
+                     1) / n
+    grads = {"Wh": dO.T @ feat, "bh": dO.sum(0)}
+    da = (dO @ Wh).reshape(n, 4, 4, 32).permute(0, 3, 1, 2)
+    for l in range(3, -1, -1):
+        dz = _rd(torch.where(acts[l + 1] > 0, da, torch.zeros_like(da)))
+        grads[f"W{l + 1}"] = G.conv2d_weight(acts[l], Ws[l].shape, dz, stride=strides[l],
+                                             padding=1)
+        grads[f"b{l + 1}"] = dz.sum((0, 2, 3))
+        if l:
+            da = G.conv2d_input(acts[l].shape, Ws[l], dz, stride=strides[l], padding=1)
+    g = np.zeros(NP)
+    for name, (off, shp) in _layout().items():
+        g[off:off + int(np.prod(shp))] = grads[name].numpy().reshape(-1)
+    return o.numpy(), g
+
+
+def test_forward_rounded_matches_torch():
+    """The bf16-rounded forward pass against the independent torch version:
+    the two sum in different orders (about 1e-16 apart before each rounding),
+    so they agree to 1e-12 unless a sum falls on a bf16 rounding boundary."""
+    P = _params(17)
+    rng = np.random.default_rng(18)
+    x = oracle.bf16(rng.uniform(-1, 1, (6, oracle.CNN_IN, 16, 16)))
+    lab = rng.integers(-8, 9, (6, 2)).astype(np.int32)
+    got = oracle.cnn_forward(P, x, rnd=True)
+    want, _ = _torch_rounded(P, x, lab)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12)
+    # the rounding matters: the exact network differs by far more
+    assert np.abs(oracle.cnn_forward(P, x, rnd=False) - want).max() > 1e-4
+
+
+@pytest.mark.parametrize("seed", [19, 20])
+def test_gradient_rounded_matches_torch(seed):
+    """The bf16-rounded loss gradient (every parameter) against the
+    independent torch version, to 1e-9 of the gradient's largest entry."""
+    P = _params(seed)
+    rng = np.random.default_rng(seed + 50)
+    x = oracle.bf16(rng.uniform(-1, 1, (4, oracle.CNN_IN, 16, 16)))
+    lab = rng.integers(-8, 9, (4, 2)).astype(np.int32)
+    _, got = oracle.cnn_loss_grad(P, x, lab, rnd=True)
+    _, want = _torch_rounded(P, x, lab)
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+    _, exact = oracle.cnn_loss_grad(P, x, lab, rnd=False)
+    assert np.abs(exact - want).max() > 1e-6 * np.abs(want).max()
+
+
 def _frozen_loss(P, x, lab, q0):
     o = oracle.cnn_forward(P, x, rnd=False)
     ex, ey = 8 * o[:, 0] - lab[:, 0], 8 * o[:, 1] - lab[:, 1]
