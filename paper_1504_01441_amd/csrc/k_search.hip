@@ -421,7 +421,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
         J.corner_xy[2 * tile] = px;
         J.corner_xy[2 * tile + 1] = py;
         J.flags[tile] = 1;
-        list[atomicAdd(count, 1)] = gidx;
+        if (list) list[atomicAdd(count, 1)] = gidx;
       }
       return;
     }
@@ -763,6 +763,67 @@ __global__ __launch_bounds__(1024) void k_search_work(SearchJob one,
                   wk.out_list, wk.out_count, dyn, S);
 }
 
+// Ordered lists of one level's tiles from their flags, by one workgroup (a
+// per-tile append to a shared counter serialises: about 12 ns per tile).
+// Without `mode`: lists[0, n) = the cornered tiles (flag bit 0), counts[0].
+// With `mode`: lists[n, 2n) = the cornered tiles of mode 0 (window search),
+// lists[2n, 3n) = those of any other mode (exhaustive fallback), counts[1]
+// and counts[2]. Tiles appear in ascending order. Thread i owns a run of
+// consecutive tiles; the runs' counts are scanned within each wave, then
+// over the waves. (Runs loaded at once as membership bits, or rounds of
+// 1024 tiles ranked by ballots, measured slower: the kernel's few loads per
+// thread are not its cost.)
+__global__ __launch_bounds__(1024) void k_tile_lists(const uint8_t* __restrict__ flags,
+                                                     const uint8_t* __restrict__ mode, int n,
+                                                     int* __restrict__ lists,
+                                                     int* __restrict__ counts) {
+  __shared__ int wsum[2][16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int per = (n + 1023) / 1024;
+  const int t0 = min(tid * per, n), t1 = min(t0 + per, n);
+  auto in_a = [&](int t) { return (flags[t] & 1) && (!mode || mode[t] == 0); };
+  auto in_b = [&](int t) { return (flags[t] & 1) && mode && mode[t] != 0; };
+  int c0 = 0, c1 = 0;
+  for (int t = t0; t < t1; ++t) {
+    c0 += in_a(t);
+    c1 += in_b(t);
+  }
+  int s0 = c0, s1 = c1;  // inclusive scans over the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u0 = __shfl_up(s0, o), u1 = __shfl_up(s1, o);
+    if (lane >= o) {
+      s0 += u0;
+      s1 += u1;
+    }
+  }
+  if (lane == 63) {
+    wsum[0][wv] = s0;
+    wsum[1][wv] = s1;
+  }
+  __syncthreads();
+  int b0 = 0, b1 = 0;
+  for (int w = 0; w < wv; ++w) {
+    b0 += wsum[0][w];
+    b1 += wsum[1][w];
+  }
+  int p0 = b0 + s0 - c0, p1 = b1 + s1 - c1;  // this run's first entries
+  int* la = mode ? lists + n : lists;
+  int* lb = lists + 2 * n;
+  for (int t = t0; t < t1; ++t) {
+    if (in_a(t)) la[p0++] = t;
+    else if (in_b(t)) lb[p1++] = t;
+  }
+  if (tid == 1023) {  // the last run ends both lists
+    if (mode) {
+      counts[1] = b0 + s0;
+      counts[2] = b1 + s1;
+    } else {
+      counts[0] = b0 + s0;
+    }
+  }
+}
+
 // A random 8-bit texture (every tile has corners): the search autotuner's input.
 __global__ __launch_bounds__(256) void k_texture(uint8_t* __restrict__ p, int n, uint32_t seed) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -913,6 +974,12 @@ int search_split_candidates(int R, const SearchCfg& c, int* out, int max) {
     for (int s = 1; s <= 7 && n < max; ++s)
       if (search_shape_fits(R, c, s | code)) out[n++] = s | code;
   return n;
+}
+
+hipError_t launch_tile_lists(const uint8_t* flags, const uint8_t* mode, int n, int* lists,
+                             int* counts, hipStream_t st) {
+  LNR_LAUNCH(k_tile_lists, dim3(1), dim3(1024), 0, st, flags, mode, n, lists, counts);
+  return hipGetLastError();
 }
 
 hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st) {

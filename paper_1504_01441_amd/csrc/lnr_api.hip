@@ -580,18 +580,18 @@ lnr_status enqueue_pair_levels(lnr_ctx* ctx, const lnr_frame* ref, const lnr_fra
       const float logit = p->conf_min <= 0.0 ? -INFINITY
                           : p->conf_min >= 1.0 ? NAN
                           : (float)std::log(p->conf_min / (1.0 - p->conf_min));
+      // (the lists are built from the flags and modes by one workgroup each)
       SearchWork wk{};
       wk.njobs = 1;
       wk.ntotal = nt;
-      wk.out_list = lists;
-      wk.out_count = counts;
       const SearchJob Jc = search_job(pref, warped, L.w, L.h, L.ntx, out->corner_xy, out->disp,
                                       out->ssd, out->flags, nullptr, wb.vb);
       LNR_HIP(launch_search_work(nullptr, wk, R, cfg, kVisitCornersOnly, 0, 0, 8, nt, st, &Jc));
+      LNR_HIP(launch_tile_lists(out->flags, nullptr, nt, lists, counts, st));
       LNR_HIP(launch_cnn_input(pref, warped, W, L.h, L.ntx, L.nty, lists, counts, x, st));
       LNR_HIP(launch_cnn_forward(ctx->cnn_packed, ctx->cnn, x, nt, nullptr, nullptr, centre, mode,
-                                 p->radius0 - p->window_r, logit, st, lists, counts, lists + nt,
-                                 counts + 1));
+                                 p->radius0 - p->window_r, logit, st, lists, counts));
+      LNR_HIP(launch_tile_lists(out->flags, mode, nt, lists, counts, st));
       SearchWork ww{};
       ww.njobs = 1;
       ww.list = lists + nt;

@@ -304,6 +304,11 @@ hipError_t launch_cnn_pack(const float* params, uint16_t* packed, hipStream_t st
 hipError_t launch_cnn_input(const uint8_t* ref, const uint8_t* warped, int w, int h, int ntx,
                             int nty, const int32_t* tiles, const int* count, uint16_t* x,
                             hipStream_t st);
+// the cornered tiles of flags[0, n) in order (lists[0 ..], counts[0]), or
+// with `mode` those of mode 0 (lists[n ..], counts[1]) and the others
+// (lists[2n ..], counts[2])
+hipError_t launch_tile_lists(const uint8_t* flags, const uint8_t* mode, int n, int* lists,
+                             int* counts, hipStream_t st);
 // inference (centre != null) or training forward of n samples; with `count`
 // (device) only the first *count samples (n is then the most there can be),
 // sample s being tile tiles[s]; with `lists`, each tile is appended to the
