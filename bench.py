@@ -337,7 +337,7 @@ def main():
         rooflines["k_search"] = {
             "kernel": "k_search", "bound": "alu", "achieved": round(ach, 2),
             "peak": round(DOT4_PEAK_TPS, 2), "unit": "T pixel-candidate products/s (v_dot4)",
-            "frac": round(ach / DOT4_PEAK_TPS, 4), "traffic": None,
+            "frac": round(ach / DOT4_PEAK_TPS, 4), "traffic": measured_traffic("k_search"),
             "avg_launch_us": round(ms / cnt * 1e3, 2),
             "products_per_launch": int(sum(prods) / cnt), "ms_per_step": round(ms, 4),
             "launches_per_step": round(cnt, 2), "products_per_level": prods}
