@@ -316,7 +316,7 @@ struct MapPtrs {
   float* out[kMaxMaps];
 };
 
-constexpr int kRedTW = 64, kRedTH = 8;
+constexpr int kRedTW = 128, kRedTH = 8;
 
 __global__ __launch_bounds__(256) void k_reduce(MapPtrs m, int w, int h, int w2, int h2) {
   __shared__ float src[2 * kRedTH + 3][2 * kRedTW + 3];
