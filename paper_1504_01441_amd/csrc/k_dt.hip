@@ -138,8 +138,6 @@ __device__ inline double coef_at(const double* cf, int gprev, int gcur) {
   return cf[abs(gcur - gprev)];
 }
 
-constexpr int kStageU = 4;
-
 // ---------------------------------------------------------------------------
 // Horizontal pass: one block per row; the row is staged in LDS (coalesced),
 // each thread keeps a segment of SEG consecutive pixels in registers.
@@ -152,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_dt_row(Rec* __restrict__ maps,
                                                 const uint8_t* __restrict__ flags, int ntx,
                                                 int nty, int tile,
                                                 uint8_t* __restrict__ rowflag) {
-  extern __shared__ float sm[];
+  extern __shared__ __align__(16) float sm[];
   __shared__ double cf[256];
   __shared__ Aff wtot[NT / 64];
   float* v0 = sm;
@@ -175,21 +173,21 @@ __global__ __launch_bounds__(NT) void k_dt_row(Rec* __restrict__ maps,
     if (!has) return;  // all zeros: the column pass does not read this row
   }
   if (tid < 256) cf[tid] = coef[tid];
-  // staging: several loads in flight per thread (batches of kStageU per
-  // thread, issued before the LDS stores)
-  for (int x0 = 0; x0 < W; x0 += kStageU * NT) {
-    uint8_t tg[kStageU];
-    Rec t[kStageU];
+  // staging: the whole row's loads in flight at once (NT * SEG covers the
+  // row, so SEG per thread), then the stores to workgroup memory
+  {
+    uint8_t tg[SEG];
+    Rec t[SEG];
 #pragma unroll
-    for (int u = 0; u < kStageU; ++u) {
-      const int xc = min(x0 + u * NT + tid, W - 1);  // in bounds; stored only if x < W
+    for (int u = 0; u < SEG; ++u) {
+      const int xc = min(u * NT + tid, W - 1);  // in bounds; stored only if x < W
       tg[u] = guide[ro + xc];
       if (FIRST) t[u] = Rec{0.f, 0.f, 0.f};
       else t[u] = maps[ro + xc];
     }
 #pragma unroll
-    for (int u = 0; u < kStageU; ++u) {
-      const int x = x0 + u * NT + tid;
+    for (int u = 0; u < SEG; ++u) {
+      const int x = u * NT + tid;
       if (x >= W) break;
       g[x] = tg[u];
       v0[x] = t[u].m0;
@@ -214,21 +212,43 @@ __global__ __launch_bounds__(NT) void k_dt_row(Rec* __restrict__ maps,
   __syncthreads();
   const int xb = tid * SEG;
   // the segment is held as float (as stored between passes); every recursion
-  // step and carry is computed in double precision
+  // step and carry is computed in double precision. A whole segment is read
+  // with 16-byte accesses where the planes allow (W a multiple of 4): a
+  // thread's elements lie SEG apart from its neighbours', which scalar reads
+  // would serve four to a bank.
   float a0[SEG], a1[SEG], a2[SEG];
-  double cc[SEG + 1];  // cc[j]: between xb+j-1 and xb+j
-  int gp = xb > 0 && xb - 1 < W ? g[xb - 1] : 0;
+  int gs[SEG + 2];  // guide bytes of pixels xb - 1 .. xb + SEG, 0 outside the row
+  const bool vec = SEG % 4 == 0 && (W & 3) == 0 && xb + SEG <= W;
+  if (vec) {
 #pragma unroll
-  for (int j = 0; j <= SEG; ++j) {
-    const int x = xb + j;
-    const int gc = x < W ? g[x] : 0;
-    cc[j] = (x > 0 && x < W) ? coef_at(cf, gp, gc) : 0.0;
-    gp = gc;
-    if (j < SEG) {
+    for (int q = 0; q < SEG / 4; ++q) {
+      const float4 f0 = reinterpret_cast<const float4*>(v0 + xb)[q];
+      const float4 f1 = reinterpret_cast<const float4*>(v1 + xb)[q];
+      const float4 f2 = reinterpret_cast<const float4*>(v2 + xb)[q];
+      a0[4 * q] = f0.x; a0[4 * q + 1] = f0.y; a0[4 * q + 2] = f0.z; a0[4 * q + 3] = f0.w;
+      a1[4 * q] = f1.x; a1[4 * q + 1] = f1.y; a1[4 * q + 2] = f1.z; a1[4 * q + 3] = f1.w;
+      a2[4 * q] = f2.x; a2[4 * q + 1] = f2.y; a2[4 * q + 2] = f2.z; a2[4 * q + 3] = f2.w;
+      const uint32_t w4 = reinterpret_cast<const uint32_t*>(g + xb)[q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) gs[1 + 4 * q + k] = (int)((w4 >> (8 * k)) & 255u);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const int x = xb + j;
       a0[j] = x < W ? v0[x] : 0.f;
       a1[j] = x < W ? v1[x] : 0.f;
       a2[j] = x < W ? v2[x] : 0.f;
+      gs[1 + j] = x < W ? g[x] : 0;
     }
+  }
+  gs[0] = xb > 0 && xb - 1 < W ? g[xb - 1] : 0;
+  gs[SEG + 1] = xb + SEG < W ? g[xb + SEG] : 0;
+  double cc[SEG + 1];  // cc[j]: between xb+j-1 and xb+j
+#pragma unroll
+  for (int j = 0; j <= SEG; ++j) {
+    const int x = xb + j;
+    cc[j] = (x > 0 && x < W) ? coef_at(cf, gs[j], gs[j + 1]) : 0.0;
   }
   // causal: J[x] = J[x] + c (J[x-1] - J[x])
   {
@@ -280,10 +300,22 @@ __global__ __launch_bounds__(NT) void k_dt_row(Rec* __restrict__ maps,
       p2 = u2 + c * (p2 - u2); a2[j] = (float)p2;
     }
   }
+  if (vec) {
 #pragma unroll
-  for (int j = 0; j < SEG; ++j) {
-    const int x = xb + j;
-    if (x < W) { v0[x] = a0[j]; v1[x] = a1[j]; v2[x] = a2[j]; }
+    for (int q = 0; q < SEG / 4; ++q) {
+      reinterpret_cast<float4*>(v0 + xb)[q] =
+          make_float4(a0[4 * q], a0[4 * q + 1], a0[4 * q + 2], a0[4 * q + 3]);
+      reinterpret_cast<float4*>(v1 + xb)[q] =
+          make_float4(a1[4 * q], a1[4 * q + 1], a1[4 * q + 2], a1[4 * q + 3]);
+      reinterpret_cast<float4*>(v2 + xb)[q] =
+          make_float4(a2[4 * q], a2[4 * q + 1], a2[4 * q + 2], a2[4 * q + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const int x = xb + j;
+      if (x < W) { v0[x] = a0[j]; v1[x] = a1[j]; v2[x] = a2[j]; }
+    }
   }
   __syncthreads();
 #pragma unroll 4
