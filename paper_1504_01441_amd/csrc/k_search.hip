@@ -308,6 +308,20 @@ __device__ inline void cross_mfma(const uint8_t* ar, const uint32_t* pr0, int LB
   }
 }
 
+// Dword dw of patch row `row` packed from the staged region (pixel - 128 as
+// a signed byte; 0 past the patch width PW): the patch's first pixel is at
+// region row r0, column c0.
+__device__ inline uint32_t patch_dword(const uint8_t* reg, int rs, int r0, int c0, int PW,
+                                       int row, int dw) {
+  const uint8_t* p = reg + (r0 + row) * rs + c0;
+  uint32_t v = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int col = dw * 4 + k;
+    if (col < PW) v |= (uint32_t)(p[col] ^ 0x80u) << (8 * k);
+  }
+  return v;
+}
+
 // One tile of one job, by the whole workgroup (every branch below that
 // skips the rest of the tile is uniform over the workgroup).
 //  list / count (kVisitCornersOnly): the cornered tile's global index gidx is
@@ -325,6 +339,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   const int ext = c.K * c.g + (c.r > c.P ? c.r : c.P);
   const int cx0 = tx * c.S + c.S / 2, cy0 = ty * c.S + c.S / 2;
   int px, py;  // corner, level coordinates
+  int pr0 = 0, pc0 = 0;  // the patch's first row and column in the staged region
 
   if (visit == kVisitKnownCorner) {
     px = J.corner_xy[2 * tile];
@@ -334,15 +349,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
     const int P = c.P, PW = 2 * P + 1;
     stage_rows(J.ref, w, h, px - P, py - P, PW, (PW + 3) / 4, reg, sh.rs, tid, nt);
     __syncthreads();
-    for (int i = tid; i < PW * NW; i += nt) {
-      const int row = i / NW, dw = i % NW;
-      uint32_t v = 0;
-      for (int k = 0; k < 4; ++k) {
-        const int col = dw * 4 + k;
-        if (col < PW) v |= (uint32_t)(reg[row * sh.rs + col] ^ 0x80u) << (8 * k);
-      }
-      S.refp[i] = v;
-    }
+    for (int i = tid; i < PW * NW; i += nt) S.refp[i] = patch_dword(reg, sh.rs, 0, 0, PW, i / NW, i % NW);
   } else {
     // 1. corners (Eq. 1-2) --------------------------------------------------
     // the region lies inside the tile; dword-aligned loads realigned in registers
@@ -429,16 +436,10 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
     // packed reference patch, centred (pixel - 128 as a signed byte; 0 past
     // the patch width)
     const int P = c.P, PW = 2 * P + 1;
-    for (int i = tid; i < PW * NW; i += nt) {
-      const int row = i / NW, dw = i % NW;
-      uint32_t v = 0;
-      for (int k = 0; k < 4; ++k) {
-        const int col = dw * 4 + k;
-        if (col < PW)
-          v |= (uint32_t)(reg[(pry - P + row) * sh.rs + prx - P + col] ^ 0x80u) << (8 * k);
-      }
-      S.refp[i] = v;
-    }
+    pr0 = pry - P;
+    pc0 = prx - P;
+    for (int i = tid; i < PW * NW; i += nt)
+      S.refp[i] = patch_dword(reg, sh.rs, pr0, pc0, PW, i / NW, i % NW);
   }
   if (J.Hlit) {  // every thread predicts the corner's source position itself
     double hp[9];
@@ -469,12 +470,14 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   }
   if constexpr (KX == 0) {
     // the patch rows with zero padding for the matrix-core operands:
-    // dword d of row i holds patch dword d - padB / 4 (0 outside the patch)
+    // dword d of row i holds patch dword d - padB / 4 (0 outside the patch),
+    // packed again from the staged region (the packed patch written above by
+    // other waves is not read before the next barrier)
     uint32_t* pb = reinterpret_cast<uint32_t*>(dyn + sh.off_pb);
     const int d0 = sh.padB >> 2;
     for (int q = tid; q < PW * sh.LB; q += nt) {
       const int i = q / sh.LB, d = q - i * sh.LB - d0;
-      pb[q] = (d >= 0 && d < NW) ? S.refp[i * NW + d] : 0u;
+      pb[q] = (d >= 0 && d < NW) ? patch_dword(reg, sh.rs, pr0, pc0, PW, i, d) : 0u;
     }
   }
   __syncthreads();
