@@ -6,8 +6,10 @@
 // blended with integer Q16 weights, so the result is exact integers.
 //
 // k_search<KX, ROLE>: one workgroup per full tile of one pair's level (ROLE
-// only names the launch for profiles: coarse levels, level 0, stage calls and
-// autotuner trials). k_search_work<KX, VISIT>: one workgroup per item of a
+// names the launch for profiles: coarse levels, level 0, stage calls and
+// autotuner trials; only the coarse-level kernel carries the on-the-fly warp
+// of the window, whose registers would cost the others occupancy).
+// k_search_work<KX, VISIT, WARP>: one workgroup per item of a
 // work list: the tiles of several pairs' levels (a SearchJob table; batches),
 // or a device list of tile indices (the learned proposal's window and
 // fallback tiles); VISIT kVisitCornersOnly runs the corner phase alone and
@@ -326,7 +328,7 @@ __device__ inline uint32_t patch_dword(const uint8_t* reg, int rs, int r0, int c
 // skips the rest of the tile is uniform over the workgroup).
 //  list / count (kVisitCornersOnly): the cornered tile's global index gidx is
 //  appended to list.
-template <int KX>
+template <int KX, bool WARP, int MB>
 __device__ void search_tile(const SearchJob& J, int tile, int gidx, const SearchCfg& c,
                             const SearchShape& sh, int visit, int want, int* list, int* count,
                             uint8_t* dyn, TileShared& S) {
@@ -461,7 +463,8 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   uint8_t* win = dyn + sh.off_win;
   uint32_t* rowsq = reinterpret_cast<uint32_t*>(dyn + sh.off_rowsq);
   const int wx0 = px + cdx - P - R, wy0 = py + cdy - P - R;
-  if (J.Hwarp) {
+  // (without WARP the job has no Hwarp: the launchers check it)
+  if (WARP && J.Hwarp) {
     double hp[9];
     pixel_homography(J.Hwarp, w, h, hp);
     stage_warped(J.wimg, w, h, hp, wx0, wy0, sh.NR, sh.stage_dw, win, sh.wrow, tid, nt, 0x80u);
@@ -599,9 +602,9 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
     const int nb = wv % sh.NB, sp = wv / sh.NB;
     const int r16 = lane & 15, cg = lane >> 4;
     const uint32_t* pb = reinterpret_cast<const uint32_t*>(dyn + sh.off_pb);
-    v4i acc[kMaxNB];
+    v4i acc[MB];
 #pragma unroll
-    for (int mb = 0; mb < kMaxNB; ++mb) acc[mb] = v4i{0, 0, 0, 0};
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = v4i{0, 0, 0, 0};
     const int i0 = sp * PW / sh.split, i1 = (sp + 1) * PW / sh.split;
     for (int kc = 0; kc < sh.KC; ++kc) {
       // B bytes: patch row i at columns x - dx, x = 64 kc + 16 g + 0..15,
@@ -609,18 +612,23 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       const int qb = 64 * kc + 16 * cg - (16 * nb + r16) + sh.padB;
       const uint8_t* ar = win + r16 * sh.wrow + 64 * kc + 16 * cg;
       const uint32_t* pr0 = pb + (qb >> 2);
-      switch (sh.NB) {
-        case 1: cross_mfma<1>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-        case 2: cross_mfma<2>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-        case 3: cross_mfma<3>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-        case 4: cross_mfma<4>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-        default: cross_mfma<5>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+      if constexpr (MB <= 3) {
+        switch (sh.NB) {
+          case 1: cross_mfma<1>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+          case 2: cross_mfma<2>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+          default: cross_mfma<3>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        }
+      } else {
+        switch (sh.NB) {
+          case 4: cross_mfma<4>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+          default: cross_mfma<5>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        }
       }
     }
     const int dxi = 16 * nb + r16;
     if (sh.split > 1) {  // exact integer partial sums: any order gives the same totals
 #pragma unroll
-      for (int mb = 0; mb < kMaxNB; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int j = 16 * mb + 4 * cg + t;
@@ -631,7 +639,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
     }
     if (sp == 0 && dxi < sh.ncand) {
 #pragma unroll
-      for (int mb = 0; mb < kMaxNB; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int j = 16 * mb + 4 * cg + t;
@@ -721,7 +729,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
 }
 
 // One workgroup per tile of one job. ROLE names the launch only.
-template <int KX, int ROLE>
+template <int KX, int ROLE, int MB>
 __global__ __launch_bounds__(1024) void k_search(SearchJob J, SearchCfg c, SearchShape sh,
                                                  const uint8_t* __restrict__ mode, int want) {
   extern __shared__ __align__(16) uint8_t dyn[];
@@ -729,7 +737,8 @@ __global__ __launch_bounds__(1024) void k_search(SearchJob J, SearchCfg c, Searc
   const int tile = blockIdx.x;
   // with a proposal, each tile is searched by the launch of its mode only
   if (mode && mode[tile] != want) return;
-  search_tile<KX>(J, tile, tile, c, sh, kVisitSearchAll, mode ? want : 0, nullptr, nullptr, dyn,
+  search_tile<KX, ROLE == kRoleCoarse, MB>(J, tile, tile, c, sh, kVisitSearchAll, mode ? want : 0,
+                                       nullptr, nullptr, dyn,
                   S);
 }
 
@@ -739,7 +748,7 @@ __global__ __launch_bounds__(1024) void k_search(SearchJob J, SearchCfg c, Searc
 // one whose first tile is <= the global tile. (Persistent workgroups looping
 // over the items, fetched by an atomic counter, were measured slower on the
 // 5 MP pair's level 0: 96 us against 82 us.)
-template <int KX, int VISIT>
+template <int KX, int VISIT, bool WARP, int MB>
 __global__ __launch_bounds__(1024) void k_search_work(SearchJob one,
                                                       const SearchJob* __restrict__ jobs,
                                                       SearchWork wk, SearchCfg c,
@@ -752,7 +761,7 @@ __global__ __launch_bounds__(1024) void k_search_work(SearchJob one,
   // uniform over the workgroup: kept in scalar registers
   const int g = __builtin_amdgcn_readfirstlane(wk.list ? wk.list[i] : i);
   if (!jobs) {  // one job, given by value
-    search_tile<KX>(one, g, g, c, sh, VISIT, want, wk.out_list, wk.out_count, dyn, S);
+    search_tile<KX, WARP, MB>(one, g, g, c, sh, VISIT, want, wk.out_list, wk.out_count, dyn, S);
     return;
   }
   int lo = 0, hi = wk.njobs - 1;
@@ -762,7 +771,8 @@ __global__ __launch_bounds__(1024) void k_search_work(SearchJob one,
     else hi = mid - 1;
   }
   const SearchJob J = jobs[lo];
-  search_tile<KX>(J, g - __builtin_amdgcn_readfirstlane(wk.first[lo]), g, c, sh, VISIT, want,
+  search_tile<KX, WARP, MB>(J, g - __builtin_amdgcn_readfirstlane(wk.first[lo]), g, c, sh, VISIT,
+                        want,
                   wk.out_list, wk.out_count, dyn, S);
 }
 
@@ -991,25 +1001,25 @@ hipError_t launch_texture(uint8_t* p, int n, uint32_t seed, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int KX>
+template <int KX, int MB>
 hipError_t launch_search_kx(const SearchJob& J, int ntiles, const SearchCfg& c,
                             const SearchShape& sh, int role, int block, size_t lds,
                             hipStream_t st, const uint8_t* mode, int want) {
   switch (role) {
     case kRoleCoarse:
-      LNR_LAUNCH((k_search<KX, kRoleCoarse>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleCoarse, MB>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
     case kRoleLevel0:
-      LNR_LAUNCH((k_search<KX, kRoleLevel0>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleLevel0, MB>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
     case kRoleTrial:
-      LNR_LAUNCH((k_search<KX, kRoleTrial>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleTrial, MB>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
     default:
-      LNR_LAUNCH((k_search<KX, kRoleStage>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
+      LNR_LAUNCH((k_search<KX, kRoleStage, MB>), dim3(ntiles), dim3(block), lds, st, J, c, sh, mode,
                  want);
       break;
   }
@@ -1020,6 +1030,7 @@ hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c,
                          hipStream_t st, const uint8_t* mode, int want, int split) {
   const int ntiles = J.ntx * nty;
   if (ntiles == 0) return hipSuccess;
+  if (J.Hwarp && role != kRoleCoarse) return hipErrorInvalidValue;  // no warp in that kernel
   // a tuned choice: the split (1..7), plus kSearchKx12 (12 candidates per
   // lane) or kSearchMfma (matrix-core cross terms)
   const int kx = shape_kx(split, 8);
@@ -1030,28 +1041,35 @@ hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c,
   int block = 0;
   const SearchShape sh = make_shape(R, c, split & kSearchSplitMask, ntiles, kx, &lds, &block);
   switch (kx) {
-    case 0: return launch_search_kx<0>(J, ntiles, c, sh, role, block, lds, st, mode, want);
-    case 12: return launch_search_kx<12>(J, ntiles, c, sh, role, block, lds, st, mode, want);
-    default: return launch_search_kx<8>(J, ntiles, c, sh, role, block, lds, st, mode, want);
+    case 0:  // (matrix-core operands held for at most 3 or 5 blocks of 16 candidates)
+      return sh.NB <= 3
+                 ? launch_search_kx<0, 3>(J, ntiles, c, sh, role, block, lds, st, mode, want)
+                 : launch_search_kx<0, kMaxNB>(J, ntiles, c, sh, role, block, lds, st, mode, want);
+    case 12: return launch_search_kx<12, 0>(J, ntiles, c, sh, role, block, lds, st, mode, want);
+    default: return launch_search_kx<8, 0>(J, ntiles, c, sh, role, block, lds, st, mode, want);
   }
 }
 
-template <int KX>
+template <int KX, int MB>
 hipError_t launch_work_kx(const SearchJob& one, const SearchJob* jobs, const SearchWork& wk,
                           const SearchCfg& c, const SearchShape& sh, int visit, int want,
-                          int grid, int block, size_t lds, hipStream_t st) {
+                          bool warp, int grid, int block, size_t lds, hipStream_t st) {
   switch (visit) {
     case kVisitCornersOnly:
-      LNR_LAUNCH((k_search_work<KX, kVisitCornersOnly>), dim3(grid), dim3(block), lds, st, one,
-                 jobs, wk, c, sh, want);
+      LNR_LAUNCH((k_search_work<KX, kVisitCornersOnly, false, MB>), dim3(grid), dim3(block), lds, st,
+                 one, jobs, wk, c, sh, want);
       break;
     case kVisitKnownCorner:
-      LNR_LAUNCH((k_search_work<KX, kVisitKnownCorner>), dim3(grid), dim3(block), lds, st, one,
-                 jobs, wk, c, sh, want);
+      LNR_LAUNCH((k_search_work<KX, kVisitKnownCorner, false, MB>), dim3(grid), dim3(block), lds, st,
+                 one, jobs, wk, c, sh, want);
       break;
     default:
-      LNR_LAUNCH((k_search_work<KX, kVisitSearchAll>), dim3(grid), dim3(block), lds, st, one,
-                 jobs, wk, c, sh, want);
+      if (warp)
+        LNR_LAUNCH((k_search_work<KX, kVisitSearchAll, true, MB>), dim3(grid), dim3(block), lds, st,
+                   one, jobs, wk, c, sh, want);
+      else
+        LNR_LAUNCH((k_search_work<KX, kVisitSearchAll, false, MB>), dim3(grid), dim3(block), lds, st,
+                   one, jobs, wk, c, sh, want);
       break;
   }
   return hipGetLastError();
@@ -1059,8 +1077,10 @@ hipError_t launch_work_kx(const SearchJob& one, const SearchJob* jobs, const Sea
 
 hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R,
                               const SearchCfg& c, int visit, int want, int split, int kx,
-                              int grid, hipStream_t st, const SearchJob* one) {
+                              int grid, hipStream_t st, const SearchJob* one, bool warp) {
   if (grid < 1) return hipSuccess;
+  // a single job with a warp needs the kernel that carries it
+  if (one && one->Hwarp && !(warp && visit == kVisitSearchAll)) return hipErrorInvalidValue;
   kx = shape_kx(split, kx);  // flags in a tuned shape code take precedence
   if ((split & kSearchSplitMask) && !search_shape_fits(R, c, split)) split = 0;
   split &= kSearchSplitMask;
@@ -1074,9 +1094,15 @@ hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R
   const SearchJob none{};
   const SearchJob& J = one ? *one : none;
   switch (kx) {
-    case 0: return launch_work_kx<0>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
-    case 12: return launch_work_kx<12>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
-    default: return launch_work_kx<8>(J, jobs, wk, c, sh, visit, want, grid, block, lds, st);
+    case 0:
+      return sh.NB <= 3 ? launch_work_kx<0, 3>(J, jobs, wk, c, sh, visit, want, warp, grid, block,
+                                               lds, st)
+                        : launch_work_kx<0, kMaxNB>(J, jobs, wk, c, sh, visit, want, warp, grid,
+                                                    block, lds, st);
+    case 12:
+      return launch_work_kx<12, 0>(J, jobs, wk, c, sh, visit, want, warp, grid, block, lds, st);
+    default:
+      return launch_work_kx<8, 0>(J, jobs, wk, c, sh, visit, want, warp, grid, block, lds, st);
   }
 }
 

@@ -1366,8 +1366,9 @@ lnr_status enqueue_batch_levels(lnr_ctx* ctx, const lnr_frame* refs, const lnr_f
     wk.ntotal = T.ntiles;
     wk.out_list = nullptr;
     wk.out_count = nullptr;
+    // (coarse levels warp their windows; level 0 reads the warped level)
     LNR_HIP(launch_search_work(reinterpret_cast<const SearchJob*>(tab + T.o_sjob), wk, R, cfg,
-                               kVisitSearchAll, 0, 0, kx, T.ntiles, origin));
+                               kVisitSearchAll, 0, 0, kx, T.ntiles, origin, nullptr, l != 0));
     LNR_HIP(launch_weed_jobs(reinterpret_cast<const WeedJob*>(tab + T.o_wjob), T.njobs,
                              T.max_tiles, l, *p, origin));
   }

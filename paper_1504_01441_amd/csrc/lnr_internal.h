@@ -144,15 +144,18 @@ struct WarpJob {
 };
 hipError_t launch_warp_jobs(const WarpJob* jobs, const int* row0, int njobs, int rows,
                             int wmax, hipStream_t st);
+// (a job with Hwarp only with role kRoleCoarse)
 hipError_t launch_search(const SearchJob& J, int nty, int R, const SearchCfg& c, int role,
                          hipStream_t st, const uint8_t* mode = nullptr, int want = 0,
                          int split = 0);
 // `grid` workgroups, one per item of the work (at least the number of items);
 // kx: candidates per lane (8 or 12); jobs null: the single job `one` (by
-// value), whose tiles the work's items are
+// value), whose tiles the work's items are; warp: the jobs may warp their
+// windows on the fly (Hwarp; only with kVisitSearchAll)
 hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R,
                               const SearchCfg& c, int visit, int want, int split, int kx,
-                              int grid, hipStream_t st, const SearchJob* one = nullptr);
+                              int grid, hipStream_t st, const SearchJob* one = nullptr,
+                              bool warp = false);
 
 // search shapes that launch_search accepts for radius R (splits of the patch
 // rows over thread groups, with 8 or 12 candidates per lane or the matrix

@@ -127,7 +127,7 @@ def test_search_other_patch_and_grid(ctx):
     assert np.array_equal(flags.cpu().numpy(), has | (valid << 1))
 
 
-@pytest.mark.parametrize("R,shape", [(0, 32 | 1), (3, 32 | 1), (3, 32 | 3), (8, 32 | 2),
+@pytest.mark.parametrize("R,shape", [(0, 32 | 1), (3, 32 | 1), (3, 32 | 3), (8, 32 | 2), (12, 32 | 4),
                                      (10, 32 | 1), (10, 32 | 4), (16, 32 | 1), (16, 32 | 3),
                                      (32, 32 | 1)])
 def test_search_mfma_vs_oracle(R, shape):
