@@ -251,10 +251,15 @@ struct SearchShape {
   // chunks of a window row, the patch rows' zero padding (bytes, before the
   // patch) and their length (dwords)
   int NB, KC, padB, LB;
-  // workgroup memory, sized for these parameters: the reference region
-  // (rows of rs bytes), the quadrant row sums, then the window, its row
-  // energies, the split totals, the window energies and the padded patch
-  int rs, off_hsum, off_win, off_rowsq, off_tot, off_colE, off_pb;
+  // workgroup memory, sized for these parameters. 8 or 12 candidates per
+  // lane: the reference region (rows of rs bytes), the quadrant row sums,
+  // then the window, its row energies, the split totals, the window
+  // energies. Matrix cores (the cross terms come first, into registers): the
+  // window, then the reference region, the quadrant row sums and the padded
+  // patch rows; the row energies then take the place of the region, the
+  // sums and the patch rows, the window energies that of the window, and
+  // the split totals follow. off_cend: the end of the corner phase's memory.
+  int rs, off_reg, off_hsum, off_cend, off_win, off_rowsq, off_tot, off_colE, off_pb;
 };
 
 // nearest integer of a predicted source coordinate (half up), clamped far
@@ -332,7 +337,7 @@ template <int KX, bool WARP, int MB>
 __device__ void search_tile(const SearchJob& J, int tile, int gidx, const SearchCfg& c,
                             const SearchShape& sh, int visit, int want, int* list, int* count,
                             uint8_t* dyn, TileShared& S) {
-  uint8_t* reg = dyn;
+  uint8_t* reg = dyn + sh.off_reg;
   uint32_t* hsum = reinterpret_cast<uint32_t*>(dyn + sh.off_hsum);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int w = J.w, h = J.h;
@@ -471,6 +476,8 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   } else {
     stage_rows(J.wimg, w, h, wx0, wy0, sh.NR, sh.stage_dw, win, sh.wrow, tid, nt, 0x80808080u);
   }
+  const int ncp = KX == 0 ? sh.ncand : sh.nstrips * KX;  // candidates per row of tot
+  uint32_t* tot = reinterpret_cast<uint32_t*>(dyn + sh.off_tot);  // split partial sums
   if constexpr (KX == 0) {
     // the patch rows with zero padding for the matrix-core operands:
     // dword d of row i holds patch dword d - padB / 4 (0 outside the patch),
@@ -482,11 +489,12 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       const int i = q / sh.LB, d = q - i * sh.LB - d0;
       pb[q] = (d >= 0 && d < NW) ? patch_dword(reg, sh.rs, pr0, pc0, PW, i, d) : 0u;
     }
+    // the split totals lie past every other buffer here: cleared now
+    if (sh.split > 1)
+      for (int i = tid; i < sh.ncand * sh.ncand; i += nt) tot[i] = 0u;
   }
   __syncthreads();
-  // patch energy and window row energies rowsq[y][k] = sum_c win[y][k + c]^2,
-  // from realigned dwords with v_dot4 (bytes past the patch width masked off)
-  // (summed over each wave first: one LDS atomic per wave)
+  // patch energy (summed over each wave first: one LDS atomic per wave)
   {
     uint32_t part = 0;
     for (int i = tid; i < PW * NW; i += nt)
@@ -495,6 +503,62 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
     if ((tid & 63) == 0 && part) atomicAdd(&S.er_sum, part);
   }
+  // matrix-core lane roles: wave (group msp, dx block mnb), lane (r16, cg)
+  const int lane = tid & 63, mwave = tid >> 6;
+  const int mnb = mwave % sh.NB, msp = mwave / sh.NB;
+  const int r16 = lane & 15, cg = lane >> 4;
+  v4i acc[MB > 0 ? MB : 1];
+  if constexpr (KX == 0) {
+    // 3. cross terms on the matrix cores. For patch row i the cross term of
+    // every candidate is a product of two small matrices,
+    //   X[dy][dx] += sum_x win[i + dy][x] * pat[i][x - dx],
+    // the window rows i .. i + 16 NB - 1 (A: 16 dy x 64 columns) times the
+    // Toeplitz matrix of patch row i (B: 64 columns x 16 dx, zero where
+    // x - dx falls outside the patch): v_mfma_i32_16x16x64_i8, exact in
+    // int32. Wave (group msp, dx block mnb) accumulates the NB dy blocks of
+    // its dx block over its group's patch rows; lane (r, g) supplies A row
+    // dy = 16 mb + r, B column dx = 16 nb + r and bytes 16 g .. 16 g + 15 of
+    // each 64-byte chunk, and receives X[16 mb + 4 g + t][16 nb + r]. The
+    // products come before the energies, which then reuse the patch rows'
+    // and the window's memory.
+    const uint32_t* pb = reinterpret_cast<const uint32_t*>(dyn + sh.off_pb);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = v4i{0, 0, 0, 0};
+    const int i0 = msp * PW / sh.split, i1 = (msp + 1) * PW / sh.split;
+    for (int kc = 0; kc < sh.KC; ++kc) {
+      // B bytes: patch row i at columns x - dx, x = 64 kc + 16 g + 0..15,
+      // i.e. bytes qb .. qb + 15 of the padded row (qb >= 1)
+      const int qb = 64 * kc + 16 * cg - (16 * mnb + r16) + sh.padB;
+      const uint8_t* ar = win + r16 * sh.wrow + 64 * kc + 16 * cg;
+      const uint32_t* pr0 = pb + (qb >> 2);
+      if constexpr (MB <= 3) {
+        switch (sh.NB) {
+          case 1: cross_mfma<1>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+          case 2: cross_mfma<2>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+          default: cross_mfma<3>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        }
+      } else {
+        switch (sh.NB) {
+          case 4: cross_mfma<4>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+          default: cross_mfma<5>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
+        }
+      }
+    }
+    if (sh.split > 1) {  // exact integer partial sums: any order gives the same totals
+      const int dxi = 16 * mnb + r16;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int j = 16 * mb + 4 * cg + t;
+          if (mb < sh.NB && j < sh.ncand && dxi < sh.ncand)
+            atomicAdd(&tot[j * ncp + dxi], (uint32_t)acc[mb][t]);
+        }
+    }
+    __syncthreads();  // (the row energies below overwrite the patch rows)
+  }
+  // window row energies rowsq[y][k] = sum_c win[y][k + c]^2, from realigned
+  // dwords with v_dot4 (bytes past the patch width masked off)
   // (a thread per run of 8 candidates of a window row: the first sum from
   // dwords, then sliding by one pixel four candidates at a time, from the
   // dword holding the pixels that leave and the realigned dword holding those
@@ -543,7 +607,7 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
     }
   }
   __syncthreads();
-  uint32_t* tot = reinterpret_cast<uint32_t*>(dyn + sh.off_tot);    // split partial sums
+  // (matrix cores: the window energies overwrite the window)
   uint32_t* colE = reinterpret_cast<uint32_t*>(dyn + sh.off_colE);  // [ncand][ncand]
   // window energies: vertical box sums of the row energies, sliding over
   // runs of 7 candidate rows per column
@@ -561,9 +625,9 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
       }
     }
   }
-  const int ncp = KX == 0 ? sh.ncand : sh.nstrips * KX;  // candidates per row of tot
-  if (sh.split > 1)
-    for (int i = tid; i < sh.ncand * ncp; i += nt) tot[i] = 0u;
+  if constexpr (KX != 0)
+    if (sh.split > 1)
+      for (int i = tid; i < sh.ncand * ncp; i += nt) tot[i] = 0u;
   __syncthreads();
 
   unsigned long long key = ~0ull;
@@ -588,56 +652,8 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   };
 
   if constexpr (KX == 0) {
-    // 3. cross terms on the matrix cores. For patch row i the cross term of
-    // every candidate is a product of two small matrices,
-    //   X[dy][dx] += sum_x win[i + dy][x] * pat[i][x - dx],
-    // the window rows i .. i + 16 NB - 1 (A: 16 dy x 64 columns) times the
-    // Toeplitz matrix of patch row i (B: 64 columns x 16 dx, zero where
-    // x - dx falls outside the patch): v_mfma_i32_16x16x64_i8, exact in
-    // int32. Wave (group sp, dx block nb) accumulates the NB dy blocks of
-    // its dx block over its group's patch rows; lane (r, g) supplies A row
-    // dy = 16 mb + r, B column dx = 16 nb + r and bytes 16 g .. 16 g + 15 of
-    // each 64-byte chunk, and receives X[16 mb + 4 g + t][16 nb + r].
-    const int lane = tid & 63, wv = tid >> 6;
-    const int nb = wv % sh.NB, sp = wv / sh.NB;
-    const int r16 = lane & 15, cg = lane >> 4;
-    const uint32_t* pb = reinterpret_cast<const uint32_t*>(dyn + sh.off_pb);
-    v4i acc[MB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) acc[mb] = v4i{0, 0, 0, 0};
-    const int i0 = sp * PW / sh.split, i1 = (sp + 1) * PW / sh.split;
-    for (int kc = 0; kc < sh.KC; ++kc) {
-      // B bytes: patch row i at columns x - dx, x = 64 kc + 16 g + 0..15,
-      // i.e. bytes qb .. qb + 15 of the padded row (qb >= 1)
-      const int qb = 64 * kc + 16 * cg - (16 * nb + r16) + sh.padB;
-      const uint8_t* ar = win + r16 * sh.wrow + 64 * kc + 16 * cg;
-      const uint32_t* pr0 = pb + (qb >> 2);
-      if constexpr (MB <= 3) {
-        switch (sh.NB) {
-          case 1: cross_mfma<1>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-          case 2: cross_mfma<2>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-          default: cross_mfma<3>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-        }
-      } else {
-        switch (sh.NB) {
-          case 4: cross_mfma<4>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-          default: cross_mfma<5>(ar, pr0, sh.LB, qb & 3, sh.wrow, i0, i1, acc); break;
-        }
-      }
-    }
-    const int dxi = 16 * nb + r16;
-    if (sh.split > 1) {  // exact integer partial sums: any order gives the same totals
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int j = 16 * mb + 4 * cg + t;
-          if (mb < sh.NB && j < sh.ncand && dxi < sh.ncand)
-            atomicAdd(&tot[j * ncp + dxi], (uint32_t)acc[mb][t]);
-        }
-      __syncthreads();
-    }
-    if (sp == 0 && dxi < sh.ncand) {
+    const int dxi = 16 * mnb + r16;
+    if (msp == 0 && dxi < sh.ncand) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -940,17 +956,37 @@ SearchShape make_shape(int R, const SearchCfg& c, int split, long long ntiles, i
   const int side = 2 * ext + 1;
   sh.rs = (side + 8 + 3) / 4 * 4;
   const int hsum_words = 2 * (c.K * c.g + c.r) * 2 * (2 * c.K + 1);
-  sh.off_hsum = (sh.rs * (side + 1) + 15) / 16 * 16;
-  sh.off_win = (sh.off_hsum + hsum_words * 4 + 15) / 16 * 16;
-  // window, row energies (+ KX words: the last strip's padded candidates read
-  // past the last row), the split totals, the window energies, the padded
-  // patch rows
-  sh.off_rowsq = sh.off_win + nrows * sh.wrow;
-  sh.off_tot = sh.off_rowsq + (sh.NR * sh.ncand + KX) * 4;
-  const int ncp = KX == 0 ? sh.ncand : sh.nstrips * KX;
-  sh.off_colE = sh.off_tot + (sh.split > 1 ? sh.ncand * ncp * 4 : 0);
-  sh.off_pb = (sh.off_colE + sh.ncand * sh.ncand * 4 + 15) / 16 * 16;
-  *lds = (size_t)sh.off_pb + (KX == 0 ? (size_t)PW * sh.LB * 4 : 0);
+  auto a16 = [](int x) { return (x + 15) / 16 * 16; };
+  const int reg_bytes = sh.rs * (side + 1);
+  const int tot_bytes = sh.split > 1 ? sh.ncand * (KX == 0 ? sh.ncand : sh.nstrips * KX) * 4 : 0;
+  if (KX != 0) {
+    // region, row sums, window, row energies (+ KX words: the last strip's
+    // padded candidates read past the last row), split totals, window
+    // energies
+    sh.off_reg = 0;
+    sh.off_hsum = a16(reg_bytes);
+    sh.off_cend = sh.off_hsum + hsum_words * 4;
+    sh.off_win = a16(sh.off_cend);
+    sh.off_rowsq = sh.off_win + nrows * sh.wrow;
+    sh.off_tot = sh.off_rowsq + (sh.NR * sh.ncand + KX) * 4;
+    sh.off_colE = sh.off_tot + tot_bytes;
+    sh.off_pb = a16(sh.off_colE + sh.ncand * sh.ncand * 4);  // (no patch rows)
+    *lds = (size_t)sh.off_pb;
+  } else {
+    // window (later its energies), region, row sums, padded patch rows (the
+    // three later the row energies), split totals; the products read whole
+    // 16-row blocks past the window, i.e. into the buffers after it, for
+    // outputs that are never used
+    sh.off_win = 0;
+    sh.off_colE = 0;
+    sh.off_reg = a16(std::max(sh.NR * sh.wrow, sh.ncand * sh.ncand * 4));
+    sh.off_hsum = a16(sh.off_reg + reg_bytes);
+    sh.off_cend = sh.off_hsum + hsum_words * 4;
+    sh.off_pb = a16(sh.off_cend);
+    sh.off_rowsq = sh.off_reg;
+    sh.off_tot = a16(std::max(sh.off_pb + PW * sh.LB * 4, sh.off_rowsq + sh.NR * sh.ncand * 4));
+    *lds = (size_t)std::max(sh.off_tot + tot_bytes, nrows * sh.wrow);
+  }
   return sh;
 }
 
@@ -1090,7 +1126,7 @@ hipError_t launch_search_work(const SearchJob* jobs, const SearchWork& wk, int R
   int block = 0;
   const SearchShape sh = make_shape(R, c, split, grid, kx, &lds, &block);
   // the corner phase uses only the reference region and its row sums
-  if (visit == kVisitCornersOnly) lds = (size_t)sh.off_win;
+  if (visit == kVisitCornersOnly) lds = (size_t)sh.off_cend;
   const SearchJob none{};
   const SearchJob& J = one ? *one : none;
   switch (kx) {

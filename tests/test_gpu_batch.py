@@ -337,9 +337,11 @@ def test_search_shape_rejects_bad_shapes(lnr):
     for bad in (0, 8, 16, 32, 16 | 32 | 1, 64, 64 | 1):
         with pytest.raises(lnr.LnrError):
             lnr.set_search_shape(c, 640, 480, 16, bad)
-    # more than 64 KB of workgroup memory (radius 32, two patch-row groups on
-    # the matrix cores) or more than 1024 threads (radius 32, 8 per lane, 2 groups)
-    for bad in (32 | 2, 2):
+    # more than 64 KB of workgroup memory (radius 32, 12 candidates per lane,
+    # two patch-row groups: ~69 KB) or more than 1024 threads (radius 32, 8
+    # per lane, 2 groups; matrix cores, 4 groups)
+    for bad in (16 | 2, 2, 32 | 4):
         with pytest.raises(lnr.LnrError):
             lnr.set_search_shape(c, 640, 480, 32, bad)
     lnr.set_search_shape(c, 640, 480, 32, 32 | 1)
+    lnr.set_search_shape(c, 640, 480, 32, 32 | 3)  # (~56 KB, 960 threads)

@@ -129,7 +129,7 @@ def test_search_other_patch_and_grid(ctx):
 
 @pytest.mark.parametrize("R,shape", [(0, 32 | 1), (3, 32 | 1), (3, 32 | 3), (8, 32 | 2), (12, 32 | 4),
                                      (10, 32 | 1), (10, 32 | 4), (16, 32 | 1), (16, 32 | 3),
-                                     (32, 32 | 1)])
+                                     (32, 32 | 1), (32, 32 | 3), (24, 32 | 2)])
 def test_search_mfma_vs_oracle(R, shape):
     """The matrix-core cross terms (window rows times the Toeplitz matrix of a
     patch row, int8 products of the centred pixels), pinned for the level's
