@@ -374,25 +374,43 @@ constexpr int kCW = kBW / 2 + 2, kCH = kBH / 2 + 2;  // coarse tile with its EXP
 //   R_l = sum_k W_k (G_k - E(G_k,l+1)) + E(R_l+1).
 // EXPAND (even 2i: (c[i-1] + 6 c[i] + c[i+1]) / 8, odd 2i+1: (c[i] + c[i+1]) / 2,
 // clamped coarse indices; rows first, then columns) reads the coarse planes
-// from LDS tiles loaded once per block and expanded along x in LDS. Each
-// thread owns one column of the tile (4 rows) and reads each weight once.
-__device__ inline float expand_col(const float* col, int lj, bool even) {
-  return even ? (col[(lj - 1) * kBW] + 6.f * col[lj * kBW] + col[(lj + 1) * kBW]) / 8.f
-              : (col[lj * kBW] + col[(lj + 1) * kBW]) / 2.f;
+// from LDS tiles (kCH x kCW, clamped at load) loaded once per block; each
+// thread expands the coarse rows it needs in registers. Each thread owns one
+// column of the tile (4 rows), or four pixels of a row, and reads each weight
+// once.
+// EXPAND at fine column 2 (li + cx0) + (xeven ? 0 : 1) of one staged row
+__device__ inline float ex_row(const float* row, int li, bool xeven) {
+  return xeven ? (row[li - 1] + 6.f * row[li] + row[li + 1]) / 8.f
+               : (row[li] + row[li + 1]) / 2.f;
 }
 
-__device__ inline float4 expand_col4(const float* col, int lj, bool even) {
-  const float4 m = *reinterpret_cast<const float4*>(col + lj * kBW);
-  const float4 p = *reinterpret_cast<const float4*>(col + (lj + 1) * kBW);
-  if (even) {
-    const float4 a = *reinterpret_cast<const float4*>(col + (lj - 1) * kBW);
+__device__ inline float expand_tile(const float* t, int li, bool xeven, int lj, bool yeven) {
+  const float m = ex_row(t + lj * kCW, li, xeven), p = ex_row(t + (lj + 1) * kCW, li, xeven);
+  if (yeven) {
+    const float a = ex_row(t + (lj - 1) * kCW, li, xeven);
+    return (a + 6.f * m + p) / 8.f;
+  }
+  return (m + p) / 2.f;
+}
+
+// the four fine columns from the even one of coarse index li (li, li + 1)
+__device__ inline float4 ex_row4(const float* row, int li) {
+  const float a = row[li - 1], m = row[li], p = row[li + 1], q = row[li + 2];
+  return make_float4((a + 6.f * m + p) / 8.f, (m + p) / 2.f, (m + 6.f * p + q) / 8.f,
+                     (p + q) / 2.f);
+}
+
+__device__ inline float4 expand_tile4(const float* t, int li, int lj, bool yeven) {
+  const float4 m = ex_row4(t + lj * kCW, li), p = ex_row4(t + (lj + 1) * kCW, li);
+  if (yeven) {
+    const float4 a = ex_row4(t + (lj - 1) * kCW, li);
     return make_float4((a.x + 6.f * m.x + p.x) / 8.f, (a.y + 6.f * m.y + p.y) / 8.f,
                        (a.z + 6.f * m.z + p.z) / 8.f, (a.w + 6.f * m.w + p.w) / 8.f);
   }
   return make_float4((m.x + p.x) / 2.f, (m.y + p.y) / 2.f, (m.z + p.z) / 2.f, (m.w + p.w) / 2.f);
 }
 
-__global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int cg, int w, int h,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_blend(BlendPtrs b, int n, int c0, int cg, int w, int h,
                                                int cw, int chh, int top, int vec) {
   extern __shared__ float sm[];
   const int tid = threadIdx.x;
@@ -402,7 +420,6 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
   const int cx0 = (ox >> 1) - 1, cy0 = (oy >> 1) - 1;
   const int nm = top ? 0 : (n + 1) * cg;  // plane m = cc (n + 1) + k, k = n: R
   float* ct = sm;                         // [nm][kCH][kCW] coarse tiles
-  float* rx = sm + nm * kCH * kCW;        // [nm][kCH][kBW] expanded along x
   if (!top) {
     const int ntot = nm * kCH * kCW;
     for (int i0 = tid; i0 < ntot; i0 += 12 * 256) {  // twelve loads in flight per thread
@@ -424,14 +441,6 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
         if (i0 + 256 * u < ntot) ct[i0 + 256 * u] = v[u];
     }
     __syncthreads();
-    for (int i = tid; i < nm * kCH * kBW; i += 256) {
-      const int m = i / (kCH * kBW), r = (i / kBW) % kCH, fx = i % kBW;
-      const float* row = ct + (m * kCH + r) * kCW;
-      const int li = ((ox + fx) >> 1) - cx0;  // local index of coarse i
-      rx[i] = ((ox + fx) & 1) == 0 ? (row[li - 1] + 6.f * row[li] + row[li + 1]) / 8.f
-                                    : (row[li] + row[li + 1]) / 2.f;
-    }
-    __syncthreads();
   }
   if (vec) {
     // rows of 16-byte aligned planes, width a multiple of 4: a thread owns four
@@ -440,7 +449,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
     const int x = ox + xq;
     if (x >= w || y >= h) return;
     const size_t o = (size_t)y * w + x;
-    const int lj = (y >> 1) - cy0;
+    const int li = (x >> 1) - cx0, lj = (y >> 1) - cy0;  // local coarse indices
     const bool even = (y & 1) == 0;
     float4 acc[3];
 #pragma unroll
@@ -456,7 +465,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
       for (int cc = 0; cc < 3; ++cc) {
         if (cc >= cg) break;
         const float4 e = top ? make_float4(0.f, 0.f, 0.f, 0.f)
-                             : expand_col4(rx + (cc * (n + 1) + k) * kCH * kBW + xq, lj, even);
+                             : expand_tile4(ct + (cc * (n + 1) + k) * kCH * kCW, li, lj, even);
         acc[cc].x += wv.x * (gv[cc].x - e.x);
         acc[cc].y += wv.y * (gv[cc].y - e.y);
         acc[cc].z += wv.z * (gv[cc].z - e.z);
@@ -468,7 +477,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
       if (cc >= cg) break;
       float4 v = acc[cc];
       if (!top) {
-        const float4 e = expand_col4(rx + (cc * (n + 1) + n) * kCH * kBW + xq, lj, even);
+        const float4 e = expand_tile4(ct + (cc * (n + 1) + n) * kCH * kCW, li, lj, even);
         v.x += e.x; v.y += e.y; v.z += e.z; v.w += e.w;
       }
       *reinterpret_cast<float4*>(b.out[c0 + cc] + o) = v;
@@ -479,6 +488,8 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
   const int fx = tid & 63, fy0 = tid >> 6;
   const int x = ox + fx;
   if (x >= w) return;
+  const int li = (x >> 1) - cx0;
+  const bool xeven = (x & 1) == 0;
   float acc[3][4];
   for (int cc = 0; cc < cg; ++cc)
     for (int q = 0; q < 4; ++q) acc[cc][q] = 0.f;
@@ -500,23 +511,24 @@ __global__ __launch_bounds__(256) void k_blend(BlendPtrs b, int n, int c0, int c
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       if (cc >= cg) break;
-      const float* col = rx + (cc * (n + 1) + k) * kCH * kBW + fx;
+      const float* t = ct + (cc * (n + 1) + k) * kCH * kCW;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int y = oy + fy0 + 4 * q;
         if (y >= h) break;
-        const float e = top ? 0.f : expand_col(col, (y >> 1) - cy0, (y & 1) == 0);
+        const float e = top ? 0.f : expand_tile(t, li, xeven, (y >> 1) - cy0, (y & 1) == 0);
         acc[cc][q] += wv[q] * (gv[cc][q] - e);
       }
     }
   }
   for (int cc = 0; cc < cg; ++cc) {
-    const float* col = rx + (cc * (n + 1) + n) * kCH * kBW + fx;
+    const float* t = ct + (cc * (n + 1) + n) * kCH * kCW;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int y = oy + fy0 + 4 * q;
       if (y >= h) break;
-      const float v = top ? acc[cc][q] : acc[cc][q] + expand_col(col, (y >> 1) - cy0, (y & 1) == 0);
+      const float v =
+          top ? acc[cc][q] : acc[cc][q] + expand_tile(t, li, xeven, (y >> 1) - cy0, (y & 1) == 0);
       b.out[c0 + cc][(size_t)y * w + x] = v;
     }
   }
@@ -683,7 +695,7 @@ hipError_t launch_merge(int n, int ch, int W, int H, const float* const* imgs,
     }
     const int cw = l + 1 < L ? lw[l + 1] : 1, chh = l + 1 < L ? lh[l + 1] : 1;
     const int top = l + 1 == L ? 1 : 0;
-    const size_t per_plane = (size_t)kCH * (kCW + kBW) * sizeof(float);
+    const size_t per_plane = (size_t)kCH * kCW * sizeof(float);
     int cg = ch;  // channels per launch, so that the coarse tiles fit in 64 KB of LDS
     while (cg > 1 && (size_t)(n + 1) * cg * per_plane > 64 * 1024) --cg;
     if ((size_t)(n + 1) * per_plane > 64 * 1024) {  // stacks of more than 15 frames
