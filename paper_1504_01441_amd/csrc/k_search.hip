@@ -196,6 +196,56 @@ __device__ inline void stage_rows(const uint8_t* __restrict__ img, int w, int h,
   }
 }
 
+// stage_rows with between() run once by every thread while its first batch
+// of loads (four dwords) is in flight, before their LDS stores.
+template <typename F>
+__device__ inline void stage_rows_around(const uint8_t* __restrict__ img, int w, int h, int x0,
+                                         int y0, int nrows, int ndw, uint8_t* dst, int ldst,
+                                         int tid, int nt, uint32_t flip, F&& between) {
+  const int total = nrows * ndw;
+  bool pending = true;
+  for (int i0 = tid; i0 < total; i0 += 4 * nt) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * nt;
+      v[u] = 0;
+      if (i >= total) continue;
+      const int r = i / ndw, j = i % ndw;
+      const int gy = y0 + r, gx = x0 + 4 * j;
+      if (gy >= 0 && gy < h) {
+        const uint8_t* row = img + (size_t)gy * w;
+        const uintptr_t addr = reinterpret_cast<uintptr_t>(row + gx);
+        const int off = (int)(addr & 3u);
+        const uint8_t* base = row + gx - off;  // aligned
+        if (gx >= 0 && (gx - off) + 8 <= w) {
+          const uint32_t lo = *reinterpret_cast<const uint32_t*>(base);
+          const uint32_t hi = *reinterpret_cast<const uint32_t*>(base + 4);
+          v[u] = __builtin_amdgcn_alignbyte(hi, lo, off);
+        } else {
+          for (int b = 0; b < 4; ++b) {
+            const int xx = gx + b;
+            if (xx >= 0 && xx < w) v[u] |= (uint32_t)row[xx] << (8 * b);
+          }
+        }
+      }
+    }
+    if (pending) {
+      between();
+      pending = false;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * nt;
+      if (i < total) {
+        const int r = i / ndw, j = i % ndw;
+        *reinterpret_cast<uint32_t*>(dst + r * ldst + 4 * j) = v[u] ^ flip;
+      }
+    }
+  }
+  if (pending) between();
+}
+
 // The window rows [y0, y0 + nrows) x bytes [x0, x0 + 4 * ndw) of the level
 // warped on the fly: each pixel inside the level is warp_px of the unwarped
 // source (the value k_warp_q8 stores there), 0 outside, as stage_rows reads
@@ -468,30 +518,35 @@ __device__ void search_tile(const SearchJob& J, int tile, int gidx, const Search
   uint8_t* win = dyn + sh.off_win;
   uint32_t* rowsq = reinterpret_cast<uint32_t*>(dyn + sh.off_rowsq);
   const int wx0 = px + cdx - P - R, wy0 = py + cdy - P - R;
+  const int ncp = KX == 0 ? sh.ncand : sh.nstrips * KX;  // candidates per row of tot
+  uint32_t* tot = reinterpret_cast<uint32_t*>(dyn + sh.off_tot);  // split partial sums
+  // the patch rows with zero padding for the matrix-core operands: dword d
+  // of row i holds patch dword d - padB / 4 (0 outside the patch), packed
+  // again from the staged region (the packed patch written above by other
+  // waves is not read before the next barrier); the split totals lie past
+  // every other buffer here and are cleared now
+  auto pack_patch = [&]() {
+    if constexpr (KX == 0) {
+      uint32_t* pb = reinterpret_cast<uint32_t*>(dyn + sh.off_pb);
+      const int d0 = sh.padB >> 2;
+      for (int q = tid; q < PW * sh.LB; q += nt) {
+        const int i = q / sh.LB, d = q - i * sh.LB - d0;
+        pb[q] = (d >= 0 && d < NW) ? patch_dword(reg, sh.rs, pr0, pc0, PW, i, d) : 0u;
+      }
+      if (sh.split > 1)
+        for (int i = tid; i < sh.ncand * sh.ncand; i += nt) tot[i] = 0u;
+    }
+  };
   // (without WARP the job has no Hwarp: the launchers check it)
   if (WARP && J.Hwarp) {
     double hp[9];
     pixel_homography(J.Hwarp, w, h, hp);
     stage_warped(J.wimg, w, h, hp, wx0, wy0, sh.NR, sh.stage_dw, win, sh.wrow, tid, nt, 0x80u);
+    pack_patch();
   } else {
-    stage_rows(J.wimg, w, h, wx0, wy0, sh.NR, sh.stage_dw, win, sh.wrow, tid, nt, 0x80808080u);
-  }
-  const int ncp = KX == 0 ? sh.ncand : sh.nstrips * KX;  // candidates per row of tot
-  uint32_t* tot = reinterpret_cast<uint32_t*>(dyn + sh.off_tot);  // split partial sums
-  if constexpr (KX == 0) {
-    // the patch rows with zero padding for the matrix-core operands:
-    // dword d of row i holds patch dword d - padB / 4 (0 outside the patch),
-    // packed again from the staged region (the packed patch written above by
-    // other waves is not read before the next barrier)
-    uint32_t* pb = reinterpret_cast<uint32_t*>(dyn + sh.off_pb);
-    const int d0 = sh.padB >> 2;
-    for (int q = tid; q < PW * sh.LB; q += nt) {
-      const int i = q / sh.LB, d = q - i * sh.LB - d0;
-      pb[q] = (d >= 0 && d < NW) ? patch_dword(reg, sh.rs, pr0, pc0, PW, i, d) : 0u;
-    }
-    // the split totals lie past every other buffer here: cleared now
-    if (sh.split > 1)
-      for (int i = tid; i < sh.ncand * sh.ncand; i += nt) tot[i] = 0u;
+    // (the patch rows are packed while the window's first loads are in flight)
+    stage_rows_around(J.wimg, w, h, wx0, wy0, sh.NR, sh.stage_dw, win, sh.wrow, tid, nt,
+                      0x80808080u, pack_patch);
   }
   __syncthreads();
   // patch energy (summed over each wave first: one LDS atomic per wave)
