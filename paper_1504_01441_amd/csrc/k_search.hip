@@ -5,11 +5,11 @@
 // precision in a fixed operation order, rounded half up to 1/256 px, and
 // blended with integer Q16 weights, so the result is exact integers.
 //
-// k_search<KX, ROLE>: one workgroup per full tile of one pair's level (ROLE
+// k_search<KX, ROLE, MB>: one workgroup per full tile of one pair's level (ROLE
 // names the launch for profiles: coarse levels, level 0, stage calls and
 // autotuner trials; only the coarse-level kernel carries the on-the-fly warp
 // of the window, whose registers would cost the others occupancy).
-// k_search_work<KX, VISIT, WARP>: one workgroup per item of a
+// k_search_work<KX, VISIT, WARP, MB>: one workgroup per item of a
 // work list: the tiles of several pairs' levels (a SearchJob table; batches),
 // or a device list of tile indices (the learned proposal's window and
 // fallback tiles); VISIT kVisitCornersOnly runs the corner phase alone and
@@ -21,17 +21,22 @@
 //     largest cornerness.
 //  2. The warped source window around the corner (patch + 2R) is staged in
 //     LDS, 0 outside the image.
-//  3. Thread (dy, strip) scores KX (8 or 12) consecutive dx. The SSD is
-//     computed exactly as  sum r^2 + sum w^2 - 2 sum r w : the cross term uses
-//     v_dot4_u32_u8 on the packed patch rows against window dwords realigned
-//     with v_alignbyte_b32 (about 0.45 VALU instructions per
-//     pixel-candidate); the window energies are vertical box sums (sliding,
-//     once per tile) of LDS row energies (also v_dot4).
+//  3. The SSD is computed exactly as  sum r^2 + sum w^2 - 2 sum r w. KX 8 or
+//     12: thread (dy, strip) scores KX consecutive dx, the cross term with
+//     v_dot4 on the packed patch rows against window dwords realigned with
+//     v_alignbyte_b32 (about 0.45 VALU instructions per pixel-candidate).
+//     KX 0: the cross terms on the matrix cores (v_mfma_i32_16x16x64_i8,
+//     window rows times the Toeplitz matrix of a patch row; MB: at most that
+//     many blocks of 16 candidates), computed first, into registers, so that
+//     the energies can reuse the patch rows' and the window's memory. The
+//     window energies are vertical box sums (sliding, once per tile) of LDS
+//     row energies (also v_dot4).
 //  Staging reads aligned dwords (realigned in registers), several in flight
 //  per thread: the kernel's latency, not its arithmetic, bounds the coarse
-//  levels, which have few tiles. The region, its row sums and the window
-//  share one dynamic allocation sized for the parameters (about 14 KB at
-//  level 0), so that ten 3-wave workgroups fit on a CU.
+//  levels, which have few tiles. The region, its row sums, the window and
+//  the energies share one dynamic allocation sized for the parameters (about
+//  14 KB for the radius-16 matrix-core tile), so that ten 3-wave workgroups
+//  fit on a CU.
 //  4. The argmin key (ssd << 32 | (|dx|+|dy|) << 16 | (dy+R) << 8 | (dx+R)) is
 //     reduced with wave shuffles and LDS; equal keys cannot occur, so the
 //     result does not depend on the reduction order.
