@@ -12,7 +12,7 @@
 //         rank-select over the words, and solves the 8x8 system in double
 //         precision (partial pivoting, fixed operation order) with the matrix
 //         in registers.
-// k_test: a (256 tiles x 8 iterations) block tests its tiles against its
+// k_test: a (256 tiles x 4 or 8 iterations) block tests its tiles against its
 //         hypotheses; wave ballots form each iteration's inlier bitmask row,
 //         and the block's count per iteration is added atomically.
 // k_union: a wave per word of 64 tiles. Every block reads the counts, takes
@@ -129,7 +129,9 @@ __device__ inline int select_bit(unsigned long long m, int k) {
 
 constexpr int kValidThreads = 256;
 constexpr int kHypThreads = 64;
-constexpr int kItPerBlock = 8;
+// hypotheses per k_test block: 4 on levels of up to kTestSmall tiles (more
+// blocks for the few tiles), 8 above (fewer re-reads of the tiles)
+constexpr int kTestSmall = 2048;
 constexpr int kTestThreads = 256;
 constexpr int kUnionThreads = 512;
 constexpr int kMaxIters = 65536;  // the parameter check's bound on weed_iters
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(kHypThreads) void k_hyp(WeedJob one,
 // Tile chunk blockIdx.x x iteration group blockIdx.y: adds the chunk's inlier
 // counts to cnt[iter] and stores the inlier bits in bal[word][iter]
 // (word-major, so that the union reads each word's rows contiguously).
-template <bool JOBS>
+template <bool JOBS, int IPB>
 __global__ __launch_bounds__(kTestThreads) void k_test(WeedJob one,
                                                        const WeedJob* __restrict__ jobs,
                                                        WeedArgs a) {
@@ -270,21 +272,21 @@ __global__ __launch_bounds__(kTestThreads) void k_test(WeedJob one,
   const double* __restrict__ G = J.b.G;
   int32_t* __restrict__ cnt = J.b.cnt;
   unsigned long long* __restrict__ bal = J.b.bal;
-  __shared__ double gs[kItPerBlock][8];
-  __shared__ int ok[kItPerBlock];
-  __shared__ int wc[kItPerBlock][kTestThreads / 64];
+  __shared__ double gs[IPB][8];
+  __shared__ int ok[IPB];
+  __shared__ int wc[IPB][kTestThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int it0 = blockIdx.y * kItPerBlock;
+  const int it0 = blockIdx.y * IPB;
   // the tile, the hypotheses and their usability are loaded together
   const int t = blockIdx.x * kTestThreads + tid;
   const int tc = t < ntiles ? t : ntiles - 1;  // ntiles >= 1 here
   const uint8_t tf = flags[tc];
   const int4 mt = tile_match(cxy, disp, tc, w / 2, h / 2);
-  if (tid < 8 * kItPerBlock) {  // one coefficient per thread
+  if (tid < 8 * IPB) {  // one coefficient per thread
     const int it = min(it0 + (tid >> 3), a.iters - 1);
     gs[tid >> 3][tid & 7] = G[(size_t)it * 8 + (tid & 7)];
   }
-  if (tid < kItPerBlock) {
+  if (tid < IPB) {
     const int it = it0 + tid;
     // usable hypotheses start at 0 and only grow, so the sign is stable
     ok[tid] = it < a.iters && __atomic_load_n(&cnt[min(it, a.iters - 1)], __ATOMIC_RELAXED) >= 0;
@@ -293,7 +295,7 @@ __global__ __launch_bounds__(kTestThreads) void k_test(WeedJob one,
   const bool valid = t < ntiles && (tf & 2);
   const int4 m = valid ? mt : make_int4(0, 0, 0, 0);
   const int word = t >> 6;
-  for (int q = 0; q < kItPerBlock; ++q) {
+  for (int q = 0; q < IPB; ++q) {
     if (!ok[q]) continue;
     const bool in = valid && is_inlier(gs[q], m, a.eps2);
     const unsigned long long b = __ballot(in);
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kTestThreads) void k_test(WeedJob one,
     }
   }
   __syncthreads();
-  if (tid < kItPerBlock && ok[tid]) {
+  if (tid < IPB && ok[tid]) {
     int s = 0;
     for (int q = 0; q < kTestThreads / 64; ++q) s += wc[tid][q];
     if (s) atomicAdd(&cnt[it0 + tid], s);
@@ -581,7 +583,8 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
   const WeedArgs a = weed_args(p, level);
   const int words = ntiles > 0 ? (ntiles + 63) / 64 : 1;
   const int chunks = ntiles > 0 ? (ntiles + kTestThreads - 1) / kTestThreads : 1;
-  const int groups = (a.iters + kItPerBlock - 1) / kItPerBlock;
+  const int ipb = ntiles <= kTestSmall ? 4 : 8;
+  const int groups = (a.iters + ipb - 1) / ipb;
   if (words > kMaxWords || a.iters > kMaxIters) return hipErrorInvalidValue;
   WeedJob J;
   J.cxy = corner_xy; J.disp = disp; J.flags = flags;
@@ -600,7 +603,12 @@ hipError_t launch_weed_fit(const int32_t* corner_xy, const int32_t* disp, uint8_
              st, J, nullptr, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ntiles > 0) {
-    LNR_LAUNCH(k_test<false>, dim3(chunks, groups), dim3(kTestThreads), 0, st, J, nullptr, a);
+    if (ipb == 4)
+      LNR_LAUNCH((k_test<false, 4>), dim3(chunks, groups), dim3(kTestThreads), 0, st, J, nullptr,
+                 a);
+    else
+      LNR_LAUNCH((k_test<false, 8>), dim3(chunks, groups), dim3(kTestThreads), 0, st, J, nullptr,
+                 a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   LNR_LAUNCH(k_union<false>, dim3((words + kUnionThreads / 64 - 1) / (kUnionThreads / 64)),
@@ -616,15 +624,20 @@ hipError_t launch_weed_jobs(const WeedJob* jobs, int njobs, int max_tiles, int l
   const WeedArgs a = weed_args(p, level);
   const int words = max_tiles > 0 ? (max_tiles + 63) / 64 : 1;
   const int chunks = max_tiles > 0 ? (max_tiles + kTestThreads - 1) / kTestThreads : 1;
-  const int groups = (a.iters + kItPerBlock - 1) / kItPerBlock;
+  const int ipb = max_tiles <= kTestSmall ? 4 : 8;
+  const int groups = (a.iters + ipb - 1) / ipb;
   if (words > kMaxWords || a.iters > kMaxIters) return hipErrorInvalidValue;
   WeedJob none{};
   hipError_t e;
   LNR_LAUNCH(k_hyp<true>, dim3((a.iters + kHypThreads - 1) / kHypThreads, 1, njobs),
              dim3(kHypThreads), 0, st, none, jobs, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  LNR_LAUNCH(k_test<true>, dim3(chunks, groups, njobs), dim3(kTestThreads), 0, st, none, jobs,
-             a);
+  if (ipb == 4)
+    LNR_LAUNCH((k_test<true, 4>), dim3(chunks, groups, njobs), dim3(kTestThreads), 0, st, none,
+               jobs, a);
+  else
+    LNR_LAUNCH((k_test<true, 8>), dim3(chunks, groups, njobs), dim3(kTestThreads), 0, st, none,
+               jobs, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   LNR_LAUNCH(k_union<true>,
              dim3((words + kUnionThreads / 64 - 1) / (kUnionThreads / 64), 1, njobs),
